@@ -1,0 +1,291 @@
+"""Pins of the oracle's reduced-order pieces (CPU only): exactness of the iSVD
+without truncation against the batch SVD of the weighted history, closed forms,
+LU-pivoting equivalence of DEIM, brute-force argmax re-evaluation, the
+HR-LSPG / HR-Galerkin equivalence under backward Euler, and reductions of the
+ROM to the FOM."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import fom as F
+from oracle import rom as O
+from paper_2605_28684_amd import workloads as W
+
+
+def _orth(N, r, seed):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.normal(size=(N, r)))
+    return Q
+
+
+# ------------------------------------------------------------------ preprocessing
+def test_preprocess_matches_loop_definition():
+    rng = np.random.default_rng(0)
+    nc, nv, w = 7, 3, 4
+    q0 = rng.normal(size=nc * nv)
+    Qt = rng.normal(size=(nc * nv, w))
+    q_ref, d = O.preprocess(Qt, q0, nv)
+    for v in range(nv):
+        acc = 0.0
+        for t in range(w):
+            for c in range(nc):
+                acc += (Qt[c * nv + v, t] - q0[c * nv + v]) ** 2
+        assert abs(d[v] - 1.0 / (acc / (w * nc))) <= 1e-12 * d[v]
+    assert np.array_equal(q_ref, q0)
+
+
+# ------------------------------------------------------------------ iSVD
+def _history(Y, lam):
+    k = Y.shape[1]
+    return Y * (lam ** np.arange(k - 1, -1, -1))[None, :]
+
+
+@pytest.mark.parametrize("lam", [1.0, 0.7, 0.1])
+def test_isvd_untruncated_reproduces_batch_svd(lam):
+    rng = np.random.default_rng(1)
+    N, k = 60, 12
+    Y = rng.normal(size=(N, k)) * (0.8 ** np.arange(k))[None, :]
+    # start from the exact SVD of the first column, then add columns without truncation
+    Phi = Y[:, :1] / np.linalg.norm(Y[:, 0])
+    sig = np.array([np.linalg.norm(Y[:, 0])])
+    for j in range(1, k):
+        Phi, sig, _ = O.isvd_update(Phi, sig, Y[:, j], lam, r=j + 1)
+    U, s, _ = np.linalg.svd(_history(Y, lam), full_matrices=False)
+    # singular values to 1e-12 relative (normwise: eps-level absolute error is the
+    # best any backward-stable SVD achieves on the tiny ones)
+    np.testing.assert_allclose(sig, s, rtol=1e-12, atol=1e-13 * s[0])
+    # vectors up to sign, where the singular value is well separated and not tiny
+    gap = np.minimum(np.abs(np.diff(np.r_[np.inf, s])), np.abs(np.diff(np.r_[s, -np.inf])))
+    ok = (s > 1e-4 * s[0]) & (gap > 1e-3 * s[0])
+    al = np.sign(np.sum(U * Phi, axis=0))
+    np.testing.assert_allclose(Phi[:, ok], (U * al[None, :])[:, ok], atol=1e-10)
+    assert np.max(np.abs(Phi.T @ Phi - np.eye(k))) < 1e-13
+
+
+def test_isvd_exact_for_low_rank_data():
+    rng = np.random.default_rng(2)
+    N, r, k = 80, 5, 30
+    B = _orth(N, 3, 3)
+    Y = B @ rng.normal(size=(3, k))           # rank 3 <= r
+    X0 = Y[:, :r]
+    Phi, sig = O.pod(X0, r)
+    lam = 0.9
+    for j in range(r, k):
+        Phi, sig, _ = O.isvd_update(Phi, sig, Y[:, j], lam, r)
+    H = np.concatenate([X0 * lam ** (k - r), _history(Y[:, r:], lam)], axis=1)
+    s = np.linalg.svd(H, compute_uv=False)
+    np.testing.assert_allclose(sig[:3], s[:3], rtol=1e-11)
+    assert np.all(sig[3:] < 1e-10 * s[0])
+
+
+def test_isvd_lambda_zero_closed_form():
+    Phi = _orth(50, 4, 4)
+    sig = np.array([5.0, 3.0, 2.0, 1.0])
+    y = np.random.default_rng(5).normal(size=50)
+    P2, s2, _ = O.isvd_update(Phi, sig, y, 0.0, 4)
+    assert abs(s2[0] - np.linalg.norm(y)) < 1e-13 * np.linalg.norm(y)
+    assert np.all(s2[1:] < 1e-13)
+    np.testing.assert_allclose(np.abs(P2[:, 0]), np.abs(y) / np.linalg.norm(y), atol=1e-14)
+
+
+def test_isvd_snapshot_in_span():
+    Phi = _orth(40, 3, 6)
+    sig = np.array([4.0, 2.0, 0.5])
+    coef = np.array([0.3, -1.2, 2.0])
+    y = Phi @ coef
+    lam = 0.6
+    _, s2, info = O.isvd_update(Phi, sig, y, lam, 3)
+    ref = np.linalg.svd(np.concatenate([lam * np.diag(sig), coef[:, None]], axis=1), compute_uv=False)
+    np.testing.assert_allclose(s2, ref, rtol=1e-13)
+    assert info["degenerate"] and info["rho"] == 0.0
+
+
+def test_isvd_covariance_recursion():
+    rng = np.random.default_rng(7)
+    Phi = _orth(30, 4, 8)
+    sig = np.array([3.0, 2.0, 1.5, 0.2])
+    y = rng.normal(size=30)
+    lam = 0.8
+    P2, s2, _ = O.isvd_update(Phi, sig, y, lam, 5)   # keep all r+1
+    C1 = P2 @ np.diag(s2 ** 2) @ P2.T
+    C0 = lam ** 2 * Phi @ np.diag(sig ** 2) @ Phi.T + np.outer(y, y)
+    np.testing.assert_allclose(C1, C0, atol=1e-12)
+
+
+def test_transfer_closed_form_equals_lift_and_project():
+    rng = np.random.default_rng(9)
+    Phi = _orth(70, 6, 10)
+    sig = np.sort(rng.uniform(0.5, 4, 6))[::-1]
+    a = rng.normal(size=6)
+    P2, _, info = O.isvd_update(Phi, sig, rng.normal(size=70), 0.5, 6)
+    plain = O.transfer(Phi, P2, a)
+    closed = info["Ubar"][:6, :6].T @ a
+    np.testing.assert_allclose(plain, closed, atol=1e-14)
+
+
+def test_reorth_restores_orthonormality():
+    Phi = _orth(100, 8, 11)
+    Pn = Phi @ (np.eye(8) + 1e-4 * np.random.default_rng(0).normal(size=(8, 8)))
+    P2, L = O.reorth(Pn, 1e-12)
+    assert L is not None
+    assert np.max(np.abs(P2.T @ P2 - np.eye(8))) < 1e-13
+    # same span
+    np.testing.assert_allclose(P2 @ (P2.T @ Pn), Pn, atol=1e-12)
+    P3, L3 = O.reorth(Phi, 1e-12)
+    assert L3 is None and P3 is Phi
+
+
+# ------------------------------------------------------------------ DEIM
+def _lu_pivots(A):
+    lu, piv = sla.lu_factor(A)
+    perm = np.arange(A.shape[0])
+    for j, pj in enumerate(piv):
+        perm[[j, pj]] = perm[[pj, j]]
+    return perm[:A.shape[1]]
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_deim_round1_equals_lu_partial_pivoting(seed):
+    Phi = _orth(90, 7, 100 + seed)
+    P = O.deim_greedy(Phi, 7)
+    np.testing.assert_array_equal(P, _lu_pivots(Phi))
+
+
+def test_deim_round2_brute_force_and_properties():
+    Phi = _orth(40, 5, 42)
+    P = O.deim_greedy(Phi, 10)
+    assert len(set(P.tolist())) == 10
+    # brute force: re-evaluate every round-2 pick by looping over candidate rows
+    r = 5
+    for j in range(5):
+        S = list(P[:r + j])
+        best, besti = -1.0, -1
+        for i in range(40):
+            if i in S:
+                continue
+            if j == 0:
+                res = Phi[i, 0]
+            else:
+                c = np.linalg.lstsq(Phi[S, :j], Phi[S, j], rcond=None)[0]
+                res = Phi[i, j] - Phi[i, :j] @ c
+            if abs(res) > best:
+                best, besti = abs(res), i
+        assert P[r + j] == besti
+    # sigma_min(P^T Phi) never decreases as rows are added
+    sm = [np.linalg.svd(Phi[P[:k]], compute_uv=False)[-1] for k in range(5, 11)]
+    assert all(sm[i + 1] >= sm[i] * (1 - 1e-12) for i in range(5))
+
+
+def test_deim_interpolation_residual_vanishes_on_chosen_rows():
+    Phi = _orth(60, 6, 43)
+    P = O.deim_greedy(Phi, 6)
+    for j in range(1, 6):
+        c = np.linalg.solve(Phi[P[:j], :j], Phi[P[:j], j])
+        res = Phi[:, j] - Phi[:, :j] @ c
+        assert np.max(np.abs(res[P[:j]])) < 1e-13
+
+
+def test_rebuild_is_pseudoinverse():
+    Phi = _orth(50, 4, 44)
+    P = O.deim_greedy(Phi, 8)
+    M = O.rebuild(Phi, P)
+    A = Phi[P]
+    np.testing.assert_allclose(M @ A, np.eye(4), atol=1e-13)
+    np.testing.assert_allclose(A @ M @ A, A, atol=1e-13)
+    np.testing.assert_allclose((A @ M).T, A @ M, atol=1e-13)
+
+
+# ------------------------------------------------------------------ ROM steps
+def _setup(problem, n, r, seed, phys):
+    q0 = W.random_state(problem, [n], seed=seed)
+    Q = F.fom_trajectory(problem, q0, 1e-3 if problem == F.BURGERS else 0.064 / n, r, phys)
+    nv = F.NVAR[problem]
+    q_ref, dv = O.preprocess(Q[:, 1:], q0, nv)
+    d = O.dfull(dv, n)
+    Phi, sig = O.pod(d[:, None] * (Q[:, 1:] - q_ref[:, None]), r)
+    a = Phi.T @ (d * (Q[:, -1] - q_ref))
+    return q_ref, d, Phi, a
+
+
+def _hr_galerkin_step(problem, phys, q_ref, d, Phi, P, M, a_prev, dt, tol, max_it):
+    """Independent route: Newton on b(a) = (a - a_prev) - dt M P^T D f(q~(a))."""
+    a = a_prev.copy()
+    PhiD = Phi / d[:, None]
+    r = Phi.shape[1]
+    for _ in range(max_it):
+        qt = q_ref + PhiD @ a
+        b = (a - a_prev) - dt * M @ (d[P] * F.fom_f(problem, qt, phys)[P])
+        Jf = F.jacobian_f(problem, qt, phys)
+        A = np.eye(r) - dt * M @ ((d[:, None] * (Jf @ PhiD))[P])
+        delta = np.linalg.solve(A, -b)
+        a = a + delta
+        if np.max(np.abs(delta)) <= tol * (1 + np.max(np.abs(a))):
+            break
+    return a
+
+
+@pytest.mark.parametrize("problem", [F.BURGERS, F.EULER_HLLC])
+def test_hr_lspg_equals_hr_galerkin_under_be(problem):
+    phys = dict(nu=0.01) if problem == F.BURGERS else dict(gamma=1.4)
+    n, r = 48, 5
+    q_ref, d, Phi, a = _setup(problem, n, r, 21, phys)
+    P = O.deim_greedy(Phi, 2 * r)
+    M = O.rebuild(Phi, P)
+    dt = 1e-3 if problem == F.BURGERS else 0.064 / n
+    a1, it, ok = O.hr_lspg_step(problem, phys, q_ref, d, Phi, P, M, a, dt, 1e-13, 20)
+    a2 = _hr_galerkin_step(problem, phys, q_ref, d, Phi, P, M, a, dt, 1e-13, 20)
+    assert ok
+    np.testing.assert_allclose(a1, a2, rtol=0, atol=1e-11 * (1 + np.max(np.abs(a1))))
+
+
+def test_hr_with_all_rows_equals_full_galerkin():
+    phys = dict(nu=0.01)
+    n, r = 40, 4
+    q_ref, d, Phi, a = _setup(F.BURGERS, n, r, 22, phys)
+    P = np.arange(n)
+    M = O.rebuild(Phi, P)
+    a1, _, _ = O.hr_lspg_step(F.BURGERS, phys, q_ref, d, Phi, P, M, a, 1e-3, 1e-13, 20)
+    a2, _, _ = O.galerkin_step(F.BURGERS, phys, q_ref, d, Phi, a, 1e-3, 1e-13, 20)
+    np.testing.assert_allclose(a1, a2, atol=1e-11)
+
+
+def test_full_basis_rom_reproduces_fom():
+    n = 30
+    phys = dict(nu=0.01)
+    q = W.random_state(F.BURGERS, [n], seed=23)
+    Phi = np.eye(n)
+    a1, _, ok = O.galerkin_step(F.BURGERS, phys, np.zeros(n), np.ones(n), Phi, q, 1e-3, 1e-14, 20)
+    q1, _, _ = F.newton_be_step(F.BURGERS, q, 1e-3, phys, tol=1e-14, max_it=20)
+    np.testing.assert_allclose(a1, q1, atol=1e-12)
+
+
+def test_fourier_basis_rom_exact_for_linear_diffusion():
+    n, nu, dt = 64, 0.02, 1e-3
+    x = (np.arange(n) + 0.5) / n
+    modes = [np.ones(n)] + [f(2 * np.pi * k * x) for k in (1, 2, 3) for f in (np.cos, np.sin)]
+    Phi = np.stack(modes, axis=1)
+    Phi /= np.linalg.norm(Phi, axis=0)[None, :]
+    phys = dict(nu=nu, conv=0.0)
+    a0 = np.random.default_rng(3).normal(size=Phi.shape[1])
+    q0 = Phi @ a0
+    a1, it, _ = O.galerkin_step(F.BURGERS, phys, np.zeros(n), np.ones(n), Phi, a0, dt, 1e-14, 5)
+    q1, _, _ = F.newton_be_step(F.BURGERS, q0, dt, phys, tol=1e-14)
+    np.testing.assert_allclose(Phi @ a1, q1, atol=1e-13)
+
+
+# ------------------------------------------------------------------ Alg. 1 (report-only quality)
+def test_alg1_adaptive_beats_static_burgers():
+    w = W.burgers_512_f64(n=128, N_t=300, w_init=20, r=6, z=5)
+    prm = w.params()
+    st, rec = O.adaptive_rom(W.BURGERS, w.phys[0], w.q0, prm)
+    # static ROM: same offline data, never adapted
+    st0 = O.offline(W.BURGERS, w.phys[0], w.q0, prm)
+    a = st0["a"]
+    for _ in range(prm["w_init"], prm["N_t"]):
+        a, _, _ = O.galerkin_step(W.BURGERS, w.phys[0], st0["q_ref"], st0["d"], st0["Phi"], a,
+                                  prm["dt"], prm["rom_tol"], prm["rom_max"])
+    qf = F.fom_trajectory(W.BURGERS, w.q0, prm["dt"], prm["N_t"], w.phys[0])[:, -1]
+    e_ad = np.linalg.norm(O.reconstruct(st["q_ref"], st["d"], st["Phi"], st["a"]) - qf) / np.linalg.norm(qf)
+    e_st = np.linalg.norm(O.reconstruct(st0["q_ref"], st0["d"], st0["Phi"], a) - qf) / np.linalg.norm(qf)
+    assert len(rec["events"]) == (prm["N_t"] - prm["w_init"]) // prm["z"]
+    assert e_ad < e_st
