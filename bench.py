@@ -1,0 +1,229 @@
+"""Benchmark of the adaptive-ROM hot path on one MI355X.
+
+Workload (the batched Burgers configuration): 256 instances, N_i drawn from
+{2048, 4096, 8192, 16384}, nu log-uniform in [1e-3, 1e-2], four seeded sine
+modes, FP32 state and basis with FP64 core SVD / reduced solves, r = 32, an
+iSVD update every z = 4 steps, full Galerkin reduced model.
+
+A "step" is one adaptation window for the whole batch: z fine reduced steps of
+every instance plus one adaptation event (coarse backward-Euler full-order step
+of the correction state, iSVD update with re-orthonormalisation schedule,
+rebuild, state transfer), replayed from a HIP graph.  The offline stage
+(training steps, POD) runs before the timed region.
+
+value        = instances x fine steps / second (events amortised in), batched path
+plain        = the same kernels launched per instance from a host loop (no graph)
+roofline     = dominant kernel of the step, timed live with HIP events on the
+               launch stream, against the 8 TB/s HBM peak
+fom_residual = R(q) on the 64 x 262,144-cell Euler (Rusanov, FP32) shape:
+               cell-updates/s and fraction of the HBM roofline (24 B/cell)
+cpu_baseline = the FP64 CPU checker timed on a bounded sample of the same workload
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "adaptive-ROM steps/s + FOM cell-updates/s (% HBM roofline), batched vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--plain-inst", type=int, default=32,
+                   help="instances timed on the plain per-instance path")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=20.0)
+    return p.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, budget_s):
+    """The FP64 oracle on a bounded sample: instances of the same workload, the
+    offline stage untimed, then whole adaptation windows timed until the budget."""
+    import numpy as np
+    from oracle import rom as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    prm = w.params()
+    order = np.argsort(np.asarray(w.n_cells))
+    picks = [int(order[len(order) * k // 4]) for k in range(4)]  # spread over the size mix
+    steps = 0
+    cells = 0
+    t_total = 0.0
+    for b in picks:
+        q0 = w.instance(b)
+        st = O.offline(W.BURGERS, w.phys[b], q0, prm)
+        n = prm["w_init"]
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s / len(picks):
+            for _ in range(prm["z"]):
+                O.rom_fine_step(W.BURGERS, w.phys[b], st, prm)
+                if (n + 1 - prm["w_init"]) % prm["z"] == 0:
+                    O.adaptation_event(W.BURGERS, w.phys[b], st, prm)
+                n += 1
+                steps += 1
+                cells += w.n_cells[b]
+        t_total += time.perf_counter() - t0
+    mean_cells = float(np.mean(w.n_cells))
+    # scale to the workload's size mix: time per instance-step grows with N
+    per_cell_step = t_total / cells
+    value = 1.0 / (per_cell_step * mean_cells)
+    return dict(value=value, unit="steps/s", cores=int(threads), kind="oracle",
+                sample="%d instance-steps of 4 instances (N=%s) in whole windows, %.1f s; "
+                       "scaled by mean N of the batch" % (steps, [w.n_cells[b] for b in picks],
+                                                         t_total))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        log("bench.py runs on one GPU only: this build has no multi-GPU path "
+            "(instances would shard across GPUs with no communication).")
+        sys.exit(2)
+    import numpy as np
+    import torch
+    global W
+    from paper_2605_28684_amd import workloads as W
+    from paper_2605_28684_amd import romhip as R
+
+    torch.cuda.set_device(0)
+    w = W.burgers_batch_f32()
+    z = w.z
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        q0 = torch.as_tensor(w.q0, dtype=torch.float32, device="cuda")
+        t0 = time.time()
+        h = R.RomBatch(w, q0=q0, use_graph=True)
+        torch.cuda.synchronize()
+        log("offline stage: %.2f s (%d instances, %d DOF)" % (time.time() - t0, w.n_inst,
+                                                             h.total_dof))
+        # warmup (first window captures the graph)
+        h.rom_step(z * args.warmup)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(s)
+        h.rom_step(z * args.steps)
+        ev1.record(s)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        ms_per_step = ms / args.steps
+        value = w.n_inst * z * args.steps / (ms / 1e3)
+        flags = h.status()
+        log("batched: %.3f ms per window, %.4g instance-steps/s, flags %s"
+            % (ms_per_step, value, np.unique(flags).tolist()))
+
+        # dominant kernel: the fused Galerkin pass (one launch = one pass over the basis)
+        reps = 50
+        ms_pass = h.profile(R.PROF_GALERKIN_PASS, reps)
+        r = w.r
+        tot = h.total_dof
+        bytes_pass = tot * r * 4 + tot * 4 + 2 * 2 * r * 4 * w.n_inst  # basis, q_ref, halo rows
+        achieved = bytes_pass / (ms_pass * 1e-3) / 1e9
+        roofline = dict(kernel="k_galerkin_pass", bound="hbm", achieved=round(achieved, 1),
+                        peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                        traffic=None, ms_per_launch=round(ms_pass, 5),
+                        bytes_per_launch=int(bytes_pass))
+        ms_proj = h.profile(R.PROF_ISVD_PROJECT, reps, h.get(R.GET_YCORR))
+        h.close()
+
+        # plain path: the same kernels per instance in a host loop, no graph
+        plain = None
+        if not args.no_plain:
+            idx = np.linspace(0, w.n_inst - 1, args.plain_inst).round().astype(int)
+            hs = []
+            for b in idx:
+                wb = W.burgers_batch_f32()
+                wb.n_cells = [w.n_cells[b]]
+                wb.phys = [w.phys[b]]
+                wb.q0 = w.instance(b)
+                hs.append(R.RomBatch(wb, q0=torch.as_tensor(wb.q0, dtype=torch.float32,
+                                                              device="cuda"), use_graph=False))
+            torch.cuda.synchronize()
+            for hb in hs:
+                hb.rom_step(z)
+            torch.cuda.synchronize()
+            nwin = max(1, args.steps // 4)
+            ev0.record(s)
+            for _ in range(nwin):
+                for hb in hs:
+                    hb.rom_step(z)
+            ev1.record(s)
+            torch.cuda.synchronize()
+            pms = ev0.elapsed_time(ev1)
+            sub_cells = sum(w.n_cells[b] for b in idx)
+            # per-instance time scales with N: extrapolate by the batch's total cells
+            plain_value = len(idx) * z * nwin / (pms / 1e3) * (sub_cells / len(idx)) / np.mean(w.n_cells)
+            plain = dict(value=plain_value, unit="steps/s", instances_timed=int(len(idx)),
+                         windows=nwin, speedup_batched=round(value / plain_value, 2))
+            for hb in hs:
+                hb.close()
+            log("plain: %.4g instance-steps/s (speed-up %.2fx)" % (plain_value, value / plain_value))
+
+        # FOM residual roofline on the 64 x 262,144 Euler shape (403 MB per evaluation)
+        we = W.euler_adjoint_f32(n_inst=64, n=262144)
+        he = R.RomBatch(we, q0=None, use_graph=False)
+        qe = torch.as_tensor(we.q0, dtype=torch.float32, device="cuda")
+        he.profile(R.PROF_RESIDUAL, 3, qe)
+        ms_res = he.profile(R.PROF_RESIDUAL, 50, qe)
+        cells = 64 * 262144
+        res_bytes = cells * 3 * 4 * 2
+        res_gbs = res_bytes / (ms_res * 1e-3) / 1e9
+        fom = dict(workload="euler_rusanov_64x262144_f32", ms_per_launch=round(ms_res, 5),
+                   cell_updates_per_s=cells / (ms_res * 1e-3), achieved_GBs=round(res_gbs, 1),
+                   frac_hbm=round(res_gbs / HBM_PEAK_GBS, 4), bytes_per_launch=res_bytes)
+        ms_vjp = he.profile(R.PROF_RESIDUAL_VJP, 20, qe)
+        fom["vjp_ms_per_launch"] = round(ms_vjp, 5)
+        fom["vjp_frac_hbm"] = round(cells * 3 * 4 * 3 / (ms_vjp * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        he.close()
+        log("R(q): %.4f ms, %.3g cell-updates/s, %.1f%% of HBM" % (ms_res, fom["cell_updates_per_s"],
+                                                                100 * fom["frac_hbm"]))
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w, args.cpu_seconds)
+        log("cpu baseline: %.4g steps/s on %d threads" % (cpu["value"], cpu["cores"]))
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "burgers_batch_f32", "n_inst": w.n_inst,
+                   "cells_total": int(sum(w.n_cells)), "r": w.r, "z": w.z, "dt": w.dt,
+                   "lambda": w.lam, "projection": "galerkin", "step": "one adaptation window "
+                   "(z fine steps + event) of all instances", "parallelism": "single GPU, batch"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "plain": plain,
+        "fom_residual": fom,
+        "isvd_project_ms": round(ms_proj, 5),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

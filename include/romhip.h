@@ -1,0 +1,238 @@
+/*
+ * romhip.h - C interface of the MI355X (gfx950) adaptive reduced-order-model
+ * hot path: full-order finite-volume residuals, backward-Euler full-order steps,
+ * the Brand incremental-SVD basis update with forgetting, hyper-reduction
+ * rebuilds and reduced time steps, for a batch of independent instances.
+ *
+ * Method: history-aware adaptive ROM via incremental SVD (Hedayat, Mohaghegh,
+ * Balzano, Huang, Duraisamy): Sec. 2 (full-order model), Sec. 3 (projection and
+ * hyper-reduction), Sec. 4 (correction signal, iSVD update, Alg. 1 and Alg. 2).
+ *
+ * Conventions shared by every call
+ *   Layout.  A batch holds n_inst independent instances.  Instance b has
+ *     n_cells[b] cells with n_var variables per cell (1 Burgers, 3 Euler,
+ *     12 reacting model).  State vectors are concatenated instance after
+ *     instance; inside an instance they are cell-major (all variables of cell 0,
+ *     then cell 1, ...): element (b, cell c, var v) sits at
+ *     dof_off[b] + c*n_var + v, dof_off = prefix sum of n_cells*n_var.
+ *     Bases are row-major per instance: row i (a degree of freedom) of the
+ *     N_b x r basis of instance b sits at (dof_off[b] + i)*r .. +r-1.
+ *   Precision.  cfg.precision selects the element type of every state/basis
+ *     buffer that crosses this interface: ROM_F32 -> float, ROM_F64 -> double.
+ *     Singular values, reduced coordinates, core SVD, pseudo-inverses and
+ *     reduced solves are always double.
+ *   Memory.  Every pointer documented "device" is caller-owned device memory
+ *     (e.g. a torch tensor) that the library only borrows for the enqueued
+ *     work; every pointer documented "host" is read before the call returns.
+ *     The handle owns all memory reachable from it; rom_destroy frees it.
+ *   Streams.  Every call enqueues its work on the given hipStream_t (NULL =
+ *     the default stream) and returns without synchronising, except
+ *     rom_get_status and the host-side rom_get of ROM_GET_COUNTERS.
+ *   Errors.  Argument and state errors are detected on the host, returned as
+ *     negative rom_status values, and leave the handle unchanged.  Conditions
+ *     detected on the device (Newton not converged, floors, non-finite values,
+ *     degenerate residual) set per-instance flag bits read by rom_get_status.
+ *     rom_last_error() returns a thread-local message for the last error.
+ *   Threading.  A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef ROMHIP_H
+#define ROMHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rom_batch* rom_handle;
+
+typedef enum {
+  ROM_OK = 0,
+  ROM_E_INVAL = -1,     /* bad argument: nothing enqueued, handle unchanged */
+  ROM_E_NOMEM = -2,     /* device allocation failed */
+  ROM_E_DEVICE = -3,    /* a HIP runtime call failed */
+  ROM_E_STATE = -6,     /* call not valid in the handle's current state */
+  ROM_E_UNSUPPORTED = -7
+} rom_status;
+
+/* per-instance device flag bits (rom_get_status) */
+enum {
+  ROM_FLAG_NEWTON_NOCONV = 1u << 0, /* a full-order Newton solve hit its cap */
+  ROM_FLAG_FLOOR = 1u << 1,         /* density/pressure/temperature floor engaged */
+  ROM_FLAG_NONFINITE = 1u << 2,     /* a non-finite value was produced */
+  ROM_FLAG_RHO_ZERO = 1u << 3,      /* iSVD residual below tau_rho: rho := 0 */
+  ROM_FLAG_SINGULAR = 1u << 4,      /* singular reduced or sampled matrix */
+  ROM_FLAG_ROM_NOCONV = 1u << 5,    /* a reduced Newton / Gauss-Newton hit its cap */
+  ROM_FLAG_REORTH = 1u << 6         /* basis re-orthonormalised at least once */
+};
+
+enum { ROM_BURGERS = 0, ROM_EULER_RUSANOV = 1, ROM_EULER_HLLC = 2, ROM_REACT = 3 };
+enum { ROM_F32 = 0, ROM_F64 = 1 };
+enum { ROM_GALERKIN = 0, ROM_LSPG = 1 };
+enum { ROM_HR_NONE = 0, ROM_HR_DEIM = 1 };
+
+/*
+ * Batch configuration (Alg. 1 inputs: r, n_s, w_init, z, lambda; the time step
+ * and the Newton settings of Sec. 5).
+ *   phys: host, n_inst * n_phys doubles, instance-major:
+ *     ROM_BURGERS              n_phys = 1: viscosity nu
+ *     ROM_EULER_RUSANOV/HLLC   n_phys = 1: gamma
+ *     ROM_REACT                n_phys = 88: nu_u, kappa, A, k_in, x_in, T_in,
+ *                              Y_in[10], then for the 12 reactions the species
+ *                              indices a[12], b[12], c[12], d[12] (as doubles),
+ *                              activation energies E[12], heat releases Q[12]
+ *   newton_tol: sup-norm tolerance of the full-order Newton residual
+ *   rom_tol:    reduced Newton stops when max|delta| <= rom_tol (1 + max|a|)
+ *   reorth_every / tau_orth: every reorth_every basis updates the Gram matrix
+ *               G = Phi^T Phi is formed in FP64; if max|G - I| > tau_orth the
+ *               basis is replaced by Phi L^-T (G = L L^T).  0 disables.
+ *   tau_rho:    iSVD residual norm below tau_rho * ||y^|| is treated as zero
+ *   use_graph:  rom_step captures each adaptation window (z fine steps plus the
+ *               event) into a HIP graph on first use and replays it afterwards
+ */
+typedef struct {
+  int32_t problem, precision, projection, hyper;
+  int32_t n_inst;
+  const int64_t* n_cells; /* host [n_inst], each >= 3 */
+  const double* phys;     /* host [n_inst * n_phys] */
+  int32_t n_phys;
+  int32_t r, n_s, w_init, z;
+  int32_t newton_max, rom_max, reorth_every;
+  int32_t use_graph;
+  double lambda, dt, newton_tol, rom_tol, tau_orth, tau_rho;
+} rom_config;
+
+/* quantities exchanged by rom_get / rom_set (element type and size) */
+enum {
+  ROM_GET_BASIS = 0,   /* T[total_dof * r]       Phi                         */
+  ROM_GET_SIGMA = 1,   /* double[n_inst * r]     singular values             */
+  ROM_GET_A = 2,       /* double[n_inst * r]     reduced coordinates a^n     */
+  ROM_GET_QTILDE = 3,  /* T[total_dof]           q_ref + D^-1 Phi a (get only) */
+  ROM_GET_SAMPLES = 4, /* int32[n_inst * n_s]    DEIM rows (instance-local DOF index, pick order) */
+  ROM_GET_YCORR = 5,   /* T[total_dof]           coarse correction state     */
+  ROM_GET_QREF = 6,    /* T[total_dof]           reference state             */
+  ROM_GET_DVAR = 7,    /* double[n_inst * n_var] diagonal of D per variable  */
+  ROM_GET_PINV = 8,    /* double[n_inst * r * n_s] (P^T Phi)^+ row-major     */
+  ROM_GET_COUNTERS = 9 /* int64[4] host: fine step n, updates k, events, reorths */
+};
+
+/*
+ * rom_create - allocate a batch handle (layout, constants, workspaces) and, if
+ * q0 is not NULL, run the offline part of Alg. 1 on the device: w_init fine
+ * backward-Euler steps from q0, preprocessing (q_ref = q0, D from the mean
+ * square of the centred training data, Sec. 3.1 eq. variable_normalization),
+ * POD to rank r, a = Phi^T D (q^{w_init} - q_ref), the first coarse step
+ * y_corr (eq. coarse_fom_backward_euler), and the first sampling / rebuild.
+ *   q0: device, T[total_dof] or NULL (then only fom_* calls and rom_set are
+ *       valid until the reduced state is loaded).
+ *   Errors: ROM_E_INVAL for inconsistent settings (r < 1, r > min N_b,
+ *   n_s outside [r, 2r] with DEIM, z < 1, lambda outside [0, 1], ...).
+ */
+rom_status rom_create(const rom_config* cfg, const void* q0, void* stream, rom_handle* out);
+rom_status rom_destroy(rom_handle h);
+
+/*
+ * fom_residual - full-order residual for every instance in one launch.
+ *   q_prev == NULL: out = f(q)                       (Sec. 2 eq. fom_continuous)
+ *   otherwise:      out = q - q_prev - dt f(q)       (backward-Euler residual,
+ *                                                    eq. be_residual_rom_section)
+ *   q, q_prev, out: device, T[total_dof]; out must not alias q or q_prev.
+ */
+rom_status fom_residual(rom_handle h, const void* q, const void* q_prev, double dt, void* out,
+                        void* stream);
+
+/*
+ * fom_step - one backward-Euler full-order step of size dt for every instance:
+ * Newton on q - q_prev - dt f(q) = 0 from q = q_prev with the exact banded
+ * Jacobian and a direct block-tridiagonal solve; stops per instance when
+ * max|r| <= newton_tol, at most newton_max solves (Sec. 5.1 setup; App. B).
+ *   q_prev, q_out: device, T[total_dof]; may alias.
+ *   iters (optional): device int32[n_inst], Newton solves used per instance.
+ */
+rom_status fom_step(rom_handle h, const void* q_prev, double dt, void* q_out, int32_t* iters,
+                    void* stream);
+
+/*
+ * isvd_update - one iSVD basis update per instance (Alg. 2), with the
+ * snapshot preprocessed inside: y^ = D (y - q_ref).  p and the residual by two
+ * classical Gram-Schmidt passes (eq. isvd_residual), core K (eq.
+ * isvd_core_matrix) decomposed in FP64, basis rotated and truncated to r
+ * (eqs. isvd_updated_basis_full, isvd_truncation).  The reduced coordinates a
+ * are carried to the new basis (Alg. 1 state transfer, in the exact closed
+ * form a <- Ubar[:r,:r]^T a) and the re-orthonormalisation schedule runs.
+ *   y: device, T[total_dof].
+ */
+rom_status isvd_update(rom_handle h, const void* y, void* stream);
+
+/*
+ * rom_rebuild - refresh every basis-dependent quantity: with DEIM, the greedy
+ * sample rows (n_s = r .. 2r), the sample mesh (the sampled cells and their
+ * two neighbours), the gathered basis / q_ref rows and (P^T Phi)^+ in FP64
+ * (Alg. 1 sampling and operator update; eq. qdeim_approximation_phi).
+ */
+rom_status rom_rebuild(rom_handle h, void* stream);
+
+/*
+ * rom_step - advance the online loop of Alg. 1 by n_fine fine steps: each step
+ * solves the reduced backward-Euler system (Galerkin: eq.
+ * galerkin_continuous_rom; hyper-reduced LSPG: eq.
+ * hyperreduced_lspg_stationarity) by Newton / Gauss-Newton with FP64 reduced
+ * solves, and every z steps runs an adaptation event: coarse full-order step
+ * of y_corr with step z dt, iSVD update, rebuild, state transfer.
+ */
+rom_status rom_step(rom_handle h, int32_t n_fine, void* stream);
+
+/* copy a handle quantity to (get) or from (set) caller device memory; see ROM_GET_* */
+rom_status rom_get(rom_handle h, int32_t what, void* dst, void* stream);
+rom_status rom_set(rom_handle h, int32_t what, const void* src, void* stream);
+
+/* synchronise the handle's last stream and copy the per-instance flag words to host */
+rom_status rom_get_status(rom_handle h, uint32_t* host_flags);
+/* zero the per-instance flag words */
+rom_status rom_clear_status(rom_handle h, void* stream);
+
+/*
+ * fom_residual_vjp - vector-Jacobian product of the residual:
+ *   q_prev == NULL: gq = J_f(q)^T gbar
+ *   otherwise:      gq = gbar - dt J_f(q)^T gbar,  gq_prev = -gbar (if not NULL)
+ *   All device, T[total_dof].
+ */
+rom_status fom_residual_vjp(rom_handle h, const void* q, const void* q_prev, double dt,
+                            const void* gbar, void* gq, void* gq_prev, void* stream);
+
+/*
+ * fom_step_vjp - adjoint of one converged backward-Euler step q = S(q_prev):
+ * given gbar = dL/dq, returns dL/dq_prev = J_r(q)^-T gbar (implicit function
+ * theorem on r(q, q_prev) = q - q_prev - dt f(q) = 0).
+ *   q: device, the converged step output; gbar, gq_prev: device; all T[total_dof].
+ */
+rom_status fom_step_vjp(rom_handle h, const void* q, double dt, const void* gbar, void* gq_prev,
+                        void* stream);
+
+/*
+ * rom_profile - time one stage of the hot path in isolation: the stage is
+ * launched reps times between two HIP events recorded on the given stream and
+ * the mean milliseconds per launch are written to *ms.  The handle's reduced
+ * state is not modified.
+ *   ROM_PROF_RESIDUAL       f(q) for the batch (one launch), q: device T[total_dof]
+ *   ROM_PROF_GALERKIN_PASS  one fused Galerkin pass over the basis (all instances)
+ *   ROM_PROF_ISVD_PROJECT   one iSVD projection pass over the basis with snapshot q
+ *   ROM_PROF_RESIDUAL_VJP   J_f(q)^T q for the batch
+ *   ROM_PROF_FOM_STEP       one full backward-Euler Newton step from q (dt = cfg.dt)
+ * Synchronises the stream.  Errors: ROM_E_INVAL for an unknown stage or reps < 1.
+ */
+enum { ROM_PROF_RESIDUAL = 0, ROM_PROF_GALERKIN_PASS = 1, ROM_PROF_ISVD_PROJECT = 2,
+       ROM_PROF_RESIDUAL_VJP = 3, ROM_PROF_FOM_STEP = 4 };
+rom_status rom_profile(rom_handle h, int32_t stage, int32_t reps, const void* q, double* ms,
+                       void* stream);
+
+/* sizes of the handle's layout: total_dof, n_var, r, n_s (any may be NULL) */
+rom_status rom_query(rom_handle h, int64_t* total_dof, int32_t* n_var, int32_t* r, int32_t* n_s);
+
+const char* rom_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ROMHIP_H */

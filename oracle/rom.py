@@ -86,8 +86,17 @@ def isvd_update(Phi, sigma, yhat, lam, r, tau_rho=1e-12):
     K[:k, :k] = lam * np.diag(sigma)
     K[:k, k] = p
     K[k, k] = rho
-    Ub, sb, _ = np.linalg.svd(K)
-    Ub = sign_fix(Ub)
+    if degenerate:
+        # the residual direction carries nothing: decompose the k x (k+1) block
+        # [lambda Sigma, p] so that only directions inside span(Phi) can be kept
+        Uk, sk, _ = np.linalg.svd(K[:k, :])
+        Ub = np.zeros((k + 1, k + 1))
+        Ub[:k, :k] = sign_fix(Uk)
+        Ub[k, k] = 1.0
+        sb = np.concatenate([sk, [0.0]])
+    else:
+        Ub, sb, _ = np.linalg.svd(K)
+        Ub = sign_fix(Ub)
     Phi_t = np.concatenate([Phi, j[:, None]], axis=1) @ Ub
     r_out = min(r, k + 1)
     info = dict(p=p, rho=rho, K=K, Ubar=Ub, sbar=sb, degenerate=degenerate)

@@ -1,0 +1,579 @@
+// C interface of the romhip library: argument checking, batch layout, device
+// allocation, the backward-Euler Newton driver and the Alg. 1 driver.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace romhip {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+namespace {
+
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_i32v(int32_t* p, int32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_copy_bytes(const uint32_t* src, uint32_t* dst, int64_t nwords) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nwords) dst[i] = src[i];
+}
+
+// Newton bookkeeping.  norms holds three (newton_max+1) x n_inst blocks: the
+// residual sup norm of each iterate (bits of a T), the iterate's sup norm
+// (bits of a T) and the sup norm of each Newton update (bits of a double).
+// Converged when ||r||_inf <= tol.  In single precision the residual of the
+// rounded solution cannot go below about eps ||J_r|| ||y||, which exceeds an
+// absolute tolerance on fine grids, so an FP32 iterate also counts as
+// converged once the last update is at round-off level:
+// ||delta||_inf <= 8 eps_32 (1 + ||y||_inf).
+template <typename T>
+__device__ __forceinline__ double bits_to(uint64_t v) {
+  return sizeof(T) == 4 ? (double)__uint_as_float((uint32_t)v) : __longlong_as_double((long long)v);
+}
+
+template <typename T>
+__device__ bool newton_converged(const uint64_t* norms, int it, int mx, int n_inst, int b,
+                                 double tol) {
+  const uint64_t rb = norms[(size_t)it * n_inst + b];
+  if (rb != ~0ull && bits_to<T>(rb) <= tol) return true;
+  if (sizeof(T) == 4 && it > 0) {
+    const uint64_t db = norms[(size_t)(2 * (mx + 1) + it - 1) * n_inst + b];
+    const int iy = it < mx ? it : it - 1;
+    const double yn = bits_to<T>(norms[(size_t)(mx + 1 + iy) * n_inst + b]);
+    const double dn = __longlong_as_double((long long)db);
+    if (db != ~0ull && dn <= 8.0 * 1.1920928955078125e-07 * (1.0 + yn)) return true;
+  }
+  return false;
+}
+
+template <typename T>
+__global__ void k_newton_decide(int n_inst, const uint64_t* norms, int it, int mx, double tol,
+                                int32_t* active, int32_t* iters) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_inst || !active[b]) return;
+  if (newton_converged<T>(norms, it, mx, n_inst, b, tol)) active[b] = 0;
+  else iters[b] += 1;
+}
+
+template <typename T>
+__global__ void k_newton_final(int n_inst, const uint64_t* norms, int mx, double tol,
+                               const int32_t* active, uint32_t* flags) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_inst || !active[b]) return;
+  if (!newton_converged<T>(norms, mx, mx, n_inst, b, tol))
+    atomicOr(&flags[b], ROM_FLAG_NEWTON_NOCONV);
+}
+
+inline int nblk(int64_t n, int t = 256) { return (int)((n + t - 1) / t); }
+
+rom_status copy_words(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  // device-to-device copy as a kernel (graph-safe; no memcpy nodes)
+  const int64_t nw = (int64_t)(bytes / 4);
+  if (nw) hipLaunchKernelGGL(k_copy_bytes, dim3(nblk(nw)), dim3(256), 0, s, (const uint32_t*)src,
+                             (uint32_t*)dst, nw);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+rom_status validate(const rom_config* c) {
+  ROM_REQUIRE(c, ROM_E_INVAL, "cfg is NULL");
+  ROM_REQUIRE(c->problem >= ROM_BURGERS && c->problem <= ROM_REACT, ROM_E_INVAL, "unknown problem");
+  ROM_REQUIRE(c->precision == ROM_F32 || c->precision == ROM_F64, ROM_E_INVAL, "bad precision");
+  ROM_REQUIRE(c->projection == ROM_GALERKIN || c->projection == ROM_LSPG, ROM_E_INVAL,
+              "bad projection");
+  ROM_REQUIRE(c->hyper == ROM_HR_NONE || c->hyper == ROM_HR_DEIM, ROM_E_INVAL, "bad hyper");
+  ROM_REQUIRE(c->n_inst >= 1, ROM_E_INVAL, "n_inst must be >= 1");
+  ROM_REQUIRE(c->n_cells && c->phys, ROM_E_INVAL, "n_cells and phys are required");
+  const int need = c->problem == ROM_REACT ? 88 : 1;
+  ROM_REQUIRE(c->n_phys == need, ROM_E_INVAL, "n_phys does not match the problem");
+  int64_t mn = INT64_MAX;
+  for (int b = 0; b < c->n_inst; ++b) {
+    ROM_REQUIRE(c->n_cells[b] >= 3, ROM_E_INVAL, "every instance needs at least 3 cells");
+    ROM_REQUIRE(c->n_cells[b] <= (int64_t)1 << 31, ROM_E_INVAL, "instance too large");
+    mn = std::min(mn, c->n_cells[b]);
+  }
+  const int nv = c->problem == ROM_REACT ? 12 : (c->problem == ROM_BURGERS ? 1 : 3);
+  ROM_REQUIRE(c->r >= 1 && c->r <= kMaxR, ROM_E_INVAL, "r must be in [1, 64]");
+  ROM_REQUIRE(c->r <= mn * nv, ROM_E_INVAL, "r exceeds the smallest instance");
+  ROM_REQUIRE(c->w_init >= c->r && c->w_init <= 100, ROM_E_INVAL, "w_init must be in [r, 100]");
+  ROM_REQUIRE(c->z >= 1, ROM_E_INVAL, "z must be >= 1");
+  ROM_REQUIRE(c->lambda >= 0.0 && c->lambda <= 1.0, ROM_E_INVAL, "lambda must be in [0, 1]");
+  ROM_REQUIRE(c->dt > 0.0 && std::isfinite(c->dt), ROM_E_INVAL, "dt must be positive");
+  ROM_REQUIRE(c->newton_max >= 1 && c->newton_max <= 50, ROM_E_INVAL, "newton_max in [1, 50]");
+  ROM_REQUIRE(c->rom_max >= 1 && c->rom_max <= 50, ROM_E_INVAL, "rom_max in [1, 50]");
+  ROM_REQUIRE(c->newton_tol > 0.0 && c->rom_tol > 0.0, ROM_E_INVAL, "tolerances must be positive");
+  ROM_REQUIRE(c->reorth_every >= 0, ROM_E_INVAL, "reorth_every must be >= 0");
+  if (c->hyper == ROM_HR_DEIM) {
+    ROM_REQUIRE(c->n_s >= c->r && c->n_s <= 2 * c->r && c->n_s <= kMaxNs, ROM_E_INVAL,
+                "n_s must be in [r, 2r] with DEIM");
+    ROM_REQUIRE(c->n_s <= mn * nv, ROM_E_INVAL, "n_s exceeds the smallest instance");
+  } else {
+    ROM_REQUIRE(c->problem == ROM_BURGERS, ROM_E_UNSUPPORTED,
+                "the full Galerkin ROM (no hyper-reduction) is implemented for Burgers");
+    ROM_REQUIRE(c->projection == ROM_GALERKIN, ROM_E_UNSUPPORTED,
+                "without hyper-reduction only the Galerkin projection is implemented");
+  }
+  return ROM_OK;
+}
+
+template <typename T>
+rom_status alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return ROM_OK;
+  if (hipMalloc((void**)p, sizeof(T) * count) != hipSuccess) {
+    set_error("hipMalloc failed");
+    return ROM_E_NOMEM;
+  }
+  return ROM_OK;
+}
+
+#define ROM_TRY(x)                 \
+  do {                             \
+    rom_status _s = (x);           \
+    if (_s != ROM_OK) return _s;   \
+  } while (0)
+
+void free_all(rom_batch* h) {
+  void* ps[] = {h->d_dof_off, h->d_cell_off, h->d_phys, h->d_tiles, h->d_ptiles, h->d_ptile_first,
+                h->Phi, h->sigma, h->a, h->a_prev, h->q_ref, h->d_var, h->y_corr, h->flags, h->P,
+                h->M, h->mesh_phi, h->mesh_qref, h->chosen, h->part, h->red, h->ubar, h->lmat,
+                h->active, h->iters, h->norms, h->rstate, h->qtmp, h->mpart, h->fq, h->fq_prev, h->vjp_tmp,
+                h->d_epoch};
+  for (void* p : ps) (void)hipFree(p);
+  bt_free(h);
+  if (h->win_exec) (void)hipGraphExecDestroy(h->win_exec);
+}
+
+rom_status setup(rom_batch* h) {
+  const rom_config& c = h->cfg;
+  const int B = c.n_inst;
+  h->nv = c.problem == ROM_REACT ? 12 : (c.problem == ROM_BURGERS ? 1 : 3);
+  h->esz = c.precision == ROM_F64 ? 8 : 4;
+  h->dof_off.assign(B + 1, 0);
+  h->cell_off.assign(B + 1, 0);
+  for (int b = 0; b < B; ++b) {
+    h->cell_off[b + 1] = h->cell_off[b] + h->n_cells[b];
+    h->dof_off[b + 1] = h->dof_off[b] + h->n_cells[b] * h->nv;
+    h->max_dof = std::max(h->max_dof, h->n_cells[b] * h->nv);
+  }
+  h->total_cells = h->cell_off[B];
+  h->total_dof = h->dof_off[B];
+  // stencil tiles (cells) and pass tiles (basis rows)
+  std::vector<Tile> tiles, ptiles;
+  h->ptile_first.assign(B + 1, 0);
+  for (int b = 0; b < B; ++b) {
+    for (int64_t c0 = 0; c0 < h->n_cells[b]; c0 += kTile)
+      tiles.push_back(Tile{b, 0, c0, std::min<int64_t>(kTile, h->n_cells[b] - c0)});
+    const int64_t rows = h->n_cells[b] * h->nv;
+    h->ptile_first[b] = (int)ptiles.size();
+    for (int64_t r0 = 0; r0 < rows; r0 += kPassRows)
+      ptiles.push_back(Tile{b, 0, r0, std::min<int64_t>(kPassRows, rows - r0)});
+  }
+  h->ptile_first[B] = (int)ptiles.size();
+  h->n_tiles = (int)tiles.size();
+  h->n_ptiles = (int)ptiles.size();
+  const size_t es = h->esz;
+  const int r = c.r;
+  ROM_TRY(alloc(&h->d_dof_off, B + 1));
+  ROM_TRY(alloc(&h->d_cell_off, B + 1));
+  ROM_TRY(alloc(&h->d_phys, h->phys.size()));
+  ROM_TRY(alloc(&h->d_tiles, tiles.size()));
+  ROM_TRY(alloc(&h->d_ptiles, ptiles.size()));
+  ROM_TRY(alloc(&h->d_ptile_first, B + 1));
+  ROM_HIP_CHECK(hipMemcpy(h->d_dof_off, h->dof_off.data(), 8 * (B + 1), hipMemcpyHostToDevice));
+  ROM_HIP_CHECK(hipMemcpy(h->d_cell_off, h->cell_off.data(), 8 * (B + 1), hipMemcpyHostToDevice));
+  ROM_HIP_CHECK(hipMemcpy(h->d_phys, h->phys.data(), 8 * h->phys.size(), hipMemcpyHostToDevice));
+  ROM_HIP_CHECK(hipMemcpy(h->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice));
+  ROM_HIP_CHECK(hipMemcpy(h->d_ptiles, ptiles.data(), sizeof(Tile) * ptiles.size(), hipMemcpyHostToDevice));
+  ROM_HIP_CHECK(hipMemcpy(h->d_ptile_first, h->ptile_first.data(), sizeof(int) * (B + 1),
+                          hipMemcpyHostToDevice));
+  const int64_t td = h->total_dof;
+  const int ns = std::max(c.n_s, 1);
+  ROM_TRY(alloc((char**)&h->Phi, es * td * r));
+  ROM_TRY(alloc(&h->sigma, (size_t)B * r));
+  ROM_TRY(alloc(&h->a, (size_t)B * r));
+  ROM_TRY(alloc(&h->a_prev, (size_t)B * r));
+  ROM_TRY(alloc((char**)&h->q_ref, es * td));
+  ROM_TRY(alloc(&h->d_var, (size_t)B * h->nv));
+  ROM_TRY(alloc((char**)&h->y_corr, es * td));
+  ROM_TRY(alloc((char**)&h->fq, es * td));
+  ROM_TRY(alloc((char**)&h->fq_prev, es * td));
+  ROM_TRY(alloc((char**)&h->vjp_tmp, es * td));
+  ROM_TRY(alloc(&h->flags, B));
+  ROM_TRY(alloc(&h->P, (size_t)B * ns));
+  ROM_TRY(alloc(&h->M, (size_t)B * r * ns));
+  ROM_TRY(alloc(&h->mesh_phi, (size_t)B * ns * 3 * h->nv * r));
+  ROM_TRY(alloc(&h->mesh_qref, (size_t)B * ns * 3 * h->nv));
+  ROM_TRY(alloc(&h->chosen, (size_t)td));
+  ROM_TRY(alloc(&h->part, (size_t)std::max(h->n_ptiles, 1) * kMaxR * kMaxR));
+  ROM_TRY(alloc(&h->red, (size_t)B * (2 * 128 + 8)));
+  ROM_TRY(alloc(&h->ubar, (size_t)B * (r + 1) * (r + 1)));
+  ROM_TRY(alloc(&h->lmat, (size_t)B * r * r));
+  ROM_TRY(alloc(&h->active, B));
+  ROM_TRY(alloc(&h->iters, B));
+  ROM_TRY(alloc(&h->norms, (size_t)3 * (c.newton_max + 1) * B));
+  ROM_TRY(alloc(&h->rstate, (size_t)B * (kMaxR * kMaxR + 4 * kMaxR)));
+  ROM_TRY(alloc(&h->qtmp, (size_t)td));
+  ROM_TRY(alloc((char**)&h->mpart, es * std::max(h->n_ptiles, 1) * kMaxR * kMaxR));
+  ROM_TRY(alloc(&h->d_epoch, 1));
+  ROM_HIP_CHECK(hipMemset(h->flags, 0, 4 * B));
+  ROM_HIP_CHECK(hipMemset(h->chosen, 0, 4 * td));
+  ROM_HIP_CHECK(hipMemset(h->d_epoch, 0, 4));
+  ROM_HIP_CHECK(hipMemset(h->P, 0, 4 * (size_t)B * ns));
+  ROM_HIP_CHECK(hipMemset(h->a, 0, 8 * (size_t)B * r));
+  ROM_HIP_CHECK(hipMemset(h->sigma, 0, 8 * (size_t)B * r));
+  ROM_TRY(bt_setup(h));
+  ROM_TRY(isvd_kernels_prepare());
+  ROM_TRY(rom_kernels_prepare());
+  ROM_HIP_CHECK(hipDeviceSynchronize());
+  return ROM_OK;
+}
+
+// One backward-Euler step of size dt for every instance (Newton, exact banded
+// Jacobian, direct block-tridiagonal solve).  q_prev and q_out may alias.
+rom_status fom_step_impl(rom_batch* h, const void* q_prev, double dt, void* q_out,
+                         int32_t* iters_out, hipStream_t s) {
+  const int B = h->cfg.n_inst;
+  const size_t bytes = h->esz * h->total_dof;
+  const bool f64 = h->cfg.precision == ROM_F64;
+  ROM_TRY(copy_words(q_prev, h->fq_prev, bytes, s));
+  ROM_TRY(copy_words(q_prev, h->fq, bytes, s));
+  const int mx = h->cfg.newton_max;
+  hipLaunchKernelGGL(k_fill_i32v, dim3(nblk(B)), dim3(256), 0, s, h->active, 1, (int64_t)B);
+  hipLaunchKernelGGL(k_fill_i32v, dim3(nblk(B)), dim3(256), 0, s, h->iters, 0, (int64_t)B);
+  const int64_t nn = (int64_t)3 * (mx + 1) * B;
+  hipLaunchKernelGGL(k_fill_u64, dim3(nblk(nn)), dim3(256), 0, s, h->norms, (uint64_t)0, nn);
+  for (int it = 0; it < mx; ++it) {
+    ROM_TRY(launch_assemble(h, h->fq, h->fq_prev, dt, it, s));
+    if (f64)
+      hipLaunchKernelGGL(k_newton_decide<double>, dim3(nblk(B)), dim3(256), 0, s, B, h->norms,
+                         it, mx, h->cfg.newton_tol, h->active, h->iters);
+    else
+      hipLaunchKernelGGL(k_newton_decide<float>, dim3(nblk(B)), dim3(256), 0, s, B, h->norms,
+                         it, mx, h->cfg.newton_tol, h->active, h->iters);
+    ROM_TRY(bt_solve(h, it, h->fq, nullptr, s));
+  }
+  ROM_TRY(launch_residual_norm(h, h->fq, h->fq_prev, dt, h->vjp_tmp, mx, s));
+  if (f64)
+    hipLaunchKernelGGL(k_newton_final<double>, dim3(nblk(B)), dim3(256), 0, s, B, h->norms, mx,
+                       h->cfg.newton_tol, h->active, h->flags);
+  else
+    hipLaunchKernelGGL(k_newton_final<float>, dim3(nblk(B)), dim3(256), 0, s, B, h->norms, mx,
+                       h->cfg.newton_tol, h->active, h->flags);
+  ROM_TRY(copy_words(h->fq, q_out, bytes, s));
+  if (iters_out) ROM_TRY(copy_words(h->iters, iters_out, 4 * (size_t)B, s));
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+rom_status isvd_impl(rom_batch* h, const void* y, hipStream_t s) {
+  ROM_TRY(launch_isvd(h, y, s));
+  h->n_update += 1;
+  if (h->cfg.reorth_every > 0 && h->n_update % h->cfg.reorth_every == 0) {
+    ROM_TRY(launch_reorth(h, s));
+    h->n_reorth += 1;
+  }
+  return ROM_OK;
+}
+
+// One adaptation window unit: a fine reduced step and, if due, the event.
+rom_status fine_step_impl(rom_batch* h, hipStream_t s) {
+  ROM_TRY(launch_rom_fine_step(h, s));
+  const int64_t n = h->n_fine;
+  if ((n + 1 - h->cfg.w_init) % h->cfg.z == 0) {
+    ROM_TRY(fom_step_impl(h, h->y_corr, h->cfg.z * h->cfg.dt, h->y_corr, nullptr, s));
+    ROM_TRY(isvd_impl(h, h->y_corr, s));
+    ROM_TRY(launch_rebuild(h, s));
+    h->n_events += 1;
+  }
+  h->n_fine += 1;
+  return ROM_OK;
+}
+
+rom_status offline(rom_batch* h, const void* q0, hipStream_t s) {
+  const int w = h->cfg.w_init;
+  const size_t bytes = h->esz * h->total_dof;
+  char* Q = nullptr;
+  ROM_TRY(alloc(&Q, bytes * w));
+  rom_status st = ROM_OK;
+  const void* prev = q0;
+  for (int j = 0; j < w && st == ROM_OK; ++j) {
+    st = fom_step_impl(h, prev, h->cfg.dt, Q + bytes * j, nullptr, s);
+    prev = Q + bytes * j;
+  }
+  if (st == ROM_OK) st = launch_preprocess(h, q0, Q, w, s);
+  if (st == ROM_OK) st = launch_pod(h, Q, w, s);
+  const void* qlast = Q + bytes * (w - 1);
+  if (st == ROM_OK) st = launch_project_state(h, qlast, s);
+  if (st == ROM_OK) st = fom_step_impl(h, qlast, h->cfg.z * h->cfg.dt, h->y_corr, nullptr, s);
+  if (st == ROM_OK) st = launch_rebuild(h, s);
+  hipError_t e = hipStreamSynchronize(s);
+  (void)hipFree(Q);
+  if (st != ROM_OK) return st;
+  if (e != hipSuccess) { set_error(hipGetErrorString(e)); return ROM_E_DEVICE; }
+  h->n_fine = w;
+  h->has_rom = true;
+  return ROM_OK;
+}
+
+}  // namespace
+
+rom_status fill_zero(void* p, size_t bytes, hipStream_t s) {
+  const int64_t nw = (int64_t)(bytes / 4);
+  if (nw) hipLaunchKernelGGL(k_fill_u32, dim3(nblk(nw)), dim3(256), 0, s, (uint32_t*)p, 0u, nw);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+}  // namespace romhip
+
+using namespace romhip;
+
+extern "C" {
+
+const char* rom_last_error(void) { return g_err.c_str(); }
+
+rom_status rom_create(const rom_config* cfg, const void* q0, void* stream, rom_handle* out) {
+  ROM_REQUIRE(out, ROM_E_INVAL, "out is NULL");
+  *out = nullptr;
+  ROM_TRY(validate(cfg));
+  rom_batch* h = new (std::nothrow) rom_batch();
+  ROM_REQUIRE(h, ROM_E_NOMEM, "host allocation failed");
+  h->cfg = *cfg;
+  h->n_cells.assign(cfg->n_cells, cfg->n_cells + cfg->n_inst);
+  h->phys.assign(cfg->phys, cfg->phys + (size_t)cfg->n_inst * cfg->n_phys);
+  h->cfg.n_cells = nullptr;
+  h->cfg.phys = nullptr;
+  rom_status st = setup(h);
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  if (st == ROM_OK && q0) st = offline(h, q0, s);
+  if (st != ROM_OK) {
+    free_all(h);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return ROM_OK;
+}
+
+rom_status rom_destroy(rom_handle h) {
+  if (!h) return ROM_OK;
+  (void)hipDeviceSynchronize();
+  free_all(h);
+  delete h;
+  return ROM_OK;
+}
+
+rom_status rom_query(rom_handle h, int64_t* total_dof, int32_t* n_var, int32_t* r, int32_t* n_s) {
+  ROM_REQUIRE(h, ROM_E_INVAL, "handle is NULL");
+  if (total_dof) *total_dof = h->total_dof;
+  if (n_var) *n_var = h->nv;
+  if (r) *r = h->cfg.r;
+  if (n_s) *n_s = h->cfg.n_s;
+  return ROM_OK;
+}
+
+rom_status fom_residual(rom_handle h, const void* q, const void* q_prev, double dt, void* out,
+                        void* stream) {
+  ROM_REQUIRE(h && q && out, ROM_E_INVAL, "handle, q and out are required");
+  ROM_REQUIRE(out != q && out != q_prev, ROM_E_INVAL, "out must not alias q or q_prev");
+  ROM_REQUIRE(std::isfinite(dt), ROM_E_INVAL, "dt must be finite");
+  h->last_stream = (hipStream_t)stream;
+  return launch_residual(h, q, q_prev, dt, out, (hipStream_t)stream);
+}
+
+rom_status fom_step(rom_handle h, const void* q_prev, double dt, void* q_out, int32_t* iters,
+                    void* stream) {
+  ROM_REQUIRE(h && q_prev && q_out, ROM_E_INVAL, "handle, q_prev and q_out are required");
+  ROM_REQUIRE(dt > 0.0 && std::isfinite(dt), ROM_E_INVAL, "dt must be positive");
+  h->last_stream = (hipStream_t)stream;
+  return fom_step_impl(h, q_prev, dt, q_out, iters, (hipStream_t)stream);
+}
+
+rom_status isvd_update(rom_handle h, const void* y, void* stream) {
+  ROM_REQUIRE(h && y, ROM_E_INVAL, "handle and y are required");
+  ROM_REQUIRE(h->has_rom, ROM_E_STATE, "no reduced state: create with q0 or load with rom_set");
+  h->last_stream = (hipStream_t)stream;
+  return isvd_impl(h, y, (hipStream_t)stream);
+}
+
+rom_status rom_rebuild(rom_handle h, void* stream) {
+  ROM_REQUIRE(h, ROM_E_INVAL, "handle is NULL");
+  ROM_REQUIRE(h->has_rom, ROM_E_STATE, "no reduced state");
+  h->last_stream = (hipStream_t)stream;
+  return launch_rebuild(h, (hipStream_t)stream);
+}
+
+rom_status rom_step(rom_handle h, int32_t n_fine, void* stream) {
+  ROM_REQUIRE(h, ROM_E_INVAL, "handle is NULL");
+  ROM_REQUIRE(n_fine >= 0, ROM_E_INVAL, "n_fine must be >= 0");
+  ROM_REQUIRE(h->has_rom, ROM_E_STATE, "no reduced state");
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  const int z = h->cfg.z;
+  int done = 0;
+  const bool graphs = h->cfg.use_graph && s != nullptr;
+  while (done < n_fine) {
+    const int64_t pos = (h->n_fine - h->cfg.w_init) % z;  // steps since the last event
+    const bool aligned = pos == 0 && n_fine - done >= z;
+    const bool reorth_due =
+        h->cfg.reorth_every > 0 && (h->n_update + 1) % h->cfg.reorth_every == 0;
+    if (graphs && aligned && !reorth_due) {
+      if (!h->win_exec || h->win_stream != s) {
+        if (h->win_exec) { (void)hipGraphExecDestroy(h->win_exec); h->win_exec = nullptr; }
+        hipGraph_t g = nullptr;
+        ROM_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        rom_status st = ROM_OK;
+        const int64_t nf = h->n_fine, nu = h->n_update, ne = h->n_events;
+        for (int k = 0; k < z && st == ROM_OK; ++k) st = fine_step_impl(h, s);
+        hipError_t e = hipStreamEndCapture(s, &g);
+        h->n_fine = nf; h->n_update = nu; h->n_events = ne;  // captured, not yet run
+        if (st != ROM_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+        ROM_HIP_CHECK(e);
+        ROM_HIP_CHECK(hipGraphInstantiate(&h->win_exec, g, nullptr, nullptr, 0));
+        ROM_HIP_CHECK(hipGraphDestroy(g));
+        h->win_stream = s;
+      }
+      ROM_HIP_CHECK(hipGraphLaunch(h->win_exec, s));
+      h->n_fine += z;
+      h->n_update += 1;
+      h->n_events += 1;
+      done += z;
+    } else {
+      ROM_TRY(fine_step_impl(h, s));
+      done += 1;
+    }
+  }
+  return ROM_OK;
+}
+
+rom_status rom_get(rom_handle h, int32_t what, void* dst, void* stream) {
+  ROM_REQUIRE(h && dst, ROM_E_INVAL, "handle and dst are required");
+  hipStream_t s = (hipStream_t)stream;
+  const int B = h->cfg.n_inst, r = h->cfg.r;
+  const size_t td = (size_t)h->total_dof;
+  switch (what) {
+    case ROM_GET_BASIS: return copy_words(h->Phi, dst, h->esz * td * r, s);
+    case ROM_GET_SIGMA: return copy_words(h->sigma, dst, 8 * (size_t)B * r, s);
+    case ROM_GET_A: return copy_words(h->a, dst, 8 * (size_t)B * r, s);
+    case ROM_GET_QTILDE: return launch_reconstruct(h, dst, s);
+    case ROM_GET_SAMPLES: return copy_words(h->P, dst, 4 * (size_t)B * std::max(h->cfg.n_s, 1), s);
+    case ROM_GET_YCORR: return copy_words(h->y_corr, dst, h->esz * td, s);
+    case ROM_GET_QREF: return copy_words(h->q_ref, dst, h->esz * td, s);
+    case ROM_GET_DVAR: return copy_words(h->d_var, dst, 8 * (size_t)B * h->nv, s);
+    case ROM_GET_PINV: return copy_words(h->M, dst, 8 * (size_t)B * r * std::max(h->cfg.n_s, 1), s);
+    case ROM_GET_COUNTERS: {
+      int64_t* o = (int64_t*)dst;
+      o[0] = h->n_fine; o[1] = h->n_update; o[2] = h->n_events; o[3] = h->n_reorth;
+      return ROM_OK;
+    }
+  }
+  set_error("unknown quantity");
+  return ROM_E_INVAL;
+}
+
+rom_status rom_set(rom_handle h, int32_t what, const void* src, void* stream) {
+  ROM_REQUIRE(h && src, ROM_E_INVAL, "handle and src are required");
+  hipStream_t s = (hipStream_t)stream;
+  const int B = h->cfg.n_inst, r = h->cfg.r;
+  const size_t td = (size_t)h->total_dof;
+  if (h->win_exec) { (void)hipGraphExecDestroy(h->win_exec); h->win_exec = nullptr; }
+  switch (what) {
+    case ROM_GET_BASIS: h->has_rom = true; return copy_words(src, h->Phi, h->esz * td * r, s);
+    case ROM_GET_SIGMA: return copy_words(src, h->sigma, 8 * (size_t)B * r, s);
+    case ROM_GET_A: return copy_words(src, h->a, 8 * (size_t)B * r, s);
+    case ROM_GET_SAMPLES: return copy_words(src, h->P, 4 * (size_t)B * std::max(h->cfg.n_s, 1), s);
+    case ROM_GET_YCORR: return copy_words(src, h->y_corr, h->esz * td, s);
+    case ROM_GET_QREF: return copy_words(src, h->q_ref, h->esz * td, s);
+    case ROM_GET_DVAR: return copy_words(src, h->d_var, 8 * (size_t)B * h->nv, s);
+    case ROM_GET_COUNTERS: {
+      const int64_t* o = (const int64_t*)src;
+      h->n_fine = o[0]; h->n_update = o[1]; h->n_events = o[2]; h->n_reorth = o[3];
+      return ROM_OK;
+    }
+  }
+  set_error("quantity cannot be set");
+  return ROM_E_INVAL;
+}
+
+rom_status rom_get_status(rom_handle h, uint32_t* host_flags) {
+  ROM_REQUIRE(h && host_flags, ROM_E_INVAL, "handle and host_flags are required");
+  ROM_HIP_CHECK(hipStreamSynchronize(h->last_stream));
+  ROM_HIP_CHECK(hipMemcpy(host_flags, h->flags, 4 * (size_t)h->cfg.n_inst, hipMemcpyDeviceToHost));
+  return ROM_OK;
+}
+
+rom_status rom_clear_status(rom_handle h, void* stream) {
+  ROM_REQUIRE(h, ROM_E_INVAL, "handle is NULL");
+  return fill_zero(h->flags, 4 * (size_t)h->cfg.n_inst, (hipStream_t)stream);
+}
+
+rom_status fom_residual_vjp(rom_handle h, const void* q, const void* q_prev, double dt,
+                            const void* gbar, void* gq, void* gq_prev, void* stream) {
+  ROM_REQUIRE(h && q && gbar && gq, ROM_E_INVAL, "handle, q, gbar and gq are required");
+  ROM_REQUIRE(gq != gbar && gq != q, ROM_E_INVAL, "gq must not alias q or gbar");
+  h->last_stream = (hipStream_t)stream;
+  return launch_residual_vjp(h, q, q_prev, dt, gbar, gq, gq_prev, (hipStream_t)stream);
+}
+
+rom_status fom_step_vjp(rom_handle h, const void* q, double dt, const void* gbar, void* gq_prev,
+                        void* stream) {
+  ROM_REQUIRE(h && q && gbar && gq_prev, ROM_E_INVAL, "handle, q, gbar and gq_prev are required");
+  ROM_REQUIRE(dt > 0.0 && std::isfinite(dt), ROM_E_INVAL, "dt must be positive");
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  ROM_TRY(launch_assemble_adjoint(h, q, dt, gbar, s));
+  return bt_solve(h, -1, nullptr, gq_prev, s);
+}
+
+rom_status rom_profile(rom_handle h, int32_t stage, int32_t reps, const void* q, double* ms,
+                       void* stream) {
+  ROM_REQUIRE(h && ms, ROM_E_INVAL, "handle and ms are required");
+  ROM_REQUIRE(reps >= 1, ROM_E_INVAL, "reps must be >= 1");
+  ROM_REQUIRE(stage >= ROM_PROF_RESIDUAL && stage <= ROM_PROF_FOM_STEP, ROM_E_INVAL, "unknown stage");
+  ROM_REQUIRE(q || stage == ROM_PROF_GALERKIN_PASS, ROM_E_INVAL, "q is required for this stage");
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  // the Galerkin pass overwrites only scratch; keep a and the flags intact
+  hipEvent_t e0, e1;
+  ROM_HIP_CHECK(hipEventCreate(&e0));
+  ROM_HIP_CHECK(hipEventCreate(&e1));
+  rom_status st = ROM_OK;
+  ROM_HIP_CHECK(hipEventRecord(e0, s));
+  for (int i = 0; i < reps && st == ROM_OK; ++i) {
+    switch (stage) {
+      case ROM_PROF_RESIDUAL: st = launch_residual(h, q, nullptr, 0.0, h->vjp_tmp, s); break;
+      case ROM_PROF_GALERKIN_PASS: st = launch_galerkin_pass(h, s); break;
+      case ROM_PROF_ISVD_PROJECT: st = launch_isvd_project(h, q, s); break;
+      case ROM_PROF_RESIDUAL_VJP:
+        st = launch_residual_vjp(h, q, nullptr, 0.0, q, h->vjp_tmp, nullptr, s);
+        break;
+      case ROM_PROF_FOM_STEP: st = fom_step_impl(h, q, h->cfg.dt, h->fq_prev, nullptr, s); break;
+    }
+  }
+  ROM_HIP_CHECK(hipEventRecord(e1, s));
+  ROM_HIP_CHECK(hipEventSynchronize(e1));
+  float t = 0.f;
+  ROM_HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != ROM_OK) return st;
+  *ms = (double)t / reps;
+  return ROM_OK;
+}
+
+}  // extern "C"

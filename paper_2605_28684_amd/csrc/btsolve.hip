@@ -1,0 +1,461 @@
+// Direct solver for the block-tridiagonal Newton systems of the backward-Euler
+// full-order step (periodic models give cyclic systems, walls give plain ones):
+//     A_i x_{i-1} + B_i x_i + C_i x_{i+1} = d_i,   i = 0..n-1 (indices cyclic),
+// with NV x NV blocks; for wall problems A_0 = C_{n-1} = 0.
+//
+// Method: recursive Schur complement on part separators.  Each instance is cut
+// into parts of m consecutive cells whose last cell is a separator.  One thread
+// eliminates the m-1 interior cells of its part by block Thomas, expressing
+// them as x_j = g_j - V_j x_{sep left} - W_j x_{sep right}.  Substituting the
+// first/last interior expressions into the separator rows gives a system of the
+// same block-tridiagonal (cyclic) form over the separators, which is solved the
+// same way until one cell per instance remains; back-substitution then walks the
+// levels down.  Work is O(n NV^3); every level is one launch over all instances.
+#include <algorithm>
+
+#include "internal.h"
+#include "physics.h"
+
+namespace romhip {
+
+namespace {
+
+template <typename T, int NV>
+DEV void mm(const T* A, const T* B, T* C) {  // C = A B
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      T s = T(0);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) s += A[i * NV + k] * B[k * NV + j];
+      C[i * NV + j] = s;
+    }
+}
+template <typename T, int NV>
+DEV void mv(const T* A, const T* x, T* y) {  // y = A x
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    T s = T(0);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s += A[i * NV + k] * x[k];
+    y[i] = s;
+  }
+}
+
+// Gauss-Jordan inverse with partial pivoting; returns false if singular.
+template <typename T, int NV>
+DEV bool inv_block(const T* A, T* X) {
+  T a[NV * NV];
+#pragma unroll
+  for (int e = 0; e < NV * NV; ++e) { a[e] = A[e]; X[e] = (e % (NV + 1)) == 0 ? T(1) : T(0); }
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    int p = k;
+    T best = fabs(a[k * NV + k]);
+#pragma unroll
+    for (int i = k + 1; i < NV; ++i) {
+      const T v = fabs(a[i * NV + k]);
+      if (v > best) { best = v; p = i; }
+    }
+#pragma unroll
+    for (int i = k + 1; i < NV; ++i) {
+      if (i == p) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+          T t = a[k * NV + j]; a[k * NV + j] = a[i * NV + j]; a[i * NV + j] = t;
+          t = X[k * NV + j]; X[k * NV + j] = X[i * NV + j]; X[i * NV + j] = t;
+        }
+      }
+    }
+    const T piv = a[k * NV + k];
+    if (!(piv != T(0))) ok = false;
+    const T ip = ok ? T(1) / piv : T(0);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) { a[k * NV + j] *= ip; X[k * NV + j] *= ip; }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      if (i == k) continue;
+      const T fct = a[i * NV + k];
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        a[i * NV + j] -= fct * a[k * NV + j];
+        X[i * NV + j] -= fct * X[k * NV + j];
+      }
+    }
+  }
+  return ok;
+}
+
+DEV int find_inst(const int64_t* off, int n_inst, int64_t g) {
+  int lo = 0, hi = n_inst;  // off[lo] <= g < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T, int NV>
+struct Lay {
+  static constexpr int NN = NV * NV;
+  static constexpr int SYS = 3 * NN + NV;   // A, B, C, d
+  static constexpr int FWD = 2 * NN + NV;   // Chat, Vhat, ghat
+  static constexpr int PRT = 3 * NN + NV;   // What_last, V_first, W_first, g_first
+};
+
+// Forward elimination of the interior of each part and the affine expression of
+// its first interior cell.
+template <typename T, int NV>
+__global__ __launch_bounds__(256) void k_bt_factor(int n_inst, const int64_t* __restrict__ cell_off,
+                                                   const int64_t* __restrict__ part_off, int m,
+                                                   const T* __restrict__ sys, T* __restrict__ fwd,
+                                                   T* __restrict__ prt, const int32_t* active,
+                                                   uint32_t* flags) {
+  using L = Lay<T, NV>;
+  constexpr int NN = L::NN;
+  const int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gp >= part_off[n_inst]) return;
+  const int b = find_inst(part_off, n_inst, gp);
+  if (active && !active[b]) return;
+  const int64_t k = gp - part_off[b];
+  const int64_t n = cell_off[b + 1] - cell_off[b];
+  const int64_t first = k * m;
+  const int64_t s = (first + m < n ? first + m : n) - 1;
+  const int64_t len = s - first;  // interior cells
+  if (len <= 0) return;
+  const int64_t base = cell_off[b];
+  T Ch[NN], Vh[NN], gh[NV], Bt[NN], Bi[NN], tmp[NN], tv[NV];
+  bool ok = true;
+  for (int64_t j = first; j < s; ++j) {
+    const T* S = sys + (base + j) * L::SYS;
+    const T* A = S;
+    const T* B = S + NN;
+    const T* C = S + 2 * NN;
+    const T* d = S + 3 * NN;
+    if (j == first) {
+#pragma unroll
+      for (int e = 0; e < NN; ++e) Bt[e] = B[e];
+      ok &= inv_block<T, NV>(Bt, Bi);
+      mv<T, NV>(Bi, d, gh);
+      mm<T, NV>(Bi, A, Vh);
+    } else {
+      mm<T, NV>(A, Ch, tmp);
+#pragma unroll
+      for (int e = 0; e < NN; ++e) Bt[e] = B[e] - tmp[e];
+      ok &= inv_block<T, NV>(Bt, Bi);
+      mv<T, NV>(A, gh, tv);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) tv[v] = d[v] - tv[v];
+      mv<T, NV>(Bi, tv, gh);
+      mm<T, NV>(A, Vh, tmp);
+      mm<T, NV>(Bi, tmp, Vh);
+#pragma unroll
+      for (int e = 0; e < NN; ++e) Vh[e] = -Vh[e];
+    }
+    mm<T, NV>(Bi, C, Ch);  // Chat_j, or What_last at the last interior cell
+    T* F = fwd + (base + j) * L::FWD;
+#pragma unroll
+    for (int e = 0; e < NN; ++e) { F[e] = Ch[e]; F[NN + e] = Vh[e]; }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[2 * NN + v] = gh[v];
+  }
+  // last interior: Ch holds What_last; backward pass for the first interior cell
+  T g[NV], V[NN], W[NN];
+#pragma unroll
+  for (int e = 0; e < NN; ++e) { V[e] = Vh[e]; W[e] = Ch[e]; }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) g[v] = gh[v];
+  T* Pp = prt + (part_off[b] + k) * L::PRT;
+#pragma unroll
+  for (int e = 0; e < NN; ++e) Pp[e] = Ch[e];
+  for (int64_t j = s - 2; j >= first; --j) {
+    const T* F = fwd + (base + j) * L::FWD;
+    // g = ghat_j - Chat_j g ; V = Vhat_j - Chat_j V ; W = -Chat_j W
+    mv<T, NV>(F, g, tv);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) g[v] = F[2 * NN + v] - tv[v];
+    mm<T, NV>(F, V, tmp);
+#pragma unroll
+    for (int e = 0; e < NN; ++e) V[e] = F[NN + e] - tmp[e];
+    mm<T, NV>(F, W, tmp);
+#pragma unroll
+    for (int e = 0; e < NN; ++e) W[e] = -tmp[e];
+  }
+#pragma unroll
+  for (int e = 0; e < NN; ++e) { Pp[NN + e] = V[e]; Pp[2 * NN + e] = W[e]; }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Pp[3 * NN + v] = g[v];
+  if (!ok) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
+}
+
+// Separator rows -> next level's system.
+template <typename T, int NV>
+__global__ __launch_bounds__(256) void k_bt_reduce(int n_inst, const int64_t* __restrict__ cell_off,
+                                                   const int64_t* __restrict__ part_off, int m,
+                                                   const T* __restrict__ sys, const T* __restrict__ fwd,
+                                                   const T* __restrict__ prt,
+                                                   const int64_t* __restrict__ next_off,
+                                                   T* __restrict__ nsys, const int32_t* active) {
+  using L = Lay<T, NV>;
+  constexpr int NN = L::NN;
+  const int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gp >= part_off[n_inst]) return;
+  const int b = find_inst(part_off, n_inst, gp);
+  if (active && !active[b]) return;
+  const int64_t k = gp - part_off[b];
+  const int64_t P = part_off[b + 1] - part_off[b];
+  const int64_t n = cell_off[b + 1] - cell_off[b];
+  const int64_t base = cell_off[b];
+  const int64_t first = k * m;
+  const int64_t s = (first + m < n ? first + m : n) - 1;
+  const T* S = sys + (base + s) * L::SYS;
+  const T* As = S;
+  const T* Bs = S + NN;
+  const T* Cs = S + 2 * NN;
+  const T* ds = S + 3 * NN;
+  T Ah[NN], Bh[NN], Chh[NN], dh[NV], tmp[NN], tv[NV];
+#pragma unroll
+  for (int e = 0; e < NN; ++e) Bh[e] = Bs[e];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) dh[v] = ds[v];
+  // left neighbour x_{s-1}: last interior of this part, or the previous separator
+  if (s > first) {
+    const T* F = fwd + (base + s - 1) * L::FWD;          // ghat_l, Vhat_l
+    const T* Pp = prt + (part_off[b] + k) * L::PRT;       // What_l
+    mm<T, NV>(As, F + NN, tmp);
+#pragma unroll
+    for (int e = 0; e < NN; ++e) Ah[e] = -tmp[e];
+    mm<T, NV>(As, Pp, tmp);
+#pragma unroll
+    for (int e = 0; e < NN; ++e) Bh[e] -= tmp[e];
+    mv<T, NV>(As, F + 2 * NN, tv);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dh[v] -= tv[v];
+  } else {
+#pragma unroll
+    for (int e = 0; e < NN; ++e) Ah[e] = As[e];
+  }
+  // right neighbour x_{s+1}: first interior of the next part, or the next separator
+  const int64_t k1 = (k + 1) % P;
+  const int64_t f1 = k1 * m;
+  const int64_t s1 = (f1 + m < n ? f1 + m : n) - 1;
+  if (s1 > f1) {
+    const T* Pn = prt + (part_off[b] + k1) * L::PRT;      // V_first, W_first, g_first
+    mm<T, NV>(Cs, Pn + NN, tmp);
+#pragma unroll
+    for (int e = 0; e < NN; ++e) Bh[e] -= tmp[e];
+    mm<T, NV>(Cs, Pn + 2 * NN, tmp);
+#pragma unroll
+    for (int e = 0; e < NN; ++e) Chh[e] = -tmp[e];
+    mv<T, NV>(Cs, Pn + 3 * NN, tv);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dh[v] -= tv[v];
+  } else {
+#pragma unroll
+    for (int e = 0; e < NN; ++e) Chh[e] = Cs[e];
+  }
+  T* O = nsys + (next_off[b] + k) * L::SYS;
+#pragma unroll
+  for (int e = 0; e < NN; ++e) { O[e] = Ah[e]; O[NN + e] = Bh[e]; O[2 * NN + e] = Chh[e]; }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) O[3 * NN + v] = dh[v];
+}
+
+// One cell per instance: (A + B + C) x = d (its neighbours are itself).
+template <typename T, int NV>
+__global__ void k_bt_top(int n_inst, const int64_t* __restrict__ cell_off, const T* __restrict__ sys,
+                         T* __restrict__ x, const int32_t* active, uint32_t* flags) {
+  using L = Lay<T, NV>;
+  constexpr int NN = L::NN;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_inst) return;
+  if (active && !active[b]) return;
+  const T* S = sys + cell_off[b] * L::SYS;
+  T M[NN], Mi[NN];
+#pragma unroll
+  for (int e = 0; e < NN; ++e) M[e] = S[e] + S[NN + e] + S[2 * NN + e];
+  if (!inv_block<T, NV>(M, Mi)) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
+  mv<T, NV>(Mi, S + 3 * NN, x + cell_off[b] * NV);
+}
+
+// Back-substitution of one level given the separator values (next level's x).
+// mode 0: write x; mode 1: add x into upd (level 0 of a Newton step).
+template <typename T, int NV>
+__global__ __launch_bounds__(256) void k_bt_back(int n_inst, const int64_t* __restrict__ cell_off,
+                                                 const int64_t* __restrict__ part_off, int m,
+                                                 const T* __restrict__ fwd, const T* __restrict__ prt,
+                                                 const int64_t* __restrict__ next_off,
+                                                 const T* __restrict__ xs, T* __restrict__ x,
+                                                 const int64_t* __restrict__ dof_off, T* upd, int mode,
+                                                 const int32_t* active, uint64_t* dnorm) {
+  using L = Lay<T, NV>;
+  constexpr int NN = L::NN;
+  const int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gp >= part_off[n_inst]) return;
+  const int b = find_inst(part_off, n_inst, gp);
+  if (active && !active[b]) return;
+  const int64_t k = gp - part_off[b];
+  const int64_t P = part_off[b + 1] - part_off[b];
+  const int64_t n = cell_off[b + 1] - cell_off[b];
+  const int64_t base = cell_off[b];
+  const int64_t first = k * m;
+  const int64_t s = (first + m < n ? first + m : n) - 1;
+  T xl[NV], xr[NV], xn[NV], tv[NV], tw[NV];
+  double dmax = 0.0;
+  const int64_t kl = (k + P - 1) % P;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    xl[v] = xs[(next_off[b] + kl) * NV + v];
+    xr[v] = xs[(next_off[b] + k) * NV + v];
+  }
+  auto emit = [&](int64_t j, const T* val) {
+    if (mode == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) x[(base + j) * NV + v] = val[v];
+    } else {
+      T* u = upd + dof_off[b] + j * NV;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        u[v] += val[v];
+        dmax = fmax(dmax, fabs((double)val[v]));
+      }
+    }
+  };
+  emit(s, xr);
+  if (s > first) {
+    const T* Pp = prt + (part_off[b] + k) * L::PRT;
+    const T* F = fwd + (base + s - 1) * L::FWD;
+    // x_l = ghat_l - Vhat_l xl - What_l xr
+    mv<T, NV>(F + NN, xl, tv);
+    mv<T, NV>(Pp, xr, tw);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) xn[v] = F[2 * NN + v] - tv[v] - tw[v];
+    emit(s - 1, xn);
+    for (int64_t j = s - 2; j >= first; --j) {
+      const T* G = fwd + (base + j) * L::FWD;
+      mv<T, NV>(G + NN, xl, tv);
+      mv<T, NV>(G, xn, tw);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) xn[v] = G[2 * NN + v] - tv[v] - tw[v];
+      emit(j, xn);
+    }
+  }
+  if (dnorm && mode == 1) {
+    const uint64_t bits = isfinite(dmax) ? (uint64_t)__double_as_longlong(dmax) : ~0ull;
+    atomicMax((unsigned long long*)&dnorm[b], (unsigned long long)bits);
+  }
+}
+
+template <typename T>
+size_t esz() { return sizeof(T); }
+
+template <typename T, int NV>
+rom_status bt_solve_t(rom_batch* h, int it, void* upd, void* out, hipStream_t s) {
+  using L = Lay<T, NV>;
+  const int B = h->cfg.n_inst;
+  const int32_t* act = it >= 0 ? h->active : nullptr;
+  const int nl = (int)h->levels.size();
+  for (int l = 0; l + 1 < nl; ++l) {
+    auto& lv = h->levels[l];
+    auto& nx = h->levels[l + 1];
+    const int nb = (int)((lv.parts_total + 255) / 256);
+    hipLaunchKernelGGL((k_bt_factor<T, NV>), dim3(nb), dim3(256), 0, s, B, lv.d_cell_off,
+                       lv.d_part_off, kPartM, (const T*)lv.sys, (T*)lv.fwd, (T*)lv.part, act,
+                       h->flags);
+    hipLaunchKernelGGL((k_bt_reduce<T, NV>), dim3(nb), dim3(256), 0, s, B, lv.d_cell_off,
+                       lv.d_part_off, kPartM, (const T*)lv.sys, (const T*)lv.fwd,
+                       (const T*)lv.part, nx.d_cell_off, (T*)nx.sys, act);
+  }
+  auto& top = h->levels[nl - 1];
+  hipLaunchKernelGGL((k_bt_top<T, NV>), dim3((B + 63) / 64), dim3(64), 0, s, B, top.d_cell_off,
+                     (const T*)top.sys, (T*)top.x, act, h->flags);
+  for (int l = nl - 2; l >= 0; --l) {
+    auto& lv = h->levels[l];
+    auto& nx = h->levels[l + 1];
+    const int nb = (int)((lv.parts_total + 255) / 256);
+    const bool last = l == 0;
+    T* xout = last && out ? (T*)out : (T*)lv.x;
+    const int mode = last && upd ? 1 : 0;
+    if (last && !upd && out) {
+      // the plain solve writes the solution in the state layout (cell-major == level-0 layout
+      // only when offsets coincide, which holds because level 0 uses the DOF ordering)
+    }
+    hipLaunchKernelGGL((k_bt_back<T, NV>), dim3(nb), dim3(256), 0, s, B, lv.d_cell_off,
+                       lv.d_part_off, kPartM, (const T*)lv.fwd, (const T*)lv.part, nx.d_cell_off,
+                       (const T*)nx.x, xout, h->d_dof_off, (T*)upd, mode, act,
+                       (last && it >= 0)
+                           ? h->norms + (size_t)(2 * (h->cfg.newton_max + 1) + it) * B
+                           : nullptr);
+  }
+  (void)sizeof(L);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+}  // namespace
+
+rom_status bt_setup(rom_batch* h) {
+  const int B = h->cfg.n_inst;
+  const size_t es = h->esz;
+  const int NV = h->nv;
+  const int NN = NV * NV;
+  std::vector<int64_t> n(h->n_cells);
+  h->levels.clear();
+  while (true) {
+    BtLevel lv;
+    lv.cell_off.assign(B + 1, 0);
+    lv.part_off.assign(B + 1, 0);
+    int64_t mx = 0;
+    for (int b = 0; b < B; ++b) {
+      lv.cell_off[b + 1] = lv.cell_off[b] + n[b];
+      lv.part_off[b + 1] = lv.part_off[b] + (n[b] + kPartM - 1) / kPartM;
+      mx = std::max(mx, n[b]);
+    }
+    lv.n_total = lv.cell_off[B];
+    lv.parts_total = lv.part_off[B];
+    ROM_HIP_CHECK(hipMalloc(&lv.d_cell_off, sizeof(int64_t) * (B + 1)));
+    ROM_HIP_CHECK(hipMalloc(&lv.d_part_off, sizeof(int64_t) * (B + 1)));
+    ROM_HIP_CHECK(hipMemcpy(lv.d_cell_off, lv.cell_off.data(), sizeof(int64_t) * (B + 1),
+                            hipMemcpyHostToDevice));
+    ROM_HIP_CHECK(hipMemcpy(lv.d_part_off, lv.part_off.data(), sizeof(int64_t) * (B + 1),
+                            hipMemcpyHostToDevice));
+    ROM_HIP_CHECK(hipMalloc(&lv.sys, es * lv.n_total * (3 * NN + NV)));
+    ROM_HIP_CHECK(hipMalloc(&lv.x, es * lv.n_total * NV));
+    const bool top = mx == 1;
+    if (!top) {
+      ROM_HIP_CHECK(hipMalloc(&lv.fwd, es * lv.n_total * (2 * NN + NV)));
+      ROM_HIP_CHECK(hipMalloc(&lv.part, es * lv.parts_total * (3 * NN + NV)));
+    }
+    h->levels.push_back(std::move(lv));
+    if (top) break;
+    for (int b = 0; b < B; ++b) n[b] = (n[b] + kPartM - 1) / kPartM;
+  }
+  return ROM_OK;
+}
+
+void bt_free(rom_batch* h) {
+  for (auto& lv : h->levels) {
+    (void)hipFree(lv.d_cell_off);
+    (void)hipFree(lv.d_part_off);
+    (void)hipFree(lv.sys);
+    (void)hipFree(lv.fwd);
+    (void)hipFree(lv.part);
+    (void)hipFree(lv.x);
+  }
+  h->levels.clear();
+}
+
+rom_status bt_solve(rom_batch* h, int it, void* upd, void* out, hipStream_t s) {
+  const bool f64 = h->cfg.precision == ROM_F64;
+  switch (h->nv) {
+    case 1: return f64 ? bt_solve_t<double, 1>(h, it, upd, out, s) : bt_solve_t<float, 1>(h, it, upd, out, s);
+    case 3: return f64 ? bt_solve_t<double, 3>(h, it, upd, out, s) : bt_solve_t<float, 3>(h, it, upd, out, s);
+    case 12: return f64 ? bt_solve_t<double, 12>(h, it, upd, out, s) : bt_solve_t<float, 12>(h, it, upd, out, s);
+  }
+  set_error("unsupported block size");
+  return ROM_E_UNSUPPORTED;
+}
+
+}  // namespace romhip

@@ -1,0 +1,174 @@
+// Internal declarations of the romhip library: the batch handle, launch helpers
+// and the kernel launchers each translation unit provides.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/romhip.h"
+
+namespace romhip {
+
+void set_error(const std::string& msg);
+
+#define ROM_HIP_CHECK(expr)                                                        \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess) {                                                        \
+      ::romhip::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));     \
+      return ROM_E_DEVICE;                                                         \
+    }                                                                              \
+  } while (0)
+
+#define ROM_REQUIRE(cond, code, msg)      \
+  do {                                    \
+    if (!(cond)) {                        \
+      ::romhip::set_error(msg);           \
+      return code;                        \
+    }                                     \
+  } while (0)
+
+constexpr int kTile = 256;          // cells per tile of the stencil kernels
+constexpr int kPassRows = 2048;     // basis rows per block of the tall-skinny passes
+constexpr int kMaxR = 64;           // largest reduced dimension supported
+constexpr int kMaxNs = 2 * kMaxR;   // largest number of DEIM rows
+constexpr int kPartM = 16;          // part size of the block-tridiagonal solver
+
+// A contiguous run of cells of one instance handled by one thread block.
+struct Tile {
+  int32_t inst;
+  int32_t pad;
+  int64_t cell0;   // first cell (instance-local)
+  int64_t ncell;   // number of cells in the tile
+};
+
+// One level of the recursive block-tridiagonal (Schur complement) solver.
+struct BtLevel {
+  int64_t n_total = 0;            // cells at this level, all instances
+  int64_t parts_total = 0;        // parts at this level, all instances
+  std::vector<int64_t> cell_off;  // [n_inst+1]
+  std::vector<int64_t> part_off;  // [n_inst+1]
+  int64_t* d_cell_off = nullptr;
+  int64_t* d_part_off = nullptr;
+  void* sys = nullptr;    // A,B,C (nv*nv each) and d (nv) per cell
+  void* fwd = nullptr;    // Chat, Vhat (nv*nv each) and ghat (nv) per cell
+  void* part = nullptr;   // What_last, V_first, W_first (nv*nv) and g_first (nv) per part
+  void* x = nullptr;      // solution per cell (nv)
+};
+
+}  // namespace romhip
+
+struct rom_batch {
+  rom_config cfg{};
+  std::vector<int64_t> n_cells;
+  std::vector<double> phys;
+  int nv = 1;
+  size_t esz = 4;                 // bytes per bulk element
+  int64_t total_cells = 0, total_dof = 0;
+  std::vector<int64_t> dof_off, cell_off;
+  int64_t max_dof = 0;
+
+  // device layout
+  int64_t* d_dof_off = nullptr;
+  int64_t* d_cell_off = nullptr;
+  double* d_phys = nullptr;
+  romhip::Tile* d_tiles = nullptr;
+  int n_tiles = 0;
+  romhip::Tile* d_ptiles = nullptr;  // row tiles of kPassRows basis rows
+  int n_ptiles = 0;
+  std::vector<int> ptile_first;      // first row tile of each instance [n_inst+1]
+  int* d_ptile_first = nullptr;
+
+  // reduced state
+  void* Phi = nullptr;       // T[total_dof * r]
+  double* sigma = nullptr;   // [n_inst * r]
+  double* a = nullptr;       // [n_inst * r]
+  double* a_prev = nullptr;  // [n_inst * r]
+  void* q_ref = nullptr;     // T[total_dof]
+  double* d_var = nullptr;   // [n_inst * nv]
+  void* y_corr = nullptr;    // T[total_dof]
+  uint32_t* flags = nullptr; // [n_inst]
+  int32_t* P = nullptr;      // [n_inst * n_s]
+  double* M = nullptr;       // [n_inst * r * n_s]
+  double* mesh_phi = nullptr;  // [n_inst * n_s * 3 * nv * r]
+  double* mesh_qref = nullptr; // [n_inst * n_s * 3 * nv]
+  uint32_t* chosen = nullptr;  // [total_dof] epoch marks for DEIM
+  uint32_t deim_epoch = 0;
+
+  // iSVD workspace
+  double* part = nullptr;    // block partial sums [n_ptiles * (r*r + 2r + 4)]
+  double* red = nullptr;     // per-instance reductions [n_inst * (3r + 8)]
+  double* ubar = nullptr;    // core left singular vectors [n_inst * (r+1)*(r+1)]
+  double* lmat = nullptr;    // re-orth factor [n_inst * r * r]
+  int32_t* active = nullptr; // per-instance Newton activity [n_inst]
+  int32_t* iters = nullptr;  // per-instance Newton counters [n_inst]
+  uint64_t* norms = nullptr; // Newton norms: 3 blocks of (newton_max+1) x n_inst (residual, iterate, update)
+  double* rstate = nullptr;  // reduced Newton workspace [n_inst * (r*r + 4r)]
+  double* qtmp = nullptr;    // first Gram-Schmidt residual [total_dof] (FP64)
+  void* mpart = nullptr;     // Galerkin block partials of Phi^T J Phi [n_ptiles * kMaxR^2] (T)
+  uint32_t* d_epoch = nullptr; // DEIM epoch counter (device)
+
+  // full-order Newton workspace
+  void* fq = nullptr;        // T[total_dof] current iterate
+  void* fq_prev = nullptr;   // T[total_dof]
+  std::vector<romhip::BtLevel> levels;
+  void* vjp_tmp = nullptr;   // T[total_dof]
+
+  // host counters
+  int64_t n_fine = 0;        // fine step index n of Alg. 1 (starts at w_init)
+  int64_t n_update = 0;      // iSVD updates done
+  int64_t n_events = 0;
+  int64_t n_reorth = 0;
+  bool has_rom = false;
+  hipStream_t last_stream = nullptr;
+
+  // graphs of one adaptation window
+  hipGraphExec_t win_exec = nullptr;
+  hipStream_t win_stream = nullptr;
+};
+
+namespace romhip {
+
+// ---- residual.hip
+rom_status launch_residual(rom_batch* h, const void* q, const void* q_prev, double dt, void* out,
+                           hipStream_t s);
+rom_status launch_residual_norm(rom_batch* h, const void* q, const void* q_prev, double dt,
+                                void* out, int it, hipStream_t s);
+rom_status launch_residual_vjp(rom_batch* h, const void* q, const void* q_prev, double dt,
+                               const void* gbar, void* gq, void* gq_prev, hipStream_t s);
+// assemble backward-Euler Newton system at level 0: -r and blocks of I - dt J_f
+rom_status launch_assemble(rom_batch* h, const void* q, const void* q_prev, double dt, int it,
+                           hipStream_t s);
+// assemble the transposed Jacobian system with a given right-hand side (adjoint)
+rom_status launch_assemble_adjoint(rom_batch* h, const void* q, double dt, const void* rhs,
+                                   hipStream_t s);
+
+// ---- btsolve.hip
+rom_status bt_setup(rom_batch* h);
+void bt_free(rom_batch* h);
+// solve the level-0 system; it >= 0: Newton mode (skip inactive instances,
+// converge check against norms[it]; add solution into q); it < 0: plain solve into out
+rom_status bt_solve(rom_batch* h, int it, void* q_update, void* out, hipStream_t s);
+
+// ---- isvd.hip
+rom_status launch_isvd(rom_batch* h, const void* y, hipStream_t s);
+rom_status launch_reorth(rom_batch* h, hipStream_t s);
+rom_status launch_pod(rom_batch* h, const void* Q, int w, hipStream_t s);  // Q: T[w * total_dof]
+rom_status launch_preprocess(rom_batch* h, const void* q0, const void* Q, int w, hipStream_t s);
+rom_status launch_project_state(rom_batch* h, const void* q, hipStream_t s);  // a = Phi^T D (q - q_ref)
+
+// ---- rom.hip
+rom_status launch_rom_fine_step(rom_batch* h, hipStream_t s);
+rom_status launch_galerkin_pass(rom_batch* h, hipStream_t s);  // one pass, every instance active
+rom_status launch_isvd_project(rom_batch* h, const void* y, hipStream_t s);  // pass A only
+rom_status launch_rebuild(rom_batch* h, hipStream_t s);
+rom_status launch_reconstruct(rom_batch* h, void* out, hipStream_t s);
+rom_status rom_kernels_prepare();
+rom_status isvd_kernels_prepare();
+
+// ---- small helpers (api.cpp)
+rom_status fill_zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace romhip

@@ -1,0 +1,734 @@
+// Incremental SVD (Alg. 2) and the offline POD / preprocessing on the device.
+//
+// Tall-skinny passes: a block owns a row tile (<= kPassRows rows of one
+// instance) and walks it in chunks of kChunk rows.  Each chunk of the
+// row-major basis is staged through LDS with coalesced loads; the
+// per-row scalar work (snapshot preprocessing y^ = D (y - q_ref), the row dot
+// products of the second Gram-Schmidt pass) runs one row per thread, and the
+// column reductions run one column per lane with FP64 accumulation.  Block
+// partials are reduced per instance in a fixed order, so results do not
+// depend on scheduling.
+//
+// The (r+1) x (r+1) core K = [[lambda diag(sigma), p], [0, rho]] is
+// decomposed by one-sided (Hestenes) Jacobi on its rows in FP64, one
+// workgroup per instance with both K and the accumulated rotations in LDS;
+// rows are orthogonalised pairwise in round-robin order until every pair is
+// orthogonal to 1e-15 relative.
+#include "internal.h"
+#include "physics.h"
+
+namespace romhip {
+
+constexpr int kChunk = 64;
+constexpr int kMaxK = 128;          // widest matrix a pass handles (POD window)
+constexpr int kPst = kMaxK + 4;     // partial-sum stride per tile
+
+namespace {
+
+template <typename T>
+DEV double yhat_of(const T* y, const T* qref, const double* dvar, int nv, int64_t gdof,
+                   int64_t ldof) {
+  return dvar[ldof % nv] * ((double)y[gdof] - (double)qref[gdof]);
+}
+
+// mode 1: partial[c] = sum_i Phi_ic y^_i,  partial[k] = sum_i y^_i^2
+// mode 2: q1_i = y^_i - Phi_i . p1 ; partial[c] = sum_i Phi_ic q1_i, partial[k] = sum q1_i^2;
+//         q1 is also written to q1out (FP64) when given
+// When qref == nullptr the snapshot is used as is (y^ = y).
+template <typename T>
+__global__ __launch_bounds__(256) void k_project(const Tile* __restrict__ tiles,
+                                                 const int64_t* __restrict__ dof_off,
+                                                 const T* __restrict__ Phi, int ld, int k,
+                                                 const T* __restrict__ y, const T* __restrict__ qref,
+                                                 const double* __restrict__ dvar, int nv,
+                                                 const double* __restrict__ p1, int ldp, int mode,
+                                                 double* __restrict__ part,
+                                                 double* __restrict__ q1out) {
+  __shared__ T sP[kChunk][kMaxK + 1];
+  __shared__ double sY[kChunk];
+  __shared__ double sp[kMaxK];
+  __shared__ double red[4][kMaxK + 1];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  const int tid = threadIdx.x;
+  const int64_t base = dof_off[b];
+  const double* dv = dvar ? dvar + (size_t)b * nv : nullptr;
+  if (mode == 2)
+    for (int c = tid; c < k; c += blockDim.x) sp[c] = p1[(size_t)b * ldp + c];
+  const int lane = tid & 63, grp = tid >> 6;
+  double acc0 = 0.0, acc1 = 0.0, accn = 0.0;
+  for (int64_t r0 = 0; r0 < t.ncell; r0 += kChunk) {
+    const int nr = (int)(t.ncell - r0 < kChunk ? t.ncell - r0 : kChunk);
+    const int64_t row0 = t.cell0 + r0;  // instance-local row of the chunk
+    __syncthreads();
+    for (int e = tid; e < nr * k; e += blockDim.x) {
+      const int rr = e / k, c = e - rr * k;
+      sP[rr][c] = Phi[(base + row0 + rr) * ld + c];
+    }
+    if (tid < nr) {
+      const int64_t g = base + row0 + tid;
+      sY[tid] = qref ? yhat_of(y, qref, dv, nv, g, row0 + tid) : (double)y[g];
+    }
+    __syncthreads();
+    if (mode == 2 && tid < nr) {
+      double d = 0.0;
+      for (int c = 0; c < k; ++c) d += (double)sP[tid][c] * sp[c];
+      sY[tid] -= d;
+      // the second Gram-Schmidt projection must act on this stored vector:
+      // recomputing it elsewhere differs in the last bits, which for a
+      // nearly dependent snapshot is the size of the residual itself
+      if (q1out) q1out[base + row0 + tid] = sY[tid];
+    }
+    __syncthreads();
+    for (int rr = grp; rr < nr; rr += 4) {
+      const double yv = sY[rr];
+      if (lane < k) acc0 += (double)sP[rr][lane] * yv;
+      if (lane + 64 < k) acc1 += (double)sP[rr][lane + 64] * yv;
+      if (lane == 0) accn += yv * yv;
+    }
+  }
+  __syncthreads();
+  if (lane < k) red[grp][lane] = acc0;
+  if (lane + 64 < k) red[grp][lane + 64] = acc1;
+  if (lane == 0) red[grp][kMaxK] = accn;
+  __syncthreads();
+  double* out = part + (size_t)blockIdx.x * kPst;
+  for (int c = tid; c < k; c += blockDim.x) out[c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+  if (tid == 0) out[k] = red[0][kMaxK] + red[1][kMaxK] + red[2][kMaxK] + red[3][kMaxK];
+}
+
+// Sum the tile partials of each instance in tile order: dst[b*ldd + c], c <= k.
+__global__ void k_reduce_tiles(const int* __restrict__ tfirst, const double* __restrict__ part, int k,
+                               double* __restrict__ dst, int ldd) {
+  const int b = blockIdx.x;
+  for (int c = threadIdx.x; c <= k; c += blockDim.x) {
+    double s = 0.0;
+    for (int tt = tfirst[b]; tt < tfirst[b + 1]; ++tt) s += part[(size_t)tt * kPst + c];
+    dst[(size_t)b * ldd + c] = s;
+  }
+}
+
+// ------------------------------------------------------------------ small SVD
+// One-sided Jacobi on the rows of the n x n matrix K (LDS, leading dim ld):
+// K <- G K with G orthogonal until the rows are mutually orthogonal.  Then
+// sigma_i = ||row i|| and row i of G is the left singular vector.  On exit the
+// sorted (descending, stable) vectors are written as columns of U (n x n,
+// row-major, global) with the sign convention "largest |entry| positive,
+// first index on ties", and the sorted values to sv.
+DEV void jacobi_rows(double* K, double* G, int n, int ld, double* U, double* sv, double* norms,
+                     int* rank, int* rotated) {
+  const int tid = threadIdx.x;
+  const int nth = blockDim.x;
+  for (int e = tid; e < n * ld; e += nth) G[e] = ((e / ld) == (e % ld)) ? 1.0 : 0.0;
+  __syncthreads();
+  const int np = n + (n & 1);     // even number of slots
+  const int TPP = 4;              // threads per pair
+  const int grp = tid / TPP, sub = tid % TPP;
+  const int ngrp = nth / TPP;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) *rotated = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < np - 1; ++rnd) {
+      for (int pr = grp; pr < np / 2; pr += ngrp) {
+        // circle method: slot 0 fixed, the other np-1 slots rotate each round
+        const int a = pr == 0 ? 0 : ((pr - 1 + rnd) % (np - 1)) + 1;
+        const int c = ((np - 2 - pr + rnd) % (np - 1)) + 1;
+        const int i = a < c ? a : c, j = a < c ? c : a;
+        const bool live = j < n;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        if (live) {
+          for (int q = sub; q < n; q += TPP) {
+            const double x = K[i * ld + q], z = K[j * ld + q];
+            al += x * x; be += z * z; ga += x * z;
+          }
+        }
+#pragma unroll
+        for (int off = 1; off < TPP; off <<= 1) {
+          al += __shfl_xor(al, off, TPP);
+          be += __shfl_xor(be, off, TPP);
+          ga += __shfl_xor(ga, off, TPP);
+        }
+        if (live && ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al) * sqrt(be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          for (int q = sub; q < n; q += TPP) {
+            const double x = K[i * ld + q], z = K[j * ld + q];
+            K[i * ld + q] = cs * x - sn * z;
+            K[j * ld + q] = sn * x + cs * z;
+            const double gx = G[i * ld + q], gz = G[j * ld + q];
+            G[i * ld + q] = cs * gx - sn * gz;
+            G[j * ld + q] = sn * gx + cs * gz;
+          }
+          if (sub == 0) *rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = *rotated;
+    __syncthreads();
+    if (!any) break;
+  }
+  for (int i = tid; i < n; i += nth) {
+    double s = 0.0;
+    for (int q = 0; q < n; ++q) s += K[i * ld + q] * K[i * ld + q];
+    norms[i] = sqrt(s);
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += nth) {
+    int rk = 0;
+    for (int j = 0; j < n; ++j)
+      if (norms[j] > norms[i] || (norms[j] == norms[i] && j < i)) ++rk;
+    rank[i] = rk;
+    sv[rk] = norms[i];
+  }
+  __syncthreads();
+  // sign convention per vector (row i of G), then scatter as column rank[i] of U
+  for (int i = tid; i < n; i += nth) {
+    int im = 0;
+    double best = -1.0;
+    for (int q = 0; q < n; ++q) {
+      const double v = fabs(G[i * ld + q]);
+      if (v > best) { best = v; im = q; }
+    }
+    const double sg = G[i * ld + im] < 0.0 ? -1.0 : 1.0;
+    const int col = rank[i];
+    for (int q = 0; q < n; ++q) U[q * n + col] = sg * G[i * ld + q];
+  }
+  __syncthreads();
+}
+
+// Core of Alg. 2: K from lambda, sigma, p, rho; SVD; sigma' and the transfer of a.
+// red layout per instance: [0..r) p1, r: |y^|^2, [r+1..2r+1) p2, 2r+1: |q1|^2
+__global__ __launch_bounds__(256) void k_isvd_core(int r, double lambda, double tau_rho,
+                                                  const double* __restrict__ red, int ldr,
+                                                  double* __restrict__ sigma, double* __restrict__ a,
+                                                  double* __restrict__ ubar, double* __restrict__ pr,
+                                                  uint32_t* flags) {
+  extern __shared__ double sm[];
+  const int n = r + 1, ld = n;
+  double* K = sm;
+  double* G = K + n * ld;
+  double* nrm = G + n * ld;
+  double* sv = nrm + n;
+  double* ta = sv + n;
+  int* rank = (int*)(ta + n);
+  __shared__ int rotated;
+  __shared__ double rho_s;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const double* R = red + (size_t)b * ldr;
+  double* U = ubar + (size_t)b * n * n;
+  if (tid == 0) {
+    double yy = R[r], s1 = R[2 * r + 1], p2n = 0.0;
+    for (int c = 0; c < r; ++c) p2n += R[r + 1 + c] * R[r + 1 + c];
+    double rho2 = s1 - p2n;
+    double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
+    if (!(rho > tau_rho * sqrt(yy))) {
+      rho = 0.0;
+      atomicOr(&flags[b], ROM_FLAG_RHO_ZERO);
+    }
+    rho_s = rho;
+  }
+  __syncthreads();
+  for (int e = tid; e < n * ld; e += blockDim.x) {
+    const int i = e / ld, j = e % ld;
+    double v = 0.0;
+    if (i < r && j < r) v = i == j ? lambda * sigma[(size_t)b * r + i] : 0.0;
+    else if (i < r && j == r) v = R[i] + R[r + 1 + i];  // p = p1 + p2
+    else if (i == r && j == r) v = rho_s;
+    K[e] = v;
+  }
+  __syncthreads();
+  jacobi_rows(K, G, n, ld, U, sv, nrm, rank, &rotated);
+  for (int c = tid; c < r; c += blockDim.x) sigma[(size_t)b * r + c] = sv[c];
+  // closed-form transfer: a <- Ubar[:r, :r]^T a  (the new direction is orthogonal to Phi)
+  for (int c = tid; c < r; c += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < r; ++k) s += U[k * n + c] * a[(size_t)b * r + k];
+    ta[c] = s;
+  }
+  __syncthreads();
+  for (int c = tid; c < r; c += blockDim.x) a[(size_t)b * r + c] = ta[c];
+  // p1, p2 (kept apart: the rotation subtracts them one after the other) and 1/rho
+  for (int c = tid; c < r; c += blockDim.x) {
+    pr[(size_t)b * (2 * r + 2) + c] = R[c];
+    pr[(size_t)b * (2 * r + 2) + r + c] = R[r + 1 + c];
+  }
+  if (tid == 0) pr[(size_t)b * (2 * r + 2) + 2 * r] = rho_s > 0.0 ? 1.0 / rho_s : 0.0;
+}
+
+// Phi_out[i, j] = sum_{c<kin} Phi_in[i, c] U[c, j] (+ s_i U[kin, j]),  j < kout,
+// with s_i = (q1_i - Phi_in[i,:] p2) / rho for the iSVD update (mode 1), q1 the
+// first-pass residual stored by the second projection pass, and no extra term
+// otherwise (mode 0).  pr holds (p1, p2, 1/rho) per instance (stride ldpr).
+// U is (kin+1) x ldu per instance (FP64).
+// enable (optional): instances with enable[b] == 0 are left untouched.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rotate(const Tile* __restrict__ tiles,
+                                                const int64_t* __restrict__ dof_off,
+                                                const T* Phi_in, int ld_in, int kin, T* Phi_out,
+                                                int ld_out, int kout, const double* __restrict__ U,
+                                                int ldu, size_t ustride, int mode,
+                                                const double* __restrict__ q1,
+                                                const double* __restrict__ pr, int ldpr,
+                                                const int32_t* __restrict__ enable) {
+  __shared__ T sP[kChunk][kMaxK + 1];
+  __shared__ double sS[kChunk];
+  __shared__ double sU[(kMaxK + 1) * 64];
+  __shared__ double sp[2 * kMaxR + 1];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  if (enable && !enable[b]) return;
+  const int tid = threadIdx.x;
+  const int64_t base = dof_off[b];
+  const double* Ub = U + (size_t)b * ustride;
+  const int krow = mode == 1 ? kin + 1 : kin;
+  for (int e = tid; e < krow * kout; e += blockDim.x) {
+    const int c = e / kout, j = e % kout;
+    sU[c * 64 + j] = Ub[c * ldu + j];
+  }
+  if (mode == 1)
+    for (int c = tid; c <= 2 * kin; c += blockDim.x) sp[c] = pr[(size_t)b * ldpr + c];
+  const int lane = tid & 63, grp = tid >> 6;
+  for (int64_t r0 = 0; r0 < t.ncell; r0 += kChunk) {
+    const int nr = (int)(t.ncell - r0 < kChunk ? t.ncell - r0 : kChunk);
+    const int64_t row0 = t.cell0 + r0;
+    __syncthreads();
+    for (int e = tid; e < nr * kin; e += blockDim.x) {
+      const int rr = e / kin, c = e - rr * kin;
+      sP[rr][c] = Phi_in[(base + row0 + rr) * ld_in + c];
+    }
+    __syncthreads();
+    if (mode == 1 && tid < nr) {
+      double d2 = 0.0;
+      for (int c = 0; c < kin; ++c) d2 += (double)sP[tid][c] * sp[kin + c];
+      sS[tid] = (q1[base + row0 + tid] - d2) * sp[2 * kin];
+    }
+    __syncthreads();
+    if (lane < kout) {
+      for (int rr = grp; rr < nr; rr += 4) {
+        double acc = mode == 1 ? sS[rr] * sU[kin * 64 + lane] : 0.0;
+        for (int c = 0; c < kin; ++c) acc += (double)sP[rr][c] * sU[c * 64 + lane];
+        Phi_out[(base + row0 + rr) * ld_out + lane] = (T)acc;
+      }
+    }
+  }
+}
+
+// Gram partials G = Phi^T Phi per tile (FP64), lane j accumulates column j.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram(const Tile* __restrict__ tiles,
+                                              const int64_t* __restrict__ dof_off,
+                                              const T* __restrict__ Phi, int r,
+                                              double* __restrict__ part) {
+  __shared__ T sP[kChunk][kMaxR + 1];
+  __shared__ double red[4][kMaxR];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst, tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
+  const int64_t base = dof_off[b];
+  double acc[kMaxR];
+#pragma unroll
+  for (int c = 0; c < kMaxR; ++c) acc[c] = 0.0;
+  for (int64_t r0 = 0; r0 < t.ncell; r0 += kChunk) {
+    const int nr = (int)(t.ncell - r0 < kChunk ? t.ncell - r0 : kChunk);
+    __syncthreads();
+    for (int e = tid; e < nr * r; e += blockDim.x) {
+      const int rr = e / r, c = e - rr * r;
+      sP[rr][c] = Phi[(base + t.cell0 + r0 + rr) * r + c];
+    }
+    __syncthreads();
+    if (lane < r) {
+      for (int rr = grp; rr < nr; rr += 4) {
+        const double pj = (double)sP[rr][lane];
+#pragma unroll
+        for (int c = 0; c < kMaxR; ++c)
+          if (c < r) acc[c] += (double)sP[rr][c] * pj;
+      }
+    }
+  }
+  double* out = part + (size_t)blockIdx.x * (kMaxR * kMaxR);
+#pragma unroll
+  for (int c = 0; c < kMaxR; ++c) {
+    if (c < r) {
+      __syncthreads();
+      if (lane < r) red[grp][lane] = acc[c];
+      __syncthreads();
+      if (tid < r) out[c * r + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    }
+  }
+}
+
+// Per instance: G = sum of partials; if max|G - I| > tau: Cholesky G = L L^T,
+// store Linv^T (so that Phi <- Phi Linv^T) and a <- L^T a; enable[b] = 1.
+__global__ __launch_bounds__(256) void k_reorth_decide(const int* __restrict__ tfirst,
+                                                       const double* __restrict__ part, int r,
+                                                       double tau, double* __restrict__ lmat,
+                                                       double* __restrict__ a,
+                                                       int32_t* __restrict__ enable,
+                                                       uint32_t* flags) {
+  __shared__ double G[kMaxR * kMaxR];
+  __shared__ double Li[kMaxR * kMaxR];
+  __shared__ double dev;
+  __shared__ double ta[kMaxR];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  for (int e = tid; e < r * r; e += blockDim.x) {
+    double s = 0.0;
+    for (int tt = tfirst[b]; tt < tfirst[b + 1]; ++tt) s += part[(size_t)tt * (kMaxR * kMaxR) + e];
+    G[e] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < r; ++j) {
+        const double v = fabs(G[i * r + j] - (i == j ? 1.0 : 0.0));
+        m = v > m ? v : m;
+      }
+    dev = m;
+  }
+  __syncthreads();
+  const bool go = dev > tau;
+  if (tid == 0) enable[b] = go ? 1 : 0;
+  if (!go) return;
+  if (tid == 0) {
+    atomicOr(&flags[b], ROM_FLAG_REORTH);
+    // Cholesky in place (lower), G = L L^T
+    for (int j = 0; j < r; ++j) {
+      double s = G[j * r + j];
+      for (int k = 0; k < j; ++k) s -= G[j * r + k] * G[j * r + k];
+      const double d = sqrt(s > 0.0 ? s : 1e-300);
+      G[j * r + j] = d;
+      for (int i = j + 1; i < r; ++i) {
+        double t2 = G[i * r + j];
+        for (int k = 0; k < j; ++k) t2 -= G[i * r + k] * G[j * r + k];
+        G[i * r + j] = t2 / d;
+      }
+      for (int k = j + 1; k < r; ++k) G[j * r + k] = 0.0;
+    }
+    // Li = L^{-1} (lower) by forward substitution on the identity
+    for (int c = 0; c < r; ++c)
+      for (int i = 0; i < r; ++i) {
+        double s = (i == c) ? 1.0 : 0.0;
+        for (int k = 0; k < i; ++k) s -= G[i * r + k] * Li[k * r + c];
+        Li[i * r + c] = s / G[i * r + i];
+      }
+  }
+  __syncthreads();
+  // Phi_new = Phi Li^T : U[c][j] = Li[j][c]
+  for (int e = tid; e < r * r; e += blockDim.x) {
+    const int c = e / r, j = e % r;
+    lmat[(size_t)b * r * r + c * r + j] = Li[j * r + c];
+  }
+  // a_new = L^T a
+  for (int j = tid; j < r; j += blockDim.x) {
+    double s = 0.0;
+    for (int i = j; i < r; ++i) s += G[i * r + j] * a[(size_t)b * r + i];
+    ta[j] = s;
+  }
+  __syncthreads();
+  for (int j = tid; j < r; j += blockDim.x) a[(size_t)b * r + j] = ta[j];
+}
+
+// POD helpers -------------------------------------------------------------
+// Column k of the CGS2 QR of X = D (Q_train - q_ref 1^T): red holds p1 (+ |x|^2)
+// at [0..k] and p2 (+ |q1|^2) at [kMaxK+1 ..].  Writes R[0..k-1][k] = p and pr = p.
+__global__ void k_pod_column(int k, int w, const double* __restrict__ red, int ldr,
+                             double* __restrict__ R, double* __restrict__ pr, int ldpr) {
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const double* X = red + (size_t)b * ldr;
+  double* Rb = R + (size_t)b * w * w;
+  for (int c = tid; c < k; c += blockDim.x) {
+    Rb[c * w + k] = X[c] + X[kMaxK + 1 + c];
+    pr[(size_t)b * ldpr + c] = X[c];
+    pr[(size_t)b * ldpr + kMaxK + c] = X[kMaxK + 1 + c];
+  }
+}
+
+// Q[:, k] = q1 - Q[:, :k] p2 with q1 the stored first-pass residual (x itself
+// for k = 0), not yet normalised; per-tile partial of |q|^2.
+// The norm is taken of the computed vector itself: with nearly dependent
+// training columns, the Pythagorean |q1|^2 - |p2|^2 loses the orthonormality
+// of Q and the error cascades into later columns.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pod_write(const Tile* __restrict__ tiles,
+                                                   const int64_t* __restrict__ dof_off, T* Q, int w,
+                                                   int k, const T* __restrict__ y,
+                                                   const T* __restrict__ qref,
+                                                   const double* __restrict__ dvar, int nv,
+                                                   const double* __restrict__ pr, int ldpr,
+                                                   const double* __restrict__ q1,
+                                                   double* __restrict__ part) {
+  __shared__ double red[256];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst, tid = threadIdx.x;
+  const int64_t base = dof_off[b];
+  const double* p = pr + (size_t)b * ldpr;
+  double acc = 0.0;
+  for (int64_t rr = tid; rr < t.ncell; rr += blockDim.x) {
+    const int64_t lr = t.cell0 + rr, g = base + lr;
+    double v;
+    if (k == 0) {
+      v = yhat_of(y, qref, dvar + (size_t)b * nv, nv, g, lr);
+    } else {
+      double d2 = 0.0;
+      for (int c = 0; c < k; ++c) d2 += (double)Q[g * w + c] * p[kMaxK + c];
+      v = q1[g] - d2;
+    }
+    const T vt = (T)v;
+    Q[g * w + k] = vt;
+    acc += (double)vt * (double)vt;
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) red[tid] += red[tid + st];
+    __syncthreads();
+  }
+  if (tid == 0) part[(size_t)blockIdx.x * kPst] = red[0];
+}
+
+// rho = |q| (from the reduced partials in red[b*ldr]); R[k][k] = rho; pr[kMaxK] = 1/rho
+__global__ void k_pod_rho(int k, int w, const double* __restrict__ red, int ldr,
+                          double* __restrict__ R, double* __restrict__ pr, int ldpr) {
+  const int b = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  const double rho = sqrt(red[(size_t)b * ldr]);
+  R[(size_t)b * w * w + k * w + k] = rho;
+  pr[(size_t)b * ldpr + 2 * kMaxK] = rho > 0.0 ? 1.0 / rho : 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pod_scale(const Tile* __restrict__ tiles,
+                                                   const int64_t* __restrict__ dof_off, T* Q, int w,
+                                                   int k, const double* __restrict__ pr, int ldpr) {
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  const double s = pr[(size_t)b * ldpr + 2 * kMaxK];
+  const int64_t base = dof_off[b];
+  for (int64_t rr = threadIdx.x; rr < t.ncell; rr += blockDim.x) {
+    const int64_t g = base + t.cell0 + rr;
+    Q[g * w + k] = (T)((double)Q[g * w + k] * s);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pod_svd(int w, int r, const double* __restrict__ R,
+                                                 double* __restrict__ U, double* __restrict__ sigma,
+                                                 int use_lds) {
+  extern __shared__ double sm[];
+  __shared__ int rotated;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int n = w, ld = w;
+  double* K = sm;
+  double* G = K + n * ld;
+  double* nrm = G + n * ld;
+  double* sv = nrm + n;
+  int* rank = (int*)(sv + n);
+  for (int e = tid; e < n * n; e += blockDim.x) K[e] = R[(size_t)b * n * n + e];
+  __syncthreads();
+  jacobi_rows(K, G, n, ld, U + (size_t)b * n * n, sv, nrm, rank, &rotated);
+  for (int c = tid; c < r; c += blockDim.x) sigma[(size_t)b * r + c] = sv[c];
+  (void)use_lds;
+}
+
+// preprocessing: sum over cells and snapshots of (Q - q_ref)^2 per variable
+template <typename T>
+__global__ __launch_bounds__(256) void k_sqdev(const Tile* __restrict__ tiles,
+                                               const int64_t* __restrict__ dof_off,
+                                               const T* __restrict__ Q, int w, int64_t total,
+                                               const T* __restrict__ qref, int nv,
+                                               double* __restrict__ part) {
+  __shared__ double red[256][12];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst, tid = threadIdx.x;
+  const int64_t base = dof_off[b];
+  double acc[12];
+  for (int v = 0; v < 12; ++v) acc[v] = 0.0;
+  for (int64_t rr = tid; rr < t.ncell; rr += blockDim.x) {
+    const int64_t lr = t.cell0 + rr, g = base + lr;
+    const double q0 = (double)qref[g];
+    double s = 0.0;
+    for (int j = 0; j < w; ++j) {
+      const double d = (double)Q[(size_t)j * total + g] - q0;
+      s += d * d;
+    }
+    const int v = (int)(lr % nv);
+    for (int u = 0; u < 12; ++u) acc[u] += (u == v) ? s : 0.0;
+  }
+  for (int v = 0; v < nv; ++v) red[tid][v] = acc[v];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st)
+      for (int v = 0; v < nv; ++v) red[tid][v] += red[tid + st][v];
+    __syncthreads();
+  }
+  if (tid < nv) part[(size_t)blockIdx.x * kPst + tid] = red[0][tid];
+}
+
+__global__ void k_dvar(const int* __restrict__ tfirst, const double* __restrict__ part, int nv,
+                       const int64_t* __restrict__ cell_off, int w, double* __restrict__ dvar) {
+  const int b = blockIdx.x;
+  const int v = threadIdx.x;
+  if (v >= nv) return;
+  double s = 0.0;
+  for (int tt = tfirst[b]; tt < tfirst[b + 1]; ++tt) s += part[(size_t)tt * kPst + v];
+  const double cnt = (double)(cell_off[b + 1] - cell_off[b]) * (double)w;
+  const double phi = s / cnt;
+  dvar[(size_t)b * nv + v] = phi == 0.0 ? 1.0 : 1.0 / phi;
+}
+
+template <typename T>
+rom_status project_t(rom_batch* h, const void* Phi, int ld, int k, const void* y, const void* qref,
+                     const double* p1, int ldp, int mode, double* dst, int ldd, hipStream_t s,
+                     double* q1out = nullptr) {
+  hipLaunchKernelGGL((k_project<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                     h->d_dof_off, (const T*)Phi, ld, k, (const T*)y, (const T*)qref, h->d_var,
+                     h->nv, p1, ldp, mode, h->part, q1out);
+  hipLaunchKernelGGL(k_reduce_tiles, dim3(h->cfg.n_inst), dim3(128), 0, s, h->d_ptile_first,
+                     h->part, k, dst, ldd);
+  return ROM_OK;
+}
+
+template <typename T>
+rom_status isvd_t(rom_batch* h, const void* y, hipStream_t s) {
+  const int r = h->cfg.r, B = h->cfg.n_inst;
+  const int ldr = 2 * r + 4;
+  double* red = h->red;
+  // pass A: p1 = Phi^T y^, |y^|^2 ; pass B: p2 = Phi^T q1, |q1|^2
+  project_t<T>(h, h->Phi, r, r, y, h->q_ref, nullptr, 0, 1, red, ldr, s);
+  project_t<T>(h, h->Phi, r, r, y, h->q_ref, red, ldr, 2, red + r + 1, ldr, s, h->qtmp);
+  const int n = r + 1;
+  const size_t shm = sizeof(double) * (2 * n * n + 3 * n) + sizeof(int) * n;
+  double* pr = h->rstate;  // (p1, p2, 1/rho) per instance, stride 2r + 2
+  hipLaunchKernelGGL(k_isvd_core, dim3(B), dim3(256), shm, s, r, h->cfg.lambda, h->cfg.tau_rho,
+                     red, ldr, h->sigma, h->a, h->ubar, pr, h->flags);
+  hipLaunchKernelGGL((k_rotate<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                     h->d_dof_off, (const T*)h->Phi, r, r, (T*)h->Phi, r, r, h->ubar, n,
+                     (size_t)n * n, 1, h->qtmp, pr, 2 * r + 2, nullptr);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+template <typename T>
+rom_status reorth_t(rom_batch* h, hipStream_t s) {
+  const int r = h->cfg.r, B = h->cfg.n_inst;
+  hipLaunchKernelGGL((k_gram<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles, h->d_dof_off,
+                     (const T*)h->Phi, r, h->part);
+  hipLaunchKernelGGL(k_reorth_decide, dim3(B), dim3(256), 0, s, h->d_ptile_first, h->part, r,
+                     h->cfg.tau_orth, h->lmat, h->a, h->active, h->flags);
+  hipLaunchKernelGGL((k_rotate<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                     h->d_dof_off, (const T*)h->Phi, r, r, (T*)h->Phi, r, r, h->lmat, r,
+                     (size_t)r * r, 0, nullptr, nullptr, 0, h->active);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+template <typename T>
+rom_status pod_t(rom_batch* h, const void* Qtrain, int w, hipStream_t s) {
+  const int r = h->cfg.r, B = h->cfg.n_inst;
+  const int64_t tot = h->total_dof;
+  T* Q = nullptr;
+  double* R = nullptr;
+  double* U = nullptr;
+  double* redp = nullptr;
+  double* prp = nullptr;
+  ROM_HIP_CHECK(hipMalloc((void**)&Q, sizeof(T) * tot * w));
+  ROM_HIP_CHECK(hipMalloc((void**)&R, sizeof(double) * B * w * w));
+  ROM_HIP_CHECK(hipMalloc((void**)&U, sizeof(double) * B * w * w));
+  const int ldr = 2 * kMaxK + 4;
+  ROM_HIP_CHECK(hipMalloc((void**)&redp, sizeof(double) * B * ldr));
+  ROM_HIP_CHECK(hipMalloc((void**)&prp, sizeof(double) * B * (2 * kMaxK + 2)));
+  ROM_HIP_CHECK(hipMemsetAsync(R, 0, sizeof(double) * B * w * w, s));
+  for (int k = 0; k < w; ++k) {
+    const T* yk = (const T*)Qtrain + (size_t)k * tot;
+    if (k > 0) {
+      project_t<T>(h, Q, w, k, yk, h->q_ref, nullptr, 0, 1, redp, ldr, s);
+      project_t<T>(h, Q, w, k, yk, h->q_ref, redp, ldr, 2, redp + kMaxK + 1, ldr, s, h->qtmp);
+    } else {
+      project_t<T>(h, Q, w, 0, yk, h->q_ref, nullptr, 0, 1, redp, ldr, s);
+    }
+    hipLaunchKernelGGL(k_pod_column, dim3(B), dim3(128), 0, s, k, w, redp, ldr, R, prp,
+                       2 * kMaxK + 2);
+    hipLaunchKernelGGL((k_pod_write<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                       h->d_dof_off, Q, w, k, yk, (const T*)h->q_ref, h->d_var, h->nv, prp,
+                       2 * kMaxK + 2, h->qtmp, h->part);
+    hipLaunchKernelGGL(k_reduce_tiles, dim3(B), dim3(128), 0, s, h->d_ptile_first, h->part, 0,
+                       redp, ldr);
+    hipLaunchKernelGGL(k_pod_rho, dim3(B), dim3(64), 0, s, k, w, redp, ldr, R, prp, 2 * kMaxK + 2);
+    hipLaunchKernelGGL((k_pod_scale<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                       h->d_dof_off, Q, w, k, prp, 2 * kMaxK + 2);
+  }
+  const size_t shm = sizeof(double) * (2 * w * w + 2 * w) + sizeof(int) * w;
+  hipLaunchKernelGGL(k_pod_svd, dim3(B), dim3(256), shm, s, w, r, R, U, h->sigma, 1);
+  hipLaunchKernelGGL((k_rotate<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                     h->d_dof_off, (const T*)Q, w, w, (T*)h->Phi, r, r, U, w, (size_t)w * w, 0,
+                     nullptr, nullptr, 0, nullptr);
+  ROM_HIP_CHECK(hipGetLastError());
+  ROM_HIP_CHECK(hipStreamSynchronize(s));
+  ROM_HIP_CHECK(hipFree(Q));
+  ROM_HIP_CHECK(hipFree(R));
+  ROM_HIP_CHECK(hipFree(U));
+  ROM_HIP_CHECK(hipFree(redp));
+  ROM_HIP_CHECK(hipFree(prp));
+  return ROM_OK;
+}
+
+template <typename T>
+rom_status preprocess_t(rom_batch* h, const void* q0, const void* Qtrain, int w, hipStream_t s) {
+  ROM_HIP_CHECK(hipMemcpyAsync(h->q_ref, q0, sizeof(T) * h->total_dof, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL((k_sqdev<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles, h->d_dof_off,
+                     (const T*)Qtrain, w, h->total_dof, (const T*)h->q_ref, h->nv, h->part);
+  hipLaunchKernelGGL(k_dvar, dim3(h->cfg.n_inst), dim3(64), 0, s, h->d_ptile_first, h->part,
+                     h->nv, h->d_cell_off, w, h->d_var);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+__global__ void k_copy_cols(const double* src, int lds, int k, double* dst) {
+  const int b = blockIdx.x;
+  for (int c = threadIdx.x; c < k; c += blockDim.x) dst[(size_t)b * k + c] = src[(size_t)b * lds + c];
+}
+
+template <typename T>
+rom_status project_state_t(rom_batch* h, const void* q, hipStream_t s) {
+  const int r = h->cfg.r;
+  // a[b*r + c] = Phi^T D (q - q_ref); the squared norm lands in red scratch
+  project_t<T>(h, h->Phi, r, r, q, h->q_ref, nullptr, 0, 1, h->red, 2 * r + 4, s);
+  hipLaunchKernelGGL(k_copy_cols, dim3(h->cfg.n_inst), dim3(64), 0, s, h->red, 2 * r + 4, r, h->a);
+  return ROM_OK;
+}
+
+}  // namespace
+
+rom_status isvd_kernels_prepare() {
+  const int big = 160 * 1024 - 1024;
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_isvd_core, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_pod_svd, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  return ROM_OK;
+}
+
+rom_status launch_isvd(rom_batch* h, const void* y, hipStream_t s) {
+  return h->cfg.precision == ROM_F64 ? isvd_t<double>(h, y, s) : isvd_t<float>(h, y, s);
+}
+rom_status launch_isvd_project(rom_batch* h, const void* y, hipStream_t s) {
+  const int r = h->cfg.r;
+  return h->cfg.precision == ROM_F64
+             ? project_t<double>(h, h->Phi, r, r, y, h->q_ref, nullptr, 0, 1, h->red, 2 * r + 4, s)
+             : project_t<float>(h, h->Phi, r, r, y, h->q_ref, nullptr, 0, 1, h->red, 2 * r + 4, s);
+}
+
+rom_status launch_reorth(rom_batch* h, hipStream_t s) {
+  return h->cfg.precision == ROM_F64 ? reorth_t<double>(h, s) : reorth_t<float>(h, s);
+}
+rom_status launch_pod(rom_batch* h, const void* Q, int w, hipStream_t s) {
+  return h->cfg.precision == ROM_F64 ? pod_t<double>(h, Q, w, s) : pod_t<float>(h, Q, w, s);
+}
+rom_status launch_preprocess(rom_batch* h, const void* q0, const void* Q, int w, hipStream_t s) {
+  return h->cfg.precision == ROM_F64 ? preprocess_t<double>(h, q0, Q, w, s)
+                                     : preprocess_t<float>(h, q0, Q, w, s);
+}
+rom_status launch_project_state(rom_batch* h, const void* q, hipStream_t s) {
+  return h->cfg.precision == ROM_F64 ? project_state_t<double>(h, q, s)
+                                     : project_state_t<float>(h, q, s);
+}
+
+}  // namespace romhip

@@ -1,0 +1,501 @@
+// Full-order residual kernels: f(q), the backward-Euler residual, the Newton
+// system of a backward-Euler step (block-tridiagonal I - dt J_f and -r), and
+// the vector-Jacobian products.
+//
+// One thread block handles a tile of up to kTile consecutive cells of one
+// instance.  The tile and its two halo cells are staged through LDS with
+// coalesced element loads (the halo wraps for periodic models and copies the
+// end cell for zero-gradient walls), face fluxes are computed once per face
+// into LDS, and results are staged back through LDS for coalesced stores.
+#include "internal.h"
+#include "physics.h"
+
+namespace romhip {
+
+namespace {
+
+template <class Mdl, typename T>
+DEV void load_tile(T* sq, const T* qb, int64_t c0, int nt, int64_t n) {
+  constexpr int NV = Mdl::NV;
+  for (int e = threadIdx.x; e < (nt + 2) * NV; e += blockDim.x) {
+    const int lc = e / NV, v = e - (e / NV) * NV;
+    int64_t c = c0 - 1 + lc;
+    if (c < 0) c = Mdl::periodic ? c + n : 0;
+    else if (c >= n) c = Mdl::periodic ? c - n : n - 1;
+    sq[e] = qb[c * NV + v];
+  }
+}
+
+template <typename T>
+DEV void flag_or(uint32_t* flags, int b, unsigned fl) {
+  if (fl) atomicOr(&flags[b], fl);
+}
+
+DEV uint64_t norm_bits(float x) { return (uint64_t)__float_as_uint(fabsf(x)); }
+DEV uint64_t norm_bits(double x) { return (uint64_t)__double_as_longlong(fabs(x)); }
+
+// f(q) (be = 0) or q - q_prev - dt f(q) (be = 1); optional per-instance sup norm
+template <class Mdl, typename T>
+__global__ __launch_bounds__(kTile) void k_residual(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off,
+    const int64_t* __restrict__ cell_off, const double* __restrict__ phys, int nphys,
+    const T* __restrict__ q, const T* __restrict__ qprev, T dt, T* __restrict__ out,
+    uint32_t* flags, uint64_t* norms, const int32_t* active) {
+  constexpr int NV = Mdl::NV;
+  __shared__ T sq[(kTile + 2) * NV];
+  __shared__ T sH[(kTile + 1) * NV];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  if (active && !active[b]) return;
+  const int64_t n = cell_off[b + 1] - cell_off[b];
+  const int nt = (int)t.ncell;
+  const int64_t base = dof_off[b];
+  Mdl m(phys + (size_t)b * nphys);
+  load_tile<Mdl>(sq, q + base, t.cell0, nt, n);
+  __syncthreads();
+  unsigned fl = 0;
+  for (int k = threadIdx.x; k <= nt; k += blockDim.x)
+    m.face(&sq[k * NV], &sq[(k + 1) * NV], &sH[k * NV], fl);
+  __syncthreads();
+  T f[NV];
+  const int i = threadIdx.x;
+  const T inv = T(n), inv2 = T(n) * T(n);
+  if (i < nt) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T qm = sq[i * NV + v], q0 = sq[(i + 1) * NV + v], qp = sq[(i + 2) * NV + v];
+      f[v] = -(sH[(i + 1) * NV + v] - sH[i * NV + v]) * inv;
+      const T kap = m.kappa(v);
+      if (kap != T(0)) f[v] += kap * ((qp - q0) - (q0 - qm)) * inv2;
+    }
+    if (Mdl::has_source) {
+      T S[NV];
+      const double x = ((double)(t.cell0 + i) + 0.5) / (double)n;
+      m.source(&sq[(i + 1) * NV], x, S, fl);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) f[v] += S[v];
+    }
+  }
+  __syncthreads();
+  if (i < nt) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sH[i * NV + v] = f[v];
+  }
+  __syncthreads();
+  const int64_t o = base + t.cell0 * NV;
+  uint64_t nb = 0;
+  for (int e = threadIdx.x; e < nt * NV; e += blockDim.x) {
+    T val = sH[e];
+    if (qprev) val = q[o + e] - qprev[o + e] - dt * val;
+    if (!isfinite(val)) fl |= ROM_FLAG_NONFINITE;
+    out[o + e] = val;
+    const uint64_t bits = isfinite(val) ? norm_bits(val) : ~0ull;
+    nb = bits > nb ? bits : nb;
+  }
+  if (norms && nb) atomicMax((unsigned long long*)&norms[b], (unsigned long long)nb);
+  flag_or<T>(flags, b, fl);
+}
+
+// Jacobian blocks of f at cell i: Jm = df_i/dq_{i-1}, J0 = df_i/dq_i, Jp = df_i/dq_{i+1}
+// and f_i itself.  sq holds cells i-1, i, i+1 at qm, q0, qp.  lw/rw mark a
+// zero-gradient wall on the left / right (ghost = copy of the end cell).
+template <class Mdl, typename T>
+DEV void cell_jacobian(const Mdl& m, const T* qm, const T* q0, const T* qp, bool lw, bool rw,
+                       T inv, T inv2, double x, T* f, T* Jm, T* J0, T* Jp, unsigned& fl) {
+  constexpr int NV = Mdl::NV;
+  constexpr int NN = NV * NV;
+  T HL[NV], HR[NV], DLl[NN], DRl[NN], DLr[NN], DRr[NN];
+  m.face_jac(qm, q0, HL, DLl, DRl, fl);   // face i-1/2: (q_{i-1}, q_i)
+  m.face_jac(q0, qp, HR, DLr, DRr, fl);   // face i+1/2: (q_i, q_{i+1})
+  // f_i = -(HR - HL) inv
+#pragma unroll
+  for (int v = 0; v < NV; ++v) f[v] = -(HR[v] - HL[v]) * inv;
+#pragma unroll
+  for (int e = 0; e < NN; ++e) {
+    Jm[e] = DLl[e] * inv;
+    J0[e] = (DRl[e] - DLr[e]) * inv;
+    Jp[e] = -DRr[e] * inv;
+  }
+  if (lw) {  // ghost q_{-1} = q_0: the left face depends on q_0 through both sides
+#pragma unroll
+    for (int e = 0; e < NN; ++e) { J0[e] += Jm[e]; Jm[e] = T(0); }
+  }
+  if (rw) {
+#pragma unroll
+    for (int e = 0; e < NN; ++e) { J0[e] += Jp[e]; Jp[e] = T(0); }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const T kap = m.kappa(v);
+    if (kap != T(0)) {
+      f[v] += kap * ((qp[v] - q0[v]) - (q0[v] - qm[v])) * inv2;
+      const T c = kap * inv2;
+      // ghost neighbours fold onto the diagonal at walls
+      Jm[v * NV + v] += lw ? T(0) : c;
+      Jp[v * NV + v] += rw ? T(0) : c;
+      J0[v * NV + v] += -T(2) * c + (lw ? c : T(0)) + (rw ? c : T(0));
+    }
+  }
+  if (Mdl::has_source) {
+    T S[NV], DS[NN];
+    m.source_jac(q0, x, S, DS, fl);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) f[v] += S[v];
+#pragma unroll
+    for (int e = 0; e < NN; ++e) J0[e] += DS[e];
+  }
+}
+
+// Newton system of r(q) = q - q_prev - dt f(q): per cell A = -dt Jm,
+// B = I - dt J0, C = -dt Jp, d = -r; plus the sup norm of r.
+template <class Mdl, typename T>
+__global__ __launch_bounds__(kTile) void k_assemble(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off,
+    const int64_t* __restrict__ cell_off, const double* __restrict__ phys, int nphys,
+    const T* __restrict__ q, const T* __restrict__ qprev, T dt, T* __restrict__ sys,
+    uint32_t* flags, uint64_t* norms, uint64_t* ynorms, const int32_t* active) {
+  constexpr int NV = Mdl::NV;
+  constexpr int NN = NV * NV;
+  constexpr int SYS = 3 * NN + NV;
+  __shared__ T sq[(kTile + 2) * NV];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  if (active && !active[b]) return;
+  const int64_t n = cell_off[b + 1] - cell_off[b];
+  const int nt = (int)t.ncell;
+  const int64_t base = dof_off[b];
+  Mdl m(phys + (size_t)b * nphys);
+  load_tile<Mdl>(sq, q + base, t.cell0, nt, n);
+  __syncthreads();
+  const int i = threadIdx.x;
+  unsigned fl = 0;
+  uint64_t nb = 0, yb = 0;
+  if (i < nt) {
+    const int64_t c = t.cell0 + i;
+    const bool lw = !Mdl::periodic && c == 0;
+    const bool rw = !Mdl::periodic && c == n - 1;
+    T f[NV], Jm[NN], J0[NN], Jp[NN];
+    const double x = ((double)c + 0.5) / (double)n;
+    cell_jacobian(m, &sq[i * NV], &sq[(i + 1) * NV], &sq[(i + 2) * NV], lw, rw, T(n),
+                  T(n) * T(n), x, f, Jm, J0, Jp, fl);
+    T* o = sys + (cell_off[b] + c) * SYS;
+#pragma unroll
+    for (int e = 0; e < NN; ++e) {
+      o[e] = -dt * Jm[e];
+      o[NN + e] = -dt * J0[e] + ((e % (NV + 1)) == 0 ? T(1) : T(0));
+      o[2 * NN + e] = -dt * Jp[e];
+    }
+    const int64_t g = base + c * NV;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T r = q[g + v] - qprev[g + v] - dt * f[v];
+      o[3 * NN + v] = -r;
+      if (!isfinite(r)) fl |= ROM_FLAG_NONFINITE;
+      const uint64_t bits = isfinite(r) ? norm_bits(r) : ~0ull;
+      nb = bits > nb ? bits : nb;
+      const uint64_t yv = norm_bits(q[g + v]);
+      yb = yv > yb ? yv : yb;
+    }
+  }
+  if (norms && nb) atomicMax((unsigned long long*)&norms[b], (unsigned long long)nb);
+  if (ynorms && yb) atomicMax((unsigned long long*)&ynorms[b], (unsigned long long)yb);
+  flag_or<T>(flags, b, fl);
+}
+
+// Transposed Newton system of the adjoint of a converged step:
+// (I - dt J_f)^T x = rhs, written as a block-tridiagonal system per cell:
+// A_i = (C_{i-1})^T, B_i = (B_i)^T, C_i = (A_{i+1})^T with the forward blocks
+// A = -dt Jm, B = I - dt J0, C = -dt Jp.  Each thread recomputes the forward
+// blocks of its two neighbours.
+template <class Mdl, typename T>
+__global__ __launch_bounds__(kTile) void k_assemble_adjoint(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off,
+    const int64_t* __restrict__ cell_off, const double* __restrict__ phys, int nphys,
+    const T* __restrict__ q, T dt, const T* __restrict__ rhs, T* __restrict__ sys,
+    uint32_t* flags) {
+  constexpr int NV = Mdl::NV;
+  constexpr int NN = NV * NV;
+  constexpr int SYS = 3 * NN + NV;
+  __shared__ T sq[(kTile + 4) * NV];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  const int64_t n = cell_off[b + 1] - cell_off[b];
+  const int nt = (int)t.ncell;
+  const int64_t base = dof_off[b];
+  Mdl m(phys + (size_t)b * nphys);
+  // stage cells c0-2 .. c0+nt+1
+  for (int e = threadIdx.x; e < (nt + 4) * NV; e += blockDim.x) {
+    const int lc = e / NV, v = e - (e / NV) * NV;
+    int64_t c = t.cell0 - 2 + lc;
+    if (Mdl::periodic) { c = ((c % n) + n) % n; }
+    else { c = c < 0 ? 0 : (c >= n ? n - 1 : c); }
+    sq[e] = q[base + c * NV + v];
+  }
+  __syncthreads();
+  const int i = threadIdx.x;
+  unsigned fl = 0;
+  if (i < nt) {
+    const int64_t c = t.cell0 + i;
+    T f[NV], Jm[NN], J0[NN], Jp[NN];
+    T* o = sys + (cell_off[b] + c) * SYS;
+    // own diagonal block
+    {
+      const bool lw = !Mdl::periodic && c == 0, rw = !Mdl::periodic && c == n - 1;
+      cell_jacobian(m, &sq[(i + 1) * NV], &sq[(i + 2) * NV], &sq[(i + 3) * NV], lw, rw, T(n),
+                    T(n) * T(n), ((double)c + 0.5) / (double)n, f, Jm, J0, Jp, fl);
+#pragma unroll
+      for (int r = 0; r < NV; ++r)
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+          o[NN + r * NV + k] = -dt * J0[k * NV + r] + (r == k ? T(1) : T(0));
+    }
+    // left neighbour's C block (row c-1, coupling to c), transposed -> our A
+    {
+      const int64_t cl = c - 1;
+      const bool exists = Mdl::periodic || cl >= 0;
+      if (exists) {
+        const int64_t cw = (cl + n) % n;
+        const bool lw = !Mdl::periodic && cw == 0, rw = !Mdl::periodic && cw == n - 1;
+        cell_jacobian(m, &sq[i * NV], &sq[(i + 1) * NV], &sq[(i + 2) * NV], lw, rw, T(n),
+                      T(n) * T(n), ((double)cw + 0.5) / (double)n, f, Jm, J0, Jp, fl);
+      }
+#pragma unroll
+      for (int r = 0; r < NV; ++r)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) o[r * NV + k] = exists ? -dt * Jp[k * NV + r] : T(0);
+    }
+    // right neighbour's A block (row c+1, coupling to c), transposed -> our C
+    {
+      const int64_t cr = c + 1;
+      const bool exists = Mdl::periodic || cr < n;
+      if (exists) {
+        const int64_t cw = cr % n;
+        const bool lw = !Mdl::periodic && cw == 0, rw = !Mdl::periodic && cw == n - 1;
+        cell_jacobian(m, &sq[(i + 2) * NV], &sq[(i + 3) * NV], &sq[(i + 4) * NV], lw, rw, T(n),
+                      T(n) * T(n), ((double)cw + 0.5) / (double)n, f, Jm, J0, Jp, fl);
+      }
+#pragma unroll
+      for (int r = 0; r < NV; ++r)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) o[2 * NN + r * NV + k] = exists ? -dt * Jm[k * NV + r] : T(0);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) o[3 * NN + v] = rhs[base + c * NV + v];
+  }
+  flag_or<T>(flags, b, fl);
+}
+
+// gq = J_f(q)^T w (be = 0) or gq = w - dt J_f^T w, gq_prev = -w (be = 1).
+// Per cell c: contributions of face c (between c-1 and c) through dH/dq_R and of
+// face c+1 through dH/dq_L, each with lambda = (w_right - w_left)/dx; the
+// diffusion adjoint; the source adjoint.
+template <class Mdl, typename T>
+__global__ __launch_bounds__(kTile) void k_residual_vjp(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off,
+    const int64_t* __restrict__ cell_off, const double* __restrict__ phys, int nphys,
+    const T* __restrict__ q, const T* __restrict__ w, T dt, int be, T* __restrict__ gq,
+    T* __restrict__ gqp, uint32_t* flags) {
+  constexpr int NV = Mdl::NV;
+  constexpr int NN = NV * NV;
+  __shared__ T sq[(kTile + 2) * NV];
+  __shared__ T sw[(kTile + 2) * NV];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  const int64_t n = cell_off[b + 1] - cell_off[b];
+  const int nt = (int)t.ncell;
+  const int64_t base = dof_off[b];
+  Mdl m(phys + (size_t)b * nphys);
+  load_tile<Mdl>(sq, q + base, t.cell0, nt, n);
+  for (int e = threadIdx.x; e < (nt + 2) * NV; e += blockDim.x) {
+    const int lc = e / NV, v = e - (e / NV) * NV;
+    int64_t c = t.cell0 - 1 + lc;
+    bool ghost = false;
+    if (c < 0) { if (Mdl::periodic) c += n; else ghost = true; }
+    else if (c >= n) { if (Mdl::periodic) c -= n; else ghost = true; }
+    sw[e] = ghost ? T(0) : w[base + c * NV + v];   // no residual row outside walls
+  }
+  __syncthreads();
+  const int i = threadIdx.x;
+  unsigned fl = 0;
+  if (i < nt) {
+    const int64_t c = t.cell0 + i;
+    const bool lw = !Mdl::periodic && c == 0, rw = !Mdl::periodic && c == n - 1;
+    const T inv = T(n), inv2 = T(n) * T(n);
+    T H[NV], DL[NN], DR[NN], g[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) g[v] = T(0);
+    // face c (left): lambda = (w_c - w_{c-1}) / dx, acts through dH/dq_R (and dH/dq_L at a wall)
+    m.face_jac(&sq[i * NV], &sq[(i + 1) * NV], H, DL, DR, fl);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      T acc = T(0);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const T lam = (sw[(i + 1) * NV + v] - sw[i * NV + v]) * inv;
+        acc += (DR[v * NV + k] + (lw ? DL[v * NV + k] : T(0))) * lam;
+      }
+      g[k] += acc;
+    }
+    // face c+1 (right): lambda = (w_{c+1} - w_c) / dx, acts through dH/dq_L (and dH/dq_R at a wall)
+    m.face_jac(&sq[(i + 1) * NV], &sq[(i + 2) * NV], H, DL, DR, fl);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      T acc = T(0);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const T lam = (sw[(i + 2) * NV + v] - sw[(i + 1) * NV + v]) * inv;
+        acc += (DL[v * NV + k] + (rw ? DR[v * NV + k] : T(0))) * lam;
+      }
+      g[k] += acc;
+    }
+    // diffusion: row j contributes kappa w_j / dx^2 to its (ghost-mapped) neighbours
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T kap = m.kappa(v);
+      if (kap != T(0)) {
+        const T wm = sw[i * NV + v], w0 = sw[(i + 1) * NV + v], wp = sw[(i + 2) * NV + v];
+        T acc = wm + wp - T(2) * w0;
+        if (lw) acc += w0;  // row 0's left ghost is cell 0 itself
+        if (rw) acc += w0;
+        g[v] += kap * inv2 * acc;
+      }
+    }
+    if (Mdl::has_source) {
+      T S[NV], DS[NN];
+      m.source_jac(&sq[(i + 1) * NV], ((double)c + 0.5) / (double)n, S, DS, fl);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        T acc = T(0);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc += DS[v * NV + k] * sw[(i + 1) * NV + v];
+        g[k] += acc;
+      }
+    }
+    const int64_t o = base + c * NV;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (be) {
+        const T wv = sw[(i + 1) * NV + v];
+        gq[o + v] = wv - dt * g[v];
+        if (gqp) gqp[o + v] = -wv;
+      } else {
+        gq[o + v] = g[v];
+      }
+    }
+  }
+  flag_or<T>(flags, b, fl);
+}
+
+}  // namespace
+
+template <class M>
+struct Tag { using type = M; };
+
+// Calls fn(Tag<Model>{}) for the model of the handle's problem.
+template <typename T, class F>
+rom_status with_model(const rom_batch* h, F&& fn) {
+  switch (h->cfg.problem) {
+    case ROM_BURGERS: return fn(Tag<BurgersModel<T>>{});
+    case ROM_EULER_RUSANOV: return fn(Tag<EulerModel<T, false>>{});
+    case ROM_EULER_HLLC: return fn(Tag<EulerModel<T, true>>{});
+    case ROM_REACT: return fn(Tag<ReactModel<T>>{});
+  }
+  set_error("unknown problem");
+  return ROM_E_INVAL;
+}
+
+template <typename T>
+static rom_status residual_t(rom_batch* h, const void* q, const void* q_prev, double dt, void* out,
+                             uint64_t* norms, const int32_t* active, hipStream_t s) {
+  return with_model<T>(h, [&](auto tag) -> rom_status {
+    using M = typename decltype(tag)::type;
+    hipLaunchKernelGGL((k_residual<M, T>), dim3(h->n_tiles), dim3(kTile), 0, s, h->d_tiles,
+                       h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const T*)q,
+                       (const T*)q_prev, (T)dt, (T*)out, h->flags, norms, active);
+    return ROM_OK;
+  });
+}
+
+rom_status launch_residual(rom_batch* h, const void* q, const void* q_prev, double dt, void* out,
+                           hipStream_t s) {
+  rom_status st = h->cfg.precision == ROM_F64
+                      ? residual_t<double>(h, q, q_prev, dt, out, nullptr, nullptr, s)
+                      : residual_t<float>(h, q, q_prev, dt, out, nullptr, nullptr, s);
+  ROM_HIP_CHECK(hipGetLastError());
+  return st;
+}
+
+rom_status launch_residual_norm(rom_batch* h, const void* q, const void* q_prev, double dt,
+                                void* out, int it, hipStream_t s) {
+  uint64_t* norms = h->norms + (size_t)it * h->cfg.n_inst;
+  rom_status st = h->cfg.precision == ROM_F64
+                      ? residual_t<double>(h, q, q_prev, dt, out, norms, h->active, s)
+                      : residual_t<float>(h, q, q_prev, dt, out, norms, h->active, s);
+  ROM_HIP_CHECK(hipGetLastError());
+  return st;
+}
+
+template <typename T>
+static rom_status assemble_t(rom_batch* h, const void* q, const void* q_prev, double dt, int it,
+                             hipStream_t s) {
+  return with_model<T>(h, [&](auto tag) -> rom_status {
+    using M = typename decltype(tag)::type;
+    hipLaunchKernelGGL((k_assemble<M, T>), dim3(h->n_tiles), dim3(kTile), 0, s, h->d_tiles,
+                       h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const T*)q,
+                       (const T*)q_prev, (T)dt, (T*)h->levels[0].sys, h->flags,
+                       h->norms + (size_t)it * h->cfg.n_inst,
+                       h->norms + (size_t)(h->cfg.newton_max + 1 + it) * h->cfg.n_inst, h->active);
+    return ROM_OK;
+  });
+}
+
+rom_status launch_assemble(rom_batch* h, const void* q, const void* q_prev, double dt, int it,
+                           hipStream_t s) {
+  rom_status st = h->cfg.precision == ROM_F64 ? assemble_t<double>(h, q, q_prev, dt, it, s)
+                                              : assemble_t<float>(h, q, q_prev, dt, it, s);
+  ROM_HIP_CHECK(hipGetLastError());
+  return st;
+}
+
+template <typename T>
+static rom_status assemble_adj_t(rom_batch* h, const void* q, double dt, const void* rhs,
+                                 hipStream_t s) {
+  return with_model<T>(h, [&](auto tag) -> rom_status {
+    using M = typename decltype(tag)::type;
+    hipLaunchKernelGGL((k_assemble_adjoint<M, T>), dim3(h->n_tiles), dim3(kTile), 0, s,
+                       h->d_tiles, h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys,
+                       (const T*)q, (T)dt, (const T*)rhs, (T*)h->levels[0].sys, h->flags);
+    return ROM_OK;
+  });
+}
+
+rom_status launch_assemble_adjoint(rom_batch* h, const void* q, double dt, const void* rhs,
+                                   hipStream_t s) {
+  rom_status st = h->cfg.precision == ROM_F64 ? assemble_adj_t<double>(h, q, dt, rhs, s)
+                                              : assemble_adj_t<float>(h, q, dt, rhs, s);
+  ROM_HIP_CHECK(hipGetLastError());
+  return st;
+}
+
+template <typename T>
+static rom_status vjp_t(rom_batch* h, const void* q, const void* q_prev, double dt,
+                        const void* gbar, void* gq, void* gq_prev, hipStream_t s) {
+  return with_model<T>(h, [&](auto tag) -> rom_status {
+    using M = typename decltype(tag)::type;
+    hipLaunchKernelGGL((k_residual_vjp<M, T>), dim3(h->n_tiles), dim3(kTile), 0, s, h->d_tiles,
+                       h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const T*)q,
+                       (const T*)gbar, (T)dt, q_prev ? 1 : 0, (T*)gq, (T*)gq_prev, h->flags);
+    return ROM_OK;
+  });
+}
+
+rom_status launch_residual_vjp(rom_batch* h, const void* q, const void* q_prev, double dt,
+                               const void* gbar, void* gq, void* gq_prev, hipStream_t s) {
+  rom_status st = h->cfg.precision == ROM_F64
+                      ? vjp_t<double>(h, q, q_prev, dt, gbar, gq, gq_prev, s)
+                      : vjp_t<float>(h, q, q_prev, dt, gbar, gq, gq_prev, s);
+  ROM_HIP_CHECK(hipGetLastError());
+  return st;
+}
+
+}  // namespace romhip

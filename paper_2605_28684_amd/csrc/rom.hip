@@ -1,0 +1,744 @@
+// Reduced steps, sampling and rebuild.
+//
+//  * Galerkin backward-Euler step (eq. galerkin_continuous_rom discretised by
+//    backward Euler): Newton on g(a) = a - a_prev - dt Phi^T D f(q~(a)) with
+//    J_g = I - dt Phi^T D J_f D^-1 Phi.  One fused pass over the basis per
+//    Newton iteration: reconstruct q~ on a chunk (+ halo), evaluate f and the
+//    three Jacobian diagonals per row, form (J_f Phi) rows on the fly and
+//    accumulate Phi^T f (FP64) and Phi^T (J_f Phi) per block; a second
+//    launch reduces the block partials in fixed order and solves the r x r
+//    system in FP64 (partial-pivoting LU), one workgroup per instance.
+//  * Hyper-reduced LSPG step (eqs. hyperreduced_lspg,
+//    hyperreduced_lspg_stationarity): Gauss-Newton on the sampled residual
+//    M P^T D r with M = (P^T Phi)^+, evaluated on the sample mesh only (each
+//    sampled row needs its cell and the two neighbours), in FP64, one
+//    workgroup per instance for all iterations.
+//  * Greedy DEIM with oversampling (interpolation-residual argmax, then a
+//    least-squares round) and the (P^T Phi)^+ rebuild by Householder QR.
+#include "internal.h"
+#include "physics.h"
+
+namespace romhip {
+
+namespace {
+
+constexpr int kGC = 64;  // rows per Galerkin chunk
+
+template <class M>
+struct Tag { using type = M; };
+
+// ------------------------------------------------------------------ Galerkin pass
+template <typename T>
+__global__ __launch_bounds__(256) void k_galerkin_pass(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off,
+    const int64_t* __restrict__ cell_off, const double* __restrict__ phys, int nphys,
+    const T* __restrict__ Phi, int r, const T* __restrict__ qref, const double* __restrict__ dvar,
+    const double* __restrict__ a, const int32_t* __restrict__ active, double* __restrict__ gpart,
+    T* __restrict__ mpart) {
+  __shared__ T sP[kGC + 2][kMaxR + 1];
+  __shared__ double sQ[kGC + 2];
+  __shared__ double sF[kGC], sA[kGC], sB[kGC], sC[kGC];
+  __shared__ double sa[kMaxR];
+  __shared__ T red[4][kMaxR];
+  __shared__ double redg[4][kMaxR];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  if (!active[b]) return;
+  const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
+  const int64_t n = cell_off[b + 1] - cell_off[b];
+  const int64_t base = dof_off[b];
+  const double nu = phys[(size_t)b * nphys];
+  const double dinv = 1.0 / dvar[b];
+  const double inv = (double)n, inv2 = (double)n * (double)n;
+  for (int c = tid; c < r; c += blockDim.x) sa[c] = a[(size_t)b * r + c];
+  T acc[kMaxR];
+#pragma unroll
+  for (int c = 0; c < kMaxR; ++c) acc[c] = T(0);
+  double accg = 0.0;
+  for (int64_t r0 = 0; r0 < t.ncell; r0 += kGC) {
+    const int nr = (int)(t.ncell - r0 < kGC ? t.ncell - r0 : kGC);
+    const int64_t c0 = t.cell0 + r0;
+    __syncthreads();
+    for (int e = tid; e < (nr + 2) * r; e += blockDim.x) {
+      const int rr = e / r, c = e - rr * r;
+      int64_t cell = c0 - 1 + rr;
+      cell = cell < 0 ? cell + n : (cell >= n ? cell - n : cell);
+      sP[rr][c] = Phi[(base + cell) * r + c];
+    }
+    __syncthreads();
+    if (tid < nr + 2) {
+      int64_t cell = c0 - 1 + tid;
+      cell = cell < 0 ? cell + n : (cell >= n ? cell - n : cell);
+      double s = 0.0;
+      for (int c = 0; c < r; ++c) s += (double)sP[tid][c] * sa[c];
+      sQ[tid] = (double)qref[base + cell] + s * dinv;
+    }
+    __syncthreads();
+    if (tid < nr) {
+      const double um = sQ[tid], u0 = sQ[tid + 1], up = sQ[tid + 2];
+      double dla, dlb, dra, drb;
+      const double FL = godunov(um, u0, dla, dlb);
+      const double FR = godunov(u0, up, dra, drb);
+      sF[tid] = -(FR - FL) * inv + nu * ((up - u0) - (u0 - um)) * inv2;
+      sA[tid] = dla * inv + nu * inv2;
+      sB[tid] = (dlb - dra) * inv - 2.0 * nu * inv2;
+      sC[tid] = -drb * inv + nu * inv2;
+    }
+    __syncthreads();
+    if (lane < r) {
+      for (int rr = grp; rr < nr; rr += 4) {
+        const double z = sA[rr] * (double)sP[rr][lane] + sB[rr] * (double)sP[rr + 1][lane] +
+                         sC[rr] * (double)sP[rr + 2][lane];
+        accg += (double)sP[rr + 1][lane] * sF[rr];
+        const T zt = (T)z;
+#pragma unroll
+        for (int c = 0; c < kMaxR; ++c)
+          if (c < r) acc[c] += sP[rr + 1][c] * zt;
+      }
+    }
+  }
+  // reduce the four row groups; M[c][lane] = sum_i Phi_ic (J Phi)_i,lane
+  T* mo = mpart + (size_t)blockIdx.x * kMaxR * kMaxR;
+#pragma unroll
+  for (int c = 0; c < kMaxR; ++c) {
+    if (c < r) {
+      __syncthreads();
+      if (lane < r) red[grp][lane] = acc[c];
+      __syncthreads();
+      if (tid < r) mo[c * r + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    }
+  }
+  __syncthreads();
+  if (lane < r) redg[grp][lane] = accg;
+  __syncthreads();
+  if (tid < r) gpart[(size_t)blockIdx.x * kMaxR + tid] = redg[0][tid] + redg[1][tid] + redg[2][tid] + redg[3][tid];
+}
+
+// LU with partial pivoting on an n x n FP64 matrix in LDS (row-major, ld n),
+// solving A x = b in place of b.  Single-thread pivot search, row updates by
+// the whole block.  Returns false (via *ok) if a pivot vanishes.
+DEV void lu_solve_block(double* A, double* bvec, int n, int* ok) {
+  __shared__ int piv;
+  const int tid = threadIdx.x;
+  if (tid == 0) *ok = 1;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      int p = k;
+      double best = fabs(A[k * n + k]);
+      for (int i = k + 1; i < n; ++i) {
+        const double v = fabs(A[i * n + k]);
+        if (v > best) { best = v; p = i; }
+      }
+      piv = p;
+      if (best == 0.0) *ok = 0;
+    }
+    __syncthreads();
+    const int p = piv;
+    if (p != k) {
+      for (int j = tid; j < n; j += blockDim.x) {
+        const double tmp = A[k * n + j]; A[k * n + j] = A[p * n + j]; A[p * n + j] = tmp;
+      }
+      if (tid == 0) { const double tmp = bvec[k]; bvec[k] = bvec[p]; bvec[p] = tmp; }
+    }
+    __syncthreads();
+    const double pk = A[k * n + k];
+    for (int i = k + 1 + tid; i < n; i += blockDim.x) {
+      const double f = pk != 0.0 ? A[i * n + k] / pk : 0.0;
+      A[i * n + k] = f;
+      for (int j = k + 1; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+      bvec[i] -= f * bvec[k];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    for (int i = n - 1; i >= 0; --i) {
+      double s = bvec[i];
+      for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * bvec[j];
+      bvec[i] = A[i * n + i] != 0.0 ? s / A[i * n + i] : 0.0;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_galerkin_solve(
+    const int* __restrict__ tfirst, const double* __restrict__ gpart, const T* __restrict__ mpart,
+    int r, double dt, const double* __restrict__ dvar, double* __restrict__ a,
+    const double* __restrict__ a_prev, int32_t* __restrict__ active, int32_t* __restrict__ iters,
+    double tol, uint32_t* flags) {
+  __shared__ double J[kMaxR * kMaxR];
+  __shared__ double g[kMaxR];
+  __shared__ int ok;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  if (!active[b]) return;
+  const double d = dvar[b];
+  for (int e = tid; e < r * r; e += blockDim.x) {
+    double s = 0.0;
+    for (int tt = tfirst[b]; tt < tfirst[b + 1]; ++tt) s += (double)mpart[(size_t)tt * kMaxR * kMaxR + e];
+    const int i = e / r, j = e % r;
+    J[e] = (i == j ? 1.0 : 0.0) - dt * s;
+  }
+  for (int c = tid; c < r; c += blockDim.x) {
+    double s = 0.0;
+    for (int tt = tfirst[b]; tt < tfirst[b + 1]; ++tt) s += gpart[(size_t)tt * kMaxR + c];
+    g[c] = -(a[(size_t)b * r + c] - a_prev[(size_t)b * r + c] - dt * d * s);
+  }
+  __syncthreads();
+  lu_solve_block(J, g, r, &ok);
+  if (tid == 0) {
+    double dm = 0.0, am = 0.0;
+    bool fin = true;
+    for (int c = 0; c < r; ++c) {
+      const double an = a[(size_t)b * r + c] + g[c];
+      a[(size_t)b * r + c] = an;
+      dm = fmax(dm, fabs(g[c]));
+      am = fmax(am, fabs(an));
+      fin = fin && isfinite(an);
+    }
+    iters[b] += 1;
+    if (!ok) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
+    if (!fin) atomicOr(&flags[b], ROM_FLAG_NONFINITE);
+    if (dm <= tol * (1.0 + am) || !fin) active[b] = 0;
+  }
+}
+
+__global__ void k_rom_finalize(int n_inst, const int32_t* active, uint32_t* flags) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n_inst && active[b]) atomicOr(&flags[b], ROM_FLAG_ROM_NOCONV);
+}
+
+// ------------------------------------------------------------------ HR-LSPG step
+// mesh_phi[b][s][o][w][k], o in {0,1,2} = cells c-1, c, c+1 of the sampled row's cell.
+template <class Mdl>
+__global__ __launch_bounds__(256) void k_hr_step(
+    int r, int ns, const int64_t* __restrict__ cell_off, const double* __restrict__ phys, int nphys,
+    const int32_t* __restrict__ P, const double* __restrict__ Mp, const double* __restrict__ mphi,
+    const double* __restrict__ mqref, const double* __restrict__ dvar, double* __restrict__ a,
+    double dt, double tol, int max_it, int32_t* __restrict__ iters, uint32_t* flags) {
+  constexpr int NV = Mdl::NV;
+  constexpr int NN = NV * NV;
+  extern __shared__ double sm[];
+  double* sa = sm;                 // r
+  double* sap = sa + kMaxR;        // r
+  double* bs = sap + kMaxR;        // ns
+  double* As = bs + kMaxNs;        // ns x r
+  double* Ar = As + kMaxNs * kMaxR;  // r x r
+  double* rh = Ar + kMaxR * kMaxR;   // r
+  __shared__ int ok, stop;
+  __shared__ unsigned flacc;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int64_t n = cell_off[b + 1] - cell_off[b];
+  Mdl m(phys + (size_t)b * nphys);
+  const double* dv = dvar + (size_t)b * NV;
+  const double* Mb = Mp + (size_t)b * r * ns;
+  for (int c = tid; c < r; c += blockDim.x) { sa[c] = a[(size_t)b * r + c]; sap[c] = sa[c]; }
+  if (tid == 0) { stop = 0; flacc = 0; }
+  __syncthreads();
+  int it = 0;
+  for (; it < max_it; ++it) {
+    // sampled rows of P^T D r and P^T D J_r D^-1 Phi
+    for (int s = tid; s < ns; s += blockDim.x) {
+      const int p = P[(size_t)b * ns + s];
+      const int64_t c = p / NV;
+      const int v = p % NV;
+      const double* Ph = mphi + ((size_t)b * ns + s) * 3 * NV * r;
+      const double* Qr = mqref + ((size_t)b * ns + s) * 3 * NV;
+      double q3[3 * NV];
+      for (int e = 0; e < 3 * NV; ++e) {
+        double acc = 0.0;
+        for (int k = 0; k < r; ++k) acc += Ph[e * r + k] * sa[k];
+        q3[e] = Qr[e] + acc / dv[e % NV];
+      }
+      const bool lw = !Mdl::periodic && c == 0, rw = !Mdl::periodic && c == n - 1;
+      double f[NV], Jm[NN], J0[NN], Jp[NN];
+      unsigned fl = 0;
+      {
+        // cell_jacobian for one cell (FP64), inlined to avoid a cross-file template
+        double HL[NV], HR[NV], DLl[NN], DRl[NN], DLr[NN], DRr[NN];
+        m.face_jac(&q3[0], &q3[NV], HL, DLl, DRl, fl);
+        m.face_jac(&q3[NV], &q3[2 * NV], HR, DLr, DRr, fl);
+        const double inv = (double)n, inv2 = (double)n * (double)n;
+        for (int w = 0; w < NV; ++w) f[w] = -(HR[w] - HL[w]) * inv;
+        for (int e = 0; e < NN; ++e) {
+          Jm[e] = DLl[e] * inv; J0[e] = (DRl[e] - DLr[e]) * inv; Jp[e] = -DRr[e] * inv;
+        }
+        if (lw) for (int e = 0; e < NN; ++e) { J0[e] += Jm[e]; Jm[e] = 0.0; }
+        if (rw) for (int e = 0; e < NN; ++e) { J0[e] += Jp[e]; Jp[e] = 0.0; }
+        for (int w = 0; w < NV; ++w) {
+          const double kap = m.kappa(w);
+          if (kap != 0.0) {
+            f[w] += kap * ((q3[2 * NV + w] - q3[NV + w]) - (q3[NV + w] - q3[w])) * inv2;
+            const double cc = kap * inv2;
+            Jm[w * NV + w] += lw ? 0.0 : cc;
+            Jp[w * NV + w] += rw ? 0.0 : cc;
+            J0[w * NV + w] += -2.0 * cc + (lw ? cc : 0.0) + (rw ? cc : 0.0);
+          }
+        }
+        if (Mdl::has_source) {
+          double S[NV], DS[NN];
+          m.source_jac(&q3[NV], ((double)c + 0.5) / (double)n, S, DS, fl);
+          for (int w = 0; w < NV; ++w) f[w] += S[w];
+          for (int e = 0; e < NN; ++e) J0[e] += DS[e];
+        }
+      }
+      if (fl) atomicOr(&flacc, fl);
+      const double dp = dv[v];
+      double bsum = 0.0;
+      for (int k = 0; k < r; ++k) bsum += Ph[(NV + v) * r + k] * (sa[k] - sap[k]);
+      bs[s] = bsum - dt * dp * f[v];
+      for (int k = 0; k < r; ++k) {
+        double acc = 0.0;
+        for (int w = 0; w < NV; ++w) {
+          acc += Jm[v * NV + w] * Ph[w * r + k] / dv[w];
+          acc += J0[v * NV + w] * Ph[(NV + w) * r + k] / dv[w];
+          acc += Jp[v * NV + w] * Ph[(2 * NV + w) * r + k] / dv[w];
+        }
+        As[s * kMaxR + k] = Ph[(NV + v) * r + k] - dt * dp * acc;
+      }
+    }
+    __syncthreads();
+    // rho = M b ; A_red = M A
+    for (int e = tid; e < r * r; e += blockDim.x) {
+      const int i = e / r, k = e % r;
+      double acc = 0.0;
+      for (int s = 0; s < ns; ++s) acc += Mb[i * ns + s] * As[s * kMaxR + k];
+      Ar[e] = acc;
+    }
+    for (int i = tid; i < r; i += blockDim.x) {
+      double acc = 0.0;
+      for (int s = 0; s < ns; ++s) acc += Mb[i * ns + s] * bs[s];
+      rh[i] = -acc;
+    }
+    __syncthreads();
+    lu_solve_block(Ar, rh, r, &ok);
+    if (tid == 0) {
+      double dm = 0.0, am = 0.0;
+      bool fin = true;
+      for (int c = 0; c < r; ++c) {
+        sa[c] += rh[c];
+        dm = fmax(dm, fabs(rh[c]));
+        am = fmax(am, fabs(sa[c]));
+        fin = fin && isfinite(sa[c]);
+      }
+      if (!ok) flacc |= ROM_FLAG_SINGULAR;
+      if (!fin) flacc |= ROM_FLAG_NONFINITE;
+      stop = (dm <= tol * (1.0 + am) || !fin) ? 1 : 0;
+    }
+    __syncthreads();
+    if (stop) { ++it; break; }
+  }
+  for (int c = tid; c < r; c += blockDim.x) a[(size_t)b * r + c] = sa[c];
+  if (tid == 0) {
+    iters[b] = it;
+    unsigned fl = flacc;
+    if (!stop) fl |= ROM_FLAG_ROM_NOCONV;
+    if (fl) atomicOr(&flags[b], fl);
+  }
+}
+
+// ------------------------------------------------------------------ DEIM
+// residual of column j after fitting columns 0..j-1 with coef; per-tile argmax
+// of |res| over rows not yet chosen (lowest row on ties).
+template <typename T>
+__global__ __launch_bounds__(256) void k_deim_argmax(const Tile* __restrict__ tiles,
+                                                     const int64_t* __restrict__ dof_off,
+                                                     const T* __restrict__ Phi, int r, int j,
+                                                     const double* __restrict__ coef, int ldc,
+                                                     const uint32_t* __restrict__ chosen,
+                                                     const uint32_t* __restrict__ epoch_p,
+                                                     double* __restrict__ tval,
+                                                     int64_t* __restrict__ tidx) {
+  __shared__ double sc[kMaxR];
+  __shared__ double bv[256];
+  __shared__ int64_t bi[256];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst, tid = threadIdx.x;
+  const int64_t base = dof_off[b];
+  const uint32_t epoch = *epoch_p;
+  for (int c = tid; c < j; c += blockDim.x) sc[c] = coef[(size_t)b * ldc + c];
+  __syncthreads();
+  double best = -1.0;
+  int64_t bidx = -1;
+  for (int64_t rr = tid; rr < t.ncell; rr += blockDim.x) {
+    const int64_t lr = t.cell0 + rr, g = base + lr;
+    if (chosen[g] == epoch) continue;
+    const T* row = Phi + g * r;
+    double res = (double)row[j];
+    for (int c = 0; c < j; ++c) res -= (double)row[c] * sc[c];
+    const double v = fabs(res);
+    if (v > best || (v == best && lr < bidx)) { best = v; bidx = lr; }
+  }
+  bv[tid] = best;
+  bi[tid] = bidx;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) {
+      const double v2 = bv[tid + st];
+      const int64_t i2 = bi[tid + st];
+      if (i2 >= 0 && (v2 > bv[tid] || (v2 == bv[tid] && (bi[tid] < 0 || i2 < bi[tid])))) {
+        bv[tid] = v2; bi[tid] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) { tval[blockIdx.x] = bv[0]; tidx[blockIdx.x] = bi[0]; }
+}
+
+// Householder QR least squares on an m x nc FP64 matrix in LDS (row-major,
+// ld = kMaxR + 1): overwrites x[0..nc) with argmin ||A x - rhs||.  Single
+// thread per column reflector application loop; sizes here are tiny.
+DEV void qr_lstsq(double* A, int m, int nc, double* rhs, double* x) {
+  const int tid = threadIdx.x;
+  constexpr int ld = kMaxR + 1;
+  __shared__ double beta, nrm2;
+  for (int k = 0; k < nc; ++k) {
+    if (tid == 0) {
+      double s = 0.0;
+      for (int i = k; i < m; ++i) s += A[i * ld + k] * A[i * ld + k];
+      nrm2 = sqrt(s);
+    }
+    __syncthreads();
+    const double alpha = A[k * ld + k] >= 0.0 ? -nrm2 : nrm2;
+    __syncthreads();
+    if (tid == 0) {
+      // v = x - alpha e1 stored in column k (rows k..m-1)
+      A[k * ld + k] -= alpha;
+      double vv = 0.0;
+      for (int i = k; i < m; ++i) vv += A[i * ld + k] * A[i * ld + k];
+      beta = vv > 0.0 ? 2.0 / vv : 0.0;
+    }
+    __syncthreads();
+    // apply H = I - beta v v^T to columns k+1..nc-1 and the rhs
+    for (int c = k + 1 + tid; c <= nc; c += blockDim.x) {
+      double s = 0.0;
+      if (c < nc) {
+        for (int i = k; i < m; ++i) s += A[i * ld + k] * A[i * ld + c];
+        s *= beta;
+        for (int i = k; i < m; ++i) A[i * ld + c] -= s * A[i * ld + k];
+      } else {
+        for (int i = k; i < m; ++i) s += A[i * ld + k] * rhs[i];
+        s *= beta;
+        for (int i = k; i < m; ++i) rhs[i] -= s * A[i * ld + k];
+      }
+    }
+    __syncthreads();
+    if (tid == 0) A[k * ld + k] = alpha;  // R diagonal
+    __syncthreads();
+  }
+  if (tid == 0) {
+    for (int i = nc - 1; i >= 0; --i) {
+      double s = rhs[i];
+      for (int c = i + 1; c < nc; ++c) s -= A[i * ld + c] * x[c];
+      x[i] = A[i * ld + i] != 0.0 ? s / A[i * ld + i] : 0.0;
+    }
+  }
+  __syncthreads();
+}
+
+// select pick t (reduce tile candidates), record it, and fit the coefficients
+// of pick t+1 on the t+1 rows chosen so far.
+template <typename T>
+__global__ __launch_bounds__(256) void k_deim_select(const int* __restrict__ tfirst,
+                                                     const double* __restrict__ tval,
+                                                     const int64_t* __restrict__ tidx,
+                                                     const int64_t* __restrict__ dof_off,
+                                                     const T* __restrict__ Phi, int r, int ns, int t,
+                                                     int32_t* __restrict__ P,
+                                                     uint32_t* __restrict__ chosen,
+                                                     const uint32_t* __restrict__ epoch_p,
+                                                     double* __restrict__ coef, int ldc,
+                                                     uint32_t* flags) {
+  __shared__ double A[kMaxNs * (kMaxR + 1)];
+  __shared__ double rhs[kMaxNs];
+  __shared__ double x[kMaxR];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  if (tid == 0) {
+    double best = -1.0;
+    int64_t bi = -1;
+    for (int tt = tfirst[b]; tt < tfirst[b + 1]; ++tt) {
+      const double v = tval[tt];
+      const int64_t i = tidx[tt];
+      if (i >= 0 && (v > best || (v == best && i < bi))) { best = v; bi = i; }
+    }
+    if (bi < 0) { bi = 0; atomicOr(&flags[b], ROM_FLAG_SINGULAR); }
+    P[(size_t)b * ns + t] = (int32_t)bi;
+    chosen[dof_off[b] + bi] = *epoch_p;
+  }
+  __syncthreads();
+  const int tn = t + 1;           // next pick
+  if (tn >= ns) return;
+  const int jn = tn < r ? tn : tn - r;   // column of the next pick
+  const int m = tn;                     // rows available
+  if (jn == 0) return;                  // no fit for the first column of a round
+  const T* Pb = Phi + dof_off[b] * r;
+  for (int e = tid; e < m * jn; e += blockDim.x) {
+    const int i = e / jn, c = e % jn;
+    A[i * (kMaxR + 1) + c] = (double)Pb[(int64_t)P[(size_t)b * ns + i] * r + c];
+  }
+  for (int i = tid; i < m; i += blockDim.x) rhs[i] = (double)Pb[(int64_t)P[(size_t)b * ns + i] * r + jn];
+  __syncthreads();
+  qr_lstsq(A, m, jn, rhs, x);
+  for (int c = tid; c < jn; c += blockDim.x) coef[(size_t)b * ldc + c] = x[c];
+}
+
+// (P^T Phi)^+ by Householder QR (A = Q R, A^+ = R^-1 Q^T) and the sample-mesh gathers.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rebuild(int r, int ns, int nv, int periodic,
+                                                 const int64_t* __restrict__ dof_off,
+                                                 const int64_t* __restrict__ cell_off,
+                                                 const T* __restrict__ Phi, const T* __restrict__ qref,
+                                                 const int32_t* __restrict__ P, double* __restrict__ Mout,
+                                                 double* __restrict__ mphi, double* __restrict__ mqref,
+                                                 uint32_t* flags) {
+  extern __shared__ double sm[];
+  constexpr int ld = kMaxR + 1;
+  double* A = sm;                    // ns x ld : R above the diagonal, reflectors below
+  double* Q = A + kMaxNs * ld;       // ns x r  : first r columns of Q
+  double* vd = Q + kMaxNs * kMaxR;   // reflector heads
+  double* bt = vd + kMaxR;           // reflector scales
+  __shared__ double nrm;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int64_t base = dof_off[b];
+  const int64_t n = cell_off[b + 1] - cell_off[b];
+  const T* Pb = Phi + base * r;
+  // gathers: mesh cells c-1, c, c+1 of every sampled row (wrap or wall copy)
+  for (int e = tid; e < ns * 3 * nv; e += blockDim.x) {
+    const int s = e / (3 * nv), rem = e % (3 * nv), o = rem / nv, w = rem % nv;
+    const int64_t c = P[(size_t)b * ns + s] / nv;
+    int64_t cc = c - 1 + o;
+    if (periodic) cc = (cc % n + n) % n;
+    else cc = cc < 0 ? 0 : (cc >= n ? n - 1 : cc);
+    const int64_t row = cc * nv + w;
+    mqref[((size_t)b * ns + s) * 3 * nv + rem] = (double)qref[base + row];
+    for (int k = 0; k < r; ++k)
+      mphi[(((size_t)b * ns + s) * 3 * nv + rem) * r + k] = (double)Pb[row * r + k];
+  }
+  for (int e = tid; e < ns * r; e += blockDim.x) {
+    const int i = e / r, c = e % r;
+    A[i * ld + c] = (double)Pb[(int64_t)P[(size_t)b * ns + i] * r + c];
+  }
+  __syncthreads();
+  // Householder QR: column k reflector v = x - alpha e_k, H = I - beta v v^T
+  for (int k = 0; k < r; ++k) {
+    if (tid == 0) {
+      double s2 = 0.0;
+      for (int i = k; i < ns; ++i) s2 += A[i * ld + k] * A[i * ld + k];
+      nrm = sqrt(s2);
+    }
+    __syncthreads();
+    const double alpha = A[k * ld + k] >= 0.0 ? -nrm : nrm;
+    __syncthreads();
+    if (tid == 0) {
+      A[k * ld + k] -= alpha;
+      double vv = 0.0;
+      for (int i = k; i < ns; ++i) vv += A[i * ld + k] * A[i * ld + k];
+      bt[k] = vv > 0.0 ? 2.0 / vv : 0.0;
+      vd[k] = A[k * ld + k];
+    }
+    __syncthreads();
+    for (int c = k + 1 + tid; c < r; c += blockDim.x) {
+      double s2 = 0.0;
+      for (int i = k; i < ns; ++i) s2 += A[i * ld + k] * A[i * ld + c];
+      s2 *= bt[k];
+      for (int i = k; i < ns; ++i) A[i * ld + c] -= s2 * A[i * ld + k];
+    }
+    __syncthreads();
+    if (tid == 0) A[k * ld + k] = alpha;
+    __syncthreads();
+  }
+  // Q[:, :r] = H_0 H_1 ... H_{r-1} [I; 0]
+  for (int e = tid; e < ns * r; e += blockDim.x) Q[e] = (e / r) == (e % r) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int k = r - 1; k >= 0; --k) {
+    for (int c = tid; c < r; c += blockDim.x) {
+      double s2 = vd[k] * Q[k * r + c];
+      for (int i = k + 1; i < ns; ++i) s2 += A[i * ld + k] * Q[i * r + c];
+      s2 *= bt[k];
+      Q[k * r + c] -= s2 * vd[k];
+      for (int i = k + 1; i < ns; ++i) Q[i * r + c] -= s2 * A[i * ld + k];
+    }
+    __syncthreads();
+  }
+  // M[:, s] = R^-1 Q[s, :]^T, one column per thread
+  for (int s = tid; s < ns; s += blockDim.x) {
+    double* Mb = Mout + (size_t)b * r * ns;
+    for (int i = r - 1; i >= 0; --i) {
+      double acc = Q[s * r + i];
+      for (int c = i + 1; c < r; ++c) acc -= A[i * ld + c] * Mb[c * ns + s];
+      Mb[i * ns + s] = A[i * ld + i] != 0.0 ? acc / A[i * ld + i] : 0.0;
+    }
+  }
+  if (tid == 0) {
+    double mx = 0.0, mn = 1e300;
+    for (int c = 0; c < r; ++c) {
+      const double d = fabs(A[c * ld + c]);
+      mx = fmax(mx, d); mn = fmin(mn, d);
+    }
+    if (!(mn > 1e-13 * mx)) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
+  }
+}
+
+size_t rebuild_shm() {
+  return sizeof(double) * (kMaxNs * (kMaxR + 1) + kMaxNs * kMaxR + 2 * kMaxR);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_reconstruct(const Tile* __restrict__ tiles,
+                                                     const int64_t* __restrict__ dof_off,
+                                                     const T* __restrict__ Phi, int r,
+                                                     const T* __restrict__ qref,
+                                                     const double* __restrict__ dvar, int nv,
+                                                     const double* __restrict__ a, T* __restrict__ out) {
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  const int64_t base = dof_off[b];
+  for (int64_t rr = threadIdx.x; rr < t.ncell; rr += blockDim.x) {
+    const int64_t lr = t.cell0 + rr, g = base + lr;
+    double s = 0.0;
+    for (int c = 0; c < r; ++c) s += (double)Phi[g * r + c] * a[(size_t)b * r + c];
+    out[g] = (T)((double)qref[g] + s / dvar[(size_t)b * nv + lr % nv]);
+  }
+}
+
+__global__ void k_bump(uint32_t* e) { if (threadIdx.x == 0 && blockIdx.x == 0) *e = *e + 1u; }
+
+__global__ void k_copy_f64(const double* src, double* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+__global__ void k_fill_i32(int32_t* dst, int32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = v;
+}
+
+template <typename T>
+rom_status galerkin_step_t(rom_batch* h, hipStream_t s) {
+  const int r = h->cfg.r, B = h->cfg.n_inst;
+  const int64_t nr = (int64_t)B * r;
+  hipLaunchKernelGGL(k_copy_f64, dim3((nr + 255) / 256), dim3(256), 0, s, h->a, h->a_prev, nr);
+  hipLaunchKernelGGL(k_fill_i32, dim3((B + 255) / 256), dim3(256), 0, s, h->active, 1, (int64_t)B);
+  hipLaunchKernelGGL(k_fill_i32, dim3((B + 255) / 256), dim3(256), 0, s, h->iters, 0, (int64_t)B);
+  double* gpart = h->part;
+  for (int it = 0; it < h->cfg.rom_max; ++it) {
+    hipLaunchKernelGGL((k_galerkin_pass<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                       h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const T*)h->Phi, r,
+                       (const T*)h->q_ref, h->d_var, h->a, h->active, gpart, (T*)h->mpart);
+    hipLaunchKernelGGL((k_galerkin_solve<T>), dim3(B), dim3(256), 0, s, h->d_ptile_first, gpart,
+                       (const T*)h->mpart, r, h->cfg.dt, h->d_var, h->a, h->a_prev, h->active,
+                       h->iters, h->cfg.rom_tol, h->flags);
+  }
+  hipLaunchKernelGGL(k_rom_finalize, dim3((B + 255) / 256), dim3(256), 0, s, B, h->active, h->flags);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+size_t hr_shm() {
+  return sizeof(double) * (2 * kMaxR + kMaxNs + kMaxNs * kMaxR + kMaxR * kMaxR + kMaxR);
+}
+
+rom_status hr_step(rom_batch* h, hipStream_t s) {
+  const int B = h->cfg.n_inst;
+  auto go = [&](auto tag) -> rom_status {
+    using M = typename decltype(tag)::type;
+    hipLaunchKernelGGL((k_hr_step<M>), dim3(B), dim3(256), hr_shm(), s, h->cfg.r, h->cfg.n_s,
+                       h->d_cell_off, h->d_phys, h->cfg.n_phys, h->P, h->M, h->mesh_phi,
+                       h->mesh_qref, h->d_var, h->a, h->cfg.dt, h->cfg.rom_tol, h->cfg.rom_max,
+                       h->iters, h->flags);
+    return ROM_OK;
+  };
+  rom_status st;
+  switch (h->cfg.problem) {
+    case ROM_BURGERS: st = go(Tag<BurgersModel<double>>{}); break;
+    case ROM_EULER_RUSANOV: st = go(Tag<EulerModel<double, false>>{}); break;
+    case ROM_EULER_HLLC: st = go(Tag<EulerModel<double, true>>{}); break;
+    default: st = go(Tag<ReactModel<double>>{}); break;
+  }
+  ROM_HIP_CHECK(hipGetLastError());
+  return st;
+}
+
+template <typename T>
+rom_status rebuild_t(rom_batch* h, hipStream_t s) {
+  const int r = h->cfg.r, ns = h->cfg.n_s, B = h->cfg.n_inst;
+  if (h->cfg.hyper != ROM_HR_DEIM) return ROM_OK;
+  hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, s, h->d_epoch);
+  double* tval = h->part;
+  int64_t* tidx = (int64_t*)(h->part + h->n_ptiles);
+  double* coef = h->rstate;  // per instance kMaxR coefficients
+  for (int t = 0; t < ns; ++t) {
+    const int j = t < r ? t : t - r;
+    hipLaunchKernelGGL((k_deim_argmax<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                       h->d_dof_off, (const T*)h->Phi, r, j, coef, kMaxR, h->chosen, h->d_epoch, tval,
+                       tidx);
+    hipLaunchKernelGGL((k_deim_select<T>), dim3(B), dim3(256), 0, s, h->d_ptile_first, tval, tidx,
+                       h->d_dof_off, (const T*)h->Phi, r, ns, t, h->P, h->chosen, h->d_epoch, coef,
+                       kMaxR, h->flags);
+  }
+  hipLaunchKernelGGL((k_rebuild<T>), dim3(B), dim3(256), rebuild_shm(), s, r, ns, h->nv,
+                     (h->cfg.problem == ROM_BURGERS || h->cfg.problem == ROM_REACT) ? 1 : 0,
+                     h->d_dof_off, h->d_cell_off, (const T*)h->Phi, (const T*)h->q_ref, h->P, h->M,
+                     h->mesh_phi, h->mesh_qref, h->flags);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+template <typename T>
+rom_status reconstruct_t(rom_batch* h, void* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_reconstruct<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                     h->d_dof_off, (const T*)h->Phi, h->cfg.r, (const T*)h->q_ref, h->d_var, h->nv,
+                     h->a, (T*)out);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+}  // namespace
+
+rom_status rom_kernels_prepare() {
+  const int big = 160 * 1024 - 1024;
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_rebuild<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_rebuild<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_step<BurgersModel<double>>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_step<EulerModel<double, false>>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_step<EulerModel<double, true>>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_step<ReactModel<double>>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  return ROM_OK;
+}
+
+rom_status launch_rom_fine_step(rom_batch* h, hipStream_t s) {
+  if (h->cfg.hyper == ROM_HR_DEIM) return hr_step(h, s);
+  if (h->cfg.problem != ROM_BURGERS) {
+    set_error("the full (non-hyper-reduced) Galerkin step is implemented for Burgers only");
+    return ROM_E_UNSUPPORTED;
+  }
+  return h->cfg.precision == ROM_F64 ? galerkin_step_t<double>(h, s) : galerkin_step_t<float>(h, s);
+}
+
+rom_status launch_galerkin_pass(rom_batch* h, hipStream_t s) {
+  const int B = h->cfg.n_inst, r = h->cfg.r;
+  if (h->cfg.problem != ROM_BURGERS) return ROM_E_UNSUPPORTED;
+  hipLaunchKernelGGL(k_fill_i32, dim3((B + 255) / 256), dim3(256), 0, s, h->active, 1, (int64_t)B);
+  if (h->cfg.precision == ROM_F64)
+    hipLaunchKernelGGL((k_galerkin_pass<double>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                       h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const double*)h->Phi,
+                       r, (const double*)h->q_ref, h->d_var, h->a, h->active, h->part,
+                       (double*)h->mpart);
+  else
+    hipLaunchKernelGGL((k_galerkin_pass<float>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                       h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const float*)h->Phi,
+                       r, (const float*)h->q_ref, h->d_var, h->a, h->active, h->part,
+                       (float*)h->mpart);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+rom_status launch_rebuild(rom_batch* h, hipStream_t s) {
+  return h->cfg.precision == ROM_F64 ? rebuild_t<double>(h, s) : rebuild_t<float>(h, s);
+}
+
+rom_status launch_reconstruct(rom_batch* h, void* out, hipStream_t s) {
+  return h->cfg.precision == ROM_F64 ? reconstruct_t<double>(h, out, s)
+                                     : reconstruct_t<float>(h, out, s);
+}
+
+}  // namespace romhip

@@ -1,0 +1,253 @@
+"""Python binding of the romhip C interface (ctypes; argument marshalling only).
+
+Every call forwards device pointers of torch tensors and the current HIP stream
+to ``libromhip.so``; all arithmetic runs in the library's HIP kernels.  The
+library must have been built (``paper_2605_28684_amd.build``); importing this
+module on a machine without it raises immediately.
+
+The functions mirror the C entry points of ``include/romhip.h``:
+``rom_create``, ``rom_destroy``, ``fom_residual``, ``fom_step``,
+``isvd_update``, ``rom_rebuild``, ``rom_step``, ``rom_get``, ``rom_set``,
+``rom_get_status``, ``fom_residual_vjp``, ``fom_step_vjp``; ``RomBatch`` bundles
+a handle with its layout.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+from . import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libromhip.so")
+
+ROM_OK = 0
+STATUS = {0: "ROM_OK", -1: "ROM_E_INVAL", -2: "ROM_E_NOMEM", -3: "ROM_E_DEVICE",
+          -6: "ROM_E_STATE", -7: "ROM_E_UNSUPPORTED"}
+FLAG_NEWTON_NOCONV, FLAG_FLOOR, FLAG_NONFINITE, FLAG_RHO_ZERO = 1, 2, 4, 8
+FLAG_SINGULAR, FLAG_ROM_NOCONV, FLAG_REORTH = 16, 32, 64
+GET_BASIS, GET_SIGMA, GET_A, GET_QTILDE, GET_SAMPLES, GET_YCORR = 0, 1, 2, 3, 4, 5
+GET_QREF, GET_DVAR, GET_PINV, GET_COUNTERS = 6, 7, 8, 9
+
+
+class RomError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class rom_config(ctypes.Structure):
+    _fields_ = [("problem", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("projection", ctypes.c_int32), ("hyper", ctypes.c_int32),
+                ("n_inst", ctypes.c_int32),
+                ("n_cells", ctypes.POINTER(ctypes.c_int64)),
+                ("phys", ctypes.POINTER(ctypes.c_double)),
+                ("n_phys", ctypes.c_int32),
+                ("r", ctypes.c_int32), ("n_s", ctypes.c_int32), ("w_init", ctypes.c_int32),
+                ("z", ctypes.c_int32),
+                ("newton_max", ctypes.c_int32), ("rom_max", ctypes.c_int32),
+                ("reorth_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("lambda_", ctypes.c_double), ("dt", ctypes.c_double),
+                ("newton_tol", ctypes.c_double), ("rom_tol", ctypes.c_double),
+                ("tau_orth", ctypes.c_double), ("tau_rho", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libromhip.so is not built (run paper_2605_28684_amd.build): " + LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "rom_create": [ctypes.POINTER(rom_config), vp, vp, ctypes.POINTER(vp)],
+        "rom_destroy": [vp],
+        "fom_residual": [vp, vp, vp, d, vp, vp],
+        "fom_step": [vp, vp, d, vp, vp, vp],
+        "isvd_update": [vp, vp, vp],
+        "rom_rebuild": [vp, vp],
+        "rom_step": [vp, i32, vp],
+        "rom_get": [vp, i32, vp, vp],
+        "rom_set": [vp, i32, vp, vp],
+        "rom_get_status": [vp, vp],
+        "rom_clear_status": [vp, vp],
+        "fom_residual_vjp": [vp, vp, vp, d, vp, vp, vp, vp],
+        "fom_step_vjp": [vp, vp, d, vp, vp, vp],
+        "rom_query": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                      ctypes.POINTER(i32)],
+        "rom_profile": [vp, i32, i32, vp, ctypes.POINTER(d), vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.rom_last_error.argtypes = []
+    lib.rom_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+LIB = _load()
+SYMBOLS = ("rom_create", "rom_destroy", "fom_residual", "fom_step", "isvd_update", "rom_rebuild",
+           "rom_step", "rom_get", "rom_set", "rom_get_status", "rom_clear_status",
+           "fom_residual_vjp", "fom_step_vjp", "rom_query", "rom_profile", "rom_last_error")
+PROF_RESIDUAL, PROF_GALERKIN_PASS, PROF_ISVD_PROJECT, PROF_RESIDUAL_VJP, PROF_FOM_STEP = range(5)
+
+
+def _check(code):
+    if code != ROM_OK:
+        raise RomError(code, LIB.rom_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor required")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor required")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_config(w: W.Workload, use_graph=True, precision=None, **over):
+    """rom_config from a workload (host arrays kept alive on the returned object)."""
+    cfg = rom_config()
+    prec = w.precision if precision is None else precision
+    cfg.problem, cfg.precision = w.problem, prec
+    cfg.projection, cfg.hyper = w.projection, w.hyper
+    cfg.n_inst = w.n_inst
+    nc = np.ascontiguousarray(np.asarray(w.n_cells, dtype=np.int64))
+    ph = np.ascontiguousarray(w.phys_vector())
+    cfg.n_cells = nc.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    cfg.phys = ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    cfg.n_phys = ph.shape[1]
+    cfg.r, cfg.n_s, cfg.w_init, cfg.z = w.r, w.n_s, w.w_init, w.z
+    cfg.newton_max, cfg.rom_max, cfg.reorth_every = w.newton_max, w.rom_max, w.reorth_every
+    cfg.use_graph = 1 if use_graph else 0
+    cfg.lambda_, cfg.dt = w.lam, w.dt
+    cfg.newton_tol, cfg.rom_tol = w.newton_tol, w.rom_tol
+    cfg.tau_orth, cfg.tau_rho = w.tau_orth, w.tau_rho
+    for k, v in over.items():
+        setattr(cfg, "lambda_" if k == "lam" else k, v)
+    cfg._keep = (nc, ph)
+    return cfg
+
+
+def torch_dtype(precision):
+    return torch.float64 if precision == W.F64 else torch.float32
+
+
+class RomBatch:
+    """A batch handle plus its layout.  q0: device tensor of the initial states
+    (or None to create a handle for full-order calls / rom_set only)."""
+
+    def __init__(self, w: W.Workload, q0=None, use_graph=True, precision=None, **over):
+        self.w = w
+        self.cfg = make_config(w, use_graph=use_graph, precision=precision, **over)
+        self.precision = self.cfg.precision
+        self.dtype = torch_dtype(self.precision)
+        self.h = ctypes.c_void_p()
+        _check(LIB.rom_create(ctypes.byref(self.cfg), _ptr(q0), _stream(), ctypes.byref(self.h)))
+        td, nv, r, ns = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(LIB.rom_query(self.h, ctypes.byref(td), ctypes.byref(nv), ctypes.byref(r),
+                             ctypes.byref(ns)))
+        self.total_dof, self.n_var, self.r, self.n_s = td.value, nv.value, r.value, ns.value
+        self.n_inst = w.n_inst
+
+    def close(self):
+        if self.h:
+            LIB.rom_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _new(self, n, dtype=None):
+        return torch.empty(n, dtype=self.dtype if dtype is None else dtype, device="cuda")
+
+    # ---- full-order model
+    def fom_residual(self, q, q_prev=None, dt=0.0, out=None):
+        out = self._new(self.total_dof) if out is None else out
+        _check(LIB.fom_residual(self.h, _ptr(q), _ptr(q_prev), float(dt), _ptr(out), _stream()))
+        return out
+
+    def fom_step(self, q_prev, dt, out=None, iters=None):
+        out = self._new(self.total_dof) if out is None else out
+        _check(LIB.fom_step(self.h, _ptr(q_prev), float(dt), _ptr(out), _ptr(iters), _stream()))
+        return out
+
+    def fom_residual_vjp(self, q, gbar, q_prev=None, dt=0.0, gq=None, gq_prev=None):
+        gq = self._new(self.total_dof) if gq is None else gq
+        if q_prev is not None and gq_prev is None:
+            gq_prev = self._new(self.total_dof)
+        _check(LIB.fom_residual_vjp(self.h, _ptr(q), _ptr(q_prev), float(dt), _ptr(gbar), _ptr(gq),
+                                    _ptr(gq_prev), _stream()))
+        return gq, gq_prev
+
+    def fom_step_vjp(self, q, dt, gbar, out=None):
+        out = self._new(self.total_dof) if out is None else out
+        _check(LIB.fom_step_vjp(self.h, _ptr(q), float(dt), _ptr(gbar), _ptr(out), _stream()))
+        return out
+
+    # ---- reduced model
+    def isvd_update(self, y):
+        _check(LIB.isvd_update(self.h, _ptr(y), _stream()))
+
+    def rom_rebuild(self):
+        _check(LIB.rom_rebuild(self.h, _stream()))
+
+    def rom_step(self, n_fine):
+        _check(LIB.rom_step(self.h, int(n_fine), _stream()))
+
+    _SIZES = {GET_BASIS: ("T", "dof*r"), GET_SIGMA: ("f64", "B*r"), GET_A: ("f64", "B*r"),
+              GET_QTILDE: ("T", "dof"), GET_SAMPLES: ("i32", "B*ns"), GET_YCORR: ("T", "dof"),
+              GET_QREF: ("T", "dof"), GET_DVAR: ("f64", "B*nv"), GET_PINV: ("f64", "B*r*ns")}
+
+    def _shape(self, what):
+        kind, n = self._SIZES[what]
+        size = {"dof*r": self.total_dof * self.r, "B*r": self.n_inst * self.r,
+                "dof": self.total_dof, "B*ns": self.n_inst * max(self.n_s, 1),
+                "B*nv": self.n_inst * self.n_var, "B*r*ns": self.n_inst * self.r * max(self.n_s, 1)}[n]
+        dt = {"T": self.dtype, "f64": torch.float64, "i32": torch.int32}[kind]
+        return size, dt
+
+    def get(self, what):
+        if what == GET_COUNTERS:
+            buf = (ctypes.c_int64 * 4)()
+            _check(LIB.rom_get(self.h, what, ctypes.cast(buf, ctypes.c_void_p), _stream()))
+            return list(buf)
+        n, dt = self._shape(what)
+        out = self._new(n, dt)
+        _check(LIB.rom_get(self.h, what, _ptr(out), _stream()))
+        return out
+
+    def set(self, what, src):
+        if what == GET_COUNTERS:
+            buf = (ctypes.c_int64 * 4)(*[int(x) for x in src])
+            _check(LIB.rom_set(self.h, what, ctypes.cast(buf, ctypes.c_void_p), _stream()))
+            return
+        n, dt = self._shape(what)
+        src = src.to(device="cuda", dtype=dt).contiguous()
+        if src.numel() != n:
+            raise ValueError("expected %d elements, got %d" % (n, src.numel()))
+        _check(LIB.rom_set(self.h, what, _ptr(src), _stream()))
+        torch.cuda.current_stream().synchronize()
+
+    def profile(self, stage, reps, q=None):
+        """Mean milliseconds per launch of one hot-path stage (HIP events on the current stream)."""
+        ms = ctypes.c_double()
+        _check(LIB.rom_profile(self.h, int(stage), int(reps), _ptr(q), ctypes.byref(ms), _stream()))
+        return ms.value
+
+    def status(self):
+        buf = np.zeros(self.n_inst, dtype=np.uint32)
+        _check(LIB.rom_get_status(self.h, ctypes.c_void_p(buf.ctypes.data)))
+        return buf
+
+    def clear_status(self):
+        _check(LIB.rom_clear_status(self.h, _stream()))

@@ -1,0 +1,169 @@
+"""GPU parity of the full-order calls against the oracle: residual f(q), the
+backward-Euler residual, one Newton backward-Euler step, and the two VJPs.
+Ragged batches span several 256-cell tiles plus a ragged tail."""
+import numpy as np
+import pytest
+
+from oracle import fom as F
+from paper_2605_28684_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+PROBLEMS = [W.BURGERS, W.EULER_RUSANOV, W.EULER_HLLC, W.REACT]
+CELLS = [300, 517, 1024, 3]
+
+
+def _workload(problem, cells, precision):
+    if problem == W.BURGERS:
+        w = W.burgers_batch_f32(n_inst=len(cells), precision=precision)
+        w.n_cells = list(cells)
+        w.phys = [dict(nu=0.004 + 0.002 * b) for b in range(len(cells))]
+    elif problem in (W.EULER_RUSANOV, W.EULER_HLLC):
+        w = W.sod_hllc_f32(n=cells[0], precision=precision, flux=problem)
+        w.n_cells = list(cells)
+        w.phys = [dict(gamma=1.4)] * len(cells)
+    else:
+        w = W.react10_f32(n_inst=len(cells), n=cells[0], precision=precision)
+        w.n_cells = list(cells)
+        w.phys = w.phys[:1] * len(cells)
+    w.hyper, w.projection = W.HR_DEIM, W.LSPG
+    w.r, w.n_s, w.w_init = 2, 2, 2
+    return w
+
+
+def _handle(w):
+    from paper_2605_28684_amd.romhip import RomBatch
+    return RomBatch(w, q0=None, use_graph=False)
+
+
+@pytest.mark.parametrize("precision", [W.F64, W.F32])
+@pytest.mark.parametrize("problem", PROBLEMS)
+def test_residual_parity(problem, precision):
+    import gpu_common as G
+    w = _workload(problem, CELLS, precision)
+    h = _handle(w)
+    q = G.rounded(W.random_state(problem, w.n_cells, seed=1), precision)
+    qp = G.rounded(W.random_state(problem, w.n_cells, seed=2), precision)
+    dt = 1e-4
+    f = G.host(h.fom_residual(G.to_dev(q, precision)))
+    r = G.host(h.fom_residual(G.to_dev(q, precision), G.to_dev(qp, precision), dt))
+    off = w.offsets()
+    tol = G.TOL[precision]
+    for b in range(w.n_inst):
+        qb, qpb = q[off[b]:off[b + 1]], qp[off[b]:off[b + 1]]
+        fref = F.fom_f(problem, qb, w.phys[b])
+        rref = qb - qpb - dt * fref
+        assert G.relerr(f[off[b]:off[b + 1]], fref) < tol * (10 if problem == W.REACT else 1), b
+        assert G.relerr(r[off[b]:off[b + 1]], rref) < tol, b
+    assert not (h.status() & 4).any()      # nothing non-finite
+
+
+@pytest.mark.parametrize("precision", [W.F64, W.F32])
+@pytest.mark.parametrize("problem", [W.BURGERS, W.EULER_RUSANOV, W.EULER_HLLC])
+def test_fom_step_parity(problem, precision):
+    import gpu_common as G
+    import torch
+    cells = [300, 517, 64]
+    w = _workload(problem, cells, precision)
+    w.newton_tol = 1e-10 if precision == W.F64 else 1e-5
+    h = _handle(w)
+    q = G.rounded(W.random_state(problem, cells, seed=3, scale=0.5), precision)
+    dt = 2e-4 if problem == W.BURGERS else 0.064 / 512
+    it = torch.zeros(w.n_inst, dtype=torch.int32, device="cuda")
+    q1 = G.host(h.fom_step(G.to_dev(q, precision), dt, iters=it))
+    its = it.cpu().numpy()
+    off = w.offsets()
+    for b in range(w.n_inst):
+        ref, n_ref, ok = F.newton_be_step(problem, q[off[b]:off[b + 1]], dt, w.phys[b],
+                                          tol=w.newton_tol, max_it=10)
+        assert ok
+        # the stopping test may straddle the tolerance by one iteration in FP32
+        assert abs(int(its[b]) - n_ref) <= (0 if precision == W.F64 else 1), (b, its[b], n_ref)
+        err = G.relerr(q1[off[b]:off[b + 1]], ref)
+        assert err < (1e-11 if precision == W.F64 else 1e-5), (b, err)
+    assert not (h.status() & 1).any()
+
+
+def test_fom_step_inplace_and_nonconvergence_flag():
+    import gpu_common as G
+    w = _workload(W.BURGERS, [256], W.F64)
+    w.newton_max = 1
+    w.newton_tol = 1e-14
+    h = _handle(w)
+    q = G.to_dev(W.random_state(W.BURGERS, [256], seed=4), W.F64)
+    h.fom_step(q, 1e-3, out=q)       # q_prev and q_out alias
+    assert (h.status() & 1).all()     # one Newton solve cannot reach 1e-14
+
+
+@pytest.mark.parametrize("precision", [W.F64, W.F32])
+@pytest.mark.parametrize("problem", PROBLEMS)
+def test_residual_vjp_parity(problem, precision):
+    import gpu_common as G
+    cells = [300, 517, 40]
+    w = _workload(problem, cells, precision)
+    h = _handle(w)
+    q = G.rounded(W.random_state(problem, cells, seed=5), precision)
+    g = G.rounded(np.random.default_rng(6).normal(size=q.shape), precision)
+    gq, _ = h.fom_residual_vjp(G.to_dev(q, precision), G.to_dev(g, precision))
+    gq = G.host(gq)
+    dt = 1e-4
+    gq2, gqp = h.fom_residual_vjp(G.to_dev(q, precision), G.to_dev(g, precision),
+                                  q_prev=G.to_dev(q, precision), dt=dt)
+    gq2, gqp = G.host(gq2), G.host(gqp)
+    off = w.offsets()
+    tol = G.TOL[precision] * (10 if precision == W.F32 else 1)
+    for b in range(w.n_inst):
+        sl = slice(off[b], off[b + 1])
+        ref = F.vjp_f(problem, q[sl], g[sl], w.phys[b])
+        assert G.relerr(gq[sl], ref) < tol, b
+        assert G.relerr(gq2[sl], g[sl] - dt * ref) < tol, b
+        assert np.array_equal(gqp[sl], -g[sl])
+
+
+@pytest.mark.parametrize("precision", [W.F64, W.F32])
+@pytest.mark.parametrize("problem", [W.BURGERS, W.EULER_RUSANOV, W.EULER_HLLC])
+def test_fom_step_vjp_parity(problem, precision):
+    import gpu_common as G
+    import scipy.sparse.linalg as spla
+    cells = [300, 517, 33]
+    w = _workload(problem, cells, precision)
+    h = _handle(w)
+    q = G.rounded(W.random_state(problem, cells, seed=7), precision)
+    g = G.rounded(np.random.default_rng(8).normal(size=q.shape), precision)
+    dt = 2e-4 if problem == W.BURGERS else 0.064 / 512
+    out = G.host(h.fom_step_vjp(G.to_dev(q, precision), dt, G.to_dev(g, precision)))
+    off = w.offsets()
+    for b in range(w.n_inst):
+        sl = slice(off[b], off[b + 1])
+        J = F.jacobian_be(problem, q[sl], dt, w.phys[b])
+        ref = spla.spsolve(J.T.tocsc(), g[sl])
+        assert G.relerr(out[sl], ref) < (1e-11 if precision == W.F64 else 1e-5), b
+
+
+def test_fom_coarse_step_batched_burgers_instances_fp32():
+    """Coarse steps (z dt) on real instances of the 256-instance Burgers batch."""
+    import gpu_common as G
+    import torch
+    from paper_2605_28684_amd.romhip import RomBatch
+    full = W.burgers_batch_f32()
+    idx = [0, 1, 2, 5, 17, 100]
+    w = W.burgers_batch_f32()
+    w.n_cells = [full.n_cells[b] for b in idx]
+    w.phys = [full.phys[b] for b in idx]
+    w.q0 = np.concatenate([full.instance(b) for b in idx])
+    h = RomBatch(w, q0=None, use_graph=False)
+    q = G.rounded(w.q0, W.F32)
+    it = torch.zeros(len(idx), dtype=torch.int32, device="cuda")
+    qd = G.to_dev(q, W.F32)
+    off = w.offsets()
+    for k in range(3):
+        qd = h.fom_step(qd, w.z * w.dt, iters=it)
+        qg = G.host(qd)
+        for b in range(len(idx)):
+            sl = slice(off[b], off[b + 1])
+            ref, n_ref, ok = F.newton_be_step(W.BURGERS, q[sl], w.z * w.dt, w.phys[b],
+                                              tol=w.newton_tol, max_it=10)
+            assert G.relerr(qg[sl], ref) < 1e-5, (k, b)
+        q = G.rounded(qg, W.F32)
+    print("iterations", it.cpu().numpy(), "flags", h.status())
+    assert not (h.status() & 1).any()

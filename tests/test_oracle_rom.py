@@ -289,3 +289,15 @@ def test_alg1_adaptive_beats_static_burgers():
     e_st = np.linalg.norm(O.reconstruct(st0["q_ref"], st0["d"], st0["Phi"], a) - qf) / np.linalg.norm(qf)
     assert len(rec["events"]) == (prm["N_t"] - prm["w_init"]) // prm["z"]
     assert e_ad < e_st
+
+
+def test_isvd_degenerate_never_keeps_residual_direction():
+    # sigma with exact zeros and a snapshot inside span(Phi): every kept column
+    # must be a unit vector of span(Phi)
+    Phi = _orth(40, 4, 77)
+    sig = np.array([3.0, 1.0, 0.0, 0.0])
+    y = Phi @ np.array([1.0, -2.0, 0.0, 0.0])
+    P2, s2, info = O.isvd_update(Phi, sig, y, 0.5, 4)
+    assert info["degenerate"]
+    np.testing.assert_allclose(P2.T @ P2, np.eye(4), atol=1e-13)
+    np.testing.assert_allclose(Phi @ (Phi.T @ P2), P2, atol=1e-13)
