@@ -20,6 +20,9 @@ ARCH = "gfx950"
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          # no packed FP32 instructions anywhere in device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # FP32 division and square root by the hardware rcp/sqrt (about 1 ulp);
+         # FP64 arithmetic is unaffected
+         "-fno-hip-fp32-correctly-rounded-divide-sqrt",
          "-I" + os.path.join(os.path.dirname(HERE), "include")]
 
 

@@ -147,7 +147,7 @@ rom_status alloc(T** p, size_t count) {
   } while (0)
 
 void free_all(rom_batch* h) {
-  void* ps[] = {h->d_dof_off, h->d_cell_off, h->d_phys, h->d_tiles, h->d_ptiles, h->d_ptile_first,
+  void* ps[] = {h->d_dof_off, h->d_cell_off, h->d_phys, h->d_tiles, h->d_btiles, h->d_ptiles, h->d_ptile_first,
                 h->Phi, h->sigma, h->a, h->a_prev, h->q_ref, h->d_var, h->y_corr, h->flags, h->P,
                 h->M, h->mesh_phi, h->mesh_qref, h->chosen, h->part, h->red, h->ubar, h->lmat,
                 h->active, h->iters, h->norms, h->rstate, h->qtmp, h->mpart, h->fq, h->fq_prev, h->vjp_tmp,
@@ -172,18 +172,22 @@ rom_status setup(rom_batch* h) {
   h->total_cells = h->cell_off[B];
   h->total_dof = h->dof_off[B];
   // stencil tiles (cells) and pass tiles (basis rows)
-  std::vector<Tile> tiles, ptiles;
+  std::vector<Tile> tiles, ptiles, btiles;
   h->ptile_first.assign(B + 1, 0);
   for (int b = 0; b < B; ++b) {
-    for (int64_t c0 = 0; c0 < h->n_cells[b]; c0 += kTile)
-      tiles.push_back(Tile{b, 0, c0, std::min<int64_t>(kTile, h->n_cells[b] - c0)});
-    const int64_t rows = h->n_cells[b] * h->nv;
+    const int64_t nb = h->n_cells[b], base = h->dof_off[b];
+    for (int64_t c0 = 0; c0 < nb; c0 += kTile)
+      tiles.push_back(Tile{b, 0, c0, std::min<int64_t>(kTile, nb - c0), nb, base});
+    for (int64_t c0 = 0; c0 < nb; c0 += kBigTile)
+      btiles.push_back(Tile{b, 0, c0, std::min<int64_t>(kBigTile, nb - c0), nb, base});
+    const int64_t rows = nb * h->nv;
     h->ptile_first[b] = (int)ptiles.size();
     for (int64_t r0 = 0; r0 < rows; r0 += kPassRows)
-      ptiles.push_back(Tile{b, 0, r0, std::min<int64_t>(kPassRows, rows - r0)});
+      ptiles.push_back(Tile{b, 0, r0, std::min<int64_t>(kPassRows, rows - r0), nb, base});
   }
   h->ptile_first[B] = (int)ptiles.size();
   h->n_tiles = (int)tiles.size();
+  h->n_btiles = (int)btiles.size();
   h->n_ptiles = (int)ptiles.size();
   const size_t es = h->esz;
   const int r = c.r;
@@ -191,12 +195,14 @@ rom_status setup(rom_batch* h) {
   ROM_TRY(alloc(&h->d_cell_off, B + 1));
   ROM_TRY(alloc(&h->d_phys, h->phys.size()));
   ROM_TRY(alloc(&h->d_tiles, tiles.size()));
+  ROM_TRY(alloc(&h->d_btiles, btiles.size()));
   ROM_TRY(alloc(&h->d_ptiles, ptiles.size()));
   ROM_TRY(alloc(&h->d_ptile_first, B + 1));
   ROM_HIP_CHECK(hipMemcpy(h->d_dof_off, h->dof_off.data(), 8 * (B + 1), hipMemcpyHostToDevice));
   ROM_HIP_CHECK(hipMemcpy(h->d_cell_off, h->cell_off.data(), 8 * (B + 1), hipMemcpyHostToDevice));
   ROM_HIP_CHECK(hipMemcpy(h->d_phys, h->phys.data(), 8 * h->phys.size(), hipMemcpyHostToDevice));
   ROM_HIP_CHECK(hipMemcpy(h->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice));
+  ROM_HIP_CHECK(hipMemcpy(h->d_btiles, btiles.data(), sizeof(Tile) * btiles.size(), hipMemcpyHostToDevice));
   ROM_HIP_CHECK(hipMemcpy(h->d_ptiles, ptiles.data(), sizeof(Tile) * ptiles.size(), hipMemcpyHostToDevice));
   ROM_HIP_CHECK(hipMemcpy(h->d_ptile_first, h->ptile_first.data(), sizeof(int) * (B + 1),
                           hipMemcpyHostToDevice));

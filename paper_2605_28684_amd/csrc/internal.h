@@ -42,7 +42,11 @@ struct Tile {
   int32_t pad;
   int64_t cell0;   // first cell (instance-local)
   int64_t ncell;   // number of cells in the tile
+  int64_t n;       // cells of the instance
+  int64_t base;    // first DOF of the instance in the batch
 };
+
+constexpr int kBigTile = 1024;      // cells per block of the streaming Euler residual
 
 // One level of the recursive block-tridiagonal (Schur complement) solver.
 struct BtLevel {
@@ -76,6 +80,8 @@ struct rom_batch {
   double* d_phys = nullptr;
   romhip::Tile* d_tiles = nullptr;
   int n_tiles = 0;
+  romhip::Tile* d_btiles = nullptr;  // kBigTile-cell tiles
+  int n_btiles = 0;
   romhip::Tile* d_ptiles = nullptr;  // row tiles of kPassRows basis rows
   int n_ptiles = 0;
   std::vector<int> ptile_first;      // first row tile of each instance [n_inst+1]
@@ -167,6 +173,13 @@ rom_status launch_rebuild(rom_batch* h, hipStream_t s);
 rom_status launch_reconstruct(rom_batch* h, void* out, hipStream_t s);
 rom_status rom_kernels_prepare();
 rom_status isvd_kernels_prepare();
+
+// ---- mfma.hip (FP32, r in {32, 64})
+bool mfma_ok(const rom_batch* h);
+rom_status launch_galerkin_mfma(rom_batch* h, hipStream_t s);
+rom_status launch_rotate_mfma(rom_batch* h, const double* pr, hipStream_t s);
+rom_status launch_project_fast(rom_batch* h, const void* y, const double* p1, int ldp, int mode,
+                               int pst, double* q1out, hipStream_t s);
 
 // ---- small helpers (api.cpp)
 rom_status fill_zero(void* p, size_t bytes, hipStream_t s);

@@ -13,7 +13,7 @@
 // decomposed by one-sided (Hestenes) Jacobi on its rows in FP64, one
 // workgroup per instance with both K and the accumulated rotations in LDS;
 // rows are orthogonalised pairwise in round-robin order until every pair is
-// orthogonal to 1e-15 relative.
+// orthogonal to 2 n eps relative.
 #include "internal.h"
 #include "physics.h"
 
@@ -109,27 +109,38 @@ __global__ void k_reduce_tiles(const int* __restrict__ tfirst, const double* __r
 }
 
 // ------------------------------------------------------------------ small SVD
-// One-sided Jacobi on the rows of the n x n matrix K (LDS, leading dim ld):
-// K <- G K with G orthogonal until the rows are mutually orthogonal.  Then
-// sigma_i = ||row i|| and row i of G is the left singular vector.  On exit the
-// sorted (descending, stable) vectors are written as columns of U (n x n,
-// row-major, global) with the sign convention "largest |entry| positive,
-// first index on ties", and the sorted values to sv.
+DEV void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One-sided Jacobi on the rows of the n x n matrix K (LDS, leading dim ld),
+// run by a single wavefront (blockDim.x == 64, n <= 128): K <- G K with G
+// orthogonal until the rows are mutually orthogonal.  Then sigma_i = ||row i||
+// and row i of G is the left singular vector.  Pairs of a round (circle
+// ordering) are independent, so each gets a lane group of TPP lanes and the
+// rounds are separated by wave-level fences only.  On exit the sorted
+// (descending, stable) vectors are the columns of U (n x n, row-major, global)
+// with the sign convention "largest |entry| positive, first index on ties",
+// and the sorted values are in sv.
 DEV void jacobi_rows(double* K, double* G, int n, int ld, double* U, double* sv, double* norms,
-                     int* rank, int* rotated) {
-  const int tid = threadIdx.x;
-  const int nth = blockDim.x;
-  for (int e = tid; e < n * ld; e += nth) G[e] = ((e / ld) == (e % ld)) ? 1.0 : 0.0;
-  __syncthreads();
-  const int np = n + (n & 1);     // even number of slots
-  const int TPP = 4;              // threads per pair
-  const int grp = tid / TPP, sub = tid % TPP;
-  const int ngrp = nth / TPP;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    if (tid == 0) *rotated = 0;
-    __syncthreads();
+                     int* rank) {
+  const int lane = threadIdx.x;
+  for (int e = lane; e < n * ld; e += 64) G[e] = ((e / ld) == (e % ld)) ? 1.0 : 0.0;
+  wave_sync();
+  const int np = n + (n & 1);
+  const int npairs = np / 2;
+  int TPP = 1;
+  while (TPP * 2 * npairs <= 64) TPP *= 2;
+  const int grp = lane / TPP, sub = lane % TPP, ngrp = 64 / TPP;
+  // rows count as orthogonal below 2 n eps: below that the rounding of the
+  // length-n dot products and of the rotations themselves dominates
+  const double tol = 2.0 * n * 2.220446049250313e-16;
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    int rotated = 0;
     for (int rnd = 0; rnd < np - 1; ++rnd) {
-      for (int pr = grp; pr < np / 2; pr += ngrp) {
+      for (int pr = grp; pr < npairs; pr += ngrp) {
         // circle method: slot 0 fixed, the other np-1 slots rotate each round
         const int a = pr == 0 ? 0 : ((pr - 1 + rnd) % (np - 1)) + 1;
         const int c = ((np - 2 - pr + rnd) % (np - 1)) + 1;
@@ -142,13 +153,12 @@ DEV void jacobi_rows(double* K, double* G, int n, int ld, double* U, double* sv,
             al += x * x; be += z * z; ga += x * z;
           }
         }
-#pragma unroll
         for (int off = 1; off < TPP; off <<= 1) {
           al += __shfl_xor(al, off, TPP);
           be += __shfl_xor(be, off, TPP);
           ga += __shfl_xor(ga, off, TPP);
         }
-        if (live && ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al) * sqrt(be)) {
+        if (live && ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -160,31 +170,29 @@ DEV void jacobi_rows(double* K, double* G, int n, int ld, double* U, double* sv,
             G[i * ld + q] = cs * gx - sn * gz;
             G[j * ld + q] = sn * gx + cs * gz;
           }
-          if (sub == 0) *rotated = 1;
+          rotated = 1;
         }
       }
-      __syncthreads();
+      wave_sync();
     }
-    const int any = *rotated;
-    __syncthreads();
-    if (!any) break;
+    if (!__any(rotated)) break;
   }
-  for (int i = tid; i < n; i += nth) {
+  for (int i = lane; i < n; i += 64) {
     double s = 0.0;
     for (int q = 0; q < n; ++q) s += K[i * ld + q] * K[i * ld + q];
     norms[i] = sqrt(s);
   }
-  __syncthreads();
-  for (int i = tid; i < n; i += nth) {
+  wave_sync();
+  for (int i = lane; i < n; i += 64) {
     int rk = 0;
     for (int j = 0; j < n; ++j)
       if (norms[j] > norms[i] || (norms[j] == norms[i] && j < i)) ++rk;
     rank[i] = rk;
     sv[rk] = norms[i];
   }
-  __syncthreads();
+  wave_sync();
   // sign convention per vector (row i of G), then scatter as column rank[i] of U
-  for (int i = tid; i < n; i += nth) {
+  for (int i = lane; i < n; i += 64) {
     int im = 0;
     double best = -1.0;
     for (int q = 0; q < n; ++q) {
@@ -200,7 +208,7 @@ DEV void jacobi_rows(double* K, double* G, int n, int ld, double* U, double* sv,
 
 // Core of Alg. 2: K from lambda, sigma, p, rho; SVD; sigma' and the transfer of a.
 // red layout per instance: [0..r) p1, r: |y^|^2, [r+1..2r+1) p2, 2r+1: |q1|^2
-__global__ __launch_bounds__(256) void k_isvd_core(int r, double lambda, double tau_rho,
+__global__ __launch_bounds__(64) void k_isvd_core(int r, double lambda, double tau_rho,
                                                   const double* __restrict__ red, int ldr,
                                                   double* __restrict__ sigma, double* __restrict__ a,
                                                   double* __restrict__ ubar, double* __restrict__ pr,
@@ -213,7 +221,6 @@ __global__ __launch_bounds__(256) void k_isvd_core(int r, double lambda, double 
   double* sv = nrm + n;
   double* ta = sv + n;
   int* rank = (int*)(ta + n);
-  __shared__ int rotated;
   __shared__ double rho_s;
   const int b = blockIdx.x, tid = threadIdx.x;
   const double* R = red + (size_t)b * ldr;
@@ -239,7 +246,7 @@ __global__ __launch_bounds__(256) void k_isvd_core(int r, double lambda, double 
     K[e] = v;
   }
   __syncthreads();
-  jacobi_rows(K, G, n, ld, U, sv, nrm, rank, &rotated);
+  jacobi_rows(K, G, n, ld, U, sv, nrm, rank);
   for (int c = tid; c < r; c += blockDim.x) sigma[(size_t)b * r + c] = sv[c];
   // closed-form transfer: a <- Ubar[:r, :r]^T a  (the new direction is orthogonal to Phi)
   for (int c = tid; c < r; c += blockDim.x) {
@@ -511,11 +518,10 @@ __global__ __launch_bounds__(256) void k_pod_scale(const Tile* __restrict__ tile
   }
 }
 
-__global__ __launch_bounds__(256) void k_pod_svd(int w, int r, const double* __restrict__ R,
-                                                 double* __restrict__ U, double* __restrict__ sigma,
-                                                 int use_lds) {
+__global__ __launch_bounds__(64) void k_pod_svd(int w, int r, const double* __restrict__ R,
+                                                double* __restrict__ U, double* __restrict__ sigma,
+                                                int use_lds) {
   extern __shared__ double sm[];
-  __shared__ int rotated;
   const int b = blockIdx.x, tid = threadIdx.x;
   const int n = w, ld = w;
   double* K = sm;
@@ -525,7 +531,7 @@ __global__ __launch_bounds__(256) void k_pod_svd(int w, int r, const double* __r
   int* rank = (int*)(sv + n);
   for (int e = tid; e < n * n; e += blockDim.x) K[e] = R[(size_t)b * n * n + e];
   __syncthreads();
-  jacobi_rows(K, G, n, ld, U + (size_t)b * n * n, sv, nrm, rank, &rotated);
+  jacobi_rows(K, G, n, ld, U + (size_t)b * n * n, sv, nrm, rank);
   for (int c = tid; c < r; c += blockDim.x) sigma[(size_t)b * r + c] = sv[c];
   (void)use_lds;
 }
@@ -588,19 +594,37 @@ rom_status project_t(rom_batch* h, const void* Phi, int ld, int k, const void* y
   return ROM_OK;
 }
 
+// pass A / pass B of the projection, through the fast kernel when it applies
+template <typename T>
+rom_status projection_pass(rom_batch* h, const void* y, const double* p1, int ldp, int mode,
+                           double* dst, int ldd, double* q1out, hipStream_t s) {
+  const int r = h->cfg.r;
+  if (mfma_ok(h)) {
+    rom_status st = launch_project_fast(h, y, p1, ldp, mode, kPst, q1out, s);
+    if (st != ROM_OK) return st;
+    hipLaunchKernelGGL(k_reduce_tiles, dim3(h->cfg.n_inst), dim3(128), 0, s, h->d_ptile_first,
+                       h->part, r, dst, ldd);
+    return ROM_OK;
+  }
+  return project_t<T>(h, h->Phi, r, r, y, h->q_ref, p1, ldp, mode, dst, ldd, s, q1out);
+}
+
 template <typename T>
 rom_status isvd_t(rom_batch* h, const void* y, hipStream_t s) {
   const int r = h->cfg.r, B = h->cfg.n_inst;
   const int ldr = 2 * r + 4;
   double* red = h->red;
-  // pass A: p1 = Phi^T y^, |y^|^2 ; pass B: p2 = Phi^T q1, |q1|^2
-  project_t<T>(h, h->Phi, r, r, y, h->q_ref, nullptr, 0, 1, red, ldr, s);
-  project_t<T>(h, h->Phi, r, r, y, h->q_ref, red, ldr, 2, red + r + 1, ldr, s, h->qtmp);
+  // pass A: p1 = Phi^T y^, |y^|^2 ; pass B: p2 = Phi^T q1, |q1|^2 (q1 stored)
+  rom_status st = projection_pass<T>(h, y, nullptr, 0, 1, red, ldr, nullptr, s);
+  if (st != ROM_OK) return st;
+  st = projection_pass<T>(h, y, red, ldr, 2, red + r + 1, ldr, h->qtmp, s);
+  if (st != ROM_OK) return st;
   const int n = r + 1;
   const size_t shm = sizeof(double) * (2 * n * n + 3 * n) + sizeof(int) * n;
   double* pr = h->rstate;  // (p1, p2, 1/rho) per instance, stride 2r + 2
-  hipLaunchKernelGGL(k_isvd_core, dim3(B), dim3(256), shm, s, r, h->cfg.lambda, h->cfg.tau_rho,
+  hipLaunchKernelGGL(k_isvd_core, dim3(B), dim3(64), shm, s, r, h->cfg.lambda, h->cfg.tau_rho,
                      red, ldr, h->sigma, h->a, h->ubar, pr, h->flags);
+  if (mfma_ok(h)) return launch_rotate_mfma(h, pr, s);
   hipLaunchKernelGGL((k_rotate<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                      h->d_dof_off, (const T*)h->Phi, r, r, (T*)h->Phi, r, r, h->ubar, n,
                      (size_t)n * n, 1, h->qtmp, pr, 2 * r + 2, nullptr);
@@ -658,7 +682,7 @@ rom_status pod_t(rom_batch* h, const void* Qtrain, int w, hipStream_t s) {
                        h->d_dof_off, Q, w, k, prp, 2 * kMaxK + 2);
   }
   const size_t shm = sizeof(double) * (2 * w * w + 2 * w) + sizeof(int) * w;
-  hipLaunchKernelGGL(k_pod_svd, dim3(B), dim3(256), shm, s, w, r, R, U, h->sigma, 1);
+  hipLaunchKernelGGL(k_pod_svd, dim3(B), dim3(64), shm, s, w, r, R, U, h->sigma, 1);
   hipLaunchKernelGGL((k_rotate<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                      h->d_dof_off, (const T*)Q, w, w, (T*)h->Phi, r, r, U, w, (size_t)w * w, 0,
                      nullptr, nullptr, 0, nullptr);
@@ -692,7 +716,8 @@ template <typename T>
 rom_status project_state_t(rom_batch* h, const void* q, hipStream_t s) {
   const int r = h->cfg.r;
   // a[b*r + c] = Phi^T D (q - q_ref); the squared norm lands in red scratch
-  project_t<T>(h, h->Phi, r, r, q, h->q_ref, nullptr, 0, 1, h->red, 2 * r + 4, s);
+  rom_status st = projection_pass<T>(h, q, nullptr, 0, 1, h->red, 2 * r + 4, nullptr, s);
+  if (st != ROM_OK) return st;
   hipLaunchKernelGGL(k_copy_cols, dim3(h->cfg.n_inst), dim3(64), 0, s, h->red, 2 * r + 4, r, h->a);
   return ROM_OK;
 }
@@ -712,8 +737,8 @@ rom_status launch_isvd(rom_batch* h, const void* y, hipStream_t s) {
 rom_status launch_isvd_project(rom_batch* h, const void* y, hipStream_t s) {
   const int r = h->cfg.r;
   return h->cfg.precision == ROM_F64
-             ? project_t<double>(h, h->Phi, r, r, y, h->q_ref, nullptr, 0, 1, h->red, 2 * r + 4, s)
-             : project_t<float>(h, h->Phi, r, r, y, h->q_ref, nullptr, 0, 1, h->red, 2 * r + 4, s);
+             ? projection_pass<double>(h, y, nullptr, 0, 1, h->red, 2 * r + 4, nullptr, s)
+             : projection_pass<float>(h, y, nullptr, 0, 1, h->red, 2 * r + 4, nullptr, s);
 }
 
 rom_status launch_reorth(rom_batch* h, hipStream_t s) {

@@ -7,6 +7,8 @@
 // coalesced element loads (the halo wraps for periodic models and copies the
 // end cell for zero-gradient walls), face fluxes are computed once per face
 // into LDS, and results are staged back through LDS for coalesced stores.
+#include <algorithm>
+
 #include "internal.h"
 #include "physics.h"
 
@@ -94,6 +96,173 @@ __global__ __launch_bounds__(kTile) void k_residual(
   }
   if (norms && nb) atomicMax((unsigned long long*)&norms[b], (unsigned long long)nb);
   flag_or<T>(flags, b, fl);
+}
+
+// Euler residual, persistent and register-resident: a block of 256 threads
+// walks kBigTile-cell tiles (tile += gridDim.x); thread t owns cells t, t+256,
+// t+512, t+768 of a tile, loads each cell's three conserved values with one
+// 12-byte load straight into registers, and computes the cell's primitives
+// there (floored density, velocity, pressure, sound speed, flux terms).  LDS
+// only exchanges what neighbours need (structure-of-arrays, conflict-free):
+// the primitives of every cell, then the face fluxes.  The next tile's states
+// are prefetched into registers while the current tile computes, so memory
+// traffic overlaps the arithmetic.  Faces follow App. B eqs.
+// sod_rusanov_flux / sod_rusanov_speed (Rusanov) or Toro's HLLC with Davis
+// speeds.  Same contract as k_residual.
+constexpr int kEulerThreads = 256;
+constexpr int kCellsPerThread = kBigTile / kEulerThreads;
+
+template <typename T>
+struct Cell3 { T v[3]; };
+
+template <typename T, bool HLLC>
+__global__ __launch_bounds__(kEulerThreads) void k_residual_euler(
+    const Tile* __restrict__ tiles, int n_tiles, const double* __restrict__ phys, int nphys,
+    const T* __restrict__ q, const T* __restrict__ qprev, T dt, T* __restrict__ out,
+    uint32_t* flags, uint64_t* norms, const int32_t* active) {
+  constexpr int NA = 8;  // rho, m, E, rf, u, p, c, (F1 or 1/rf)
+  constexpr int LA = kBigTile + 2, LH = kBigTile + 1;
+  __shared__ T sa[NA * LA];
+  __shared__ T sH[3 * LH];
+  const int tid = threadIdx.x;
+  // registers: this thread's cells of the current / next tile (+ halo cells for two threads)
+  Cell3<T> cur[kCellsPerThread], nxt[kCellsPerThread];
+  Cell3<T> hcur, hnxt;  // halo cell: thread 0 -> left, thread 1 -> right
+  auto fetch = [&](int ti, Cell3<T>* dst, Cell3<T>& hd) {
+    const Tile t = tiles[ti];
+    const int64_t n = t.n;
+#pragma unroll
+    for (int j = 0; j < kCellsPerThread; ++j) {
+      const int lc = tid + kEulerThreads * j;
+      if (lc < t.ncell) dst[j] = *reinterpret_cast<const Cell3<T>*>(q + t.base + (t.cell0 + lc) * 3);
+    }
+    if (tid < 2) {
+      int64_t c = tid == 0 ? t.cell0 - 1 : t.cell0 + t.ncell;
+      c = c < 0 ? 0 : (c >= n ? n - 1 : c);   // zero-gradient ghosts
+      hd = *reinterpret_cast<const Cell3<T>*>(q + t.base + c * 3);
+    }
+  };
+  int ti = blockIdx.x;
+  if (ti < n_tiles) fetch(ti, cur, hcur);
+  unsigned fl = 0;
+  for (; ti < n_tiles; ti += gridDim.x) {
+    const Tile t = tiles[ti];
+    const int b = t.inst;
+    const bool skip = active && !active[b];
+    const int64_t n = t.n;
+    const int nt = (int)t.ncell;
+    const T gamma = T(phys[(size_t)b * nphys]);
+    const int tn = ti + gridDim.x;
+    // primitives of owned cells (LDS slot lc + 1) and of the halo cells
+    auto prim = [&](const Cell3<T>& c3, int slot) {
+      const T rho = c3.v[0], m = c3.v[1], E = c3.v[2];
+      if (rho < T(kRhoMin)) fl |= ROM_FLAG_FLOOR;
+      const T rf = rho >= T(kRhoMin) ? rho : T(kRhoMin);
+      const T ir = T(1) / rf;
+      const T u = m * ir;
+      const T pe = (gamma - T(1)) * (E - T(0.5) * m * u);
+      if (pe < T(kPMin)) fl |= ROM_FLAG_FLOOR;
+      const T p = pe >= T(kPMin) ? pe : T(kPMin);
+      sa[slot] = rho; sa[LA + slot] = m; sa[2 * LA + slot] = E; sa[3 * LA + slot] = rf;
+      sa[4 * LA + slot] = u; sa[5 * LA + slot] = p; sa[6 * LA + slot] = dsqrt(gamma * p * ir);
+      sa[7 * LA + slot] = HLLC ? ir : m * u + p;
+    };
+    if (!skip) {
+#pragma unroll
+      for (int j = 0; j < kCellsPerThread; ++j) {
+        const int lc = tid + kEulerThreads * j;
+        if (lc < nt) prim(cur[j], lc + 1);
+      }
+      if (tid == 0) prim(hcur, 0);
+      if (tid == 1) prim(hcur, nt + 1);
+    }
+    // the next tile's loads overlap everything below
+    if (tn < n_tiles) fetch(tn, nxt, hnxt);
+    __syncthreads();
+    if (!skip) {
+      for (int k = tid; k <= nt; k += kEulerThreads) {
+        T L[NA], R[NA], H[3];
+#pragma unroll
+        for (int v = 0; v < NA; ++v) { L[v] = sa[v * LA + k]; R[v] = sa[v * LA + k + 1]; }
+        if (!HLLC) {
+          const T uL = L[4], uR = R[4];
+          const T aL = (uL >= T(0) ? uL : -uL) + L[6], aR = (uR >= T(0) ? uR : -uR) + R[6];
+          const T s = aL >= aR ? aL : aR;
+          const T h = T(0.5);
+          H[0] = h * (L[1] + R[1]) - h * s * (R[0] - L[0]);
+          H[1] = h * (L[7] + R[7]) - h * s * (R[1] - L[1]);
+          H[2] = h * (uL * (L[2] + L[5]) + uR * (R[2] + R[5])) - h * s * (R[2] - L[2]);
+        } else {
+          const T rL = L[3], uL = L[4], pL = L[5], cL = L[6];
+          const T rR = R[3], uR = R[4], pR = R[5], cR = R[6];
+          const T SL = (uL - cL) <= (uR - cR) ? (uL - cL) : (uR - cR);
+          const T SR = (uL + cL) >= (uR + cR) ? (uL + cL) : (uR + cR);
+          if (SL >= T(0)) {
+            H[0] = L[1]; H[1] = L[1] * uL + pL; H[2] = uL * (L[2] + pL);
+          } else {
+            const T num = pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR);
+            const T den = rL * (SL - uL) - rR * (SR - uR);
+            const T Ss = num / den;
+            if (Ss >= T(0)) {
+              const T fac = rL * (SL - uL) / (SL - Ss);
+              const T e = L[2] * L[7] + (Ss - uL) * (Ss + pL / (rL * (SL - uL)));
+              H[0] = L[1] + SL * (fac - L[0]);
+              H[1] = L[1] * uL + pL + SL * (fac * Ss - L[1]);
+              H[2] = uL * (L[2] + pL) + SL * (fac * e - L[2]);
+            } else if (SR >= T(0)) {
+              const T fac = rR * (SR - uR) / (SR - Ss);
+              const T e = R[2] * R[7] + (Ss - uR) * (Ss + pR / (rR * (SR - uR)));
+              H[0] = R[1] + SR * (fac - R[0]);
+              H[1] = R[1] * uR + pR + SR * (fac * Ss - R[1]);
+              H[2] = uR * (R[2] + pR) + SR * (fac * e - R[2]);
+            } else {
+              H[0] = R[1]; H[1] = R[1] * uR + pR; H[2] = uR * (R[2] + pR);
+            }
+          }
+        }
+        sH[k] = H[0]; sH[LH + k] = H[1]; sH[2 * LH + k] = H[2];
+      }
+    }
+    __syncthreads();
+    if (!skip) {
+      const T nn = T(n);
+      uint64_t nb = 0;
+#pragma unroll
+      for (int j = 0; j < kCellsPerThread; ++j) {
+        const int lc = tid + kEulerThreads * j;
+        if (lc < nt) {
+          const int64_t g = t.base + (t.cell0 + lc) * 3;
+          Cell3<T> o;
+          Cell3<T> pv;
+          if (qprev) pv = *reinterpret_cast<const Cell3<T>*>(qprev + g);
+#pragma unroll
+          for (int v = 0; v < 3; ++v) {
+            T val = -(sH[v * LH + lc + 1] - sH[v * LH + lc]) * nn;
+            if (qprev) val = cur[j].v[v] - pv.v[v] - dt * val;
+            if (!isfinite(val)) fl |= ROM_FLAG_NONFINITE;
+            o.v[v] = val;
+            const uint64_t bits = isfinite(val) ? norm_bits(val) : ~0ull;
+            nb = bits > nb ? bits : nb;
+          }
+          *reinterpret_cast<Cell3<T>*>(out + g) = o;
+        }
+      }
+      if (norms) {
+        // wave-level max first: one atomic per wave instead of one per lane
+        for (int o = 32; o > 0; o >>= 1) {
+          const uint64_t other = __shfl_xor((unsigned long long)nb, o);
+          nb = other > nb ? other : nb;
+        }
+        if ((tid & 63) == 0 && nb) atomicMax((unsigned long long*)&norms[b], (unsigned long long)nb);
+      }
+      flag_or<T>(flags, b, fl);
+      fl = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < kCellsPerThread; ++j) cur[j] = nxt[j];
+    hcur = hnxt;
+    __syncthreads();   // LDS is rewritten by the next tile
+  }
 }
 
 // Jacobian blocks of f at cell i: Jm = df_i/dq_{i-1}, J0 = df_i/dq_i, Jp = df_i/dq_{i+1}
@@ -407,6 +576,20 @@ rom_status with_model(const rom_batch* h, F&& fn) {
 template <typename T>
 static rom_status residual_t(rom_batch* h, const void* q, const void* q_prev, double dt, void* out,
                              uint64_t* norms, const int32_t* active, hipStream_t s) {
+  if (h->cfg.problem == ROM_EULER_RUSANOV || h->cfg.problem == ROM_EULER_HLLC) {
+    // persistent grid: a few blocks per CU, each walking tiles
+    // (LDS use allows three FP32 blocks or one FP64 block per CU)
+    const int grid = std::min(h->n_btiles, 256 * (sizeof(T) == 4 ? 3 : 1));
+    if (h->cfg.problem == ROM_EULER_HLLC)
+      hipLaunchKernelGGL((k_residual_euler<T, true>), dim3(grid), dim3(kEulerThreads), 0, s,
+                         h->d_btiles, h->n_btiles, h->d_phys, h->cfg.n_phys, (const T*)q,
+                         (const T*)q_prev, (T)dt, (T*)out, h->flags, norms, active);
+    else
+      hipLaunchKernelGGL((k_residual_euler<T, false>), dim3(grid), dim3(kEulerThreads), 0, s,
+                         h->d_btiles, h->n_btiles, h->d_phys, h->cfg.n_phys, (const T*)q,
+                         (const T*)q_prev, (T)dt, (T*)out, h->flags, norms, active);
+    return ROM_OK;
+  }
   return with_model<T>(h, [&](auto tag) -> rom_status {
     using M = typename decltype(tag)::type;
     hipLaunchKernelGGL((k_residual<M, T>), dim3(h->n_tiles), dim3(kTile), 0, s, h->d_tiles,

@@ -621,9 +621,14 @@ rom_status galerkin_step_t(rom_batch* h, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3((B + 255) / 256), dim3(256), 0, s, h->iters, 0, (int64_t)B);
   double* gpart = h->part;
   for (int it = 0; it < h->cfg.rom_max; ++it) {
-    hipLaunchKernelGGL((k_galerkin_pass<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
-                       h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const T*)h->Phi, r,
-                       (const T*)h->q_ref, h->d_var, h->a, h->active, gpart, (T*)h->mpart);
+    if (mfma_ok(h)) {
+      rom_status st = launch_galerkin_mfma(h, s);
+      if (st != ROM_OK) return st;
+    } else {
+      hipLaunchKernelGGL((k_galerkin_pass<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                         h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const T*)h->Phi,
+                         r, (const T*)h->q_ref, h->d_var, h->a, h->active, gpart, (T*)h->mpart);
+    }
     hipLaunchKernelGGL((k_galerkin_solve<T>), dim3(B), dim3(256), 0, s, h->d_ptile_first, gpart,
                        (const T*)h->mpart, r, h->cfg.dt, h->d_var, h->a, h->a_prev, h->active,
                        h->iters, h->cfg.rom_tol, h->flags);
@@ -718,6 +723,7 @@ rom_status launch_galerkin_pass(rom_batch* h, hipStream_t s) {
   const int B = h->cfg.n_inst, r = h->cfg.r;
   if (h->cfg.problem != ROM_BURGERS) return ROM_E_UNSUPPORTED;
   hipLaunchKernelGGL(k_fill_i32, dim3((B + 255) / 256), dim3(256), 0, s, h->active, 1, (int64_t)B);
+  if (mfma_ok(h)) return launch_galerkin_mfma(h, s);
   if (h->cfg.precision == ROM_F64)
     hipLaunchKernelGGL((k_galerkin_pass<double>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                        h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const double*)h->Phi,

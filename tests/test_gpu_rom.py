@@ -43,13 +43,13 @@ def _burgers_batch(cells, precision, r):
     return w
 
 
+@pytest.mark.parametrize("r", [8, 32])
 @pytest.mark.parametrize("precision", [W.F64, W.F32])
 @pytest.mark.parametrize("lam", [0.5, 0.0, 1.0])
-def test_isvd_update_parity(precision, lam):
+def test_isvd_update_parity(precision, lam, r):
     import gpu_common as G
     from paper_2605_28684_amd import romhip as R
     cells = [700, 2100, 64]
-    r = 8
     w = _burgers_batch(cells, precision, r)
     w.lam = lam
     w.reorth_every = 0
@@ -229,13 +229,14 @@ def test_hr_lspg_step_parity(problem):
     assert G.relerr(G.host(h.get(R.GET_A)), a1) < 1e-11
 
 
-def test_galerkin_fine_step_parity_fp32():
-    """One FP32 Galerkin step of a ragged batch from identical state (no event)."""
+@pytest.mark.parametrize("r", [8, 32])
+def test_galerkin_fine_step_parity_fp32(r):
+    """One FP32 Galerkin step of a ragged batch from identical state (no event);
+    r = 32 runs the MFMA pass."""
     import gpu_common as G
     import torch
     from paper_2605_28684_amd import romhip as R
     cells = [2048, 4096, 700]
-    r = 8
     w = _burgers_batch(cells, W.F32, r)
     w.phys = [dict(nu=0.002 + 0.003 * b) for b in range(3)]
     h = _handle(w)
