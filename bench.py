@@ -42,6 +42,10 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
+    p.add_argument("--only", choices=["all", "copy", "galerkin", "residual"], default="all",
+                   help="profiling runs: 'copy' times a plain 512 MiB device copy (the "
+                        "reference for counter scaling), 'galerkin' only the Galerkin pass, "
+                        "'residual' only R(q); 'all' is the benchmark")
     return p.parse_args()
 
 
@@ -89,6 +93,36 @@ def cpu_baseline(w, budget_s):
                                                          t_total))
 
 
+def profile_only(args, torch, W, R):
+    """One kernel family at a time, for rocprofv3 counter runs."""
+    reps = max(args.steps, 1)
+    if args.only == "copy":
+        n = 128 * 1024 * 1024                      # 512 MiB of float32 each way
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(reps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy: %d x %d bytes" % (reps, 4 * n))
+    elif args.only == "galerkin":
+        w = W.burgers_batch_f32()
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            h = R.RomBatch(w, q0=torch.as_tensor(w.q0, dtype=torch.float32, device="cuda"),
+                           use_graph=True)
+            ms = h.profile(R.PROF_GALERKIN_PASS, reps)
+            h.close()
+        log("galerkin pass: %.5f ms per launch" % ms)
+    else:
+        we = W.euler_adjoint_f32(n_inst=64, n=262144)
+        he = R.RomBatch(we, q0=None, use_graph=False)
+        qe = torch.as_tensor(we.q0, dtype=torch.float32, device="cuda")
+        ms = he.profile(R.PROF_RESIDUAL, reps, qe)
+        he.close()
+        log("residual: %.5f ms per launch" % ms)
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -102,6 +136,8 @@ def main():
     from paper_2605_28684_amd import romhip as R
 
     torch.cuda.set_device(0)
+    if args.only != "all":
+        return profile_only(args, torch, W, R)
     w = W.burgers_batch_f32()
     z = w.z
     s = torch.cuda.Stream()

@@ -242,6 +242,7 @@ rom_status setup(rom_batch* h) {
   ROM_HIP_CHECK(hipMemset(h->a, 0, 8 * (size_t)B * r));
   ROM_HIP_CHECK(hipMemset(h->sigma, 0, 8 * (size_t)B * r));
   ROM_TRY(bt_setup(h));
+  h->fom_block = fom_block_ok(h);
   ROM_TRY(isvd_kernels_prepare());
   ROM_TRY(rom_kernels_prepare());
   ROM_HIP_CHECK(hipDeviceSynchronize());
@@ -255,6 +256,11 @@ rom_status fom_step_impl(rom_batch* h, const void* q_prev, double dt, void* q_ou
   const int B = h->cfg.n_inst;
   const size_t bytes = h->esz * h->total_dof;
   const bool f64 = h->cfg.precision == ROM_F64;
+  if (h->fom_block) {
+    ROM_TRY(launch_fom_block(h, q_prev, dt, q_out, h->iters, s));
+    if (iters_out) ROM_TRY(copy_words(h->iters, iters_out, 4 * (size_t)B, s));
+    return ROM_OK;
+  }
   ROM_TRY(copy_words(q_prev, h->fq_prev, bytes, s));
   ROM_TRY(copy_words(q_prev, h->fq, bytes, s));
   const int mx = h->cfg.newton_max;
@@ -554,11 +560,12 @@ rom_status rom_profile(rom_handle h, int32_t stage, int32_t reps, const void* q,
   ROM_REQUIRE(q || stage == ROM_PROF_GALERKIN_PASS, ROM_E_INVAL, "q is required for this stage");
   hipStream_t s = (hipStream_t)stream;
   h->last_stream = s;
-  // the Galerkin pass overwrites only scratch; keep a and the flags intact
+  // the Galerkin pass writes only scratch: a and the flags stay intact
   hipEvent_t e0, e1;
   ROM_HIP_CHECK(hipEventCreate(&e0));
   ROM_HIP_CHECK(hipEventCreate(&e1));
   rom_status st = ROM_OK;
+  if (stage == ROM_PROF_GALERKIN_PASS) st = prepare_galerkin_pass(h, s);
   ROM_HIP_CHECK(hipEventRecord(e0, s));
   for (int i = 0; i < reps && st == ROM_OK; ++i) {
     switch (stage) {

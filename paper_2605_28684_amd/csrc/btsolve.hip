@@ -293,9 +293,12 @@ __global__ __launch_bounds__(256) void k_bt_back(int n_inst, const int64_t* __re
   using L = Lay<T, NV>;
   constexpr int NN = L::NN;
   const int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gp >= part_off[n_inst]) return;
-  const int b = find_inst(part_off, n_inst, gp);
-  if (active && !active[b]) return;
+  // no early return: the update norm is reduced across the wavefront below
+  const bool inb = gp < part_off[n_inst];
+  const int b = inb ? find_inst(part_off, n_inst, gp) : -1;
+  const bool live = inb && !(active && !active[b]);
+  double dmax = 0.0;
+  if (live) {
   const int64_t k = gp - part_off[b];
   const int64_t P = part_off[b + 1] - part_off[b];
   const int64_t n = cell_off[b + 1] - cell_off[b];
@@ -303,7 +306,6 @@ __global__ __launch_bounds__(256) void k_bt_back(int n_inst, const int64_t* __re
   const int64_t first = k * m;
   const int64_t s = (first + m < n ? first + m : n) - 1;
   T xl[NV], xr[NV], xn[NV], tv[NV], tw[NV];
-  double dmax = 0.0;
   const int64_t kl = (k + P - 1) % P;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -342,9 +344,14 @@ __global__ __launch_bounds__(256) void k_bt_back(int n_inst, const int64_t* __re
       emit(j, xn);
     }
   }
+  }
   if (dnorm && mode == 1) {
-    const uint64_t bits = isfinite(dmax) ? (uint64_t)__double_as_longlong(dmax) : ~0ull;
-    atomicMax((unsigned long long*)&dnorm[b], (unsigned long long)bits);
+    const uint64_t bits = !live ? 0ull
+                          : isfinite(dmax) ? (uint64_t)__double_as_longlong(dmax) : ~0ull;
+    // one atomic per wavefront when all its live lanes belong to one instance
+    const int b0 = __builtin_amdgcn_readfirstlane(b);
+    if (__all(!live || b == b0) && b0 >= 0) wave_atomic_max(&dnorm[b0], bits);
+    else if (live) atomicMax((unsigned long long*)&dnorm[b], (unsigned long long)bits);
   }
 }
 

@@ -62,6 +62,17 @@ struct BtLevel {
   void* x = nullptr;      // solution per cell (nv)
 };
 
+// Max of v over the 64 lanes of a wavefront, then one atomicMax into *dst from
+// lane 0.  Every lane of the wavefront must call it with the same dst.
+__device__ __forceinline__ void wave_atomic_max(uint64_t* dst, uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor((unsigned long long)v, off);
+    v = o > v ? o : v;
+  }
+  if ((threadIdx.x & 63) == 0 && v) atomicMax((unsigned long long*)dst, (unsigned long long)v);
+}
+
 }  // namespace romhip
 
 struct rom_batch {
@@ -128,6 +139,7 @@ struct rom_batch {
   int64_t n_events = 0;
   int64_t n_reorth = 0;
   bool has_rom = false;
+  bool fom_block = false;          // backward-Euler steps run one workgroup per instance
   hipStream_t last_stream = nullptr;
 
   // graphs of one adaptation window
@@ -167,6 +179,12 @@ rom_status launch_project_state(rom_batch* h, const void* q, hipStream_t s);  //
 
 // ---- rom.hip
 rom_status launch_rom_fine_step(rom_batch* h, hipStream_t s);
+// Whole-Newton-loop-per-workgroup backward-Euler step for batches of small
+// scalar instances (see fomblock.hip); fom_block_ok tells whether it applies.
+bool fom_block_ok(const rom_batch* h);
+rom_status launch_fom_block(rom_batch* h, const void* q_prev, double dt, void* q_out,
+                            int32_t* iters, hipStream_t s);
+rom_status prepare_galerkin_pass(rom_batch* h, hipStream_t s);
 rom_status launch_galerkin_pass(rom_batch* h, hipStream_t s);  // one pass, every instance active
 rom_status launch_isvd_project(rom_batch* h, const void* y, hipStream_t s);  // pass A only
 rom_status launch_rebuild(rom_batch* h, hipStream_t s);

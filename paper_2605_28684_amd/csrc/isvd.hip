@@ -136,7 +136,7 @@ DEV void jacobi_rows(double* K, double* G, int n, int ld, double* U, double* sv,
   const int grp = lane / TPP, sub = lane % TPP, ngrp = 64 / TPP;
   // rows count as orthogonal below 2 n eps: below that the rounding of the
   // length-n dot products and of the rotations themselves dominates
-  const double tol = 2.0 * n * 2.220446049250313e-16;
+  const double tol = 2.0 * n * 2.220446049250313e-16, tol2 = tol * tol;
   for (int sweep = 0; sweep < 30; ++sweep) {
     int rotated = 0;
     for (int rnd = 0; rnd < np - 1; ++rnd) {
@@ -158,7 +158,7 @@ DEV void jacobi_rows(double* K, double* G, int n, int ld, double* U, double* sv,
           be += __shfl_xor(be, off, TPP);
           ga += __shfl_xor(ga, off, TPP);
         }
-        if (live && ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+        if (live && ga != 0.0 && ga * ga > tol2 * al * be) {
           const double zeta = (be - al) / (2.0 * ga);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -206,9 +206,118 @@ DEV void jacobi_rows(double* K, double* G, int n, int ld, double* U, double* sv,
   __syncthreads();
 }
 
+// The same one-sided Jacobi for a compile-time size N (the online core, N = r + 1
+// with r in {32, 64}), run by a whole 256-thread block: each pair of a round
+// gets TPP lanes (8 for N = 33, 4 for N = 65), every lane loads its at most
+// EPL elements of both K rows and both G rows at once, keeps the K values in
+// registers for the rotation, and the rounds are separated by one block
+// barrier.  Same pair order, test and conventions as jacobi_rows.
+template <int N>
+DEV void jacobi_rows_blk(double* K, double* G, double* U, double* sv, double* norms, int* rank) {
+  constexpr int ld = N;
+  constexpr int NP = N + (N & 1), NPAIRS = NP / 2;
+  constexpr int TPP = NPAIRS * 16 <= 256 ? 16 : NPAIRS * 8 <= 256 ? 8 : NPAIRS * 4 <= 256 ? 4 : 2;
+  constexpr int EPL = (N + TPP - 1) / TPP;
+  static_assert(NPAIRS * TPP <= 256, "core too large for one block");
+  const int tid = threadIdx.x, grp = tid / TPP, sub = tid % TPP;
+  for (int e = tid; e < N * ld; e += 256) G[e] = ((e / ld) == (e % ld)) ? 1.0 : 0.0;
+  __syncthreads();
+  const double tol = 2.0 * N * 2.220446049250313e-16, tol2 = tol * tol;
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    int rotated = 0;
+    for (int rnd = 0; rnd < NP - 1; ++rnd) {
+      if (grp < NPAIRS) {
+        const int a = grp == 0 ? 0 : ((grp - 1 + rnd) % (NP - 1)) + 1;
+        const int c = ((NP - 2 - grp + rnd) % (NP - 1)) + 1;
+        const int i = a < c ? a : c, j = a < c ? c : a;
+        if (j < N) {
+          double x[EPL], z[EPL], gx[EPL], gz[EPL];
+          double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) {
+            const int q = sub + TPP * e;
+            const bool in = q < N;
+            x[e] = in ? K[i * ld + q] : 0.0;
+            z[e] = in ? K[j * ld + q] : 0.0;
+            gx[e] = in ? G[i * ld + q] : 0.0;
+            gz[e] = in ? G[j * ld + q] : 0.0;
+          }
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) {
+            al += x[e] * x[e];
+            be += z[e] * z[e];
+            ga += x[e] * z[e];
+          }
+#pragma unroll
+          for (int off = 1; off < TPP; off <<= 1) {
+            al += __shfl_xor(al, off, TPP);
+            be += __shfl_xor(be, off, TPP);
+            ga += __shfl_xor(ga, off, TPP);
+          }
+          if (ga != 0.0 && ga * ga > tol2 * al * be) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) {
+              const int q = sub + TPP * e;
+              if (q < N) {
+                K[i * ld + q] = cs * x[e] - sn * z[e];
+                K[j * ld + q] = sn * x[e] + cs * z[e];
+                G[i * ld + q] = cs * gx[e] - sn * gz[e];
+                G[j * ld + q] = sn * gx[e] + cs * gz[e];
+              }
+            }
+            rotated = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (!__syncthreads_or(rotated)) break;
+  }
+  if (tid < N) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < N; ++q) s += K[tid * ld + q] * K[tid * ld + q];
+    norms[tid] = sqrt(s);
+  }
+  __syncthreads();
+  if (tid < N) {
+    int rk = 0;
+    const double ni = norms[tid];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const double nj = norms[j];
+      if (nj > ni || (nj == ni && j < tid)) ++rk;
+    }
+    rank[tid] = rk;
+    sv[rk] = ni;
+  }
+  __syncthreads();
+  // sign convention per vector (row i of G), then scatter as column rank[i] of U
+  if (tid < N) {
+    int im = 0;
+    double best = -1.0;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      const double v = fabs(G[tid * ld + q]);
+      if (v > best) { best = v; im = q; }
+    }
+    const double sg = G[tid * ld + im] < 0.0 ? -1.0 : 1.0;
+    const int col = rank[tid];
+#pragma unroll 4
+    for (int q = 0; q < N; ++q) U[q * N + col] = sg * G[tid * ld + q];
+  }
+  __syncthreads();
+}
+
 // Core of Alg. 2: K from lambda, sigma, p, rho; SVD; sigma' and the transfer of a.
 // red layout per instance: [0..r) p1, r: |y^|^2, [r+1..2r+1) p2, 2r+1: |q1|^2
-__global__ __launch_bounds__(64) void k_isvd_core(int r, double lambda, double tau_rho,
+// NF = 0: any r, one wavefront (jacobi_rows); NF = r + 1 in {33, 65}: 256 threads
+// (jacobi_rows_blk<NF>).
+template <int NF>
+__global__ __launch_bounds__(NF == 0 ? 64 : 256) void k_isvd_core(int r, double lambda, double tau_rho,
                                                   const double* __restrict__ red, int ldr,
                                                   double* __restrict__ sigma, double* __restrict__ a,
                                                   double* __restrict__ ubar, double* __restrict__ pr,
@@ -246,7 +355,8 @@ __global__ __launch_bounds__(64) void k_isvd_core(int r, double lambda, double t
     K[e] = v;
   }
   __syncthreads();
-  jacobi_rows(K, G, n, ld, U, sv, nrm, rank);
+  if constexpr (NF == 0) jacobi_rows(K, G, n, ld, U, sv, nrm, rank);
+  else jacobi_rows_blk<NF>(K, G, U, sv, nrm, rank);
   for (int c = tid; c < r; c += blockDim.x) sigma[(size_t)b * r + c] = sv[c];
   // closed-form transfer: a <- Ubar[:r, :r]^T a  (the new direction is orthogonal to Phi)
   for (int c = tid; c < r; c += blockDim.x) {
@@ -622,8 +732,15 @@ rom_status isvd_t(rom_batch* h, const void* y, hipStream_t s) {
   const int n = r + 1;
   const size_t shm = sizeof(double) * (2 * n * n + 3 * n) + sizeof(int) * n;
   double* pr = h->rstate;  // (p1, p2, 1/rho) per instance, stride 2r + 2
-  hipLaunchKernelGGL(k_isvd_core, dim3(B), dim3(64), shm, s, r, h->cfg.lambda, h->cfg.tau_rho,
-                     red, ldr, h->sigma, h->a, h->ubar, pr, h->flags);
+  if (r == 32)
+    hipLaunchKernelGGL(k_isvd_core<33>, dim3(B), dim3(256), shm, s, r, h->cfg.lambda,
+                       h->cfg.tau_rho, red, ldr, h->sigma, h->a, h->ubar, pr, h->flags);
+  else if (r == 64)
+    hipLaunchKernelGGL(k_isvd_core<65>, dim3(B), dim3(256), shm, s, r, h->cfg.lambda,
+                       h->cfg.tau_rho, red, ldr, h->sigma, h->a, h->ubar, pr, h->flags);
+  else
+    hipLaunchKernelGGL(k_isvd_core<0>, dim3(B), dim3(64), shm, s, r, h->cfg.lambda,
+                       h->cfg.tau_rho, red, ldr, h->sigma, h->a, h->ubar, pr, h->flags);
   if (mfma_ok(h)) return launch_rotate_mfma(h, pr, s);
   hipLaunchKernelGGL((k_rotate<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                      h->d_dof_off, (const T*)h->Phi, r, r, (T*)h->Phi, r, r, h->ubar, n,
@@ -726,7 +843,9 @@ rom_status project_state_t(rom_batch* h, const void* q, hipStream_t s) {
 
 rom_status isvd_kernels_prepare() {
   const int big = 160 * 1024 - 1024;
-  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_isvd_core, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_isvd_core<0>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_isvd_core<33>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_isvd_core<65>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_pod_svd, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   return ROM_OK;
 }

@@ -348,4 +348,54 @@ struct ReactModel {
   }
 };
 
+// Jacobian blocks of f at cell i: Jm = df_i/dq_{i-1}, J0 = df_i/dq_i, Jp = df_i/dq_{i+1}
+// and f_i itself.  sq holds cells i-1, i, i+1 at qm, q0, qp.  lw/rw mark a
+// zero-gradient wall on the left / right (ghost = copy of the end cell).
+template <class Mdl, typename T>
+DEV void cell_jacobian(const Mdl& m, const T* qm, const T* q0, const T* qp, bool lw, bool rw,
+                       T inv, T inv2, double x, T* f, T* Jm, T* J0, T* Jp, unsigned& fl) {
+  constexpr int NV = Mdl::NV;
+  constexpr int NN = NV * NV;
+  T HL[NV], HR[NV], DLl[NN], DRl[NN], DLr[NN], DRr[NN];
+  m.face_jac(qm, q0, HL, DLl, DRl, fl);   // face i-1/2: (q_{i-1}, q_i)
+  m.face_jac(q0, qp, HR, DLr, DRr, fl);   // face i+1/2: (q_i, q_{i+1})
+  // f_i = -(HR - HL) inv
+#pragma unroll
+  for (int v = 0; v < NV; ++v) f[v] = -(HR[v] - HL[v]) * inv;
+#pragma unroll
+  for (int e = 0; e < NN; ++e) {
+    Jm[e] = DLl[e] * inv;
+    J0[e] = (DRl[e] - DLr[e]) * inv;
+    Jp[e] = -DRr[e] * inv;
+  }
+  if (lw) {  // ghost q_{-1} = q_0: the left face depends on q_0 through both sides
+#pragma unroll
+    for (int e = 0; e < NN; ++e) { J0[e] += Jm[e]; Jm[e] = T(0); }
+  }
+  if (rw) {
+#pragma unroll
+    for (int e = 0; e < NN; ++e) { J0[e] += Jp[e]; Jp[e] = T(0); }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const T kap = m.kappa(v);
+    if (kap != T(0)) {
+      f[v] += kap * ((qp[v] - q0[v]) - (q0[v] - qm[v])) * inv2;
+      const T c = kap * inv2;
+      // ghost neighbours fold onto the diagonal at walls
+      Jm[v * NV + v] += lw ? T(0) : c;
+      Jp[v * NV + v] += rw ? T(0) : c;
+      J0[v * NV + v] += -T(2) * c + (lw ? c : T(0)) + (rw ? c : T(0));
+    }
+  }
+  if (Mdl::has_source) {
+    T S[NV], DS[NN];
+    m.source_jac(q0, x, S, DS, fl);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) f[v] += S[v];
+#pragma unroll
+    for (int e = 0; e < NN; ++e) J0[e] += DS[e];
+  }
+}
+
 }  // namespace romhip

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kTile) void k_residual(
     const uint64_t bits = isfinite(val) ? norm_bits(val) : ~0ull;
     nb = bits > nb ? bits : nb;
   }
-  if (norms && nb) atomicMax((unsigned long long*)&norms[b], (unsigned long long)nb);
+  if (norms) wave_atomic_max(&norms[b], nb);
   flag_or<T>(flags, b, fl);
 }
 
@@ -247,14 +247,7 @@ __global__ __launch_bounds__(kEulerThreads) void k_residual_euler(
           *reinterpret_cast<Cell3<T>*>(out + g) = o;
         }
       }
-      if (norms) {
-        // wave-level max first: one atomic per wave instead of one per lane
-        for (int o = 32; o > 0; o >>= 1) {
-          const uint64_t other = __shfl_xor((unsigned long long)nb, o);
-          nb = other > nb ? other : nb;
-        }
-        if ((tid & 63) == 0 && nb) atomicMax((unsigned long long*)&norms[b], (unsigned long long)nb);
-      }
+      if (norms) wave_atomic_max(&norms[b], nb);
       flag_or<T>(flags, b, fl);
       fl = 0;
     }
@@ -262,56 +255,6 @@ __global__ __launch_bounds__(kEulerThreads) void k_residual_euler(
     for (int j = 0; j < kCellsPerThread; ++j) cur[j] = nxt[j];
     hcur = hnxt;
     __syncthreads();   // LDS is rewritten by the next tile
-  }
-}
-
-// Jacobian blocks of f at cell i: Jm = df_i/dq_{i-1}, J0 = df_i/dq_i, Jp = df_i/dq_{i+1}
-// and f_i itself.  sq holds cells i-1, i, i+1 at qm, q0, qp.  lw/rw mark a
-// zero-gradient wall on the left / right (ghost = copy of the end cell).
-template <class Mdl, typename T>
-DEV void cell_jacobian(const Mdl& m, const T* qm, const T* q0, const T* qp, bool lw, bool rw,
-                       T inv, T inv2, double x, T* f, T* Jm, T* J0, T* Jp, unsigned& fl) {
-  constexpr int NV = Mdl::NV;
-  constexpr int NN = NV * NV;
-  T HL[NV], HR[NV], DLl[NN], DRl[NN], DLr[NN], DRr[NN];
-  m.face_jac(qm, q0, HL, DLl, DRl, fl);   // face i-1/2: (q_{i-1}, q_i)
-  m.face_jac(q0, qp, HR, DLr, DRr, fl);   // face i+1/2: (q_i, q_{i+1})
-  // f_i = -(HR - HL) inv
-#pragma unroll
-  for (int v = 0; v < NV; ++v) f[v] = -(HR[v] - HL[v]) * inv;
-#pragma unroll
-  for (int e = 0; e < NN; ++e) {
-    Jm[e] = DLl[e] * inv;
-    J0[e] = (DRl[e] - DLr[e]) * inv;
-    Jp[e] = -DRr[e] * inv;
-  }
-  if (lw) {  // ghost q_{-1} = q_0: the left face depends on q_0 through both sides
-#pragma unroll
-    for (int e = 0; e < NN; ++e) { J0[e] += Jm[e]; Jm[e] = T(0); }
-  }
-  if (rw) {
-#pragma unroll
-    for (int e = 0; e < NN; ++e) { J0[e] += Jp[e]; Jp[e] = T(0); }
-  }
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const T kap = m.kappa(v);
-    if (kap != T(0)) {
-      f[v] += kap * ((qp[v] - q0[v]) - (q0[v] - qm[v])) * inv2;
-      const T c = kap * inv2;
-      // ghost neighbours fold onto the diagonal at walls
-      Jm[v * NV + v] += lw ? T(0) : c;
-      Jp[v * NV + v] += rw ? T(0) : c;
-      J0[v * NV + v] += -T(2) * c + (lw ? c : T(0)) + (rw ? c : T(0));
-    }
-  }
-  if (Mdl::has_source) {
-    T S[NV], DS[NN];
-    m.source_jac(q0, x, S, DS, fl);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) f[v] += S[v];
-#pragma unroll
-    for (int e = 0; e < NN; ++e) J0[e] += DS[e];
   }
 }
 
@@ -366,8 +309,8 @@ __global__ __launch_bounds__(kTile) void k_assemble(
       yb = yv > yb ? yv : yb;
     }
   }
-  if (norms && nb) atomicMax((unsigned long long*)&norms[b], (unsigned long long)nb);
-  if (ynorms && yb) atomicMax((unsigned long long*)&ynorms[b], (unsigned long long)yb);
+  if (norms) wave_atomic_max(&norms[b], nb);
+  if (ynorms) wave_atomic_max(&ynorms[b], yb);
   flag_or<T>(flags, b, fl);
 }
 

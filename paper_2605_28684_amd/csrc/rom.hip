@@ -16,6 +16,7 @@
 //  * Greedy DEIM with oversampling (interpolation-residual argmax, then a
 //    least-squares round) and the (P^T Phi)^+ rebuild by Householder QR.
 #include "internal.h"
+#include "linalg.h"
 #include "physics.h"
 
 namespace romhip {
@@ -117,47 +118,11 @@ __global__ __launch_bounds__(256) void k_galerkin_pass(
 // LU with partial pivoting on an n x n FP64 matrix in LDS (row-major, ld n),
 // solving A x = b in place of b.  Single-thread pivot search, row updates by
 // the whole block.  Returns false (via *ok) if a pivot vanishes.
-DEV void lu_solve_block(double* A, double* bvec, int n, int* ok) {
-  __shared__ int piv;
-  const int tid = threadIdx.x;
-  if (tid == 0) *ok = 1;
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (tid == 0) {
-      int p = k;
-      double best = fabs(A[k * n + k]);
-      for (int i = k + 1; i < n; ++i) {
-        const double v = fabs(A[i * n + k]);
-        if (v > best) { best = v; p = i; }
-      }
-      piv = p;
-      if (best == 0.0) *ok = 0;
-    }
-    __syncthreads();
-    const int p = piv;
-    if (p != k) {
-      for (int j = tid; j < n; j += blockDim.x) {
-        const double tmp = A[k * n + j]; A[k * n + j] = A[p * n + j]; A[p * n + j] = tmp;
-      }
-      if (tid == 0) { const double tmp = bvec[k]; bvec[k] = bvec[p]; bvec[p] = tmp; }
-    }
-    __syncthreads();
-    const double pk = A[k * n + k];
-    for (int i = k + 1 + tid; i < n; i += blockDim.x) {
-      const double f = pk != 0.0 ? A[i * n + k] / pk : 0.0;
-      A[i * n + k] = f;
-      for (int j = k + 1; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
-      bvec[i] -= f * bvec[k];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    for (int i = n - 1; i >= 0; --i) {
-      double s = bvec[i];
-      for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * bvec[j];
-      bvec[i] = A[i * n + i] != 0.0 ? s / A[i * n + i] : 0.0;
-    }
-  }
+// Block-level wrapper (A row-major, leading dimension ld); *ok is written for
+// the whole block.
+DEV void lu_solve_block(double* A, int ld, double* bvec, int n, int* ok) {
+  const int r = block_lu_solve(A, ld, bvec, n);
+  if (threadIdx.x == 0) *ok = r;
   __syncthreads();
 }
 
@@ -167,25 +132,43 @@ __global__ __launch_bounds__(256) void k_galerkin_solve(
     int r, double dt, const double* __restrict__ dvar, double* __restrict__ a,
     const double* __restrict__ a_prev, int32_t* __restrict__ active, int32_t* __restrict__ iters,
     double tol, uint32_t* flags) {
-  __shared__ double J[kMaxR * kMaxR];
+  __shared__ double J[kMaxR * (kMaxR + 1)];
   __shared__ double g[kMaxR];
   __shared__ int ok;
   const int b = blockIdx.x, tid = threadIdx.x;
   if (!active[b]) return;
+  const int ld = r + 1;
   const double d = dvar[b];
+  // tile partials summed in tile order; the loads of 8 tiles are issued together
+  const int t0 = tfirst[b], t1 = tfirst[b + 1];
   for (int e = tid; e < r * r; e += blockDim.x) {
     double s = 0.0;
-    for (int tt = tfirst[b]; tt < tfirst[b + 1]; ++tt) s += (double)mpart[(size_t)tt * kMaxR * kMaxR + e];
+    for (int tt = t0; tt < t1; tt += 8) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = tt + u < t1 ? mpart[(size_t)(tt + u) * kMaxR * kMaxR + e] : T(0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (tt + u < t1) s += (double)v[u];
+    }
     const int i = e / r, j = e % r;
-    J[e] = (i == j ? 1.0 : 0.0) - dt * s;
+    J[i * ld + j] = (i == j ? 1.0 : 0.0) - dt * s;
   }
   for (int c = tid; c < r; c += blockDim.x) {
     double s = 0.0;
-    for (int tt = tfirst[b]; tt < tfirst[b + 1]; ++tt) s += gpart[(size_t)tt * kMaxR + c];
+    for (int tt = t0; tt < t1; tt += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = tt + u < t1 ? gpart[(size_t)(tt + u) * kMaxR + c] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (tt + u < t1) s += v[u];
+    }
     g[c] = -(a[(size_t)b * r + c] - a_prev[(size_t)b * r + c] - dt * d * s);
   }
   __syncthreads();
-  lu_solve_block(J, g, r, &ok);
+  lu_solve_block(J, ld, g, r, &ok);
   if (tid == 0) {
     double dm = 0.0, am = 0.0;
     bool fin = true;
@@ -223,8 +206,8 @@ __global__ __launch_bounds__(256) void k_hr_step(
   double* sap = sa + kMaxR;        // r
   double* bs = sap + kMaxR;        // ns
   double* As = bs + kMaxNs;        // ns x r
-  double* Ar = As + kMaxNs * kMaxR;  // r x r
-  double* rh = Ar + kMaxR * kMaxR;   // r
+  double* Ar = As + kMaxNs * kMaxR;  // r x r, leading dimension r + 1
+  double* rh = Ar + kMaxR * (kMaxR + 1);  // r
   __shared__ int ok, stop;
   __shared__ unsigned flacc;
   const int b = blockIdx.x, tid = threadIdx.x;
@@ -303,7 +286,7 @@ __global__ __launch_bounds__(256) void k_hr_step(
       const int i = e / r, k = e % r;
       double acc = 0.0;
       for (int s = 0; s < ns; ++s) acc += Mb[i * ns + s] * As[s * kMaxR + k];
-      Ar[e] = acc;
+      Ar[i * (r + 1) + k] = acc;
     }
     for (int i = tid; i < r; i += blockDim.x) {
       double acc = 0.0;
@@ -311,7 +294,7 @@ __global__ __launch_bounds__(256) void k_hr_step(
       rh[i] = -acc;
     }
     __syncthreads();
-    lu_solve_block(Ar, rh, r, &ok);
+    lu_solve_block(Ar, r + 1, rh, r, &ok);
     if (tid == 0) {
       double dm = 0.0, am = 0.0;
       bool fin = true;
@@ -639,7 +622,7 @@ rom_status galerkin_step_t(rom_batch* h, hipStream_t s) {
 }
 
 size_t hr_shm() {
-  return sizeof(double) * (2 * kMaxR + kMaxNs + kMaxNs * kMaxR + kMaxR * kMaxR + kMaxR);
+  return sizeof(double) * (2 * kMaxR + kMaxNs + kMaxNs * kMaxR + kMaxR * (kMaxR + 1) + kMaxR);
 }
 
 rom_status hr_step(rom_batch* h, hipStream_t s) {
@@ -719,10 +702,19 @@ rom_status launch_rom_fine_step(rom_batch* h, hipStream_t s) {
   return h->cfg.precision == ROM_F64 ? galerkin_step_t<double>(h, s) : galerkin_step_t<float>(h, s);
 }
 
-rom_status launch_galerkin_pass(rom_batch* h, hipStream_t s) {
-  const int B = h->cfg.n_inst, r = h->cfg.r;
+rom_status prepare_galerkin_pass(rom_batch* h, hipStream_t s) {
+  const int B = h->cfg.n_inst;
   if (h->cfg.problem != ROM_BURGERS) return ROM_E_UNSUPPORTED;
   hipLaunchKernelGGL(k_fill_i32, dim3((B + 255) / 256), dim3(256), 0, s, h->active, 1, (int64_t)B);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+// One Galerkin pass over the basis (block partials only: no reduced state
+// changes); prepare_galerkin_pass must have marked the instances active.
+rom_status launch_galerkin_pass(rom_batch* h, hipStream_t s) {
+  const int r = h->cfg.r;
+  if (h->cfg.problem != ROM_BURGERS) return ROM_E_UNSUPPORTED;
   if (mfma_ok(h)) return launch_galerkin_mfma(h, s);
   if (h->cfg.precision == ROM_F64)
     hipLaunchKernelGGL((k_galerkin_pass<double>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,

@@ -84,6 +84,37 @@ def test_fom_step_parity(problem, precision):
     assert not (h.status() & 1).any()
 
 
+@pytest.mark.parametrize("precision", [W.F64, W.F32])
+@pytest.mark.parametrize("path", ["block", "grid"])
+def test_burgers_fom_step_block_and_grid_paths(path, precision):
+    """Scalar periodic steps run one workgroup per instance while every instance
+    fits (16384 cells in FP32, 8192 in FP64: 16 or 8 cells per thread); a larger
+    instance sends the batch through the grid-wide solver.  Block-path edge
+    cases: the largest instance, a ragged one whose last part is a lone
+    separator (1025 = 512 parts of 2 + 1) and the smallest (3 cells)."""
+    import gpu_common as G
+    import torch
+    cap = 16384 if precision == W.F32 else 8192
+    cells = [cap, 1025, 3] if path == "block" else [cap + 1000, 300]
+    w = _workload(W.BURGERS, cells, precision)
+    w.newton_tol = 1e-10 if precision == W.F64 else 1e-5
+    h = _handle(w)
+    q = G.rounded(W.random_state(W.BURGERS, cells, seed=31, scale=0.5), precision)
+    dt = 2e-4
+    it = torch.zeros(w.n_inst, dtype=torch.int32, device="cuda")
+    q1 = G.host(h.fom_step(G.to_dev(q, precision), dt, iters=it))
+    its = it.cpu().numpy()
+    off = w.offsets()
+    for b in range(w.n_inst):
+        ref, n_ref, ok = F.newton_be_step(W.BURGERS, q[off[b]:off[b + 1]], dt, w.phys[b],
+                                          tol=w.newton_tol, max_it=10)
+        assert ok
+        assert abs(int(its[b]) - n_ref) <= (0 if precision == W.F64 else 1), (b, its[b], n_ref)
+        err = G.relerr(q1[off[b]:off[b + 1]], ref)
+        assert err < (1e-11 if precision == W.F64 else 1e-5), (b, err)
+    assert not (h.status() & (1 | 4 | 16)).any()
+
+
 def test_fom_step_inplace_and_nonconvergence_flag():
     import gpu_common as G
     w = _workload(W.BURGERS, [256], W.F64)

@@ -43,13 +43,15 @@ def _burgers_batch(cells, precision, r):
     return w
 
 
-@pytest.mark.parametrize("r", [8, 32])
+@pytest.mark.parametrize("r", [8, 32, 64])
 @pytest.mark.parametrize("precision", [W.F64, W.F32])
 @pytest.mark.parametrize("lam", [0.5, 0.0, 1.0])
 def test_isvd_update_parity(precision, lam, r):
+    """r = 32 and 64 run the block-wide core SVD (and, in FP32, the MFMA
+    rotation); r = 8 the single-wavefront one."""
     import gpu_common as G
     from paper_2605_28684_amd import romhip as R
-    cells = [700, 2100, 64]
+    cells = [700, 2100, 64 if r < 64 else 130]
     w = _burgers_batch(cells, precision, r)
     w.lam = lam
     w.reorth_every = 0
@@ -229,10 +231,10 @@ def test_hr_lspg_step_parity(problem):
     assert G.relerr(G.host(h.get(R.GET_A)), a1) < 1e-11
 
 
-@pytest.mark.parametrize("r", [8, 32])
+@pytest.mark.parametrize("r", [8, 32, 64])
 def test_galerkin_fine_step_parity_fp32(r):
     """One FP32 Galerkin step of a ragged batch from identical state (no event);
-    r = 32 runs the MFMA pass."""
+    r = 32 and 64 run the MFMA pass."""
     import gpu_common as G
     import torch
     from paper_2605_28684_amd import romhip as R
