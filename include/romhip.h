@@ -211,6 +211,30 @@ rom_status fom_step_vjp(rom_handle h, const void* q, double dt, const void* gbar
                         void* stream);
 
 /*
+ * rom_rollout_vjp - gradient of a loss of the final state of a backward-Euler
+ * full-order rollout with respect to its initial state (an extension beyond
+ * the paper: the adjoint of eq. fom_discrete_solve iterated).  The rollout is
+ * q^{k+1} = S(q^k), k = 0 .. n_steps-1, each step solved by Newton as in
+ * fom_step with step dt; given gbar = dL/dq^T it returns
+ *   gq0 = dL/dq^0 = J_r(q^1)^-T J_r(q^2)^-T ... J_r(q^T)^-T gbar.
+ * Memory follows sqrt(T) checkpointing: the forward pass keeps one state every
+ * S = ceil(n_steps / n_ckpt) steps; the backward pass recomputes one segment
+ * at a time from its checkpoint and applies the step adjoints in reverse, so
+ * about n_ckpt + S + 3 states are held and 2 n_steps forward steps are run.
+ * The result does not depend on n_ckpt (every recomputation is bitwise
+ * identical).
+ *   q0, gbar, gq0: device T[total_dof] (q0 and gbar are not modified; gq0 may
+ *   alias gbar).  n_ckpt = 0 chooses ceil(sqrt(n_steps)); n_ckpt > n_steps is
+ *   clamped.  The checkpoint storage is allocated on the first call that needs
+ *   it (hipMalloc; this call is not meant for stream capture) and kept with
+ *   the handle.  Newton flags raised on the way are recorded as for fom_step.
+ * Errors: ROM_E_INVAL (NULL pointers, n_steps < 1, n_ckpt < 0, dt <= 0),
+ * ROM_E_NOMEM.
+ */
+rom_status rom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, double dt,
+                           int32_t n_ckpt, const void* gbar, void* gq0, void* stream);
+
+/*
  * rom_profile - time one stage of the hot path in isolation: the stage is
  * launched reps times between two HIP events recorded on the given stream and
  * the mean milliseconds per launch are written to *ms.  The handle's reduced

@@ -21,6 +21,8 @@ Definitions followed
     max(|u_L|+c_L, |u_R|+c_R), zero-gradient ghosts, ideal gas       paper App. B, eqs. sod_*
   * Euler HLLC flux (not in the paper): Toro's HLLC with Davis wave-speed
     estimates, used by the 65,536-cell Sod workload
+  * gradient of a final-state loss through a backward-Euler rollout (an
+    extension beyond the paper): implicit-function adjoint of every step
 """
 import numpy as np
 import scipy.sparse as sp
@@ -245,6 +247,20 @@ def fom_trajectory(problem, q0, dt, n_steps, phys, tol=1e-8, max_it=10):
         q, _, _ = newton_be_step(problem, q, dt, phys, tol, max_it)
         Q.append(q)
     return np.stack(Q, axis=1)
+
+
+def be_rollout_vjp(problem, q0, dt, n_steps, phys, gbar, tol=1e-8, max_it=10):
+    """Gradient of L(q^T) through a backward-Euler rollout q^{k+1} = S(q^k):
+    dL/dq^0 = J_r(q^1)^-T ... J_r(q^T)^-T dL/dq^T, where each step's sensitivity
+    dq^{k+1}/dq^k = J_r(q^{k+1})^-1 follows from differentiating the converged
+    residual q^{k+1} - q^k - dt f(q^{k+1}) = 0 (eq. be_residual_rom_section).
+    Every state is kept; the transposed systems are solved exactly."""
+    Q = fom_trajectory(problem, q0, dt, n_steps, phys, tol, max_it)
+    g = np.asarray(gbar, dtype=np.float64).copy()
+    for k in range(n_steps - 1, -1, -1):
+        J = jacobian_be(problem, Q[:, k + 1], dt, phys)
+        g = spla.spsolve(J.T.tocsc(), g)
+    return g
 
 
 def vjp_f(problem, q, w, phys):

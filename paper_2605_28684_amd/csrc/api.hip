@@ -151,7 +151,7 @@ void free_all(rom_batch* h) {
                 h->Phi, h->sigma, h->a, h->a_prev, h->q_ref, h->d_var, h->y_corr, h->flags, h->P,
                 h->M, h->mesh_phi, h->mesh_qref, h->chosen, h->part, h->red, h->ubar, h->lmat,
                 h->active, h->iters, h->norms, h->rstate, h->qtmp, h->mpart, h->fq, h->fq_prev, h->vjp_tmp,
-                h->d_epoch};
+                h->d_epoch, h->rvjp};
   for (void* p : ps) (void)hipFree(p);
   bt_free(h);
   if (h->win_exec) (void)hipGraphExecDestroy(h->win_exec);
@@ -550,6 +550,60 @@ rom_status fom_step_vjp(rom_handle h, const void* q, double dt, const void* gbar
   h->last_stream = s;
   ROM_TRY(launch_assemble_adjoint(h, q, dt, gbar, s));
   return bt_solve(h, -1, nullptr, gq_prev, s);
+}
+
+rom_status rom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, double dt,
+                           int32_t n_ckpt, const void* gbar, void* gq0, void* stream) {
+  ROM_REQUIRE(h && q0 && gbar && gq0, ROM_E_INVAL, "handle, q0, gbar and gq0 are required");
+  ROM_REQUIRE(n_steps >= 1, ROM_E_INVAL, "n_steps must be >= 1");
+  ROM_REQUIRE(n_ckpt >= 0, ROM_E_INVAL, "n_ckpt must be >= 0");
+  ROM_REQUIRE(dt > 0.0 && std::isfinite(dt), ROM_E_INVAL, "dt must be positive");
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  const int64_t T = n_steps;
+  int64_t C = n_ckpt > 0 ? n_ckpt : (int64_t)std::ceil(std::sqrt((double)T));
+  if (C > T) C = T;
+  const int64_t S = (T + C - 1) / C;      // steps per segment
+  const int64_t nseg = (T + S - 1) / S;   // checkpoints (states q^0, q^S, q^2S, ...)
+  const size_t st = h->esz * (size_t)h->total_dof;
+  const size_t need = (size_t)(nseg + S + 1 + 2) * st;
+  if (h->rvjp_bytes < need) {
+    ROM_HIP_CHECK(hipStreamSynchronize(s));
+    if (h->rvjp) (void)hipFree(h->rvjp);
+    h->rvjp = nullptr;
+    h->rvjp_bytes = 0;
+    char* p = nullptr;
+    ROM_TRY(alloc(&p, need));
+    h->rvjp = p;
+    h->rvjp_bytes = need;
+  }
+  char* ck = (char*)h->rvjp;
+  char* seg = ck + (size_t)nseg * st;
+  char* ga = seg + (size_t)(S + 1) * st;
+  char* gb = ga + st;
+  // forward: checkpoints only
+  ROM_TRY(copy_words(q0, ck, st, s));
+  for (int64_t j = 0; j + 1 < nseg; ++j) {
+    char* nxt = ck + (size_t)(j + 1) * st;
+    ROM_TRY(copy_words(ck + (size_t)j * st, nxt, st, s));
+    for (int64_t k = 0; k < S; ++k) ROM_TRY(fom_step_impl(h, nxt, dt, nxt, nullptr, s));
+  }
+  // backward, one segment at a time
+  ROM_TRY(copy_words(gbar, ga, st, s));
+  for (int64_t j = nseg - 1; j >= 0; --j) {
+    const int64_t k0 = j * S, k1 = std::min(k0 + S, T), L = k1 - k0;
+    ROM_TRY(copy_words(ck + (size_t)j * st, seg, st, s));
+    for (int64_t i = 0; i < L; ++i)
+      ROM_TRY(fom_step_impl(h, seg + (size_t)i * st, dt, seg + (size_t)(i + 1) * st, nullptr, s));
+    for (int64_t i = L - 1; i >= 0; --i) {
+      ROM_TRY(launch_assemble_adjoint(h, seg + (size_t)(i + 1) * st, dt, ga, s));
+      ROM_TRY(bt_solve(h, -1, nullptr, gb, s));
+      std::swap(ga, gb);
+    }
+  }
+  ROM_TRY(copy_words(ga, gq0, st, s));
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
 }
 
 rom_status rom_profile(rom_handle h, int32_t stage, int32_t reps, const void* q, double* ms,

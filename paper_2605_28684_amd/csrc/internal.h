@@ -132,6 +132,8 @@ struct rom_batch {
   void* fq_prev = nullptr;   // T[total_dof]
   std::vector<romhip::BtLevel> levels;
   void* vjp_tmp = nullptr;   // T[total_dof]
+  void* rvjp = nullptr;      // rollout-adjoint checkpoints and segment states
+  size_t rvjp_bytes = 0;
 
   // host counters
   int64_t n_fine = 0;        // fine step index n of Alg. 1 (starts at w_init)

@@ -72,6 +72,7 @@ def _load():
         "rom_clear_status": [vp, vp],
         "fom_residual_vjp": [vp, vp, vp, d, vp, vp, vp, vp],
         "fom_step_vjp": [vp, vp, d, vp, vp, vp],
+        "rom_rollout_vjp": [vp, vp, i32, d, i32, vp, vp, vp],
         "rom_query": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
                       ctypes.POINTER(i32)],
         "rom_profile": [vp, i32, i32, vp, ctypes.POINTER(d), vp],
@@ -88,7 +89,8 @@ def _load():
 LIB = _load()
 SYMBOLS = ("rom_create", "rom_destroy", "fom_residual", "fom_step", "isvd_update", "rom_rebuild",
            "rom_step", "rom_get", "rom_set", "rom_get_status", "rom_clear_status",
-           "fom_residual_vjp", "fom_step_vjp", "rom_query", "rom_profile", "rom_last_error")
+           "fom_residual_vjp", "fom_step_vjp", "rom_rollout_vjp", "rom_query", "rom_profile",
+           "rom_last_error")
 PROF_RESIDUAL, PROF_GALERKIN_PASS, PROF_ISVD_PROJECT, PROF_RESIDUAL_VJP, PROF_FOM_STEP = range(5)
 
 
@@ -194,6 +196,12 @@ class RomBatch:
         _check(LIB.fom_step_vjp(self.h, _ptr(q), float(dt), _ptr(gbar), _ptr(out), _stream()))
         return out
 
+    def rollout_vjp(self, q0, n_steps, dt, gbar, n_ckpt=0, out=None):
+        out = self._new(self.total_dof) if out is None else out
+        _check(LIB.rom_rollout_vjp(self.h, _ptr(q0), int(n_steps), float(dt), int(n_ckpt),
+                                   _ptr(gbar), _ptr(out), _stream()))
+        return out
+
     # ---- reduced model
     def isvd_update(self, y):
         _check(LIB.isvd_update(self.h, _ptr(y), _stream()))
@@ -251,3 +259,42 @@ class RomBatch:
 
     def clear_status(self):
         _check(LIB.rom_clear_status(self.h, _stream()))
+
+
+class FomResidual(torch.autograd.Function):
+    """f(q) of a handle's batch as a differentiable op; the backward pass is the
+    hand-written adjoint J_f(q)^T g (fom_residual_vjp)."""
+
+    @staticmethod
+    def forward(ctx, q, handle):
+        q = q.contiguous()
+        ctx.save_for_backward(q)
+        ctx.handle = handle
+        return handle.fom_residual(q)
+
+    @staticmethod
+    def backward(ctx, g):
+        (q,) = ctx.saved_tensors
+        gq, _ = ctx.handle.fom_residual_vjp(q, g.contiguous())
+        return gq, None
+
+
+class FomRollout(torch.autograd.Function):
+    """q^T after n_steps backward-Euler steps of size dt from q0 (fom_step); the
+    backward pass is the checkpointed rollout adjoint (rom_rollout_vjp)."""
+
+    @staticmethod
+    def forward(ctx, q0, handle, n_steps, dt, n_ckpt=0):
+        q0 = q0.contiguous()
+        q = q0.clone()
+        for _ in range(int(n_steps)):
+            handle.fom_step(q, dt, out=q)
+        ctx.save_for_backward(q0)
+        ctx.handle, ctx.n_steps, ctx.dt, ctx.n_ckpt = handle, int(n_steps), float(dt), int(n_ckpt)
+        return q
+
+    @staticmethod
+    def backward(ctx, g):
+        (q0,) = ctx.saved_tensors
+        gq0 = ctx.handle.rollout_vjp(q0, ctx.n_steps, ctx.dt, g.contiguous(), ctx.n_ckpt)
+        return gq0, None, None, None, None

@@ -58,17 +58,24 @@ def test_residual_parity(problem, precision):
     assert not (h.status() & 4).any()      # nothing non-finite
 
 
+def _step_dt(problem):
+    return {W.BURGERS: 2e-4, W.REACT: 1e-4}.get(problem, 0.064 / 512)
+
+
 @pytest.mark.parametrize("precision", [W.F64, W.F32])
-@pytest.mark.parametrize("problem", [W.BURGERS, W.EULER_RUSANOV, W.EULER_HLLC])
+@pytest.mark.parametrize("problem", PROBLEMS)
 def test_fom_step_parity(problem, precision):
+    """Backward-Euler step by Newton with the block-tridiagonal solver (NV = 1, 3
+    and the 12 x 12 blocks of the reacting model) against the oracle's Newton
+    with a sparse direct solve."""
     import gpu_common as G
     import torch
-    cells = [300, 517, 64]
+    cells = [96, 130, 64] if problem == W.REACT else [300, 517, 64]
     w = _workload(problem, cells, precision)
     w.newton_tol = 1e-10 if precision == W.F64 else 1e-5
     h = _handle(w)
     q = G.rounded(W.random_state(problem, cells, seed=3, scale=0.5), precision)
-    dt = 2e-4 if problem == W.BURGERS else 0.064 / 512
+    dt = _step_dt(problem)
     it = torch.zeros(w.n_inst, dtype=torch.int32, device="cuda")
     q1 = G.host(h.fom_step(G.to_dev(q, precision), dt, iters=it))
     its = it.cpu().numpy()
@@ -152,16 +159,16 @@ def test_residual_vjp_parity(problem, precision):
 
 
 @pytest.mark.parametrize("precision", [W.F64, W.F32])
-@pytest.mark.parametrize("problem", [W.BURGERS, W.EULER_RUSANOV, W.EULER_HLLC])
+@pytest.mark.parametrize("problem", PROBLEMS)
 def test_fom_step_vjp_parity(problem, precision):
     import gpu_common as G
     import scipy.sparse.linalg as spla
-    cells = [300, 517, 33]
+    cells = [96, 130, 33] if problem == W.REACT else [300, 517, 33]
     w = _workload(problem, cells, precision)
     h = _handle(w)
     q = G.rounded(W.random_state(problem, cells, seed=7), precision)
     g = G.rounded(np.random.default_rng(8).normal(size=q.shape), precision)
-    dt = 2e-4 if problem == W.BURGERS else 0.064 / 512
+    dt = _step_dt(problem)
     out = G.host(h.fom_step_vjp(G.to_dev(q, precision), dt, G.to_dev(g, precision)))
     off = w.offsets()
     for b in range(w.n_inst):
@@ -198,3 +205,96 @@ def test_fom_coarse_step_batched_burgers_instances_fp32():
         q = G.rounded(qg, W.F32)
     print("iterations", it.cpu().numpy(), "flags", h.status())
     assert not (h.status() & 1).any()
+
+
+def _rollout_case(problem, precision):
+    cells = [96, 130] if problem == W.BURGERS else [96, 60]
+    w = _workload(problem, cells, precision)
+    w.newton_tol = 1e-12 if precision == W.F64 else 1e-5
+    w.newton_max = 20
+    q = W.random_state(problem, cells, seed=51, scale=0.5)
+    dt = 2e-3 if problem == W.BURGERS else 0.064 / 96
+    return w, G_rounded(q, precision), dt
+
+
+def G_rounded(q, precision):
+    import gpu_common as G
+    return G.rounded(q, precision)
+
+
+@pytest.mark.parametrize("precision", [W.F64, W.F32])
+@pytest.mark.parametrize("problem", [W.BURGERS, W.EULER_RUSANOV])
+def test_rollout_vjp_parity_and_checkpoint_invariance(problem, precision):
+    """Checkpointed rollout adjoint against the oracle's store-everything
+    adjoint; the checkpoint spacing must not change a single bit."""
+    import gpu_common as G
+    w, q0, dt = _rollout_case(problem, precision)
+    T = 12
+    h = _handle(w)
+    gbar = G.rounded(np.random.default_rng(52).normal(size=q0.shape), precision)
+    qd, gd = G.to_dev(q0, precision), G.to_dev(gbar, precision)
+    outs = [G.host(h.rollout_vjp(qd, T, dt, gd, n_ckpt=c)) for c in (0, 1, T, 5)]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    off = w.offsets()
+    for b in range(w.n_inst):
+        sl = slice(off[b], off[b + 1])
+        ref = F.be_rollout_vjp(problem, q0[sl], dt, T, w.phys[b], gbar[sl], tol=1e-13, max_it=30)
+        err = G.relerr(outs[0][sl], ref)
+        assert err < (1e-10 if precision == W.F64 else 1e-5), (b, err)
+    assert not (h.status() & (1 | 4 | 16)).any()
+
+
+def test_rollout_vjp_central_differences_fp64():
+    """<dL/dq0, v> from the GPU adjoint against central differences of GPU
+    rollouts (h = 1e-6), L = <gbar, q^T>, on the 2-instance Burgers batch."""
+    import gpu_common as G
+    import torch
+    w, q0, dt = _rollout_case(W.BURGERS, W.F64)
+    T = 10
+    h = _handle(w)
+    rng = np.random.default_rng(53)
+    gbar = rng.normal(size=q0.shape)
+    g0 = G.host(h.rollout_vjp(G.to_dev(q0, W.F64), T, dt, G.to_dev(gbar, W.F64)))
+    off = w.offsets()
+
+    def roll(q):
+        qd = G.to_dev(q, W.F64)
+        for _ in range(T):
+            h.fom_step(qd, dt, out=qd)
+        return G.host(qd)
+
+    eps = 1e-6
+    for _ in range(4):
+        v = rng.normal(size=q0.shape)
+        qp, qm = roll(q0 + eps * v), roll(q0 - eps * v)
+        for b in range(w.n_inst):
+            sl = slice(off[b], off[b + 1])
+            fd = (gbar[sl] @ qp[sl] - gbar[sl] @ qm[sl]) / (2 * eps)
+            an = g0[sl] @ v[sl]
+            assert abs(an - fd) <= 1e-6 * max(1.0, abs(fd)), (b, an, fd)
+
+
+def test_autograd_functions_use_the_adjoint_kernels():
+    """FomRollout / FomResidual backward passes equal the adjoint entry points
+    and the oracle's J^T w."""
+    import gpu_common as G
+    import torch
+    from paper_2605_28684_amd import romhip as R
+    w, q0, dt = _rollout_case(W.EULER_RUSANOV, W.F64)
+    h = _handle(w)
+    q = G.to_dev(q0, W.F64).requires_grad_(True)
+    gbar = torch.as_tensor(np.random.default_rng(54).normal(size=q0.shape), device="cuda")
+    qT = R.FomRollout.apply(q, h, 6, dt, 0)
+    (gq,) = torch.autograd.grad((qT * gbar).sum(), q)
+    ref = h.rollout_vjp(G.to_dev(q0, W.F64), 6, dt, gbar)
+    assert torch.equal(gq, ref)
+    q2 = G.to_dev(q0, W.F64).requires_grad_(True)
+    f = R.FomResidual.apply(q2, h)
+    (gf,) = torch.autograd.grad((f * gbar).sum(), q2)
+    off = w.offsets()
+    gb = G.host(gbar)
+    for b in range(w.n_inst):
+        sl = slice(off[b], off[b + 1])
+        ref = F.vjp_f(W.EULER_RUSANOV, q0[sl], gb[sl], w.phys[b])
+        assert G.relerr(G.host(gf)[sl], ref) < 1e-11, b

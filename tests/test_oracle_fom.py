@@ -240,3 +240,34 @@ def test_burgers_jacobian_column_sums_vanish():
     nz = np.abs(J) > 0
     i, j = np.nonzero(nz)
     assert np.all(((j - i) % 40 <= 1) | ((i - j) % 40 <= 1))
+
+
+@pytest.mark.parametrize("problem", [F.BURGERS, F.EULER_RUSANOV])
+def test_rollout_vjp_matches_central_differences(problem):
+    """<dL/dq0, v> against central differences of L = <gbar, q^T> over a short
+    backward-Euler rollout with a tight Newton tolerance (pins the adjoint
+    recursion, including the transposes and the step order)."""
+    rng = np.random.default_rng(41)
+    if problem == F.BURGERS:
+        n, phys, dt = 48, dict(nu=0.01), 2e-3
+        x = (np.arange(n) + 0.5) / n
+        q0 = 0.5 + 0.8 * np.sin(2 * np.pi * x)
+    else:
+        n, phys, dt = 40, dict(gamma=1.4), 0.064 / 40
+        x = (np.arange(n) + 0.5) / n
+        rho = 1.0 + 0.3 * np.sin(2 * np.pi * x)
+        u = 0.2 * np.cos(2 * np.pi * x)
+        p = 1.0 + 0.2 * np.sin(4 * np.pi * x)
+        q0 = np.stack([rho, rho * u, p / 0.4 + 0.5 * rho * u * u], axis=1).reshape(-1)
+    T = 6
+    gbar = rng.normal(size=q0.shape)
+    g0 = F.be_rollout_vjp(problem, q0, dt, T, phys, gbar, tol=1e-13, max_it=30)
+
+    def L(q):
+        return gbar @ F.fom_trajectory(problem, q, dt, T, phys, tol=1e-13, max_it=30)[:, -1]
+
+    h = 1e-6
+    for _ in range(3):
+        v = rng.normal(size=q0.shape)
+        fd = (L(q0 + h * v) - L(q0 - h * v)) / (2 * h)
+        assert abs(g0 @ v - fd) <= 1e-6 * max(1.0, abs(fd)), (g0 @ v, fd)
