@@ -117,6 +117,7 @@ def profile_only(args, torch, W, R):
         we = W.euler_adjoint_f32(n_inst=64, n=262144)
         he = R.RomBatch(we, q0=None, use_graph=False)
         qe = torch.as_tensor(we.q0, dtype=torch.float32, device="cuda")
+        he.autotune(R.TUNE_RESIDUAL, qe)
         ms = he.profile(R.PROF_RESIDUAL, reps, qe)
         he.close()
         log("residual: %.5f ms per launch" % ms)
@@ -215,6 +216,7 @@ def main():
         we = W.euler_adjoint_f32(n_inst=64, n=262144)
         he = R.RomBatch(we, q0=None, use_graph=False)
         qe = torch.as_tensor(we.q0, dtype=torch.float32, device="cuda")
+        shape = he.autotune(R.TUNE_RESIDUAL, qe)
         he.profile(R.PROF_RESIDUAL, 3, qe)
         ms_res = he.profile(R.PROF_RESIDUAL, 50, qe)
         cells = 64 * 262144
@@ -222,7 +224,8 @@ def main():
         res_gbs = res_bytes / (ms_res * 1e-3) / 1e9
         fom = dict(workload="euler_rusanov_64x262144_f32", ms_per_launch=round(ms_res, 5),
                    cell_updates_per_s=cells / (ms_res * 1e-3), achieved_GBs=round(res_gbs, 1),
-                   frac_hbm=round(res_gbs / HBM_PEAK_GBS, 4), bytes_per_launch=res_bytes)
+                   frac_hbm=round(res_gbs / HBM_PEAK_GBS, 4), bytes_per_launch=res_bytes,
+                   tuned_shape=int(shape))
         ms_vjp = he.profile(R.PROF_RESIDUAL_VJP, 20, qe)
         fom["vjp_ms_per_launch"] = round(ms_vjp, 5)
         fom["vjp_frac_hbm"] = round(cells * 3 * 4 * 3 / (ms_vjp * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)

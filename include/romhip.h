@@ -235,6 +235,27 @@ rom_status rom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, double
                            int32_t n_ckpt, const void* gbar, void* gq0, void* stream);
 
 /*
+ * Autotuning of launch shapes.  Only shapes that cannot change results are
+ * tuned: for ROM_TUNE_RESIDUAL, the streaming residual of the Euler problems
+ * (fom_residual, and the residual evaluations inside the grid-wide Newton
+ * step) can use tiles of 1024 or 512 cells (4 or 2 cells per thread) and a
+ * persistent grid of 1..6 resident blocks per compute unit; every cell is
+ * computed by the same arithmetic in every shape, so outputs are bitwise
+ * identical.  Other problems have a single candidate.
+ *
+ * rom_autotune - time every candidate on the given stream (2 warm-up and 5
+ *   timed residual evaluations of q each, HIP events) and keep the fastest for
+ *   the handle; *choice (optional) receives its index.  q: device
+ *   T[total_dof]; the handle's state is not modified.  Synchronises the stream.
+ * rom_set_tuning - force candidate `choice` (choice < 0 only queries);
+ *   *n_candidates (optional) receives the number of candidates.
+ * Errors: ROM_E_INVAL (NULL handle or q, unknown target, choice out of range).
+ */
+enum { ROM_TUNE_RESIDUAL = 0 };
+rom_status rom_autotune(rom_handle h, int32_t what, const void* q, int32_t* choice, void* stream);
+rom_status rom_set_tuning(rom_handle h, int32_t what, int32_t choice, int32_t* n_candidates);
+
+/*
  * rom_profile - time one stage of the hot path in isolation: the stage is
  * launched reps times between two HIP events recorded on the given stream and
  * the mean milliseconds per launch are written to *ms.  The handle's reduced

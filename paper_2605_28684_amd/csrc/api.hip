@@ -147,7 +147,7 @@ rom_status alloc(T** p, size_t count) {
   } while (0)
 
 void free_all(rom_batch* h) {
-  void* ps[] = {h->d_dof_off, h->d_cell_off, h->d_phys, h->d_tiles, h->d_btiles, h->d_ptiles, h->d_ptile_first,
+  void* ps[] = {h->d_dof_off, h->d_cell_off, h->d_phys, h->d_tiles, h->d_btiles, h->d_btiles2, h->d_ptiles, h->d_ptile_first,
                 h->Phi, h->sigma, h->a, h->a_prev, h->q_ref, h->d_var, h->y_corr, h->flags, h->P,
                 h->M, h->mesh_phi, h->mesh_qref, h->chosen, h->part, h->red, h->ubar, h->lmat,
                 h->active, h->iters, h->norms, h->rstate, h->qtmp, h->mpart, h->fq, h->fq_prev, h->vjp_tmp,
@@ -172,7 +172,7 @@ rom_status setup(rom_batch* h) {
   h->total_cells = h->cell_off[B];
   h->total_dof = h->dof_off[B];
   // stencil tiles (cells) and pass tiles (basis rows)
-  std::vector<Tile> tiles, ptiles, btiles;
+  std::vector<Tile> tiles, ptiles, btiles, btiles2;
   h->ptile_first.assign(B + 1, 0);
   for (int b = 0; b < B; ++b) {
     const int64_t nb = h->n_cells[b], base = h->dof_off[b];
@@ -180,6 +180,8 @@ rom_status setup(rom_batch* h) {
       tiles.push_back(Tile{b, 0, c0, std::min<int64_t>(kTile, nb - c0), nb, base});
     for (int64_t c0 = 0; c0 < nb; c0 += kBigTile)
       btiles.push_back(Tile{b, 0, c0, std::min<int64_t>(kBigTile, nb - c0), nb, base});
+    for (int64_t c0 = 0; c0 < nb; c0 += kBigTile / 2)
+      btiles2.push_back(Tile{b, 0, c0, std::min<int64_t>(kBigTile / 2, nb - c0), nb, base});
     const int64_t rows = nb * h->nv;
     h->ptile_first[b] = (int)ptiles.size();
     for (int64_t r0 = 0; r0 < rows; r0 += kPassRows)
@@ -188,6 +190,7 @@ rom_status setup(rom_batch* h) {
   h->ptile_first[B] = (int)ptiles.size();
   h->n_tiles = (int)tiles.size();
   h->n_btiles = (int)btiles.size();
+  h->n_btiles2 = (int)btiles2.size();
   h->n_ptiles = (int)ptiles.size();
   const size_t es = h->esz;
   const int r = c.r;
@@ -196,6 +199,7 @@ rom_status setup(rom_batch* h) {
   ROM_TRY(alloc(&h->d_phys, h->phys.size()));
   ROM_TRY(alloc(&h->d_tiles, tiles.size()));
   ROM_TRY(alloc(&h->d_btiles, btiles.size()));
+  ROM_TRY(alloc(&h->d_btiles2, btiles2.size()));
   ROM_TRY(alloc(&h->d_ptiles, ptiles.size()));
   ROM_TRY(alloc(&h->d_ptile_first, B + 1));
   ROM_HIP_CHECK(hipMemcpy(h->d_dof_off, h->dof_off.data(), 8 * (B + 1), hipMemcpyHostToDevice));
@@ -203,6 +207,13 @@ rom_status setup(rom_batch* h) {
   ROM_HIP_CHECK(hipMemcpy(h->d_phys, h->phys.data(), 8 * h->phys.size(), hipMemcpyHostToDevice));
   ROM_HIP_CHECK(hipMemcpy(h->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice));
   ROM_HIP_CHECK(hipMemcpy(h->d_btiles, btiles.data(), sizeof(Tile) * btiles.size(), hipMemcpyHostToDevice));
+  ROM_HIP_CHECK(hipMemcpy(h->d_btiles2, btiles2.data(), sizeof(Tile) * btiles2.size(), hipMemcpyHostToDevice));
+  {
+    int dev = 0, ncu = 0;
+    ROM_HIP_CHECK(hipGetDevice(&dev));
+    ROM_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    h->n_cu = ncu > 0 ? ncu : 256;
+  }
   ROM_HIP_CHECK(hipMemcpy(h->d_ptiles, ptiles.data(), sizeof(Tile) * ptiles.size(), hipMemcpyHostToDevice));
   ROM_HIP_CHECK(hipMemcpy(h->d_ptile_first, h->ptile_first.data(), sizeof(int) * (B + 1),
                           hipMemcpyHostToDevice));
@@ -603,6 +614,49 @@ rom_status rom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, double
   }
   ROM_TRY(copy_words(ga, gq0, st, s));
   ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+rom_status rom_autotune(rom_handle h, int32_t what, const void* q, int32_t* choice,
+                        void* stream) {
+  ROM_REQUIRE(h && q, ROM_E_INVAL, "handle and q are required");
+  ROM_REQUIRE(what == ROM_TUNE_RESIDUAL, ROM_E_INVAL, "unknown tuning target");
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  const int n = residual_shape_count(h);
+  int best = 0;
+  if (n > 1) {
+    hipEvent_t e0, e1;
+    ROM_HIP_CHECK(hipEventCreate(&e0));
+    ROM_HIP_CHECK(hipEventCreate(&e1));
+    float tbest = 0.f;
+    for (int i = 0; i < n; ++i) {
+      h->tune_residual = i;
+      for (int w = 0; w < 2; ++w) ROM_TRY(launch_residual(h, q, nullptr, 0.0, h->vjp_tmp, s));
+      ROM_HIP_CHECK(hipEventRecord(e0, s));
+      for (int k = 0; k < 5; ++k) ROM_TRY(launch_residual(h, q, nullptr, 0.0, h->vjp_tmp, s));
+      ROM_HIP_CHECK(hipEventRecord(e1, s));
+      ROM_HIP_CHECK(hipEventSynchronize(e1));
+      float t = 0.f;
+      ROM_HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
+      if (i == 0 || t < tbest) { tbest = t; best = i; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  h->tune_residual = best;
+  if (choice) *choice = best;
+  return ROM_OK;
+}
+
+rom_status rom_set_tuning(rom_handle h, int32_t what, int32_t choice, int32_t* n_candidates) {
+  ROM_REQUIRE(h, ROM_E_INVAL, "handle is required");
+  ROM_REQUIRE(what == ROM_TUNE_RESIDUAL, ROM_E_INVAL, "unknown tuning target");
+  const int n = residual_shape_count(h);
+  if (n_candidates) *n_candidates = n;
+  if (choice < 0) return ROM_OK;  // query only
+  ROM_REQUIRE(choice < n, ROM_E_INVAL, "tuning choice out of range");
+  h->tune_residual = choice;
   return ROM_OK;
 }
 

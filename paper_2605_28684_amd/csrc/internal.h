@@ -93,6 +93,10 @@ struct rom_batch {
   int n_tiles = 0;
   romhip::Tile* d_btiles = nullptr;  // kBigTile-cell tiles
   int n_btiles = 0;
+  romhip::Tile* d_btiles2 = nullptr; // kBigTile/2-cell tiles
+  int n_btiles2 = 0;
+  int n_cu = 256;                    // compute units of the device
+  int tune_residual = 0;             // chosen launch shape of the streaming residual
   romhip::Tile* d_ptiles = nullptr;  // row tiles of kPassRows basis rows
   int n_ptiles = 0;
   std::vector<int> ptile_first;      // first row tile of each instance [n_inst+1]
@@ -183,6 +187,12 @@ rom_status launch_project_state(rom_batch* h, const void* q, hipStream_t s);  //
 rom_status launch_rom_fine_step(rom_batch* h, hipStream_t s);
 // Whole-Newton-loop-per-workgroup backward-Euler step for batches of small
 // scalar instances (see fomblock.hip); fom_block_ok tells whether it applies.
+struct ResidualShape {
+  int cpt;            // cells per thread (tile = 256 cpt cells)
+  int blocks_per_cu;  // persistent grid = blocks_per_cu x compute units
+};
+int residual_shape_count(const rom_batch* h);
+ResidualShape residual_shape(const rom_batch* h, int i);
 bool fom_block_ok(const rom_batch* h);
 rom_status launch_fom_block(rom_batch* h, const void* q_prev, double dt, void* q_out,
                             int32_t* iters, hipStream_t s);

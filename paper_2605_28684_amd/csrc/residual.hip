@@ -99,8 +99,8 @@ __global__ __launch_bounds__(kTile) void k_residual(
 }
 
 // Euler residual, persistent and register-resident: a block of 256 threads
-// walks kBigTile-cell tiles (tile += gridDim.x); thread t owns cells t, t+256,
-// t+512, t+768 of a tile, loads each cell's three conserved values with one
+// walks tiles of 256 CPT cells (tile += gridDim.x); thread t owns cells t,
+// t+256, ... of a tile, loads each cell's three conserved values with one
 // 12-byte load straight into registers, and computes the cell's primitives
 // there (floored density, velocity, pressure, sound speed, flux terms).  LDS
 // only exchanges what neighbours need (structure-of-arrays, conflict-free):
@@ -110,18 +110,18 @@ __global__ __launch_bounds__(kTile) void k_residual(
 // sod_rusanov_flux / sod_rusanov_speed (Rusanov) or Toro's HLLC with Davis
 // speeds.  Same contract as k_residual.
 constexpr int kEulerThreads = 256;
-constexpr int kCellsPerThread = kBigTile / kEulerThreads;
 
 template <typename T>
 struct Cell3 { T v[3]; };
 
-template <typename T, bool HLLC>
+template <typename T, bool HLLC, int CPT>
 __global__ __launch_bounds__(kEulerThreads) void k_residual_euler(
     const Tile* __restrict__ tiles, int n_tiles, const double* __restrict__ phys, int nphys,
     const T* __restrict__ q, const T* __restrict__ qprev, T dt, T* __restrict__ out,
     uint32_t* flags, uint64_t* norms, const int32_t* active) {
   constexpr int NA = 8;  // rho, m, E, rf, u, p, c, (F1 or 1/rf)
-  constexpr int LA = kBigTile + 2, LH = kBigTile + 1;
+  constexpr int kCellsPerThread = CPT, TILE = kEulerThreads * CPT;
+  constexpr int LA = TILE + 2, LH = TILE + 1;
   __shared__ T sa[NA * LA];
   __shared__ T sH[3 * LH];
   const int tid = threadIdx.x;
@@ -520,17 +520,23 @@ template <typename T>
 static rom_status residual_t(rom_batch* h, const void* q, const void* q_prev, double dt, void* out,
                              uint64_t* norms, const int32_t* active, hipStream_t s) {
   if (h->cfg.problem == ROM_EULER_RUSANOV || h->cfg.problem == ROM_EULER_HLLC) {
-    // persistent grid: a few blocks per CU, each walking tiles
-    // (LDS use allows three FP32 blocks or one FP64 block per CU)
-    const int grid = std::min(h->n_btiles, 256 * (sizeof(T) == 4 ? 3 : 1));
-    if (h->cfg.problem == ROM_EULER_HLLC)
-      hipLaunchKernelGGL((k_residual_euler<T, true>), dim3(grid), dim3(kEulerThreads), 0, s,
-                         h->d_btiles, h->n_btiles, h->d_phys, h->cfg.n_phys, (const T*)q,
-                         (const T*)q_prev, (T)dt, (T*)out, h->flags, norms, active);
-    else
-      hipLaunchKernelGGL((k_residual_euler<T, false>), dim3(grid), dim3(kEulerThreads), 0, s,
-                         h->d_btiles, h->n_btiles, h->d_phys, h->cfg.n_phys, (const T*)q,
-                         (const T*)q_prev, (T)dt, (T*)out, h->flags, norms, active);
+    // persistent grid of (blocks per CU) x CUs walking tiles of 256 CPT cells;
+    // the shape comes from the autotuner (results do not depend on it)
+    const ResidualShape sh = residual_shape(h, h->tune_residual);
+    const Tile* tl = sh.cpt == 4 ? h->d_btiles : h->d_btiles2;
+    const int nt = sh.cpt == 4 ? h->n_btiles : h->n_btiles2;
+    const int grid = std::max(1, std::min(nt, h->n_cu * sh.blocks_per_cu));
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(kEulerThreads), 0, s, tl, nt, h->d_phys,
+                         h->cfg.n_phys, (const T*)q, (const T*)q_prev, (T)dt, (T*)out, h->flags,
+                         norms, active);
+    };
+    const bool hllc = h->cfg.problem == ROM_EULER_HLLC;
+    if (sh.cpt == 4) {
+      if (hllc) go(k_residual_euler<T, true, 4>); else go(k_residual_euler<T, false, 4>);
+    } else {
+      if (hllc) go(k_residual_euler<T, true, 2>); else go(k_residual_euler<T, false, 2>);
+    }
     return ROM_OK;
   }
   return with_model<T>(h, [&](auto tag) -> rom_status {
@@ -559,6 +565,24 @@ rom_status launch_residual_norm(rom_batch* h, const void* q, const void* q_prev,
                       : residual_t<float>(h, q, q_prev, dt, out, norms, h->active, s);
   ROM_HIP_CHECK(hipGetLastError());
   return st;
+}
+
+// Launch shapes of the streaming Euler residual that the autotuner chooses
+// from: (cells per thread, resident blocks per CU), limited by LDS (a 1024-cell
+// FP32 tile uses 45 KB, a 512-cell one 23 KB; FP64 doubles that).
+static const ResidualShape kShapesF32[] = {{4, 3}, {4, 2}, {4, 1}, {2, 6}, {2, 4}, {2, 2}};
+static const ResidualShape kShapesF64[] = {{4, 1}, {2, 3}, {2, 2}, {2, 1}};
+
+int residual_shape_count(const rom_batch* h) {
+  if (h->cfg.problem != ROM_EULER_RUSANOV && h->cfg.problem != ROM_EULER_HLLC) return 1;
+  return h->cfg.precision == ROM_F32 ? (int)(sizeof(kShapesF32) / sizeof(kShapesF32[0]))
+                                     : (int)(sizeof(kShapesF64) / sizeof(kShapesF64[0]));
+}
+
+ResidualShape residual_shape(const rom_batch* h, int i) {
+  const int n = residual_shape_count(h);
+  if (i < 0 || i >= n) i = 0;
+  return h->cfg.precision == ROM_F32 ? kShapesF32[i] : kShapesF64[i];
 }
 
 template <typename T>

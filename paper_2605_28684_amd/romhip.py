@@ -73,6 +73,8 @@ def _load():
         "fom_residual_vjp": [vp, vp, vp, d, vp, vp, vp, vp],
         "fom_step_vjp": [vp, vp, d, vp, vp, vp],
         "rom_rollout_vjp": [vp, vp, i32, d, i32, vp, vp, vp],
+        "rom_autotune": [vp, i32, vp, ctypes.POINTER(i32), vp],
+        "rom_set_tuning": [vp, i32, i32, ctypes.POINTER(i32)],
         "rom_query": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
                       ctypes.POINTER(i32)],
         "rom_profile": [vp, i32, i32, vp, ctypes.POINTER(d), vp],
@@ -89,8 +91,9 @@ def _load():
 LIB = _load()
 SYMBOLS = ("rom_create", "rom_destroy", "fom_residual", "fom_step", "isvd_update", "rom_rebuild",
            "rom_step", "rom_get", "rom_set", "rom_get_status", "rom_clear_status",
-           "fom_residual_vjp", "fom_step_vjp", "rom_rollout_vjp", "rom_query", "rom_profile",
-           "rom_last_error")
+           "fom_residual_vjp", "fom_step_vjp", "rom_rollout_vjp", "rom_autotune",
+           "rom_set_tuning", "rom_query", "rom_profile", "rom_last_error")
+TUNE_RESIDUAL = 0
 PROF_RESIDUAL, PROF_GALERKIN_PASS, PROF_ISVD_PROJECT, PROF_RESIDUAL_VJP, PROF_FOM_STEP = range(5)
 
 
@@ -245,6 +248,18 @@ class RomBatch:
             raise ValueError("expected %d elements, got %d" % (n, src.numel()))
         _check(LIB.rom_set(self.h, what, _ptr(src), _stream()))
         torch.cuda.current_stream().synchronize()
+
+    def autotune(self, what, q):
+        """Pick the fastest result-invariant launch shape; returns its index."""
+        c = ctypes.c_int32()
+        _check(LIB.rom_autotune(self.h, int(what), _ptr(q), ctypes.byref(c), _stream()))
+        return c.value
+
+    def set_tuning(self, what, choice):
+        """Force a launch shape (choice < 0 only queries); returns the candidate count."""
+        n = ctypes.c_int32()
+        _check(LIB.rom_set_tuning(self.h, int(what), int(choice), ctypes.byref(n)))
+        return n.value
 
     def profile(self, stage, reps, q=None):
         """Mean milliseconds per launch of one hot-path stage (HIP events on the current stream)."""

@@ -298,3 +298,32 @@ def test_autograd_functions_use_the_adjoint_kernels():
         sl = slice(off[b], off[b + 1])
         ref = F.vjp_f(W.EULER_RUSANOV, q0[sl], gb[sl], w.phys[b])
         assert G.relerr(G.host(gf)[sl], ref) < 1e-11, b
+
+
+@pytest.mark.parametrize("precision", [W.F64, W.F32])
+@pytest.mark.parametrize("problem", [W.EULER_RUSANOV, W.EULER_HLLC])
+def test_residual_autotune_shapes_are_result_invariant(problem, precision):
+    """Every launch shape the autotuner may pick gives bitwise-identical f(q) and
+    BE residuals (ragged batch with partial tiles); the tuned choice is valid."""
+    import gpu_common as G
+    from paper_2605_28684_amd import romhip as R
+    cells = [5000, 1500, 700, 33]
+    w = _workload(problem, cells, precision)
+    h = _handle(w)
+    q = G.to_dev(G.rounded(W.random_state(problem, cells, seed=61), precision), precision)
+    qp = G.to_dev(G.rounded(W.random_state(problem, cells, seed=62), precision), precision)
+    n = h.set_tuning(R.TUNE_RESIDUAL, -1)
+    assert n >= 2
+    ref = ref_be = None
+    for c in range(n):
+        h.set_tuning(R.TUNE_RESIDUAL, c)
+        f = G.host(h.fom_residual(q))
+        rb = G.host(h.fom_residual(q, qp, 1e-3))
+        if ref is None:
+            ref, ref_be = f, rb
+        else:
+            assert np.array_equal(f, ref), c
+            assert np.array_equal(rb, ref_be), c
+    c = h.autotune(R.TUNE_RESIDUAL, q)
+    assert 0 <= c < n
+    assert np.array_equal(G.host(h.fom_residual(q)), ref)
