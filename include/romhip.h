@@ -238,8 +238,9 @@ rom_status rom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, double
  * Autotuning of launch shapes.  Only shapes that cannot change results are
  * tuned: for ROM_TUNE_RESIDUAL, the streaming residual of the Euler problems
  * (fom_residual, and the residual evaluations inside the grid-wide Newton
- * step) can use tiles of 1024 or 512 cells (4 or 2 cells per thread) and a
- * persistent grid of 1..6 resident blocks per compute unit; every cell is
+ * step) can use tiles of 1024, 512 or 256 cells (4, 2 or 1 cells per thread),
+ * a persistent grid of 1..12 resident blocks per compute unit and plain or
+ * non-temporal loads and stores of the streamed state; every cell is
  * computed by the same arithmetic in every shape, so outputs are bitwise
  * identical.  Other problems have a single candidate.
  *

@@ -190,6 +190,7 @@ rom_status launch_rom_fine_step(rom_batch* h, hipStream_t s);
 struct ResidualShape {
   int cpt;            // cells per thread (tile = 256 cpt cells)
   int blocks_per_cu;  // persistent grid = blocks_per_cu x compute units
+  int nt;             // non-temporal loads / stores of the streamed state
 };
 int residual_shape_count(const rom_batch* h);
 ResidualShape residual_shape(const rom_batch* h, int i);

@@ -7,7 +7,14 @@
 // coalesced element loads (the halo wraps for periodic models and copies the
 // end cell for zero-gradient walls), face fluxes are computed once per face
 // into LDS, and results are staged back through LDS for coalesced stores.
+// No multiply-add contraction: every product and sum is rounded on its own, so
+// every launch shape and template instance of a kernel performs the same IEEE
+// operations (the autotuner relies on bitwise-identical results; the compiler
+// may otherwise fuse or not fuse a multiply-add differently per instance).
+#pragma clang fp contract(off)
+
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 #include "physics.h"
@@ -114,7 +121,41 @@ constexpr int kEulerThreads = 256;
 template <typename T>
 struct Cell3 { T v[3]; };
 
-template <typename T, bool HLLC, int CPT>
+// Reciprocal and square root of the streaming Euler residual with a fixed
+// instruction choice: in FP32 the hardware v_rcp_f32 / v_sqrt_f32 (1 ulp; the
+// arguments are normal numbers: densities and pressures are floored at 1e-10),
+// in FP64 correctly rounded.  Left to the compiler, the FP32 lowering of a
+// division depends on the surrounding code, which would make results differ
+// between launch shapes.
+DEV float rcp_s(float x) { return __builtin_amdgcn_rcpf(x); }
+DEV double rcp_s(double x) { return 1.0 / x; }
+DEV float sqrt_s(float x) { return __builtin_amdgcn_sqrtf(x); }
+DEV double sqrt_s(double x) { return sqrt(x); }
+
+// One cell's three conserved values; NT = non-temporal (streamed, not kept in
+// the caches) for data that is touched exactly once.
+template <bool NT, typename T>
+DEV Cell3<T> load3(const T* p) {
+  if constexpr (NT) {
+    Cell3<T> c;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) c.v[v] = __builtin_nontemporal_load(p + v);
+    return c;
+  } else {
+    return *reinterpret_cast<const Cell3<T>*>(p);
+  }
+}
+template <bool NT, typename T>
+DEV void store3(T* p, const Cell3<T>& c) {
+  if constexpr (NT) {
+#pragma unroll
+    for (int v = 0; v < 3; ++v) __builtin_nontemporal_store(c.v[v], p + v);
+  } else {
+    *reinterpret_cast<Cell3<T>*>(p) = c;
+  }
+}
+
+template <typename T, bool HLLC, int CPT, bool NT>
 __global__ __launch_bounds__(kEulerThreads) void k_residual_euler(
     const Tile* __restrict__ tiles, int n_tiles, const double* __restrict__ phys, int nphys,
     const T* __restrict__ q, const T* __restrict__ qprev, T dt, T* __restrict__ out,
@@ -134,7 +175,7 @@ __global__ __launch_bounds__(kEulerThreads) void k_residual_euler(
 #pragma unroll
     for (int j = 0; j < kCellsPerThread; ++j) {
       const int lc = tid + kEulerThreads * j;
-      if (lc < t.ncell) dst[j] = *reinterpret_cast<const Cell3<T>*>(q + t.base + (t.cell0 + lc) * 3);
+      if (lc < t.ncell) dst[j] = load3<NT>(q + t.base + (t.cell0 + lc) * 3);
     }
     if (tid < 2) {
       int64_t c = tid == 0 ? t.cell0 - 1 : t.cell0 + t.ncell;
@@ -158,13 +199,13 @@ __global__ __launch_bounds__(kEulerThreads) void k_residual_euler(
       const T rho = c3.v[0], m = c3.v[1], E = c3.v[2];
       if (rho < T(kRhoMin)) fl |= ROM_FLAG_FLOOR;
       const T rf = rho >= T(kRhoMin) ? rho : T(kRhoMin);
-      const T ir = T(1) / rf;
+      const T ir = rcp_s(rf);
       const T u = m * ir;
       const T pe = (gamma - T(1)) * (E - T(0.5) * m * u);
       if (pe < T(kPMin)) fl |= ROM_FLAG_FLOOR;
       const T p = pe >= T(kPMin) ? pe : T(kPMin);
       sa[slot] = rho; sa[LA + slot] = m; sa[2 * LA + slot] = E; sa[3 * LA + slot] = rf;
-      sa[4 * LA + slot] = u; sa[5 * LA + slot] = p; sa[6 * LA + slot] = dsqrt(gamma * p * ir);
+      sa[4 * LA + slot] = u; sa[5 * LA + slot] = p; sa[6 * LA + slot] = sqrt_s(gamma * p * ir);
       sa[7 * LA + slot] = HLLC ? ir : m * u + p;
     };
     if (!skip) {
@@ -202,16 +243,16 @@ __global__ __launch_bounds__(kEulerThreads) void k_residual_euler(
           } else {
             const T num = pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR);
             const T den = rL * (SL - uL) - rR * (SR - uR);
-            const T Ss = num / den;
+            const T Ss = num * rcp_s(den);
             if (Ss >= T(0)) {
-              const T fac = rL * (SL - uL) / (SL - Ss);
-              const T e = L[2] * L[7] + (Ss - uL) * (Ss + pL / (rL * (SL - uL)));
+              const T fac = rL * (SL - uL) * rcp_s(SL - Ss);
+              const T e = L[2] * L[7] + (Ss - uL) * (Ss + pL * rcp_s(rL * (SL - uL)));
               H[0] = L[1] + SL * (fac - L[0]);
               H[1] = L[1] * uL + pL + SL * (fac * Ss - L[1]);
               H[2] = uL * (L[2] + pL) + SL * (fac * e - L[2]);
             } else if (SR >= T(0)) {
-              const T fac = rR * (SR - uR) / (SR - Ss);
-              const T e = R[2] * R[7] + (Ss - uR) * (Ss + pR / (rR * (SR - uR)));
+              const T fac = rR * (SR - uR) * rcp_s(SR - Ss);
+              const T e = R[2] * R[7] + (Ss - uR) * (Ss + pR * rcp_s(rR * (SR - uR)));
               H[0] = R[1] + SR * (fac - R[0]);
               H[1] = R[1] * uR + pR + SR * (fac * Ss - R[1]);
               H[2] = uR * (R[2] + pR) + SR * (fac * e - R[2]);
@@ -234,7 +275,7 @@ __global__ __launch_bounds__(kEulerThreads) void k_residual_euler(
           const int64_t g = t.base + (t.cell0 + lc) * 3;
           Cell3<T> o;
           Cell3<T> pv;
-          if (qprev) pv = *reinterpret_cast<const Cell3<T>*>(qprev + g);
+          if (qprev) pv = load3<NT>(qprev + g);
 #pragma unroll
           for (int v = 0; v < 3; ++v) {
             T val = -(sH[v * LH + lc + 1] - sH[v * LH + lc]) * nn;
@@ -244,7 +285,7 @@ __global__ __launch_bounds__(kEulerThreads) void k_residual_euler(
             const uint64_t bits = isfinite(val) ? norm_bits(val) : ~0ull;
             nb = bits > nb ? bits : nb;
           }
-          *reinterpret_cast<Cell3<T>*>(out + g) = o;
+          store3<NT>(out + g, o);
         }
       }
       if (norms) wave_atomic_max(&norms[b], nb);
@@ -523,20 +564,28 @@ static rom_status residual_t(rom_batch* h, const void* q, const void* q_prev, do
     // persistent grid of (blocks per CU) x CUs walking tiles of 256 CPT cells;
     // the shape comes from the autotuner (results do not depend on it)
     const ResidualShape sh = residual_shape(h, h->tune_residual);
-    const Tile* tl = sh.cpt == 4 ? h->d_btiles : h->d_btiles2;
-    const int nt = sh.cpt == 4 ? h->n_btiles : h->n_btiles2;
+    const Tile* tl = sh.cpt == 4 ? h->d_btiles : sh.cpt == 2 ? h->d_btiles2 : h->d_tiles;
+    const int nt = sh.cpt == 4 ? h->n_btiles : sh.cpt == 2 ? h->n_btiles2 : h->n_tiles;
     const int grid = std::max(1, std::min(nt, h->n_cu * sh.blocks_per_cu));
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(grid), dim3(kEulerThreads), 0, s, tl, nt, h->d_phys,
                          h->cfg.n_phys, (const T*)q, (const T*)q_prev, (T)dt, (T*)out, h->flags,
                          norms, active);
     };
-    const bool hllc = h->cfg.problem == ROM_EULER_HLLC;
-    if (sh.cpt == 4) {
-      if (hllc) go(k_residual_euler<T, true, 4>); else go(k_residual_euler<T, false, 4>);
-    } else {
-      if (hllc) go(k_residual_euler<T, true, 2>); else go(k_residual_euler<T, false, 2>);
-    }
+    auto pick = [&](auto hllc_tag) {
+      constexpr bool HL = decltype(hllc_tag)::value;
+      if (sh.nt) {
+        if (sh.cpt == 4) go(k_residual_euler<T, HL, 4, true>);
+        else if (sh.cpt == 2) go(k_residual_euler<T, HL, 2, true>);
+        else go(k_residual_euler<T, HL, 1, true>);
+      } else {
+        if (sh.cpt == 4) go(k_residual_euler<T, HL, 4, false>);
+        else if (sh.cpt == 2) go(k_residual_euler<T, HL, 2, false>);
+        else go(k_residual_euler<T, HL, 1, false>);
+      }
+    };
+    if (h->cfg.problem == ROM_EULER_HLLC) pick(std::true_type{});
+    else pick(std::false_type{});
     return ROM_OK;
   }
   return with_model<T>(h, [&](auto tag) -> rom_status {
@@ -568,10 +617,14 @@ rom_status launch_residual_norm(rom_batch* h, const void* q, const void* q_prev,
 }
 
 // Launch shapes of the streaming Euler residual that the autotuner chooses
-// from: (cells per thread, resident blocks per CU), limited by LDS (a 1024-cell
-// FP32 tile uses 45 KB, a 512-cell one 23 KB; FP64 doubles that).
-static const ResidualShape kShapesF32[] = {{4, 3}, {4, 2}, {4, 1}, {2, 6}, {2, 4}, {2, 2}};
-static const ResidualShape kShapesF64[] = {{4, 1}, {2, 3}, {2, 2}, {2, 1}};
+// from: (cells per thread, resident blocks per CU, non-temporal streaming),
+// limited by LDS (FP32 tiles of 1024 / 512 / 256 cells use 45 / 23 / 11 KB;
+// FP64 doubles that).
+static const ResidualShape kShapesF32[] = {{4, 3, 0}, {4, 2, 0}, {2, 7, 0}, {2, 6, 0}, {2, 4, 0},
+                                           {1, 8, 0}, {1, 12, 0}, {4, 3, 1}, {2, 7, 1}, {2, 6, 1},
+                                           {1, 8, 1}, {1, 12, 1}};
+static const ResidualShape kShapesF64[] = {{4, 1, 0}, {2, 3, 0}, {2, 2, 0}, {1, 6, 0},
+                                           {2, 3, 1}, {1, 6, 1}};
 
 int residual_shape_count(const rom_batch* h) {
   if (h->cfg.problem != ROM_EULER_RUSANOV && h->cfg.problem != ROM_EULER_HLLC) return 1;
