@@ -31,6 +31,26 @@ sys.path.insert(0, ROOT)
 METRIC = "adaptive-ROM steps/s + FOM cell-updates/s (% HBM roofline), batched vs plain"
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic per launch from rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE
+# in KiB per dispatch, bench.py --only galerkin / --only residual), each scaled
+# by what the same counter reads for a plain 512 MiB device copy (bench.py --only
+# copy: FETCH_SIZE reads 262157 KiB for 524288 KiB moved, WRITE_SIZE exactly
+# 524288 KiB).  Valid only for the kernel version they were taken on; the
+# summaries of those runs are kept in the profiles directory.
+COPY_SCALE = {"fetch": 524288.0 / 262157.4, "write": 1.0}
+MEASURED_KIB = {
+    "k_galerkin_pass": {"fetch": 135660.5, "write": 4245.8},
+    # streaming Euler residual, shape 8 (512-cell tiles, 7 blocks/CU, non-temporal)
+    "k_residual_euler/8": {"fetch": 105506.6, "write": 196608.0},
+}
+
+
+def traffic_bytes(key):
+    m = MEASURED_KIB.get(key)
+    if m is None:
+        return None
+    return int(1024 * (m["fetch"] * COPY_SCALE["fetch"] + m["write"] * COPY_SCALE["write"]))
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -42,10 +62,12 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
-    p.add_argument("--only", choices=["all", "copy", "galerkin", "residual"], default="all",
+    p.add_argument("--only", choices=["all", "copy", "galerkin", "residual", "windows"],
+                   default="all",
                    help="profiling runs: 'copy' times a plain 512 MiB device copy (the "
                         "reference for counter scaling), 'galerkin' only the Galerkin pass, "
-                        "'residual' only R(q); 'all' is the benchmark")
+                        "'residual' only R(q), 'windows' the offline stage plus --warmup and "
+                        "--steps adaptation windows; 'all' is the benchmark")
     return p.parse_args()
 
 
@@ -104,6 +126,21 @@ def profile_only(args, torch, W, R):
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copy: %d x %d bytes" % (reps, 4 * n))
+    elif args.only == "windows":
+        w = W.burgers_batch_f32()
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            h = R.RomBatch(w, q0=torch.as_tensor(w.q0, dtype=torch.float32, device="cuda"),
+                           use_graph=True)
+            h.rom_step(w.z * args.warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if args.steps:
+                h.rom_step(w.z * args.steps)
+            torch.cuda.synchronize()
+            h.close()
+        log("windows: %d after %d warm-up, %.3f ms each" % (
+            args.steps, args.warmup, 1e3 * (time.perf_counter() - t0) / max(args.steps, 1)))
     elif args.only == "galerkin":
         w = W.burgers_batch_f32()
         s = torch.cuda.Stream()
@@ -174,7 +211,7 @@ def main():
         achieved = bytes_pass / (ms_pass * 1e-3) / 1e9
         roofline = dict(kernel="k_galerkin_pass", bound="hbm", achieved=round(achieved, 1),
                         peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                        traffic=None, ms_per_launch=round(ms_pass, 5),
+                        traffic=traffic_bytes("k_galerkin_pass"), ms_per_launch=round(ms_pass, 5),
                         bytes_per_launch=int(bytes_pass))
         ms_proj = h.profile(R.PROF_ISVD_PROJECT, reps, h.get(R.GET_YCORR))
         h.close()
@@ -225,7 +262,7 @@ def main():
         fom = dict(workload="euler_rusanov_64x262144_f32", ms_per_launch=round(ms_res, 5),
                    cell_updates_per_s=cells / (ms_res * 1e-3), achieved_GBs=round(res_gbs, 1),
                    frac_hbm=round(res_gbs / HBM_PEAK_GBS, 4), bytes_per_launch=res_bytes,
-                   tuned_shape=int(shape))
+                   tuned_shape=int(shape), traffic=traffic_bytes("k_residual_euler/%d" % shape))
         ms_vjp = he.profile(R.PROF_RESIDUAL_VJP, 20, qe)
         fom["vjp_ms_per_launch"] = round(ms_vjp, 5)
         fom["vjp_frac_hbm"] = round(cells * 3 * 4 * 3 / (ms_vjp * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)

@@ -115,6 +115,19 @@ DEV void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Rotation that orthogonalises two rows with squared norms al, be and inner
+// product ga: tan(theta) = t with t the smaller root of t^2 + 2 zeta t - 1 = 0,
+// zeta = (be - al) / (2 ga), written as t = 2 ga sign / (|be - al| +
+// sqrt((be - al)^2 + 4 ga^2)) (one square root and one division on the
+// critical path), cos = 1 / sqrt(1 + t^2), sin = t cos.
+DEV void rotation(double al, double be, double ga, double& cs, double& sn) {
+  const double dd = be - al;
+  const double num = (dd * ga >= 0.0) ? fabs(2.0 * ga) : -fabs(2.0 * ga);
+  const double tt = num / (fabs(dd) + sqrt(dd * dd + 4.0 * ga * ga));
+  cs = rsqrt(1.0 + tt * tt);
+  sn = cs * tt;
+}
+
 // One-sided Jacobi on the rows of the n x n matrix K (LDS, leading dim ld),
 // run by a single wavefront (blockDim.x == 64, n <= 128): K <- G K with G
 // orthogonal until the rows are mutually orthogonal.  Then sigma_i = ||row i||
@@ -159,9 +172,8 @@ DEV void jacobi_rows(double* K, double* G, int n, int ld, double* U, double* sv,
           ga += __shfl_xor(ga, off, TPP);
         }
         if (live && ga != 0.0 && ga * ga > tol2 * al * be) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          double cs, sn;
+          rotation(al, be, ga, cs, sn);
           for (int q = sub; q < n; q += TPP) {
             const double x = K[i * ld + q], z = K[j * ld + q];
             K[i * ld + q] = cs * x - sn * z;
@@ -255,9 +267,8 @@ DEV void jacobi_rows_blk(double* K, double* G, double* U, double* sv, double* no
             ga += __shfl_xor(ga, off, TPP);
           }
           if (ga != 0.0 && ga * ga > tol2 * al * be) {
-            const double zeta = (be - al) / (2.0 * ga);
-            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+            double cs, sn;
+            rotation(al, be, ga, cs, sn);
 #pragma unroll
             for (int e = 0; e < EPL; ++e) {
               const int q = sub + TPP * e;

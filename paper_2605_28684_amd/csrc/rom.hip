@@ -169,16 +169,130 @@ __global__ __launch_bounds__(256) void k_galerkin_solve(
   }
   __syncthreads();
   lu_solve_block(J, ld, g, r, &ok);
-  if (tid == 0) {
+  // a += delta, one lane per component (r <= 64), then the stopping test
+  if (tid < 64) {
     double dm = 0.0, am = 0.0;
-    bool fin = true;
-    for (int c = 0; c < r; ++c) {
-      const double an = a[(size_t)b * r + c] + g[c];
-      a[(size_t)b * r + c] = an;
-      dm = fmax(dm, fabs(g[c]));
-      am = fmax(am, fabs(an));
-      fin = fin && isfinite(an);
+    int fin = 1;
+    if (tid < r) {
+      const double an = a[(size_t)b * r + tid] + g[tid];
+      a[(size_t)b * r + tid] = an;
+      dm = fabs(g[tid]);
+      am = fabs(an);
+      fin = isfinite(an) ? 1 : 0;
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      dm = fmax(dm, __shfl_xor(dm, off));
+      am = fmax(am, __shfl_xor(am, off));
+      fin &= __shfl_xor(fin, off);
+    }
+    if (tid == 0) {
+      iters[b] += 1;
+      if (!ok) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
+      if (!fin) atomicOr(&flags[b], ROM_FLAG_NONFINITE);
+      if (dm <= tol * (1.0 + am) || !fin) active[b] = 0;
+    }
+  }
+}
+
+// The same reduced Newton step for r = RT = 32 (the FP32 MFMA path), by
+// one wavefront and no block barriers: lane i sums row i of the tile partials
+// (J_g row i and g_i) into registers, then LU with partial pivoting runs on the
+// register rows -- each column's pivot is the wave-wide argmax of the remaining
+// rows (lowest row on ties), its row is broadcast through LDS and every
+// remaining lane eliminates its own row; no rows move, only the pivot order is
+// recorded.  Back-substitution walks the pivot order from the last column.
+template <int RT>
+__global__ __launch_bounds__(64) void k_galerkin_solve_w(
+    const int* __restrict__ tfirst, const double* __restrict__ gpart,
+    const float* __restrict__ mpart, double dt, const double* __restrict__ dvar,
+    double* __restrict__ a, const double* __restrict__ a_prev, int32_t* __restrict__ active,
+    int32_t* __restrict__ iters, double tol, uint32_t* flags) {
+  __shared__ double prow[RT + 1];
+  __shared__ double xs[RT];
+  const int b = blockIdx.x, lane = threadIdx.x;
+  if (!active[b]) return;
+  const bool row = lane < RT;
+  const int li = row ? lane : 0;
+  const int t0 = tfirst[b], t1 = tfirst[b + 1];
+  double A[RT];
+#pragma unroll
+  for (int j = 0; j < RT; ++j) A[j] = 0.0;
+  double gs = 0.0;
+  for (int tt = t0; tt < t1; ++tt) {
+    const float4* mr = reinterpret_cast<const float4*>(mpart + (size_t)tt * kMaxR * kMaxR + li * RT);
+#pragma unroll
+    for (int j4 = 0; j4 < RT / 4; ++j4) {
+      const float4 v = mr[j4];
+      A[4 * j4] += (double)v.x;
+      A[4 * j4 + 1] += (double)v.y;
+      A[4 * j4 + 2] += (double)v.z;
+      A[4 * j4 + 3] += (double)v.w;
+    }
+    gs += gpart[(size_t)tt * kMaxR + li];
+  }
+#pragma unroll
+  for (int j = 0; j < RT; ++j) A[j] = (j == li ? 1.0 : 0.0) - dt * A[j];
+  const double ai = a[(size_t)b * RT + li];
+  double bi = -(ai - a_prev[(size_t)b * RT + li] - dt * dvar[b] * gs);
+  bool used = !row;
+  int ord = -1;
+  int ok = 1;
+#pragma unroll
+  for (int k = 0; k < RT; ++k) {
+    double v = used ? -1.0 : fabs(A[k]);
+    int idx = lane;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(v, off);
+      const int oi = __shfl_xor(idx, off);
+      if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    }
+    const int p = __builtin_amdgcn_readfirstlane(idx);
+    if (v == 0.0) ok = 0;
+    if (lane == p) {
+#pragma unroll
+      for (int j = k; j < RT; ++j) prow[j] = A[j];
+      prow[RT] = bi;
+      used = true;
+      ord = k;
+    }
+    lds_wave_sync();
+    if (!used) {
+      const double pk = prow[k];
+      const double f = pk != 0.0 ? A[k] / pk : 0.0;
+#pragma unroll
+      for (int j = k + 1; j < RT; ++j) A[j] -= f * prow[j];
+      bi -= f * prow[RT];
+    }
+    lds_wave_sync();
+  }
+  // back-substitution: the lane with pivot order k holds row k of U
+#pragma unroll
+  for (int k = RT - 1; k >= 0; --k) {
+    if (ord == k) xs[k] = A[k] != 0.0 ? bi / A[k] : 0.0;
+    lds_wave_sync();
+    const double xk = xs[k];
+    if (ord >= 0 && ord < k) bi -= A[k] * xk;
+  }
+  lds_wave_sync();
+  double dm = 0.0, am = 0.0;
+  int fin = 1;
+  if (row) {
+    const double del = xs[lane];
+    const double an = ai + del;
+    a[(size_t)b * RT + lane] = an;
+    dm = fabs(del);
+    am = fabs(an);
+    fin = isfinite(an) ? 1 : 0;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    dm = fmax(dm, __shfl_xor(dm, off));
+    am = fmax(am, __shfl_xor(am, off));
+    fin &= __shfl_xor(fin, off);
+  }
+  if (lane == 0) {
     iters[b] += 1;
     if (!ok) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
     if (!fin) atomicOr(&flags[b], ROM_FLAG_NONFINITE);
@@ -607,6 +721,12 @@ rom_status galerkin_step_t(rom_batch* h, hipStream_t s) {
     if (mfma_ok(h)) {
       rom_status st = launch_galerkin_mfma(h, s);
       if (st != ROM_OK) return st;
+      if (r == 32) {  // register-resident single-wave solve (r = 64 rows do not fit)
+        hipLaunchKernelGGL(k_galerkin_solve_w<32>, dim3(B), dim3(64), 0, s, h->d_ptile_first,
+                           gpart, (const float*)h->mpart, h->cfg.dt, h->d_var, h->a, h->a_prev,
+                           h->active, h->iters, h->cfg.rom_tol, h->flags);
+        continue;
+      }
     } else {
       hipLaunchKernelGGL((k_galerkin_pass<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                          h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const T*)h->Phi,

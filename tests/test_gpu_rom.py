@@ -171,6 +171,50 @@ def test_galerkin_steps_and_events_parity_fp64():
     assert h.get(R.GET_COUNTERS)[2] == 2
 
 
+@pytest.mark.parametrize("problem", [W.EULER_HLLC, W.REACT])
+def test_hr_lspg_steps_and_events_parity_fp64(problem):
+    """Alg. 1 on the hyper-reduced path (LSPG + greedy DEIM) from identical
+    offline state: fine steps, and events with the coarse step, iSVD,
+    re-sampling, rebuild and transfer; sample rows bit-exact after every event."""
+    import gpu_common as G
+    import torch
+    from paper_2605_28684_amd import romhip as R
+    if problem == W.EULER_HLLC:
+        w = W.sod_hllc_f32(n=128, r=5, n_s=10, z=3, precision=W.F64, flux=W.EULER_HLLC, N_t=40)
+        q0 = w.q0
+    else:
+        w = W.react10_f32(n_inst=1, n=48, r=6, n_s=12, z=3, N_t=40, precision=W.F64)
+        w.dt = 2e-4
+        q0 = w.q0
+    w.rom_tol = 1e-13
+    prm = w.params()
+    assert prm["hyper"] == "deim"
+    h = _handle(w, q0=G.to_dev(q0, W.F64))
+    st = O.offline(problem, w.phys[0], q0, prm)
+    h.set(R.GET_BASIS, G.to_dev(st["Phi"].reshape(-1), W.F64))
+    h.set(R.GET_SIGMA, torch.as_tensor(st["sigma"]))
+    h.set(R.GET_A, torch.as_tensor(st["a"]))
+    h.set(R.GET_YCORR, G.to_dev(st["y_corr"], W.F64))
+    h.set(R.GET_DVAR, torch.as_tensor(st["d_var"]))
+    h.rom_rebuild()
+    np.testing.assert_array_equal(h.get(R.GET_SAMPLES).cpu().numpy(), st["P"])
+    events = 0
+    for k in range(10):
+        h.rom_step(1)
+        n = prm["w_init"] + k
+        O.rom_fine_step(problem, w.phys[0], st, prm)
+        if (n + 1 - prm["w_init"]) % prm["z"] == 0:
+            O.adaptation_event(problem, w.phys[0], st, prm)
+            events += 1
+            np.testing.assert_array_equal(h.get(R.GET_SAMPLES).cpu().numpy(), st["P"])
+        ref = O.reconstruct(st["q_ref"], st["d"], st["Phi"], st["a"])
+        qg = G.host(h.get(R.GET_QTILDE))
+        assert G.relerr(qg, ref) < 1e-10, (k, G.relerr(qg, ref))
+        assert G.relerr(G.host(h.get(R.GET_SIGMA)), st["sigma"]) < 1e-10, k
+    assert events == 3 and h.get(R.GET_COUNTERS)[2] == 3
+    assert not (h.status() & (4 | 16 | 32)).any()
+
+
 @pytest.mark.parametrize("precision", [W.F64, W.F32])
 def test_deim_rows_bit_exact_and_pinv(precision):
     import gpu_common as G
