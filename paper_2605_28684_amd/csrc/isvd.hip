@@ -15,6 +15,7 @@
 // rows are orthogonalised pairwise in round-robin order until every pair is
 // orthogonal to 2 n eps relative.
 #include "internal.h"
+#include "linalg.h"
 #include "physics.h"
 
 namespace romhip {
@@ -323,12 +324,266 @@ DEV void jacobi_rows_blk(double* K, double* G, double* U, double* sv, double* no
   __syncthreads();
 }
 
+// ------------------------------------------------------------------ arrowhead SVD
+// Left singular vectors and values of the core K = [[diag(d), p], [0, rho]]
+// (d = lambda sigma, sorted descending) from the eigenproblem of
+// K K^T = D^2 + z z^T, D = diag(d, 0), z = (p, rho): a rank-one change of a
+// diagonal matrix (Brand's update core).  Steps, one wavefront per instance:
+//  * scale by max(|d|, |z|);
+//  * deflation: weights |z_i| <= 8 eps max(d_0, |z|) give the value d_i with
+//    vector e_i; a pole within that tolerance of the previous kept pole is
+//    removed by a plane rotation that moves its weight onto the kept one;
+//  * the K remaining roots of the secular equation
+//      1 + sum_i zeta_i^2 / (delta_i^2 - omega^2) = 0
+//    one per lane, each in its interlacing interval, written as
+//    omega = delta_o + tau with o the nearer pole so that every
+//    delta_i - omega = (delta_i - delta_o) - tau is formed without
+//    cancellation; iteration on a two-pole rational model of the secular
+//    function (value and slope of the sums over the poles on each side) with a
+//    bisection safeguard;
+//  * weights recomputed from the roots by Loewner's formula
+//      zhat_i^2 = prod_k (omega_k^2 - delta_i^2) / prod_{j != i} (delta_j^2 - delta_i^2),
+//    which makes the vectors u_k ~ zhat / (delta^2 - omega_k^2) orthogonal to
+//    working precision (Gu and Eisenstat);
+//  * the deflation rotations undone, then the same stable descending sort and
+//    sign convention as the Jacobi path.
+// Returns false (nothing written) when d is not sorted descending.
+DEV void sec_sums(int o, double x, int k, int K, const double* delta, const double* zeta2,
+                  double& psi, double& dpsi, double& phi, double& dphi, double& dl, double& du) {
+  const double dO = delta[o], w = dO + x;
+  psi = dpsi = phi = dphi = 0.0;
+  dl = du = 0.0;
+  for (int i = 0; i < K; ++i) {
+    const double den = ((delta[i] - dO) - x) * (delta[i] + w);   // delta_i^2 - omega^2
+    const double inv = 1.0 / den;
+    const double t = zeta2[i] * inv;
+    if (i >= k) { psi += t; dpsi += t * inv; } else { phi += t; dphi += t * inv; }
+    if (i == k) dl = den;
+    if (i == k - 1) du = den;
+  }
+}
+
+DEV void sec_root(int k, int K, const double* delta, const double* zeta2, double rho2, int& o,
+                  double& tau) {
+  const double eps = 2.220446049250313e-16;
+  if (K == 1) {  // closed form: omega^2 = delta_0^2 + zeta_0^2
+    o = 0;
+    tau = zeta2[0] / (delta[0] + sqrt(delta[0] * delta[0] + zeta2[0]));
+    return;
+  }
+  double lo, hi, psi, dpsi, phi, dphi, dl, du;
+  if (k == 0) {
+    o = 0;
+    lo = 0.0;
+    hi = rho2 / (delta[0] + sqrt(delta[0] * delta[0] + rho2));
+  } else {
+    const double a2 = (delta[k - 1] - delta[k]) * (delta[k - 1] + delta[k]);
+    const double wm = sqrt(0.5 * (delta[k - 1] * delta[k - 1] + delta[k] * delta[k]));
+    const double tm = 0.5 * a2 / (wm + delta[k]);
+    sec_sums(k, tm, k, K, delta, zeta2, psi, dpsi, phi, dphi, dl, du);
+    if (1.0 + psi + phi >= 0.0) { o = k; lo = 0.0; hi = tm; }
+    else { o = k - 1; lo = -(0.5 * a2) / (delta[k - 1] + wm); hi = 0.0; }
+  }
+  const double dO = delta[o];
+  double x = 0.5 * (lo + hi);
+  for (int it = 0; it < 100; ++it) {
+    sec_sums(o, x, k, K, delta, zeta2, psi, dpsi, phi, dphi, dl, du);
+    const double g = 1.0 + psi + phi;
+    if (g == 0.0) break;
+    if (g < 0.0) lo = x; else hi = x;
+    const double sl = dpsi * dl * dl;
+    double c = 1.0 + (psi - sl / dl), eta;
+    if (k == 0) {
+      c += phi;
+      eta = c != 0.0 ? dl + sl / c : NAN;
+    } else {
+      const double su = dphi * du * du;
+      c += phi - su / du;
+      const double B = c * (dl + du) + sl + su;
+      const double disc = sqrt(fmax(B * B - 4.0 * c * dl * du * g, 0.0));
+      eta = B > 0.0 ? 2.0 * dl * du * g / (B + disc) : (c != 0.0 ? (B - disc) / (2.0 * c) : NAN);
+    }
+    const double mu_rel = x * (2.0 * dO + x) + eta;             // omega'^2 - delta_o^2
+    double xn = isfinite(eta) ? mu_rel / (sqrt(fmax(dO * dO + mu_rel, 0.0)) + dO) : NAN;
+    if (isfinite(xn) && fabs(xn - x) <= 4.0 * eps * fabs(x)) {
+      if (lo < xn && xn < hi) x = xn;
+      break;
+    }
+    if (!(lo < xn && xn < hi)) xn = 0.5 * (lo + hi);
+    if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi))) { x = xn; break; }
+    x = xn;
+  }
+  tau = x;
+}
+
+// K: the core in LDS (N x N, row-major); Uc: LDS N x N scratch (column c at
+// Uc + c N); U: output N x N (row-major, columns = sorted vectors); sv: LDS N.
+template <int N>
+DEV bool arrow_svd_wave(const double* K, double* Uc, double* U, double* sv, double* ws, int* iw) {
+  const int lane = threadIdx.x & 63;
+  const double eps = 2.220446049250313e-16;
+  double* d = ws;            // N
+  double* z = d + N;         // N
+  double* delta = z + N;     // N
+  double* zeta2 = delta + N; // N
+  double* zsgn = zeta2 + N;  // N
+  double* tau = zsgn + N;    // N
+  double* omg = tau + N;     // N
+  double* zhat = omg + N;    // N
+  double* vals = zhat + N;   // N
+  double* rc = vals + N;     // N
+  double* rsn = rc + N;      // N
+  double* scal = rsn + N;    // [0] scale, [1] rho2
+  int* L = iw;               // N: kept poles
+  int* orig = L + N;         // N
+  int* ri = orig + N;        // N
+  int* rj = ri + N;          // N
+  int* key = rj + N;         // N
+  int* rnk = key + N;        // N
+  int* dfl = rnk + N;        // N: deflated indices in order
+  int* cnt = dfl + N;        // [0] K, [1] nrot, [2] ndefl
+  double m = 0.0;
+  int sorted = 1;
+  for (int i = lane; i < N; i += 64) {
+    d[i] = i < N - 1 ? K[i * N + i] : 0.0;
+    z[i] = K[i * N + N - 1];
+    m = fmax(m, fmax(fabs(d[i]), fabs(z[i])));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  lds_wave_sync();
+  for (int i = lane; i + 1 < N; i += 64)
+    if (!(d[i] >= d[i + 1])) sorted = 0;
+  if (!__all(sorted)) return false;
+  const double scale = m;
+  if (scale == 0.0) {
+    for (int e = lane; e < N * N; e += 64) U[e] = (e / N == e % N) ? 1.0 : 0.0;
+    for (int i = lane; i < N; i += 64) sv[i] = 0.0;
+    lds_wave_sync();
+    return true;
+  }
+  for (int i = lane; i < N; i += 64) { d[i] /= scale; z[i] /= scale; }
+  lds_wave_sync();
+  if (lane == 0) {  // deflation (at most N entries; sequential)
+    double zn2 = 0.0;
+    for (int i = 0; i < N; ++i) zn2 += z[i] * z[i];
+    const double tol = 8.0 * eps * fmax(d[0], sqrt(zn2));
+    int nrot = 0, nd = 0, prev = -1;
+    for (int j = 0; j < N; ++j) {
+      if (fabs(z[j]) <= tol) { z[j] = 0.0; dfl[nd++] = j; continue; }
+      if (prev >= 0 && d[prev] - d[j] <= tol) {
+        const double h = hypot(z[prev], z[j]);
+        const double c = z[prev] / h, sn = z[j] / h;
+        z[prev] = h;
+        z[j] = 0.0;
+        ri[nrot] = prev; rj[nrot] = j; rc[nrot] = c; rsn[nrot] = sn;
+        ++nrot;
+        dfl[nd++] = j;
+        continue;
+      }
+      prev = j;
+    }
+    int Kk = 0;
+    double rho2 = 0.0;
+    for (int j = 0; j < N; ++j) {
+      if (z[j] == 0.0) continue;
+      L[Kk] = j;
+      delta[Kk] = d[j];
+      zeta2[Kk] = z[j] * z[j];
+      zsgn[Kk] = z[j] < 0.0 ? -1.0 : 1.0;
+      rho2 += zeta2[Kk];
+      ++Kk;
+    }
+    cnt[0] = Kk; cnt[1] = nrot; cnt[2] = nd;
+    scal[1] = rho2;
+  }
+  lds_wave_sync();
+  const int Kk = cnt[0], nrot = cnt[1], nd = cnt[2];
+  const double rho2 = scal[1];
+  for (int k = lane; k < Kk; k += 64) {
+    int o;
+    double t;
+    sec_root(k, Kk, delta, zeta2, rho2, o, t);
+    orig[k] = o;
+    tau[k] = t;
+    omg[k] = delta[o] + t;
+  }
+  lds_wave_sync();
+  for (int mm = lane; mm < Kk; mm += 64) {  // Loewner weights
+    const double dm = delta[mm];
+    double p = ((delta[orig[mm]] - dm) + tau[mm]) * (omg[mm] + dm);
+    for (int k = 0; k < Kk; ++k) {
+      if (k == mm) continue;
+      const double wd = (delta[orig[k]] - dm) + tau[k];
+      p *= (wd * (omg[k] + dm)) / ((delta[k] - dm) * (delta[k] + dm));
+    }
+    zhat[mm] = zsgn[mm] * sqrt(fabs(p));
+  }
+  for (int e = lane; e < N * N; e += 64) Uc[e] = 0.0;
+  lds_wave_sync();
+  for (int k = lane; k < Kk; k += 64) {  // vectors of the kept poles
+    const int o = orig[k];
+    double nn = 0.0;
+    for (int mm = 0; mm < Kk; ++mm) {
+      const double v = zhat[mm] / (((delta[mm] - delta[o]) - tau[k]) * (delta[mm] + omg[k]));
+      Uc[k * N + L[mm]] = v;
+      nn += v * v;
+    }
+    const double inv = 1.0 / sqrt(nn);
+    for (int mm = 0; mm < Kk; ++mm) Uc[k * N + L[mm]] *= inv;
+    vals[k] = omg[k] * scale;
+    key[k] = L[k];
+  }
+  for (int t = lane; t < nd; t += 64) {  // deflated: e_j with value d_j
+    const int j = dfl[t];
+    Uc[(Kk + t) * N + j] = 1.0;
+    vals[Kk + t] = d[j] * scale;
+    key[Kk + t] = j;
+  }
+  lds_wave_sync();
+  for (int c = lane; c < N; c += 64) {   // undo the deflation rotations, last first
+    double* col = Uc + c * N;
+    for (int t = nrot - 1; t >= 0; --t) {
+      const int i = ri[t], j = rj[t];
+      const double vi = col[i], vj = col[j];
+      col[i] = rc[t] * vi - rsn[t] * vj;
+      col[j] = rsn[t] * vi + rc[t] * vj;
+    }
+  }
+  lds_wave_sync();
+  for (int c = lane; c < N; c += 64) {   // stable descending rank
+    int rk = 0;
+    const double vc = vals[c];
+    for (int c2 = 0; c2 < N; ++c2) {
+      const double v2 = vals[c2];
+      if (v2 > vc || (v2 == vc && key[c2] < key[c])) ++rk;
+    }
+    rnk[c] = rk;
+    sv[rk] = vc;
+  }
+  lds_wave_sync();
+  for (int c = lane; c < N; c += 64) {   // sign convention, scatter as column rank
+    const double* col = Uc + c * N;
+    int im = 0;
+    double best = -1.0;
+    for (int q = 0; q < N; ++q) {
+      const double v = fabs(col[q]);
+      if (v > best) { best = v; im = q; }
+    }
+    const double sg = col[im] < 0.0 ? -1.0 : 1.0;
+    const int dst = rnk[c];
+    for (int q = 0; q < N; ++q) U[q * N + dst] = sg * col[q];
+  }
+  lds_wave_sync();
+  return true;
+}
+
 // Core of Alg. 2: K from lambda, sigma, p, rho; SVD; sigma' and the transfer of a.
 // red layout per instance: [0..r) p1, r: |y^|^2, [r+1..2r+1) p2, 2r+1: |q1|^2
-// NF = 0: any r, one wavefront (jacobi_rows); NF = r + 1 in {33, 65}: 256 threads
-// (jacobi_rows_blk<NF>).
+// One wavefront per instance.  NF = 0: any r, one-sided Jacobi (jacobi_rows);
+// NF = r + 1 in {33, 65}: the arrowhead SVD (arrow_svd_wave).
 template <int NF>
-__global__ __launch_bounds__(NF == 0 ? 64 : 256) void k_isvd_core(int r, double lambda, double tau_rho,
+__global__ __launch_bounds__(64) void k_isvd_core(int r, double lambda, double tau_rho,
                                                   const double* __restrict__ red, int ldr,
                                                   double* __restrict__ sigma, double* __restrict__ a,
                                                   double* __restrict__ ubar, double* __restrict__ pr,
@@ -366,8 +621,15 @@ __global__ __launch_bounds__(NF == 0 ? 64 : 256) void k_isvd_core(int r, double 
     K[e] = v;
   }
   __syncthreads();
-  if constexpr (NF == 0) jacobi_rows(K, G, n, ld, U, sv, nrm, rank);
-  else jacobi_rows_blk<NF>(K, G, U, sv, nrm, rank);
+  if constexpr (NF == 0) {
+    jacobi_rows(K, G, n, ld, U, sv, nrm, rank);
+  } else {
+    // arrowhead SVD (one wavefront); Jacobi when sigma is not sorted
+    double* ws = reinterpret_cast<double*>(rank + n + (n & 1));
+    int* iw = reinterpret_cast<int*>(ws + 13 * NF);
+    if (!arrow_svd_wave<NF>(K, G, U, sv, ws, iw)) jacobi_rows(K, G, n, ld, U, sv, nrm, rank);
+    __syncthreads();
+  }
   for (int c = tid; c < r; c += blockDim.x) sigma[(size_t)b * r + c] = sv[c];
   // closed-form transfer: a <- Ubar[:r, :r]^T a  (the new direction is orthogonal to Phi)
   for (int c = tid; c < r; c += blockDim.x) {
@@ -743,11 +1005,13 @@ rom_status isvd_t(rom_batch* h, const void* y, hipStream_t s) {
   const int n = r + 1;
   const size_t shm = sizeof(double) * (2 * n * n + 3 * n) + sizeof(int) * n;
   double* pr = h->rstate;  // (p1, p2, 1/rho) per instance, stride 2r + 2
+  // the arrowhead path adds 13 N doubles and 8 N + 3 ints of workspace
+  const size_t shm_arrow = shm + sizeof(double) * (13 * n + 2) + sizeof(int) * (8 * n + 3 + 2);
   if (r == 32)
-    hipLaunchKernelGGL(k_isvd_core<33>, dim3(B), dim3(256), shm, s, r, h->cfg.lambda,
+    hipLaunchKernelGGL(k_isvd_core<33>, dim3(B), dim3(64), shm_arrow, s, r, h->cfg.lambda,
                        h->cfg.tau_rho, red, ldr, h->sigma, h->a, h->ubar, pr, h->flags);
   else if (r == 64)
-    hipLaunchKernelGGL(k_isvd_core<65>, dim3(B), dim3(256), shm, s, r, h->cfg.lambda,
+    hipLaunchKernelGGL(k_isvd_core<65>, dim3(B), dim3(64), shm_arrow, s, r, h->cfg.lambda,
                        h->cfg.tau_rho, red, ldr, h->sigma, h->a, h->ubar, pr, h->flags);
   else
     hipLaunchKernelGGL(k_isvd_core<0>, dim3(B), dim3(64), shm, s, r, h->cfg.lambda,
