@@ -171,6 +171,51 @@ def test_galerkin_steps_and_events_parity_fp64():
     assert h.get(R.GET_COUNTERS)[2] == 2
 
 
+def test_isvd_update_clustered_sigma_and_zero_weights_fp64():
+    """Core SVD deflation cases: exactly repeated and nearly repeated sigma and
+    snapshot components orthogonal to some basis columns (zero weights).  Vectors
+    inside a cluster are fixed only up to a rotation, so the covariance
+    Phi' Sigma'^2 Phi'^T is compared instead, with sigma' and orthonormality."""
+    import gpu_common as G
+    from paper_2605_28684_amd import romhip as R
+    r = 32
+    cells = [700, 300]
+    w = _burgers_batch(cells, W.F64, r)
+    w.lam = 0.5
+    w.reorth_every = 0
+    h = _handle(w)
+    rng = np.random.default_rng(71)
+    Phis = [_orth(n, r, 80 + b) for b, n in enumerate(cells)]
+    base = np.sort(rng.uniform(0.5, 5.0, r // 2))[::-1]
+    sig0 = np.repeat(base, 2)                       # exact pairs
+    sig1 = sig0 * (1.0 + 1e-14 * np.arange(r))       # near pairs
+    sig1 = np.sort(sig1)[::-1]
+    sigs = [sig0, sig1]
+    a = [rng.normal(size=r) for _ in cells]
+    ys = []
+    for b, n in enumerate(cells):
+        c = rng.normal(size=r)
+        c[[1, 5, 6, 20]] = 0.0                        # zero weights
+        ys.append(Phis[b] @ c + 1e-3 * rng.normal(size=n))
+    y = np.concatenate(ys)
+    qref = np.zeros(sum(cells))
+    dvar = [np.array([1.0]), np.array([1.0])]
+    _load_state(h, w, Phis, sigs, a, qref, dvar, W.F64)
+    h.isvd_update(G.to_dev(y, W.F64))
+    P2 = G.host(h.get(R.GET_BASIS))
+    s2 = G.host(h.get(R.GET_SIGMA))
+    off = w.offsets()
+    for b, n in enumerate(cells):
+        Pg = P2[off[b] * r:off[b + 1] * r].reshape(n, r)
+        sg = s2[b * r:(b + 1) * r]
+        Po, so, info = O.isvd_update(Phis[b], sigs[b], ys[b], w.lam, r, w.tau_rho)
+        assert G.relerr(sg, so) < 1e-12, b
+        assert np.max(np.abs(Pg.T @ Pg - np.eye(r))) < 1e-12, b
+        Cg = (Pg * sg ** 2) @ Pg.T
+        Co = (Po * so ** 2) @ Po.T
+        assert G.relerr(Cg, Co) < 1e-11, b
+
+
 @pytest.mark.parametrize("problem", [W.EULER_HLLC, W.REACT])
 def test_hr_lspg_steps_and_events_parity_fp64(problem):
     """Alg. 1 on the hyper-reduced path (LSPG + greedy DEIM) from identical
