@@ -19,6 +19,7 @@
 // A[l % 32][l / 32] and B[l / 32][l % 32]; accumulator element v of lane l is
 // D[(v / 4) * 8 + (l / 32) * 4 + v % 4][l % 32].
 #include "internal.h"
+#include "linalg.h"
 #include "physics.h"
 
 namespace romhip {
@@ -40,37 +41,43 @@ DEV int64_t wrap_cell(int64_t c, int64_t n) { return c < 0 ? c + n : (c >= n ? c
 // ------------------------------------------------------------------ Galerkin pass
 constexpr int kGW = 8;  // waves per Galerkin block
 
+// LDS of one Galerkin block (8 waves).
 template <int RT>
-__global__ __launch_bounds__(64 * kGW) void k_galerkin_mfma(
-    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off,
-    const int64_t* __restrict__ cell_off, const double* __restrict__ phys, int nphys,
-    const float* __restrict__ Phi, const float* __restrict__ qref,
-    const double* __restrict__ dvar, const double* __restrict__ a,
-    const int32_t* __restrict__ active, double* __restrict__ gpart, float* __restrict__ mpart) {
+struct GalerkinLds {
+  float sP[kGW][kCh + 2][RT + 1];
+  double sQ[kGW][kCh + 2];
+  double sF[kGW][kCh];
+  float sAl[kGW][kCh], sBe[kGW][kCh], sGa[kGW][kCh];
+  double sa[RT];        // the reduced state a (set by the caller)
+  float redM[RT * RT];  // Phi^T J_f Phi of the tile
+  double redG[RT];      // Phi^T f of the tile
+};
+
+// One block's share of a Galerkin pass: the rows of tile t (cells of one
+// instance).  Each wave streams its row range in 32-row chunks (next chunk
+// prefetched into registers, staged through LDS): q~ = q_ref + Phi a / d in
+// FP64, f(q~) and the three diagonals of J_f, then Phi^T f (FP64) and
+// Phi^T J_f Phi (v_mfma_f32_32x32x2f32).  The waves' sums are added in a fixed
+// order into L.redM / L.redG.  L.sa must hold a; ends with a block barrier.
+template <int RT>
+DEV void galerkin_tile(const Tile& t, const double* __restrict__ phys, int nphys,
+                       const float* __restrict__ Phi, const float* __restrict__ qref,
+                       const double* __restrict__ dvar, GalerkinLds<RT>& L) {
   constexpr int NCB = RT / 32;
   constexpr int LDP = RT + 1;
   constexpr int NV4 = (kCh + 2) * (RT / 4);       // float4 per chunk (with halo)
   constexpr int NPF = (NV4 + 63) / 64;            // float4 per lane
   constexpr int NT = 64 * kGW;
-  __shared__ float sP[kGW][kCh + 2][LDP];
-  __shared__ double sQ[kGW][kCh + 2];
-  __shared__ double sF[kGW][kCh];
-  __shared__ float sAl[kGW][kCh], sBe[kGW][kCh], sGa[kGW][kCh];
-  __shared__ double sa[RT];
-  __shared__ float redM[RT * RT];
-  __shared__ double redG[RT];
-  const Tile t = tiles[blockIdx.x];
   const int b = t.inst;
-  if (!active[b]) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t n = t.n;
   const int64_t base = t.base;
   const double nu = phys[(size_t)b * nphys];
   const double dinv = 1.0 / dvar[b];
   const double inv = (double)n, inv2 = (double)n * (double)n;
-  for (int c = tid; c < RT; c += NT) { sa[c] = a[(size_t)b * RT + c]; redG[c] = 0.0; }
-  for (int e = tid; e < RT * RT; e += NT) redM[e] = 0.f;
-  for (int e = tid; e < kGW * (kCh + 2) * LDP; e += NT) (&sP[0][0][0])[e] = 0.f;
+  for (int c = tid; c < RT; c += NT) L.redG[c] = 0.0;
+  for (int e = tid; e < RT * RT; e += NT) L.redM[e] = 0.f;
+  for (int e = tid; e < kGW * (kCh + 2) * LDP; e += NT) (&L.sP[0][0][0])[e] = 0.f;
   __syncthreads();
   // this wave's rows of the tile
   const int64_t per = ((t.ncell + kGW * kCh - 1) / (kGW * kCh)) * kCh;
@@ -87,7 +94,7 @@ __global__ __launch_bounds__(64 * kGW) void k_galerkin_mfma(
   double gacc[NCB];
 #pragma unroll
   for (int i = 0; i < NCB; ++i) gacc[i] = 0.0;
-  float(*P)[LDP] = sP[wave];
+  float(*P)[LDP] = L.sP[wave];
   // register prefetch of one chunk: basis rows c0-1 .. c0+nr and q_ref of those rows
   float4 pf[NPF];
   float pq = 0.f;
@@ -124,18 +131,18 @@ __global__ __launch_bounds__(64 * kGW) void k_galerkin_mfma(
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll 2
       for (int c = 0; c < RT; c += 4) {
-        s0 += (double)P[lane][c] * sa[c];
-        s1 += (double)P[lane][c + 1] * sa[c + 1];
-        s2 += (double)P[lane][c + 2] * sa[c + 2];
-        s3 += (double)P[lane][c + 3] * sa[c + 3];
+        s0 += (double)P[lane][c] * L.sa[c];
+        s1 += (double)P[lane][c + 1] * L.sa[c + 1];
+        s2 += (double)P[lane][c + 2] * L.sa[c + 2];
+        s3 += (double)P[lane][c + 3] * L.sa[c + 3];
       }
-      sQ[wave][lane] = qr + ((s0 + s1) + (s2 + s3)) * dinv;
+      L.sQ[wave][lane] = qr + ((s0 + s1) + (s2 + s3)) * dinv;
     }
     wave_sync();
     if (lane < kCh) {
       double f = 0.0, al = 0.0, be = 0.0, ga = 0.0;
       if (lane < nr) {
-        const double um = sQ[wave][lane], u0 = sQ[wave][lane + 1], up = sQ[wave][lane + 2];
+        const double um = L.sQ[wave][lane], u0 = L.sQ[wave][lane + 1], up = L.sQ[wave][lane + 2];
         double dla, dlb, dra, drb;
         const double FL = godunov(um, u0, dla, dlb);
         const double FR = godunov(u0, up, dra, drb);
@@ -144,18 +151,18 @@ __global__ __launch_bounds__(64 * kGW) void k_galerkin_mfma(
         be = (dlb - dra) * inv - 2.0 * nu * inv2;
         ga = -drb * inv + nu * inv2;
       }
-      sF[wave][lane] = f;
-      sAl[wave][lane] = (float)al;
-      sBe[wave][lane] = (float)be;
-      sGa[wave][lane] = (float)ga;
+      L.sF[wave][lane] = f;
+      L.sAl[wave][lane] = (float)al;
+      L.sBe[wave][lane] = (float)be;
+      L.sGa[wave][lane] = (float)ga;
     }
     wave_sync();
 #pragma unroll 4
     for (int k = 0; k < kCh / 2; ++k) {
       const int row = 2 * k + par;
       const bool live = row < nr;
-      const float al = sAl[wave][row], be = sBe[wave][row], ga = sGa[wave][row];
-      const double fr = sF[wave][row];
+      const float al = L.sAl[wave][row], be = L.sBe[wave][row], ga = L.sGa[wave][row];
+      const double fr = L.sF[wave][row];
       float A[NCB], Z[NCB];
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
@@ -186,18 +193,116 @@ __global__ __launch_bounds__(64 * kGW) void k_galerkin_mfma(
           for (int v = 0; v < 16; ++v) {
             const int i = ca * 32 + (v >> 2) * 8 + par * 4 + (v & 3);
             const int j = cb * 32 + cl;
-            redM[i * RT + j] += acc[ca][cb][v];
+            L.redM[i * RT + j] += acc[ca][cb][v];
           }
       if (par == 0) {
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) redG[cb * 32 + cl] += gacc[cb];
+        for (int cb = 0; cb < NCB; ++cb) L.redG[cb * 32 + cl] += gacc[cb];
       }
     }
     __syncthreads();
   }
+}
+
+template <int RT>
+__global__ __launch_bounds__(64 * kGW) void k_galerkin_mfma(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off,
+    const int64_t* __restrict__ cell_off, const double* __restrict__ phys, int nphys,
+    const float* __restrict__ Phi, const float* __restrict__ qref,
+    const double* __restrict__ dvar, const double* __restrict__ a,
+    const int32_t* __restrict__ active, double* __restrict__ gpart, float* __restrict__ mpart) {
+  constexpr int NT = 64 * kGW;
+  __shared__ GalerkinLds<RT> L;
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  if (!active[b]) return;
+  const int tid = threadIdx.x;
+  for (int c = tid; c < RT; c += NT) L.sa[c] = a[(size_t)b * RT + c];
+  galerkin_tile<RT>(t, phys, nphys, Phi, qref, dvar, L);
   float* mo = mpart + (size_t)blockIdx.x * kMaxR * kMaxR;
-  for (int e = tid; e < RT * RT; e += NT) mo[e] = redM[e];
-  for (int c = tid; c < RT; c += NT) gpart[(size_t)blockIdx.x * kMaxR + c] = redG[c];
+  for (int e = tid; e < RT * RT; e += NT) mo[e] = L.redM[e];
+  for (int c = tid; c < RT; c += NT) gpart[(size_t)blockIdx.x * kMaxR + c] = L.redG[c];
+}
+
+// Newton iterations it0 .. max_it-1 of the reduced backward-Euler step for the
+// instances still active after the grid-wide iterations: one block per
+// instance streams all of its rows (galerkin_tile on the whole instance),
+// solves J_g delta = -g in FP64 (block LU with partial pivoting) and repeats
+// until ||delta||_inf <= tol (1 + ||a||_inf) or max_it; a is kept in LDS and
+// written back at the end.  Instances still unconverged get the ROM
+// non-convergence flag.  Converged instances exit at once, so in the common
+// case this is one cheap launch in place of the remaining iterations.
+template <int RT>
+__global__ __launch_bounds__(64 * kGW) void k_galerkin_tail(
+    const int64_t* __restrict__ cell_off, const int64_t* __restrict__ dof_off,
+    const double* __restrict__ phys, int nphys, const float* __restrict__ Phi,
+    const float* __restrict__ qref, const double* __restrict__ dvar, double* __restrict__ a,
+    const double* __restrict__ a_prev, int32_t* __restrict__ active, int32_t* __restrict__ iters,
+    double dt, double tol, int it0, int max_it, uint32_t* __restrict__ flags) {
+  constexpr int NT = 64 * kGW;
+  constexpr int LDJ = RT + 1;
+  __shared__ GalerkinLds<RT> L;
+  __shared__ double J[RT * LDJ];
+  __shared__ double g[RT], ap[RT];
+  __shared__ int stop, nit;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  if (!active[b]) return;
+  Tile t;
+  t.inst = b;
+  t.pad = 0;
+  t.cell0 = 0;
+  t.ncell = cell_off[b + 1] - cell_off[b];
+  t.n = t.ncell;
+  t.base = dof_off[b];
+  for (int c = tid; c < RT; c += NT) {
+    L.sa[c] = a[(size_t)b * RT + c];
+    ap[c] = a_prev[(size_t)b * RT + c];
+  }
+  if (tid == 0) { stop = 0; nit = 0; }
+  const double dd = dvar[b];
+  unsigned fl = 0;
+  for (int it = it0; it < max_it; ++it) {
+    galerkin_tile<RT>(t, phys, nphys, Phi, qref, dvar, L);
+    for (int e = tid; e < RT * RT; e += NT) {
+      const int i = e / RT, j = e % RT;
+      J[i * LDJ + j] = (i == j ? 1.0 : 0.0) - dt * (double)L.redM[e];
+    }
+    for (int c = tid; c < RT; c += NT) g[c] = -(L.sa[c] - ap[c] - dt * dd * L.redG[c]);
+    __syncthreads();
+    const int ok = block_lu_solve(J, LDJ, g, RT);
+    if (tid < 64) {
+      double dm = 0.0, am = 0.0;
+      int fin = 1;
+      if (tid < RT) {
+        const double an = L.sa[tid] + g[tid];
+        L.sa[tid] = an;
+        dm = fabs(g[tid]);
+        am = fabs(an);
+        fin = isfinite(an) ? 1 : 0;
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        dm = fmax(dm, __shfl_xor(dm, off));
+        am = fmax(am, __shfl_xor(am, off));
+        fin &= __shfl_xor(fin, off);
+      }
+      if (tid == 0) {
+        nit += 1;
+        if (!ok) fl |= ROM_FLAG_SINGULAR;
+        if (!fin) fl |= ROM_FLAG_NONFINITE;
+        stop = (dm <= tol * (1.0 + am) || !fin) ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    if (stop) break;
+  }
+  for (int c = tid; c < RT; c += NT) a[(size_t)b * RT + c] = L.sa[c];
+  if (tid == 0) {
+    iters[b] += nit;
+    if (!stop) fl |= ROM_FLAG_ROM_NOCONV;
+    else active[b] = 0;
+    if (fl) atomicOr(&flags[b], fl);
+  }
 }
 
 // ------------------------------------------------------------------ iSVD rotation
@@ -361,6 +466,19 @@ rom_status launch_galerkin_mfma(rom_batch* h, hipStream_t s) {
                        h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const float*)h->Phi,
                        (const float*)h->q_ref, h->d_var, h->a, h->active, h->part,
                        (float*)h->mpart);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+rom_status launch_galerkin_tail(rom_batch* h, int it0, hipStream_t s) {
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(h->cfg.n_inst), dim3(64 * kGW), 0, s, h->d_cell_off,
+                       h->d_dof_off, h->d_phys, h->cfg.n_phys, (const float*)h->Phi,
+                       (const float*)h->q_ref, h->d_var, h->a, h->a_prev, h->active, h->iters,
+                       h->cfg.dt, h->cfg.rom_tol, it0, h->cfg.rom_max, h->flags);
+  };
+  if (h->cfg.r == 32) go(k_galerkin_tail<32>);
+  else go(k_galerkin_tail<64>);
   ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
 }

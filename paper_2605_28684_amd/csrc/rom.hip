@@ -709,29 +709,50 @@ __global__ void k_fill_i32(int32_t* dst, int32_t v, int64_t n) {
   if (i < n) dst[i] = v;
 }
 
+// a_prev <- a, active <- 1, iters <- 0 for every instance (one launch).
+__global__ void k_rom_step_setup(int n_inst, int r, const double* __restrict__ a,
+                                 double* __restrict__ a_prev, int32_t* __restrict__ active,
+                                 int32_t* __restrict__ iters) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (int64_t)n_inst * r) a_prev[i] = a[i];
+  if (i < n_inst) { active[i] = 1; iters[i] = 0; }
+}
+
+// Grid-wide Newton iterations of the Galerkin step kept in the captured launch
+// sequence when the MFMA pass applies; later iterations (rare) run in
+// k_galerkin_tail, one block per instance that has not converged.
+constexpr int kGridNewton = 2;
+
 template <typename T>
 rom_status galerkin_step_t(rom_batch* h, hipStream_t s) {
   const int r = h->cfg.r, B = h->cfg.n_inst;
   const int64_t nr = (int64_t)B * r;
-  hipLaunchKernelGGL(k_copy_f64, dim3((nr + 255) / 256), dim3(256), 0, s, h->a, h->a_prev, nr);
-  hipLaunchKernelGGL(k_fill_i32, dim3((B + 255) / 256), dim3(256), 0, s, h->active, 1, (int64_t)B);
-  hipLaunchKernelGGL(k_fill_i32, dim3((B + 255) / 256), dim3(256), 0, s, h->iters, 0, (int64_t)B);
+  const int64_t nset = std::max<int64_t>(nr, B);
+  hipLaunchKernelGGL(k_rom_step_setup, dim3((nset + 255) / 256), dim3(256), 0, s, B, r, h->a,
+                     h->a_prev, h->active, h->iters);
   double* gpart = h->part;
-  for (int it = 0; it < h->cfg.rom_max; ++it) {
-    if (mfma_ok(h)) {
+  if (mfma_ok(h)) {
+    const int ng = std::min(kGridNewton, h->cfg.rom_max);
+    for (int it = 0; it < ng; ++it) {
       rom_status st = launch_galerkin_mfma(h, s);
       if (st != ROM_OK) return st;
-      if (r == 32) {  // register-resident single-wave solve (r = 64 rows do not fit)
+      if (r == 32)  // register-resident single-wave solve (r = 64 rows do not fit)
         hipLaunchKernelGGL(k_galerkin_solve_w<32>, dim3(B), dim3(64), 0, s, h->d_ptile_first,
                            gpart, (const float*)h->mpart, h->cfg.dt, h->d_var, h->a, h->a_prev,
                            h->active, h->iters, h->cfg.rom_tol, h->flags);
-        continue;
-      }
-    } else {
-      hipLaunchKernelGGL((k_galerkin_pass<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
-                         h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const T*)h->Phi,
-                         r, (const T*)h->q_ref, h->d_var, h->a, h->active, gpart, (T*)h->mpart);
+      else
+        hipLaunchKernelGGL((k_galerkin_solve<float>), dim3(B), dim3(256), 0, s,
+                           h->d_ptile_first, gpart, (const float*)h->mpart, r, h->cfg.dt,
+                           h->d_var, h->a, h->a_prev, h->active, h->iters, h->cfg.rom_tol,
+                           h->flags);
     }
+    // remaining iterations and the non-convergence flag
+    return launch_galerkin_tail(h, ng, s);
+  }
+  for (int it = 0; it < h->cfg.rom_max; ++it) {
+    hipLaunchKernelGGL((k_galerkin_pass<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                       h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const T*)h->Phi,
+                       r, (const T*)h->q_ref, h->d_var, h->a, h->active, gpart, (T*)h->mpart);
     hipLaunchKernelGGL((k_galerkin_solve<T>), dim3(B), dim3(256), 0, s, h->d_ptile_first, gpart,
                        (const T*)h->mpart, r, h->cfg.dt, h->d_var, h->a, h->a_prev, h->active,
                        h->iters, h->cfg.rom_tol, h->flags);

@@ -320,6 +320,45 @@ def test_hr_lspg_step_parity(problem):
     assert G.relerr(G.host(h.get(R.GET_A)), a1) < 1e-11
 
 
+@pytest.mark.parametrize("r", [32, 64])
+def test_galerkin_step_tail_iterations_fp32(r):
+    """Newton iterations past the grid-wide ones run one block per instance: an
+    unattainable tolerance forces all rom_max iterations (the last ones in that
+    kernel) and the non-convergence flag; the iterate still matches the oracle's
+    converged step (the reduced residual is accumulated in FP64, so Newton sits
+    at its round-off level long before the cap)."""
+    import gpu_common as G
+    from paper_2605_28684_amd import romhip as R
+    cells = [2048, 700]
+    w = _burgers_batch(cells, W.F32, r)
+    w.phys = [dict(nu=0.003), dict(nu=0.006)]
+    w.rom_tol = 1e-300
+    h = _handle(w)
+    rng = np.random.default_rng(9)
+    Phis, sig, a, dv = [], [], [], []
+    qref = G.rounded(W.random_state(W.BURGERS, cells, seed=63, scale=0.3), W.F32)
+    off = w.offsets()
+    for b, n in enumerate(cells):
+        x = W.centres(n)
+        modes = np.stack([np.sin(2 * np.pi * (k + 1) * x + 0.3 * k) for k in range(r)], axis=1)
+        Q, _ = np.linalg.qr(modes + 0.01 * rng.normal(size=modes.shape))
+        Phis.append(G.rounded(Q, W.F32))
+        sig.append(np.linspace(5, 1, r))
+        a.append(rng.normal(size=r) * 3)
+        dv.append(np.array([1.5]))
+    _load_state(h, w, Phis, sig, a, qref, dv, W.F32)
+    h.set(R.GET_COUNTERS, [w.w_init, 0, 0, 0])
+    h.rom_step(1)
+    ag = G.host(h.get(R.GET_A))
+    assert (h.status() & 32).all()                 # ROM Newton hit its cap
+    for b, n in enumerate(cells):
+        sl = slice(off[b], off[b + 1])
+        d = np.full(n, dv[b][0])
+        ar, it, ok = O.galerkin_step(W.BURGERS, w.phys[b], qref[sl], d, Phis[b], a[b], w.dt,
+                                     1e-12, w.rom_max)
+        assert G.relerr(ag[b * r:(b + 1) * r], ar) < 1e-5, b
+
+
 @pytest.mark.parametrize("r", [8, 32, 64])
 def test_galerkin_fine_step_parity_fp32(r):
     """One FP32 Galerkin step of a ragged batch from identical state (no event);
