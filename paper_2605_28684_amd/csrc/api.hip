@@ -102,7 +102,7 @@ rom_status validate(const rom_config* c) {
   int64_t mn = INT64_MAX;
   for (int b = 0; b < c->n_inst; ++b) {
     ROM_REQUIRE(c->n_cells[b] >= 3, ROM_E_INVAL, "every instance needs at least 3 cells");
-    ROM_REQUIRE(c->n_cells[b] <= (int64_t)1 << 31, ROM_E_INVAL, "instance too large");
+    ROM_REQUIRE(c->n_cells[b] < (int64_t)1 << 31, ROM_E_INVAL, "instance too large");
     mn = std::min(mn, c->n_cells[b]);
   }
   const int nv = c->problem == ROM_REACT ? 12 : (c->problem == ROM_BURGERS ? 1 : 3);

@@ -41,48 +41,93 @@ DEV int64_t wrap_cell(int64_t c, int64_t n) { return c < 0 ? c + n : (c >= n ? c
 // ------------------------------------------------------------------ Galerkin pass
 constexpr int kGW = 8;  // waves per Galerkin block
 
-// LDS of one Galerkin block (8 waves).
+// LDS of one Galerkin block (8 waves).  Basis rows are padded to RT + 4 floats:
+// 16-byte aligned stores, and the row-wise reads of the reconstruction hit
+// distinct banks.
 template <int RT>
 struct GalerkinLds {
-  float sP[kGW][kCh + 2][RT + 1];
-  double sQ[kGW][kCh + 2];
-  double sF[kGW][kCh];
-  float sAl[kGW][kCh], sBe[kGW][kCh], sGa[kGW][kCh];
-  double sa[RT];        // the reduced state a (set by the caller)
-  float redM[RT * RT];  // Phi^T J_f Phi of the tile
-  double redG[RT];      // Phi^T f of the tile
+  float sP[kGW][kCh + 2][RT + 4];  // basis rows of the wave's window (see galerkin_tile)
+  double sQ[kGW][kCh + 2];         // q~ of those rows
+  float4 sJ[kGW][kCh];             // (alpha, beta, gamma, 0) of the 32 output rows
+  double sF[kGW][kCh];             // f of the 32 output rows
+  double sa[RT];                   // the reduced state a (set by the caller)
+  float redM[RT * RT];             // Phi^T J_f Phi of the tile
+  double redG[RT];                 // Phi^T f of the tile
 };
 
+// Prefetch of one window of 32 basis rows (stream rows 32 j + 2 .. 32 j + 33
+// of the wave, zero outside 0 .. m + 1) and of q_ref of those rows (lanes < 32).
+// Cell indices are instance-local (below 2^31).
+template <int RT, int NPF>
+DEV void galerkin_fetch(const float* __restrict__ Pb, const float* __restrict__ qb, int s_cell,
+                        int n, int m, int j, int lane, float4 (&pf)[NPF], float& pq) {
+  constexpr int NQ = RT / 4;
+  const int s0 = kCh * j + 2;
+  const int c0 = s_cell + s0;
+  if (s0 >= 0 && s0 + kCh - 1 <= m + 1 && c0 >= 0 && c0 + kCh - 1 < n) {
+    // the usual case: all 32 rows present and contiguous (no wrap-around)
+    const float4* src = reinterpret_cast<const float4*>(Pb + (int64_t)c0 * RT);
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) pf[u] = src[lane + 64 * u];
+    pq = qb[c0 + (lane & 31)];
+    return;
+  }
+#pragma unroll
+  for (int u = 0; u < NPF; ++u) {
+    const int e = lane + 64 * u;
+    const int s = s0 + e / NQ;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (s >= 0 && s <= m + 1) {
+      int c = s_cell + s;
+      c = c < 0 ? c + n : (c >= n ? c - n : c);
+      v = *reinterpret_cast<const float4*>(Pb + (int64_t)c * RT + 4 * (e % NQ));
+    }
+    pf[u] = v;
+  }
+  const int s = s0 + (lane & 31);
+  int c = s_cell + s;
+  c = c < 0 ? c + n : (c >= n ? c - n : c);
+  pq = (s >= 0 && s <= m + 1) ? qb[c] : 0.f;
+}
+
 // One block's share of a Galerkin pass: the rows of tile t (cells of one
-// instance).  Each wave streams its row range in 32-row chunks (next chunk
-// prefetched into registers, staged through LDS): q~ = q_ref + Phi a / d in
-// FP64, f(q~) and the three diagonals of J_f, then Phi^T f (FP64) and
-// Phi^T J_f Phi (v_mfma_f32_32x32x2f32).  The waves' sums are added in a fixed
-// order into L.redM / L.redG.  L.sa must hold a; ends with a block barrier.
+// instance).  Each wave owns m consecutive output rows and streams the m + 2
+// basis rows around them (its "stream": row s is cell lo - 1 + s) in windows
+// of 32: the LDS window holds stream rows 32 j .. 32 j + 33, the first two
+// carried over from the previous window, the other 32 prefetched into
+// registers while the previous window is processed.  Per window: q~ = q_ref +
+// Phi a / d in FP64 (two lanes per row), f(q~) and the three diagonals of J_f
+// for the 32 output rows 32 j + 1 .. 32 j + 32, then Phi^T f (FP64) and
+// Phi^T J_f Phi (v_mfma_f32_32x32x2f32, two rows per instruction).  Output
+// rows past m get zero coefficients and add nothing.  The waves' sums are
+// added in a fixed order into L.redM / L.redG.  L.sa must hold a; ends with a
+// block barrier.
 template <int RT>
 DEV void galerkin_tile(const Tile& t, const double* __restrict__ phys, int nphys,
                        const float* __restrict__ Phi, const float* __restrict__ qref,
                        const double* __restrict__ dvar, GalerkinLds<RT>& L) {
   constexpr int NCB = RT / 32;
-  constexpr int LDP = RT + 1;
-  constexpr int NV4 = (kCh + 2) * (RT / 4);       // float4 per chunk (with halo)
-  constexpr int NPF = (NV4 + 63) / 64;            // float4 per lane
+  constexpr int NQ = RT / 4;            // float4 per basis row
+  constexpr int NPF = kCh * NQ / 64;    // float4 per lane per window
+  constexpr int HC = RT / 2;            // columns per lane in the reconstruction
   constexpr int NT = 64 * kGW;
   const int b = t.inst;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int64_t n = t.n;
-  const int64_t base = t.base;
+  const int n = (int)t.n;
+  const float* __restrict__ Pb = Phi + t.base * RT;
+  const float* __restrict__ qb = qref + t.base;
   const double nu = phys[(size_t)b * nphys];
   const double dinv = 1.0 / dvar[b];
   const double inv = (double)n, inv2 = (double)n * (double)n;
   for (int c = tid; c < RT; c += NT) L.redG[c] = 0.0;
   for (int e = tid; e < RT * RT; e += NT) L.redM[e] = 0.f;
-  for (int e = tid; e < kGW * (kCh + 2) * LDP; e += NT) (&L.sP[0][0][0])[e] = 0.f;
   __syncthreads();
-  // this wave's rows of the tile
+  // this wave's output rows of the tile
   const int64_t per = ((t.ncell + kGW * kCh - 1) / (kGW * kCh)) * kCh;
   const int64_t lo = wave * per;
-  const int64_t hi = lo + per < t.ncell ? lo + per : t.ncell;
+  const int m = (int)((lo + per < t.ncell ? lo + per : t.ncell) - lo);
+  const int s_cell = (int)(t.cell0 + lo - 1);
+  const int nwin = m > 0 ? (m + kCh - 1) / kCh : 0;
   const int par = lane >> 5, cl = lane & 31;
   f32x16 acc[NCB][NCB];
 #pragma unroll
@@ -94,55 +139,55 @@ DEV void galerkin_tile(const Tile& t, const double* __restrict__ phys, int nphys
   double gacc[NCB];
 #pragma unroll
   for (int i = 0; i < NCB; ++i) gacc[i] = 0.0;
-  float(*P)[LDP] = L.sP[wave];
-  // register prefetch of one chunk: basis rows c0-1 .. c0+nr and q_ref of those rows
+  float(*P)[RT + 4] = L.sP[wave];
+  double* Q = L.sQ[wave];
   float4 pf[NPF];
   float pq = 0.f;
-  auto fetch = [&](int64_t r0) {
-    const int nr = (int)(hi - r0 < kCh ? hi - r0 : kCh);
-    const int64_t c0 = t.cell0 + r0;
-#pragma unroll
-    for (int u = 0; u < NPF; ++u) {
-      const int e4 = lane + 64 * u;
-      if (e4 < (nr + 2) * (RT / 4)) {
-        const int row = e4 / (RT / 4), col = (e4 % (RT / 4)) * 4;
-        const int64_t cell = wrap_cell(c0 - 1 + row, n);
-        pf[u] = *reinterpret_cast<const float4*>(Phi + (base + cell) * RT + col);
-      }
-    }
-    if (lane < nr + 2) pq = qref[base + wrap_cell(c0 - 1 + lane, n)];
-  };
-  if (lo < hi) fetch(lo);
-  for (int64_t r0 = lo; r0 < hi; r0 += kCh) {
-    const int nr = (int)(hi - r0 < kCh ? hi - r0 : kCh);
-#pragma unroll
-    for (int u = 0; u < NPF; ++u) {
-      const int e4 = lane + 64 * u;
-      if (e4 < (nr + 2) * (RT / 4)) {
-        const int row = e4 / (RT / 4), col = (e4 % (RT / 4)) * 4;
-        P[row][col] = pf[u].x; P[row][col + 1] = pf[u].y;
-        P[row][col + 2] = pf[u].z; P[row][col + 3] = pf[u].w;
-      }
-    }
-    const double qr = (double)pq;
+  // window -1 brings stream rows 0 and 1 (into LDS rows 32, 33)
+  if (nwin > 0) galerkin_fetch<RT, NPF>(Pb, qb, s_cell, n, m, -1, lane, pf, pq);
+  for (int j = -1; j < nwin; ++j) {
     wave_sync();
-    if (r0 + kCh < hi) fetch(r0 + kCh);     // overlaps the compute below
-    if (lane < nr + 2) {
+    // carry rows 32, 33 to 0, 1, then store the prefetched rows into 2 .. 33
+#pragma unroll
+    for (int v = 0; v < 2 * RT / 64; ++v) {
+      const int e = lane + 64 * v;
+      const float x = P[kCh + e / RT][e % RT];
+      P[e / RT][e % RT] = x;
+    }
+    if (lane < 2) Q[lane] = Q[kCh + lane];
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) {
+      const int e = lane + 64 * u;
+      *reinterpret_cast<float4*>(&P[2 + e / NQ][4 * (e % NQ)]) = pf[u];
+    }
+    const float qr = pq;
+    wave_sync();
+    if (j + 1 < nwin) galerkin_fetch<RT, NPF>(Pb, qb, s_cell, n, m, j + 1, lane, pf, pq);
+    // q~ of rows 2 .. 33: lanes r and r + 32 take the two halves of row 2 + r
+    {
+      const float* pr = &P[2 + cl][par * HC];
+      const double* ar = &L.sa[par * HC];
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll 2
-      for (int c = 0; c < RT; c += 4) {
-        s0 += (double)P[lane][c] * L.sa[c];
-        s1 += (double)P[lane][c + 1] * L.sa[c + 1];
-        s2 += (double)P[lane][c + 2] * L.sa[c + 2];
-        s3 += (double)P[lane][c + 3] * L.sa[c + 3];
+#pragma unroll
+      for (int c = 0; c < HC; c += 4) {
+        const float4 p = *reinterpret_cast<const float4*>(pr + c);
+        s0 += (double)p.x * ar[c];
+        s1 += (double)p.y * ar[c + 1];
+        s2 += (double)p.z * ar[c + 2];
+        s3 += (double)p.w * ar[c + 3];
       }
-      L.sQ[wave][lane] = qr + ((s0 + s1) + (s2 + s3)) * dinv;
+      double s = (s0 + s1) + (s2 + s3);
+      s += __shfl_xor(s, 32);
+      if (par == 0) Q[2 + cl] = (double)qr + s * dinv;
     }
     wave_sync();
+    if (j < 0) continue;
+    // f and the Jacobian diagonals of output rows 1 .. 32 (stream 32 j + 1 ..)
     if (lane < kCh) {
+      const int i = lane + 1;
       double f = 0.0, al = 0.0, be = 0.0, ga = 0.0;
-      if (lane < nr) {
-        const double um = L.sQ[wave][lane], u0 = L.sQ[wave][lane + 1], up = L.sQ[wave][lane + 2];
+      if (kCh * j + i <= m) {
+        const double um = Q[i - 1], u0 = Q[i], up = Q[i + 1];
         double dla, dlb, dra, drb;
         const double FL = godunov(um, u0, dla, dlb);
         const double FR = godunov(u0, up, dra, drb);
@@ -152,25 +197,27 @@ DEV void galerkin_tile(const Tile& t, const double* __restrict__ phys, int nphys
         ga = -drb * inv + nu * inv2;
       }
       L.sF[wave][lane] = f;
-      L.sAl[wave][lane] = (float)al;
-      L.sBe[wave][lane] = (float)be;
-      L.sGa[wave][lane] = (float)ga;
+      L.sJ[wave][lane] = make_float4((float)al, (float)be, (float)ga, 0.f);
     }
     wave_sync();
+    // output row i = 2 k + 1 + par: A = Phi row i, Z = (J_f Phi) row i
+    float pm[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) pm[cb] = P[par][cb * 32 + cl];
 #pragma unroll 4
     for (int k = 0; k < kCh / 2; ++k) {
-      const int row = 2 * k + par;
-      const bool live = row < nr;
-      const float al = L.sAl[wave][row], be = L.sBe[wave][row], ga = L.sGa[wave][row];
-      const double fr = L.sF[wave][row];
+      const int i = 2 * k + 1 + par;
+      const float4 J = L.sJ[wave][i - 1];
+      const double fr = L.sF[wave][i - 1];
       float A[NCB], Z[NCB];
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
         const int col = cb * 32 + cl;
-        const float p0 = P[row + 1][col];
-        A[cb] = live ? p0 : 0.f;
-        Z[cb] = live ? (al * P[row][col] + be * p0 + ga * P[row + 2][col]) : 0.f;
-        gacc[cb] += (double)A[cb] * fr;
+        const float p0 = P[i][col], pp = P[i + 1][col];
+        A[cb] = p0;
+        Z[cb] = J.x * pm[cb] + J.y * p0 + J.z * pp;
+        gacc[cb] += (double)p0 * fr;
+        pm[cb] = pp;
       }
 #pragma unroll
       for (int ca = 0; ca < NCB; ++ca)
@@ -178,7 +225,6 @@ DEV void galerkin_tile(const Tile& t, const double* __restrict__ phys, int nphys
         for (int cb = 0; cb < NCB; ++cb)
           acc[ca][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[ca], Z[cb], acc[ca][cb], 0, 0, 0);
     }
-    wave_sync();
   }
   // combine the two row parities of Phi^T f, then the waves in order
 #pragma unroll
@@ -204,8 +250,11 @@ DEV void galerkin_tile(const Tile& t, const double* __restrict__ phys, int nphys
   }
 }
 
+// r = 32: two blocks (16 waves) per CU, which the LDS allows; r = 64 is held to
+// one block per CU by its LDS.
 template <int RT>
-__global__ __launch_bounds__(64 * kGW) void k_galerkin_mfma(
+__global__ __launch_bounds__(64 * kGW)
+__attribute__((amdgpu_waves_per_eu(RT == 32 ? 4 : 1))) void k_galerkin_mfma(
     const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off,
     const int64_t* __restrict__ cell_off, const double* __restrict__ phys, int nphys,
     const float* __restrict__ Phi, const float* __restrict__ qref,

@@ -196,20 +196,47 @@ __global__ __launch_bounds__(256) void k_galerkin_solve(
 }
 
 // The same reduced Newton step for r = RT = 32 (the FP32 MFMA path), by
-// one wavefront and no block barriers: lane i sums row i of the tile partials
-// (J_g row i and g_i) into registers, then LU with partial pivoting runs on the
-// register rows -- each column's pivot is the wave-wide argmax of the remaining
-// rows (lowest row on ties), its row is broadcast through LDS and every
-// remaining lane eliminates its own row; no rows move, only the pivot order is
-// recorded.  Back-substitution walks the pivot order from the last column.
+// one wavefront with no LDS and no barriers: lane i sums row i of the tile
+// partials (J_g row i and g_i) into registers, then LU with partial pivoting
+// runs on the register rows.  Each column's pivot is the argmax of |J_g| over
+// the remaining rows (lowest row on ties) by DPP exchanges within and then
+// across the 16-lane rows (the winner ends in lane RT - 1).  The pivot row is broadcast by lane
+// permutes and every remaining lane eliminates its own row with the pivot's
+// reciprocal; no rows move, only the pivot order is recorded.
+// Back-substitution walks the pivot order from the last column.
+// One exchange of a wave argmax of (v, idx), ties to the lower index: lanes in
+// the rows of ROWMASK take the DPP source CTRL, the other lanes keep their own.
+template <int CTRL, int ROWMASK>
+DEV void amax_dpp(double& v, int& idx) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = (int)(unsigned)u, hi = (int)(unsigned)(u >> 32);
+  const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
+  const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
+  const int oi = __builtin_amdgcn_update_dpp(idx, idx, CTRL, ROWMASK, 0xF, false);
+  const double ov = __builtin_bit_cast(
+      double, ((unsigned long long)(unsigned)ohi << 32) | (unsigned long long)(unsigned)olo);
+  const bool take = (ov > v) | ((ov == v) & (oi < idx));
+  v = take ? ov : v;
+  idx = take ? oi : idx;
+}
+
+DEV double readlane_d(double x, int l) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// One wave per instance and a few hundred instances: occupancy is irrelevant,
+// registers are spent on keeping the broadcasts in flight.
 template <int RT>
-__global__ __launch_bounds__(64) void k_galerkin_solve_w(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void k_galerkin_solve_w(
     const int* __restrict__ tfirst, const double* __restrict__ gpart,
     const float* __restrict__ mpart, double dt, const double* __restrict__ dvar,
     double* __restrict__ a, const double* __restrict__ a_prev, int32_t* __restrict__ active,
     int32_t* __restrict__ iters, double tol, uint32_t* flags) {
-  __shared__ double prow[RT + 1];
-  __shared__ double xs[RT];
+  static_assert(RT == 32 || RT == 64, "rows of 16 lanes");
   const int b = blockIdx.x, lane = threadIdx.x;
   if (!active[b]) return;
   const bool row = lane < RT;
@@ -237,49 +264,48 @@ __global__ __launch_bounds__(64) void k_galerkin_solve_w(
   double bi = -(ai - a_prev[(size_t)b * RT + li] - dt * dvar[b] * gs);
   bool used = !row;
   int ord = -1;
-  int ok = 1;
+  int okv = 1;
+  int pivl = 0;       // lane k: the pivot lane of column k
+  double myr = 0.0;   // pivot lane: the reciprocal of its pivot
 #pragma unroll
   for (int k = 0; k < RT; ++k) {
     double v = used ? -1.0 : fabs(A[k]);
     int idx = lane;
+    amax_dpp<0xB1, 0xF>(v, idx);   // quad_perm [1,0,3,2]
+    amax_dpp<0x4E, 0xF>(v, idx);   // quad_perm [2,3,0,1]
+    amax_dpp<0x141, 0xF>(v, idx);  // row_half_mirror
+    amax_dpp<0x140, 0xF>(v, idx);  // row_mirror: each 16-lane row holds its best
+    amax_dpp<0x142, 0xA>(v, idx);  // row_bcast:15 into rows 1, 3
+    if (RT > 32) amax_dpp<0x143, 0xC>(v, idx);  // row_bcast:31 into rows 2, 3
+    const int p = __builtin_amdgcn_readlane(idx, RT - 1);
+    okv &= (v != 0.0) ? 1 : 0;  // lane RT - 1 holds the pivot magnitude
+    const double pk = readlane_d(A[k], p);
+    const double rp = pk != 0.0 ? 1.0 / pk : 0.0;
+    if (lane == k) pivl = p;
+    // rows already pivoted and the pivot row itself keep their values (f = 0)
+    const double f = (used || lane == p) ? 0.0 : A[k] * rp;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(v, off);
-      const int oi = __shfl_xor(idx, off);
-      if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-    }
-    const int p = __builtin_amdgcn_readfirstlane(idx);
-    if (v == 0.0) ok = 0;
+    for (int j = k + 1; j < RT; ++j) A[j] -= f * __shfl(A[j], p);
+    bi -= f * __shfl(bi, p);
     if (lane == p) {
-#pragma unroll
-      for (int j = k; j < RT; ++j) prow[j] = A[j];
-      prow[RT] = bi;
       used = true;
       ord = k;
+      myr = rp;
     }
-    lds_wave_sync();
-    if (!used) {
-      const double pk = prow[k];
-      const double f = pk != 0.0 ? A[k] / pk : 0.0;
-#pragma unroll
-      for (int j = k + 1; j < RT; ++j) A[j] -= f * prow[j];
-      bi -= f * prow[RT];
-    }
-    lds_wave_sync();
   }
-  // back-substitution: the lane with pivot order k holds row k of U
+  const int ok = __builtin_amdgcn_readlane(okv, RT - 1);
+  // back-substitution: the pivot lane of column k holds row k of U and its
+  // right-hand side; rows solved earlier are not read again
+  double del = 0.0;
 #pragma unroll
   for (int k = RT - 1; k >= 0; --k) {
-    if (ord == k) xs[k] = A[k] != 0.0 ? bi / A[k] : 0.0;
-    lds_wave_sync();
-    const double xk = xs[k];
-    if (ord >= 0 && ord < k) bi -= A[k] * xk;
+    const double xk = readlane_d(bi * myr, __builtin_amdgcn_readlane(pivl, k));
+    bi -= A[k] * xk;
+    if (lane == k) del = xk;
   }
-  lds_wave_sync();
   double dm = 0.0, am = 0.0;
   int fin = 1;
   if (row) {
-    const double del = xs[lane];
     const double an = ai + del;
     a[(size_t)b * RT + lane] = an;
     dm = fabs(del);
