@@ -138,9 +138,10 @@ def profile_only(args, torch, W, R):
             if args.steps:
                 h.rom_step(w.z * args.steps)
             torch.cuda.synchronize()
+            t1 = time.perf_counter()
             h.close()
         log("windows: %d after %d warm-up, %.3f ms each" % (
-            args.steps, args.warmup, 1e3 * (time.perf_counter() - t0) / max(args.steps, 1)))
+            args.steps, args.warmup, 1e3 * (t1 - t0) / max(args.steps, 1)))
     elif args.only == "galerkin":
         w = W.burgers_batch_f32()
         s = torch.cuda.Stream()

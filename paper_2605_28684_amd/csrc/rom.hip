@@ -195,29 +195,24 @@ __global__ __launch_bounds__(256) void k_galerkin_solve(
   }
 }
 
-// The same reduced Newton step for r = RT = 32 (the FP32 MFMA path), by
-// one wavefront with no LDS and no barriers: lane i sums row i of the tile
-// partials (J_g row i and g_i) into registers, then LU with partial pivoting
-// runs on the register rows.  Each column's pivot is the argmax of |J_g| over
-// the remaining rows (lowest row on ties) by DPP exchanges within and then
-// across the 16-lane rows (the winner ends in lane RT - 1).  The pivot row is broadcast by lane
-// permutes and every remaining lane eliminates its own row with the pivot's
-// reciprocal; no rows move, only the pivot order is recorded.
-// Back-substitution walks the pivot order from the last column.
-// One exchange of a wave argmax of (v, idx), ties to the lower index: lanes in
-// the rows of ROWMASK take the DPP source CTRL, the other lanes keep their own.
+// One exchange of a wave max of v: lanes in the rows of ROWMASK combine with
+// the DPP source CTRL, the other lanes keep their own value.  (A compare and
+// select: a NaN never replaces a number, and the maximum of numbers is exact.)
 template <int CTRL, int ROWMASK>
-DEV void amax_dpp(double& v, int& idx) {
+DEV double max_dpp(double v) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
   const int lo = (int)(unsigned)u, hi = (int)(unsigned)(u >> 32);
-  const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
-  const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
-  const int oi = __builtin_amdgcn_update_dpp(idx, idx, CTRL, ROWMASK, 0xF, false);
-  const double ov = __builtin_bit_cast(
-      double, ((unsigned long long)(unsigned)ohi << 32) | (unsigned long long)(unsigned)olo);
-  const bool take = (ov > v) | ((ov == v) & (oi < idx));
-  v = take ? ov : v;
-  idx = take ? oi : idx;
+  int olo, ohi;
+  if (ROWMASK == 0xF) {
+    olo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+    ohi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
+  } else {
+    olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
+    ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
+  }
+  const double o = __builtin_bit_cast(double, ((unsigned long long)(unsigned)ohi << 32) |
+                                                  (unsigned long long)(unsigned)olo);
+  return o > v ? o : v;
 }
 
 DEV double readlane_d(double x, int l) {
@@ -227,8 +222,29 @@ DEV double readlane_d(double x, int l) {
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-// One wave per instance and a few hundred instances: occupancy is irrelevant,
-// registers are spent on keeping the broadcasts in flight.
+// The value that lane (l & 31) + 32 H holds, for every lane l (H = 0 or 1):
+// v_permlane32_swap with both operands x returns the half-0 copy in its first
+// and the half-1 copy in its second result.
+template <int H>
+DEV double half_value(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi[H] << 32) | (unsigned)lo[H]);
+}
+
+// The same reduced Newton step for r = 32 (the FP32 MFMA path), by one
+// wavefront with no LDS and no barriers.  Lane l holds row l & 31 of J_g,
+// the even columns in lanes 0-31 and the odd ones in lanes 32-63, summed
+// from the tile partials into registers; the right-hand side is kept in both
+// halves.  LU with partial pivoting runs on the register rows: the pivot of
+// column k is the lowest remaining row attaining max |J_g[:, k]| (a DPP max
+// inside the half that holds column k, then a ballot), each row's
+// column-k entry reaches the other half by a cross-half lane swap, the pivot
+// row is broadcast by lane permutes, and every remaining row is eliminated
+// with the pivot's reciprocal.  No rows move; the pivot order is recorded.
+// Back-substitution walks the pivot order from the last column, each half
+// summing the products of its own columns.
 template <int RT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void k_galerkin_solve_w(
@@ -236,78 +252,83 @@ void k_galerkin_solve_w(
     const float* __restrict__ mpart, double dt, const double* __restrict__ dvar,
     double* __restrict__ a, const double* __restrict__ a_prev, int32_t* __restrict__ active,
     int32_t* __restrict__ iters, double tol, uint32_t* flags) {
-  static_assert(RT == 32 || RT == 64, "rows of 16 lanes");
+  static_assert(RT == 32, "two columns per lane pair, 32 rows");
+  constexpr int NL = RT / 2;   // columns per lane
   const int b = blockIdx.x, lane = threadIdx.x;
   if (!active[b]) return;
-  const bool row = lane < RT;
-  const int li = row ? lane : 0;
+  const int i = lane & 31, h = lane >> 5;
   const int t0 = tfirst[b], t1 = tfirst[b + 1];
-  double A[RT];
+  double A[NL];
 #pragma unroll
-  for (int j = 0; j < RT; ++j) A[j] = 0.0;
+  for (int jj = 0; jj < NL; ++jj) A[jj] = 0.0;
   double gs = 0.0;
   for (int tt = t0; tt < t1; ++tt) {
-    const float4* mr = reinterpret_cast<const float4*>(mpart + (size_t)tt * kMaxR * kMaxR + li * RT);
+    const float2* mr = reinterpret_cast<const float2*>(mpart + (size_t)tt * kMaxR * kMaxR + i * RT);
 #pragma unroll
-    for (int j4 = 0; j4 < RT / 4; ++j4) {
-      const float4 v = mr[j4];
-      A[4 * j4] += (double)v.x;
-      A[4 * j4 + 1] += (double)v.y;
-      A[4 * j4 + 2] += (double)v.z;
-      A[4 * j4 + 3] += (double)v.w;
+    for (int jj = 0; jj < NL; ++jj) {
+      const float2 v = mr[jj];
+      A[jj] += (double)(h ? v.y : v.x);
     }
-    gs += gpart[(size_t)tt * kMaxR + li];
+    gs += gpart[(size_t)tt * kMaxR + i];
   }
 #pragma unroll
-  for (int j = 0; j < RT; ++j) A[j] = (j == li ? 1.0 : 0.0) - dt * A[j];
-  const double ai = a[(size_t)b * RT + li];
-  double bi = -(ai - a_prev[(size_t)b * RT + li] - dt * dvar[b] * gs);
-  bool used = !row;
+  for (int jj = 0; jj < NL; ++jj) A[jj] = (2 * jj + h == i ? 1.0 : 0.0) - dt * A[jj];
+  const double ai = a[(size_t)b * RT + i];
+  double bi = -(ai - a_prev[(size_t)b * RT + i] - dt * dvar[b] * gs);
+  bool used = false;
   int ord = -1;
-  int okv = 1;
-  int pivl = 0;       // lane k: the pivot lane of column k
-  double myr = 0.0;   // pivot lane: the reciprocal of its pivot
+  int pivl = 0;       // lane k: the pivot row of column k
+  double myr = 0.0;   // pivot rows: the reciprocal of their pivot
 #pragma unroll
   for (int k = 0; k < RT; ++k) {
-    double v = used ? -1.0 : fabs(A[k]);
-    int idx = lane;
-    amax_dpp<0xB1, 0xF>(v, idx);   // quad_perm [1,0,3,2]
-    amax_dpp<0x4E, 0xF>(v, idx);   // quad_perm [2,3,0,1]
-    amax_dpp<0x141, 0xF>(v, idx);  // row_half_mirror
-    amax_dpp<0x140, 0xF>(v, idx);  // row_mirror: each 16-lane row holds its best
-    amax_dpp<0x142, 0xA>(v, idx);  // row_bcast:15 into rows 1, 3
-    if (RT > 32) amax_dpp<0x143, 0xC>(v, idx);  // row_bcast:31 into rows 2, 3
-    const int p = __builtin_amdgcn_readlane(idx, RT - 1);
-    okv &= (v != 0.0) ? 1 : 0;  // lane RT - 1 holds the pivot magnitude
-    const double pk = readlane_d(A[k], p);
+    const int hk = k & 1, kk = k >> 1;
+    const double cand = used ? -1.0 : fabs(A[kk]);
+    double v = max_dpp<0xB1, 0xF>(cand);   // quad_perm [1,0,3,2]
+    v = max_dpp<0x4E, 0xF>(v);              // quad_perm [2,3,0,1]
+    v = max_dpp<0x141, 0xF>(v);             // row_half_mirror
+    v = max_dpp<0x140, 0xF>(v);             // row_mirror: each 16-lane row holds its max
+    v = max_dpp<0x142, 0xA>(v);             // row_bcast:15 into rows 1, 3
+    const double vmax = readlane_d(v, hk ? 63 : 31);  // max of the half holding column k
+    // the pivot: the lowest row of that half attaining the max (any remaining
+    // row if the column holds no number)
+    unsigned long long m = __ballot((cand == vmax) & (h == hk));
+    if (m == 0) m = __ballot(!used & (h == hk));
+    const int p = (__ffsll((long long)m) - 1) & 31;   // pivot row
+    const double ck = hk ? half_value<1>(A[kk]) : half_value<0>(A[kk]);  // row's column-k entry
+    const double pk = readlane_d(A[kk], p + 32 * hk);
     const double rp = pk != 0.0 ? 1.0 / pk : 0.0;
     if (lane == k) pivl = p;
     // rows already pivoted and the pivot row itself keep their values (f = 0)
-    const double f = (used || lane == p) ? 0.0 : A[k] * rp;
-#pragma unroll
-    for (int j = k + 1; j < RT; ++j) A[j] -= f * __shfl(A[j], p);
-    bi -= f * __shfl(bi, p);
-    if (lane == p) {
+    const double f = (used || i == p) ? 0.0 : ck * rp;
+    if (i == p) {
       used = true;
       ord = k;
       myr = rp;
     }
+    const int from = p + 32 * h;   // the pivot row's copy of this lane's columns
+#pragma unroll
+    for (int jj = kk; jj < NL; ++jj) A[jj] -= f * __shfl(A[jj], from);
+    bi -= f * readlane_d(bi, p);
   }
-  const int ok = __builtin_amdgcn_readlane(okv, RT - 1);
-  // back-substitution: the pivot lane of column k holds row k of U and its
-  // right-hand side; rows solved earlier are not read again
-  double del = 0.0;
+  // a zero pivot leaves a zero reciprocal on its row
+  const int ok = __ballot((h == 0) & (myr == 0.0)) == 0ull;
+  // back-substitution: x_k = (c_q - s0_q - s1_q) / U_qk for the pivot row q of
+  // column k, where s0 and s1 are the products already subtracted by the even
+  // and odd columns
+  double sh = 0.0, del = 0.0;
 #pragma unroll
   for (int k = RT - 1; k >= 0; --k) {
-    const double xk = readlane_d(bi * myr, __builtin_amdgcn_readlane(pivl, k));
-    bi -= A[k] * xk;
-    if (lane == k) del = xk;
+    const int hk = k & 1, kk = k >> 1;
+    const double st = half_value<0>(sh) + half_value<1>(sh);
+    const double xk = readlane_d((bi - st) * myr, __builtin_amdgcn_readlane(pivl, k));
+    if (h == hk) sh += A[kk] * xk;
+    if (i == k) del = xk;
   }
   double dm = 0.0, am = 0.0;
   int fin = 1;
-  if (row) {
+  if (h == 0) {
     const double an = ai + del;
-    a[(size_t)b * RT + lane] = an;
+    a[(size_t)b * RT + i] = an;
     dm = fabs(del);
     am = fabs(an);
     fin = isfinite(an) ? 1 : 0;
