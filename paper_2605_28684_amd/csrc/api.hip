@@ -151,10 +151,23 @@ void free_all(rom_batch* h) {
                 h->Phi, h->sigma, h->a, h->a_prev, h->q_ref, h->d_var, h->y_corr, h->flags, h->P,
                 h->M, h->mesh_phi, h->mesh_qref, h->chosen, h->part, h->red, h->ubar, h->lmat,
                 h->active, h->iters, h->norms, h->rstate, h->qtmp, h->mpart, h->fq, h->fq_prev, h->vjp_tmp,
-                h->d_epoch, h->rvjp};
+                h->d_epoch, h->rvjp, h->epart, h->ev_iters};
   for (void* p : ps) (void)hipFree(p);
   bt_free(h);
   if (h->win_exec) (void)hipGraphExecDestroy(h->win_exec);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->aux) (void)hipStreamDestroy(h->aux);
+}
+
+// The event at the end of a window (coarse step of y_corr, then the iSVD
+// projections and core SVD) reads nothing the window's fine steps write, and
+// the fine steps read nothing it writes, when the steps are Galerkin on the
+// MFMA path (partials in part and mpart, the projections' in epart) and the
+// coarse step is the one-workgroup kernel (its counters in ev_iters).  Only
+// the state transfer and the rotation of Phi need the fine steps done.
+bool window_split_ok(const rom_batch* h) {
+  return h->cfg.hyper == ROM_HR_NONE && mfma_ok(h) && h->fom_block;
 }
 
 rom_status setup(rom_batch* h) {
@@ -245,6 +258,8 @@ rom_status setup(rom_batch* h) {
   ROM_TRY(alloc(&h->rstate, (size_t)B * (kMaxR * kMaxR + 4 * kMaxR)));
   ROM_TRY(alloc(&h->qtmp, (size_t)td));
   ROM_TRY(alloc((char**)&h->mpart, es * std::max(h->n_ptiles, 1) * kMaxR * kMaxR));
+  ROM_TRY(alloc(&h->epart, (size_t)std::max(h->n_ptiles, 1) * kMaxR * kMaxR));
+  ROM_TRY(alloc(&h->ev_iters, B));
   ROM_TRY(alloc(&h->d_epoch, 1));
   ROM_HIP_CHECK(hipMemset(h->flags, 0, 4 * B));
   ROM_HIP_CHECK(hipMemset(h->chosen, 0, 4 * td));
@@ -254,6 +269,11 @@ rom_status setup(rom_batch* h) {
   ROM_HIP_CHECK(hipMemset(h->sigma, 0, 8 * (size_t)B * r));
   ROM_TRY(bt_setup(h));
   h->fom_block = fom_block_ok(h);
+  if (window_split_ok(h)) {  // the second stream of a window (created outside any capture)
+    ROM_HIP_CHECK(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+    ROM_HIP_CHECK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    ROM_HIP_CHECK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+  }
   ROM_TRY(isvd_kernels_prepare());
   ROM_TRY(rom_kernels_prepare());
   ROM_HIP_CHECK(hipDeviceSynchronize());
@@ -309,6 +329,30 @@ rom_status isvd_impl(rom_batch* h, const void* y, hipStream_t s) {
     ROM_TRY(launch_reorth(h, s));
     h->n_reorth += 1;
   }
+  return ROM_OK;
+}
+
+// One whole window with that overlap: the event chain on a second stream,
+// forked from s at the start and joined before the transfer and rotation.
+// The kernels and their inputs are those of the serial order, so the results
+// are the same.
+rom_status window_split_impl(rom_batch* h, hipStream_t s) {
+  ROM_REQUIRE(h->aux && h->ev_fork && h->ev_join, ROM_E_STATE, "no second stream");
+  const int z = h->cfg.z;
+  ROM_HIP_CHECK(hipEventRecord(h->ev_fork, s));
+  ROM_HIP_CHECK(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
+  rom_status st = launch_fom_block(h, h->y_corr, z * h->cfg.dt, h->y_corr, h->ev_iters, h->aux);
+  if (st == ROM_OK) st = launch_isvd_core(h, h->y_corr, h->epart, h->aux);
+  // join even after an error, so that a capture in progress ends consistently
+  ROM_HIP_CHECK(hipEventRecord(h->ev_join, h->aux));
+  for (int k = 0; k < z && st == ROM_OK; ++k) st = launch_rom_fine_step(h, s);
+  ROM_HIP_CHECK(hipStreamWaitEvent(s, h->ev_join, 0));
+  ROM_TRY(st);
+  ROM_TRY(launch_isvd_apply(h, s));
+  h->n_update += 1;
+  ROM_TRY(launch_rebuild(h, s));
+  h->n_events += 1;
+  h->n_fine += z;
   return ROM_OK;
 }
 
@@ -462,7 +506,9 @@ rom_status rom_step(rom_handle h, int32_t n_fine, void* stream) {
         ROM_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         rom_status st = ROM_OK;
         const int64_t nf = h->n_fine, nu = h->n_update, ne = h->n_events;
-        for (int k = 0; k < z && st == ROM_OK; ++k) st = fine_step_impl(h, s);
+        if (window_split_ok(h)) st = window_split_impl(h, s);
+        else
+          for (int k = 0; k < z && st == ROM_OK; ++k) st = fine_step_impl(h, s);
         hipError_t e = hipStreamEndCapture(s, &g);
         h->n_fine = nf; h->n_update = nu; h->n_events = ne;  // captured, not yet run
         if (st != ROM_OK) { if (g) (void)hipGraphDestroy(g); return st; }

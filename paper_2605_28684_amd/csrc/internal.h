@@ -129,6 +129,8 @@ struct rom_batch {
   double* rstate = nullptr;  // reduced Newton workspace [n_inst * (r*r + 4r)]
   double* qtmp = nullptr;    // first Gram-Schmidt residual [total_dof] (FP64)
   void* mpart = nullptr;     // Galerkin block partials of Phi^T J Phi [n_ptiles * kMaxR^2] (T)
+  double* epart = nullptr;   // projection partials of the event chain [n_ptiles * kMaxR^2]
+  int32_t* ev_iters = nullptr; // Newton counters of the event's coarse step [n_inst]
   uint32_t* d_epoch = nullptr; // DEIM epoch counter (device)
 
   // full-order Newton workspace
@@ -151,6 +153,10 @@ struct rom_batch {
   // graphs of one adaptation window
   hipGraphExec_t win_exec = nullptr;
   hipStream_t win_stream = nullptr;
+  // second stream of a window: the event's coarse step, projections and core
+  // SVD run beside the fine steps (they share no written data)
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace romhip {
@@ -178,6 +184,10 @@ rom_status bt_solve(rom_batch* h, int it, void* q_update, void* out, hipStream_t
 
 // ---- isvd.hip
 rom_status launch_isvd(rom_batch* h, const void* y, hipStream_t s);
+// The two halves of launch_isvd: projections and core SVD (partials in part),
+// then the state transfer and the basis rotation.
+rom_status launch_isvd_core(rom_batch* h, const void* y, double* part, hipStream_t s);
+rom_status launch_isvd_apply(rom_batch* h, hipStream_t s);
 rom_status launch_reorth(rom_batch* h, hipStream_t s);
 rom_status launch_pod(rom_batch* h, const void* Q, int w, hipStream_t s);  // Q: T[w * total_dof]
 rom_status launch_preprocess(rom_batch* h, const void* q0, const void* Q, int w, hipStream_t s);
@@ -211,7 +221,7 @@ rom_status launch_galerkin_mfma(rom_batch* h, hipStream_t s);
 rom_status launch_galerkin_tail(rom_batch* h, int it0, hipStream_t s);
 rom_status launch_rotate_mfma(rom_batch* h, const double* pr, hipStream_t s);
 rom_status launch_project_fast(rom_batch* h, const void* y, const double* p1, int ldp, int mode,
-                               int pst, double* q1out, hipStream_t s);
+                               double* part, int pst, double* q1out, hipStream_t s);
 
 // ---- small helpers (api.cpp)
 rom_status fill_zero(void* p, size_t bytes, hipStream_t s);

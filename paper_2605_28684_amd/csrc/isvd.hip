@@ -585,7 +585,7 @@ DEV bool arrow_svd_wave(const double* K, double* Uc, double* U, double* sv, doub
 template <int NF>
 __global__ __launch_bounds__(64) void k_isvd_core(int r, double lambda, double tau_rho,
                                                   const double* __restrict__ red, int ldr,
-                                                  double* __restrict__ sigma, double* __restrict__ a,
+                                                  double* __restrict__ sigma,
                                                   double* __restrict__ ubar, double* __restrict__ pr,
                                                   uint32_t* flags) {
   extern __shared__ double sm[];
@@ -631,20 +631,31 @@ __global__ __launch_bounds__(64) void k_isvd_core(int r, double lambda, double t
     __syncthreads();
   }
   for (int c = tid; c < r; c += blockDim.x) sigma[(size_t)b * r + c] = sv[c];
-  // closed-form transfer: a <- Ubar[:r, :r]^T a  (the new direction is orthogonal to Phi)
-  for (int c = tid; c < r; c += blockDim.x) {
-    double s = 0.0;
-    for (int k = 0; k < r; ++k) s += U[k * n + c] * a[(size_t)b * r + k];
-    ta[c] = s;
-  }
-  __syncthreads();
-  for (int c = tid; c < r; c += blockDim.x) a[(size_t)b * r + c] = ta[c];
   // p1, p2 (kept apart: the rotation subtracts them one after the other) and 1/rho
   for (int c = tid; c < r; c += blockDim.x) {
     pr[(size_t)b * (2 * r + 2) + c] = R[c];
     pr[(size_t)b * (2 * r + 2) + r + c] = R[r + 1 + c];
   }
   if (tid == 0) pr[(size_t)b * (2 * r + 2) + 2 * r] = rho_s > 0.0 ? 1.0 / rho_s : 0.0;
+}
+
+// Closed-form state transfer of an iSVD update: a <- Ubar[:r, :r]^T a (the new
+// direction is orthogonal to Phi, so its coefficient is zero).  One 64-thread
+// block per instance.
+__global__ __launch_bounds__(64) void k_isvd_transfer(int r, const double* __restrict__ ubar,
+                                                      double* __restrict__ a) {
+  __shared__ double sU[kMaxR * (kMaxR + 1)];  // rows 0 .. r-1 of Ubar (row length n)
+  __shared__ double sa[kMaxR];
+  const int b = blockIdx.x, tid = threadIdx.x, n = r + 1;
+  const double* U = ubar + (size_t)b * n * n;
+  for (int e = tid; e < r * n; e += blockDim.x) sU[e] = U[e];   // all loads in flight at once
+  for (int k = tid; k < r; k += blockDim.x) sa[k] = a[(size_t)b * r + k];
+  __syncthreads();
+  for (int c = tid; c < r; c += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < r; ++k) s += sU[k * n + c] * sa[k];
+    a[(size_t)b * r + c] = s;
+  }
 }
 
 // Phi_out[i, j] = sum_{c<kin} Phi_in[i, c] U[c, j] (+ s_i U[kin, j]),  j < kout,
@@ -977,30 +988,36 @@ rom_status project_t(rom_batch* h, const void* Phi, int ld, int k, const void* y
   return ROM_OK;
 }
 
-// pass A / pass B of the projection, through the fast kernel when it applies
+// pass A / pass B of the projection, through the fast kernel when it applies;
+// the fast kernel's per-tile partials go to part (h->part when null), the
+// generic kernel always uses h->part
 template <typename T>
 rom_status projection_pass(rom_batch* h, const void* y, const double* p1, int ldp, int mode,
-                           double* dst, int ldd, double* q1out, hipStream_t s) {
+                           double* dst, int ldd, double* q1out, hipStream_t s,
+                           double* part = nullptr) {
   const int r = h->cfg.r;
   if (mfma_ok(h)) {
-    rom_status st = launch_project_fast(h, y, p1, ldp, mode, kPst, q1out, s);
+    double* pp = part ? part : h->part;
+    rom_status st = launch_project_fast(h, y, p1, ldp, mode, pp, kPst, q1out, s);
     if (st != ROM_OK) return st;
     hipLaunchKernelGGL(k_reduce_tiles, dim3(h->cfg.n_inst), dim3(128), 0, s, h->d_ptile_first,
-                       h->part, r, dst, ldd);
+                       pp, r, dst, ldd);
     return ROM_OK;
   }
   return project_t<T>(h, h->Phi, r, r, y, h->q_ref, p1, ldp, mode, dst, ldd, s, q1out);
 }
 
+// Projections and core SVD of one iSVD update (Alg. 2): reads Phi and y,
+// writes sigma, Ubar and (p1, p2, 1/rho); a and Phi are left alone.
 template <typename T>
-rom_status isvd_t(rom_batch* h, const void* y, hipStream_t s) {
+rom_status isvd_core_t(rom_batch* h, const void* y, double* part, hipStream_t s) {
   const int r = h->cfg.r, B = h->cfg.n_inst;
   const int ldr = 2 * r + 4;
   double* red = h->red;
   // pass A: p1 = Phi^T y^, |y^|^2 ; pass B: p2 = Phi^T q1, |q1|^2 (q1 stored)
-  rom_status st = projection_pass<T>(h, y, nullptr, 0, 1, red, ldr, nullptr, s);
+  rom_status st = projection_pass<T>(h, y, nullptr, 0, 1, red, ldr, nullptr, s, part);
   if (st != ROM_OK) return st;
-  st = projection_pass<T>(h, y, red, ldr, 2, red + r + 1, ldr, h->qtmp, s);
+  st = projection_pass<T>(h, y, red, ldr, 2, red + r + 1, ldr, h->qtmp, s, part);
   if (st != ROM_OK) return st;
   const int n = r + 1;
   const size_t shm = sizeof(double) * (2 * n * n + 3 * n) + sizeof(int) * n;
@@ -1009,19 +1026,37 @@ rom_status isvd_t(rom_batch* h, const void* y, hipStream_t s) {
   const size_t shm_arrow = shm + sizeof(double) * (13 * n + 2) + sizeof(int) * (8 * n + 3 + 2);
   if (r == 32)
     hipLaunchKernelGGL(k_isvd_core<33>, dim3(B), dim3(64), shm_arrow, s, r, h->cfg.lambda,
-                       h->cfg.tau_rho, red, ldr, h->sigma, h->a, h->ubar, pr, h->flags);
+                       h->cfg.tau_rho, red, ldr, h->sigma, h->ubar, pr, h->flags);
   else if (r == 64)
     hipLaunchKernelGGL(k_isvd_core<65>, dim3(B), dim3(64), shm_arrow, s, r, h->cfg.lambda,
-                       h->cfg.tau_rho, red, ldr, h->sigma, h->a, h->ubar, pr, h->flags);
+                       h->cfg.tau_rho, red, ldr, h->sigma, h->ubar, pr, h->flags);
   else
     hipLaunchKernelGGL(k_isvd_core<0>, dim3(B), dim3(64), shm, s, r, h->cfg.lambda,
-                       h->cfg.tau_rho, red, ldr, h->sigma, h->a, h->ubar, pr, h->flags);
+                       h->cfg.tau_rho, red, ldr, h->sigma, h->ubar, pr, h->flags);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+// The rest of the update: the closed-form transfer of a, then the rotation of
+// Phi by Ubar (with the new direction).
+template <typename T>
+rom_status isvd_apply_t(rom_batch* h, hipStream_t s) {
+  const int r = h->cfg.r, B = h->cfg.n_inst, n = r + 1;
+  double* pr = h->rstate;
+  hipLaunchKernelGGL(k_isvd_transfer, dim3(B), dim3(64), 0, s, r, h->ubar, h->a);
   if (mfma_ok(h)) return launch_rotate_mfma(h, pr, s);
   hipLaunchKernelGGL((k_rotate<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                      h->d_dof_off, (const T*)h->Phi, r, r, (T*)h->Phi, r, r, h->ubar, n,
                      (size_t)n * n, 1, h->qtmp, pr, 2 * r + 2, nullptr);
   ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
+}
+
+template <typename T>
+rom_status isvd_t(rom_batch* h, const void* y, hipStream_t s) {
+  rom_status st = isvd_core_t<T>(h, y, h->part, s);
+  if (st != ROM_OK) return st;
+  return isvd_apply_t<T>(h, s);
 }
 
 template <typename T>
@@ -1127,6 +1162,13 @@ rom_status isvd_kernels_prepare() {
 
 rom_status launch_isvd(rom_batch* h, const void* y, hipStream_t s) {
   return h->cfg.precision == ROM_F64 ? isvd_t<double>(h, y, s) : isvd_t<float>(h, y, s);
+}
+rom_status launch_isvd_core(rom_batch* h, const void* y, double* part, hipStream_t s) {
+  return h->cfg.precision == ROM_F64 ? isvd_core_t<double>(h, y, part, s)
+                                     : isvd_core_t<float>(h, y, part, s);
+}
+rom_status launch_isvd_apply(rom_batch* h, hipStream_t s) {
+  return h->cfg.precision == ROM_F64 ? isvd_apply_t<double>(h, s) : isvd_apply_t<float>(h, s);
 }
 rom_status launch_isvd_project(rom_batch* h, const void* y, hipStream_t s) {
   const int r = h->cfg.r;

@@ -544,15 +544,15 @@ rom_status launch_rotate_mfma(rom_batch* h, const double* pr, hipStream_t s) {
 }
 
 rom_status launch_project_fast(rom_batch* h, const void* y, const double* p1, int ldp, int mode,
-                               int pst, double* q1out, hipStream_t s) {
+                               double* part, int pst, double* q1out, hipStream_t s) {
   if (h->cfg.r == 32)
     hipLaunchKernelGGL((k_project_fast<32>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                        h->d_dof_off, (const float*)h->Phi, (const float*)y, (const float*)h->q_ref,
-                       h->d_var, h->nv, p1, ldp, mode, h->part, pst, q1out);
+                       h->d_var, h->nv, p1, ldp, mode, part, pst, q1out);
   else
     hipLaunchKernelGGL((k_project_fast<64>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                        h->d_dof_off, (const float*)h->Phi, (const float*)y, (const float*)h->q_ref,
-                       h->d_var, h->nv, p1, ldp, mode, h->part, pst, q1out);
+                       h->d_var, h->nv, p1, ldp, mode, part, pst, q1out);
   ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
 }

@@ -393,3 +393,60 @@ def test_galerkin_fine_step_parity_fp32(r):
                                      w.rom_tol, w.rom_max)
         assert ok
         assert G.relerr(ag[b * r:(b + 1) * r], ar) < 1e-5, b
+
+
+def test_graph_windows_overlap_bitwise_eager_and_oracle_fp32():
+    """Whole adaptation windows of an FP32 Burgers batch (MFMA Galerkin path,
+    one-workgroup coarse step): replayed from a HIP graph, where the event's
+    coarse step, projections and core SVD run on a second stream beside the
+    fine steps, they give bit for bit what the serial eager path gives, and
+    both match the oracle's Alg. 1 from the same state within the FP32
+    tolerance."""
+    import gpu_common as G
+    import torch
+    from paper_2605_28684_amd import romhip as R
+    cells = [2048, 4096, 700, 1024]
+    w = W.burgers_batch_f32(n_inst=len(cells), r=32)
+    w.n_cells = list(cells)
+    w.phys = [dict(nu=0.002 + 0.002 * b) for b in range(len(cells))]
+    w.q0 = np.concatenate([0.3 * np.sin(2 * np.pi * W.centres(n)) + 0.5
+                           + 0.1 * np.cos(6 * np.pi * W.centres(n)) for n in cells])
+    prm = w.params()
+    off = w.offsets()
+    sts = []
+    for b in range(len(cells)):
+        st = O.offline(W.BURGERS, w.phys[b], w.q0[off[b]:off[b + 1]], prm)
+        for k in ("Phi", "q_ref", "y_corr"):
+            st[k] = G.rounded(st[k], W.F32)
+        sts.append(st)
+    n_win = 3
+    keys = ("GET_A", "GET_BASIS", "GET_SIGMA", "GET_YCORR", "GET_QTILDE")
+    out = {}
+    s = torch.cuda.Stream()   # graphs are captured on a non-default stream
+    with torch.cuda.stream(s):
+        for graph in (False, True):
+            h = R.RomBatch(w, q0=G.to_dev(w.q0, W.F32), use_graph=graph)
+            _load_state(h, w, [st["Phi"] for st in sts], [st["sigma"] for st in sts],
+                        [st["a"] for st in sts], np.concatenate([st["q_ref"] for st in sts]),
+                        [st["d_var"] for st in sts], W.F32)
+            h.set(R.GET_YCORR, G.to_dev(np.concatenate([st["y_corr"] for st in sts]), W.F32))
+            h.set(R.GET_COUNTERS, [w.w_init, 0, 0, 0])
+            h.rom_step(w.z * n_win)
+            torch.cuda.synchronize()
+            out[graph] = {k: G.host(h.get(getattr(R, k))).copy() for k in keys}
+            out[graph]["flags"] = h.status().copy()
+            out[graph]["counters"] = list(h.get(R.GET_COUNTERS))
+            h.close()
+    for k in out[False]:
+        assert np.array_equal(np.asarray(out[False][k]), np.asarray(out[True][k])), k
+    assert out[True]["counters"][2] == n_win
+    for b, st in enumerate(sts):
+        for k in range(n_win * w.z):
+            O.rom_fine_step(W.BURGERS, w.phys[b], st, prm)
+            if (k + 1) % w.z == 0:
+                O.adaptation_event(W.BURGERS, w.phys[b], st, prm)
+        sl = slice(off[b], off[b + 1])
+        ref = O.reconstruct(st["q_ref"], st["d"], st["Phi"], st["a"])
+        assert G.relerr(out[True]["GET_QTILDE"][sl], ref) < 1e-5, b
+        assert G.relerr(out[True]["GET_YCORR"][sl], st["y_corr"]) < 1e-5, b
+        assert G.relerr(out[True]["GET_SIGMA"][b * 32:(b + 1) * 32], st["sigma"]) < 1e-5, b
