@@ -235,6 +235,40 @@ rom_status rom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, double
                            int32_t n_ckpt, const void* gbar, void* gq0, void* stream);
 
 /*
+ * rom_online_vjp - gradient through the online part of Alg. 1 (an extension
+ * beyond the paper): n_fine fine Galerkin steps from the current state, with
+ * the adaptation events that fall due (coarse backward-Euler step of y_corr,
+ * Alg. 2's Brand update with forgetting factor lambda, the closed-form state
+ * transfer a <- Ubar[:r, :r]^T a).  Given qbar = dL/dq~ for the reconstructed
+ * state q~ = q_ref + D^-1 Phi a at the end, it returns the gradients of L with
+ * respect to the state at the start:
+ *   abar   = dL/da,      device double[n_inst * r]
+ *   phibar = dL/dPhi,    device double[total_dof * r] (row-major like the basis)
+ *   sigbar = dL/dsigma,  device double[n_inst * r]
+ *   ycbar  = dL/dy_corr, device double[total_dof]
+ * (q_ref and D are held fixed).  Each fine step is differentiated by the
+ * implicit-function theorem at its converged state (a transposed r x r solve
+ * with J_g = I - dt Phi^T J_f Phi); each event by the adjoints of the
+ * transfer, the rotation of eq. isvd_updated_basis_full, the SVD of the core
+ * matrix of eq. isvd_core_matrix (distinct singular values), the two
+ * Gram-Schmidt passes, the preprocessing, and the coarse step (a transposed
+ * banded solve).  The forward pass keeps about sqrt(n_fine) checkpoints
+ * (n_ckpt > 0 sets their number) and recomputes one segment at a time; the
+ * result does not depend on n_ckpt.  The handle is left in the state that
+ * rom_step(h, n_fine) would leave.
+ *   qbar: device T[total_dof] (not modified).  Workspace is allocated and
+ *   freed inside the call (hipMalloc; not for stream capture); the call
+ *   synchronises the stream.  An event with rho = 0 (snapshot inside the
+ *   basis span) is not differentiable: its instance gets ROM_FLAG_SINGULAR.
+ * Errors: ROM_E_INVAL (NULL pointers, n_fine < 1, n_ckpt < 0), ROM_E_STATE
+ * (no reduced state), ROM_E_UNSUPPORTED (hyper-reduction or a problem other
+ * than Burgers, or a re-orthonormalisation inside the range).
+ */
+rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const void* qbar,
+                          double* abar, double* phibar, double* sigbar, double* ycbar,
+                          void* stream);
+
+/*
  * Autotuning of launch shapes.  Only shapes that cannot change results are
  * tuned: for ROM_TUNE_RESIDUAL, the streaming residual of the Euler problems
  * (fom_residual, and the residual evaluations inside the grid-wide Newton

@@ -1,0 +1,435 @@
+// Reverse mode of Alg. 1's online loop (an extension; the paper has no
+// adjoint): Galerkin fine steps (Burgers), adaptation events with the coarse
+// backward-Euler step, the Brand update (Alg. 2) and the closed-form state
+// transfer.  One workgroup per instance, FP64 throughout; the basis and the
+// states are read in the storage precision T.
+//
+//  * k_online_seed: the loss seed at the end, q~ = q_ref + D^-1 Phi a:
+//    abar = Phi^T D^-1 qbar, Phibar = D^-1 qbar a^T.
+//  * k_step_vjp: one fine step a_{n+1} = G(a_n, Phi) with
+//    g(a) = a - a_n - dt Phi^T D f(q_ref + D^-1 Phi a) = 0, differentiated by
+//    the implicit-function theorem at the converged a_{n+1}:
+//    J_g^T lambda = abar, abar_n = lambda and
+//    Phibar += dt (D f) lambda^T + dt D^-1 J_f^T (D Phi lambda) a_{n+1}^T.
+//    J_g = I - dt Phi^T J_f Phi comes from the Galerkin pass's tile partials.
+//  * k_event_vjp: one event from the transfer back to yhat = D (y - q_ref):
+//    transfer a' = Ubar[:r, :r]^T a, rotation Phi' = [Phi, q / rho] Ubar[:, :r],
+//    truncation sigma' = Sbar[:r], the SVD of the core K (distinct singular
+//    values: Kbar = Ubar G Vbar^T with G_ii = sbar_i and
+//    G_ij = s_j (M_ij - M_ji) / (s_j^2 - s_i^2), M = Ubar^T Ubarbar), the core's
+//    entries lambda sigma, p = p1 + p2 and rho = |q|, and the two classical
+//    Gram-Schmidt passes.  The coarse step's transposed solve is done by the
+//    banded solver outside.
+#include "internal.h"
+#include "linalg.h"
+#include "physics.h"
+
+namespace romhip {
+
+namespace {
+
+constexpr int kAT = 256;   // threads per instance
+
+// Block-wide sum of one double per thread (all threads call; result in all).
+DEV double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// Burgers on the periodic unit grid: f_i, its diagonal derivative and the two
+// off-diagonal entries of column i of J_f (d f_{i+1} / d u_i, d f_{i-1} / d u_i).
+DEV void burgers_col(double um, double u0, double up, double nu, double inv, double inv2,
+                     double& f, double& be, double& al_next, double& ga_prev) {
+  double dla, dlb, dra, drb;
+  const double FL = godunov(um, u0, dla, dlb);
+  const double FR = godunov(u0, up, dra, drb);
+  f = -(FR - FL) * inv + nu * ((up - u0) - (u0 - um)) * inv2;
+  be = (dlb - dra) * inv - 2.0 * nu * inv2;
+  al_next = dra * inv + nu * inv2;    // f_{i+1} through its left face (u_i, u_{i+1})
+  ga_prev = -dlb * inv + nu * inv2;   // f_{i-1} through its right face (u_{i-1}, u_i)
+}
+
+DEV int64_t wrap(int64_t c, int64_t n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
+template <typename T>
+__global__ __launch_bounds__(kAT) void k_online_seed(
+    int r, const int64_t* __restrict__ dof_off, const double* __restrict__ dvar,
+    const T* __restrict__ Phi, const double* __restrict__ a, const T* __restrict__ qbar,
+    double* __restrict__ abar, double* __restrict__ phibar) {
+  __shared__ double red[kAT / 64];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int64_t base = dof_off[b], n = dof_off[b + 1] - base;
+  const double dinv = 1.0 / dvar[b];
+  for (int c = 0; c < r; ++c) {
+    double s = 0.0;
+    for (int64_t i = tid; i < n; i += kAT) s += (double)Phi[(base + i) * r + c] * (double)qbar[base + i];
+    s = block_sum(s, red);
+    if (tid == 0) abar[(size_t)b * r + c] = s * dinv;
+  }
+  for (int64_t e = tid; e < n * r; e += kAT) {
+    const int64_t i = e / r;
+    const int c = (int)(e % r);
+    phibar[(base + i) * r + c] = (double)qbar[base + i] * dinv * a[(size_t)b * r + c];
+  }
+}
+
+// One fine step backward.  mpart/tfirst: the Galerkin pass's tile partials of
+// Phi^T J_f Phi at a1 (= a_{n+1}); qt, w: per-DOF scratch.
+template <typename T>
+__global__ __launch_bounds__(kAT) void k_step_vjp(
+    int r, double dt, const int64_t* __restrict__ dof_off, const double* __restrict__ phys,
+    int nphys, const double* __restrict__ dvar, const int* __restrict__ tfirst,
+    const T* __restrict__ mpart, const T* __restrict__ Phi, const T* __restrict__ qref,
+    const double* __restrict__ a1, double* __restrict__ abar, double* __restrict__ phibar,
+    double* __restrict__ qt, double* __restrict__ w, uint32_t* flags) {
+  __shared__ double A[kMaxR * (kMaxR + 1)];
+  __shared__ double lam[kMaxR];
+  __shared__ double sa[kMaxR];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int ld = r + 1;
+  const int64_t base = dof_off[b], n = dof_off[b + 1] - base;
+  const double d = dvar[b], dinv = 1.0 / d;
+  const double nu = phys[(size_t)b * nphys];
+  const double inv = (double)n, inv2 = (double)n * (double)n;
+  // A = J_g^T with J_g = I - dt M, M summed over the instance's tiles in tile order
+  const int t0 = tfirst[b], t1 = tfirst[b + 1];
+  for (int e = tid; e < r * r; e += kAT) {
+    double s = 0.0;
+    for (int tt = t0; tt < t1; ++tt) s += (double)mpart[(size_t)tt * kMaxR * kMaxR + e];
+    const int i = e / r, j = e % r;
+    A[j * ld + i] = (i == j ? 1.0 : 0.0) - dt * s;
+  }
+  for (int c = tid; c < r; c += kAT) {
+    lam[c] = abar[(size_t)b * r + c];
+    sa[c] = a1[(size_t)b * r + c];
+  }
+  __syncthreads();
+  const int ok = block_lu_solve(A, ld, lam, r);
+  if (!ok && tid == 0) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
+  for (int c = tid; c < r; c += kAT) abar[(size_t)b * r + c] = lam[c];
+  // q~ = q_ref + D^-1 Phi a1 and w = Phi lambda
+  for (int64_t i = tid; i < n; i += kAT) {
+    const T* pr = Phi + (base + i) * r;
+    double sq = 0.0, sw = 0.0;
+    for (int c = 0; c < r; ++c) {
+      const double p = (double)pr[c];
+      sq += p * sa[c];
+      sw += p * lam[c];
+    }
+    qt[base + i] = (double)qref[base + i] + sq * dinv;
+    w[base + i] = sw;
+  }
+  __syncthreads();
+  // Phibar += dt d f lambda^T + dt (J_f^T w) a1^T
+  for (int64_t i = tid; i < n; i += kAT) {
+    const int64_t im = wrap(i - 1, n), ip = wrap(i + 1, n);
+    const double um = qt[base + im], u0 = qt[base + i], up = qt[base + ip];
+    double f, be, al_next, ga_prev;
+    burgers_col(um, u0, up, nu, inv, inv2, f, be, al_next, ga_prev);
+    const double v = al_next * w[base + ip] + be * w[base + i] + ga_prev * w[base + im];
+    double* pb = phibar + (base + i) * r;
+    for (int c = 0; c < r; ++c) pb[c] += dt * d * f * lam[c] + dt * v * sa[c];
+  }
+}
+
+// One event backward, from the transfer down to yhat (the coarse step's
+// transposed solve follows outside).  Inputs recorded in the forward pass:
+// Phi_old, y_new (after the coarse step), sigma_old, a_old (before the
+// transfer), Ubar (n x n), pr = (p1, p2, 1/rho, s_{n}).  abar, sigbar and the
+// rows of phibar are replaced by the adjoints of the pre-event state; ybar
+// receives D yhatbar.  Dynamic LDS: 4 n^2 doubles.
+template <typename T>
+__global__ __launch_bounds__(kAT) void k_event_vjp(
+    int r, double lam_f, const int64_t* __restrict__ dof_off, const double* __restrict__ dvar,
+    const T* __restrict__ Phi, const T* __restrict__ ynew, const T* __restrict__ qref,
+    const double* __restrict__ sig_old, const double* __restrict__ a_old,
+    const double* __restrict__ ubar, const double* __restrict__ prs,
+    const double* __restrict__ sig_new, double* __restrict__ abar,
+    double* __restrict__ phibar, double* __restrict__ sigbar, double* __restrict__ ybar,
+    double* __restrict__ qs, double* __restrict__ js, uint32_t* flags) {
+  extern __shared__ double sm[];
+  __shared__ double red[kAT / 64];
+  __shared__ double vr[6][kMaxR + 1];  // p1, p2, abar', pbar, p1bar, p2bar
+  __shared__ double sv[kMaxR + 1];
+  const int n = r + 1, tid = threadIdx.x, b = blockIdx.x;
+  double* U = sm;              // Ubar
+  double* Ub = U + n * n;      // its adjoint, then G
+  double* Mm = Ub + n * n;     // U^T Ub, then T = G V^T
+  double* V = Mm + n * n;
+  double* p1 = vr[0];
+  double* p2 = vr[1];
+  double* ab = vr[2];
+  double* pb = vr[3];
+  double* p1b = vr[4];
+  double* p2b = vr[5];
+  const int64_t base = dof_off[b], nd = dof_off[b + 1] - base;
+  const double d = dvar[b];
+  const double* pr = prs + (size_t)b * (2 * r + 2);
+  const double irho = pr[2 * r];
+  if (irho == 0.0) {   // rho = 0: the update is not differentiable there
+    if (tid == 0) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
+    return;
+  }
+  const double rho = 1.0 / irho;
+  for (int e = tid; e < n * n; e += kAT) {
+    U[e] = ubar[(size_t)b * n * n + e];
+    Ub[e] = 0.0;
+  }
+  for (int c = tid; c < r; c += kAT) {
+    p1[c] = pr[c];
+    p2[c] = pr[r + c];
+    ab[c] = abar[(size_t)b * r + c];
+    sv[c] = sig_new[(size_t)b * r + c];
+  }
+  if (tid == 0) sv[r] = pr[2 * r + 1];
+  __syncthreads();
+  // transfer a' = U[:r, :r]^T a: abar_old = U[:r, :r] abar, Ubar[:r, :r] += a_old abar^T
+  for (int c = tid; c < r; c += kAT) {
+    double s = 0.0;
+    for (int k = 0; k < r; ++k) s += U[c * n + k] * ab[k];
+    abar[(size_t)b * r + c] = s;
+  }
+  for (int e = tid; e < r * r; e += kAT) {
+    const int i = e / r, j = e % r;
+    Ub[i * n + j] += a_old[(size_t)b * r + i] * ab[j];
+  }
+  __syncthreads();
+  // rotation: Ubar[:r, :r] += Phi^T Phibar', Ubar[r, :r] += j^T Phibar' (j = q / rho),
+  // computed before the rows of Phibar are replaced
+  for (int64_t i = tid; i < nd; i += kAT) {
+    const T* ph = Phi + (base + i) * r;
+    double q = d * ((double)ynew[base + i] - (double)qref[base + i]);
+    for (int c = 0; c < r; ++c) q -= (double)ph[c] * (p1[c] + p2[c]);
+    qs[base + i] = q;
+  }
+  __syncthreads();
+  for (int e = tid; e < n * r; e += kAT) {
+    const int i = e / r, j = e % r;   // row i of [Phi, j]^T, column j of Phibar'
+    double s = 0.0;
+    if (i < r)
+      for (int64_t k = 0; k < nd; ++k) s += (double)Phi[(base + k) * r + i] * phibar[(base + k) * r + j];
+    else
+      for (int64_t k = 0; k < nd; ++k) s += qs[base + k] * irho * phibar[(base + k) * r + j];
+    Ub[i * n + j] += s;
+  }
+  // rows: Phibar_old = Phibar' U[:r, :r]^T, jbar = Phibar' U[r, :r]^T (in js)
+  double jq = 0.0;
+  __syncthreads();
+  for (int64_t i = tid; i < nd; i += kAT) {
+    double* pb_row = phibar + (base + i) * r;
+    double row[kMaxR];
+    for (int c = 0; c < r; ++c) row[c] = pb_row[c];
+    double jb = 0.0;
+    for (int c = 0; c < r; ++c) jb += row[c] * U[r * n + c];
+    for (int k = 0; k < r; ++k) {
+      double s = 0.0;
+      for (int c = 0; c < r; ++c) s += row[c] * U[k * n + c];
+      pb_row[k] = s;
+    }
+    js[base + i] = jb;
+    jq += jb * qs[base + i];
+  }
+  jq = block_sum(jq, red);
+  // SVD of K: V = K^T U / s, M = U^T Ubar, G, T = G V^T, Kbar entries needed
+  for (int e = tid; e < n * n; e += kAT) {
+    const int k = e / n, j = e % n;   // V[k][j]
+    double s = 0.0;
+    if (sv[j] > 0.0) {
+      const double kt = k < r ? lam_f * sig_old[(size_t)b * r + k] * U[k * n + j]
+                              : [&] {
+                                  double t = rho * U[r * n + j];
+                                  for (int i = 0; i < r; ++i) t += (p1[i] + p2[i]) * U[i * n + j];
+                                  return t;
+                                }();
+      s = kt / sv[j];
+    }
+    V[e] = s;
+  }
+  for (int e = tid; e < n * n; e += kAT) {
+    const int i = e / n, j = e % n;
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += U[k * n + i] * Ub[k * n + j];
+    Mm[e] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < n * n; e += kAT) {
+    const int i = e / n, j = e % n;
+    double g;
+    if (i == j) g = i < r ? sigbar[(size_t)b * r + i] : 0.0;
+    else g = sv[j] > 0.0 ? sv[j] * (Mm[i * n + j] - Mm[j * n + i]) / ((sv[j] - sv[i]) * (sv[j] + sv[i]))
+                         : 0.0;
+    Ub[e] = g;   // G
+  }
+  __syncthreads();
+  for (int e = tid; e < n * n; e += kAT) {   // T = G V^T
+    const int i = e / n, j = e % n;
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += Ub[i * n + k] * V[j * n + k];
+    Mm[e] = s;
+  }
+  __syncthreads();
+  // Kbar = U T: sigma_old (diagonal, times lambda), p (last column), rho (corner)
+  for (int c = tid; c < n; c += kAT) {
+    double kd = 0.0, kc = 0.0;
+    for (int k = 0; k < n; ++k) {
+      kd += U[c * n + k] * Mm[k * n + c];
+      kc += U[c * n + k] * Mm[k * n + r];
+    }
+    if (c < r) {
+      sigbar[(size_t)b * r + c] = lam_f * kd;
+      pb[c] = kc;
+    } else {
+      pb[r] = kc;   // rhobar from K
+    }
+  }
+  __syncthreads();
+  // j = q / rho, rho = |q|: qbar = jbar / rho + rhobar q / rho
+  const double rhob = pb[r] - jq * irho * irho;
+  double t2 = 0.0;
+  // pass 2: qbar (into js); Phibar_old -= qbar p2^T; t2 = Phi^T qbar
+  for (int c = 0; c < r; ++c) {
+    double s = 0.0;
+    for (int64_t i = tid; i < nd; i += kAT) {
+      const double qb = (js[base + i] + rhob * qs[base + i]) * irho;
+      s += (double)Phi[(base + i) * r + c] * qb;
+    }
+    s = block_sum(s, red);
+    if (tid == 0) p2b[c] = pb[c] - s;
+  }
+  (void)t2;
+  __syncthreads();
+  for (int64_t i = tid; i < nd; i += kAT) {
+    const double qb = (js[base + i] + rhob * qs[base + i]) * irho;
+    const T* ph = Phi + (base + i) * r;
+    double* pbr = phibar + (base + i) * r;
+    // q1 = yhat - Phi p1
+    double q1 = d * ((double)ynew[base + i] - (double)qref[base + i]);
+    for (int c = 0; c < r; ++c) q1 -= (double)ph[c] * p1[c];
+    double q1b = qb;
+    for (int c = 0; c < r; ++c) {
+      pbr[c] += -qb * p2[c] + q1 * p2b[c];
+      q1b += (double)ph[c] * p2b[c];
+    }
+    js[base + i] = q1b;   // q1bar
+  }
+  __syncthreads();
+  // p1bar = pbar - Phi^T q1bar
+  for (int c = 0; c < r; ++c) {
+    double s = 0.0;
+    for (int64_t i = tid; i < nd; i += kAT) s += (double)Phi[(base + i) * r + c] * js[base + i];
+    s = block_sum(s, red);
+    if (tid == 0) p1b[c] = pb[c] - s;
+  }
+  __syncthreads();
+  // Phibar_old += -q1bar p1^T + yhat p1bar^T; yhatbar = q1bar + Phi p1bar; ybar += D yhatbar
+  for (int64_t i = tid; i < nd; i += kAT) {
+    const T* ph = Phi + (base + i) * r;
+    double* pbr = phibar + (base + i) * r;
+    const double yh = d * ((double)ynew[base + i] - (double)qref[base + i]);
+    const double q1b = js[base + i];
+    double yb = q1b;
+    for (int c = 0; c < r; ++c) {
+      pbr[c] += -q1b * p1[c] + yh * p1b[c];
+      yb += (double)ph[c] * p1b[c];
+    }
+    ybar[base + i] += d * yb;
+  }
+}
+
+__global__ void k_to_double(const float* __restrict__ x, double* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (double)x[i];
+}
+__global__ void k_to_float(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+
+}  // namespace
+
+rom_status launch_online_seed(rom_batch* h, const void* qbar, double* abar, double* phibar,
+                              hipStream_t s) {
+  const int B = h->cfg.n_inst, r = h->cfg.r;
+  if (h->cfg.precision == ROM_F64)
+    hipLaunchKernelGGL((k_online_seed<double>), dim3(B), dim3(kAT), 0, s, r, h->d_dof_off,
+                       h->d_var, (const double*)h->Phi, h->a, (const double*)qbar, abar, phibar);
+  else
+    hipLaunchKernelGGL((k_online_seed<float>), dim3(B), dim3(kAT), 0, s, r, h->d_dof_off,
+                       h->d_var, (const float*)h->Phi, h->a, (const float*)qbar, abar, phibar);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+rom_status launch_step_vjp(rom_batch* h, const void* Phi, const double* a1, double* abar,
+                           double* phibar, double* qt, double* w, hipStream_t s) {
+  const int B = h->cfg.n_inst, r = h->cfg.r;
+  if (h->cfg.precision == ROM_F64)
+    hipLaunchKernelGGL((k_step_vjp<double>), dim3(B), dim3(kAT), 0, s, r, h->cfg.dt, h->d_dof_off,
+                       h->d_phys, h->cfg.n_phys, h->d_var, h->d_ptile_first,
+                       (const double*)h->mpart, (const double*)Phi, (const double*)h->q_ref, a1,
+                       abar, phibar, qt, w, h->flags);
+  else
+    hipLaunchKernelGGL((k_step_vjp<float>), dim3(B), dim3(kAT), 0, s, r, h->cfg.dt, h->d_dof_off,
+                       h->d_phys, h->cfg.n_phys, h->d_var, h->d_ptile_first,
+                       (const float*)h->mpart, (const float*)Phi, (const float*)h->q_ref, a1, abar,
+                       phibar, qt, w, h->flags);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+size_t event_vjp_shm(int r) { return sizeof(double) * 4 * (size_t)(r + 1) * (r + 1); }
+
+rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new,
+                            const double* sig_old, const double* a_old, const double* ubar,
+                            const double* pr, const double* sig_new, double* abar,
+                            double* phibar, double* sigbar, double* ybar, double* qs, double* js,
+                            hipStream_t s) {
+  const int B = h->cfg.n_inst, r = h->cfg.r;
+  const size_t shm = event_vjp_shm(r);
+  if (h->cfg.precision == ROM_F64)
+    hipLaunchKernelGGL((k_event_vjp<double>), dim3(B), dim3(kAT), shm, s, r, h->cfg.lambda,
+                       h->d_dof_off, h->d_var, (const double*)Phi_old, (const double*)y_new,
+                       (const double*)h->q_ref, sig_old, a_old, ubar, pr, sig_new, abar, phibar,
+                       sigbar, ybar, qs, js, h->flags);
+  else
+    hipLaunchKernelGGL((k_event_vjp<float>), dim3(B), dim3(kAT), shm, s, r, h->cfg.lambda,
+                       h->d_dof_off, h->d_var, (const float*)Phi_old, (const float*)y_new,
+                       (const float*)h->q_ref, sig_old, a_old, ubar, pr, sig_new, abar, phibar,
+                       sigbar, ybar, qs, js, h->flags);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+rom_status convert_words(const void* src, bool src_f64, void* dst, bool dst_f64, int64_t n,
+                         hipStream_t s) {
+  if (src_f64 == dst_f64) {
+    ROM_HIP_CHECK(hipMemcpyAsync(dst, src, (size_t)n * (src_f64 ? 8 : 4), hipMemcpyDeviceToDevice, s));
+    return ROM_OK;
+  }
+  const int64_t nb = (n + 255) / 256;
+  if (nb > 0) {
+    if (src_f64) hipLaunchKernelGGL(k_to_float, dim3(nb), dim3(256), 0, s, (const double*)src, (float*)dst, n);
+    else hipLaunchKernelGGL(k_to_double, dim3(nb), dim3(256), 0, s, (const float*)src, (double*)dst, n);
+  }
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+rom_status adjoint_kernels_prepare() {
+  const int big = 160 * 1024 - 4096;
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_event_vjp<float>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_event_vjp<double>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  return ROM_OK;
+}
+
+}  // namespace romhip

@@ -275,6 +275,7 @@ rom_status setup(rom_batch* h) {
     ROM_HIP_CHECK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
   }
   ROM_TRY(isvd_kernels_prepare());
+  ROM_TRY(adjoint_kernels_prepare());
   ROM_TRY(rom_kernels_prepare());
   ROM_HIP_CHECK(hipDeviceSynchronize());
   return ROM_OK;
@@ -660,6 +661,158 @@ rom_status rom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, double
   }
   ROM_TRY(copy_words(ga, gq0, st, s));
   ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const void* qbar,
+                          double* abar, double* phibar, double* sigbar, double* ycbar,
+                          void* stream) {
+  ROM_REQUIRE(h && qbar && abar && phibar && sigbar && ycbar, ROM_E_INVAL,
+              "handle, qbar and the four gradient buffers are required");
+  ROM_REQUIRE(n_fine >= 1, ROM_E_INVAL, "n_fine must be >= 1");
+  ROM_REQUIRE(n_ckpt >= 0, ROM_E_INVAL, "n_ckpt must be >= 0");
+  ROM_REQUIRE(h->has_rom, ROM_E_STATE, "no reduced state");
+  ROM_REQUIRE(h->cfg.hyper == ROM_HR_NONE && h->cfg.problem == ROM_BURGERS, ROM_E_UNSUPPORTED,
+              "the online adjoint covers the Galerkin (Burgers) path only");
+  const rom_config& c = h->cfg;
+  const int B = c.n_inst, r = c.r, n = r + 1, z = c.z;
+  const int64_t T = n_fine;
+  auto due = [&](int64_t nf) { return (nf + 1 - c.w_init) % z == 0; };
+  {  // no re-orthonormalisation may fall inside the range
+    int64_t nu = h->n_update;
+    for (int64_t k = 0; k < T; ++k)
+      if (due(h->n_fine + k)) {
+        ++nu;
+        ROM_REQUIRE(!(c.reorth_every > 0 && nu % c.reorth_every == 0), ROM_E_UNSUPPORTED,
+                    "a re-orthonormalisation falls inside the adjoint's range");
+      }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  const bool f64 = c.precision == ROM_F64;
+  int64_t C = n_ckpt > 0 ? n_ckpt : (int64_t)std::ceil(std::sqrt((double)T));
+  if (C > T) C = T;
+  const int64_t S = (T + C - 1) / C;      // fine steps per segment
+  const int64_t nseg = (T + S - 1) / S;
+  const int64_t E = S / z + 1;            // events per segment, at most
+  const size_t phi_b = h->esz * (size_t)h->total_dof * r, y_b = h->esz * (size_t)h->total_dof;
+  const size_t br = 8 * (size_t)B * r;
+  const size_t state_b = phi_b + y_b + 2 * br;        // Phi, y_corr, sigma, a
+  const size_t ev_b = phi_b + y_b + 3 * br + 8 * (size_t)B * n * n + 8 * (size_t)B * (2 * r + 2);
+  const size_t td8 = 8 * (size_t)h->total_dof;
+  const size_t need = (size_t)(nseg + 1) * state_b + (size_t)S * br + (size_t)E * ev_b +
+                      2 * td8 + 2 * y_b + 1024;
+  char* ws = nullptr;
+  ROM_TRY(alloc(&ws, need));
+  struct Host { int64_t nf, nu, ne; };
+  std::vector<Host> hc(nseg + 1);
+  char* ck = ws;
+  char* rec_a = ck + (size_t)(nseg + 1) * state_b;
+  char* ev = rec_a + (size_t)S * br;
+  double* scr0 = (double*)(ev + (size_t)E * ev_b);
+  double* scr1 = scr0 + h->total_dof;
+  char* rhs = (char*)(scr1 + h->total_dof);
+  char* out = rhs + y_b;
+  auto save = [&](int64_t j) -> rom_status {
+    char* p = ck + (size_t)j * state_b;
+    ROM_TRY(copy_words(h->Phi, p, phi_b, s));
+    ROM_TRY(copy_words(h->y_corr, p + phi_b, y_b, s));
+    ROM_TRY(copy_words(h->sigma, p + phi_b + y_b, br, s));
+    ROM_TRY(copy_words(h->a, p + phi_b + y_b + br, br, s));
+    hc[j] = Host{h->n_fine, h->n_update, h->n_events};
+    return ROM_OK;
+  };
+  auto restore = [&](int64_t j) -> rom_status {
+    const char* p = ck + (size_t)j * state_b;
+    ROM_TRY(copy_words(p, h->Phi, phi_b, s));
+    ROM_TRY(copy_words(p + phi_b, h->y_corr, y_b, s));
+    ROM_TRY(copy_words(p + phi_b + y_b, h->sigma, br, s));
+    ROM_TRY(copy_words(p + phi_b + y_b + br, h->a, br, s));
+    h->n_fine = hc[j].nf;
+    h->n_update = hc[j].nu;
+    h->n_events = hc[j].ne;
+    return ROM_OK;
+  };
+  // event record e: Phi_old, y_new, sigma_old, a_old, sigma_new, Ubar, pr
+  auto ev_phi = [&](int64_t e) { return ev + (size_t)e * ev_b; };
+  auto ev_y = [&](int64_t e) { return ev_phi(e) + phi_b; };
+  auto ev_sold = [&](int64_t e) { return (double*)(ev_y(e) + y_b); };
+  auto ev_aold = [&](int64_t e) { return ev_sold(e) + (size_t)B * r; };
+  auto ev_snew = [&](int64_t e) { return ev_aold(e) + (size_t)B * r; };
+  auto ev_u = [&](int64_t e) { return ev_snew(e) + (size_t)B * r; };
+  auto ev_pr = [&](int64_t e) { return ev_u(e) + (size_t)B * n * n; };
+  rom_status st = ROM_OK;
+  // forward: checkpoints at segment starts, and the end state
+  for (int64_t j = 0; j < nseg && st == ROM_OK; ++j) {
+    st = save(j);
+    const int64_t L = std::min(S, T - j * S);
+    for (int64_t k = 0; k < L && st == ROM_OK; ++k) st = fine_step_impl(h, s);
+  }
+  if (st == ROM_OK) st = save(nseg);
+  // seed at the end state
+  if (st == ROM_OK) st = launch_online_seed(h, qbar, abar, phibar, s);
+  if (st == ROM_OK) st = fill_zero(sigbar, br, s);
+  if (st == ROM_OK) st = fill_zero(ycbar, td8, s);
+  // backward, one segment at a time
+  for (int64_t j = nseg - 1; j >= 0 && st == ROM_OK; --j) {
+    st = restore(j);
+    const int64_t L = std::min(S, T - j * S);
+    std::vector<int64_t> after;   // event e follows fine step after[e] of the segment
+    for (int64_t k = 0; k < L && st == ROM_OK; ++k) {
+      st = launch_rom_fine_step(h, s);
+      if (st == ROM_OK) st = copy_words(h->a, rec_a + (size_t)k * br, br, s);
+      if (st == ROM_OK && due(h->n_fine)) {
+        const int64_t e = (int64_t)after.size();
+        after.push_back(k);
+        st = copy_words(h->Phi, ev_phi(e), phi_b, s);
+        if (st == ROM_OK) st = copy_words(h->sigma, ev_sold(e), br, s);
+        if (st == ROM_OK) st = copy_words(h->a, ev_aold(e), br, s);
+        if (st == ROM_OK) st = fom_step_impl(h, h->y_corr, z * c.dt, h->y_corr, nullptr, s);
+        if (st == ROM_OK) st = copy_words(h->y_corr, ev_y(e), y_b, s);
+        if (st == ROM_OK) st = launch_isvd_core(h, h->y_corr, h->part, s);
+        if (st == ROM_OK) st = copy_words(h->ubar, ev_u(e), 8 * (size_t)B * n * n, s);
+        if (st == ROM_OK) st = copy_words(h->rstate, ev_pr(e), 8 * (size_t)B * (2 * r + 2), s);
+        if (st == ROM_OK) st = copy_words(h->sigma, ev_snew(e), br, s);
+        if (st == ROM_OK) st = launch_isvd_apply(h, s);
+        h->n_update += 1;
+        if (st == ROM_OK) st = launch_rebuild(h, s);
+        h->n_events += 1;
+      }
+      h->n_fine += 1;
+    }
+    for (int64_t k = L - 1; k >= 0 && st == ROM_OK; --k) {
+      int64_t e_next = -1;   // first event at or after step k: its Phi_old is step k's basis
+      for (int64_t e = 0; e < (int64_t)after.size(); ++e)
+        if (after[e] >= k) { e_next = e; break; }
+      if (e_next >= 0 && after[e_next] == k) {
+        const int64_t e = e_next;
+        st = launch_event_vjp(h, ev_phi(e), ev_y(e), ev_sold(e), ev_aold(e), ev_u(e), ev_pr(e),
+                              ev_snew(e), abar, phibar, sigbar, ycbar, scr0, scr1, s);
+        // coarse step y_new = BE(y_prev) over z dt: ybar <- J_r(y_new)^-T ybar
+        if (st == ROM_OK) st = convert_words(ycbar, true, rhs, f64, h->total_dof, s);
+        if (st == ROM_OK) st = launch_assemble_adjoint(h, ev_y(e), z * c.dt, rhs, s);
+        if (st == ROM_OK) st = bt_solve(h, -1, nullptr, out, s);
+        if (st == ROM_OK) st = convert_words(out, f64, ycbar, true, h->total_dof, s);
+      }
+      if (st != ROM_OK) break;
+      void* phi_k = e_next >= 0 ? (void*)ev_phi(e_next) : h->Phi;
+      double* a_k = (double*)(rec_a + (size_t)k * br);
+      void* phi_live = h->Phi;
+      double* a_live = h->a;
+      h->Phi = phi_k;
+      h->a = a_k;
+      st = prepare_galerkin_pass(h, s);
+      if (st == ROM_OK) st = launch_galerkin_pass(h, s);
+      h->Phi = phi_live;
+      h->a = a_live;
+      if (st == ROM_OK) st = launch_step_vjp(h, phi_k, a_k, abar, phibar, scr0, scr1, s);
+    }
+  }
+  if (st == ROM_OK) st = restore(nseg);
+  hipError_t e = hipStreamSynchronize(s);
+  (void)hipFree(ws);
+  ROM_TRY(st);
+  if (e != hipSuccess) { set_error(hipGetErrorString(e)); return ROM_E_DEVICE; }
   return ROM_OK;
 }
 

@@ -188,6 +188,21 @@ rom_status launch_isvd(rom_batch* h, const void* y, hipStream_t s);
 // then the state transfer and the basis rotation.
 rom_status launch_isvd_core(rom_batch* h, const void* y, double* part, hipStream_t s);
 rom_status launch_isvd_apply(rom_batch* h, hipStream_t s);
+// Online-loop adjoint pieces (adjoint.hip): the loss seed at the end state,
+// one fine step backward (after a Galerkin pass at its converged state), one
+// event backward down to yhat, FP32/FP64 conversion of device vectors.
+rom_status launch_online_seed(rom_batch* h, const void* qbar, double* abar, double* phibar,
+                              hipStream_t s);
+rom_status launch_step_vjp(rom_batch* h, const void* Phi, const double* a1, double* abar,
+                           double* phibar, double* qt, double* w, hipStream_t s);
+rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new,
+                            const double* sig_old, const double* a_old, const double* ubar,
+                            const double* pr, const double* sig_new, double* abar,
+                            double* phibar, double* sigbar, double* ybar, double* qs, double* js,
+                            hipStream_t s);
+rom_status convert_words(const void* src, bool src_f64, void* dst, bool dst_f64, int64_t n,
+                         hipStream_t s);
+rom_status adjoint_kernels_prepare();
 rom_status launch_reorth(rom_batch* h, hipStream_t s);
 rom_status launch_pod(rom_batch* h, const void* Q, int w, hipStream_t s);  // Q: T[w * total_dof]
 rom_status launch_preprocess(rom_batch* h, const void* q0, const void* Q, int w, hipStream_t s);

@@ -631,12 +631,16 @@ __global__ __launch_bounds__(64) void k_isvd_core(int r, double lambda, double t
     __syncthreads();
   }
   for (int c = tid; c < r; c += blockDim.x) sigma[(size_t)b * r + c] = sv[c];
-  // p1, p2 (kept apart: the rotation subtracts them one after the other) and 1/rho
+  // p1, p2 (kept apart: the rotation subtracts them one after the other), 1/rho and
+  // the (r+1)-th singular value
   for (int c = tid; c < r; c += blockDim.x) {
     pr[(size_t)b * (2 * r + 2) + c] = R[c];
     pr[(size_t)b * (2 * r + 2) + r + c] = R[r + 1 + c];
   }
-  if (tid == 0) pr[(size_t)b * (2 * r + 2) + 2 * r] = rho_s > 0.0 ? 1.0 / rho_s : 0.0;
+  if (tid == 0) {
+    pr[(size_t)b * (2 * r + 2) + 2 * r] = rho_s > 0.0 ? 1.0 / rho_s : 0.0;
+    pr[(size_t)b * (2 * r + 2) + 2 * r + 1] = sv[r];   // the truncated singular value
+  }
 }
 
 // Closed-form state transfer of an iSVD update: a <- Ubar[:r, :r]^T a (the new

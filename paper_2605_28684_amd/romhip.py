@@ -73,6 +73,7 @@ def _load():
         "fom_residual_vjp": [vp, vp, vp, d, vp, vp, vp, vp],
         "fom_step_vjp": [vp, vp, d, vp, vp, vp],
         "rom_rollout_vjp": [vp, vp, i32, d, i32, vp, vp, vp],
+        "rom_online_vjp": [vp, i32, i32, vp, vp, vp, vp, vp, vp],
         "rom_autotune": [vp, i32, vp, ctypes.POINTER(i32), vp],
         "rom_set_tuning": [vp, i32, i32, ctypes.POINTER(i32)],
         "rom_query": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -91,7 +92,7 @@ def _load():
 LIB = _load()
 SYMBOLS = ("rom_create", "rom_destroy", "fom_residual", "fom_step", "isvd_update", "rom_rebuild",
            "rom_step", "rom_get", "rom_set", "rom_get_status", "rom_clear_status",
-           "fom_residual_vjp", "fom_step_vjp", "rom_rollout_vjp", "rom_autotune",
+           "fom_residual_vjp", "fom_step_vjp", "rom_rollout_vjp", "rom_online_vjp", "rom_autotune",
            "rom_set_tuning", "rom_query", "rom_profile", "rom_last_error")
 TUNE_RESIDUAL = 0
 PROF_RESIDUAL, PROF_GALERKIN_PASS, PROF_ISVD_PROJECT, PROF_RESIDUAL_VJP, PROF_FOM_STEP = range(5)
@@ -204,6 +205,21 @@ class RomBatch:
         _check(LIB.rom_rollout_vjp(self.h, _ptr(q0), int(n_steps), float(dt), int(n_ckpt),
                                    _ptr(gbar), _ptr(out), _stream()))
         return out
+
+    def online_vjp(self, n_fine, qbar, n_ckpt=0):
+        """Gradient of <qbar, q~_end> over n_fine online steps (events included)
+        with respect to the starting (a, Phi, sigma, y_corr); FP64 tensors.
+        Advances the state as rom_step(n_fine) would."""
+        import torch
+        B, r, tot = self.n_inst, self.r, self.total_dof
+        dev = torch.device("cuda", torch.cuda.current_device())
+        ab = torch.empty(B * r, dtype=torch.float64, device=dev)
+        pb = torch.empty(tot * r, dtype=torch.float64, device=dev)
+        sb = torch.empty(B * r, dtype=torch.float64, device=dev)
+        yb = torch.empty(tot, dtype=torch.float64, device=dev)
+        _check(LIB.rom_online_vjp(self.h, int(n_fine), int(n_ckpt), _ptr(qbar), _ptr(ab),
+                                  _ptr(pb), _ptr(sb), _ptr(yb), _stream()))
+        return ab, pb, sb, yb
 
     # ---- reduced model
     def isvd_update(self, y):

@@ -1,0 +1,138 @@
+"""GPU parity of the online-loop adjoint (rom_online_vjp) against the
+oracle's reverse mode (oracle/adjoint.py, itself pinned by finite
+differences): Galerkin steps with two adaptation events on a ragged FP64
+Burgers batch, from the oracle's offline state; checkpoint-count invariance;
+the handle's state afterwards equals rom_step's."""
+import numpy as np
+import pytest
+
+from oracle import adjoint as A
+from oracle import rom as O
+from paper_2605_28684_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CELLS = [64, 96]
+R = 4
+N_FINE = 7          # fine steps n = 4 .. 10; events after n = 6 and n = 9
+
+
+def _prm():
+    return O.default_params(r=R, n_s=R, w_init=R, z=3, dt=2e-3, lam=0.7, newton_tol=1e-13,
+                            newton_max=30, rom_tol=1e-14, rom_max=30, reorth_every=0)
+
+
+def _workload(prm, precision):
+    w = W.burgers_batch_f32(n_inst=len(CELLS), r=R, z=prm["z"], w_init=prm["w_init"],
+                            precision=precision)
+    w.n_cells = list(CELLS)
+    w.phys = [dict(nu=0.01), dict(nu=0.006)]
+    w.q0 = np.concatenate([0.4 + 0.3 * np.sin(2 * np.pi * W.centres(n) + 0.5 * b)
+                           + 0.1 * np.cos(6 * np.pi * W.centres(n) + 0.4)
+                           for b, n in enumerate(CELLS)])
+    w.dt, w.lam = prm["dt"], prm["lam"]
+    w.newton_tol, w.newton_max = prm["newton_tol"], prm["newton_max"]
+    w.rom_tol, w.rom_max = prm["rom_tol"], prm["rom_max"]
+    w.reorth_every, w.tau_rho = 0, prm["tau_rho"]
+    return w
+
+
+def _start(w, prm, precision):
+    """Oracle offline state per instance (basis and states rounded to the
+    storage precision) and a device handle loaded with it."""
+    import gpu_common as G
+    import torch
+    from paper_2605_28684_amd import romhip as RH
+    off = w.offsets()
+    sts = []
+    for b in range(len(CELLS)):
+        st = O.offline(W.BURGERS, w.phys[b], w.q0[off[b]:off[b + 1]], prm)
+        for k in ("Phi", "q_ref", "y_corr"):
+            st[k] = G.rounded(st[k], precision)
+        sts.append(st)
+    h = RH.RomBatch(w, q0=G.to_dev(w.q0, precision), use_graph=False)
+    h.set(RH.GET_BASIS, G.to_dev(np.concatenate([s["Phi"].reshape(-1) for s in sts]), precision))
+    h.set(RH.GET_SIGMA, torch.as_tensor(np.concatenate([s["sigma"] for s in sts])))
+    h.set(RH.GET_A, torch.as_tensor(np.concatenate([s["a"] for s in sts])))
+    h.set(RH.GET_QREF, G.to_dev(np.concatenate([s["q_ref"] for s in sts]), precision))
+    h.set(RH.GET_DVAR, torch.as_tensor(np.concatenate([s["d_var"] for s in sts])))
+    h.set(RH.GET_YCORR, G.to_dev(np.concatenate([s["y_corr"] for s in sts]), precision))
+    h.set(RH.GET_COUNTERS, [prm["w_init"], 0, 0, 0])
+    return h, sts
+
+
+def _qbar(w, prm, sts, seed=11):
+    """dL/dq~ for L = 1/2 |q~_end - q_tgt|^2, from the oracle's forward."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for b, st in enumerate(sts):
+        fin, _ = A.online_forward(W.BURGERS, w.phys[b], st, prm, prm["w_init"], N_FINE)
+        qt = O.reconstruct(fin["q_ref"], fin["d"], fin["Phi"], fin["a"])
+        out.append(qt - (qt + 0.05 * rng.normal(size=qt.shape)))
+    return np.concatenate(out)
+
+
+def test_online_vjp_matches_oracle_fp64():
+    import gpu_common as G
+    prm = _prm()
+    w = _workload(prm, W.F64)
+    h, sts = _start(w, prm, W.F64)
+    qbar = _qbar(w, prm, sts)
+    ab, pb, sb, yb = [G.host(t) for t in h.online_vjp(N_FINE, G.to_dev(qbar, W.F64))]
+    assert not np.any(h.status() & 0x10)   # no singular solve / degenerate event
+    off = w.offsets()
+    for b, st in enumerate(sts):
+        sl = slice(off[b], off[b + 1])
+        ra, rP, rs, ry = A.online_vjp(W.BURGERS, w.phys[b], st, prm, prm["w_init"], N_FINE,
+                                      qbar[sl])
+        # measured: a ~1e-13, Phi and y_corr ~5e-12; sigma's gradient is ~1e-7 the
+        # size of the others, so its FP64 round-off shows as ~2e-9 relative
+        assert G.relerr(ab[b * R:(b + 1) * R], ra) < 1e-10, (b, G.relerr(ab[b * R:(b + 1) * R], ra))
+        assert G.relerr(pb[off[b] * R:off[b + 1] * R], rP.reshape(-1)) < 1e-10, b
+        assert G.relerr(sb[b * R:(b + 1) * R], rs) < 1e-8, (b, sb[b * R:(b + 1) * R], rs)
+        assert G.relerr(yb[sl], ry) < 1e-10, (b, G.relerr(yb[sl], ry))
+
+
+def test_online_vjp_fp32_storage_near_oracle():
+    """FP32 basis and states (FP64 reduced algebra): the gradients follow the FP32
+    forward trajectory, whose snapshots enter through D = 1/phi_norm (about 4e4
+    here), so they sit within 1e-2 of the FP64 oracle (measured 5e-4 .. 3.4e-3)."""
+    import gpu_common as G
+    prm = _prm()
+    w = _workload(prm, W.F32)
+    w.newton_tol, w.rom_tol = 1e-6, 1e-7
+    h, sts = _start(w, prm, W.F32)
+    qbar = _qbar(w, prm, sts)
+    ab, pb, sb, yb = [G.host(t) for t in h.online_vjp(N_FINE, G.to_dev(qbar, W.F32))]
+    assert not np.any(h.status() & 0x10)
+    off = w.offsets()
+    for b, st in enumerate(sts):
+        sl = slice(off[b], off[b + 1])
+        ra, rP, rs, ry = A.online_vjp(W.BURGERS, w.phys[b], st, prm, prm["w_init"], N_FINE,
+                                      qbar[sl])
+        for got, ref in ((ab[b * R:(b + 1) * R], ra), (pb[off[b] * R:off[b + 1] * R], rP.reshape(-1)),
+                         (sb[b * R:(b + 1) * R], rs), (yb[sl], ry)):
+            assert np.all(np.isfinite(got))
+            assert G.relerr(got, ref) < 1e-2, (b, G.relerr(got, ref))
+
+
+def test_online_vjp_checkpoint_invariance_and_end_state():
+    import gpu_common as G
+    from paper_2605_28684_amd import romhip as RH
+    prm = _prm()
+    w = _workload(prm, W.F64)
+    h0, sts = _start(w, prm, W.F64)
+    qbar = G.to_dev(_qbar(w, prm, sts), W.F64)
+    h0.rom_step(N_FINE)
+    end = {k: G.host(h0.get(k)).copy() for k in (RH.GET_A, RH.GET_BASIS, RH.GET_SIGMA, RH.GET_YCORR)}
+    res = []
+    for nc in (1, 3, N_FINE):
+        h, _ = _start(w, prm, W.F64)
+        res.append([G.host(t).copy() for t in h.online_vjp(N_FINE, qbar, n_ckpt=nc)])
+        for k, v in end.items():
+            assert np.array_equal(G.host(h.get(k)), v), (nc, k)
+        assert list(h.get(RH.GET_COUNTERS))[:3] == list(h0.get(RH.GET_COUNTERS))[:3]
+        h.close()
+    for other in res[1:]:
+        for x, y in zip(res[0], other):
+            assert np.array_equal(x, y)
