@@ -24,11 +24,13 @@
 #include "linalg.h"
 #include "physics.h"
 
+#define DEV_HOST_INLINE __host__ __device__ inline
+
 namespace romhip {
 
 namespace {
 
-constexpr int kAT = 256;   // threads per instance
+constexpr int kAT = 1024;  // threads per instance (seed and step adjoints)
 
 // Block-wide sum of one double per thread (all threads call; result in all).
 DEV double block_sum(double v, double* red) {
@@ -59,26 +61,31 @@ DEV void burgers_col(double um, double u0, double up, double nu, double inv, dou
 
 DEV int64_t wrap(int64_t c, int64_t n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
+constexpr int kSC = 64;   // rows of a staged chunk in the seed and step adjoints
+
 template <typename T>
 __global__ __launch_bounds__(kAT) void k_online_seed(
     int r, const int64_t* __restrict__ dof_off, const double* __restrict__ dvar,
     const T* __restrict__ Phi, const double* __restrict__ a, const T* __restrict__ qbar,
     double* __restrict__ abar, double* __restrict__ phibar) {
-  __shared__ double red[kAT / 64];
+  __shared__ double cP[kSC * kMaxR];
+  __shared__ double cq[kSC];
   const int b = blockIdx.x, tid = threadIdx.x;
   const int64_t base = dof_off[b], n = dof_off[b + 1] - base;
   const double dinv = 1.0 / dvar[b];
-  for (int c = 0; c < r; ++c) {
-    double s = 0.0;
-    for (int64_t i = tid; i < n; i += kAT) s += (double)Phi[(base + i) * r + c] * (double)qbar[base + i];
-    s = block_sum(s, red);
-    if (tid == 0) abar[(size_t)b * r + c] = s * dinv;
+  double acc = 0.0;   // thread c < r: (Phi^T qbar)_c
+  for (int64_t r0 = 0; r0 < n; r0 += kSC) {
+    const int nr = (int)(n - r0 < kSC ? n - r0 : kSC);
+    for (int e = tid; e < nr * r; e += kAT) cP[e] = (double)Phi[(base + r0) * r + e];
+    for (int k = tid; k < nr; k += kAT) cq[k] = (double)qbar[base + r0 + k];
+    __syncthreads();
+    if (tid < r)
+      for (int k = 0; k < nr; ++k) acc += cP[k * r + tid] * cq[k];
+    for (int e = tid; e < nr * r; e += kAT)
+      phibar[(base + r0) * r + e] = cq[e / r] * dinv * a[(size_t)b * r + e % r];
+    __syncthreads();
   }
-  for (int64_t e = tid; e < n * r; e += kAT) {
-    const int64_t i = e / r;
-    const int c = (int)(e % r);
-    phibar[(base + i) * r + c] = (double)qbar[base + i] * dinv * a[(size_t)b * r + c];
-  }
+  if (tid < r) abar[(size_t)b * r + tid] = acc * dinv;
 }
 
 // One fine step backward.  mpart/tfirst: the Galerkin pass's tile partials of
@@ -140,14 +147,62 @@ __global__ __launch_bounds__(kAT) void k_step_vjp(
   }
 }
 
+constexpr int kET = 512;  // threads of the event adjoint
+
+constexpr int kEChunk = 8192;   // elements of a staged chunk (rows x r), at most
+constexpr int kELds = 19200;    // doubles of dynamic LDS, at most (150 KB)
+
+// Rows of a staged chunk: as many as the LDS left after the three n x n core
+// matrices holds (two rows x r arrays and four per-row scalars), at most 1024
+// rows and kEChunk elements.
+DEV_HOST_INLINE int event_chunk_rows(int r) {
+  const int n = r + 1;
+  int c = (kELds - 3 * n * n - n) / (2 * r + 4);
+  if (c > kEChunk / r) c = kEChunk / r;
+  return c > 1024 ? 1024 : c;
+}
+
+constexpr int kEPF = (kEChunk + kET - 1) / kET;   // chunk elements per thread
+
+// Loads of one chunk (ne <= kEChunk elements from offset off) into registers, so that the
+// next chunk is in flight while the current one is processed from LDS.
+template <typename T>
+DEV void chunk_fetch(const T* __restrict__ Phi, const double* __restrict__ pb, int64_t off, int ne,
+                     bool with_b, double (&rp)[kEPF], double (&rb)[kEPF]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kEPF; ++u) {
+    const int e = tid + u * kET;
+    if (e < ne) {
+      rp[u] = (double)Phi[off + e];
+      if (with_b) rb[u] = pb[off + e];
+    }
+  }
+}
+
+DEV void chunk_put(double* cP, double* cB, int ne, bool with_b, const double (&rp)[kEPF],
+                   const double (&rb)[kEPF]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kEPF; ++u) {
+    const int e = tid + u * kET;
+    if (e < ne) {
+      cP[e] = rp[u];
+      if (with_b) cB[e] = rb[u];
+    }
+  }
+}
+
 // One event backward, from the transfer down to yhat (the coarse step's
 // transposed solve follows outside).  Inputs recorded in the forward pass:
 // Phi_old, y_new (after the coarse step), sigma_old, a_old (before the
-// transfer), Ubar (n x n), pr = (p1, p2, 1/rho, s_{n}).  abar, sigbar and the
+// transfer), Ubar (n x n), pr = (p1, p2, 1/rho, s_n).  abar, sigbar and the
 // rows of phibar are replaced by the adjoints of the pre-event state; ybar
-// receives D yhatbar.  Dynamic LDS: 4 n^2 doubles.
+// receives D yhatbar.  Rows are streamed in chunks staged in LDS (Phi as FP64
+// and the matching rows of phibar); dynamic LDS: 3 n^2 + 2 C r + 4 C + n
+// doubles for C = event_chunk_rows(r).
 template <typename T>
-__global__ __launch_bounds__(kAT) void k_event_vjp(
+__global__ __launch_bounds__(kET) void k_event_vjp(
     int r, double lam_f, const int64_t* __restrict__ dof_off, const double* __restrict__ dvar,
     const T* __restrict__ Phi, const T* __restrict__ ynew, const T* __restrict__ qref,
     const double* __restrict__ sig_old, const double* __restrict__ a_old,
@@ -156,20 +211,27 @@ __global__ __launch_bounds__(kAT) void k_event_vjp(
     double* __restrict__ phibar, double* __restrict__ sigbar, double* __restrict__ ybar,
     double* __restrict__ qs, double* __restrict__ js, uint32_t* flags) {
   extern __shared__ double sm[];
-  __shared__ double red[kAT / 64];
-  __shared__ double vr[6][kMaxR + 1];  // p1, p2, abar', pbar, p1bar, p2bar
+  __shared__ double red[kET / 64];
+  __shared__ double vr[7][kMaxR + 1];  // p1, p2, abar', pbar (rhobar in [r]), p1bar, p2bar, wr
   __shared__ double sv[kMaxR + 1];
   const int n = r + 1, tid = threadIdx.x, b = blockIdx.x;
-  double* U = sm;              // Ubar
-  double* Ub = U + n * n;      // its adjoint, then G
-  double* Mm = Ub + n * n;     // U^T Ub, then T = G V^T
-  double* V = Mm + n * n;
+  const int CH = event_chunk_rows(r);
+  double* U = sm;               // Ubar
+  double* Ub = U + n * n;       // its adjoint, then G
+  double* X = Ub + n * n;       // U^T Ub, then V
+  double* cP = X + n * n;       // chunk of Phi rows (FP64)
+  double* cB = cP + CH * r;     // the same rows of phibar
+  double* c0 = cB + CH * r;     // per-row scalars of the chunk
+  double* c1 = c0 + CH;
+  double* c2 = c1 + CH;
+  double* c3 = c2 + CH;
   double* p1 = vr[0];
   double* p2 = vr[1];
   double* ab = vr[2];
   double* pb = vr[3];
   double* p1b = vr[4];
   double* p2b = vr[5];
+  double* wr = vr[6];
   const int64_t base = dof_off[b], nd = dof_off[b + 1] - base;
   const double d = dvar[b];
   const double* pr = prs + (size_t)b * (2 * r + 2);
@@ -179,11 +241,11 @@ __global__ __launch_bounds__(kAT) void k_event_vjp(
     return;
   }
   const double rho = 1.0 / irho;
-  for (int e = tid; e < n * n; e += kAT) {
+  for (int e = tid; e < n * n; e += kET) {
     U[e] = ubar[(size_t)b * n * n + e];
     Ub[e] = 0.0;
   }
-  for (int c = tid; c < r; c += kAT) {
+  for (int c = tid; c < r; c += kET) {
     p1[c] = pr[c];
     p2[c] = pr[r + c];
     ab[c] = abar[(size_t)b * r + c];
@@ -192,155 +254,189 @@ __global__ __launch_bounds__(kAT) void k_event_vjp(
   if (tid == 0) sv[r] = pr[2 * r + 1];
   __syncthreads();
   // transfer a' = U[:r, :r]^T a: abar_old = U[:r, :r] abar, Ubar[:r, :r] += a_old abar^T
-  for (int c = tid; c < r; c += kAT) {
+  for (int c = tid; c < r; c += kET) {
     double s = 0.0;
     for (int k = 0; k < r; ++k) s += U[c * n + k] * ab[k];
     abar[(size_t)b * r + c] = s;
   }
-  for (int e = tid; e < r * r; e += kAT) {
+  for (int e = tid; e < r * r; e += kET) {
     const int i = e / r, j = e % r;
     Ub[i * n + j] += a_old[(size_t)b * r + i] * ab[j];
   }
   __syncthreads();
-  // rotation: Ubar[:r, :r] += Phi^T Phibar', Ubar[r, :r] += j^T Phibar' (j = q / rho),
-  // computed before the rows of Phibar are replaced
-  for (int64_t i = tid; i < nd; i += kAT) {
-    const T* ph = Phi + (base + i) * r;
-    double q = d * ((double)ynew[base + i] - (double)qref[base + i]);
-    for (int c = 0; c < r; ++c) q -= (double)ph[c] * (p1[c] + p2[c]);
-    qs[base + i] = q;
-  }
-  __syncthreads();
-  for (int e = tid; e < n * r; e += kAT) {
-    const int i = e / r, j = e % r;   // row i of [Phi, j]^T, column j of Phibar'
-    double s = 0.0;
-    if (i < r)
-      for (int64_t k = 0; k < nd; ++k) s += (double)Phi[(base + k) * r + i] * phibar[(base + k) * r + j];
-    else
-      for (int64_t k = 0; k < nd; ++k) s += qs[base + k] * irho * phibar[(base + k) * r + j];
-    Ub[i * n + j] += s;
-  }
-  // rows: Phibar_old = Phibar' U[:r, :r]^T, jbar = Phibar' U[r, :r]^T (in js)
+  // pass A: q = yhat - Phi (p1 + p2); rotation adjoint Ubar[:r, :r] += Phi^T Phibar',
+  // Ubar[r, :r] += (q / rho)^T Phibar'; rows Phibar_old = Phibar' U[:r, :r]^T and
+  // jbar = Phibar' U[r, :r]^T; jq = jbar . q
   double jq = 0.0;
-  __syncthreads();
-  for (int64_t i = tid; i < nd; i += kAT) {
-    double* pb_row = phibar + (base + i) * r;
-    double row[kMaxR];
-    for (int c = 0; c < r; ++c) row[c] = pb_row[c];
-    double jb = 0.0;
-    for (int c = 0; c < r; ++c) jb += row[c] * U[r * n + c];
-    for (int k = 0; k < r; ++k) {
-      double s = 0.0;
-      for (int c = 0; c < r; ++c) s += row[c] * U[k * n + c];
-      pb_row[k] = s;
+  double rp[kEPF], rb[kEPF];
+  auto chunk_ne = [&](int64_t r0) { return (int)((nd - r0 < CH ? nd - r0 : CH) * r); };
+  if (nd > 0) chunk_fetch(Phi, phibar, base * r, chunk_ne(0), true, rp, rb);
+  for (int64_t r0 = 0; r0 < nd; r0 += CH) {
+    const int nr = (int)(nd - r0 < CH ? nd - r0 : CH);
+    chunk_put(cP, cB, nr * r, true, rp, rb);
+    __syncthreads();
+    if (r0 + CH < nd) chunk_fetch(Phi, phibar, (base + r0 + CH) * r, chunk_ne(r0 + CH), true, rp, rb);
+    for (int k = tid; k < nr; k += kET) {
+      double q = d * ((double)ynew[base + r0 + k] - (double)qref[base + r0 + k]);
+      for (int c = 0; c < r; ++c) q -= cP[k * r + c] * (p1[c] + p2[c]);
+      c0[k] = q;
+      qs[base + r0 + k] = q;
     }
-    js[base + i] = jb;
-    jq += jb * qs[base + i];
+    __syncthreads();
+    for (int e = tid; e < n * r; e += kET) {
+      const int i = e / r, j = e % r;
+      double s = 0.0;
+      if (i < r)
+        for (int k = 0; k < nr; ++k) s += cP[k * r + i] * cB[k * r + j];
+      else
+        for (int k = 0; k < nr; ++k) s += c0[k] * irho * cB[k * r + j];
+      Ub[i * n + j] += s;
+    }
+    for (int e = tid; e < nr * n; e += kET) {
+      const int k = e / n, c = e % n;
+      double s = 0.0;
+      for (int m = 0; m < r; ++m) s += cB[k * r + m] * U[c * n + m];
+      if (c < r) phibar[(base + r0 + k) * r + c] = s;
+      else {
+        js[base + r0 + k] = s;
+        jq += s * c0[k];
+      }
+    }
+    __syncthreads();
   }
   jq = block_sum(jq, red);
-  // SVD of K: V = K^T U / s, M = U^T Ubar, G, T = G V^T, Kbar entries needed
-  for (int e = tid; e < n * n; e += kAT) {
-    const int k = e / n, j = e % n;   // V[k][j]
-    double s = 0.0;
-    if (sv[j] > 0.0) {
-      const double kt = k < r ? lam_f * sig_old[(size_t)b * r + k] * U[k * n + j]
-                              : [&] {
-                                  double t = rho * U[r * n + j];
-                                  for (int i = 0; i < r; ++i) t += (p1[i] + p2[i]) * U[i * n + j];
-                                  return t;
-                                }();
-      s = kt / sv[j];
-    }
-    V[e] = s;
-  }
-  for (int e = tid; e < n * n; e += kAT) {
+  // SVD of K: M = U^T Ub (in X), G (in Ub), V = K^T U / s (in X), then the entries of
+  // Kbar = U G V^T that K depends on: lambda sigma (diagonal), p (last column), rho
+  for (int e = tid; e < n * n; e += kET) {
     const int i = e / n, j = e % n;
     double s = 0.0;
     for (int k = 0; k < n; ++k) s += U[k * n + i] * Ub[k * n + j];
-    Mm[e] = s;
+    X[e] = s;
   }
   __syncthreads();
-  for (int e = tid; e < n * n; e += kAT) {
+  for (int e = tid; e < n * n; e += kET) {
     const int i = e / n, j = e % n;
     double g;
     if (i == j) g = i < r ? sigbar[(size_t)b * r + i] : 0.0;
-    else g = sv[j] > 0.0 ? sv[j] * (Mm[i * n + j] - Mm[j * n + i]) / ((sv[j] - sv[i]) * (sv[j] + sv[i]))
+    else g = sv[j] > 0.0 ? sv[j] * (X[i * n + j] - X[j * n + i]) / ((sv[j] - sv[i]) * (sv[j] + sv[i]))
                          : 0.0;
-    Ub[e] = g;   // G
+    Ub[e] = g;
   }
   __syncthreads();
-  for (int e = tid; e < n * n; e += kAT) {   // T = G V^T
-    const int i = e / n, j = e % n;
+  for (int e = tid; e < n * n; e += kET) {
+    const int k = e / n, j = e % n;   // V[k][j]
+    double v = 0.0;
+    if (sv[j] > 0.0) {
+      double t;
+      if (k < r) {
+        t = lam_f * sig_old[(size_t)b * r + k] * U[k * n + j];
+      } else {
+        t = rho * U[r * n + j];
+        for (int i = 0; i < r; ++i) t += (p1[i] + p2[i]) * U[i * n + j];
+      }
+      v = t / sv[j];
+    }
+    X[e] = v;
+  }
+  __syncthreads();
+  for (int k = tid; k < n; k += kET) {   // wr = G V[r, :]^T
     double s = 0.0;
-    for (int k = 0; k < n; ++k) s += Ub[i * n + k] * V[j * n + k];
-    Mm[e] = s;
+    for (int m = 0; m < n; ++m) s += Ub[k * n + m] * X[r * n + m];
+    wr[k] = s;
   }
   __syncthreads();
-  // Kbar = U T: sigma_old (diagonal, times lambda), p (last column), rho (corner)
-  for (int c = tid; c < n; c += kAT) {
+  for (int c = tid; c < n; c += kET) {
     double kd = 0.0, kc = 0.0;
     for (int k = 0; k < n; ++k) {
-      kd += U[c * n + k] * Mm[k * n + c];
-      kc += U[c * n + k] * Mm[k * n + r];
+      double gv = 0.0;   // (G V^T)[k][c]
+      for (int m = 0; m < n; ++m) gv += Ub[k * n + m] * X[c * n + m];
+      kd += U[c * n + k] * gv;
+      kc += U[c * n + k] * wr[k];
     }
     if (c < r) {
       sigbar[(size_t)b * r + c] = lam_f * kd;
       pb[c] = kc;
     } else {
-      pb[r] = kc;   // rhobar from K
+      pb[r] = kc;
     }
   }
   __syncthreads();
-  // j = q / rho, rho = |q|: qbar = jbar / rho + rhobar q / rho
+  // j = q / rho, rho = |q|: qbar = (jbar + rhobar q) / rho
   const double rhob = pb[r] - jq * irho * irho;
-  double t2 = 0.0;
-  // pass 2: qbar (into js); Phibar_old -= qbar p2^T; t2 = Phi^T qbar
-  for (int c = 0; c < r; ++c) {
-    double s = 0.0;
-    for (int64_t i = tid; i < nd; i += kAT) {
-      const double qb = (js[base + i] + rhob * qs[base + i]) * irho;
-      s += (double)Phi[(base + i) * r + c] * qb;
-    }
-    s = block_sum(s, red);
-    if (tid == 0) p2b[c] = pb[c] - s;
+  // pass B: p2bar = pbar - Phi^T qbar
+  double acc = 0.0;
+  if (nd > 0) chunk_fetch(Phi, phibar, base * r, chunk_ne(0), false, rp, rb);
+  for (int64_t r0 = 0; r0 < nd; r0 += CH) {
+    const int nr = (int)(nd - r0 < CH ? nd - r0 : CH);
+    chunk_put(cP, cB, nr * r, false, rp, rb);
+    if (r0 + CH < nd) chunk_fetch(Phi, phibar, (base + r0 + CH) * r, chunk_ne(r0 + CH), false, rp, rb);
+    for (int k = tid; k < nr; k += kET)
+      c0[k] = (js[base + r0 + k] + rhob * qs[base + r0 + k]) * irho;
+    __syncthreads();
+    if (tid < r)
+      for (int k = 0; k < nr; ++k) acc += cP[k * r + tid] * c0[k];
+    __syncthreads();
   }
-  (void)t2;
+  if (tid < r) p2b[tid] = pb[tid] - acc;
   __syncthreads();
-  for (int64_t i = tid; i < nd; i += kAT) {
-    const double qb = (js[base + i] + rhob * qs[base + i]) * irho;
-    const T* ph = Phi + (base + i) * r;
-    double* pbr = phibar + (base + i) * r;
-    // q1 = yhat - Phi p1
-    double q1 = d * ((double)ynew[base + i] - (double)qref[base + i]);
-    for (int c = 0; c < r; ++c) q1 -= (double)ph[c] * p1[c];
-    double q1b = qb;
-    for (int c = 0; c < r; ++c) {
-      pbr[c] += -qb * p2[c] + q1 * p2b[c];
-      q1b += (double)ph[c] * p2b[c];
+  // pass C: q1 = yhat - Phi p1, q1bar = qbar + Phi p2bar (into js);
+  // Phibar_old += -qbar p2^T + q1 p2bar^T; p1bar = pbar - Phi^T q1bar
+  acc = 0.0;
+  if (nd > 0) chunk_fetch(Phi, phibar, base * r, chunk_ne(0), true, rp, rb);
+  for (int64_t r0 = 0; r0 < nd; r0 += CH) {
+    const int nr = (int)(nd - r0 < CH ? nd - r0 : CH);
+    chunk_put(cP, cB, nr * r, true, rp, rb);
+    __syncthreads();
+    if (r0 + CH < nd) chunk_fetch(Phi, phibar, (base + r0 + CH) * r, chunk_ne(r0 + CH), true, rp, rb);
+    for (int k = tid; k < nr; k += kET) {
+      const int64_t g = base + r0 + k;
+      double q1 = d * ((double)ynew[g] - (double)qref[g]);
+      double t = 0.0;
+      for (int c = 0; c < r; ++c) {
+        q1 -= cP[k * r + c] * p1[c];
+        t += cP[k * r + c] * p2b[c];
+      }
+      const double qb = (js[g] + rhob * qs[g]) * irho;
+      c0[k] = qb;
+      c1[k] = q1;
+      c2[k] = qb + t;   // q1bar
+      js[g] = qb + t;
     }
-    js[base + i] = q1b;   // q1bar
-  }
-  __syncthreads();
-  // p1bar = pbar - Phi^T q1bar
-  for (int c = 0; c < r; ++c) {
-    double s = 0.0;
-    for (int64_t i = tid; i < nd; i += kAT) s += (double)Phi[(base + i) * r + c] * js[base + i];
-    s = block_sum(s, red);
-    if (tid == 0) p1b[c] = pb[c] - s;
-  }
-  __syncthreads();
-  // Phibar_old += -q1bar p1^T + yhat p1bar^T; yhatbar = q1bar + Phi p1bar; ybar += D yhatbar
-  for (int64_t i = tid; i < nd; i += kAT) {
-    const T* ph = Phi + (base + i) * r;
-    double* pbr = phibar + (base + i) * r;
-    const double yh = d * ((double)ynew[base + i] - (double)qref[base + i]);
-    const double q1b = js[base + i];
-    double yb = q1b;
-    for (int c = 0; c < r; ++c) {
-      pbr[c] += -q1b * p1[c] + yh * p1b[c];
-      yb += (double)ph[c] * p1b[c];
+    __syncthreads();
+    for (int e = tid; e < nr * r; e += kET) {
+      const int k = e / r, c = e % r;
+      phibar[(base + r0) * r + e] = cB[e] - c0[k] * p2[c] + c1[k] * p2b[c];
     }
-    ybar[base + i] += d * yb;
+    if (tid < r)
+      for (int k = 0; k < nr; ++k) acc += cP[k * r + tid] * c2[k];
+    __syncthreads();
+  }
+  if (tid < r) p1b[tid] = pb[tid] - acc;
+  __syncthreads();
+  // pass D: Phibar_old += -q1bar p1^T + yhat p1bar^T; yhatbar = q1bar + Phi p1bar;
+  // ybar += D yhatbar
+  if (nd > 0) chunk_fetch(Phi, phibar, base * r, chunk_ne(0), true, rp, rb);
+  for (int64_t r0 = 0; r0 < nd; r0 += CH) {
+    const int nr = (int)(nd - r0 < CH ? nd - r0 : CH);
+    chunk_put(cP, cB, nr * r, true, rp, rb);
+    __syncthreads();
+    if (r0 + CH < nd) chunk_fetch(Phi, phibar, (base + r0 + CH) * r, chunk_ne(r0 + CH), true, rp, rb);
+    for (int k = tid; k < nr; k += kET) {
+      const int64_t g = base + r0 + k;
+      const double yh = d * ((double)ynew[g] - (double)qref[g]);
+      const double q1b = js[g];
+      double t = 0.0;
+      for (int c = 0; c < r; ++c) t += cP[k * r + c] * p1b[c];
+      c0[k] = q1b;
+      c1[k] = yh;
+      ybar[g] += d * (q1b + t);
+    }
+    __syncthreads();
+    for (int e = tid; e < nr * r; e += kET) {
+      const int k = e / r, c = e % r;
+      phibar[(base + r0) * r + e] = cB[e] - c0[k] * p1[c] + c1[k] * p1b[c];
+    }
+    __syncthreads();
   }
 }
 
@@ -385,7 +481,10 @@ rom_status launch_step_vjp(rom_batch* h, const void* Phi, const double* a1, doub
   return ROM_OK;
 }
 
-size_t event_vjp_shm(int r) { return sizeof(double) * 4 * (size_t)(r + 1) * (r + 1); }
+size_t event_vjp_shm(int r) {
+  const size_t n = (size_t)r + 1, C = (size_t)event_chunk_rows(r);
+  return sizeof(double) * (3 * n * n + 2 * C * r + 4 * C + n);
+}
 
 rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new,
                             const double* sig_old, const double* a_old, const double* ubar,
@@ -395,12 +494,12 @@ rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new
   const int B = h->cfg.n_inst, r = h->cfg.r;
   const size_t shm = event_vjp_shm(r);
   if (h->cfg.precision == ROM_F64)
-    hipLaunchKernelGGL((k_event_vjp<double>), dim3(B), dim3(kAT), shm, s, r, h->cfg.lambda,
+    hipLaunchKernelGGL((k_event_vjp<double>), dim3(B), dim3(kET), shm, s, r, h->cfg.lambda,
                        h->d_dof_off, h->d_var, (const double*)Phi_old, (const double*)y_new,
                        (const double*)h->q_ref, sig_old, a_old, ubar, pr, sig_new, abar, phibar,
                        sigbar, ybar, qs, js, h->flags);
   else
-    hipLaunchKernelGGL((k_event_vjp<float>), dim3(B), dim3(kAT), shm, s, r, h->cfg.lambda,
+    hipLaunchKernelGGL((k_event_vjp<float>), dim3(B), dim3(kET), shm, s, r, h->cfg.lambda,
                        h->d_dof_off, h->d_var, (const float*)Phi_old, (const float*)y_new,
                        (const float*)h->q_ref, sig_old, a_old, ubar, pr, sig_new, abar, phibar,
                        sigbar, ybar, qs, js, h->flags);
@@ -424,7 +523,7 @@ rom_status convert_words(const void* src, bool src_f64, void* dst, bool dst_f64,
 }
 
 rom_status adjoint_kernels_prepare() {
-  const int big = 160 * 1024 - 4096;
+  const int big = (int)(sizeof(double) * kELds);   // bound of event_vjp_shm(r) for every r
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_event_vjp<float>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, big));
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_event_vjp<double>,
