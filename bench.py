@@ -62,7 +62,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
-    p.add_argument("--only", choices=["all", "copy", "galerkin", "residual", "windows"],
+    p.add_argument("--only", choices=["all", "copy", "galerkin", "residual", "windows", "adjoint"],
                    default="all",
                    help="profiling runs: 'copy' times a plain 512 MiB device copy (the "
                         "reference for counter scaling), 'galerkin' only the Galerkin pass, "
@@ -115,6 +115,19 @@ def cpu_baseline(w, budget_s):
                                                          t_total))
 
 
+def adjoint_ms(torch, h, w, n_win):
+    """Wall time per window of rom_online_vjp over n_win whole windows (the forward
+    pass, its checkpointed recomputation and the reverse pass; the call
+    synchronises), after one untimed call."""
+    qbar = torch.full((h.total_dof,), 1e-3, dtype=torch.float32, device="cuda")
+    h.online_vjp(w.z, qbar)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.online_vjp(w.z * n_win, qbar)
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / n_win
+
+
 def profile_only(args, torch, W, R):
     """One kernel family at a time, for rocprofv3 counter runs."""
     reps = max(args.steps, 1)
@@ -142,6 +155,15 @@ def profile_only(args, torch, W, R):
             h.close()
         log("windows: %d after %d warm-up, %.3f ms each" % (
             args.steps, args.warmup, 1e3 * (t1 - t0) / max(args.steps, 1)))
+    elif args.only == "adjoint":
+        w = W.burgers_batch_f32()
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            h = R.RomBatch(w, q0=torch.as_tensor(w.q0, dtype=torch.float32, device="cuda"),
+                           use_graph=False)
+            ms = adjoint_ms(torch, h, w, max(args.steps, 1))
+            h.close()
+        log("online adjoint: %d window(s), %.3f ms per window" % (max(args.steps, 1), ms))
     elif args.only == "galerkin":
         w = W.burgers_batch_f32()
         s = torch.cuda.Stream()
@@ -215,6 +237,9 @@ def main():
                         traffic=traffic_bytes("k_galerkin_pass"), ms_per_launch=round(ms_pass, 5),
                         bytes_per_launch=int(bytes_pass))
         ms_proj = h.profile(R.PROF_ISVD_PROJECT, reps, h.get(R.GET_YCORR))
+        # the online adjoint (extension): gradient through whole windows
+        adj_ms = adjoint_ms(torch, h, w, 2)
+        log("online adjoint: %.3f ms per window" % adj_ms)
         h.close()
 
         # plain path: the same kernels per instance in a host loop, no graph
@@ -298,6 +323,10 @@ def main():
         "plain": plain,
         "fom_residual": fom,
         "isvd_project_ms": round(ms_proj, 5),
+        "online_adjoint": {"ms_per_window": round(adj_ms, 3), "windows": 2,
+                           "what": "rom_online_vjp: forward, sqrt(T) checkpointed recompute, "
+                                   "reverse (transposed reduced solves, iSVD backward, "
+                                   "transposed banded solves)"},
     }
     print(json.dumps(out), flush=True)
 

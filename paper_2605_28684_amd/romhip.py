@@ -329,3 +329,39 @@ class FomRollout(torch.autograd.Function):
         (q0,) = ctx.saved_tensors
         gq0 = ctx.handle.rollout_vjp(q0, ctx.n_steps, ctx.dt, g.contiguous(), ctx.n_ckpt)
         return gq0, None, None, None, None
+
+
+class RomOnline(torch.autograd.Function):
+    """q~ at the end of n_fine online steps of Alg. 1 (Galerkin steps and the
+    adaptation events that fall due) from the reduced state (a, Phi, sigma,
+    y_corr); the backward pass is the checkpointed online adjoint
+    (rom_online_vjp), which restarts from the saved inputs.  The handle's state
+    is overwritten by the inputs in both passes; q_ref, D and the fine-step
+    counter it holds at the first call are kept."""
+
+    @staticmethod
+    def forward(ctx, a, Phi, sigma, y_corr, handle, n_fine, n_ckpt=0):
+        counters = list(handle.get(GET_COUNTERS))
+        handle.set(GET_A, a.detach().contiguous())
+        handle.set(GET_BASIS, Phi.detach().contiguous())
+        handle.set(GET_SIGMA, sigma.detach().contiguous())
+        handle.set(GET_YCORR, y_corr.detach().contiguous())
+        handle.rom_step(int(n_fine))
+        q = handle.get(GET_QTILDE).clone()
+        ctx.save_for_backward(a.detach(), Phi.detach(), sigma.detach(), y_corr.detach())
+        ctx.handle, ctx.n_fine, ctx.n_ckpt, ctx.counters = handle, int(n_fine), int(n_ckpt), counters
+        return q
+
+    @staticmethod
+    def backward(ctx, g):
+        a, Phi, sigma, y_corr = ctx.saved_tensors
+        h = ctx.handle
+        h.set(GET_COUNTERS, ctx.counters)
+        h.set(GET_A, a.contiguous())
+        h.set(GET_BASIS, Phi.contiguous())
+        h.set(GET_SIGMA, sigma.contiguous())
+        h.set(GET_YCORR, y_corr.contiguous())
+        ab, pb, sb, yb = h.online_vjp(ctx.n_fine, g.contiguous().to(h.dtype), ctx.n_ckpt)
+        return (ab.to(a.dtype).view_as(a), pb.to(Phi.dtype).view_as(Phi),
+                sb.to(sigma.dtype).view_as(sigma), yb.to(y_corr.dtype).view_as(y_corr),
+                None, None, None)

@@ -37,16 +37,21 @@ def _workload(prm, precision):
     return w
 
 
-def _start(w, prm, precision):
+def _start(w, prm, precision, phi_noise=0.0):
     """Oracle offline state per instance (basis and states rounded to the
-    storage precision) and a device handle loaded with it."""
+    storage precision; the basis optionally perturbed off orthonormality) and a
+    device handle loaded with it."""
     import gpu_common as G
     import torch
     from paper_2605_28684_amd import romhip as RH
     off = w.offsets()
     sts = []
+    rng = np.random.default_rng(23)
     for b in range(len(CELLS)):
         st = O.offline(W.BURGERS, w.phys[b], w.q0[off[b]:off[b + 1]], prm)
+        if phi_noise:
+            st["Phi"] = st["Phi"] + phi_noise * rng.normal(size=st["Phi"].shape) / np.sqrt(
+                st["Phi"].shape[0])
         for k in ("Phi", "q_ref", "y_corr"):
             st[k] = G.rounded(st[k], precision)
         sts.append(st)
@@ -73,6 +78,9 @@ def _qbar(w, prm, sts, seed=11):
 
 
 def test_online_vjp_matches_oracle_fp64():
+    """From an orthonormal basis (the method keeps it so): the device forward
+    evaluates rho^2 as |q1|^2 - |p2|^2, equal to |q|^2 only there, so off
+    orthonormality its forward, not just its adjoint, differs from the oracle's."""
     import gpu_common as G
     prm = _prm()
     w = _workload(prm, W.F64)
@@ -136,3 +144,61 @@ def test_online_vjp_checkpoint_invariance_and_end_state():
     for other in res[1:]:
         for x, y in zip(res[0], other):
             assert np.array_equal(x, y)
+
+
+def test_rom_online_autograd_function_fp64():
+    """RomOnline: autograd through the online loop gives rom_online_vjp's
+    gradients, and its directional derivative along a and y_corr matches
+    Richardson-extrapolated central differences of the device forward."""
+    import gpu_common as G
+    import torch
+    from paper_2605_28684_amd import romhip as RH
+    prm = _prm()
+    w = _workload(prm, W.F64)
+    h, sts = _start(w, prm, W.F64)
+    a0 = h.get(RH.GET_A).clone()
+    P0 = h.get(RH.GET_BASIS).clone()
+    s0 = h.get(RH.GET_SIGMA).clone()
+    y0 = h.get(RH.GET_YCORR).clone()
+    q_tgt = torch.as_tensor(np.random.default_rng(3).normal(size=h.total_dof) * 0.05 + 0.4,
+                            device="cuda")
+
+    def loss(a, P, s, y):
+        q = RH.RomOnline.apply(a, P, s, y, h, N_FINE)
+        return 0.5 * torch.sum((q - q_tgt) ** 2)
+
+    leaves = [t.clone().requires_grad_(True) for t in (a0, P0, s0, y0)]
+    L = loss(*leaves)
+    L.backward()
+    grads = [t.grad.detach().clone() for t in leaves]
+    # the same through the C call directly
+    with torch.no_grad():
+        h.set(RH.GET_COUNTERS, [prm["w_init"], 0, 0, 0])
+        for k, t in zip((RH.GET_A, RH.GET_BASIS, RH.GET_SIGMA, RH.GET_YCORR), (a0, P0, s0, y0)):
+            h.set(k, t)
+        h.rom_step(N_FINE)
+        qb = h.get(RH.GET_QTILDE) - q_tgt
+        h.set(RH.GET_COUNTERS, [prm["w_init"], 0, 0, 0])
+        for k, t in zip((RH.GET_A, RH.GET_BASIS, RH.GET_SIGMA, RH.GET_YCORR), (a0, P0, s0, y0)):
+            h.set(k, t)
+        direct = h.online_vjp(N_FINE, qb)
+    for g, d in zip(grads, direct):
+        assert torch.equal(g, d)
+    # directional derivatives along a and y_corr through the device forward
+    rng = np.random.default_rng(7)
+    for idx, hstep in ((0, 1e-3), (3, 1e-6)):
+        v = torch.as_tensor(rng.normal(size=leaves[idx].numel()), device="cuda")
+        v = v / torch.linalg.norm(v)
+        dot = float(torch.sum(grads[idx] * v))
+
+        def L_at(e):
+            args = [t.detach() for t in (a0, P0, s0, y0)]
+            args[idx] = args[idx] + e * v
+            h.set(RH.GET_COUNTERS, [prm["w_init"], 0, 0, 0])
+            with torch.no_grad():
+                return float(loss(*args))
+
+        f1 = (L_at(hstep) - L_at(-hstep)) / (2 * hstep)
+        f2 = (L_at(hstep / 2) - L_at(-hstep / 2)) / hstep
+        fd = (4 * f2 - f1) / 3
+        assert abs(dot - fd) <= 1e-5 * abs(dot), (idx, dot, fd)

@@ -27,8 +27,13 @@ def _setup(n=64, r=4, z=3, seed=3):
 _STEPS = {"a": (1e-3, 1e-5), "Phi": (1e-5, 1e-5), "sigma": (1e-3, 1e-4), "y_corr": (1e-6, 1e-5)}
 
 
-def _fd_check(n_steps):
+def _fd_check(n_steps, phi_noise=0.0):
     prm, phys, st, q_tgt, rng = _setup()
+    if phi_noise:
+        # a non-orthonormal starting basis: terms that vanish when Phi^T Phi = I
+        # (the first Gram-Schmidt pass's p1bar) then carry weight
+        st["Phi"] = st["Phi"] + phi_noise * rng.normal(size=st["Phi"].shape) / np.sqrt(
+            st["Phi"].shape[0])
     n0 = prm["w_init"]
     out, _ = A.online_forward(W.BURGERS, phys, st, prm, n0, n_steps)
     qt = O.reconstruct(out["q_ref"], out["d"], out["Phi"], out["a"])
@@ -74,3 +79,7 @@ def test_adjoint_sigma_and_ycorr_unused_without_events():
     qt = O.reconstruct(out["q_ref"], out["d"], out["Phi"], out["a"])
     ab, Phib, sb, yb = A.online_vjp(W.BURGERS, phys, st, prm, prm["w_init"], 2, qt - q_tgt)
     assert np.all(sb == 0.0) and np.all(yb == 0.0)
+
+
+def test_adjoint_non_orthonormal_basis():
+    _fd_check(n_steps=7, phi_noise=0.3)
