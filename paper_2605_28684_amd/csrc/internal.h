@@ -232,7 +232,8 @@ rom_status isvd_kernels_prepare();
 
 // ---- mfma.hip (FP32, r in {32, 64})
 bool mfma_ok(const rom_batch* h);
-rom_status launch_galerkin_mfma(rom_batch* h, hipStream_t s);
+// first: the first Newton iteration of a step (every instance runs)
+rom_status launch_galerkin_mfma(rom_batch* h, hipStream_t s, int first = 0);
 rom_status launch_galerkin_tail(rom_batch* h, int it0, hipStream_t s);
 rom_status launch_rotate_mfma(rom_batch* h, const double* pr, hipStream_t s);
 rom_status launch_project_fast(rom_batch* h, const void* y, const double* p1, int ldp, int mode,

@@ -259,12 +259,13 @@ __attribute__((amdgpu_waves_per_eu(RT == 32 ? 4 : 1))) void k_galerkin_mfma(
     const int64_t* __restrict__ cell_off, const double* __restrict__ phys, int nphys,
     const float* __restrict__ Phi, const float* __restrict__ qref,
     const double* __restrict__ dvar, const double* __restrict__ a,
-    const int32_t* __restrict__ active, double* __restrict__ gpart, float* __restrict__ mpart) {
+    const int32_t* __restrict__ active, double* __restrict__ gpart, float* __restrict__ mpart,
+    int first) {
   constexpr int NT = 64 * kGW;
   __shared__ GalerkinLds<RT> L;
   const Tile t = tiles[blockIdx.x];
   const int b = t.inst;
-  if (!active[b]) return;
+  if (!first && !active[b]) return;   // the first iteration of a step runs every instance
   const int tid = threadIdx.x;
   for (int c = tid; c < RT; c += NT) L.sa[c] = a[(size_t)b * RT + c];
   galerkin_tile<RT>(t, phys, nphys, Phi, qref, dvar, L);
@@ -504,17 +505,17 @@ bool mfma_ok(const rom_batch* h) {
   return h->cfg.precision == ROM_F32 && (h->cfg.r == 32 || h->cfg.r == 64);
 }
 
-rom_status launch_galerkin_mfma(rom_batch* h, hipStream_t s) {
+rom_status launch_galerkin_mfma(rom_batch* h, hipStream_t s, int first) {
   if (h->cfg.r == 32)
     hipLaunchKernelGGL((k_galerkin_mfma<32>), dim3(h->n_ptiles), dim3(64 * kGW), 0, s, h->d_ptiles,
                        h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const float*)h->Phi,
                        (const float*)h->q_ref, h->d_var, h->a, h->active, h->part,
-                       (float*)h->mpart);
+                       (float*)h->mpart, first);
   else
     hipLaunchKernelGGL((k_galerkin_mfma<64>), dim3(h->n_ptiles), dim3(64 * kGW), 0, s, h->d_ptiles,
                        h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const float*)h->Phi,
                        (const float*)h->q_ref, h->d_var, h->a, h->active, h->part,
-                       (float*)h->mpart);
+                       (float*)h->mpart, first);
   ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
 }

@@ -130,13 +130,13 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_galerkin_solve(
     const int* __restrict__ tfirst, const double* __restrict__ gpart, const T* __restrict__ mpart,
     int r, double dt, const double* __restrict__ dvar, double* __restrict__ a,
-    const double* __restrict__ a_prev, int32_t* __restrict__ active, int32_t* __restrict__ iters,
-    double tol, uint32_t* flags) {
+    double* __restrict__ a_prev, int32_t* __restrict__ active, int32_t* __restrict__ iters,
+    double tol, uint32_t* flags, int first) {
   __shared__ double J[kMaxR * (kMaxR + 1)];
   __shared__ double g[kMaxR];
   __shared__ int ok;
   const int b = blockIdx.x, tid = threadIdx.x;
-  if (!active[b]) return;
+  if (!first && !active[b]) return;
   const int ld = r + 1;
   const double d = dvar[b];
   // tile partials summed in tile order; the loads of 8 tiles are issued together
@@ -165,7 +165,10 @@ __global__ __launch_bounds__(256) void k_galerkin_solve(
       for (int u = 0; u < 8; ++u)
         if (tt + u < t1) s += v[u];
     }
-    g[c] = -(a[(size_t)b * r + c] - a_prev[(size_t)b * r + c] - dt * d * s);
+    // the first iteration of a step starts from a_prev = a (and records it)
+    const double ac = a[(size_t)b * r + c];
+    if (first) a_prev[(size_t)b * r + c] = ac;
+    g[c] = -(ac - (first ? ac : a_prev[(size_t)b * r + c]) - dt * d * s);
   }
   __syncthreads();
   lu_solve_block(J, ld, g, r, &ok);
@@ -187,10 +190,10 @@ __global__ __launch_bounds__(256) void k_galerkin_solve(
       fin &= __shfl_xor(fin, off);
     }
     if (tid == 0) {
-      iters[b] += 1;
+      iters[b] = first ? 1 : iters[b] + 1;
       if (!ok) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
       if (!fin) atomicOr(&flags[b], ROM_FLAG_NONFINITE);
-      if (dm <= tol * (1.0 + am) || !fin) active[b] = 0;
+      active[b] = (dm <= tol * (1.0 + am) || !fin) ? 0 : 1;
     }
   }
 }
@@ -250,12 +253,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2)))
 void k_galerkin_solve_w(
     const int* __restrict__ tfirst, const double* __restrict__ gpart,
     const float* __restrict__ mpart, double dt, const double* __restrict__ dvar,
-    double* __restrict__ a, const double* __restrict__ a_prev, int32_t* __restrict__ active,
-    int32_t* __restrict__ iters, double tol, uint32_t* flags) {
+    double* __restrict__ a, double* __restrict__ a_prev, int32_t* __restrict__ active,
+    int32_t* __restrict__ iters, double tol, uint32_t* flags, int first) {
   static_assert(RT == 32, "two columns per lane pair, 32 rows");
   constexpr int NL = RT / 2;   // columns per lane
   const int b = blockIdx.x, lane = threadIdx.x;
-  if (!active[b]) return;
+  if (!first && !active[b]) return;
   const int i = lane & 31, h = lane >> 5;
   const int t0 = tfirst[b], t1 = tfirst[b + 1];
   double A[NL];
@@ -274,7 +277,9 @@ void k_galerkin_solve_w(
 #pragma unroll
   for (int jj = 0; jj < NL; ++jj) A[jj] = (2 * jj + h == i ? 1.0 : 0.0) - dt * A[jj];
   const double ai = a[(size_t)b * RT + i];
-  double bi = -(ai - a_prev[(size_t)b * RT + i] - dt * dvar[b] * gs);
+  // the first iteration of a step starts from a_prev = a (and records it)
+  if (first && h == 0) a_prev[(size_t)b * RT + i] = ai;
+  double bi = -(ai - (first ? ai : a_prev[(size_t)b * RT + i]) - dt * dvar[b] * gs);
   bool used = false;
   int ord = -1;
   int pivl = 0;       // lane k: the pivot row of column k
@@ -340,10 +345,10 @@ void k_galerkin_solve_w(
     fin &= __shfl_xor(fin, off);
   }
   if (lane == 0) {
-    iters[b] += 1;
+    iters[b] = first ? 1 : iters[b] + 1;
     if (!ok) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
     if (!fin) atomicOr(&flags[b], ROM_FLAG_NONFINITE);
-    if (dm <= tol * (1.0 + am) || !fin) active[b] = 0;
+    active[b] = (dm <= tol * (1.0 + am) || !fin) ? 0 : 1;
   }
 }
 
@@ -775,34 +780,36 @@ rom_status galerkin_step_t(rom_batch* h, hipStream_t s) {
   const int r = h->cfg.r, B = h->cfg.n_inst;
   const int64_t nr = (int64_t)B * r;
   const int64_t nset = std::max<int64_t>(nr, B);
-  hipLaunchKernelGGL(k_rom_step_setup, dim3((nset + 255) / 256), dim3(256), 0, s, B, r, h->a,
-                     h->a_prev, h->active, h->iters);
   double* gpart = h->part;
   if (mfma_ok(h)) {
+    // the first iteration's kernels do the step's set-up (a_prev, active, iters)
     const int ng = std::min(kGridNewton, h->cfg.rom_max);
     for (int it = 0; it < ng; ++it) {
-      rom_status st = launch_galerkin_mfma(h, s);
+      const int first = it == 0 ? 1 : 0;
+      rom_status st = launch_galerkin_mfma(h, s, first);
       if (st != ROM_OK) return st;
       if (r == 32)  // register-resident single-wave solve (r = 64 rows do not fit)
         hipLaunchKernelGGL(k_galerkin_solve_w<32>, dim3(B), dim3(64), 0, s, h->d_ptile_first,
                            gpart, (const float*)h->mpart, h->cfg.dt, h->d_var, h->a, h->a_prev,
-                           h->active, h->iters, h->cfg.rom_tol, h->flags);
+                           h->active, h->iters, h->cfg.rom_tol, h->flags, first);
       else
         hipLaunchKernelGGL((k_galerkin_solve<float>), dim3(B), dim3(256), 0, s,
                            h->d_ptile_first, gpart, (const float*)h->mpart, r, h->cfg.dt,
                            h->d_var, h->a, h->a_prev, h->active, h->iters, h->cfg.rom_tol,
-                           h->flags);
+                           h->flags, first);
     }
     // remaining iterations and the non-convergence flag
     return launch_galerkin_tail(h, ng, s);
   }
+  hipLaunchKernelGGL(k_rom_step_setup, dim3((nset + 255) / 256), dim3(256), 0, s, B, r, h->a,
+                     h->a_prev, h->active, h->iters);
   for (int it = 0; it < h->cfg.rom_max; ++it) {
     hipLaunchKernelGGL((k_galerkin_pass<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                        h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const T*)h->Phi,
                        r, (const T*)h->q_ref, h->d_var, h->a, h->active, gpart, (T*)h->mpart);
     hipLaunchKernelGGL((k_galerkin_solve<T>), dim3(B), dim3(256), 0, s, h->d_ptile_first, gpart,
                        (const T*)h->mpart, r, h->cfg.dt, h->d_var, h->a, h->a_prev, h->active,
-                       h->iters, h->cfg.rom_tol, h->flags);
+                       h->iters, h->cfg.rom_tol, h->flags, 0);
   }
   hipLaunchKernelGGL(k_rom_finalize, dim3((B + 255) / 256), dim3(256), 0, s, B, h->active, h->flags);
   ROM_HIP_CHECK(hipGetLastError());
