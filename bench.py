@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "adaptive-ROM steps/s + FOM cell-updates/s (% HBM roofline), batched vs plain"
 HBM_PEAK_GBS = 8000.0
+MFMA_F32_TFLOPS = 157.3
 
 # HBM traffic per launch from rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE
 # in KiB per dispatch, bench.py --only galerkin / --only residual), each scaled
@@ -61,6 +62,7 @@ def parse():
                    help="instances timed on the plain per-instance path")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--no-configs", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--only", choices=["all", "copy", "galerkin", "residual", "windows", "adjoint"],
                    default="all",
@@ -113,6 +115,70 @@ def cpu_baseline(w, budget_s):
                 sample="%d instance-steps of 4 instances (N=%s) in whole windows, %.1f s; "
                        "scaled by mean N of the batch" % (steps, [w.n_cells[b] for b in picks],
                                                          t_total))
+
+
+def _timed(torch, fn, reps):
+    """Mean ms per call of fn (enqueued on the current stream), after one warm-up."""
+    fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def config_measurements(torch, W, R):
+    """The other configurations' figures: C1 (the FP64 parity anchor, steps/s), C3
+    (one Sod/HLLC instance with HR-LSPG: windows and the cost split of an event) and
+    C5 (32 reacting instances with HR-LSPG: windows and R(q), which is
+    MALL-resident at 101 MB)."""
+    out = {}
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        # C1
+        w = W.burgers_512_f64()
+        h = R.RomBatch(w, q0=torch.as_tensor(w.q0, dtype=torch.float64, device="cuda"),
+                       use_graph=True)
+        nwin = 20
+        ms = _timed(torch, lambda: h.rom_step(w.z * nwin), 1) / nwin
+        out["C1_burgers_512_f64"] = dict(ms_per_window=round(ms, 4),
+                                         steps_per_s=w.z / (ms * 1e-3))
+        h.close()
+        # C3
+        w = W.sod_hllc_f32()
+        h = R.RomBatch(w, q0=torch.as_tensor(w.q0, dtype=torch.float32, device="cuda"),
+                       use_graph=True)
+        ms_win = _timed(torch, lambda: h.rom_step(w.z * 5), 1) / 5
+        y = h.get(R.GET_YCORR).clone()
+        y2 = torch.empty_like(y)
+        ms_coarse = _timed(torch, lambda: h.fom_step(y, w.z * w.dt, out=y2), 3)
+        ms_isvd = _timed(torch, lambda: h.isvd_update(y2), 3)
+        ms_rebuild = _timed(torch, lambda: h.rom_rebuild(), 3)
+        out["C3_sod_hllc_65536_f32"] = dict(
+            ms_per_window=round(ms_win, 4), steps_per_s=w.z / (ms_win * 1e-3),
+            event_split_ms=dict(coarse_step=round(ms_coarse, 4), isvd_update=round(ms_isvd, 4),
+                                deim_rebuild=round(ms_rebuild, 4)))
+        h.close()
+        # C5
+        w = W.react10_f32()
+        q = torch.as_tensor(w.q0, dtype=torch.float32, device="cuda")
+        h = R.RomBatch(w, q0=q, use_graph=True)
+        ms_win = _timed(torch, lambda: h.rom_step(w.z * 3), 1) / 3
+        ms_res = h.profile(R.PROF_RESIDUAL, 20, q)
+        cells = sum(w.n_cells)
+        cu = cells / (ms_res * 1e-3)
+        out["C5_react10_32x32768_f32"] = dict(
+            ms_per_window=round(ms_win, 4),
+            instance_steps_per_s=w.n_inst * w.z / (ms_win * 1e-3),
+            residual_cell_updates_per_s=cu,
+            residual_frac_of_peak=round(cu / (HBM_PEAK_GBS * 1e9 / 96.0), 4),
+            residual_note="96 B per cell; 101 MB per evaluation is MALL-resident")
+        h.close()
+    return out
 
 
 def adjoint_ms(torch, h, w, n_win):
@@ -236,6 +302,12 @@ def main():
                         peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
                         traffic=traffic_bytes("k_galerkin_pass"), ms_per_launch=round(ms_pass, 5),
                         bytes_per_launch=int(bytes_pass))
+        # the same pass against the FP32 MFMA peak: 2 N r^2 flops per launch
+        flops_pass = 2.0 * tot * r * r
+        roofline_mfma = dict(kernel="k_galerkin_pass", bound="mfma",
+                             achieved=round(flops_pass / (ms_pass * 1e-3) / 1e12, 2),
+                             peak=MFMA_F32_TFLOPS, unit="TFLOP/s",
+                             frac=round(flops_pass / (ms_pass * 1e-3) / 1e12 / MFMA_F32_TFLOPS, 4))
         ms_proj = h.profile(R.PROF_ISVD_PROJECT, reps, h.get(R.GET_YCORR))
         # the online adjoint (extension): gradient through whole windows
         adj_ms = adjoint_ms(torch, h, w, 2)
@@ -296,6 +368,11 @@ def main():
         log("R(q): %.4f ms, %.3g cell-updates/s, %.1f%% of HBM" % (ms_res, fom["cell_updates_per_s"],
                                                                 100 * fom["frac_hbm"]))
 
+    configs = None
+    if not args.no_configs:
+        configs = config_measurements(torch, W, R)
+        log("other configurations: %s" % json.dumps(configs))
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w, args.cpu_seconds)
@@ -323,6 +400,8 @@ def main():
         "plain": plain,
         "fom_residual": fom,
         "isvd_project_ms": round(ms_proj, 5),
+        "roofline_mfma": roofline_mfma,
+        "other_configs": configs,
         "online_adjoint": {"ms_per_window": round(adj_ms, 3), "windows": 2,
                            "what": "rom_online_vjp: forward, sqrt(T) checkpointed recompute, "
                                    "reverse (transposed reduced solves, iSVD backward, "
