@@ -538,48 +538,53 @@ __global__ __launch_bounds__(256) void k_deim_argmax(const Tile* __restrict__ ti
 // ld = kMaxR + 1): overwrites x[0..nc) with argmin ||A x - rhs||.  Single
 // thread per column reflector application loop; sizes here are tiny.
 DEV void qr_lstsq(double* A, int m, int nc, double* rhs, double* x) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   constexpr int ld = kMaxR + 1;
-  __shared__ double beta, nrm2;
+  __shared__ double beta, alpha_s;
   for (int k = 0; k < nc; ++k) {
-    if (tid == 0) {
+    if (wave == 0) {   // |A[k:, k]| by the first wavefront
       double s = 0.0;
-      for (int i = k; i < m; ++i) s += A[i * ld + k] * A[i * ld + k];
-      nrm2 = sqrt(s);
-    }
-    __syncthreads();
-    const double alpha = A[k * ld + k] >= 0.0 ? -nrm2 : nrm2;
-    __syncthreads();
-    if (tid == 0) {
-      // v = x - alpha e1 stored in column k (rows k..m-1)
-      A[k * ld + k] -= alpha;
-      double vv = 0.0;
-      for (int i = k; i < m; ++i) vv += A[i * ld + k] * A[i * ld + k];
-      beta = vv > 0.0 ? 2.0 / vv : 0.0;
-    }
-    __syncthreads();
-    // apply H = I - beta v v^T to columns k+1..nc-1 and the rhs
-    for (int c = k + 1 + tid; c <= nc; c += blockDim.x) {
-      double s = 0.0;
-      if (c < nc) {
-        for (int i = k; i < m; ++i) s += A[i * ld + k] * A[i * ld + c];
-        s *= beta;
-        for (int i = k; i < m; ++i) A[i * ld + c] -= s * A[i * ld + k];
-      } else {
-        for (int i = k; i < m; ++i) s += A[i * ld + k] * rhs[i];
-        s *= beta;
-        for (int i = k; i < m; ++i) rhs[i] -= s * A[i * ld + k];
+      for (int i = k + lane; i < m; i += 64) s += A[i * ld + k] * A[i * ld + k];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+      const double nrm = sqrt(s);
+      const double akk = A[k * ld + k];
+      const double alpha = akk >= 0.0 ? -nrm : nrm;
+      // v = x - alpha e1 in column k (rows k..m-1); v^T v = s - akk^2 + (akk - alpha)^2
+      const double vk = akk - alpha;
+      const double vv = (s - akk * akk) + vk * vk;
+      if (lane == 0) {
+        A[k * ld + k] = vk;
+        alpha_s = alpha;
+        beta = vv > 0.0 ? 2.0 / vv : 0.0;
       }
     }
     __syncthreads();
-    if (tid == 0) A[k * ld + k] = alpha;  // R diagonal
+    // apply H = I - beta v v^T to columns k+1..nc-1 and the rhs, one wavefront per column
+    for (int c = k + 1 + wave; c <= nc; c += nw) {
+      double* col = c < nc ? A + c : rhs;
+      const int cs = c < nc ? ld : 1;
+      double sdot = 0.0;
+      for (int i = k + lane; i < m; i += 64) sdot += A[i * ld + k] * col[i * cs];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) sdot += __shfl_xor(sdot, off);
+      sdot *= beta;
+      for (int i = k + lane; i < m; i += 64) col[i * cs] -= sdot * A[i * ld + k];
+    }
+    __syncthreads();
+    if (tid == 0) A[k * ld + k] = alpha_s;  // R diagonal
     __syncthreads();
   }
-  if (tid == 0) {
+  // back substitution R x = rhs[0..nc), column-oriented by the first wavefront
+  if (wave == 0) {
     for (int i = nc - 1; i >= 0; --i) {
-      double s = rhs[i];
-      for (int c = i + 1; c < nc; ++c) s -= A[i * ld + c] * x[c];
-      x[i] = A[i * ld + i] != 0.0 ? s / A[i * ld + i] : 0.0;
+      const double d = A[i * ld + i];
+      const double xi = d != 0.0 ? rhs[i] / d : 0.0;
+      if (lane == 0) x[i] = xi;
+      for (int j = lane; j < i; j += 64) rhs[j] -= A[j * ld + i] * xi;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
   __syncthreads();
@@ -601,20 +606,39 @@ __global__ __launch_bounds__(256) void k_deim_select(const int* __restrict__ tfi
   __shared__ double A[kMaxNs * (kMaxR + 1)];
   __shared__ double rhs[kMaxNs];
   __shared__ double x[kMaxR];
+  __shared__ double bv[256];
+  __shared__ int64_t bix[256];
   const int b = blockIdx.x, tid = threadIdx.x;
-  if (tid == 0) {
+  {  // argmax over the instance's tile winners (largest value, lowest row on ties)
     double best = -1.0;
     int64_t bi = -1;
-    for (int tt = tfirst[b]; tt < tfirst[b + 1]; ++tt) {
+    for (int tt = tfirst[b] + tid; tt < tfirst[b + 1]; tt += blockDim.x) {
       const double v = tval[tt];
       const int64_t i = tidx[tt];
-      if (i >= 0 && (v > best || (v == best && i < bi))) { best = v; bi = i; }
+      if (i >= 0 && (bi < 0 || v > best || (v == best && i < bi))) { best = v; bi = i; }
     }
-    if (bi < 0) { bi = 0; atomicOr(&flags[b], ROM_FLAG_SINGULAR); }
-    P[(size_t)b * ns + t] = (int32_t)bi;
-    chosen[dof_off[b] + bi] = *epoch_p;
+    bv[tid] = best;
+    bix[tid] = bi;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st) {
+        const double v2 = bv[tid + st];
+        const int64_t i2 = bix[tid + st];
+        if (i2 >= 0 && (bix[tid] < 0 || v2 > bv[tid] || (v2 == bv[tid] && i2 < bix[tid]))) {
+          bv[tid] = v2;
+          bix[tid] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      int64_t w = bix[0];
+      if (w < 0) { w = 0; atomicOr(&flags[b], ROM_FLAG_SINGULAR); }
+      P[(size_t)b * ns + t] = (int32_t)w;
+      chosen[dof_off[b] + w] = *epoch_p;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int tn = t + 1;           // next pick
   if (tn >= ns) return;
   const int jn = tn < r ? tn : tn - r;   // column of the next pick
