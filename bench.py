@@ -40,7 +40,7 @@ MFMA_F32_TFLOPS = 157.3
 # summaries of those runs are kept in the profiles directory.
 COPY_SCALE = {"fetch": 524288.0 / 262157.4, "write": 1.0}
 MEASURED_KIB = {
-    "k_galerkin_pass": {"fetch": 134540.1, "write": 4245.8},
+    "k_galerkin_pass": {"fetch": 134607.7, "write": 4245.8},
     # streaming Euler residual, shape 8 (512-cell tiles, 7 blocks/CU, non-temporal)
     "k_residual_euler/8": {"fetch": 105506.6, "write": 196608.0},
 }
@@ -133,9 +133,10 @@ def _timed(torch, fn, reps):
 
 def config_measurements(torch, W, R):
     """The other configurations' figures: C1 (the FP64 parity anchor, steps/s), C3
-    (one Sod/HLLC instance with HR-LSPG: windows and the cost split of an event) and
+    (one Sod/HLLC instance with HR-LSPG: windows and the cost split of an event),
     C5 (32 reacting instances with HR-LSPG: windows and R(q), which is
-    MALL-resident at 101 MB)."""
+    MALL-resident at 101 MB) and C4 (64 Euler instances: the full-order step and
+    the checkpointed rollout adjoint)."""
     out = {}
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
@@ -177,6 +178,26 @@ def config_measurements(torch, W, R):
             residual_cell_updates_per_s=cu,
             residual_frac_of_peak=round(cu / (HBM_PEAK_GBS * 1e9 / 96.0), 4),
             residual_note="96 B per cell; 101 MB per evaluation is MALL-resident")
+        h.close()
+        # C4: 64 Euler (Rusanov) instances of 262,144 cells, the full-order rollout
+        # and its checkpointed adjoint
+        w = W.euler_adjoint_f32(n_inst=64, n=262144)
+        h = R.RomBatch(w, q0=None, use_graph=False)
+        q0 = torch.as_tensor(w.q0, dtype=torch.float32, device="cuda")
+        gbar = q0 - torch.as_tensor(w.extra["target"], dtype=torch.float32, device="cuda")
+        q = q0.clone()
+        gq = torch.empty_like(q0)
+        ms_step = _timed(torch, lambda: h.fom_step(q, w.dt, out=q), 5)
+        n_steps, n_ckpt = 16, 4
+        ms_vjp = _timed(torch, lambda: h.rollout_vjp(q0, n_steps, w.dt, gbar, n_ckpt=n_ckpt,
+                                                     out=gq), 2)
+        cells = sum(w.n_cells)
+        out["C4_euler_rusanov_64x262144_f32"] = dict(
+            fom_step_ms=round(ms_step, 4), fom_step_cell_updates_per_s=cells / (ms_step * 1e-3),
+            rollout_vjp_ms_per_step=round(ms_vjp / n_steps, 4),
+            rollout_vjp_steps=n_steps, rollout_vjp_checkpoints=n_ckpt,
+            note="backward-Euler Newton steps at dt = 0.064/N; the adjoint call runs the "
+                 "forward pass, the checkpointed recomputation and the transposed solves")
         h.close()
     return out
 
