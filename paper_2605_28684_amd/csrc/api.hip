@@ -151,7 +151,7 @@ void free_all(rom_batch* h) {
                 h->Phi, h->sigma, h->a, h->a_prev, h->q_ref, h->d_var, h->y_corr, h->flags, h->P,
                 h->M, h->mesh_phi, h->mesh_qref, h->chosen, h->part, h->red, h->ubar, h->lmat,
                 h->active, h->iters, h->norms, h->rstate, h->qtmp, h->mpart, h->fq, h->fq_prev, h->vjp_tmp,
-                h->d_epoch, h->rvjp, h->epart, h->ev_iters};
+                h->d_epoch, h->rvjp, h->epart, h->ev_iters, h->phi_cm};
   for (void* p : ps) (void)hipFree(p);
   bt_free(h);
   if (h->win_exec) (void)hipGraphExecDestroy(h->win_exec);
@@ -248,6 +248,7 @@ rom_status setup(rom_batch* h) {
   ROM_TRY(alloc(&h->mesh_phi, (size_t)B * ns * 3 * h->nv * r));
   ROM_TRY(alloc(&h->mesh_qref, (size_t)B * ns * 3 * h->nv));
   ROM_TRY(alloc(&h->chosen, (size_t)td));
+  if (c.hyper == ROM_HR_DEIM) ROM_TRY(alloc((char**)&h->phi_cm, es * td * r));
   ROM_TRY(alloc(&h->part, (size_t)std::max(h->n_ptiles, 1) * kMaxR * kMaxR));
   ROM_TRY(alloc(&h->red, (size_t)B * (2 * 128 + 8)));
   ROM_TRY(alloc(&h->ubar, (size_t)B * (r + 1) * (r + 1)));

@@ -116,6 +116,7 @@ struct rom_batch {
   double* mesh_phi = nullptr;  // [n_inst * n_s * 3 * nv * r]
   double* mesh_qref = nullptr; // [n_inst * n_s * 3 * nv]
   uint32_t* chosen = nullptr;  // [total_dof] epoch marks for DEIM
+  void* phi_cm = nullptr;      // T[total_dof * r]: Phi by columns per instance (DEIM only)
   uint32_t deim_epoch = 0;
 
   // iSVD workspace

@@ -487,36 +487,91 @@ __global__ __launch_bounds__(256) void k_hr_step(
 }
 
 // ------------------------------------------------------------------ DEIM
-// residual of column j after fitting columns 0..j-1 with coef; per-tile argmax
-// of |res| over rows not yet chosen (lowest row on ties).
+// The greedy picks read the leading columns of every row of the basis, one
+// column more per pick.  They read a column-major copy (per instance, column c
+// of instance b at phi_cm + dof_off[b] r + c n_b with n_b its row count), so
+// that a wavefront's loads of one column are contiguous and each pass moves
+// only the columns it uses.
+constexpr int kCmRows = 64;   // rows per step of the transposition
+
+// phi_cm <- Phi by columns, one pass tile per block: 64-row slabs are read
+// row-major into LDS and written out a column at a time.
 template <typename T>
+__global__ __launch_bounds__(256) void k_cols_transpose(const Tile* __restrict__ tiles,
+                                                        const int64_t* __restrict__ dof_off,
+                                                        const T* __restrict__ Phi, int r,
+                                                        T* __restrict__ phi_cm) {
+  __shared__ T sl[kCmRows][kMaxR + 1];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst, tid = threadIdx.x;
+  const int64_t base = dof_off[b], nb = dof_off[b + 1] - base;
+  const T* src = Phi + base * r;
+  T* dst = phi_cm + base * r;
+  for (int64_t r0 = t.cell0; r0 < t.cell0 + t.ncell; r0 += kCmRows) {
+    const int nr = (int)(t.cell0 + t.ncell - r0 < kCmRows ? t.cell0 + t.ncell - r0 : kCmRows);
+    __syncthreads();
+    for (int e = tid; e < nr * r; e += blockDim.x) sl[e / r][e % r] = src[r0 * r + e];
+    __syncthreads();
+    for (int e = tid; e < nr * r; e += blockDim.x) {
+      const int c = e / nr, i = e % nr;
+      dst[(int64_t)c * nb + r0 + i] = sl[i][c];
+    }
+  }
+}
+
+// Residual of column j after fitting columns 0..j-1 with coef, and the argmax
+// of |res| over the rows not yet chosen (lowest row on ties) in one of the S
+// equal parts of a pass tile; block tt * S + s writes the candidate of part s
+// of tile tt (value -1 and row -1 when the part has no free row).  The sum
+// runs over the columns in increasing order in FP64.
+template <typename T, int RPT>
 __global__ __launch_bounds__(256) void k_deim_argmax(const Tile* __restrict__ tiles,
                                                      const int64_t* __restrict__ dof_off,
-                                                     const T* __restrict__ Phi, int r, int j,
+                                                     const T* __restrict__ phi_cm, int r, int j,
                                                      const double* __restrict__ coef, int ldc,
                                                      const uint32_t* __restrict__ chosen,
                                                      const uint32_t* __restrict__ epoch_p,
-                                                     double* __restrict__ tval,
+                                                     int S, double* __restrict__ tval,
                                                      int64_t* __restrict__ tidx) {
   __shared__ double sc[kMaxR];
   __shared__ double bv[256];
   __shared__ int64_t bi[256];
-  const Tile t = tiles[blockIdx.x];
+  const Tile t = tiles[blockIdx.x / S];
+  const int part = blockIdx.x % S;
   const int b = t.inst, tid = threadIdx.x;
-  const int64_t base = dof_off[b];
+  const int64_t base = dof_off[b], nb = dof_off[b + 1] - base;
+  const int64_t len = (t.ncell + S - 1) / S;
+  const int64_t lo = t.cell0 + part * len;
+  const int64_t hi = t.cell0 + ((part + 1) * len < t.ncell ? (part + 1) * len : t.ncell);
   const uint32_t epoch = *epoch_p;
+  const T* cols = phi_cm + base * r;
   for (int c = tid; c < j; c += blockDim.x) sc[c] = coef[(size_t)b * ldc + c];
   __syncthreads();
   double best = -1.0;
   int64_t bidx = -1;
-  for (int64_t rr = tid; rr < t.ncell; rr += blockDim.x) {
-    const int64_t lr = t.cell0 + rr, g = base + lr;
-    if (chosen[g] == epoch) continue;
-    const T* row = Phi + g * r;
-    double res = (double)row[j];
-    for (int c = 0; c < j; ++c) res -= (double)row[c] * sc[c];
-    const double v = fabs(res);
-    if (v > best || (v == best && lr < bidx)) { best = v; bidx = lr; }
+  for (int64_t r0 = lo; r0 < hi; r0 += 256 * RPT) {
+    int64_t lr[RPT];
+    bool ok[RPT];
+    double res[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      lr[u] = r0 + tid + 256 * u;
+      ok[u] = lr[u] < hi;
+      res[u] = ok[u] ? (double)cols[(int64_t)j * nb + lr[u]] : 0.0;
+    }
+    for (int c = 0; c < j; ++c) {
+      const double w = sc[c];
+      const T* col = cols + (int64_t)c * nb;
+#pragma unroll
+      for (int u = 0; u < RPT; ++u)
+        if (ok[u]) res[u] -= (double)col[lr[u]] * w;
+    }
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      if (!ok[u] || chosen[base + lr[u]] == epoch) continue;
+      const double v = fabs(res[u]);
+      if (v > best || (v == best && lr[u] < bidx)) { best = v; bidx = lr[u]; }
+    }
   }
   bv[tid] = best;
   bi[tid] = bidx;
@@ -593,7 +648,7 @@ DEV void qr_lstsq(double* A, int m, int nc, double* rhs, double* x) {
 // select pick t (reduce tile candidates), record it, and fit the coefficients
 // of pick t+1 on the t+1 rows chosen so far.
 template <typename T>
-__global__ __launch_bounds__(256) void k_deim_select(const int* __restrict__ tfirst,
+__global__ __launch_bounds__(256) void k_deim_select(const int* __restrict__ tfirst, int S,
                                                      const double* __restrict__ tval,
                                                      const int64_t* __restrict__ tidx,
                                                      const int64_t* __restrict__ dof_off,
@@ -612,7 +667,7 @@ __global__ __launch_bounds__(256) void k_deim_select(const int* __restrict__ tfi
   {  // argmax over the instance's tile winners (largest value, lowest row on ties)
     double best = -1.0;
     int64_t bi = -1;
-    for (int tt = tfirst[b] + tid; tt < tfirst[b + 1]; tt += blockDim.x) {
+    for (int tt = tfirst[b] * S + tid; tt < tfirst[b + 1] * S; tt += blockDim.x) {
       const double v = tval[tt];
       const int64_t i = tidx[tt];
       if (i >= 0 && (bi < 0 || v > best || (v == best && i < bi))) { best = v; bi = i; }
@@ -870,15 +925,20 @@ rom_status rebuild_t(rom_batch* h, hipStream_t s) {
   const int r = h->cfg.r, ns = h->cfg.n_s, B = h->cfg.n_inst;
   if (h->cfg.hyper != ROM_HR_DEIM) return ROM_OK;
   hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, s, h->d_epoch);
+  hipLaunchKernelGGL((k_cols_transpose<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                     h->d_dof_off, (const T*)h->Phi, r, (T*)h->phi_cm);
+  // four candidates per pass tile (512 rows per block, 2 per thread)
+  constexpr int S = 4;
+  static_assert(S * 2 <= kMaxR * kMaxR, "tile candidates must fit the partials buffer");
   double* tval = h->part;
-  int64_t* tidx = (int64_t*)(h->part + h->n_ptiles);
+  int64_t* tidx = (int64_t*)(h->part + (size_t)S * h->n_ptiles);
   double* coef = h->rstate;  // per instance kMaxR coefficients
   for (int t = 0; t < ns; ++t) {
     const int j = t < r ? t : t - r;
-    hipLaunchKernelGGL((k_deim_argmax<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
-                       h->d_dof_off, (const T*)h->Phi, r, j, coef, kMaxR, h->chosen, h->d_epoch, tval,
-                       tidx);
-    hipLaunchKernelGGL((k_deim_select<T>), dim3(B), dim3(256), 0, s, h->d_ptile_first, tval, tidx,
+    hipLaunchKernelGGL((k_deim_argmax<T, 2>), dim3(h->n_ptiles * S), dim3(256), 0, s, h->d_ptiles,
+                       h->d_dof_off, (const T*)h->phi_cm, r, j, coef, kMaxR, h->chosen, h->d_epoch,
+                       S, tval, tidx);
+    hipLaunchKernelGGL((k_deim_select<T>), dim3(B), dim3(256), 0, s, h->d_ptile_first, S, tval, tidx,
                        h->d_dof_off, (const T*)h->Phi, r, ns, t, h->P, h->chosen, h->d_epoch, coef,
                        kMaxR, h->flags);
   }
