@@ -261,21 +261,58 @@ void k_galerkin_solve_w(
   if (!first && !active[b]) return;
   const int i = lane & 31, h = lane >> 5;
   const int t0 = tfirst[b], t1 = tfirst[b + 1];
+  // Sum the tile partials of Phi^T J_f Phi and Phi^T f.  Each tile's r x r
+  // block is read as 4 KB contiguous (4 float4 per lane) with up to kTG
+  // tiles in flight at once; every element is summed over the tiles in order
+  // in FP64, then the sums go through LDS (rows padded to 33 doubles) into
+  // the row layout of the solve.
+  constexpr int kTG = 4;
+  __shared__ double sM[RT * (RT + 1)];
+  double acc[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+  double gs = 0.0;
+  for (int tt = t0; tt < t1; tt += kTG) {
+    float4 v[kTG][4];
+    double gv[kTG];
+#pragma unroll
+    for (int g = 0; g < kTG; ++g) {
+      if (tt + g < t1) {
+        const float4* src = reinterpret_cast<const float4*>(mpart + (size_t)(tt + g) * kMaxR * kMaxR);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[g][u] = src[lane + 64 * u];
+        gv[g] = gpart[(size_t)(tt + g) * kMaxR + i];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < kTG; ++g) {
+      if (tt + g < t1) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          acc[4 * u + 0] += (double)v[g][u].x;
+          acc[4 * u + 1] += (double)v[g][u].y;
+          acc[4 * u + 2] += (double)v[g][u].z;
+          acc[4 * u + 3] += (double)v[g][u].w;
+        }
+        gs += gv[g];
+      }
+    }
+  }
+  // element e = 4 (lane + 64 u) + c of the row-major block: row e / 32, column e % 32
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int e = 4 * (lane + 64 * u) + c;
+      sM[(e / RT) * (RT + 1) + e % RT] = acc[4 * u + c];
+    }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   double A[NL];
 #pragma unroll
-  for (int jj = 0; jj < NL; ++jj) A[jj] = 0.0;
-  double gs = 0.0;
-  for (int tt = t0; tt < t1; ++tt) {
-    const float2* mr = reinterpret_cast<const float2*>(mpart + (size_t)tt * kMaxR * kMaxR + i * RT);
-#pragma unroll
-    for (int jj = 0; jj < NL; ++jj) {
-      const float2 v = mr[jj];
-      A[jj] += (double)(h ? v.y : v.x);
-    }
-    gs += gpart[(size_t)tt * kMaxR + i];
-  }
-#pragma unroll
-  for (int jj = 0; jj < NL; ++jj) A[jj] = (2 * jj + h == i ? 1.0 : 0.0) - dt * A[jj];
+  for (int jj = 0; jj < NL; ++jj)
+    A[jj] = (2 * jj + h == i ? 1.0 : 0.0) - dt * sM[i * (RT + 1) + 2 * jj + h];
   const double ai = a[(size_t)b * RT + i];
   // the first iteration of a step starts from a_prev = a (and records it)
   if (first && h == 0) a_prev[(size_t)b * RT + i] = ai;
