@@ -153,11 +153,12 @@ constexpr int kEChunk = 8192;   // elements of a staged chunk (rows x r), at mos
 constexpr int kELds = 19200;    // doubles of dynamic LDS, at most (150 KB)
 
 // Rows of a staged chunk: as many as the LDS left after the three n x n core
-// matrices holds (two rows x r arrays and four per-row scalars), at most 1024
-// rows and kEChunk elements.
+// matrices holds (two rows x (r + 1) arrays, rows padded by one double so that
+// lanes walking rows hit distinct banks, and four per-row scalars), at most
+// 1024 rows and kEChunk elements.
 DEV_HOST_INLINE int event_chunk_rows(int r) {
   const int n = r + 1;
-  int c = (kELds - 3 * n * n - n) / (2 * r + 4);
+  int c = (kELds - 3 * n * n - n) / (2 * (r + 1) + 4);
   if (c > kEChunk / r) c = kEChunk / r;
   return c > 1024 ? 1024 : c;
 }
@@ -180,15 +181,19 @@ DEV void chunk_fetch(const T* __restrict__ Phi, const double* __restrict__ pb, i
   }
 }
 
-DEV void chunk_put(double* cP, double* cB, int ne, bool with_b, const double (&rp)[kEPF],
+// Element e = k r + c of the chunk goes to row k, column c of the padded LDS
+// copy (row stride r + 1).
+DEV void chunk_put(double* cP, double* cB, int ne, int r, bool with_b, const double (&rp)[kEPF],
                    const double (&rb)[kEPF]) {
   const int tid = threadIdx.x;
 #pragma unroll
   for (int u = 0; u < kEPF; ++u) {
     const int e = tid + u * kET;
     if (e < ne) {
-      cP[e] = rp[u];
-      if (with_b) cB[e] = rb[u];
+      const int k = e / r;
+      const int o = e + k;   // k (r + 1) + (e - k r)
+      cP[o] = rp[u];
+      if (with_b) cB[o] = rb[u];
     }
   }
 }
@@ -199,7 +204,8 @@ DEV void chunk_put(double* cP, double* cB, int ne, bool with_b, const double (&r
 // transfer), Ubar (n x n), pr = (p1, p2, 1/rho, s_n).  abar, sigbar and the
 // rows of phibar are replaced by the adjoints of the pre-event state; ybar
 // receives D yhatbar.  Rows are streamed in chunks staged in LDS (Phi as FP64
-// and the matching rows of phibar); dynamic LDS: 3 n^2 + 2 C r + 4 C + n
+// and the matching rows of phibar, rows padded to r + 1); dynamic LDS:
+// 3 n^2 + 2 C (r + 1) + 4 C + n
 // doubles for C = event_chunk_rows(r).
 template <typename T>
 __global__ __launch_bounds__(kET) void k_event_vjp(
@@ -219,9 +225,10 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
   double* U = sm;               // Ubar
   double* Ub = U + n * n;       // its adjoint, then G
   double* X = Ub + n * n;       // U^T Ub, then V
+  const int LDR = r + 1;         // padded row stride of the staged chunk
   double* cP = X + n * n;       // chunk of Phi rows (FP64)
-  double* cB = cP + CH * r;     // the same rows of phibar
-  double* c0 = cB + CH * r;     // per-row scalars of the chunk
+  double* cB = cP + CH * LDR;   // the same rows of phibar
+  double* c0 = cB + CH * LDR;   // per-row scalars of the chunk
   double* c1 = c0 + CH;
   double* c2 = c1 + CH;
   double* c3 = c2 + CH;
@@ -273,12 +280,12 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
   if (nd > 0) chunk_fetch(Phi, phibar, base * r, chunk_ne(0), true, rp, rb);
   for (int64_t r0 = 0; r0 < nd; r0 += CH) {
     const int nr = (int)(nd - r0 < CH ? nd - r0 : CH);
-    chunk_put(cP, cB, nr * r, true, rp, rb);
+    chunk_put(cP, cB, nr * r, r, true, rp, rb);
     __syncthreads();
     if (r0 + CH < nd) chunk_fetch(Phi, phibar, (base + r0 + CH) * r, chunk_ne(r0 + CH), true, rp, rb);
     for (int k = tid; k < nr; k += kET) {
       double q = d * ((double)ynew[base + r0 + k] - (double)qref[base + r0 + k]);
-      for (int c = 0; c < r; ++c) q -= cP[k * r + c] * (p1[c] + p2[c]);
+      for (int c = 0; c < r; ++c) q -= cP[k * LDR + c] * (p1[c] + p2[c]);
       c0[k] = q;
       qs[base + r0 + k] = q;
     }
@@ -287,15 +294,15 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
       const int i = e / r, j = e % r;
       double s = 0.0;
       if (i < r)
-        for (int k = 0; k < nr; ++k) s += cP[k * r + i] * cB[k * r + j];
+        for (int k = 0; k < nr; ++k) s += cP[k * LDR + i] * cB[k * LDR + j];
       else
-        for (int k = 0; k < nr; ++k) s += c0[k] * irho * cB[k * r + j];
+        for (int k = 0; k < nr; ++k) s += c0[k] * irho * cB[k * LDR + j];
       Ub[i * n + j] += s;
     }
     for (int e = tid; e < nr * n; e += kET) {
       const int k = e / n, c = e % n;
       double s = 0.0;
-      for (int m = 0; m < r; ++m) s += cB[k * r + m] * U[c * n + m];
+      for (int m = 0; m < r; ++m) s += cB[k * LDR + m] * U[c * n + m];
       if (c < r) phibar[(base + r0 + k) * r + c] = s;
       else {
         js[base + r0 + k] = s;
@@ -368,13 +375,13 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
   if (nd > 0) chunk_fetch(Phi, phibar, base * r, chunk_ne(0), false, rp, rb);
   for (int64_t r0 = 0; r0 < nd; r0 += CH) {
     const int nr = (int)(nd - r0 < CH ? nd - r0 : CH);
-    chunk_put(cP, cB, nr * r, false, rp, rb);
+    chunk_put(cP, cB, nr * r, r, false, rp, rb);
     if (r0 + CH < nd) chunk_fetch(Phi, phibar, (base + r0 + CH) * r, chunk_ne(r0 + CH), false, rp, rb);
     for (int k = tid; k < nr; k += kET)
       c0[k] = (js[base + r0 + k] + rhob * qs[base + r0 + k]) * irho;
     __syncthreads();
     if (tid < r)
-      for (int k = 0; k < nr; ++k) acc += cP[k * r + tid] * c0[k];
+      for (int k = 0; k < nr; ++k) acc += cP[k * LDR + tid] * c0[k];
     __syncthreads();
   }
   if (tid < r) p2b[tid] = pb[tid] - acc;
@@ -385,7 +392,7 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
   if (nd > 0) chunk_fetch(Phi, phibar, base * r, chunk_ne(0), true, rp, rb);
   for (int64_t r0 = 0; r0 < nd; r0 += CH) {
     const int nr = (int)(nd - r0 < CH ? nd - r0 : CH);
-    chunk_put(cP, cB, nr * r, true, rp, rb);
+    chunk_put(cP, cB, nr * r, r, true, rp, rb);
     __syncthreads();
     if (r0 + CH < nd) chunk_fetch(Phi, phibar, (base + r0 + CH) * r, chunk_ne(r0 + CH), true, rp, rb);
     for (int k = tid; k < nr; k += kET) {
@@ -393,8 +400,8 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
       double q1 = d * ((double)ynew[g] - (double)qref[g]);
       double t = 0.0;
       for (int c = 0; c < r; ++c) {
-        q1 -= cP[k * r + c] * p1[c];
-        t += cP[k * r + c] * p2b[c];
+        q1 -= cP[k * LDR + c] * p1[c];
+        t += cP[k * LDR + c] * p2b[c];
       }
       const double qb = (js[g] + rhob * qs[g]) * irho;
       c0[k] = qb;
@@ -405,10 +412,10 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
     __syncthreads();
     for (int e = tid; e < nr * r; e += kET) {
       const int k = e / r, c = e % r;
-      phibar[(base + r0) * r + e] = cB[e] - c0[k] * p2[c] + c1[k] * p2b[c];
+      phibar[(base + r0) * r + e] = cB[k * LDR + c] - c0[k] * p2[c] + c1[k] * p2b[c];
     }
     if (tid < r)
-      for (int k = 0; k < nr; ++k) acc += cP[k * r + tid] * c2[k];
+      for (int k = 0; k < nr; ++k) acc += cP[k * LDR + tid] * c2[k];
     __syncthreads();
   }
   if (tid < r) p1b[tid] = pb[tid] - acc;
@@ -418,7 +425,7 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
   if (nd > 0) chunk_fetch(Phi, phibar, base * r, chunk_ne(0), true, rp, rb);
   for (int64_t r0 = 0; r0 < nd; r0 += CH) {
     const int nr = (int)(nd - r0 < CH ? nd - r0 : CH);
-    chunk_put(cP, cB, nr * r, true, rp, rb);
+    chunk_put(cP, cB, nr * r, r, true, rp, rb);
     __syncthreads();
     if (r0 + CH < nd) chunk_fetch(Phi, phibar, (base + r0 + CH) * r, chunk_ne(r0 + CH), true, rp, rb);
     for (int k = tid; k < nr; k += kET) {
@@ -426,7 +433,7 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
       const double yh = d * ((double)ynew[g] - (double)qref[g]);
       const double q1b = js[g];
       double t = 0.0;
-      for (int c = 0; c < r; ++c) t += cP[k * r + c] * p1b[c];
+      for (int c = 0; c < r; ++c) t += cP[k * LDR + c] * p1b[c];
       c0[k] = q1b;
       c1[k] = yh;
       ybar[g] += d * (q1b + t);
@@ -434,7 +441,7 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
     __syncthreads();
     for (int e = tid; e < nr * r; e += kET) {
       const int k = e / r, c = e % r;
-      phibar[(base + r0) * r + e] = cB[e] - c0[k] * p1[c] + c1[k] * p1b[c];
+      phibar[(base + r0) * r + e] = cB[k * LDR + c] - c0[k] * p1[c] + c1[k] * p1b[c];
     }
     __syncthreads();
   }
@@ -483,7 +490,7 @@ rom_status launch_step_vjp(rom_batch* h, const void* Phi, const double* a1, doub
 
 size_t event_vjp_shm(int r) {
   const size_t n = (size_t)r + 1, C = (size_t)event_chunk_rows(r);
-  return sizeof(double) * (3 * n * n + 2 * C * r + 4 * C + n);
+  return sizeof(double) * (3 * n * n + 2 * C * (r + 1) + 4 * C + n);
 }
 
 rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new,

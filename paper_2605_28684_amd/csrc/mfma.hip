@@ -39,7 +39,7 @@ constexpr int kCh = 32;  // rows per wave chunk
 DEV int64_t wrap_cell(int64_t c, int64_t n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
 // ------------------------------------------------------------------ Galerkin pass
-constexpr int kGW = 8;  // waves per Galerkin block
+constexpr int kGW = 4;  // waves per Galerkin block
 
 // LDS of one Galerkin block (8 waves).  Basis rows are padded to RT + 4 floats:
 // 16-byte aligned stores, and the row-wise reads of the reconstruction hit
@@ -250,8 +250,9 @@ DEV void galerkin_tile(const Tile& t, const double* __restrict__ phys, int nphys
   }
 }
 
-// r = 32: two blocks (16 waves) per CU, which the LDS allows; r = 64 is held to
-// one block per CU by its LDS.
+// r = 32: four blocks of four waves (16 waves) per CU, within the LDS and the
+// 128-register budget, so the 2048-row tiles of the batched configuration fit
+// in one round of the grid; r = 64: two blocks per CU (LDS).
 template <int RT>
 __global__ __launch_bounds__(64 * kGW)
 __attribute__((amdgpu_waves_per_eu(RT == 32 ? 4 : 1))) void k_galerkin_mfma(
