@@ -151,10 +151,10 @@ void free_all(rom_batch* h) {
                 h->Phi, h->sigma, h->a, h->a_prev, h->q_ref, h->d_var, h->y_corr, h->flags, h->P,
                 h->M, h->mesh_phi, h->mesh_qref, h->chosen, h->part, h->red, h->ubar, h->lmat,
                 h->active, h->iters, h->norms, h->rstate, h->qtmp, h->mpart, h->fq, h->fq_prev, h->vjp_tmp,
-                h->d_epoch, h->rvjp, h->epart, h->ev_iters, h->phi_cm};
+                h->d_epoch, h->rvjp, h->epart, h->ev_iters, h->phi_cm, h->Phi_alt};
   for (void* p : ps) (void)hipFree(p);
   bt_free(h);
-  if (h->win_exec) (void)hipGraphExecDestroy(h->win_exec);
+  for (auto& g : h->win_exec) if (g) (void)hipGraphExecDestroy(g);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->aux) (void)hipStreamDestroy(h->aux);
@@ -233,6 +233,7 @@ rom_status setup(rom_batch* h) {
   const int64_t td = h->total_dof;
   const int ns = std::max(c.n_s, 1);
   ROM_TRY(alloc((char**)&h->Phi, es * td * r));
+  h->phi_first = h->Phi;
   ROM_TRY(alloc(&h->sigma, (size_t)B * r));
   ROM_TRY(alloc(&h->a, (size_t)B * r));
   ROM_TRY(alloc(&h->a_prev, (size_t)B * r));
@@ -271,6 +272,7 @@ rom_status setup(rom_batch* h) {
   ROM_TRY(bt_setup(h));
   h->fom_block = fom_block_ok(h);
   if (window_split_ok(h)) {  // the second stream of a window (created outside any capture)
+    ROM_TRY(alloc((char**)&h->Phi_alt, es * td * r));
     ROM_HIP_CHECK(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
     ROM_HIP_CHECK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
     ROM_HIP_CHECK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
@@ -335,22 +337,26 @@ rom_status isvd_impl(rom_batch* h, const void* y, hipStream_t s) {
 }
 
 // One whole window with that overlap: the event chain on a second stream,
-// forked from s at the start and joined before the transfer and rotation.
-// The kernels and their inputs are those of the serial order, so the results
-// are the same.
+// forked from s at the start and joined before the state transfer.  The event
+// chain ends with the rotation of the basis into the second buffer Phi_alt
+// (the fine steps only read Phi), so only the transfer waits for the fine
+// steps.  The kernels and their inputs are those of the serial order, so the
+// results are the same.  The caller makes Phi_alt the current basis (swaps the
+// two pointers) once the window's work is enqueued or replayed.
 rom_status window_split_impl(rom_batch* h, hipStream_t s) {
-  ROM_REQUIRE(h->aux && h->ev_fork && h->ev_join, ROM_E_STATE, "no second stream");
+  ROM_REQUIRE(h->aux && h->ev_fork && h->ev_join && h->Phi_alt, ROM_E_STATE, "no second stream");
   const int z = h->cfg.z;
   ROM_HIP_CHECK(hipEventRecord(h->ev_fork, s));
   ROM_HIP_CHECK(hipStreamWaitEvent(h->aux, h->ev_fork, 0));
   rom_status st = launch_fom_block(h, h->y_corr, z * h->cfg.dt, h->y_corr, h->ev_iters, h->aux);
   if (st == ROM_OK) st = launch_isvd_core(h, h->y_corr, h->epart, h->aux);
+  if (st == ROM_OK) st = launch_isvd_rotate_into(h, h->Phi_alt, h->aux);
   // join even after an error, so that a capture in progress ends consistently
   ROM_HIP_CHECK(hipEventRecord(h->ev_join, h->aux));
   for (int k = 0; k < z && st == ROM_OK; ++k) st = launch_rom_fine_step(h, s);
   ROM_HIP_CHECK(hipStreamWaitEvent(s, h->ev_join, 0));
   ROM_TRY(st);
-  ROM_TRY(launch_isvd_apply(h, s));
+  ROM_TRY(launch_isvd_transfer(h, s));
   h->n_update += 1;
   ROM_TRY(launch_rebuild(h, s));
   h->n_events += 1;
@@ -502,24 +508,30 @@ rom_status rom_step(rom_handle h, int32_t n_fine, void* stream) {
     const bool reorth_due =
         h->cfg.reorth_every > 0 && (h->n_update + 1) % h->cfg.reorth_every == 0;
     if (graphs && aligned && !reorth_due) {
-      if (!h->win_exec || h->win_stream != s) {
-        if (h->win_exec) { (void)hipGraphExecDestroy(h->win_exec); h->win_exec = nullptr; }
+      // one graph per buffer holding the current basis: an overlapped window
+      // rotates into the other buffer, so consecutive windows alternate
+      const bool split = window_split_ok(h);
+      const int gk = (split && h->Phi != h->phi_first) ? 1 : 0;
+      hipGraphExec_t& ex = h->win_exec[gk];
+      if (!ex || h->win_stream[gk] != s) {
+        if (ex) { (void)hipGraphExecDestroy(ex); ex = nullptr; }
         hipGraph_t g = nullptr;
         ROM_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         rom_status st = ROM_OK;
         const int64_t nf = h->n_fine, nu = h->n_update, ne = h->n_events;
-        if (window_split_ok(h)) st = window_split_impl(h, s);
+        if (split) st = window_split_impl(h, s);
         else
           for (int k = 0; k < z && st == ROM_OK; ++k) st = fine_step_impl(h, s);
         hipError_t e = hipStreamEndCapture(s, &g);
         h->n_fine = nf; h->n_update = nu; h->n_events = ne;  // captured, not yet run
         if (st != ROM_OK) { if (g) (void)hipGraphDestroy(g); return st; }
         ROM_HIP_CHECK(e);
-        ROM_HIP_CHECK(hipGraphInstantiate(&h->win_exec, g, nullptr, nullptr, 0));
+        ROM_HIP_CHECK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
         ROM_HIP_CHECK(hipGraphDestroy(g));
-        h->win_stream = s;
+        h->win_stream[gk] = s;
       }
-      ROM_HIP_CHECK(hipGraphLaunch(h->win_exec, s));
+      ROM_HIP_CHECK(hipGraphLaunch(ex, s));
+      if (split) std::swap(h->Phi, h->Phi_alt);
       h->n_fine += z;
       h->n_update += 1;
       h->n_events += 1;
@@ -562,7 +574,8 @@ rom_status rom_set(rom_handle h, int32_t what, const void* src, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   const int B = h->cfg.n_inst, r = h->cfg.r;
   const size_t td = (size_t)h->total_dof;
-  if (h->win_exec) { (void)hipGraphExecDestroy(h->win_exec); h->win_exec = nullptr; }
+  for (auto& g : h->win_exec)
+    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
   switch (what) {
     case ROM_GET_BASIS: h->has_rom = true; return copy_words(src, h->Phi, h->esz * td * r, s);
     case ROM_GET_SIGMA: return copy_words(src, h->sigma, 8 * (size_t)B * r, s);

@@ -152,8 +152,12 @@ struct rom_batch {
   hipStream_t last_stream = nullptr;
 
   // graphs of one adaptation window
-  hipGraphExec_t win_exec = nullptr;
-  hipStream_t win_stream = nullptr;
+  // window graphs, one per basis buffer holding the current basis (the
+  // overlapped window rotates into the other buffer)
+  hipGraphExec_t win_exec[2] = {nullptr, nullptr};
+  hipStream_t win_stream[2] = {nullptr, nullptr};
+  void* Phi_alt = nullptr;     // T[total_dof * r]: second basis buffer (overlapped windows)
+  void* phi_first = nullptr;   // the first basis allocation (identifies the buffer in use)
   // second stream of a window: the event's coarse step, projections and core
   // SVD run beside the fine steps (they share no written data)
   hipStream_t aux = nullptr;
@@ -189,6 +193,10 @@ rom_status launch_isvd(rom_batch* h, const void* y, hipStream_t s);
 // then the state transfer and the basis rotation.
 rom_status launch_isvd_core(rom_batch* h, const void* y, double* part, hipStream_t s);
 rom_status launch_isvd_apply(rom_batch* h, hipStream_t s);
+// launch_isvd_apply split for the overlapped window (MFMA path): rotation of
+// the current basis into dst (out of place), then the state transfer.
+rom_status launch_isvd_rotate_into(rom_batch* h, void* dst, hipStream_t s);
+rom_status launch_isvd_transfer(rom_batch* h, hipStream_t s);
 // Online-loop adjoint pieces (adjoint.hip): the loss seed at the end state,
 // one fine step backward (after a Galerkin pass at its converged state), one
 // event backward down to yhat, FP32/FP64 conversion of device vectors.
@@ -236,7 +244,7 @@ bool mfma_ok(const rom_batch* h);
 // first: the first Newton iteration of a step (every instance runs)
 rom_status launch_galerkin_mfma(rom_batch* h, hipStream_t s, int first = 0);
 rom_status launch_galerkin_tail(rom_batch* h, int it0, hipStream_t s);
-rom_status launch_rotate_mfma(rom_batch* h, const double* pr, hipStream_t s);
+rom_status launch_rotate_mfma(rom_batch* h, const double* pr, void* dst, hipStream_t s);
 rom_status launch_project_fast(rom_batch* h, const void* y, const double* p1, int ldp, int mode,
                                double* part, int pst, double* q1out, hipStream_t s);
 

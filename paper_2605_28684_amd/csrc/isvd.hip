@@ -1048,7 +1048,7 @@ rom_status isvd_apply_t(rom_batch* h, hipStream_t s) {
   const int r = h->cfg.r, B = h->cfg.n_inst, n = r + 1;
   double* pr = h->rstate;
   hipLaunchKernelGGL(k_isvd_transfer, dim3(B), dim3(64), 0, s, r, h->ubar, h->a);
-  if (mfma_ok(h)) return launch_rotate_mfma(h, pr, s);
+  if (mfma_ok(h)) return launch_rotate_mfma(h, pr, h->Phi, s);
   hipLaunchKernelGGL((k_rotate<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                      h->d_dof_off, (const T*)h->Phi, r, r, (T*)h->Phi, r, r, h->ubar, n,
                      (size_t)n * n, 1, h->qtmp, pr, 2 * r + 2, nullptr);
@@ -1173,6 +1173,20 @@ rom_status launch_isvd_core(rom_batch* h, const void* y, double* part, hipStream
 }
 rom_status launch_isvd_apply(rom_batch* h, hipStream_t s) {
   return h->cfg.precision == ROM_F64 ? isvd_apply_t<double>(h, s) : isvd_apply_t<float>(h, s);
+}
+// The two halves of launch_isvd_apply for the overlapped window (MFMA path):
+// the rotation of the current basis into dst, and the state transfer.
+rom_status launch_isvd_rotate_into(rom_batch* h, void* dst, hipStream_t s) {
+  if (!mfma_ok(h)) {
+    set_error("the rotation into a second buffer needs the MFMA path");
+    return ROM_E_UNSUPPORTED;
+  }
+  return launch_rotate_mfma(h, h->rstate, dst, s);
+}
+rom_status launch_isvd_transfer(rom_batch* h, hipStream_t s) {
+  hipLaunchKernelGGL(k_isvd_transfer, dim3(h->cfg.n_inst), dim3(64), 0, s, h->cfg.r, h->ubar, h->a);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
 }
 rom_status launch_isvd_project(rom_batch* h, const void* y, hipStream_t s) {
   const int r = h->cfg.r;

@@ -357,12 +357,14 @@ __global__ __launch_bounds__(64 * kGW) void k_galerkin_tail(
 }
 
 // ------------------------------------------------------------------ iSVD rotation
-// Phi[i, :] <- Phi[i, :] U[:r, :r] + s_i U[r, :],  s_i = (q1_i - Phi[i, :] p2) / rho,
-// in place.  pr holds (p1, p2, 1/rho) per instance with stride 2r + 2.
+// dst[i, :] <- Phi[i, :] U[:r, :r] + s_i U[r, :],  s_i = (q1_i - Phi[i, :] p2) / rho;
+// dst may be Phi (in place: every row is read before it is written, by the same
+// wave).  pr holds (p1, p2, 1/rho) per instance with stride 2r + 2.
 template <int RT>
 __global__ __launch_bounds__(256) void k_rotate_mfma(const Tile* __restrict__ tiles,
                                                      const int64_t* __restrict__ dof_off,
-                                                     float* Phi, const double* __restrict__ U,
+                                                     const float* Phi, float* dst,
+                                                     const double* __restrict__ U,
                                                      const double* __restrict__ q1,
                                                      const double* __restrict__ pr) {
   constexpr int NCB = RT / 32;
@@ -425,7 +427,7 @@ __global__ __launch_bounds__(256) void k_rotate_mfma(const Tile* __restrict__ ti
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int i = (v >> 2) * 8 + par * 4 + (v & 3);
-        if (i < nr) Phi[(g0 + i) * RT + cb * 32 + cl] = acc[v];
+        if (i < nr) dst[(g0 + i) * RT + cb * 32 + cl] = acc[v];
       }
     }
     wave_sync();
@@ -534,13 +536,13 @@ rom_status launch_galerkin_tail(rom_batch* h, int it0, hipStream_t s) {
   return ROM_OK;
 }
 
-rom_status launch_rotate_mfma(rom_batch* h, const double* pr, hipStream_t s) {
+rom_status launch_rotate_mfma(rom_batch* h, const double* pr, void* dst, hipStream_t s) {
   if (h->cfg.r == 32)
     hipLaunchKernelGGL((k_rotate_mfma<32>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
-                       h->d_dof_off, (float*)h->Phi, h->ubar, h->qtmp, pr);
+                       h->d_dof_off, (const float*)h->Phi, (float*)dst, h->ubar, h->qtmp, pr);
   else
     hipLaunchKernelGGL((k_rotate_mfma<64>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
-                       h->d_dof_off, (float*)h->Phi, h->ubar, h->qtmp, pr);
+                       h->d_dof_off, (const float*)h->Phi, (float*)dst, h->ubar, h->qtmp, pr);
   ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
 }
