@@ -351,14 +351,17 @@ struct ReactModel {
 // Jacobian blocks of f at cell i: Jm = df_i/dq_{i-1}, J0 = df_i/dq_i, Jp = df_i/dq_{i+1}
 // and f_i itself.  sq holds cells i-1, i, i+1 at qm, q0, qp.  lw/rw mark a
 // zero-gradient wall on the left / right (ghost = copy of the end cell).
-template <class Mdl, typename T>
-DEV void cell_jacobian(const Mdl& m, const T* qm, const T* q0, const T* qp, bool lw, bool rw,
-                       T inv, T inv2, double x, T* f, T* Jm, T* J0, T* Jp, unsigned& fl) {
+// The cell's part given its two faces: face i-1/2 (flux HL, derivatives DLl /
+// DRl with respect to q_{i-1} / q_i) and face i+1/2 (HR, DLr / DRr with respect
+// to q_i / q_{i+1}).  Each face (FA) may be any indexable of NV or NV x NV
+// values (registers or a view of LDS).
+template <class Mdl, typename T, class FA>
+DEV void cell_combine(const Mdl& m, const FA& HL, const FA& DLl, const FA& DRl, const FA& HR,
+                      const FA& DLr, const FA& DRr, const T* qm, const T* q0, const T* qp,
+                      bool lw, bool rw, T inv, T inv2, double x, T* f, T* Jm, T* J0, T* Jp,
+                      unsigned& fl) {
   constexpr int NV = Mdl::NV;
   constexpr int NN = NV * NV;
-  T HL[NV], HR[NV], DLl[NN], DRl[NN], DLr[NN], DRr[NN];
-  m.face_jac(qm, q0, HL, DLl, DRl, fl);   // face i-1/2: (q_{i-1}, q_i)
-  m.face_jac(q0, qp, HR, DLr, DRr, fl);   // face i+1/2: (q_i, q_{i+1})
   // f_i = -(HR - HL) inv
 #pragma unroll
   for (int v = 0; v < NV; ++v) f[v] = -(HR[v] - HL[v]) * inv;
@@ -396,6 +399,19 @@ DEV void cell_jacobian(const Mdl& m, const T* qm, const T* q0, const T* qp, bool
 #pragma unroll
     for (int e = 0; e < NN; ++e) J0[e] += DS[e];
   }
+}
+
+template <class Mdl, typename T>
+DEV void cell_jacobian(const Mdl& m, const T* qm, const T* q0, const T* qp, bool lw, bool rw,
+                       T inv, T inv2, double x, T* f, T* Jm, T* J0, T* Jp, unsigned& fl) {
+  constexpr int NV = Mdl::NV;
+  constexpr int NN = NV * NV;
+  T HL[NV], HR[NV], DLl[NN], DRl[NN], DLr[NN], DRr[NN];
+  m.face_jac(qm, q0, HL, DLl, DRl, fl);   // face i-1/2: (q_{i-1}, q_i)
+  m.face_jac(q0, qp, HR, DLr, DRr, fl);   // face i+1/2: (q_i, q_{i+1})
+  const T* hl = HL; const T* dll = DLl; const T* drl = DRl;
+  const T* hr = HR; const T* dlr = DLr; const T* drr = DRr;
+  cell_combine(m, hl, dll, drl, hr, dlr, drr, qm, q0, qp, lw, rw, inv, inv2, x, f, Jm, J0, Jp, fl);
 }
 
 }  // namespace romhip

@@ -40,6 +40,34 @@ DEV void flag_or(uint32_t* flags, int b, unsigned fl) {
   if (fl) atomicOr(&flags[b], fl);
 }
 
+// Max of a and of b over the whole block (kTile threads), then one atomicMax
+// each from thread 0 (none for a zero).  Per-instance sup norms gathered this
+// way cost one atomic per block instead of one per wavefront: with 1024 tiles
+// per instance the per-wavefront atomics on one address serialise.  Every
+// thread of the block must call it.
+DEV void block_atomic_max2(uint64_t* da, uint64_t a, uint64_t* db, uint64_t b) {
+  __shared__ uint64_t ra[kTile / 64], rb[kTile / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t oa = __shfl_xor((unsigned long long)a, off);
+    const uint64_t ob = __shfl_xor((unsigned long long)b, off);
+    a = oa > a ? oa : a;
+    b = ob > b ? ob : b;
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { ra[w] = a; rb[w] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t ma = 0, mb = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+      ma = ra[k] > ma ? ra[k] : ma;
+      mb = rb[k] > mb ? rb[k] : mb;
+    }
+    if (da && ma) atomicMax((unsigned long long*)da, (unsigned long long)ma);
+    if (db && mb) atomicMax((unsigned long long*)db, (unsigned long long)mb);
+  }
+}
+
 DEV uint64_t norm_bits(float x) { return (uint64_t)__float_as_uint(fabsf(x)); }
 DEV uint64_t norm_bits(double x) { return (uint64_t)__double_as_longlong(fabs(x)); }
 
@@ -101,7 +129,7 @@ __global__ __launch_bounds__(kTile) void k_residual(
     const uint64_t bits = isfinite(val) ? norm_bits(val) : ~0ull;
     nb = bits > nb ? bits : nb;
   }
-  if (norms) wave_atomic_max(&norms[b], nb);
+  if (norms) block_atomic_max2(&norms[b], nb, nullptr, 0);
   flag_or<T>(flags, b, fl);
 }
 
@@ -350,8 +378,201 @@ __global__ __launch_bounds__(kTile) void k_assemble(
       yb = yv > yb ? yv : yb;
     }
   }
-  if (norms) wave_atomic_max(&norms[b], nb);
-  if (ynorms) wave_atomic_max(&ynorms[b], yb);
+  block_atomic_max2(norms ? &norms[b] : nullptr, nb, ynorms ? &ynorms[b] : nullptr, yb);
+  flag_or<T>(flags, b, fl);
+}
+
+// A face quantity in LDS: word w of face k at p[w * st] (structure of arrays).
+template <typename T>
+struct FaceView {
+  const T* p;
+  int st;
+  DEV T operator[](int w) const { return p[w * st]; }
+};
+
+// The same Newton system for models of at most three variables (Burgers,
+// Euler), with each face's flux Jacobian evaluated once: a thread per face
+// (nt + 1 faces) into LDS, then a thread per cell combines its two faces
+// exactly as cell_jacobian does (bitwise the same blocks), and the tile's
+// rows of sys, contiguous in memory, are written from LDS with coalesced
+// stores.
+template <class Mdl, typename T>
+__global__ __launch_bounds__(kTile) void k_assemble_faces(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off,
+    const int64_t* __restrict__ cell_off, const double* __restrict__ phys, int nphys,
+    const T* __restrict__ q, const T* __restrict__ qprev, T dt, T* __restrict__ sys,
+    uint32_t* flags, uint64_t* norms, uint64_t* ynorms, const int32_t* active) {
+  constexpr int NV = Mdl::NV;
+  constexpr int NN = NV * NV;
+  constexpr int SYS = 3 * NN + NV;
+  constexpr int FW = NV + 2 * NN;   // words per face: flux, d/dq_left, d/dq_right
+  constexpr int FS = kTile + 1;     // faces per tile
+  static_assert(FW * FS <= SYS * kTile, "face words must fit the output staging");
+  __shared__ T sq[(kTile + 2) * NV];
+  __shared__ T sw[SYS * kTile];     // face words, then the tile's rows of sys
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  if (active && !active[b]) return;
+  const int64_t n = cell_off[b + 1] - cell_off[b];
+  const int nt = (int)t.ncell;
+  const int64_t base = dof_off[b];
+  Mdl m(phys + (size_t)b * nphys);
+  load_tile<Mdl>(sq, q + base, t.cell0, nt, n);
+  __syncthreads();
+  unsigned fl = 0;
+  for (int k = threadIdx.x; k <= nt; k += blockDim.x) {   // face between cells k - 1 and k
+    T H[NV], DL[NN], DR[NN];
+    m.face_jac(&sq[k * NV], &sq[(k + 1) * NV], H, DL, DR, fl);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sw[v * FS + k] = H[v];
+#pragma unroll
+    for (int e = 0; e < NN; ++e) {
+      sw[(NV + e) * FS + k] = DL[e];
+      sw[(NV + NN + e) * FS + k] = DR[e];
+    }
+  }
+  __syncthreads();
+  const int i = threadIdx.x;
+  T o[SYS];
+  uint64_t nb = 0, yb = 0;
+  if (i < nt) {
+    const int64_t c = t.cell0 + i;
+    const bool lw = !Mdl::periodic && c == 0;
+    const bool rw = !Mdl::periodic && c == n - 1;
+    T f[NV], Jm[NN], J0[NN], Jp[NN];
+    const double x = ((double)c + 0.5) / (double)n;
+    const FaceView<T> HL{sw + i, FS}, DLl{sw + NV * FS + i, FS}, DRl{sw + (NV + NN) * FS + i, FS};
+    const FaceView<T> HR{sw + i + 1, FS}, DLr{sw + NV * FS + i + 1, FS},
+        DRr{sw + (NV + NN) * FS + i + 1, FS};
+    cell_combine(m, HL, DLl, DRl, HR, DLr, DRr, &sq[i * NV], &sq[(i + 1) * NV],
+                 &sq[(i + 2) * NV], lw, rw, T(n), T(n) * T(n), x, f, Jm, J0, Jp, fl);
+#pragma unroll
+    for (int e = 0; e < NN; ++e) {
+      o[e] = -dt * Jm[e];
+      o[NN + e] = -dt * J0[e] + ((e % (NV + 1)) == 0 ? T(1) : T(0));
+      o[2 * NN + e] = -dt * Jp[e];
+    }
+    const int64_t g = base + c * NV;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T qv = sq[(i + 1) * NV + v];
+      const T r = qv - qprev[g + v] - dt * f[v];
+      o[3 * NN + v] = -r;
+      if (!isfinite(r)) fl |= ROM_FLAG_NONFINITE;
+      const uint64_t bits = isfinite(r) ? norm_bits(r) : ~0ull;
+      nb = bits > nb ? bits : nb;
+      const uint64_t yv = norm_bits(qv);
+      yb = yv > yb ? yv : yb;
+    }
+  }
+  __syncthreads();   // the face words are no longer read
+  if (i < nt) {
+#pragma unroll
+    for (int e = 0; e < SYS; ++e) sw[i * SYS + e] = o[e];
+  }
+  __syncthreads();
+  T* dst = sys + (cell_off[b] + t.cell0) * SYS;
+  for (int e = threadIdx.x; e < nt * SYS; e += blockDim.x) dst[e] = sw[e];
+  block_atomic_max2(norms ? &norms[b] : nullptr, nb, ynorms ? &ynorms[b] : nullptr, yb);
+  flag_or<T>(flags, b, fl);
+}
+
+// The transposed system of k_assemble_adjoint for models of at most three
+// variables, with each face's flux Jacobian evaluated once (nt + 3 faces of
+// cells c0 - 2 .. c0 + nt + 1 into LDS); the blocks of cells i - 1, i and
+// i + 1 are combined from them exactly as cell_jacobian does, and the rows
+// are written from LDS with coalesced stores.
+template <class Mdl, typename T>
+__global__ __launch_bounds__(kTile) void k_assemble_adjoint_faces(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off,
+    const int64_t* __restrict__ cell_off, const double* __restrict__ phys, int nphys,
+    const T* __restrict__ q, T dt, const T* __restrict__ rhs, T* __restrict__ sys,
+    uint32_t* flags) {
+  constexpr int NV = Mdl::NV;
+  constexpr int NN = NV * NV;
+  constexpr int SYS = 3 * NN + NV;
+  constexpr int FW = NV + 2 * NN;
+  constexpr int FS = kTile + 3;
+  static_assert(FW * FS <= SYS * kTile, "face words must fit the output staging");
+  __shared__ T sq[(kTile + 4) * NV];
+  __shared__ T sw[SYS * kTile];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  const int64_t n = cell_off[b + 1] - cell_off[b];
+  const int nt = (int)t.ncell;
+  const int64_t base = dof_off[b];
+  Mdl m(phys + (size_t)b * nphys);
+  // stage cells c0-2 .. c0+nt+1 (wrapped, or clamped at walls)
+  for (int e = threadIdx.x; e < (nt + 4) * NV; e += blockDim.x) {
+    const int lc = e / NV, v = e - (e / NV) * NV;
+    int64_t c = t.cell0 - 2 + lc;
+    if (Mdl::periodic) { c = ((c % n) + n) % n; }
+    else { c = c < 0 ? 0 : (c >= n ? n - 1 : c); }
+    sq[e] = q[base + c * NV + v];
+  }
+  __syncthreads();
+  unsigned fl = 0;
+  for (int k = threadIdx.x; k < nt + 3; k += blockDim.x) {   // face between staged k, k + 1
+    T H[NV], DL[NN], DR[NN];
+    m.face_jac(&sq[k * NV], &sq[(k + 1) * NV], H, DL, DR, fl);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sw[v * FS + k] = H[v];
+#pragma unroll
+    for (int e = 0; e < NN; ++e) {
+      sw[(NV + e) * FS + k] = DL[e];
+      sw[(NV + NN + e) * FS + k] = DR[e];
+    }
+  }
+  __syncthreads();
+  // blocks of the cell in staged slot sl (faces sl - 1 and sl)
+  auto blocks = [&](int sl, int64_t cw, T* Jm, T* J0, T* Jp) {
+    const bool lw = !Mdl::periodic && cw == 0, rw = !Mdl::periodic && cw == n - 1;
+    T f[NV];
+    const FaceView<T> HL{sw + sl - 1, FS}, DLl{sw + NV * FS + sl - 1, FS},
+        DRl{sw + (NV + NN) * FS + sl - 1, FS};
+    const FaceView<T> HR{sw + sl, FS}, DLr{sw + NV * FS + sl, FS}, DRr{sw + (NV + NN) * FS + sl, FS};
+    cell_combine(m, HL, DLl, DRl, HR, DLr, DRr, &sq[(sl - 1) * NV], &sq[sl * NV],
+                 &sq[(sl + 1) * NV], lw, rw, T(n), T(n) * T(n), ((double)cw + 0.5) / (double)n,
+                 f, Jm, J0, Jp, fl);
+  };
+  const int i = threadIdx.x;
+  T o[SYS];
+  if (i < nt) {
+    const int64_t c = t.cell0 + i;
+    T Jm[NN], J0[NN], Jp[NN];
+    blocks(i + 2, c, Jm, J0, Jp);                  // own diagonal block
+#pragma unroll
+    for (int r = 0; r < NV; ++r)
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+        o[NN + r * NV + k] = -dt * J0[k * NV + r] + (r == k ? T(1) : T(0));
+    {  // left neighbour's C block (row c-1, coupling to c), transposed -> our A
+      const bool exists = Mdl::periodic || c - 1 >= 0;
+      if (exists) blocks(i + 1, (c - 1 + n) % n, Jm, J0, Jp);
+#pragma unroll
+      for (int r = 0; r < NV; ++r)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) o[r * NV + k] = exists ? -dt * Jp[k * NV + r] : T(0);
+    }
+    {  // right neighbour's A block (row c+1, coupling to c), transposed -> our C
+      const bool exists = Mdl::periodic || c + 1 < n;
+      if (exists) blocks(i + 3, (c + 1) % n, Jm, J0, Jp);
+#pragma unroll
+      for (int r = 0; r < NV; ++r)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) o[2 * NN + r * NV + k] = exists ? -dt * Jm[k * NV + r] : T(0);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) o[3 * NN + v] = rhs[base + c * NV + v];
+  }
+  __syncthreads();   // the face words are no longer read
+  if (i < nt) {
+#pragma unroll
+    for (int e = 0; e < SYS; ++e) sw[i * SYS + e] = o[e];
+  }
+  __syncthreads();
+  T* dst = sys + (cell_off[b] + t.cell0) * SYS;
+  for (int e = threadIdx.x; e < nt * SYS; e += blockDim.x) dst[e] = sw[e];
   flag_or<T>(flags, b, fl);
 }
 
@@ -643,11 +864,16 @@ static rom_status assemble_t(rom_batch* h, const void* q, const void* q_prev, do
                              hipStream_t s) {
   return with_model<T>(h, [&](auto tag) -> rom_status {
     using M = typename decltype(tag)::type;
-    hipLaunchKernelGGL((k_assemble<M, T>), dim3(h->n_tiles), dim3(kTile), 0, s, h->d_tiles,
-                       h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const T*)q,
-                       (const T*)q_prev, (T)dt, (T*)h->levels[0].sys, h->flags,
-                       h->norms + (size_t)it * h->cfg.n_inst,
-                       h->norms + (size_t)(h->cfg.newton_max + 1 + it) * h->cfg.n_inst, h->active);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(h->n_tiles), dim3(kTile), 0, s, h->d_tiles, h->d_dof_off,
+                         h->d_cell_off, h->d_phys, h->cfg.n_phys, (const T*)q, (const T*)q_prev,
+                         (T)dt, (T*)h->levels[0].sys, h->flags,
+                         h->norms + (size_t)it * h->cfg.n_inst,
+                         h->norms + (size_t)(h->cfg.newton_max + 1 + it) * h->cfg.n_inst,
+                         h->active);
+    };
+    if constexpr (M::NV <= 3) go(k_assemble_faces<M, T>);
+    else go(k_assemble<M, T>);
     return ROM_OK;
   });
 }
@@ -665,9 +891,13 @@ static rom_status assemble_adj_t(rom_batch* h, const void* q, double dt, const v
                                  hipStream_t s) {
   return with_model<T>(h, [&](auto tag) -> rom_status {
     using M = typename decltype(tag)::type;
-    hipLaunchKernelGGL((k_assemble_adjoint<M, T>), dim3(h->n_tiles), dim3(kTile), 0, s,
-                       h->d_tiles, h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys,
-                       (const T*)q, (T)dt, (const T*)rhs, (T*)h->levels[0].sys, h->flags);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(h->n_tiles), dim3(kTile), 0, s, h->d_tiles, h->d_dof_off,
+                         h->d_cell_off, h->d_phys, h->cfg.n_phys, (const T*)q, (T)dt,
+                         (const T*)rhs, (T*)h->levels[0].sys, h->flags);
+    };
+    if constexpr (M::NV <= 3) go(k_assemble_adjoint_faces<M, T>);
+    else go(k_assemble_adjoint<M, T>);
     return ROM_OK;
   });
 }
