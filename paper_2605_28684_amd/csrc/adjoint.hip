@@ -277,6 +277,22 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
   double jq = 0.0;
   double rp[kEPF], rb[kEPF];
   auto chunk_ne = [&](int64_t r0) { return (int)((nd - r0 < CH ? nd - r0 : CH) * r); };
+  // Ubar rows 0..r (row r from q / rho) against the r columns of Phibar', in
+  // 4 x 4 register tiles; KS thread groups split the rows of each chunk and
+  // keep their sums over the whole pass, added in group order at the end
+  constexpr int TI = 4, TJ = 4;
+  const int NI = (n + TI - 1) / TI, NJ = (r + TJ - 1) / TJ, NTL = NI * NJ;
+  int KS = kET / NTL;
+  if (KS * NTL * TI * TJ > 2 * CH * LDR) KS = 2 * CH * LDR / (NTL * TI * TJ);
+  if (KS < 1) KS = 1;
+  const bool tl_on = tid < NTL * KS;
+  const int ks = tid / NTL, tt = tid - (tid / NTL) * NTL;
+  const int i0 = (tt / NJ) * TI, j0 = (tt - (tt / NJ) * NJ) * TJ;
+  double ta[TI][TJ];
+#pragma unroll
+  for (int a = 0; a < TI; ++a)
+#pragma unroll
+    for (int c = 0; c < TJ; ++c) ta[a][c] = 0.0;
   if (nd > 0) chunk_fetch(Phi, phibar, base * r, chunk_ne(0), true, rp, rb);
   for (int64_t r0 = 0; r0 < nd; r0 += CH) {
     const int nr = (int)(nd - r0 < CH ? nd - r0 : CH);
@@ -290,24 +306,79 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
       qs[base + r0 + k] = q;
     }
     __syncthreads();
+    if (tl_on) {
+      for (int k = ks; k < nr; k += KS) {
+        double av[TI], bv[TJ];
+#pragma unroll
+        for (int a = 0; a < TI; ++a) {
+          const int i = i0 + a;
+          av[a] = i < r ? cP[k * LDR + i] : (i == r ? c0[k] * irho : 0.0);
+        }
+#pragma unroll
+        for (int c = 0; c < TJ; ++c) bv[c] = j0 + c < r ? cB[k * LDR + j0 + c] : 0.0;
+#pragma unroll
+        for (int a = 0; a < TI; ++a)
+#pragma unroll
+          for (int c = 0; c < TJ; ++c) ta[a][c] += av[a] * bv[c];
+      }
+    }
+    // rows of Phibar_old = Phibar' U[:r, :r]^T and jbar = Phibar' U[r, :r]^T in 4 x 3
+    // register tiles (each output summed over m in order by one thread)
+    {
+      constexpr int TR = 4, TC = 3;
+      const int NR = (nr + TR - 1) / TR, NC = (n + TC - 1) / TC;
+      for (int e = tid; e < NR * NC; e += kET) {
+        const int k0 = (e / NC) * TR, c0t = (e - (e / NC) * NC) * TC;
+        double o[TR][TC];
+#pragma unroll
+        for (int a = 0; a < TR; ++a)
+#pragma unroll
+          for (int c = 0; c < TC; ++c) o[a][c] = 0.0;
+        for (int m = 0; m < r; ++m) {
+          double bv[TR], uv[TC];
+#pragma unroll
+          for (int a = 0; a < TR; ++a) bv[a] = k0 + a < nr ? cB[(k0 + a) * LDR + m] : 0.0;
+#pragma unroll
+          for (int c = 0; c < TC; ++c) uv[c] = c0t + c < n ? U[(c0t + c) * n + m] : 0.0;
+#pragma unroll
+          for (int a = 0; a < TR; ++a)
+#pragma unroll
+            for (int c = 0; c < TC; ++c) o[a][c] += bv[a] * uv[c];
+        }
+#pragma unroll
+        for (int a = 0; a < TR; ++a) {
+          const int k = k0 + a;
+          if (k >= nr) continue;
+#pragma unroll
+          for (int c = 0; c < TC; ++c) {
+            const int cc = c0t + c;
+            if (cc < r) phibar[(base + r0 + k) * r + cc] = o[a][c];
+            else if (cc == r) {
+              js[base + r0 + k] = o[a][c];
+              jq += o[a][c] * c0[k];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // the row groups' sums of the Ubar tiles, added in group order (the chunk area is free)
+  {
+    double* part = cP;
+    if (tl_on) {
+#pragma unroll
+      for (int a = 0; a < TI; ++a)
+#pragma unroll
+        for (int c = 0; c < TJ; ++c) part[((size_t)ks * NTL + tt) * (TI * TJ) + a * TJ + c] = ta[a][c];
+    }
+    __syncthreads();
     for (int e = tid; e < n * r; e += kET) {
       const int i = e / r, j = e % r;
-      double s = 0.0;
-      if (i < r)
-        for (int k = 0; k < nr; ++k) s += cP[k * LDR + i] * cB[k * LDR + j];
-      else
-        for (int k = 0; k < nr; ++k) s += c0[k] * irho * cB[k * LDR + j];
-      Ub[i * n + j] += s;
-    }
-    for (int e = tid; e < nr * n; e += kET) {
-      const int k = e / n, c = e % n;
-      double s = 0.0;
-      for (int m = 0; m < r; ++m) s += cB[k * LDR + m] * U[c * n + m];
-      if (c < r) phibar[(base + r0 + k) * r + c] = s;
-      else {
-        js[base + r0 + k] = s;
-        jq += s * c0[k];
-      }
+      const int t2 = (i / TI) * NJ + j / TJ, w = (i % TI) * TJ + j % TJ;
+      double sacc = 0.0;
+      for (int g = 0; g < KS; ++g) sacc += part[((size_t)g * NTL + t2) * (TI * TJ) + w];
+      Ub[i * n + j] += sacc;
     }
     __syncthreads();
   }
@@ -352,12 +423,18 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
     wr[k] = s;
   }
   __syncthreads();
+  double* GVt = cP;   // (G V^T)[k][c], in the chunk area (at least n^2 doubles)
+  for (int e = tid; e < n * n; e += kET) {
+    const int k = e / n, c = e - (e / n) * n;
+    double gv = 0.0;
+    for (int m = 0; m < n; ++m) gv += Ub[k * n + m] * X[c * n + m];
+    GVt[e] = gv;
+  }
+  __syncthreads();
   for (int c = tid; c < n; c += kET) {
     double kd = 0.0, kc = 0.0;
     for (int k = 0; k < n; ++k) {
-      double gv = 0.0;   // (G V^T)[k][c]
-      for (int m = 0; m < n; ++m) gv += Ub[k * n + m] * X[c * n + m];
-      kd += U[c * n + k] * gv;
+      kd += U[c * n + k] * GVt[k * n + c];
       kc += U[c * n + k] * wr[k];
     }
     if (c < r) {
@@ -370,7 +447,21 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
   __syncthreads();
   // j = q / rho, rho = |q|: qbar = (jbar + rhobar q) / rho
   const double rhob = pb[r] - jq * irho * irho;
-  // pass B: p2bar = pbar - Phi^T qbar
+  // pass B: p2bar = pbar - Phi^T qbar (G row groups of r threads; their sums
+  // are added in group order)
+  const int G = kET / r;
+  const int gq = tid / r, gc = tid - (tid / r) * r;
+  auto group_sum = [&](double acc, double* out) {
+    __syncthreads();
+    if (gq < G) cP[gq * r + gc] = acc;
+    __syncthreads();
+    if (tid < r) {
+      double sacc = 0.0;
+      for (int g = 0; g < G; ++g) sacc += cP[g * r + tid];
+      out[tid] = pb[tid] - sacc;
+    }
+    __syncthreads();
+  };
   double acc = 0.0;
   if (nd > 0) chunk_fetch(Phi, phibar, base * r, chunk_ne(0), false, rp, rb);
   for (int64_t r0 = 0; r0 < nd; r0 += CH) {
@@ -380,12 +471,11 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
     for (int k = tid; k < nr; k += kET)
       c0[k] = (js[base + r0 + k] + rhob * qs[base + r0 + k]) * irho;
     __syncthreads();
-    if (tid < r)
-      for (int k = 0; k < nr; ++k) acc += cP[k * LDR + tid] * c0[k];
+    if (gq < G)
+      for (int k = gq; k < nr; k += G) acc += cP[k * LDR + gc] * c0[k];
     __syncthreads();
   }
-  if (tid < r) p2b[tid] = pb[tid] - acc;
-  __syncthreads();
+  group_sum(acc, p2b);
   // pass C: q1 = yhat - Phi p1, q1bar = qbar + Phi p2bar (into js);
   // Phibar_old += -qbar p2^T + q1 p2bar^T; p1bar = pbar - Phi^T q1bar
   acc = 0.0;
@@ -414,12 +504,11 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
       const int k = e / r, c = e % r;
       phibar[(base + r0) * r + e] = cB[k * LDR + c] - c0[k] * p2[c] + c1[k] * p2b[c];
     }
-    if (tid < r)
-      for (int k = 0; k < nr; ++k) acc += cP[k * LDR + tid] * c2[k];
+    if (gq < G)
+      for (int k = gq; k < nr; k += G) acc += cP[k * LDR + gc] * c2[k];
     __syncthreads();
   }
-  if (tid < r) p1b[tid] = pb[tid] - acc;
-  __syncthreads();
+  group_sum(acc, p1b);
   // pass D: Phibar_old += -q1bar p1^T + yhat p1bar^T; yhatbar = q1bar + Phi p1bar;
   // ybar += D yhatbar
   if (nd > 0) chunk_fetch(Phi, phibar, base * r, chunk_ne(0), true, rp, rb);
