@@ -1,25 +1,26 @@
 // Reverse mode of Alg. 1's online loop (an extension; the paper has no
 // adjoint): Galerkin fine steps (Burgers), adaptation events with the coarse
 // backward-Euler step, the Brand update (Alg. 2) and the closed-form state
-// transfer.  One workgroup per instance, FP64 throughout; the basis and the
-// states are read in the storage precision T.
+// transfer.  FP64 throughout; the basis and the states are read in the
+// storage precision T.
 //
 //  * k_online_seed: the loss seed at the end, q~ = q_ref + D^-1 Phi a:
 //    abar = Phi^T D^-1 qbar, Phibar = D^-1 qbar a^T.
-//  * k_step_vjp: one fine step a_{n+1} = G(a_n, Phi) with
+//  * k_step_vjp_solve + k_step_vjp_rows: one fine step a_{n+1} = G(a_n, Phi) with
 //    g(a) = a - a_n - dt Phi^T D f(q_ref + D^-1 Phi a) = 0, differentiated by
 //    the implicit-function theorem at the converged a_{n+1}:
 //    J_g^T lambda = abar, abar_n = lambda and
 //    Phibar += dt (D f) lambda^T + dt D^-1 J_f^T (D Phi lambda) a_{n+1}^T.
-//    J_g = I - dt Phi^T J_f Phi comes from the Galerkin pass's tile partials.
+//    J_g = I - dt Phi^T J_f Phi comes from the Galerkin pass's tile partials;
+//    the r x r solve runs per instance, the Phibar update per pass tile.
 //  * k_event_vjp: one event from the transfer back to yhat = D (y - q_ref):
 //    transfer a' = Ubar[:r, :r]^T a, rotation Phi' = [Phi, q / rho] Ubar[:, :r],
 //    truncation sigma' = Sbar[:r], the SVD of the core K (distinct singular
 //    values: Kbar = Ubar G Vbar^T with G_ii = sbar_i and
 //    G_ij = s_j (M_ij - M_ji) / (s_j^2 - s_i^2), M = Ubar^T Ubarbar), the core's
 //    entries lambda sigma, p = p1 + p2 and rho = |q|, and the two classical
-//    Gram-Schmidt passes.  The coarse step's transposed solve is done by the
-//    banded solver outside.
+//    Gram-Schmidt passes, one workgroup per instance.  The coarse step's
+//    transposed solve is done by the banded solver outside.
 #include "internal.h"
 #include "linalg.h"
 #include "physics.h"
@@ -88,25 +89,23 @@ __global__ __launch_bounds__(kAT) void k_online_seed(
   if (tid < r) abar[(size_t)b * r + tid] = acc * dinv;
 }
 
-// One fine step backward.  mpart/tfirst: the Galerkin pass's tile partials of
-// Phi^T J_f Phi at a1 (= a_{n+1}); qt, w: per-DOF scratch.
+// One fine step backward, in two launches.  k_step_vjp_solve (a workgroup per
+// instance): lambda = J_g^-T abar with J_g = I - dt M, M = Phi^T J_f Phi at a1
+// (= a_{n+1}) summed from the Galerkin pass's tile partials in tile order;
+// abar is replaced by lambda.  k_step_vjp_rows (a workgroup per pass tile):
+// Phibar += dt d f lambda^T + dt (J_f^T Phi lambda) a1^T over the tile's rows,
+// with q~ = q_ref + D^-1 Phi a1 and w = Phi lambda of the rows and their two
+// neighbours kept in LDS (the neighbours are recomputed by each tile).
 template <typename T>
-__global__ __launch_bounds__(kAT) void k_step_vjp(
-    int r, double dt, const int64_t* __restrict__ dof_off, const double* __restrict__ phys,
-    int nphys, const double* __restrict__ dvar, const int* __restrict__ tfirst,
-    const T* __restrict__ mpart, const T* __restrict__ Phi, const T* __restrict__ qref,
-    const double* __restrict__ a1, double* __restrict__ abar, double* __restrict__ phibar,
-    double* __restrict__ qt, double* __restrict__ w, uint32_t* flags) {
+__global__ __launch_bounds__(kAT) void k_step_vjp_solve(int r, double dt,
+                                                        const int* __restrict__ tfirst,
+                                                        const T* __restrict__ mpart,
+                                                        double* __restrict__ abar,
+                                                        uint32_t* flags) {
   __shared__ double A[kMaxR * (kMaxR + 1)];
   __shared__ double lam[kMaxR];
-  __shared__ double sa[kMaxR];
   const int b = blockIdx.x, tid = threadIdx.x;
   const int ld = r + 1;
-  const int64_t base = dof_off[b], n = dof_off[b + 1] - base;
-  const double d = dvar[b], dinv = 1.0 / d;
-  const double nu = phys[(size_t)b * nphys];
-  const double inv = (double)n, inv2 = (double)n * (double)n;
-  // A = J_g^T with J_g = I - dt M, M summed over the instance's tiles in tile order
   const int t0 = tfirst[b], t1 = tfirst[b + 1];
   for (int e = tid; e < r * r; e += kAT) {
     double s = 0.0;
@@ -114,36 +113,65 @@ __global__ __launch_bounds__(kAT) void k_step_vjp(
     const int i = e / r, j = e % r;
     A[j * ld + i] = (i == j ? 1.0 : 0.0) - dt * s;
   }
-  for (int c = tid; c < r; c += kAT) {
-    lam[c] = abar[(size_t)b * r + c];
-    sa[c] = a1[(size_t)b * r + c];
-  }
+  for (int c = tid; c < r; c += kAT) lam[c] = abar[(size_t)b * r + c];
   __syncthreads();
   const int ok = block_lu_solve(A, ld, lam, r);
   if (!ok && tid == 0) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
   for (int c = tid; c < r; c += kAT) abar[(size_t)b * r + c] = lam[c];
-  // q~ = q_ref + D^-1 Phi a1 and w = Phi lambda
-  for (int64_t i = tid; i < n; i += kAT) {
-    const T* pr = Phi + (base + i) * r;
-    double sq = 0.0, sw = 0.0;
-    for (int c = 0; c < r; ++c) {
-      const double p = (double)pr[c];
-      sq += p * sa[c];
-      sw += p * lam[c];
-    }
-    qt[base + i] = (double)qref[base + i] + sq * dinv;
-    w[base + i] = sw;
+}
+
+constexpr int kRT = 256;   // threads of k_step_vjp_rows
+constexpr int kSL = 8;     // lanes per row (each holds kSL-strided columns)
+
+template <typename T>
+__global__ __launch_bounds__(kRT) void k_step_vjp_rows(
+    const Tile* __restrict__ tiles, int r, double dt, const int64_t* __restrict__ dof_off,
+    const double* __restrict__ phys, int nphys, const double* __restrict__ dvar,
+    const T* __restrict__ Phi, const T* __restrict__ qref, const double* __restrict__ a1,
+    const double* __restrict__ lambda, double* __restrict__ phibar) {
+  __shared__ double sq[kPassRows + 2], sw[kPassRows + 2];
+  __shared__ double lam[kMaxR], sa[kMaxR];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst, tid = threadIdx.x;
+  const int64_t base = dof_off[b], n = dof_off[b + 1] - base;
+  const int nt = (int)t.ncell;
+  const double d = dvar[b], dinv = 1.0 / d;
+  const double nu = phys[(size_t)b * nphys];
+  const double inv = (double)n, inv2 = (double)n * (double)n;
+  for (int c = tid; c < r; c += kRT) {
+    lam[c] = lambda[(size_t)b * r + c];
+    sa[c] = a1[(size_t)b * r + c];
   }
   __syncthreads();
-  // Phibar += dt d f lambda^T + dt (J_f^T w) a1^T
-  for (int64_t i = tid; i < n; i += kAT) {
-    const int64_t im = wrap(i - 1, n), ip = wrap(i + 1, n);
-    const double um = qt[base + im], u0 = qt[base + i], up = qt[base + ip];
+  const int sub = tid % kSL;
+  // q~ and w of rows cell0 - 1 .. cell0 + nt (periodic), each summed over its lanes
+  for (int rr = tid / kSL; rr < nt + 2; rr += kRT / kSL) {
+    const int64_t i = wrap(t.cell0 - 1 + rr, n);
+    const T* pr = Phi + (base + i) * r;
+    double sqv = 0.0, swv = 0.0;
+    for (int c = sub; c < r; c += kSL) {
+      const double p = (double)pr[c];
+      sqv += p * sa[c];
+      swv += p * lam[c];
+    }
+#pragma unroll
+    for (int off = kSL / 2; off > 0; off >>= 1) {
+      sqv += __shfl_xor(sqv, off);
+      swv += __shfl_xor(swv, off);
+    }
+    if (sub == 0) {
+      sq[rr] = (double)qref[base + i] + sqv * dinv;
+      sw[rr] = swv;
+    }
+  }
+  __syncthreads();
+  for (int rr = tid / kSL; rr < nt; rr += kRT / kSL) {
+    const int64_t i = t.cell0 + rr;
     double f, be, al_next, ga_prev;
-    burgers_col(um, u0, up, nu, inv, inv2, f, be, al_next, ga_prev);
-    const double v = al_next * w[base + ip] + be * w[base + i] + ga_prev * w[base + im];
+    burgers_col(sq[rr], sq[rr + 1], sq[rr + 2], nu, inv, inv2, f, be, al_next, ga_prev);
+    const double v = al_next * sw[rr + 2] + be * sw[rr + 1] + ga_prev * sw[rr];
     double* pb = phibar + (base + i) * r;
-    for (int c = 0; c < r; ++c) pb[c] += dt * d * f * lam[c] + dt * v * sa[c];
+    for (int c = sub; c < r; c += kSL) pb[c] += dt * d * f * lam[c] + dt * v * sa[c];
   }
 }
 
@@ -562,17 +590,19 @@ rom_status launch_online_seed(rom_batch* h, const void* qbar, double* abar, doub
 
 rom_status launch_step_vjp(rom_batch* h, const void* Phi, const double* a1, double* abar,
                            double* phibar, double* qt, double* w, hipStream_t s) {
+  (void)qt;
+  (void)w;
   const int B = h->cfg.n_inst, r = h->cfg.r;
-  if (h->cfg.precision == ROM_F64)
-    hipLaunchKernelGGL((k_step_vjp<double>), dim3(B), dim3(kAT), 0, s, r, h->cfg.dt, h->d_dof_off,
-                       h->d_phys, h->cfg.n_phys, h->d_var, h->d_ptile_first,
-                       (const double*)h->mpart, (const double*)Phi, (const double*)h->q_ref, a1,
-                       abar, phibar, qt, w, h->flags);
-  else
-    hipLaunchKernelGGL((k_step_vjp<float>), dim3(B), dim3(kAT), 0, s, r, h->cfg.dt, h->d_dof_off,
-                       h->d_phys, h->cfg.n_phys, h->d_var, h->d_ptile_first,
-                       (const float*)h->mpart, (const float*)Phi, (const float*)h->q_ref, a1, abar,
-                       phibar, qt, w, h->flags);
+  auto go = [&](auto tag) {
+    using T = decltype(tag);
+    hipLaunchKernelGGL((k_step_vjp_solve<T>), dim3(B), dim3(kAT), 0, s, r, h->cfg.dt,
+                       h->d_ptile_first, (const T*)h->mpart, abar, h->flags);
+    hipLaunchKernelGGL((k_step_vjp_rows<T>), dim3(h->n_ptiles), dim3(kRT), 0, s, h->d_ptiles, r,
+                       h->cfg.dt, h->d_dof_off, h->d_phys, h->cfg.n_phys, h->d_var,
+                       (const T*)Phi, (const T*)h->q_ref, a1, abar, phibar);
+  };
+  if (h->cfg.precision == ROM_F64) go(double{});
+  else go(float{});
   ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
 }
