@@ -418,8 +418,8 @@ DEV void sec_root(int k, int K, const double* delta, const double* zeta2, double
 
 // K: the core in LDS (N x N, row-major); Uc: LDS N x N scratch (column c at
 // Uc + c N); U: output N x N (row-major, columns = sorted vectors); sv: LDS N.
-template <int N>
-DEV bool arrow_svd_wave(const double* K, double* Uc, double* U, double* sv, double* ws, int* iw) {
+DEV bool arrow_svd_wave(const int N, const double* K, double* Uc, double* U, double* sv, double* ws,
+                        int* iw) {
   const int lane = threadIdx.x & 63;
   const double eps = 2.220446049250313e-16;
   double* d = ws;            // N
@@ -580,9 +580,10 @@ DEV bool arrow_svd_wave(const double* K, double* Uc, double* U, double* sv, doub
 
 // Core of Alg. 2: K from lambda, sigma, p, rho; SVD; sigma' and the transfer of a.
 // red layout per instance: [0..r) p1, r: |y^|^2, [r+1..2r+1) p2, 2r+1: |q1|^2
-// One wavefront per instance.  NF = 0: any r, one-sided Jacobi (jacobi_rows);
-// NF = r + 1 in {33, 65}: the arrowhead SVD (arrow_svd_wave).
-template <int NF>
+// One wavefront per instance: the arrowhead SVD (arrow_svd_wave), with the
+// one-sided Jacobi SVD (jacobi_rows) when sigma is not sorted (ARROW), or
+// Jacobi alone (!ARROW).
+template <bool ARROW>
 __global__ __launch_bounds__(64) void k_isvd_core(int r, double lambda, double tau_rho,
                                                   const double* __restrict__ red, int ldr,
                                                   double* __restrict__ sigma,
@@ -621,13 +622,13 @@ __global__ __launch_bounds__(64) void k_isvd_core(int r, double lambda, double t
     K[e] = v;
   }
   __syncthreads();
-  if constexpr (NF == 0) {
+  if constexpr (!ARROW) {
     jacobi_rows(K, G, n, ld, U, sv, nrm, rank);
   } else {
     // arrowhead SVD (one wavefront); Jacobi when sigma is not sorted
     double* ws = reinterpret_cast<double*>(rank + n + (n & 1));
-    int* iw = reinterpret_cast<int*>(ws + 13 * NF);
-    if (!arrow_svd_wave<NF>(K, G, U, sv, ws, iw)) jacobi_rows(K, G, n, ld, U, sv, nrm, rank);
+    int* iw = reinterpret_cast<int*>(ws + 13 * n);
+    if (!arrow_svd_wave(n, K, G, U, sv, ws, iw)) jacobi_rows(K, G, n, ld, U, sv, nrm, rank);
     __syncthreads();
   }
   for (int c = tid; c < r; c += blockDim.x) sigma[(size_t)b * r + c] = sv[c];
@@ -1028,15 +1029,9 @@ rom_status isvd_core_t(rom_batch* h, const void* y, double* part, hipStream_t s)
   double* pr = h->rstate;  // (p1, p2, 1/rho) per instance, stride 2r + 2
   // the arrowhead path adds 13 N doubles and 8 N + 3 ints of workspace
   const size_t shm_arrow = shm + sizeof(double) * (13 * n + 2) + sizeof(int) * (8 * n + 3 + 2);
-  if (r == 32)
-    hipLaunchKernelGGL(k_isvd_core<33>, dim3(B), dim3(64), shm_arrow, s, r, h->cfg.lambda,
-                       h->cfg.tau_rho, red, ldr, h->sigma, h->ubar, pr, h->flags);
-  else if (r == 64)
-    hipLaunchKernelGGL(k_isvd_core<65>, dim3(B), dim3(64), shm_arrow, s, r, h->cfg.lambda,
-                       h->cfg.tau_rho, red, ldr, h->sigma, h->ubar, pr, h->flags);
-  else
-    hipLaunchKernelGGL(k_isvd_core<0>, dim3(B), dim3(64), shm, s, r, h->cfg.lambda,
-                       h->cfg.tau_rho, red, ldr, h->sigma, h->ubar, pr, h->flags);
+  (void)shm;
+  hipLaunchKernelGGL(k_isvd_core<true>, dim3(B), dim3(64), shm_arrow, s, r, h->cfg.lambda,
+                     h->cfg.tau_rho, red, ldr, h->sigma, h->ubar, pr, h->flags);
   ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
 }
@@ -1157,9 +1152,7 @@ rom_status project_state_t(rom_batch* h, const void* q, hipStream_t s) {
 
 rom_status isvd_kernels_prepare() {
   const int big = 160 * 1024 - 1024;
-  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_isvd_core<0>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_isvd_core<33>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_isvd_core<65>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_isvd_core<true>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_pod_svd, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   return ROM_OK;
 }
