@@ -23,6 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libromhip.so")
 
 ROM_OK = 0
+ROM_E_INVAL, ROM_E_NOMEM, ROM_E_DEVICE, ROM_E_STATE, ROM_E_UNSUPPORTED = -1, -2, -3, -6, -7
 STATUS = {0: "ROM_OK", -1: "ROM_E_INVAL", -2: "ROM_E_NOMEM", -3: "ROM_E_DEVICE",
           -6: "ROM_E_STATE", -7: "ROM_E_UNSUPPORTED"}
 FLAG_NEWTON_NOCONV, FLAG_FLOOR, FLAG_NONFINITE, FLAG_RHO_ZERO = 1, 2, 4, 8

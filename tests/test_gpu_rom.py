@@ -283,6 +283,67 @@ def test_deim_rows_bit_exact_and_pinv(precision):
         assert G.relerr(M[b], O.rebuild(Phis[b], ref)) < 1e-12
 
 
+@pytest.mark.parametrize("precision", [W.F64, W.F32])
+def test_deim_rows_bit_exact_at_maximum_sizes(precision):
+    """The largest sample set the library takes (r = 64, n_s = 2 r = 128, the
+    reacting configuration's sizes), on ragged instances of several pass tiles
+    with a ragged tail: the two-round greedy picks match the oracle row for row
+    and the pseudo-inverse within FP64 round-off."""
+    import gpu_common as G
+    from paper_2605_28684_amd import romhip as R
+    cells = [700, 1501]
+    r, ns = 64, 128
+    w = W.sod_hllc_f32(n=cells[0], r=r, n_s=ns, precision=precision)
+    w.n_cells = cells
+    w.phys = [dict(gamma=1.4)] * 2
+    w.w_init = r
+    h = _handle(w)
+    Phis = [G.rounded(_orth(3 * n, r, 60 + b), precision) for b, n in enumerate(cells)]
+    rng = np.random.default_rng(2)
+    _load_state(h, w, Phis, [np.ones(r)] * 2, [rng.normal(size=r)] * 2,
+                np.zeros(3 * sum(cells)), [np.ones(3)] * 2, precision)
+    h.rom_rebuild()
+    P = h.get(R.GET_SAMPLES).cpu().numpy().reshape(2, ns)
+    M = G.host(h.get(R.GET_PINV)).reshape(2, r, ns)
+    for b in range(2):
+        ref = O.deim_greedy(Phis[b], ns)
+        np.testing.assert_array_equal(P[b], ref)
+        assert len(set(P[b].tolist())) == ns
+        assert G.relerr(M[b], O.rebuild(Phis[b], ref)) < 1e-11
+    assert not (h.status() & 16).any()
+
+
+def test_invalid_arguments_are_rejected():
+    """Argument errors come back as ROM_E_INVAL (state errors as ROM_E_STATE)
+    before anything is enqueued, and the handle keeps working afterwards."""
+    import gpu_common as G
+    import torch
+    from paper_2605_28684_amd import romhip as R
+    w = _burgers_batch([300, 517], W.F32, 8)
+    with pytest.raises(R.RomError) as e:      # r above the library's maximum
+        R.RomBatch(_burgers_batch([300], W.F32, 65), q0=None, use_graph=False)
+    assert e.value.code == R.ROM_E_INVAL
+    bad = _burgers_batch([300], W.F32, 8)
+    bad.hyper, bad.projection, bad.n_s = W.HR_DEIM, W.LSPG, 17   # n_s above 2 r
+    with pytest.raises(R.RomError) as e:
+        R.RomBatch(bad, q0=None, use_graph=False)
+    assert e.value.code == R.ROM_E_INVAL
+    h = _handle(w)
+    q = G.to_dev(W.random_state(W.BURGERS, w.n_cells, seed=4), W.F32)
+    with pytest.raises(R.RomError) as e:      # no reduced state yet
+        h.rom_step(1)
+    assert e.value.code == R.ROM_E_STATE
+    with pytest.raises(R.RomError) as e:
+        h.fom_step(q, -1.0)
+    assert e.value.code == R.ROM_E_INVAL
+    with pytest.raises(R.RomError) as e:
+        h.rollout_vjp(q, 0, 1e-3, q)
+    assert e.value.code == R.ROM_E_INVAL
+    out = h.fom_step(q, 1e-3)                 # still usable
+    torch.cuda.synchronize()
+    assert torch.isfinite(out).all()
+
+
 @pytest.mark.parametrize("problem", [W.EULER_RUSANOV, W.EULER_HLLC, W.BURGERS])
 def test_hr_lspg_step_parity(problem):
     import gpu_common as G
