@@ -589,9 +589,7 @@ rom_status launch_online_seed(rom_batch* h, const void* qbar, double* abar, doub
 }
 
 rom_status launch_step_vjp(rom_batch* h, const void* Phi, const double* a1, double* abar,
-                           double* phibar, double* qt, double* w, hipStream_t s) {
-  (void)qt;
-  (void)w;
+                           double* phibar, hipStream_t s) {
   const int B = h->cfg.n_inst, r = h->cfg.r;
   auto go = [&](auto tag) {
     using T = decltype(tag);

@@ -819,7 +819,7 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
       if (st == ROM_OK) st = launch_galerkin_pass(h, s);
       h->Phi = phi_live;
       h->a = a_live;
-      if (st == ROM_OK) st = launch_step_vjp(h, phi_k, a_k, abar, phibar, scr0, scr1, s);
+      if (st == ROM_OK) st = launch_step_vjp(h, phi_k, a_k, abar, phibar, s);
     }
   }
   if (st == ROM_OK) st = restore(nseg);

@@ -203,7 +203,7 @@ rom_status launch_isvd_transfer(rom_batch* h, hipStream_t s);
 rom_status launch_online_seed(rom_batch* h, const void* qbar, double* abar, double* phibar,
                               hipStream_t s);
 rom_status launch_step_vjp(rom_batch* h, const void* Phi, const double* a1, double* abar,
-                           double* phibar, double* qt, double* w, hipStream_t s);
+                           double* phibar, hipStream_t s);
 rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new,
                             const double* sig_old, const double* a_old, const double* ubar,
                             const double* pr, const double* sig_new, double* abar,
