@@ -62,7 +62,7 @@ DEV void burgers_col(double um, double u0, double up, double nu, double inv, dou
 
 DEV int64_t wrap(int64_t c, int64_t n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
-constexpr int kSC = 64;   // rows of a staged chunk in the seed and step adjoints
+constexpr int kSC = 64;   // rows of a staged chunk in the seed adjoint
 
 template <typename T>
 __global__ __launch_bounds__(kAT) void k_online_seed(
@@ -74,19 +74,27 @@ __global__ __launch_bounds__(kAT) void k_online_seed(
   const int b = blockIdx.x, tid = threadIdx.x;
   const int64_t base = dof_off[b], n = dof_off[b + 1] - base;
   const double dinv = 1.0 / dvar[b];
-  double acc = 0.0;   // thread c < r: (Phi^T qbar)_c
+  // (Phi^T qbar)_c: G row groups of r threads, their sums added in group order
+  const int G = kAT / r, gq = tid / r, gc = tid - (tid / r) * r;
+  double acc = 0.0;
   for (int64_t r0 = 0; r0 < n; r0 += kSC) {
     const int nr = (int)(n - r0 < kSC ? n - r0 : kSC);
     for (int e = tid; e < nr * r; e += kAT) cP[e] = (double)Phi[(base + r0) * r + e];
     for (int k = tid; k < nr; k += kAT) cq[k] = (double)qbar[base + r0 + k];
     __syncthreads();
-    if (tid < r)
-      for (int k = 0; k < nr; ++k) acc += cP[k * r + tid] * cq[k];
+    if (gq < G)
+      for (int k = gq; k < nr; k += G) acc += cP[k * r + gc] * cq[k];
     for (int e = tid; e < nr * r; e += kAT)
       phibar[(base + r0) * r + e] = cq[e / r] * dinv * a[(size_t)b * r + e % r];
     __syncthreads();
   }
-  if (tid < r) abar[(size_t)b * r + tid] = acc * dinv;
+  if (gq < G) cP[gq * r + gc] = acc;
+  __syncthreads();
+  if (tid < r) {
+    double s = 0.0;
+    for (int g = 0; g < G; ++g) s += cP[g * r + tid];
+    abar[(size_t)b * r + tid] = s * dinv;
+  }
 }
 
 // One fine step backward, in two launches.  k_step_vjp_solve (a workgroup per

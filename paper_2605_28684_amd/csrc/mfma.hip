@@ -264,6 +264,9 @@ __attribute__((amdgpu_waves_per_eu(RT == 32 ? 4 : 1))) void k_galerkin_mfma(
     int first) {
   constexpr int NT = 64 * kGW;
   __shared__ GalerkinLds<RT> L;
+  // the fine steps are the window's critical path: their waves win issue
+  // arbitration against the event chain running beside them
+  __builtin_amdgcn_s_setprio(3);
   const Tile t = tiles[blockIdx.x];
   const int b = t.inst;
   if (!first && !active[b]) return;   // the first iteration of a step runs every instance

@@ -257,6 +257,7 @@ void k_galerkin_solve_w(
     int32_t* __restrict__ iters, double tol, uint32_t* flags, int first) {
   static_assert(RT == 32, "two columns per lane pair, 32 rows");
   constexpr int NL = RT / 2;   // columns per lane
+  __builtin_amdgcn_s_setprio(3);   // critical path of the window (see k_galerkin_mfma)
   const int b = blockIdx.x, lane = threadIdx.x;
   if (!first && !active[b]) return;
   const int i = lane & 31, h = lane >> 5;
