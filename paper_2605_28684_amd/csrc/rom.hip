@@ -653,16 +653,42 @@ DEV void qr_lstsq(double* A, int m, int nc, double* rhs, double* x) {
       }
     }
     __syncthreads();
-    // apply H = I - beta v v^T to columns k+1..nc-1 and the rhs, one wavefront per column
-    for (int c = k + 1 + wave; c <= nc; c += nw) {
-      double* col = c < nc ? A + c : rhs;
-      const int cs = c < nc ? ld : 1;
-      double sdot = 0.0;
-      for (int i = k + lane; i < m; i += 64) sdot += A[i * ld + k] * col[i * cs];
+    // apply H = I - beta v v^T to columns k+1..nc-1 and the rhs: each wavefront
+    // takes kQG consecutive columns at a time, whose dot products and updates
+    // are interleaved (independent chains in flight); every column's sum runs
+    // in the same order as with one column at a time
+    constexpr int kQG = 4;
+    for (int c0 = k + 1 + wave * kQG; c0 <= nc; c0 += nw * kQG) {
+      double* col[kQG];
+      int cs[kQG];
+      bool on[kQG];
+      double sdot[kQG];
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) sdot += __shfl_xor(sdot, off);
-      sdot *= beta;
-      for (int i = k + lane; i < m; i += 64) col[i * cs] -= sdot * A[i * ld + k];
+      for (int g = 0; g < kQG; ++g) {
+        const int c = c0 + g;
+        on[g] = c <= nc;
+        col[g] = c < nc ? A + c : rhs;
+        cs[g] = c < nc ? ld : 1;
+        sdot[g] = 0.0;
+      }
+      for (int i = k + lane; i < m; i += 64) {
+        const double vi = A[i * ld + k];
+#pragma unroll
+        for (int g = 0; g < kQG; ++g)
+          if (on[g]) sdot[g] += vi * col[g][i * cs[g]];
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int g = 0; g < kQG; ++g) sdot[g] += __shfl_xor(sdot[g], off);
+#pragma unroll
+      for (int g = 0; g < kQG; ++g) sdot[g] *= beta;
+      for (int i = k + lane; i < m; i += 64) {
+        const double vi = A[i * ld + k];
+#pragma unroll
+        for (int g = 0; g < kQG; ++g)
+          if (on[g]) col[g][i * cs[g]] -= sdot[g] * vi;
+      }
     }
     __syncthreads();
     if (tid == 0) A[k * ld + k] = alpha_s;  // R diagonal
