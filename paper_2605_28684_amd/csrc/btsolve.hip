@@ -358,6 +358,12 @@ __global__ __launch_bounds__(256) void k_bt_back(int n_inst, const int64_t* __re
 template <typename T>
 size_t esz() { return sizeof(T); }
 
+// Cells per part.  One thread eliminates a part, so the part size trades the
+// threads a level has against the work of the upper levels.  Small blocks favour
+// long parts (fewer levels); 12 x 12 blocks keep one thread's state far beyond
+// the register file, so shorter parts (four times the threads) win there.
+int bt_part_size(int nv) { return nv >= 8 ? 4 : 16; }
+
 template <typename T, int NV>
 rom_status bt_solve_t(rom_batch* h, int it, void* upd, void* out, hipStream_t s) {
   using L = Lay<T, NV>;
@@ -369,10 +375,10 @@ rom_status bt_solve_t(rom_batch* h, int it, void* upd, void* out, hipStream_t s)
     auto& nx = h->levels[l + 1];
     const int nb = (int)((lv.parts_total + 255) / 256);
     hipLaunchKernelGGL((k_bt_factor<T, NV>), dim3(nb), dim3(256), 0, s, B, lv.d_cell_off,
-                       lv.d_part_off, kPartM, (const T*)lv.sys, (T*)lv.fwd, (T*)lv.part, act,
+                       lv.d_part_off, h->bt_m, (const T*)lv.sys, (T*)lv.fwd, (T*)lv.part, act,
                        h->flags);
     hipLaunchKernelGGL((k_bt_reduce<T, NV>), dim3(nb), dim3(256), 0, s, B, lv.d_cell_off,
-                       lv.d_part_off, kPartM, (const T*)lv.sys, (const T*)lv.fwd,
+                       lv.d_part_off, h->bt_m, (const T*)lv.sys, (const T*)lv.fwd,
                        (const T*)lv.part, nx.d_cell_off, (T*)nx.sys, act);
   }
   auto& top = h->levels[nl - 1];
@@ -390,7 +396,7 @@ rom_status bt_solve_t(rom_batch* h, int it, void* upd, void* out, hipStream_t s)
       // only when offsets coincide, which holds because level 0 uses the DOF ordering)
     }
     hipLaunchKernelGGL((k_bt_back<T, NV>), dim3(nb), dim3(256), 0, s, B, lv.d_cell_off,
-                       lv.d_part_off, kPartM, (const T*)lv.fwd, (const T*)lv.part, nx.d_cell_off,
+                       lv.d_part_off, h->bt_m, (const T*)lv.fwd, (const T*)lv.part, nx.d_cell_off,
                        (const T*)nx.x, xout, h->d_dof_off, (T*)upd, mode, act,
                        (last && it >= 0)
                            ? h->norms + (size_t)(2 * (h->cfg.newton_max + 1) + it) * B
@@ -408,6 +414,7 @@ rom_status bt_setup(rom_batch* h) {
   const size_t es = h->esz;
   const int NV = h->nv;
   const int NN = NV * NV;
+  const int pm = h->bt_m = bt_part_size(NV);
   std::vector<int64_t> n(h->n_cells);
   h->levels.clear();
   while (true) {
@@ -417,7 +424,7 @@ rom_status bt_setup(rom_batch* h) {
     int64_t mx = 0;
     for (int b = 0; b < B; ++b) {
       lv.cell_off[b + 1] = lv.cell_off[b] + n[b];
-      lv.part_off[b + 1] = lv.part_off[b] + (n[b] + kPartM - 1) / kPartM;
+      lv.part_off[b + 1] = lv.part_off[b] + (n[b] + pm - 1) / pm;
       mx = std::max(mx, n[b]);
     }
     lv.n_total = lv.cell_off[B];
@@ -437,7 +444,7 @@ rom_status bt_setup(rom_batch* h) {
     }
     h->levels.push_back(std::move(lv));
     if (top) break;
-    for (int b = 0; b < B; ++b) n[b] = (n[b] + kPartM - 1) / kPartM;
+    for (int b = 0; b < B; ++b) n[b] = (n[b] + pm - 1) / pm;
   }
   return ROM_OK;
 }

@@ -34,7 +34,6 @@ constexpr int kTile = 256;          // cells per tile of the stencil kernels
 constexpr int kPassRows = 2048;     // basis rows per block of the tall-skinny passes
 constexpr int kMaxR = 64;           // largest reduced dimension supported
 constexpr int kMaxNs = 2 * kMaxR;   // largest number of DEIM rows
-constexpr int kPartM = 16;          // part size of the block-tridiagonal solver
 
 // A contiguous run of cells of one instance handled by one thread block.
 struct Tile {
@@ -138,6 +137,7 @@ struct rom_batch {
   void* fq = nullptr;        // T[total_dof] current iterate
   void* fq_prev = nullptr;   // T[total_dof]
   std::vector<romhip::BtLevel> levels;
+  int bt_m = 16;                      // part size of the block-tridiagonal solver
   void* vjp_tmp = nullptr;   // T[total_dof]
   void* rvjp = nullptr;      // rollout-adjoint checkpoints and segment states
   size_t rvjp_bytes = 0;
