@@ -190,6 +190,191 @@ __global__ __launch_bounds__(256) void k_bt_factor(int n_inst, const int64_t* __
   if (!ok) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
 }
 
+// The same elimination for large blocks, where one thread's state (several NV x NV
+// blocks) would not fit in registers.  A group of 16 lanes eliminates one part:
+// lane i owns row i of every block, and whole blocks are shared through LDS.  At
+// each cell the group forms the augmented rows [B - A Chat | C | A Vhat | d - A ghat]
+// (at the first cell [B | C | A | d]) and reduces them by Gauss-Jordan with
+// partial pivoting, which leaves Chat, -Vhat (+Vhat at the first cell) and ghat in
+// the right-hand columns.  Pivot rows stay with the lane that holds them, so after
+// the reduction lane i holds the row of the solution numbered by the step at which
+// it was chosen.  The loops run the longest part's trip count on every group, so
+// control flow, and every barrier, is uniform across the block.
+template <typename T, int NV>
+__global__ __launch_bounds__(64) void k_bt_factor_rows(int n_inst, const int64_t* __restrict__ cell_off,
+                                                       const int64_t* __restrict__ part_off, int m,
+                                                       const T* __restrict__ sys, T* __restrict__ fwd,
+                                                       T* __restrict__ prt, const int32_t* active,
+                                                       uint32_t* flags) {
+  static_assert(NV <= 16, "one row per lane of a 16-lane group");
+  using L = Lay<T, NV>;
+  constexpr int NN = L::NN;
+  constexpr int NA = 3 * NV + 1;   // augmented row: [Bt | C | X | y]
+  constexpr int GP = 4;            // parts (16-lane groups) per block
+  __shared__ T sC[GP][NN];         // Chat of the last cell (W in the backward sweep)
+  __shared__ T sV[GP][NN];         // Vhat of the last cell (V in the backward sweep)
+  __shared__ T sg[GP][NV];         // ghat of the last cell (g in the backward sweep)
+  __shared__ T sp[GP][2][NA];      // scaled pivot row, double-buffered
+  const int grp = threadIdx.x >> 4;
+  const int i = threadIdx.x & 15;
+  const bool row = i < NV;
+  const int64_t gp = (int64_t)blockIdx.x * GP + grp;
+  bool live = gp < part_off[n_inst];
+  int b = 0;
+  int64_t k = 0, first = 0, len = 0, base = 0;
+  if (live) {
+    b = find_inst(part_off, n_inst, gp);
+    live = !(active && !active[b]);
+  }
+  if (live) {
+    k = gp - part_off[b];
+    const int64_t n = cell_off[b + 1] - cell_off[b];
+    first = k * m;
+    const int64_t s = (first + m < n ? first + m : n) - 1;
+    len = s - first;
+    base = cell_off[b];
+    live = len > 0;
+  }
+  T* Pp = prt + (live ? (part_off[b] + k) * L::PRT : 0);
+  bool ok = true;
+  for (int t = 0; t < m - 1; ++t) {
+    const bool act = live && t < len;
+    const bool mine = act && row;
+    T aug[NA], arow[NV];
+#pragma unroll
+    for (int e = 0; e < NA; ++e) aug[e] = T(0);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) arow[c] = T(0);
+    if (mine) {
+      const T* S = sys + (base + first + t) * L::SYS;
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        arow[c] = S[i * NV + c];
+        aug[c] = S[NN + i * NV + c];
+        aug[NV + c] = S[2 * NN + i * NV + c];
+      }
+      aug[3 * NV] = S[3 * NN + i];
+    }
+    if (t == 0) {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) aug[2 * NV + c] = arow[c];
+    } else {
+      // rows of the previous cell's Chat, Vhat, ghat were written to LDS and a
+      // barrier followed
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        T s1 = T(0), s2 = T(0);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          s1 += arow[q] * sC[grp][q * NV + c];
+          s2 += arow[q] * sV[grp][q * NV + c];
+        }
+        aug[c] -= s1;
+        aug[2 * NV + c] = s2;
+      }
+      T s3 = T(0);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) s3 += arow[q] * sg[grp][q];
+      aug[3 * NV] -= s3;
+    }
+    // Gauss-Jordan over the group's rows
+    bool done = !row;
+    int myrow = 0;
+#pragma unroll
+    for (int kk = 0; kk < NV; ++kk) {
+      const T a = aug[kk];
+      T key = done ? T(-1) : (isnan(a) ? T(INFINITY) : fabs(a));
+      int kl = i;
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) {
+        const T ko = __shfl_xor(key, o, 16);
+        const int lo = __shfl_xor(kl, o, 16);
+        if (ko > key || (ko == key && lo < kl)) { key = ko; kl = lo; }
+      }
+      if (act && !(key != T(0))) ok = false;
+      if (i == kl) {
+        const T ip = a != T(0) ? T(1) / a : T(0);
+#pragma unroll
+        for (int c = kk + 1; c < NA; ++c) {
+          aug[c] *= ip;
+          sp[grp][kk & 1][c] = aug[c];
+        }
+        done = true;
+        myrow = kk;
+      }
+      __syncthreads();
+      if (i != kl) {
+#pragma unroll
+        for (int c = kk + 1; c < NA; ++c) aug[c] -= a * sp[grp][kk & 1][c];
+      }
+    }
+    const T sgn = t == 0 ? T(1) : T(-1);
+    if (mine) {
+      T* F = fwd + (base + first + t) * L::FWD;
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        F[myrow * NV + c] = aug[NV + c];
+        F[NN + myrow * NV + c] = sgn * aug[2 * NV + c];
+        sC[grp][myrow * NV + c] = aug[NV + c];
+        sV[grp][myrow * NV + c] = sgn * aug[2 * NV + c];
+      }
+      F[2 * NN + myrow] = aug[3 * NV];
+      sg[grp][myrow] = aug[3 * NV];
+      if (t == len - 1) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) Pp[myrow * NV + c] = aug[NV + c];   // What of the last cell
+      }
+    }
+    __syncthreads();
+  }
+  // Backward sweep for the first interior cell, starting from the last cell's
+  // (Vhat, Chat, ghat): g = ghat_j - Chat_j g, V = Vhat_j - Chat_j V, W = -Chat_j W.
+  for (int t = m - 3; t >= 0; --t) {
+    const bool mine = live && row && t <= len - 2;
+    T vn[NV], wn[NV], gn = T(0);
+    if (mine) {
+      const T* F = fwd + (base + first + t) * L::FWD;
+      T crow[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) crow[q] = F[i * NV + q];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        T s1 = T(0), s2 = T(0);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          s1 += crow[q] * sV[grp][q * NV + c];
+          s2 += crow[q] * sC[grp][q * NV + c];
+        }
+        vn[c] = F[NN + i * NV + c] - s1;
+        wn[c] = -s2;
+      }
+      T s3 = T(0);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) s3 += crow[q] * sg[grp][q];
+      gn = F[2 * NN + i] - s3;
+    }
+    __syncthreads();
+    if (mine) {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        sV[grp][i * NV + c] = vn[c];
+        sC[grp][i * NV + c] = wn[c];
+      }
+      sg[grp][i] = gn;
+    }
+    __syncthreads();
+  }
+  if (live && row) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      Pp[NN + i * NV + c] = sV[grp][i * NV + c];
+      Pp[2 * NN + i * NV + c] = sC[grp][i * NV + c];
+    }
+    Pp[3 * NN + i] = sg[grp][i];
+    if (!ok) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
+  }
+}
+
 // Separator rows -> next level's system.
 template <typename T, int NV>
 __global__ __launch_bounds__(256) void k_bt_reduce(int n_inst, const int64_t* __restrict__ cell_off,
@@ -358,11 +543,10 @@ __global__ __launch_bounds__(256) void k_bt_back(int n_inst, const int64_t* __re
 template <typename T>
 size_t esz() { return sizeof(T); }
 
-// Cells per part.  One thread eliminates a part, so the part size trades the
-// threads a level has against the work of the upper levels.  Small blocks favour
-// long parts (fewer levels); 12 x 12 blocks keep one thread's state far beyond
-// the register file, so shorter parts (four times the threads) win there.
-int bt_part_size(int nv) { return nv >= 8 ? 4 : 16; }
+// Cells per part.  The part size trades the parallelism of a level against the
+// work of the upper levels: 16 for small blocks (one thread per part); 8 for the
+// 12 x 12 blocks, whose parts are eliminated by 16-lane groups.
+int bt_part_size(int nv) { return nv >= 8 ? 8 : 16; }
 
 template <typename T, int NV>
 rom_status bt_solve_t(rom_batch* h, int it, void* upd, void* out, hipStream_t s) {
@@ -374,9 +558,16 @@ rom_status bt_solve_t(rom_batch* h, int it, void* upd, void* out, hipStream_t s)
     auto& lv = h->levels[l];
     auto& nx = h->levels[l + 1];
     const int nb = (int)((lv.parts_total + 255) / 256);
-    hipLaunchKernelGGL((k_bt_factor<T, NV>), dim3(nb), dim3(256), 0, s, B, lv.d_cell_off,
-                       lv.d_part_off, h->bt_m, (const T*)lv.sys, (T*)lv.fwd, (T*)lv.part, act,
-                       h->flags);
+    if constexpr (NV >= 8) {
+      const int ng = (int)((lv.parts_total + 3) / 4);
+      hipLaunchKernelGGL((k_bt_factor_rows<T, NV>), dim3(ng), dim3(64), 0, s, B, lv.d_cell_off,
+                         lv.d_part_off, h->bt_m, (const T*)lv.sys, (T*)lv.fwd, (T*)lv.part, act,
+                         h->flags);
+    } else {
+      hipLaunchKernelGGL((k_bt_factor<T, NV>), dim3(nb), dim3(256), 0, s, B, lv.d_cell_off,
+                         lv.d_part_off, h->bt_m, (const T*)lv.sys, (T*)lv.fwd, (T*)lv.part, act,
+                         h->flags);
+    }
     hipLaunchKernelGGL((k_bt_reduce<T, NV>), dim3(nb), dim3(256), 0, s, B, lv.d_cell_off,
                        lv.d_part_off, h->bt_m, (const T*)lv.sys, (const T*)lv.fwd,
                        (const T*)lv.part, nx.d_cell_off, (T*)nx.sys, act);
