@@ -306,6 +306,75 @@ struct ReactModel {
       S[10] += kin * (T(ph[5]) - q[10]);
     }
   }
+  // Row v of face_jac: H_v and row v of dH/dq_L, dH/dq_R, with the same
+  // arithmetic as the full blocks.  Used where only sampled rows are needed.
+  DEV void face_jac_row(const T* L, const T* R, int v, T& H, T* dl, T* dr) const {
+#pragma unroll
+    for (int w = 0; w < 12; ++w) { dl[w] = T(0); dr[w] = T(0); }
+    const T uf = T(0.5) * (L[11] + R[11]);
+    const bool left = uf >= T(0);
+    if (v == 11) {
+      H = godunov(L[11], R[11], dl[11], dr[11]);
+    } else {
+      const T up = left ? L[v] : R[v];
+      H = uf * up;
+      dl[11] = T(0.5) * up;
+      dr[11] = T(0.5) * up;
+#pragma unroll
+      for (int w = 0; w < 11; ++w)
+        if (w == v) { if (left) dl[w] = uf; else dr[w] = uf; }
+    }
+  }
+  // Row v of source_jac: S_v and row v of dS/dq, accumulated in the same order
+  // as the full block.
+  DEV void source_jac_row(const T* q, double x, int v, T& Sv, T* ds, unsigned& fl) const {
+    const T A = T(ph[2]);
+    const T Tc = q[10];
+    if (Tc < T(kTFloor)) fl |= ROM_FLAG_FLOOR;
+    const bool live = Tc >= T(kTFloor);
+    const T Tf = live ? Tc : T(kTFloor);
+    Sv = T(0);
+#pragma unroll
+    for (int w = 0; w < 12; ++w) ds[w] = T(0);
+    auto put = [&](int ia, int ib, T s, T dwa, T dwb, T dwT) {
+#pragma unroll
+      for (int w = 0; w < 12; ++w) {
+        if (w == ia) ds[w] += s * dwa;
+        if (w == ib) ds[w] += s * dwb;
+        if (w == 10) ds[w] += s * dwT;
+      }
+    };
+    for (int j = 0; j < 12; ++j) {
+      const int ia = int(ph[16 + j]), ib = int(ph[28 + j]), ic = int(ph[40 + j]), id = int(ph[52 + j]);
+      const T E = T(ph[64 + j]);
+      const T k = A * dexp(-E / Tf);
+      const T w = k * q[ia] * q[ib];
+      const T dwa = k * q[ib], dwb = k * q[ia];
+      const T dwT = live ? w * E / (Tf * Tf) : T(0);
+      const int rows[4] = {ia, ib, ic, id};
+      const T sg[4] = {T(-1), T(-1), T(1), T(1)};
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        if (rows[m] == v) {
+          Sv += sg[m] * w;
+          put(ia, ib, sg[m], dwa, dwb, dwT);
+        }
+      }
+      if (v == 10) {
+        const T Qj = T(ph[76 + j]);
+        Sv += Qj * w;
+        put(ia, ib, Qj, dwa, dwb, dwT);
+      }
+    }
+    if (x < ph[4]) {
+      const T kin = T(ph[3]);
+      if (v < 10) Sv += kin * (T(ph[6 + v]) - q[v]);
+      if (v == 10) Sv += kin * (T(ph[5]) - q[10]);
+#pragma unroll
+      for (int w = 0; w < 11; ++w)
+        if (w == v) ds[w] -= kin;
+    }
+  }
   // S and dS/dq (row-major 12 x 12)
   DEV void source_jac(const T* q, double x, T* S, T* DS, unsigned& fl) const {
     const T A = T(ph[2]);

@@ -405,13 +405,19 @@ __global__ __launch_bounds__(256) void k_hr_step(
     double dt, double tol, int max_it, int32_t* __restrict__ iters, uint32_t* flags) {
   constexpr int NV = Mdl::NV;
   constexpr int NN = NV * NV;
+  constexpr int E3 = 3 * NV;       // entries of a sampled row's three-cell stencil
+  static_assert(E3 <= kMaxR, "the stencil states share the A_s buffer");
   extern __shared__ double sm[];
   double* sa = sm;                 // r
   double* sap = sa + kMaxR;        // r
   double* bs = sap + kMaxR;        // ns
-  double* As = bs + kMaxNs;        // ns x r
+  double* rh = bs + kMaxNs;        // r
+  double* As = rh + kMaxR;         // ns x r (leading dimension kMaxR); first the stencil states
+  double* sq3 = As;                // ns x E3: reconstructed states of the sampled stencils
   double* Ar = As + kMaxNs * kMaxR;  // r x r, leading dimension r + 1
-  double* rh = Ar + kMaxR * (kMaxR + 1);  // r
+  double* sjr = Ar;                // ns x E3: sampled Jacobian rows scaled by 1 / d (before Ar)
+  __shared__ int sv[kMaxNs];       // variable of each sampled row
+  __shared__ double sdd[kMaxNs];   // dt d_v of each sampled row
   __shared__ int ok, stop;
   __shared__ unsigned flacc;
   const int b = blockIdx.x, tid = threadIdx.x;
@@ -419,70 +425,127 @@ __global__ __launch_bounds__(256) void k_hr_step(
   Mdl m(phys + (size_t)b * nphys);
   const double* dv = dvar + (size_t)b * NV;
   const double* Mb = Mp + (size_t)b * r * ns;
+  const double* mph = mphi + (size_t)b * ns * E3 * r;
   for (int c = tid; c < r; c += blockDim.x) { sa[c] = a[(size_t)b * r + c]; sap[c] = sa[c]; }
   if (tid == 0) { stop = 0; flacc = 0; }
   __syncthreads();
   int it = 0;
   for (; it < max_it; ++it) {
-    // sampled rows of P^T D r and P^T D J_r D^-1 Phi
+    // stencil states q = q_ref + D^-1 Phi a of every sampled row, one entry per
+    // thread
+    for (int idx = tid; idx < ns * E3; idx += blockDim.x) {
+      const int s = idx / E3, e = idx - s * E3;
+      const double* Ph = mph + ((size_t)s * E3 + e) * r;
+      double acc = 0.0;
+      for (int k = 0; k < r; ++k) acc += Ph[k] * sa[k];
+      sq3[idx] = mqref[((size_t)b * ns + s) * E3 + e] + acc / dv[e % NV];
+    }
+    __syncthreads();
+    // sampled rows of P^T D r and of the Jacobian P^T D J_r D^-1 (one row per thread)
     for (int s = tid; s < ns; s += blockDim.x) {
       const int p = P[(size_t)b * ns + s];
       const int64_t c = p / NV;
       const int v = p % NV;
-      const double* Ph = mphi + ((size_t)b * ns + s) * 3 * NV * r;
-      const double* Qr = mqref + ((size_t)b * ns + s) * 3 * NV;
-      double q3[3 * NV];
-      for (int e = 0; e < 3 * NV; ++e) {
-        double acc = 0.0;
-        for (int k = 0; k < r; ++k) acc += Ph[e * r + k] * sa[k];
-        q3[e] = Qr[e] + acc / dv[e % NV];
-      }
+      const double* Ph = mph + (size_t)s * E3 * r;
       const bool lw = !Mdl::periodic && c == 0, rw = !Mdl::periodic && c == n - 1;
-      double f[NV], Jm[NN], J0[NN], Jp[NN];
+      const double inv = (double)n, inv2 = (double)n * (double)n;
+      double fv, jm[NV], j0[NV], jp[NV];   // f_v and row v of the three Jacobian blocks
       unsigned fl = 0;
-      {
-        // cell_jacobian for one cell (FP64), inlined to avoid a cross-file template
-        double HL[NV], HR[NV], DLl[NN], DRl[NN], DLr[NN], DRr[NN];
-        m.face_jac(&q3[0], &q3[NV], HL, DLl, DRl, fl);
-        m.face_jac(&q3[NV], &q3[2 * NV], HR, DLr, DRr, fl);
-        const double inv = (double)n, inv2 = (double)n * (double)n;
-        for (int w = 0; w < NV; ++w) f[w] = -(HR[w] - HL[w]) * inv;
-        for (int e = 0; e < NN; ++e) {
-          Jm[e] = DLl[e] * inv; J0[e] = (DRl[e] - DLr[e]) * inv; Jp[e] = -DRr[e] * inv;
-        }
-        if (lw) for (int e = 0; e < NN; ++e) { J0[e] += Jm[e]; Jm[e] = 0.0; }
-        if (rw) for (int e = 0; e < NN; ++e) { J0[e] += Jp[e]; Jp[e] = 0.0; }
+      if constexpr (NV >= 8) {
+        // large blocks: only row v is formed (the model's row methods), reading
+        // the stencil states from LDS
+        const double* q3 = sq3 + s * E3;
+        double hl, hr, dll[NV], drl[NV], dlr[NV], drr[NV];
+        m.face_jac_row(&q3[0], &q3[NV], v, hl, dll, drl);
+        m.face_jac_row(&q3[NV], &q3[2 * NV], v, hr, dlr, drr);
+        fv = -(hr - hl) * inv;
         for (int w = 0; w < NV; ++w) {
-          const double kap = m.kappa(w);
-          if (kap != 0.0) {
-            f[w] += kap * ((q3[2 * NV + w] - q3[NV + w]) - (q3[NV + w] - q3[w])) * inv2;
-            const double cc = kap * inv2;
-            Jm[w * NV + w] += lw ? 0.0 : cc;
-            Jp[w * NV + w] += rw ? 0.0 : cc;
-            J0[w * NV + w] += -2.0 * cc + (lw ? cc : 0.0) + (rw ? cc : 0.0);
-          }
+          jm[w] = dll[w] * inv; j0[w] = (drl[w] - dlr[w]) * inv; jp[w] = -drr[w] * inv;
+        }
+        if (lw) for (int w = 0; w < NV; ++w) { j0[w] += jm[w]; jm[w] = 0.0; }
+        if (rw) for (int w = 0; w < NV; ++w) { j0[w] += jp[w]; jp[w] = 0.0; }
+        const double kap = m.kappa(v);
+        if (kap != 0.0) {
+          fv += kap * ((q3[2 * NV + v] - q3[NV + v]) - (q3[NV + v] - q3[v])) * inv2;
+          const double cc = kap * inv2;
+          for (int w = 0; w < NV; ++w)
+            if (w == v) {
+              jm[w] += lw ? 0.0 : cc;
+              jp[w] += rw ? 0.0 : cc;
+              j0[w] += -2.0 * cc + (lw ? cc : 0.0) + (rw ? cc : 0.0);
+            }
         }
         if (Mdl::has_source) {
-          double S[NV], DS[NN];
-          m.source_jac(&q3[NV], ((double)c + 0.5) / (double)n, S, DS, fl);
-          for (int w = 0; w < NV; ++w) f[w] += S[w];
-          for (int e = 0; e < NN; ++e) J0[e] += DS[e];
+          double sv_, ds[NV];
+          m.source_jac_row(&q3[NV], ((double)c + 0.5) / (double)n, v, sv_, ds, fl);
+          fv += sv_;
+          for (int w = 0; w < NV; ++w) j0[w] += ds[w];
+        }
+      } else {
+        double q3[E3];
+        for (int e = 0; e < E3; ++e) q3[e] = sq3[s * E3 + e];
+        double f[NV], Jm[NN], J0[NN], Jp[NN];
+        {
+          // cell_jacobian for one cell (FP64), inlined to avoid a cross-file template
+          double HL[NV], HR[NV], DLl[NN], DRl[NN], DLr[NN], DRr[NN];
+          m.face_jac(&q3[0], &q3[NV], HL, DLl, DRl, fl);
+          m.face_jac(&q3[NV], &q3[2 * NV], HR, DLr, DRr, fl);
+          for (int w = 0; w < NV; ++w) f[w] = -(HR[w] - HL[w]) * inv;
+          for (int e = 0; e < NN; ++e) {
+            Jm[e] = DLl[e] * inv; J0[e] = (DRl[e] - DLr[e]) * inv; Jp[e] = -DRr[e] * inv;
+          }
+          if (lw) for (int e = 0; e < NN; ++e) { J0[e] += Jm[e]; Jm[e] = 0.0; }
+          if (rw) for (int e = 0; e < NN; ++e) { J0[e] += Jp[e]; Jp[e] = 0.0; }
+          for (int w = 0; w < NV; ++w) {
+            const double kap = m.kappa(w);
+            if (kap != 0.0) {
+              f[w] += kap * ((q3[2 * NV + w] - q3[NV + w]) - (q3[NV + w] - q3[w])) * inv2;
+              const double cc = kap * inv2;
+              Jm[w * NV + w] += lw ? 0.0 : cc;
+              Jp[w * NV + w] += rw ? 0.0 : cc;
+              J0[w * NV + w] += -2.0 * cc + (lw ? cc : 0.0) + (rw ? cc : 0.0);
+            }
+          }
+          if (Mdl::has_source) {
+            double S[NV], DS[NN];
+            m.source_jac(&q3[NV], ((double)c + 0.5) / (double)n, S, DS, fl);
+            for (int w = 0; w < NV; ++w) f[w] += S[w];
+            for (int e = 0; e < NN; ++e) J0[e] += DS[e];
+          }
+        }
+        fv = f[v];
+        for (int w = 0; w < NV; ++w) {
+          jm[w] = Jm[v * NV + w]; j0[w] = J0[v * NV + w]; jp[w] = Jp[v * NV + w];
         }
       }
       if (fl) atomicOr(&flacc, fl);
       const double dp = dv[v];
       double bsum = 0.0;
       for (int k = 0; k < r; ++k) bsum += Ph[(NV + v) * r + k] * (sa[k] - sap[k]);
-      bs[s] = bsum - dt * dp * f[v];
-      for (int k = 0; k < r; ++k) {
-        double acc = 0.0;
-        for (int w = 0; w < NV; ++w) {
-          acc += Jm[v * NV + w] * Ph[w * r + k] / dv[w];
-          acc += J0[v * NV + w] * Ph[(NV + w) * r + k] / dv[w];
-          acc += Jp[v * NV + w] * Ph[(2 * NV + w) * r + k] / dv[w];
-        }
-        As[s * kMaxR + k] = Ph[(NV + v) * r + k] - dt * dp * acc;
+      bs[s] = bsum - dt * dp * fv;
+      for (int w = 0; w < NV; ++w) {
+        const double id = 1.0 / dv[w];
+        sjr[s * E3 + w] = jm[w] * id;
+        sjr[s * E3 + NV + w] = j0[w] * id;
+        sjr[s * E3 + 2 * NV + w] = jp[w] * id;
       }
+      sv[s] = v;
+      sdd[s] = dt * dp;
+    }
+    __syncthreads();
+    // A_s = P^T Phi - dt P^T D J_r D^-1 Phi, one entry per thread (consecutive
+    // threads take consecutive basis columns)
+    for (int idx = tid; idx < ns * r; idx += blockDim.x) {
+      const int s = idx / r, k = idx - s * r;
+      const double* Ph = mph + (size_t)s * E3 * r + k;
+      const double* jr = sjr + s * E3;
+      double acc = 0.0;
+      for (int w = 0; w < NV; ++w) {
+        acc += jr[w] * Ph[w * r];
+        acc += jr[NV + w] * Ph[(NV + w) * r];
+        acc += jr[2 * NV + w] * Ph[(2 * NV + w) * r];
+      }
+      As[s * kMaxR + k] = Ph[(NV + sv[s]) * r] - sdd[s] * acc;
     }
     __syncthreads();
     // rho = M b ; A_red = M A
@@ -960,7 +1023,9 @@ rom_status galerkin_step_t(rom_batch* h, hipStream_t s) {
 }
 
 size_t hr_shm() {
-  return sizeof(double) * (2 * kMaxR + kMaxNs + kMaxNs * kMaxR + kMaxR * (kMaxR + 1) + kMaxR);
+  constexpr int kJr = kMaxNs * 3 * 12;   // sampled Jacobian rows of the 12-variable model
+  constexpr int kAr = kMaxR * (kMaxR + 1);
+  return sizeof(double) * (2 * kMaxR + kMaxNs + kMaxR + kMaxNs * kMaxR + (kJr > kAr ? kJr : kAr));
 }
 
 rom_status hr_step(rom_batch* h, hipStream_t s) {
@@ -1027,12 +1092,13 @@ rom_status reconstruct_t(rom_batch* h, void* out, hipStream_t s) {
 
 rom_status rom_kernels_prepare() {
   const int big = 160 * 1024 - 1024;
+  const int hr = (int)hr_shm();   // beside the step's static LDS
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_rebuild<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_rebuild<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_step<BurgersModel<double>>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_step<EulerModel<double, false>>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_step<EulerModel<double, true>>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_step<ReactModel<double>>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_step<BurgersModel<double>>, hipFuncAttributeMaxDynamicSharedMemorySize, hr));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_step<EulerModel<double, false>>, hipFuncAttributeMaxDynamicSharedMemorySize, hr));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_step<EulerModel<double, true>>, hipFuncAttributeMaxDynamicSharedMemorySize, hr));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_step<ReactModel<double>>, hipFuncAttributeMaxDynamicSharedMemorySize, hr));
   return ROM_OK;
 }
 
