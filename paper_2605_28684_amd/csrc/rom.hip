@@ -396,9 +396,10 @@ __global__ void k_rom_finalize(int n_inst, const int32_t* active, uint32_t* flag
 }
 
 // ------------------------------------------------------------------ HR-LSPG step
+constexpr int kHrThreads = 512;   // one workgroup per instance
 // mesh_phi[b][s][o][w][k], o in {0,1,2} = cells c-1, c, c+1 of the sampled row's cell.
 template <class Mdl>
-__global__ __launch_bounds__(256) void k_hr_step(
+__global__ __launch_bounds__(kHrThreads) void k_hr_step(
     int r, int ns, const int64_t* __restrict__ cell_off, const double* __restrict__ phys, int nphys,
     const int32_t* __restrict__ P, const double* __restrict__ Mp, const double* __restrict__ mphi,
     const double* __restrict__ mqref, const double* __restrict__ dvar, double* __restrict__ a,
@@ -1032,7 +1033,7 @@ rom_status hr_step(rom_batch* h, hipStream_t s) {
   const int B = h->cfg.n_inst;
   auto go = [&](auto tag) -> rom_status {
     using M = typename decltype(tag)::type;
-    hipLaunchKernelGGL((k_hr_step<M>), dim3(B), dim3(256), hr_shm(), s, h->cfg.r, h->cfg.n_s,
+    hipLaunchKernelGGL((k_hr_step<M>), dim3(B), dim3(kHrThreads), hr_shm(), s, h->cfg.r, h->cfg.n_s,
                        h->d_cell_off, h->d_phys, h->cfg.n_phys, h->P, h->M, h->mesh_phi,
                        h->mesh_qref, h->d_var, h->a, h->cfg.dt, h->cfg.rom_tol, h->cfg.rom_max,
                        h->iters, h->flags);
