@@ -395,6 +395,59 @@ __global__ void k_rom_finalize(int n_inst, const int32_t* active, uint32_t* flag
   if (b < n_inst && active[b]) atomicOr(&flags[b], ROM_FLAG_ROM_NOCONV);
 }
 
+// Solves A x = b (n x n, n <= kMaxR, A row-major in LDS with leading dimension
+// ld) on the first wavefront of the block, with no barrier: lane i keeps row i
+// of [A | b] in registers.  Partial pivoting chooses rows without moving them
+// (the largest magnitude, lowest lane on ties); the elimination and the
+// multipliers are those of row-pivoted LU, and back-substitution reads each
+// column's pivot row by its lane.  x overwrites b; *ok is 0 if a pivot vanishes.
+// The caller synchronises the block afterwards.
+DEV void wave_lu_solve(const double* A, int ld, double* bvec, int n, int* ok) {
+  const int lane = threadIdx.x & 63;
+  double row[kMaxR + 1];   // columns beyond n stay zero and are updated harmlessly
+#pragma unroll
+  for (int c = 0; c < kMaxR; ++c) row[c] = (lane < n && c < n) ? A[lane * ld + c] : 0.0;
+  row[kMaxR] = lane < n ? bvec[lane] : 0.0;
+  bool used = lane >= n, good = true;
+  int pivl = 0;        // lane k: the pivot row (lane) of column k
+  double myr = 0.0;    // pivot rows: the reciprocal of their pivot
+#pragma unroll
+  for (int k = 0; k < kMaxR; ++k) {
+    if (k < n) {
+      const double a = row[k];
+      double key = used ? -1.0 : (isnan(a) ? (double)INFINITY : fabs(a));
+      int kl = lane;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ko = __shfl_xor(key, off);
+        const int lo = __shfl_xor(kl, off);
+        if (ko > key || (ko == key && lo < kl)) { key = ko; kl = lo; }
+      }
+      const int p = __builtin_amdgcn_readfirstlane(kl);
+      const double pk = readlane_d(a, p);
+      const double rp = pk != 0.0 ? 1.0 / pk : 0.0;
+      if (!(pk != 0.0)) good = false;
+      if (lane == k) pivl = p;
+      const double f = (used || lane == p) ? 0.0 : a * rp;
+      if (lane == p) { used = true; myr = rp; }
+#pragma unroll
+      for (int c = k + 1; c <= kMaxR; ++c) row[c] -= f * readlane_d(row[c], p);
+    }
+  }
+  double sh = 0.0, xm = 0.0;   // sh: sum over the solved columns of row * x
+#pragma unroll
+  for (int k = kMaxR - 1; k >= 0; --k) {
+    if (k < n) {
+      const int q = __builtin_amdgcn_readlane(pivl, k);
+      const double xk = readlane_d((row[kMaxR] - sh) * myr, q);
+      sh += row[k] * xk;
+      if (lane == k) xm = xk;
+    }
+  }
+  if (lane < n) bvec[lane] = xm;
+  if (lane == 0) *ok = good ? 1 : 0;
+}
+
 // ------------------------------------------------------------------ HR-LSPG step
 constexpr int kHrThreads = 512;   // one workgroup per instance
 // mesh_phi[b][s][o][w][k], o in {0,1,2} = cells c-1, c, c+1 of the sampled row's cell.
@@ -432,14 +485,40 @@ __global__ __launch_bounds__(kHrThreads) void k_hr_step(
   __syncthreads();
   int it = 0;
   for (; it < max_it; ++it) {
-    // stencil states q = q_ref + D^-1 Phi a of every sampled row, one entry per
-    // thread
-    for (int idx = tid; idx < ns * E3; idx += blockDim.x) {
-      const int s = idx / E3, e = idx - s * E3;
-      const double* Ph = mph + ((size_t)s * E3 + e) * r;
-      double acc = 0.0;
-      for (int k = 0; k < r; ++k) acc += Ph[k] * sa[k];
-      sq3[idx] = mqref[((size_t)b * ns + s) * E3 + e] + acc / dv[e % NV];
+    // stencil states q = q_ref + D^-1 Phi a of every sampled row: eight lanes per
+    // entry, each summing every eighth basis column, so that a wavefront reads
+    // eight rows of the stencil basis whole
+    {
+      // all of a lane's loads (at most kMaxR / 8 per entry, two entries) are
+      // issued before its sums
+      static_assert(kMaxR <= 64, "eight columns per lane");
+      const int l8 = tid & 7;
+      const int nq = ns * E3, step = blockDim.x >> 3;
+      for (int idx0 = tid >> 3; idx0 < nq; idx0 += 2 * step) {
+        double v[2][8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int idx = idx0 + h * step < nq ? idx0 + h * step : idx0;
+          const double* Ph = mph + (size_t)idx * r;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[h][u] = l8 + 8 * u < r ? Ph[l8 + 8 * u] : 0.0;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int idx = idx0 + h * step;
+          double acc = 0.0;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (l8 + 8 * u < r) acc += v[h][u] * sa[l8 + 8 * u];
+          acc += __shfl_xor(acc, 1, 8);
+          acc += __shfl_xor(acc, 2, 8);
+          acc += __shfl_xor(acc, 4, 8);
+          if (l8 == 0 && idx < nq) {
+            const int s = idx / E3, e = idx - s * E3;
+            sq3[idx] = mqref[((size_t)b * ns + s) * E3 + e] + acc / dv[e % NV];
+          }
+        }
+      }
     }
     __syncthreads();
     // sampled rows of P^T D r and of the Jacobian P^T D J_r D^-1 (one row per thread)
@@ -536,33 +615,68 @@ __global__ __launch_bounds__(kHrThreads) void k_hr_step(
     __syncthreads();
     // A_s = P^T Phi - dt P^T D J_r D^-1 Phi, one entry per thread (consecutive
     // threads take consecutive basis columns)
-    for (int idx = tid; idx < ns * r; idx += blockDim.x) {
-      const int s = idx / r, k = idx - s * r;
-      const double* Ph = mph + (size_t)s * E3 * r + k;
-      const double* jr = sjr + s * E3;
-      double acc = 0.0;
-      for (int w = 0; w < NV; ++w) {
-        acc += jr[w] * Ph[w * r];
-        acc += jr[NV + w] * Ph[(NV + w) * r];
-        acc += jr[2 * NV + w] * Ph[(2 * NV + w) * r];
+    for (int idx0 = tid; idx0 < ns * r; idx0 += 2 * blockDim.x) {
+      // two entries per thread, so that twice the loads are in flight
+      double acc[2] = {0.0, 0.0};
+      const double* Ph[2];
+      int sx[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int idx = idx0 + h * blockDim.x < ns * r ? idx0 + h * blockDim.x : idx0;
+        const int s = idx / r, k = idx - s * r;
+        sx[h] = s;
+        Ph[h] = mph + (size_t)s * E3 * r + k;
       }
-      As[s * kMaxR + k] = Ph[(NV + sv[s]) * r] - sdd[s] * acc;
+#pragma unroll
+      for (int w = 0; w < NV; ++w)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const double* jr = sjr + sx[h] * E3;
+          acc[h] += jr[w] * Ph[h][w * r];
+          acc[h] += jr[NV + w] * Ph[h][(NV + w) * r];
+          acc[h] += jr[2 * NV + w] * Ph[h][(2 * NV + w) * r];
+        }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int idx = idx0 + h * blockDim.x;
+        if (idx < ns * r) {
+          const int s = sx[h], k = idx - s * r;
+          As[s * kMaxR + k] = Ph[h][(NV + sv[s]) * r] - sdd[s] * acc[h];
+        }
+      }
     }
     __syncthreads();
-    // rho = M b ; A_red = M A
-    for (int e = tid; e < r * r; e += blockDim.x) {
-      const int i = e / r, k = e % r;
-      double acc = 0.0;
-      for (int s = 0; s < ns; ++s) acc += Mb[i * ns + s] * As[s * kMaxR + k];
-      Ar[i * (r + 1) + k] = acc;
-    }
-    for (int i = tid; i < r; i += blockDim.x) {
-      double acc = 0.0;
-      for (int s = 0; s < ns; ++s) acc += Mb[i * ns + s] * bs[s];
-      rh[i] = -acc;
+    // rho = M b ; A_red = M A: eight threads per row of M, each summing eight
+    // columns of A_s (and rho) over the samples in order
+    for (int e = tid; e < r * 8; e += blockDim.x) {
+      const int i = e >> 3, k0 = e & 7;
+      const double* Mi = Mb + (size_t)i * ns;
+      double acc[8], accb = 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+      for (int s0 = 0; s0 < ns; s0 += 16) {
+        double mv[16];   // sixteen loads of M in flight
+#pragma unroll
+        for (int j = 0; j < 16; ++j) mv[j] = s0 + j < ns ? Mi[s0 + j] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          if (s0 + j < ns) {
+            const double* Arow = As + (s0 + j) * kMaxR + k0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (k0 + 8 * u < r) acc[u] += mv[j] * Arow[8 * u];
+            accb += mv[j] * bs[s0 + j];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + 8 * u < r) Ar[i * (r + 1) + k0 + 8 * u] = acc[u];
+      if (k0 == 0) rh[i] = -accb;
     }
     __syncthreads();
-    lu_solve_block(Ar, r + 1, rh, r, &ok);
+    if (tid < 64) wave_lu_solve(Ar, r + 1, rh, r, &ok);
+    __syncthreads();
     if (tid == 0) {
       double dm = 0.0, am = 0.0;
       bool fin = true;
