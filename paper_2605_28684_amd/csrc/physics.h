@@ -375,38 +375,52 @@ struct ReactModel {
         if (w == v) ds[w] -= kin;
     }
   }
-  // S and dS/dq (row-major 12 x 12)
+  // S and dS/dq (row-major 12 x 12).  Reaction j adds g_j w_j to S and the outer
+  // product g_j h_j to dS/dq, with g_j the stoichiometric column (-1 at the two
+  // reactants, +1 at the two products, Q_j at the temperature) and h_j = dw_j/dq
+  // (nonzero at the two reactants and the temperature); both are formed with
+  // constant indices so that S and dS/dq stay in registers.
   DEV void source_jac(const T* q, double x, T* S, T* DS, unsigned& fl) const {
     const T A = T(ph[2]);
     const T Tc = q[10];
     if (Tc < T(kTFloor)) fl |= ROM_FLAG_FLOOR;
     const bool live = Tc >= T(kTFloor);
     const T Tf = live ? Tc : T(kTFloor);
+#pragma unroll
     for (int v = 0; v < 12; ++v) S[v] = T(0);
+#pragma unroll
     for (int i = 0; i < 144; ++i) DS[i] = T(0);
     for (int j = 0; j < 12; ++j) {
       const int ia = int(ph[16 + j]), ib = int(ph[28 + j]), ic = int(ph[40 + j]), id = int(ph[52 + j]);
       const T E = T(ph[64 + j]);
       const T k = A * dexp(-E / Tf);
-      const T w = k * q[ia] * q[ib];
-      const T dwa = k * q[ib], dwb = k * q[ia];
-      const T dwT = live ? w * E / (Tf * Tf) : T(0);
-      const int rows[4] = {ia, ib, ic, id};
-      const T sg[4] = {T(-1), T(-1), T(1), T(1)};
-      for (int m = 0; m < 4; ++m) {
-        S[rows[m]] += sg[m] * w;
-        DS[rows[m] * 12 + ia] += sg[m] * dwa;
-        DS[rows[m] * 12 + ib] += sg[m] * dwb;
-        DS[rows[m] * 12 + 10] += sg[m] * dwT;
+      T qa = T(0), qb = T(0);
+#pragma unroll
+      for (int v = 0; v < 12; ++v) {
+        if (v == ia) qa = q[v];
+        if (v == ib) qb = q[v];
       }
+      const T w = k * qa * qb;
+      const T dwa = k * qb, dwb = k * qa;
+      const T dwT = live ? w * E / (Tf * Tf) : T(0);
       const T Qj = T(ph[76 + j]);
-      S[10] += Qj * w;
-      DS[10 * 12 + ia] += Qj * dwa;
-      DS[10 * 12 + ib] += Qj * dwb;
-      DS[10 * 12 + 10] += Qj * dwT;
+      T g[12], hc[12];
+#pragma unroll
+      for (int v = 0; v < 12; ++v) {
+        g[v] = (v == ia ? T(-1) : T(0)) + (v == ib ? T(-1) : T(0)) + (v == ic ? T(1) : T(0)) +
+               (v == id ? T(1) : T(0)) + (v == 10 ? Qj : T(0));
+        hc[v] = (v == ia ? dwa : T(0)) + (v == ib ? dwb : T(0)) + (v == 10 ? dwT : T(0));
+      }
+#pragma unroll
+      for (int v = 0; v < 12; ++v) {
+        S[v] += g[v] * w;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) DS[v * 12 + c] += g[v] * hc[c];
+      }
     }
     if (x < ph[4]) {
       const T kin = T(ph[3]);
+#pragma unroll
       for (int l = 0; l < 10; ++l) {
         S[l] += kin * (T(ph[6 + l]) - q[l]);
         DS[l * 12 + l] -= kin;
