@@ -92,6 +92,34 @@ def test_fom_step_parity(problem, precision):
 
 
 @pytest.mark.parametrize("precision", [W.F64, W.F32])
+def test_react_fom_step_ragged_parts(precision):
+    """The 12 x 12 factorisation by 16-lane groups (8-cell parts) on ragged part
+    layouts: a last part that is a lone separator (97 = 12 x 8 + 1, then a level
+    of 13 cells, then 2), a two-part instance (9 cells: 8 + 1) and an instance of
+    one 5-cell part, against the oracle's Newton with a sparse direct solve."""
+    import gpu_common as G
+    import torch
+    cells = [97, 9, 5, 130]
+    w = _workload(W.REACT, cells, precision)
+    w.newton_tol = 1e-10 if precision == W.F64 else 1e-5
+    h = _handle(w)
+    q = G.rounded(W.random_state(W.REACT, cells, seed=13, scale=0.5), precision)
+    dt = _step_dt(W.REACT)
+    it = torch.zeros(w.n_inst, dtype=torch.int32, device="cuda")
+    q1 = G.host(h.fom_step(G.to_dev(q, precision), dt, iters=it))
+    its = it.cpu().numpy()
+    off = w.offsets()
+    for b in range(w.n_inst):
+        ref, n_ref, ok = F.newton_be_step(W.REACT, q[off[b]:off[b + 1]], dt, w.phys[b],
+                                          tol=w.newton_tol, max_it=10)
+        assert ok
+        assert abs(int(its[b]) - n_ref) <= (0 if precision == W.F64 else 1), (b, its[b], n_ref)
+        err = G.relerr(q1[off[b]:off[b + 1]], ref)
+        assert err < (1e-11 if precision == W.F64 else 1e-5), (b, err)
+    assert not (h.status() & 1).any()
+
+
+@pytest.mark.parametrize("precision", [W.F64, W.F32])
 @pytest.mark.parametrize("path", ["block", "grid"])
 def test_burgers_fom_step_block_and_grid_paths(path, precision):
     """Scalar periodic steps run one workgroup per instance while every instance
