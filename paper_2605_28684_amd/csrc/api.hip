@@ -151,7 +151,7 @@ void free_all(rom_batch* h) {
                 h->Phi, h->sigma, h->a, h->a_prev, h->q_ref, h->d_var, h->y_corr, h->flags, h->P,
                 h->M, h->mesh_phi, h->mesh_qref, h->chosen, h->part, h->red, h->ubar, h->lmat,
                 h->active, h->iters, h->norms, h->rstate, h->qtmp, h->mpart, h->fq, h->fq_prev, h->vjp_tmp,
-                h->d_epoch, h->rvjp, h->epart, h->ev_iters, h->phi_cm, h->Phi_alt};
+                h->d_epoch, h->rvjp, h->epart, h->ev_iters, h->phi_cm, h->Phi_alt, h->hr_as, h->hr_cnt};
   for (void* p : ps) (void)hipFree(p);
   bt_free(h);
   for (auto& g : h->win_exec) if (g) (void)hipGraphExecDestroy(g);
@@ -250,6 +250,11 @@ rom_status setup(rom_batch* h) {
   ROM_TRY(alloc(&h->mesh_qref, (size_t)B * ns * 3 * h->nv));
   ROM_TRY(alloc(&h->chosen, (size_t)td));
   if (c.hyper == ROM_HR_DEIM) ROM_TRY(alloc((char**)&h->phi_cm, es * td * r));
+  if (c.hyper == ROM_HR_DEIM) ROM_TRY(alloc(&h->hr_as, (size_t)B * (ns + r) * (r + 1)));
+  if (c.hyper == ROM_HR_DEIM) {
+    ROM_TRY(alloc(&h->hr_cnt, (size_t)B));
+    ROM_HIP_CHECK(hipMemset(h->hr_cnt, 0, sizeof(int32_t) * B));
+  }
   ROM_TRY(alloc(&h->part, (size_t)std::max(h->n_ptiles, 1) * kMaxR * kMaxR));
   ROM_TRY(alloc(&h->red, (size_t)B * (2 * 128 + 8)));
   ROM_TRY(alloc(&h->ubar, (size_t)B * (r + 1) * (r + 1)));

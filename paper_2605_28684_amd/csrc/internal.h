@@ -116,6 +116,8 @@ struct rom_batch {
   double* mesh_qref = nullptr; // [n_inst * n_s * 3 * nv]
   uint32_t* chosen = nullptr;  // [total_dof] epoch marks for DEIM
   void* phi_cm = nullptr;      // T[total_dof * r]: Phi by columns per instance (DEIM only)
+  double* hr_as = nullptr;     // [n_inst * (n_s + r) * (r + 1)]: rows of [A_s | b], then [M A_s | -M b] (DEIM only)
+  int32_t* hr_cnt = nullptr;   // [n_inst]: arrival counters of the HR reduction blocks (zero between launches)
   uint32_t deim_epoch = 0;
 
   // iSVD workspace

@@ -402,17 +402,20 @@ __global__ void k_rom_finalize(int n_inst, const int32_t* active, uint32_t* flag
 // multipliers are those of row-pivoted LU, and back-substitution reads each
 // column's pivot row by its lane.  x overwrites b; *ok is 0 if a pivot vanishes.
 // The caller synchronises the block afterwards.
+// NM >= n bounds the columns kept per lane (a multiple of 16 up to kMaxR).
+template <int NM>
 DEV void wave_lu_solve(const double* A, int ld, double* bvec, int n, int* ok) {
+  static_assert(NM <= kMaxR && NM <= 64, "one row per lane");
   const int lane = threadIdx.x & 63;
-  double row[kMaxR + 1];   // columns beyond n stay zero and are updated harmlessly
+  double row[NM + 1];   // columns beyond n stay zero and are updated harmlessly
 #pragma unroll
-  for (int c = 0; c < kMaxR; ++c) row[c] = (lane < n && c < n) ? A[lane * ld + c] : 0.0;
-  row[kMaxR] = lane < n ? bvec[lane] : 0.0;
+  for (int c = 0; c < NM; ++c) row[c] = (lane < n && c < n) ? A[lane * ld + c] : 0.0;
+  row[NM] = lane < n ? bvec[lane] : 0.0;
   bool used = lane >= n, good = true;
   int pivl = 0;        // lane k: the pivot row (lane) of column k
   double myr = 0.0;    // pivot rows: the reciprocal of their pivot
 #pragma unroll
-  for (int k = 0; k < kMaxR; ++k) {
+  for (int k = 0; k < NM; ++k) {
     if (k < n) {
       const double a = row[k];
       double key = used ? -1.0 : (isnan(a) ? (double)INFINITY : fabs(a));
@@ -431,15 +434,15 @@ DEV void wave_lu_solve(const double* A, int ld, double* bvec, int n, int* ok) {
       const double f = (used || lane == p) ? 0.0 : a * rp;
       if (lane == p) { used = true; myr = rp; }
 #pragma unroll
-      for (int c = k + 1; c <= kMaxR; ++c) row[c] -= f * readlane_d(row[c], p);
+      for (int c = k + 1; c <= NM; ++c) row[c] -= f * readlane_d(row[c], p);
     }
   }
   double sh = 0.0, xm = 0.0;   // sh: sum over the solved columns of row * x
 #pragma unroll
-  for (int k = kMaxR - 1; k >= 0; --k) {
+  for (int k = NM - 1; k >= 0; --k) {
     if (k < n) {
       const int q = __builtin_amdgcn_readlane(pivl, k);
-      const double xk = readlane_d((row[kMaxR] - sh) * myr, q);
+      const double xk = readlane_d((row[NM] - sh) * myr, q);
       sh += row[k] * xk;
       if (lane == k) xm = xk;
     }
@@ -449,256 +452,302 @@ DEV void wave_lu_solve(const double* A, int ld, double* bvec, int n, int* ok) {
 }
 
 // ------------------------------------------------------------------ HR-LSPG step
-constexpr int kHrThreads = 512;   // one workgroup per instance
+// One Gauss-Newton iteration is two launches: k_hr_eval spreads the sampled
+// rows of every instance over blocks of kHrRows rows (stencil states, the
+// sampled Jacobian rows, the rows of A_s and b); k_hr_reduce_solve forms M A_s
+// and M b over blocks of rows of M, and the last block of each instance solves
+// its r x r system on one wavefront and updates a.  Instances that have
+// converged skip both.
+constexpr int kHrRows = 8;            // sampled rows per evaluation block
+constexpr int kHrEvalThreads = 128;
 // mesh_phi[b][s][o][w][k], o in {0,1,2} = cells c-1, c, c+1 of the sampled row's cell.
+// hr_as[b][s][0..r) = row s of A_s, hr_as[b][s][r] = b_s.
 template <class Mdl>
-__global__ __launch_bounds__(kHrThreads) void k_hr_step(
-    int r, int ns, const int64_t* __restrict__ cell_off, const double* __restrict__ phys, int nphys,
-    const int32_t* __restrict__ P, const double* __restrict__ Mp, const double* __restrict__ mphi,
-    const double* __restrict__ mqref, const double* __restrict__ dvar, double* __restrict__ a,
-    double dt, double tol, int max_it, int32_t* __restrict__ iters, uint32_t* flags) {
+__global__ __launch_bounds__(kHrEvalThreads) void k_hr_eval(
+    int r, int ns, int gpi, const int64_t* __restrict__ cell_off, const double* __restrict__ phys,
+    int nphys, const int32_t* __restrict__ P, const double* __restrict__ mphi,
+    const double* __restrict__ mqref, const double* __restrict__ dvar, const double* __restrict__ a,
+    const double* __restrict__ a_prev, double dt, const int32_t* __restrict__ active,
+    double* __restrict__ hr_as, uint32_t* flags) {
   constexpr int NV = Mdl::NV;
   constexpr int NN = NV * NV;
   constexpr int E3 = 3 * NV;       // entries of a sampled row's three-cell stencil
-  static_assert(E3 <= kMaxR, "the stencil states share the A_s buffer");
-  extern __shared__ double sm[];
-  double* sa = sm;                 // r
-  double* sap = sa + kMaxR;        // r
-  double* bs = sap + kMaxR;        // ns
-  double* rh = bs + kMaxNs;        // r
-  double* As = rh + kMaxR;         // ns x r (leading dimension kMaxR); first the stencil states
-  double* sq3 = As;                // ns x E3: reconstructed states of the sampled stencils
-  double* Ar = As + kMaxNs * kMaxR;  // r x r, leading dimension r + 1
-  double* sjr = Ar;                // ns x E3: sampled Jacobian rows scaled by 1 / d (before Ar)
-  __shared__ int sv[kMaxNs];       // variable of each sampled row
-  __shared__ double sdd[kMaxNs];   // dt d_v of each sampled row
-  __shared__ int ok, stop;
+  static_assert(kMaxR <= 64, "eight columns per lane");
+  __shared__ double sa[kMaxR], sap[kMaxR];
+  __shared__ double sq3[kHrRows * E3];   // reconstructed states of the block's stencils
+  __shared__ double sjr[kHrRows * E3];   // sampled Jacobian rows scaled by 1 / d
+  __shared__ int sv[kHrRows];            // variable of each sampled row
+  __shared__ double sdd[kHrRows];        // dt d_v of each sampled row
   __shared__ unsigned flacc;
-  const int b = blockIdx.x, tid = threadIdx.x;
+  const int b = blockIdx.x / gpi, g = blockIdx.x - b * gpi, tid = threadIdx.x;
+  if (!active[b]) return;
+  const int s0 = g * kHrRows;
+  const int nr = ns - s0 < kHrRows ? ns - s0 : kHrRows;
   const int64_t n = cell_off[b + 1] - cell_off[b];
   Mdl m(phys + (size_t)b * nphys);
   const double* dv = dvar + (size_t)b * NV;
-  const double* Mb = Mp + (size_t)b * r * ns;
-  const double* mph = mphi + (size_t)b * ns * E3 * r;
-  for (int c = tid; c < r; c += blockDim.x) { sa[c] = a[(size_t)b * r + c]; sap[c] = sa[c]; }
-  if (tid == 0) { stop = 0; flacc = 0; }
+  const double* mph = mphi + ((size_t)b * ns + s0) * E3 * r;   // the block's stencil rows
+  double* out = hr_as + ((size_t)b * ns + s0) * (r + 1);
+  for (int c = tid; c < r; c += blockDim.x) {
+    sa[c] = a[(size_t)b * r + c];
+    sap[c] = a_prev[(size_t)b * r + c];
+  }
+  if (tid == 0) flacc = 0;
   __syncthreads();
-  int it = 0;
-  for (; it < max_it; ++it) {
-    // stencil states q = q_ref + D^-1 Phi a of every sampled row: eight lanes per
-    // entry, each summing every eighth basis column, so that a wavefront reads
-    // eight rows of the stencil basis whole
-    {
-      // all of a lane's loads (at most kMaxR / 8 per entry, two entries) are
-      // issued before its sums
-      static_assert(kMaxR <= 64, "eight columns per lane");
-      const int l8 = tid & 7;
-      const int nq = ns * E3, step = blockDim.x >> 3;
-      for (int idx0 = tid >> 3; idx0 < nq; idx0 += 2 * step) {
-        double v[2][8];
+  // stencil states q = q_ref + D^-1 Phi a: eight lanes per entry, each summing
+  // every eighth basis column; all of a lane's loads (at most eight per entry,
+  // two entries) are issued before its sums
+  {
+    const int l8 = tid & 7;
+    const int nq = nr * E3, step = blockDim.x >> 3;
+    for (int idx0 = tid >> 3; idx0 < nq; idx0 += 2 * step) {
+      double v[2][8];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int idx = idx0 + h * step < nq ? idx0 + h * step : idx0;
-          const double* Ph = mph + (size_t)idx * r;
+      for (int h = 0; h < 2; ++h) {
+        const int idx = idx0 + h * step < nq ? idx0 + h * step : idx0;
+        const double* Ph = mph + (size_t)idx * r;
 #pragma unroll
-          for (int u = 0; u < 8; ++u) v[h][u] = l8 + 8 * u < r ? Ph[l8 + 8 * u] : 0.0;
-        }
+        for (int u = 0; u < 8; ++u) v[h][u] = l8 + 8 * u < r ? Ph[l8 + 8 * u] : 0.0;
+      }
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int idx = idx0 + h * step;
-          double acc = 0.0;
+      for (int h = 0; h < 2; ++h) {
+        const int idx = idx0 + h * step;
+        double acc = 0.0;
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (l8 + 8 * u < r) acc += v[h][u] * sa[l8 + 8 * u];
-          acc += __shfl_xor(acc, 1, 8);
-          acc += __shfl_xor(acc, 2, 8);
-          acc += __shfl_xor(acc, 4, 8);
-          if (l8 == 0 && idx < nq) {
-            const int s = idx / E3, e = idx - s * E3;
-            sq3[idx] = mqref[((size_t)b * ns + s) * E3 + e] + acc / dv[e % NV];
-          }
+        for (int u = 0; u < 8; ++u)
+          if (l8 + 8 * u < r) acc += v[h][u] * sa[l8 + 8 * u];
+        acc += __shfl_xor(acc, 1, 8);
+        acc += __shfl_xor(acc, 2, 8);
+        acc += __shfl_xor(acc, 4, 8);
+        if (l8 == 0 && idx < nq) {
+          const int s = idx / E3, e = idx - s * E3;
+          sq3[idx] = mqref[((size_t)b * ns + s0 + s) * E3 + e] + acc / dv[e % NV];
         }
       }
     }
-    __syncthreads();
-    // sampled rows of P^T D r and of the Jacobian P^T D J_r D^-1 (one row per thread)
-    for (int s = tid; s < ns; s += blockDim.x) {
-      const int p = P[(size_t)b * ns + s];
-      const int64_t c = p / NV;
-      const int v = p % NV;
-      const double* Ph = mph + (size_t)s * E3 * r;
-      const bool lw = !Mdl::periodic && c == 0, rw = !Mdl::periodic && c == n - 1;
-      const double inv = (double)n, inv2 = (double)n * (double)n;
-      double fv, jm[NV], j0[NV], jp[NV];   // f_v and row v of the three Jacobian blocks
-      unsigned fl = 0;
-      if constexpr (NV >= 8) {
-        // large blocks: only row v is formed (the model's row methods), reading
-        // the stencil states from LDS
-        const double* q3 = sq3 + s * E3;
-        double hl, hr, dll[NV], drl[NV], dlr[NV], drr[NV];
-        m.face_jac_row(&q3[0], &q3[NV], v, hl, dll, drl);
-        m.face_jac_row(&q3[NV], &q3[2 * NV], v, hr, dlr, drr);
-        fv = -(hr - hl) * inv;
-        for (int w = 0; w < NV; ++w) {
-          jm[w] = dll[w] * inv; j0[w] = (drl[w] - dlr[w]) * inv; jp[w] = -drr[w] * inv;
+  }
+  __syncthreads();
+  // sampled rows of P^T D r and of the Jacobian P^T D J_r D^-1 (one row per thread)
+  for (int s = tid; s < nr; s += blockDim.x) {
+    const double* Ph = mph + (size_t)s * E3 * r;
+    const int p = P[(size_t)b * ns + s0 + s];
+    const int64_t c = p / NV;
+    const int v = p % NV;
+    const bool lw = !Mdl::periodic && c == 0, rw = !Mdl::periodic && c == n - 1;
+    const double inv = (double)n, inv2 = (double)n * (double)n;
+    double fv, jm[NV], j0[NV], jp[NV];   // f_v and row v of the three Jacobian blocks
+    unsigned fl = 0;
+    if constexpr (NV >= 8) {
+      // large blocks: only row v is formed (the model's row methods), reading
+      // the stencil states from LDS
+      const double* q3 = sq3 + s * E3;
+      double hl, hr, dll[NV], drl[NV], dlr[NV], drr[NV];
+      m.face_jac_row(&q3[0], &q3[NV], v, hl, dll, drl);
+      m.face_jac_row(&q3[NV], &q3[2 * NV], v, hr, dlr, drr);
+      fv = -(hr - hl) * inv;
+      for (int w = 0; w < NV; ++w) {
+        jm[w] = dll[w] * inv; j0[w] = (drl[w] - dlr[w]) * inv; jp[w] = -drr[w] * inv;
+      }
+      if (lw) for (int w = 0; w < NV; ++w) { j0[w] += jm[w]; jm[w] = 0.0; }
+      if (rw) for (int w = 0; w < NV; ++w) { j0[w] += jp[w]; jp[w] = 0.0; }
+      const double kap = m.kappa(v);
+      if (kap != 0.0) {
+        fv += kap * ((q3[2 * NV + v] - q3[NV + v]) - (q3[NV + v] - q3[v])) * inv2;
+        const double cc = kap * inv2;
+        for (int w = 0; w < NV; ++w)
+          if (w == v) {
+            jm[w] += lw ? 0.0 : cc;
+            jp[w] += rw ? 0.0 : cc;
+            j0[w] += -2.0 * cc + (lw ? cc : 0.0) + (rw ? cc : 0.0);
+          }
+      }
+      if (Mdl::has_source) {
+        double sv_, ds[NV];
+        m.source_jac_row(&q3[NV], ((double)c + 0.5) / (double)n, v, sv_, ds, fl);
+        fv += sv_;
+        for (int w = 0; w < NV; ++w) j0[w] += ds[w];
+      }
+    } else {
+      double q3[E3];
+      for (int e = 0; e < E3; ++e) q3[e] = sq3[s * E3 + e];
+      double f[NV], Jm[NN], J0[NN], Jp[NN];
+      {
+        // cell_jacobian for one cell (FP64), inlined to avoid a cross-file template
+        double HL[NV], HR[NV], DLl[NN], DRl[NN], DLr[NN], DRr[NN];
+        m.face_jac(&q3[0], &q3[NV], HL, DLl, DRl, fl);
+        m.face_jac(&q3[NV], &q3[2 * NV], HR, DLr, DRr, fl);
+        for (int w = 0; w < NV; ++w) f[w] = -(HR[w] - HL[w]) * inv;
+        for (int e = 0; e < NN; ++e) {
+          Jm[e] = DLl[e] * inv; J0[e] = (DRl[e] - DLr[e]) * inv; Jp[e] = -DRr[e] * inv;
         }
-        if (lw) for (int w = 0; w < NV; ++w) { j0[w] += jm[w]; jm[w] = 0.0; }
-        if (rw) for (int w = 0; w < NV; ++w) { j0[w] += jp[w]; jp[w] = 0.0; }
-        const double kap = m.kappa(v);
-        if (kap != 0.0) {
-          fv += kap * ((q3[2 * NV + v] - q3[NV + v]) - (q3[NV + v] - q3[v])) * inv2;
-          const double cc = kap * inv2;
-          for (int w = 0; w < NV; ++w)
-            if (w == v) {
-              jm[w] += lw ? 0.0 : cc;
-              jp[w] += rw ? 0.0 : cc;
-              j0[w] += -2.0 * cc + (lw ? cc : 0.0) + (rw ? cc : 0.0);
-            }
+        if (lw) for (int e = 0; e < NN; ++e) { J0[e] += Jm[e]; Jm[e] = 0.0; }
+        if (rw) for (int e = 0; e < NN; ++e) { J0[e] += Jp[e]; Jp[e] = 0.0; }
+        for (int w = 0; w < NV; ++w) {
+          const double kap = m.kappa(w);
+          if (kap != 0.0) {
+            f[w] += kap * ((q3[2 * NV + w] - q3[NV + w]) - (q3[NV + w] - q3[w])) * inv2;
+            const double cc = kap * inv2;
+            Jm[w * NV + w] += lw ? 0.0 : cc;
+            Jp[w * NV + w] += rw ? 0.0 : cc;
+            J0[w * NV + w] += -2.0 * cc + (lw ? cc : 0.0) + (rw ? cc : 0.0);
+          }
         }
         if (Mdl::has_source) {
-          double sv_, ds[NV];
-          m.source_jac_row(&q3[NV], ((double)c + 0.5) / (double)n, v, sv_, ds, fl);
-          fv += sv_;
-          for (int w = 0; w < NV; ++w) j0[w] += ds[w];
-        }
-      } else {
-        double q3[E3];
-        for (int e = 0; e < E3; ++e) q3[e] = sq3[s * E3 + e];
-        double f[NV], Jm[NN], J0[NN], Jp[NN];
-        {
-          // cell_jacobian for one cell (FP64), inlined to avoid a cross-file template
-          double HL[NV], HR[NV], DLl[NN], DRl[NN], DLr[NN], DRr[NN];
-          m.face_jac(&q3[0], &q3[NV], HL, DLl, DRl, fl);
-          m.face_jac(&q3[NV], &q3[2 * NV], HR, DLr, DRr, fl);
-          for (int w = 0; w < NV; ++w) f[w] = -(HR[w] - HL[w]) * inv;
-          for (int e = 0; e < NN; ++e) {
-            Jm[e] = DLl[e] * inv; J0[e] = (DRl[e] - DLr[e]) * inv; Jp[e] = -DRr[e] * inv;
-          }
-          if (lw) for (int e = 0; e < NN; ++e) { J0[e] += Jm[e]; Jm[e] = 0.0; }
-          if (rw) for (int e = 0; e < NN; ++e) { J0[e] += Jp[e]; Jp[e] = 0.0; }
-          for (int w = 0; w < NV; ++w) {
-            const double kap = m.kappa(w);
-            if (kap != 0.0) {
-              f[w] += kap * ((q3[2 * NV + w] - q3[NV + w]) - (q3[NV + w] - q3[w])) * inv2;
-              const double cc = kap * inv2;
-              Jm[w * NV + w] += lw ? 0.0 : cc;
-              Jp[w * NV + w] += rw ? 0.0 : cc;
-              J0[w * NV + w] += -2.0 * cc + (lw ? cc : 0.0) + (rw ? cc : 0.0);
-            }
-          }
-          if (Mdl::has_source) {
-            double S[NV], DS[NN];
-            m.source_jac(&q3[NV], ((double)c + 0.5) / (double)n, S, DS, fl);
-            for (int w = 0; w < NV; ++w) f[w] += S[w];
-            for (int e = 0; e < NN; ++e) J0[e] += DS[e];
-          }
-        }
-        fv = f[v];
-        for (int w = 0; w < NV; ++w) {
-          jm[w] = Jm[v * NV + w]; j0[w] = J0[v * NV + w]; jp[w] = Jp[v * NV + w];
+          double S[NV], DS[NN];
+          m.source_jac(&q3[NV], ((double)c + 0.5) / (double)n, S, DS, fl);
+          for (int w = 0; w < NV; ++w) f[w] += S[w];
+          for (int e = 0; e < NN; ++e) J0[e] += DS[e];
         }
       }
-      if (fl) atomicOr(&flacc, fl);
-      const double dp = dv[v];
-      double bsum = 0.0;
-      for (int k = 0; k < r; ++k) bsum += Ph[(NV + v) * r + k] * (sa[k] - sap[k]);
-      bs[s] = bsum - dt * dp * fv;
+      fv = f[v];
       for (int w = 0; w < NV; ++w) {
-        const double id = 1.0 / dv[w];
-        sjr[s * E3 + w] = jm[w] * id;
-        sjr[s * E3 + NV + w] = j0[w] * id;
-        sjr[s * E3 + 2 * NV + w] = jp[w] * id;
-      }
-      sv[s] = v;
-      sdd[s] = dt * dp;
-    }
-    __syncthreads();
-    // A_s = P^T Phi - dt P^T D J_r D^-1 Phi, one entry per thread (consecutive
-    // threads take consecutive basis columns)
-    for (int idx0 = tid; idx0 < ns * r; idx0 += 2 * blockDim.x) {
-      // two entries per thread, so that twice the loads are in flight
-      double acc[2] = {0.0, 0.0};
-      const double* Ph[2];
-      int sx[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int idx = idx0 + h * blockDim.x < ns * r ? idx0 + h * blockDim.x : idx0;
-        const int s = idx / r, k = idx - s * r;
-        sx[h] = s;
-        Ph[h] = mph + (size_t)s * E3 * r + k;
-      }
-#pragma unroll
-      for (int w = 0; w < NV; ++w)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const double* jr = sjr + sx[h] * E3;
-          acc[h] += jr[w] * Ph[h][w * r];
-          acc[h] += jr[NV + w] * Ph[h][(NV + w) * r];
-          acc[h] += jr[2 * NV + w] * Ph[h][(2 * NV + w) * r];
-        }
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int idx = idx0 + h * blockDim.x;
-        if (idx < ns * r) {
-          const int s = sx[h], k = idx - s * r;
-          As[s * kMaxR + k] = Ph[h][(NV + sv[s]) * r] - sdd[s] * acc[h];
-        }
+        jm[w] = Jm[v * NV + w]; j0[w] = J0[v * NV + w]; jp[w] = Jp[v * NV + w];
       }
     }
-    __syncthreads();
-    // rho = M b ; A_red = M A: eight threads per row of M, each summing eight
-    // columns of A_s (and rho) over the samples in order
-    for (int e = tid; e < r * 8; e += blockDim.x) {
-      const int i = e >> 3, k0 = e & 7;
-      const double* Mi = Mb + (size_t)i * ns;
-      double acc[8], accb = 0.0;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-      for (int s0 = 0; s0 < ns; s0 += 16) {
-        double mv[16];   // sixteen loads of M in flight
-#pragma unroll
-        for (int j = 0; j < 16; ++j) mv[j] = s0 + j < ns ? Mi[s0 + j] : 0.0;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          if (s0 + j < ns) {
-            const double* Arow = As + (s0 + j) * kMaxR + k0;
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-              if (k0 + 8 * u < r) acc[u] += mv[j] * Arow[8 * u];
-            accb += mv[j] * bs[s0 + j];
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (k0 + 8 * u < r) Ar[i * (r + 1) + k0 + 8 * u] = acc[u];
-      if (k0 == 0) rh[i] = -accb;
+    if (fl) atomicOr(&flacc, fl);
+    const double dp = dv[v];
+    double bsum = 0.0;
+    for (int k = 0; k < r; ++k) bsum += Ph[(NV + v) * r + k] * (sa[k] - sap[k]);
+    out[(size_t)s * (r + 1) + r] = bsum - dt * dp * fv;
+    for (int w = 0; w < NV; ++w) {
+      const double id = 1.0 / dv[w];
+      sjr[s * E3 + w] = jm[w] * id;
+      sjr[s * E3 + NV + w] = j0[w] * id;
+      sjr[s * E3 + 2 * NV + w] = jp[w] * id;
     }
-    __syncthreads();
-    if (tid < 64) wave_lu_solve(Ar, r + 1, rh, r, &ok);
-    __syncthreads();
-    if (tid == 0) {
-      double dm = 0.0, am = 0.0;
-      bool fin = true;
-      for (int c = 0; c < r; ++c) {
-        sa[c] += rh[c];
-        dm = fmax(dm, fabs(rh[c]));
-        am = fmax(am, fabs(sa[c]));
-        fin = fin && isfinite(sa[c]);
-      }
-      if (!ok) flacc |= ROM_FLAG_SINGULAR;
-      if (!fin) flacc |= ROM_FLAG_NONFINITE;
-      stop = (dm <= tol * (1.0 + am) || !fin) ? 1 : 0;
-    }
-    __syncthreads();
-    if (stop) { ++it; break; }
+    sv[s] = v;
+    sdd[s] = dt * dp;
   }
-  for (int c = tid; c < r; c += blockDim.x) a[(size_t)b * r + c] = sa[c];
-  if (tid == 0) {
-    iters[b] = it;
-    unsigned fl = flacc;
-    if (!stop) fl |= ROM_FLAG_ROM_NOCONV;
+  __syncthreads();
+  // rows of A_s = P^T Phi - dt P^T D J_r D^-1 Phi, one entry per thread
+  // (consecutive threads take consecutive basis columns), two per thread
+  for (int idx0 = tid; idx0 < nr * r; idx0 += 2 * blockDim.x) {
+    double acc[2] = {0.0, 0.0};
+    const double* Ph[2];
+    int sx[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int idx = idx0 + h * blockDim.x < nr * r ? idx0 + h * blockDim.x : idx0;
+      const int s = idx / r, k = idx - s * r;
+      sx[h] = s;
+      Ph[h] = mph + (size_t)s * E3 * r + k;
+    }
+#pragma unroll
+    for (int w = 0; w < NV; ++w)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double* jr = sjr + sx[h] * E3;
+        acc[h] += jr[w] * Ph[h][w * r];
+        acc[h] += jr[NV + w] * Ph[h][(NV + w) * r];
+        acc[h] += jr[2 * NV + w] * Ph[h][(2 * NV + w) * r];
+      }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int idx = idx0 + h * blockDim.x;
+      if (idx < nr * r) {
+        const int s = sx[h], k = idx - s * r;
+        out[(size_t)s * (r + 1) + k] = Ph[h][(NV + sv[s]) * r] - sdd[s] * acc[h];
+      }
+    }
+  }
+  if (tid == 0 && flacc) atomicOr(&flags[b], flacc);
+}
+
+// A_red = M A_s and rho = -M b, then the r x r solve and the update of a.  One
+// block per instance and group of kHrRedRows rows of M, one thread per column
+// of [A_s | b], summed over the samples in order, into hr_ar[b] (r rows of
+// r + 1: A_red | rho).  The last of an instance's blocks to finish (counted in
+// cnt[b], which it resets) solves the system on its first wavefront.
+constexpr int kHrRedRows = 8;
+template <int NM>
+__global__ __launch_bounds__(128) void k_hr_reduce_solve(
+    int r, int ns, int gpr, const double* __restrict__ Mp, const double* __restrict__ hr_as,
+    int32_t* __restrict__ active, double* __restrict__ hr_ar, int32_t* __restrict__ cnt,
+    double* __restrict__ a, int32_t* __restrict__ iters, double tol, uint32_t* flags) {
+  __shared__ double sMr[kHrRedRows * kMaxNs];   // the block's rows of M
+  __shared__ double Ar[kMaxR * (kMaxR + 1)];
+  __shared__ double rh[kMaxR];
+  __shared__ int ok, last;
+  const int b = blockIdx.x / gpr, g = blockIdx.x - b * gpr, k = threadIdx.x;
+  if (!active[b]) return;
+  const int ld = r + 1;
+  const int i0 = g * kHrRedRows;
+  const int ni = r - i0 < kHrRedRows ? r - i0 : kHrRedRows;
+  const double* Mg = Mp + (size_t)b * r * ns + (size_t)i0 * ns;
+  for (int e = k; e < ni * ns; e += blockDim.x) sMr[e] = Mg[e];
+  __syncthreads();
+  double* out = hr_ar + (size_t)b * r * ld;
+  if (k <= r) {
+    const double* As = hr_as + (size_t)b * ns * ld + k;
+    double acc[kHrRedRows];
+#pragma unroll
+    for (int u = 0; u < kHrRedRows; ++u) acc[u] = 0.0;
+    for (int s0 = 0; s0 < ns; s0 += 8) {
+      double av[8];   // eight samples' loads in flight
+#pragma unroll
+      for (int j = 0; j < 8; ++j) av[j] = s0 + j < ns ? As[(size_t)(s0 + j) * ld] : 0.0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (s0 + j < ns) {
+#pragma unroll
+          for (int u = 0; u < kHrRedRows; ++u)
+            if (u < ni) acc[u] += sMr[u * ns + s0 + j] * av[j];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kHrRedRows; ++u)
+      if (u < ni) out[(size_t)(i0 + u) * ld + k] = k < r ? acc[u] : -acc[u];
+  }
+  // publish the rows, then count the block in
+  __threadfence();
+  __syncthreads();
+  if (k == 0) last = atomicAdd(&cnt[b], 1) == gpr - 1 ? 1 : 0;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();   // the other blocks' rows, not stale copies
+  for (int e0 = k; e0 < r * ld; e0 += 128 * 4) {
+    double v[4];   // four loads in flight per thread
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = e0 + 128 * j < r * ld ? out[e0 + 128 * j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = e0 + 128 * j;
+      if (e < r * ld) {
+        const int i = e / ld, c = e - i * ld;
+        if (c < r) Ar[e] = v[j]; else rh[i] = v[j];
+      }
+    }
+  }
+  if (k == 0) cnt[b] = 0;   // ready for the next iteration
+  __syncthreads();
+  if (k >= 64) return;
+  wave_lu_solve<NM>(Ar, ld, rh, r, &ok);
+  // the update: lane c takes a_c (its own entry of rh); maxima by a wavefront
+  // reduction
+  const int lane = k;
+  double dm = 0.0, am = 0.0;
+  int fin = 1;
+  if (lane < r) {
+    const double an = a[(size_t)b * r + lane] + rh[lane];
+    a[(size_t)b * r + lane] = an;
+    dm = fabs(rh[lane]);
+    am = fabs(an);
+    fin = isfinite(an) ? 1 : 0;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    dm = fmax(dm, __shfl_xor(dm, off));
+    am = fmax(am, __shfl_xor(am, off));
+    fin &= __shfl_xor(fin, off);
+  }
+  if (lane == 0) {
+    unsigned fl = 0;
+    if (!ok) fl |= ROM_FLAG_SINGULAR;
+    if (!fin) fl |= ROM_FLAG_NONFINITE;
     if (fl) atomicOr(&flags[b], fl);
+    iters[b] += 1;
+    active[b] = (dm <= tol * (1.0 + am) || !fin) ? 0 : 1;
   }
 }
 
@@ -1137,20 +1186,29 @@ rom_status galerkin_step_t(rom_batch* h, hipStream_t s) {
   return ROM_OK;
 }
 
-size_t hr_shm() {
-  constexpr int kJr = kMaxNs * 3 * 12;   // sampled Jacobian rows of the 12-variable model
-  constexpr int kAr = kMaxR * (kMaxR + 1);
-  return sizeof(double) * (2 * kMaxR + kMaxNs + kMaxR + kMaxNs * kMaxR + (kJr > kAr ? kJr : kAr));
-}
-
 rom_status hr_step(rom_batch* h, hipStream_t s) {
-  const int B = h->cfg.n_inst;
+  const int B = h->cfg.n_inst, r = h->cfg.r, ns = h->cfg.n_s;
+  const int gpi = (ns + kHrRows - 1) / kHrRows;         // evaluation blocks per instance
+  const int gpr = (r + kHrRedRows - 1) / kHrRedRows;    // reduction blocks per instance
+  double* hr_ar = h->hr_as + (size_t)B * ns * (r + 1);
+  const int nset = B * r > B ? B * r : B;
+  hipLaunchKernelGGL(k_rom_step_setup, dim3((nset + 255) / 256), dim3(256), 0, s, B, r, h->a,
+                     h->a_prev, h->active, h->iters);
   auto go = [&](auto tag) -> rom_status {
     using M = typename decltype(tag)::type;
-    hipLaunchKernelGGL((k_hr_step<M>), dim3(B), dim3(kHrThreads), hr_shm(), s, h->cfg.r, h->cfg.n_s,
-                       h->d_cell_off, h->d_phys, h->cfg.n_phys, h->P, h->M, h->mesh_phi,
-                       h->mesh_qref, h->d_var, h->a, h->cfg.dt, h->cfg.rom_tol, h->cfg.rom_max,
-                       h->iters, h->flags);
+    for (int it = 0; it < h->cfg.rom_max; ++it) {
+      hipLaunchKernelGGL((k_hr_eval<M>), dim3(B * gpi), dim3(kHrEvalThreads), 0, s, r, ns, gpi,
+                         h->d_cell_off, h->d_phys, h->cfg.n_phys, h->P, h->mesh_phi,
+                         h->mesh_qref, h->d_var, h->a, h->a_prev, h->cfg.dt, h->active,
+                         h->hr_as, h->flags);
+      // register rows of the solve sized to r rounded up to 16
+      auto rsolve = r <= 16 ? k_hr_reduce_solve<16> : r <= 32 ? k_hr_reduce_solve<32>
+                  : r <= 48 ? k_hr_reduce_solve<48> : k_hr_reduce_solve<64>;
+      hipLaunchKernelGGL(rsolve, dim3(B * gpr), dim3(128), 0, s, r, ns, gpr, h->M, h->hr_as,
+                         h->active, hr_ar, h->hr_cnt, h->a, h->iters, h->cfg.rom_tol, h->flags);
+    }
+    hipLaunchKernelGGL(k_rom_finalize, dim3((B + 255) / 256), dim3(256), 0, s, B, h->active,
+                       h->flags);
     return ROM_OK;
   };
   rom_status st;
@@ -1207,13 +1265,8 @@ rom_status reconstruct_t(rom_batch* h, void* out, hipStream_t s) {
 
 rom_status rom_kernels_prepare() {
   const int big = 160 * 1024 - 1024;
-  const int hr = (int)hr_shm();   // beside the step's static LDS
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_rebuild<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_rebuild<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_step<BurgersModel<double>>, hipFuncAttributeMaxDynamicSharedMemorySize, hr));
-  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_step<EulerModel<double, false>>, hipFuncAttributeMaxDynamicSharedMemorySize, hr));
-  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_step<EulerModel<double, true>>, hipFuncAttributeMaxDynamicSharedMemorySize, hr));
-  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_step<ReactModel<double>>, hipFuncAttributeMaxDynamicSharedMemorySize, hr));
   return ROM_OK;
 }
 
