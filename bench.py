@@ -64,12 +64,14 @@ def parse():
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-configs", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
-    p.add_argument("--only", choices=["all", "copy", "galerkin", "residual", "windows", "adjoint"],
+    p.add_argument("--only", choices=["all", "copy", "galerkin", "residual", "windows", "adjoint",
+                                      "configs"],
                    default="all",
                    help="profiling runs: 'copy' times a plain 512 MiB device copy (the "
                         "reference for counter scaling), 'galerkin' only the Galerkin pass, "
                         "'residual' only R(q), 'windows' the offline stage plus --warmup and "
-                        "--steps adaptation windows; 'all' is the benchmark")
+                        "--steps adaptation windows, 'adjoint' the online adjoint, 'configs' "
+                        "the other configurations' figures; 'all' is the benchmark")
     return p.parse_args()
 
 
@@ -242,6 +244,8 @@ def profile_only(args, torch, W, R):
             h.close()
         log("windows: %d after %d warm-up, %.3f ms each" % (
             args.steps, args.warmup, 1e3 * (t1 - t0) / max(args.steps, 1)))
+    elif args.only == "configs":
+        log("other configurations: " + json.dumps(config_measurements(torch, W, R)))
     elif args.only == "adjoint":
         w = W.burgers_batch_f32()
         s = torch.cuda.Stream()
