@@ -11,8 +11,9 @@
 //  * Hyper-reduced LSPG step (eqs. hyperreduced_lspg,
 //    hyperreduced_lspg_stationarity): Gauss-Newton on the sampled residual
 //    M P^T D r with M = (P^T Phi)^+, evaluated on the sample mesh only (each
-//    sampled row needs its cell and the two neighbours), in FP64, one
-//    workgroup per instance for all iterations.
+//    sampled row needs its cell and the two neighbours), in FP64; each
+//    iteration evaluates the sampled rows over many blocks per instance, then
+//    reduces M A_s, M b and solves the r x r system per instance.
 //  * Greedy DEIM with oversampling (interpolation-residual argmax, then a
 //    least-squares round) and the (P^T Phi)^+ rebuild by Householder QR.
 #include "internal.h"
