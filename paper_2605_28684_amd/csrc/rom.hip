@@ -855,6 +855,88 @@ __global__ __launch_bounds__(256) void k_deim_argmax(const Tile* __restrict__ ti
   if (tid == 0) { tval[blockIdx.x] = bv[0]; tidx[blockIdx.x] = bi[0]; }
 }
 
+// The same pass for an FP32 basis with four consecutive rows per lane: each
+// column is read as one 16-byte load per lane where the lane's rows are 16-byte
+// aligned (scalar loads otherwise), with the per-row arithmetic of
+// k_deim_argmax.
+__global__ __launch_bounds__(128) void k_deim_argmax_v4(const Tile* __restrict__ tiles,
+                                                        const int64_t* __restrict__ dof_off,
+                                                        const float* __restrict__ phi_cm, int r,
+                                                        int j, const double* __restrict__ coef,
+                                                        int ldc, const uint32_t* __restrict__ chosen,
+                                                        const uint32_t* __restrict__ epoch_p, int S,
+                                                        double* __restrict__ tval,
+                                                        int64_t* __restrict__ tidx) {
+  constexpr int NT = 128;
+  __shared__ double sc[kMaxR];
+  __shared__ double bv[NT];
+  __shared__ int64_t bi[NT];
+  const Tile t = tiles[blockIdx.x / S];
+  const int part = blockIdx.x % S;
+  const int b = t.inst, tid = threadIdx.x;
+  const int64_t base = dof_off[b], nb = dof_off[b + 1] - base;
+  const int64_t len = (t.ncell + S - 1) / S;
+  const int64_t lo = t.cell0 + part * len;
+  const int64_t hi = t.cell0 + ((part + 1) * len < t.ncell ? (part + 1) * len : t.ncell);
+  const uint32_t epoch = *epoch_p;
+  const float* cols = phi_cm + base * r;
+  for (int c = tid; c < j; c += blockDim.x) sc[c] = coef[(size_t)b * ldc + c];
+  __syncthreads();
+  double best = -1.0;
+  int64_t bidx = -1;
+  for (int64_t r0 = lo; r0 < hi; r0 += NT * 4) {
+    const int64_t l0 = r0 + 4 * tid;
+    bool ok[4];
+    double res[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ok[u] = l0 + u < hi;
+    // all four rows in range and every column's four rows 16-byte aligned
+    const bool vec = l0 + 4 <= hi && (nb & 3) == 0 &&
+                     (reinterpret_cast<uintptr_t>(cols + l0) & 15) == 0;
+    if (vec) {
+      const float4 v0 = *reinterpret_cast<const float4*>(cols + (int64_t)j * nb + l0);
+      res[0] = (double)v0.x; res[1] = (double)v0.y; res[2] = (double)v0.z; res[3] = (double)v0.w;
+      for (int c = 0; c < j; ++c) {
+        const double w = sc[c];
+        const float4 v = *reinterpret_cast<const float4*>(cols + (int64_t)c * nb + l0);
+        res[0] -= (double)v.x * w;
+        res[1] -= (double)v.y * w;
+        res[2] -= (double)v.z * w;
+        res[3] -= (double)v.w * w;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) res[u] = ok[u] ? (double)cols[(int64_t)j * nb + l0 + u] : 0.0;
+      for (int c = 0; c < j; ++c) {
+        const double w = sc[c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (ok[u]) res[u] -= (double)cols[(int64_t)c * nb + l0 + u] * w;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!ok[u] || chosen[base + l0 + u] == epoch) continue;
+      const double v = fabs(res[u]);
+      if (v > best || (v == best && l0 + u < bidx)) { best = v; bidx = l0 + u; }
+    }
+  }
+  bv[tid] = best;
+  bi[tid] = bidx;
+  __syncthreads();
+  for (int st = NT / 2; st > 0; st >>= 1) {
+    if (tid < st) {
+      const double v2 = bv[tid + st];
+      const int64_t i2 = bi[tid + st];
+      if (i2 >= 0 && (v2 > bv[tid] || (v2 == bv[tid] && (bi[tid] < 0 || i2 < bi[tid])))) {
+        bv[tid] = v2; bi[tid] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) { tval[blockIdx.x] = bv[0]; tidx[blockIdx.x] = bi[0]; }
+}
+
 // Householder QR least squares on an m x nc FP64 matrix in LDS (row-major,
 // ld = kMaxR + 1): overwrites x[0..nc) with argmin ||A x - rhs||.  Single
 // thread per column reflector application loop; sizes here are tiny.
@@ -1238,9 +1320,15 @@ rom_status rebuild_t(rom_batch* h, hipStream_t s) {
   double* coef = h->rstate;  // per instance kMaxR coefficients
   for (int t = 0; t < ns; ++t) {
     const int j = t < r ? t : t - r;
-    hipLaunchKernelGGL((k_deim_argmax<T, 2>), dim3(h->n_ptiles * S), dim3(256), 0, s, h->d_ptiles,
-                       h->d_dof_off, (const T*)h->phi_cm, r, j, coef, kMaxR, h->chosen, h->d_epoch,
-                       S, tval, tidx);
+    if constexpr (sizeof(T) == 4) {
+      hipLaunchKernelGGL(k_deim_argmax_v4, dim3(h->n_ptiles * S), dim3(128), 0, s, h->d_ptiles,
+                         h->d_dof_off, (const float*)h->phi_cm, r, j, coef, kMaxR, h->chosen,
+                         h->d_epoch, S, tval, tidx);
+    } else {
+      hipLaunchKernelGGL((k_deim_argmax<T, 2>), dim3(h->n_ptiles * S), dim3(256), 0, s,
+                         h->d_ptiles, h->d_dof_off, (const T*)h->phi_cm, r, j, coef, kMaxR,
+                         h->chosen, h->d_epoch, S, tval, tidx);
+    }
     hipLaunchKernelGGL((k_deim_select<T>), dim3(B), dim3(256), 0, s, h->d_ptile_first, S, tval, tidx,
                        h->d_dof_off, (const T*)h->Phi, r, ns, t, h->P, h->chosen, h->d_epoch, coef,
                        kMaxR, h->flags);
