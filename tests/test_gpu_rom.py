@@ -260,6 +260,38 @@ def test_hr_lspg_steps_and_events_parity_fp64(problem):
     assert not (h.status() & (4 | 16 | 32)).any()
 
 
+def test_hr_lspg_fine_steps_at_reacting_sizes_fp64():
+    """HR-LSPG fine steps at the reacting configuration's reduced sizes (12
+    variables, r = 64, n_s = 128: sixteen evaluation blocks and eight reduction
+    blocks per instance, the 64-column wavefront solve), from identical offline
+    state, against the oracle's Gauss-Newton steps."""
+    import gpu_common as G
+    import torch
+    from paper_2605_28684_amd import romhip as R
+    w = W.react10_f32(n_inst=1, n=96, r=64, n_s=128, z=1000, N_t=80, precision=W.F64)
+    w.dt = 2e-4
+    w.rom_tol = 1e-13
+    q0 = w.q0
+    prm = w.params()
+    h = _handle(w, q0=G.to_dev(q0, W.F64))
+    st = O.offline(W.REACT, w.phys[0], q0, prm)
+    h.set(R.GET_BASIS, G.to_dev(st["Phi"].reshape(-1), W.F64))
+    h.set(R.GET_SIGMA, torch.as_tensor(st["sigma"]))
+    h.set(R.GET_A, torch.as_tensor(st["a"]))
+    h.set(R.GET_YCORR, G.to_dev(st["y_corr"], W.F64))
+    h.set(R.GET_DVAR, torch.as_tensor(st["d_var"]))
+    h.rom_rebuild()
+    np.testing.assert_array_equal(h.get(R.GET_SAMPLES).cpu().numpy(), st["P"])
+    for k in range(3):
+        h.rom_step(1)
+        O.rom_fine_step(W.REACT, w.phys[0], st, prm)
+        ref = O.reconstruct(st["q_ref"], st["d"], st["Phi"], st["a"])
+        qg = G.host(h.get(R.GET_QTILDE))
+        assert G.relerr(qg, ref) < 1e-10, (k, G.relerr(qg, ref))
+        assert G.relerr(G.host(h.get(R.GET_A)), st["a"]) < 1e-9, k
+    assert not (h.status() & (4 | 16 | 32)).any()
+
+
 @pytest.mark.parametrize("precision", [W.F64, W.F32])
 def test_deim_rows_bit_exact_and_pinv(precision):
     import gpu_common as G
