@@ -109,9 +109,13 @@ def rusanov_flux(UL, UR, gamma):
     return 0.5 * (FL + FR) - 0.5 * s[:, None] * (UR - UL)
 
 
-def hllc_flux(UL, UR, gamma):
-    """Toro's HLLC flux with Davis speeds S_L = min(u_L-c_L, u_R-c_R),
-    S_R = max(u_L+c_L, u_R+c_R) and the standard contact speed S*."""
+def hllc_waves(UL, UR, gamma):
+    """Wave speeds and star states of Toro's HLLC solver with Davis speeds
+    S_L = min(u_L-c_L, u_R-c_R), S_R = max(u_L+c_L, u_R+c_R), the contact speed
+    S* = (p_R - p_L + rho_L u_L (S_L-u_L) - rho_R u_R (S_R-u_R))
+         / (rho_L (S_L-u_L) - rho_R (S_R-u_R))
+    and U*_K = rho_K (S_K-u_K)/(S_K-S*) [1, S*, E_K/rho_K + (S*-u_K)(S* + p_K/(rho_K (S_K-u_K)))].
+    Returns (SL, Ss, SR, UsL, UsR, FL, FR)."""
     rL, uL, pL, cL = euler_primitives(UL, gamma)
     rR, uR, pR, cR = euler_primitives(UR, gamma)
     SL = cmin(uL - cL, uR - cR)
@@ -128,8 +132,18 @@ def hllc_flux(UL, UR, gamma):
             e = U[:, 2] / r + (Ss - u) * (Ss + p / (r * (S - u)))
             return np.stack([fac, fac * Ss, fac * e], axis=1)
 
-        FsL = FL + SL[:, None] * (star(UL, rL, uL, pL, SL) - UL)
-        FsR = FR + SR[:, None] * (star(UR, rR, uR, pR, SR) - UR)
+        UsL = star(UL, rL, uL, pL, SL)
+        UsR = star(UR, rR, uR, pR, SR)
+    return SL, Ss, SR, UsL, UsR, FL, FR
+
+
+def hllc_flux(UL, UR, gamma):
+    """Toro's HLLC flux: F_L if S_L >= 0, F*_L = F_L + S_L (U*_L - U_L) if
+    S_L < 0 <= S*, F*_R = F_R + S_R (U*_R - U_R) if S* < 0 <= S_R, else F_R."""
+    SL, Ss, SR, UsL, UsR, FL, FR = hllc_waves(UL, UR, gamma)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        FsL = FL + SL[:, None] * (UsL - UL)
+        FsR = FR + SR[:, None] * (UsR - UR)
     sl = np.real(SL)[:, None]
     ss = np.real(Ss)[:, None]
     sr = np.real(SR)[:, None]

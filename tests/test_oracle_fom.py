@@ -271,3 +271,194 @@ def test_rollout_vjp_matches_central_differences(problem):
         v = rng.normal(size=q0.shape)
         fd = (L(q0 + h * v) - L(q0 - h * v)) / (2 * h)
         assert abs(g0 @ v - fd) <= 1e-6 * max(1.0, abs(fd)), (g0 @ v, fd)
+
+
+# ------------------------------------------------------------------ flux pins by hand values
+# One asymmetric subsonic pair, gamma = 1.4: left (rho, u, p) = (1, 0.5, 1),
+# right (0.5, -0.2, 0.4).  The figures below were worked out from the
+# primitive values alone, in 40-digit decimal arithmetic:
+#   c_L = sqrt(1.4), c_R = sqrt(1.12); |u_L| + c_L = 1.68321595661992...,
+#   |u_R| + c_R = 1.25830052442583...  (the interface speed of App. B, eq.
+#   sod_rusanov_speed, is the larger one)
+#   Rusanov (eq. sod_rusanov_flux): 1/2 (F_L + F_R) - 1/2 s (U_R - U_L)
+#   HLLC (Davis speeds): S_L = -1.25830052442583..., S* = 0.47810089313876...,
+#   S_R = 1.68321595661992..., so the flux is the left star flux F*_L.
+_PAIR_L = np.array([[1.0, 0.5, 1.0 / 0.4 + 0.5 * 0.25]])
+_PAIR_R = np.array([[0.5, -0.1, 0.4 / 0.4 + 0.5 * 0.5 * 0.04]])
+_RUSANOV_HAND = [0.6208039891549808021, 1.339964786985976963, 2.124446884970587991]
+_HLLC_HAND = [0.4841305948214439552, 1.269968480858503152, 1.768313943155533271]
+_HLLC_SPEEDS = [-1.258300524425836236, 0.4781008931387631863, 1.683215956619923209]
+
+
+def test_rusanov_flux_hand_evaluated_pair():
+    f = F.rusanov_flux(_PAIR_L, _PAIR_R, 1.4)[0]
+    np.testing.assert_allclose(f, _RUSANOV_HAND, rtol=2e-15, atol=0)
+    # the same pair reversed in space (x -> -x): mass and energy fluxes flip sign
+    mirror = np.array([[1.0, -1.0, 1.0]])
+    g = F.rusanov_flux(_PAIR_R * mirror, _PAIR_L * mirror, 1.4)[0]
+    np.testing.assert_allclose(g, -np.array(_RUSANOV_HAND) * mirror[0], rtol=2e-15, atol=0)
+
+
+def test_rusanov_dissipation_speed_is_the_larger_signal_speed():
+    """Eq. sod_rusanov_speed: the dissipation coefficient is max(|u_L|+c_L, |u_R|+c_R);
+    recovered from the flux as s = -(2 F - F_L - F_R)/(U_R - U_L) on random pairs."""
+    rng = np.random.default_rng(71)
+    n = 400
+    rho = rng.uniform(0.2, 2.0, size=(2, n))
+    u = rng.uniform(-1.5, 1.5, size=(2, n))
+    p = rng.uniform(0.1, 3.0, size=(2, n))
+    U = np.stack([rho, rho * u, p / 0.4 + 0.5 * rho * u * u], axis=2)
+    f = F.rusanov_flux(U[0], U[1], 1.4)
+    avg = 0.5 * (F.euler_flux(U[0], 1.4) + F.euler_flux(U[1], 1.4))
+    s = -2.0 * (f - avg)[:, 0] / (U[1, :, 0] - U[0, :, 0])
+    c = np.sqrt(1.4 * p / rho)
+    np.testing.assert_allclose(s, np.maximum(np.abs(u[0]) + c[0], np.abs(u[1]) + c[1]),
+                               rtol=1e-9)
+
+
+def test_hllc_flux_hand_evaluated_pair():
+    SL, Ss, SR, _, _, _, _ = F.hllc_waves(_PAIR_L, _PAIR_R, 1.4)
+    np.testing.assert_allclose([SL[0], Ss[0], SR[0]], _HLLC_SPEEDS, rtol=2e-15, atol=0)
+    np.testing.assert_allclose(F.hllc_flux(_PAIR_L, _PAIR_R, 1.4)[0], _HLLC_HAND,
+                               rtol=3e-15, atol=0)
+
+
+def test_hllc_stationary_contact_is_exact():
+    """A resting contact (u_L = u_R = 0, p_L = p_R, rho_L != rho_R) is an exact
+    solution that HLLC resolves: the flux is (0, p, 0) whatever the densities."""
+    rng = np.random.default_rng(72)
+    n = 200
+    rho = rng.uniform(0.1, 5.0, size=(2, n))
+    p = rng.uniform(0.05, 4.0, size=n)
+    U = np.stack([rho, 0.0 * rho, np.broadcast_to(p / 0.4, (2, n))], axis=2)
+    f = F.hllc_flux(U[0], U[1], 1.4)
+    np.testing.assert_allclose(f[:, 1], p, rtol=1e-14)
+    assert np.max(np.abs(f[:, [0, 2]])) <= 1e-14 * np.max(p)
+
+
+def test_hllc_star_states_satisfy_the_integral_consistency_condition():
+    """Toro's consistency condition for the two star states on random subsonic pairs:
+    (S_R - S*) U*_R + (S* - S_L) U*_L = S_R U_R - S_L U_L - (F_R - F_L),
+    with one pressure p*_K = p_K + rho_K (S_K - u_K)(S* - u_K) and one velocity S*
+    in both star regions (the jump conditions across the contact)."""
+    rng = np.random.default_rng(73)
+    n = 500
+    rho = rng.uniform(0.2, 2.0, size=(2, n))
+    u = rng.uniform(-0.6, 0.6, size=(2, n))
+    p = rng.uniform(0.2, 3.0, size=(2, n))
+    U = np.stack([rho, rho * u, p / 0.4 + 0.5 * rho * u * u], axis=2)
+    SL, Ss, SR, UsL, UsR, FL, FR = F.hllc_waves(U[0], U[1], 1.4)
+    lhs = (SR - Ss)[:, None] * UsR + (Ss - SL)[:, None] * UsL
+    rhs = SR[:, None] * U[1] - SL[:, None] * U[0] - (FR - FL)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(UsL[:, 1] / UsL[:, 0], Ss, rtol=1e-13)
+    np.testing.assert_allclose(UsR[:, 1] / UsR[:, 0], Ss, rtol=1e-13)
+    psL = p[0] + rho[0] * (SL - u[0]) * (Ss - u[0])
+    psR = p[1] + rho[1] * (SR - u[1]) * (Ss - u[1])
+    np.testing.assert_allclose(psL, psR, rtol=1e-12)
+    # the contact carries the star fluxes into each other: F*_R - F*_L = S* (U*_R - U*_L)
+    FsL = FL + SL[:, None] * (UsL - U[0])
+    FsR = FR + SR[:, None] * (UsR - U[1])
+    np.testing.assert_allclose(FsR - FsL, Ss[:, None] * (UsR - UsL), rtol=1e-11, atol=1e-12)
+
+
+# ------------------------------------------------------------------ reacting transport pins
+def _transport_only(n, kappa=None, k_in=0.0):
+    """The reacting model's constants with reactions switched off (A = 0)."""
+    ph = dict(W.react10_f32(n_inst=1, n=n).phys[0])
+    ph["A"] = 0.0
+    ph["k_in"] = k_in
+    if kappa is not None:
+        ph["kappa"] = kappa
+    return ph
+
+
+@pytest.mark.parametrize("c", [0.7, -0.45])
+def test_react_scalar_advection_is_upwind_fourier_eigenvalue(c):
+    """Constant velocity c, no sources: each scalar obeys the linear upwind +
+    diffusion scheme, whose Fourier mode exp(i theta j) has the eigenvalue
+    lam = -c (1 - e^{-i theta})/dx + kappa (2 cos theta - 2)/dx^2 for c > 0 and
+    lam = -c (e^{i theta} - 1)/dx + kappa (2 cos theta - 2)/dx^2 for c < 0.
+    The real field cos(theta j) then maps to Re(lam) cos - Im(lam) sin, and one
+    backward-Euler step multiplies the mode by 1/(1 - dt lam)."""
+    n, k = 48, 5
+    ph = _transport_only(n)
+    dx = 1.0 / n
+    th = 2 * np.pi * k / n
+    j = np.arange(n)
+    kap = ph["kappa"]
+    if c > 0:
+        lam = -c * (1 - np.exp(-1j * th)) / dx + kap * (2 * np.cos(th) - 2) / dx ** 2
+    else:
+        lam = -c * (np.exp(1j * th) - 1) / dx + kap * (2 * np.cos(th) - 2) / dx ** 2
+    Q = np.zeros((n, 12))
+    Q[:, 11] = c
+    for v in (0, 4, 10):
+        Q[:, v] = 0.3 * (v + 1) * np.cos(th * j)
+    f = R.react_f(Q, ph)
+    for v in (0, 4, 10):
+        ref = 0.3 * (v + 1) * (lam.real * np.cos(th * j) - lam.imag * np.sin(th * j))
+        np.testing.assert_allclose(f[:, v], ref, rtol=0, atol=1e-11 * np.max(np.abs(ref)))
+    assert np.all(f[:, 11] == 0.0)
+    # one backward-Euler step of the mode
+    dt = 2e-3
+    q1, it, ok = F.newton_be_step(F.REACT, Q.reshape(-1), dt, ph, tol=1e-13)
+    assert ok
+    m = 1.0 / (1.0 - dt * lam)
+    Q1 = q1.reshape(n, 12)
+    ref = 0.3 * (m * np.exp(1j * th * j)).real
+    np.testing.assert_allclose(Q1[:, 0], ref, rtol=0, atol=1e-12)
+
+
+def test_react_face_velocity_is_the_average_of_the_two_cells():
+    """A constant scalar is carried by the face velocity alone: with phi = 1 and no
+    diffusion the flux difference is the centred difference of u,
+    f_phi,i = -(u_{i+1} - u_{i-1}) / (2 dx), for any velocity field."""
+    n = 40
+    ph = _transport_only(n, kappa=0.0)
+    rng = np.random.default_rng(74)
+    u = rng.uniform(-1.0, 1.0, size=n)
+    Q = np.zeros((n, 12))
+    Q[:, 11] = u
+    Q[:, 2] = 1.0
+    f = R.react_f(Q, ph)
+    ref = -(np.roll(u, -1) - np.roll(u, 1)) * n / 2.0
+    np.testing.assert_allclose(f[:, 2], ref, rtol=1e-13, atol=1e-12)
+
+
+def test_react_inflow_relaxation_backward_euler_closed_form():
+    """No transport and no reactions (u = 0, kappa = 0, A = 0): cells with centre
+    x < x_in relax towards the inflow state, so one backward-Euler step gives
+    Y+ = (Y + k_in dt Y_in) / (1 + k_in dt) there and leaves the other cells alone."""
+    n = 64
+    ph = _transport_only(n, kappa=0.0, k_in=50.0)
+    ph["nu_u"] = 0.0
+    rng = np.random.default_rng(75)
+    Q = np.zeros((n, 12))
+    Q[:, :10] = rng.uniform(0.0, 1.0, size=(n, 10))
+    Q[:, 10] = rng.uniform(0.2, 1.0, size=n)
+    dt = 1e-2
+    q1, it, ok = F.newton_be_step(F.REACT, Q.reshape(-1), dt, ph, tol=1e-14)
+    assert ok and it == 1
+    Q1 = q1.reshape(n, 12)
+    x = (np.arange(n) + 0.5) / n
+    inl = x < ph["x_in"]
+    assert 0 < inl.sum() < n
+    kd = ph["k_in"] * dt
+    Yin = np.asarray(ph["Y_in"])
+    np.testing.assert_allclose(Q1[inl, :10], (Q[inl, :10] + kd * Yin[None, :]) / (1 + kd),
+                               rtol=1e-14)
+    np.testing.assert_allclose(Q1[inl, 10], (Q[inl, 10] + kd * ph["T_in"]) / (1 + kd), rtol=1e-14)
+    np.testing.assert_array_equal(Q1[~inl, :11], Q[~inl, :11])
+
+
+def test_react_species_sum_is_conserved_by_transport_and_reactions():
+    """With no inflow, the species mass sum_i sum_l Y_l changes by neither the
+    conservative transport (periodic) nor the reactions (two reactants -> two products)."""
+    n = 48
+    ph = dict(W.react10_f32(n_inst=1, n=n).phys[0])
+    ph["k_in"] = 0.0
+    Q = W.random_state(W.REACT, [n], seed=76).reshape(n, 12)
+    f = R.react_f(Q, ph)
+    tot = np.abs(f[:, :10]).sum()
+    assert abs(f[:, :10].sum()) <= 1e-12 * tot
