@@ -191,7 +191,7 @@ def config_measurements(torch, W, R):
         gq = torch.empty_like(q0)
         ms_step = _timed(torch, lambda: h.fom_step(q, w.dt, out=q), 5)
         n_steps, n_ckpt = 16, 4
-        ms_vjp = _timed(torch, lambda: h.rollout_vjp(q0, n_steps, w.dt, gbar, n_ckpt=n_ckpt,
+        ms_vjp = _timed(torch, lambda: h.fom_rollout_vjp(q0, n_steps, w.dt, gbar, n_ckpt=n_ckpt,
                                                      out=gq), 2)
         cells = sum(w.n_cells)
         out["C4_euler_rusanov_64x262144_f32"] = dict(

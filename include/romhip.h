@@ -211,7 +211,7 @@ rom_status fom_step_vjp(rom_handle h, const void* q, double dt, const void* gbar
                         void* stream);
 
 /*
- * rom_rollout_vjp - gradient of a loss of the final state of a backward-Euler
+ * fom_rollout_vjp - gradient of a loss of the final state of a backward-Euler
  * full-order rollout with respect to its initial state (an extension beyond
  * the paper: the adjoint of eq. fom_discrete_solve iterated).  The rollout is
  * q^{k+1} = S(q^k), k = 0 .. n_steps-1, each step solved by Newton as in
@@ -231,7 +231,7 @@ rom_status fom_step_vjp(rom_handle h, const void* q, double dt, const void* gbar
  * Errors: ROM_E_INVAL (NULL pointers, n_steps < 1, n_ckpt < 0, dt <= 0),
  * ROM_E_NOMEM.
  */
-rom_status rom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, double dt,
+rom_status fom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, double dt,
                            int32_t n_ckpt, const void* gbar, void* gq0, void* stream);
 
 /*

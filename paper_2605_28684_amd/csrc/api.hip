@@ -409,6 +409,68 @@ rom_status offline(rom_batch* h, const void* q0, hipStream_t s) {
   return ROM_OK;
 }
 
+// ---- the rollout adjoint's checkpoint plan and body
+struct RolloutPlan {
+  int64_t T = 0, S = 0, nseg = 0;  // steps, steps per segment, checkpoints
+  size_t st = 0;                    // bytes of one state
+  size_t bytes = 0;                 // checkpoints + segment states + two adjoint vectors
+};
+
+rom_status rollout_check(rom_batch* h, const void* q0, int32_t n_steps, double dt, int32_t n_ckpt,
+                         const void* gbar, void* gq0) {
+  ROM_REQUIRE(h && q0 && gbar && gq0, ROM_E_INVAL, "handle, q0, gbar and gq0 are required");
+  ROM_REQUIRE(n_steps >= 1, ROM_E_INVAL, "n_steps must be >= 1");
+  ROM_REQUIRE(n_ckpt >= 0, ROM_E_INVAL, "n_ckpt must be >= 0");
+  ROM_REQUIRE(dt > 0.0 && std::isfinite(dt), ROM_E_INVAL, "dt must be positive");
+  return ROM_OK;
+}
+
+RolloutPlan rollout_plan(const rom_batch* h, int32_t n_steps, int32_t n_ckpt) {
+  RolloutPlan p;
+  p.T = n_steps;
+  int64_t C = n_ckpt > 0 ? n_ckpt : (int64_t)std::ceil(std::sqrt((double)p.T));
+  if (C > p.T) C = p.T;
+  p.S = (p.T + C - 1) / C;
+  p.nseg = (p.T + p.S - 1) / p.S;  // states q^0, q^S, q^2S, ...
+  p.st = h->esz * (size_t)h->total_dof;
+  p.bytes = (size_t)(p.nseg + p.S + 1 + 2) * p.st;
+  return p;
+}
+
+// Forward pass keeping only the checkpoints, then one segment at a time:
+// recompute its states from the checkpoint and apply the step adjoints in
+// reverse.  Every byte of ws that is read was written earlier in the call.
+rom_status rollout_vjp_impl(rom_batch* h, const void* q0, double dt, const RolloutPlan& pl,
+                            const void* gbar, void* gq0, char* ws, hipStream_t s) {
+  const int64_t T = pl.T, S = pl.S, nseg = pl.nseg;
+  const size_t st = pl.st;
+  char* ck = ws;
+  char* seg = ck + (size_t)nseg * st;
+  char* ga = seg + (size_t)(S + 1) * st;
+  char* gb = ga + st;
+  ROM_TRY(copy_words(q0, ck, st, s));
+  for (int64_t j = 0; j + 1 < nseg; ++j) {
+    char* nxt = ck + (size_t)(j + 1) * st;
+    ROM_TRY(copy_words(ck + (size_t)j * st, nxt, st, s));
+    for (int64_t k = 0; k < S; ++k) ROM_TRY(fom_step_impl(h, nxt, dt, nxt, nullptr, s));
+  }
+  ROM_TRY(copy_words(gbar, ga, st, s));
+  for (int64_t j = nseg - 1; j >= 0; --j) {
+    const int64_t k0 = j * S, k1 = std::min(k0 + S, T), L = k1 - k0;
+    ROM_TRY(copy_words(ck + (size_t)j * st, seg, st, s));
+    for (int64_t i = 0; i < L; ++i)
+      ROM_TRY(fom_step_impl(h, seg + (size_t)i * st, dt, seg + (size_t)(i + 1) * st, nullptr, s));
+    for (int64_t i = L - 1; i >= 0; --i) {
+      ROM_TRY(launch_assemble_adjoint(h, seg + (size_t)(i + 1) * st, dt, ga, s));
+      ROM_TRY(bt_solve(h, -1, nullptr, gb, s));
+      std::swap(ga, gb);
+    }
+  }
+  ROM_TRY(copy_words(ga, gq0, st, s));
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
 }  // namespace
 
 rom_status fill_zero(void* p, size_t bytes, hipStream_t s) {
@@ -629,58 +691,23 @@ rom_status fom_step_vjp(rom_handle h, const void* q, double dt, const void* gbar
   return bt_solve(h, -1, nullptr, gq_prev, s);
 }
 
-rom_status rom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, double dt,
+rom_status fom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, double dt,
                            int32_t n_ckpt, const void* gbar, void* gq0, void* stream) {
-  ROM_REQUIRE(h && q0 && gbar && gq0, ROM_E_INVAL, "handle, q0, gbar and gq0 are required");
-  ROM_REQUIRE(n_steps >= 1, ROM_E_INVAL, "n_steps must be >= 1");
-  ROM_REQUIRE(n_ckpt >= 0, ROM_E_INVAL, "n_ckpt must be >= 0");
-  ROM_REQUIRE(dt > 0.0 && std::isfinite(dt), ROM_E_INVAL, "dt must be positive");
+  ROM_TRY(rollout_check(h, q0, n_steps, dt, n_ckpt, gbar, gq0));
   hipStream_t s = (hipStream_t)stream;
   h->last_stream = s;
-  const int64_t T = n_steps;
-  int64_t C = n_ckpt > 0 ? n_ckpt : (int64_t)std::ceil(std::sqrt((double)T));
-  if (C > T) C = T;
-  const int64_t S = (T + C - 1) / C;      // steps per segment
-  const int64_t nseg = (T + S - 1) / S;   // checkpoints (states q^0, q^S, q^2S, ...)
-  const size_t st = h->esz * (size_t)h->total_dof;
-  const size_t need = (size_t)(nseg + S + 1 + 2) * st;
-  if (h->rvjp_bytes < need) {
+  const RolloutPlan pl = rollout_plan(h, n_steps, n_ckpt);
+  if (h->rvjp_bytes < pl.bytes) {
     ROM_HIP_CHECK(hipStreamSynchronize(s));
     if (h->rvjp) (void)hipFree(h->rvjp);
     h->rvjp = nullptr;
     h->rvjp_bytes = 0;
     char* p = nullptr;
-    ROM_TRY(alloc(&p, need));
+    ROM_TRY(alloc(&p, pl.bytes));
     h->rvjp = p;
-    h->rvjp_bytes = need;
+    h->rvjp_bytes = pl.bytes;
   }
-  char* ck = (char*)h->rvjp;
-  char* seg = ck + (size_t)nseg * st;
-  char* ga = seg + (size_t)(S + 1) * st;
-  char* gb = ga + st;
-  // forward: checkpoints only
-  ROM_TRY(copy_words(q0, ck, st, s));
-  for (int64_t j = 0; j + 1 < nseg; ++j) {
-    char* nxt = ck + (size_t)(j + 1) * st;
-    ROM_TRY(copy_words(ck + (size_t)j * st, nxt, st, s));
-    for (int64_t k = 0; k < S; ++k) ROM_TRY(fom_step_impl(h, nxt, dt, nxt, nullptr, s));
-  }
-  // backward, one segment at a time
-  ROM_TRY(copy_words(gbar, ga, st, s));
-  for (int64_t j = nseg - 1; j >= 0; --j) {
-    const int64_t k0 = j * S, k1 = std::min(k0 + S, T), L = k1 - k0;
-    ROM_TRY(copy_words(ck + (size_t)j * st, seg, st, s));
-    for (int64_t i = 0; i < L; ++i)
-      ROM_TRY(fom_step_impl(h, seg + (size_t)i * st, dt, seg + (size_t)(i + 1) * st, nullptr, s));
-    for (int64_t i = L - 1; i >= 0; --i) {
-      ROM_TRY(launch_assemble_adjoint(h, seg + (size_t)(i + 1) * st, dt, ga, s));
-      ROM_TRY(bt_solve(h, -1, nullptr, gb, s));
-      std::swap(ga, gb);
-    }
-  }
-  ROM_TRY(copy_words(ga, gq0, st, s));
-  ROM_HIP_CHECK(hipGetLastError());
-  return ROM_OK;
+  return rollout_vjp_impl(h, q0, dt, pl, gbar, gq0, (char*)h->rvjp, s);
 }
 
 rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const void* qbar,

@@ -73,7 +73,7 @@ def _load():
         "rom_clear_status": [vp, vp],
         "fom_residual_vjp": [vp, vp, vp, d, vp, vp, vp, vp],
         "fom_step_vjp": [vp, vp, d, vp, vp, vp],
-        "rom_rollout_vjp": [vp, vp, i32, d, i32, vp, vp, vp],
+        "fom_rollout_vjp": [vp, vp, i32, d, i32, vp, vp, vp],
         "rom_online_vjp": [vp, i32, i32, vp, vp, vp, vp, vp, vp],
         "rom_autotune": [vp, i32, vp, ctypes.POINTER(i32), vp],
         "rom_set_tuning": [vp, i32, i32, ctypes.POINTER(i32)],
@@ -93,7 +93,7 @@ def _load():
 LIB = _load()
 SYMBOLS = ("rom_create", "rom_destroy", "fom_residual", "fom_step", "isvd_update", "rom_rebuild",
            "rom_step", "rom_get", "rom_set", "rom_get_status", "rom_clear_status",
-           "fom_residual_vjp", "fom_step_vjp", "rom_rollout_vjp", "rom_online_vjp", "rom_autotune",
+           "fom_residual_vjp", "fom_step_vjp", "fom_rollout_vjp", "rom_online_vjp", "rom_autotune",
            "rom_set_tuning", "rom_query", "rom_profile", "rom_last_error")
 TUNE_RESIDUAL = 0
 PROF_RESIDUAL, PROF_GALERKIN_PASS, PROF_ISVD_PROJECT, PROF_RESIDUAL_VJP, PROF_FOM_STEP = range(5)
@@ -201,9 +201,9 @@ class RomBatch:
         _check(LIB.fom_step_vjp(self.h, _ptr(q), float(dt), _ptr(gbar), _ptr(out), _stream()))
         return out
 
-    def rollout_vjp(self, q0, n_steps, dt, gbar, n_ckpt=0, out=None):
+    def fom_rollout_vjp(self, q0, n_steps, dt, gbar, n_ckpt=0, out=None):
         out = self._new(self.total_dof) if out is None else out
-        _check(LIB.rom_rollout_vjp(self.h, _ptr(q0), int(n_steps), float(dt), int(n_ckpt),
+        _check(LIB.fom_rollout_vjp(self.h, _ptr(q0), int(n_steps), float(dt), int(n_ckpt),
                                    _ptr(gbar), _ptr(out), _stream()))
         return out
 
@@ -313,7 +313,7 @@ class FomResidual(torch.autograd.Function):
 
 class FomRollout(torch.autograd.Function):
     """q^T after n_steps backward-Euler steps of size dt from q0 (fom_step); the
-    backward pass is the checkpointed rollout adjoint (rom_rollout_vjp)."""
+    backward pass is the checkpointed rollout adjoint (fom_rollout_vjp)."""
 
     @staticmethod
     def forward(ctx, q0, handle, n_steps, dt, n_ckpt=0):
@@ -328,7 +328,7 @@ class FomRollout(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         (q0,) = ctx.saved_tensors
-        gq0 = ctx.handle.rollout_vjp(q0, ctx.n_steps, ctx.dt, g.contiguous(), ctx.n_ckpt)
+        gq0 = ctx.handle.fom_rollout_vjp(q0, ctx.n_steps, ctx.dt, g.contiguous(), ctx.n_ckpt)
         return gq0, None, None, None, None
 
 

@@ -261,7 +261,7 @@ def test_rollout_vjp_parity_and_checkpoint_invariance(problem, precision):
     h = _handle(w)
     gbar = G.rounded(np.random.default_rng(52).normal(size=q0.shape), precision)
     qd, gd = G.to_dev(q0, precision), G.to_dev(gbar, precision)
-    outs = [G.host(h.rollout_vjp(qd, T, dt, gd, n_ckpt=c)) for c in (0, 1, T, 5)]
+    outs = [G.host(h.fom_rollout_vjp(qd, T, dt, gd, n_ckpt=c)) for c in (0, 1, T, 5)]
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     off = w.offsets()
@@ -283,7 +283,7 @@ def test_rollout_vjp_central_differences_fp64():
     h = _handle(w)
     rng = np.random.default_rng(53)
     gbar = rng.normal(size=q0.shape)
-    g0 = G.host(h.rollout_vjp(G.to_dev(q0, W.F64), T, dt, G.to_dev(gbar, W.F64)))
+    g0 = G.host(h.fom_rollout_vjp(G.to_dev(q0, W.F64), T, dt, G.to_dev(gbar, W.F64)))
     off = w.offsets()
 
     def roll(q):
@@ -315,7 +315,7 @@ def test_autograd_functions_use_the_adjoint_kernels():
     gbar = torch.as_tensor(np.random.default_rng(54).normal(size=q0.shape), device="cuda")
     qT = R.FomRollout.apply(q, h, 6, dt, 0)
     (gq,) = torch.autograd.grad((qT * gbar).sum(), q)
-    ref = h.rollout_vjp(G.to_dev(q0, W.F64), 6, dt, gbar)
+    ref = h.fom_rollout_vjp(G.to_dev(q0, W.F64), 6, dt, gbar)
     assert torch.equal(gq, ref)
     q2 = G.to_dev(q0, W.F64).requires_grad_(True)
     f = R.FomResidual.apply(q2, h)

@@ -369,7 +369,7 @@ def test_invalid_arguments_are_rejected():
         h.fom_step(q, -1.0)
     assert e.value.code == R.ROM_E_INVAL
     with pytest.raises(R.RomError) as e:
-        h.rollout_vjp(q, 0, 1e-3, q)
+        h.fom_rollout_vjp(q, 0, 1e-3, q)
     assert e.value.code == R.ROM_E_INVAL
     out = h.fom_step(q, 1e-3)                 # still usable
     torch.cuda.synchronize()
