@@ -235,6 +235,29 @@ rom_status fom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, double
                            int32_t n_ckpt, const void* gbar, void* gq0, void* stream);
 
 /*
+ * fom_rollout_vjp_noalloc - fom_rollout_vjp for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and result, bit for bit;
+ * the checkpoints, segment states and the two adjoint vectors live in a
+ * static device array of the library instead of handle-owned memory.
+ *   Limit: (nseg + S + 3) * total_dof * sizeof(T) <= 32 MiB, where S =
+ *   ceil(n_steps / C), nseg = ceil(n_steps / S), C = n_ckpt (0: ceil(sqrt(n_steps)),
+ *   clamped to n_steps).  Larger requests return ROM_E_INVAL before anything
+ *   is enqueued.
+ *   The array is one per device, held until the process ends, and shared by
+ *   every handle on that device: calls that overlap on one device (two
+ *   streams, or two host threads) race on it and must be serialised by the
+ *   caller.  Every byte the call reads from it was written earlier in the
+ *   same call, so nothing carries over from a previous call.
+ *   The call makes no allocation: no hipMalloc, hipFree or allocating library
+ *   routine.  The handle must be used on the device it was created on.
+ * Errors: as fom_rollout_vjp, plus ROM_E_INVAL when the plan exceeds the
+ * array, ROM_E_STATE when the current device is not the handle's.
+ */
+rom_status fom_rollout_vjp_noalloc(rom_handle h, const void* q0, int32_t n_steps, double dt,
+                                   int32_t n_ckpt, const void* gbar, void* gq0, void* stream);
+
+/*
  * rom_online_vjp - gradient through the online part of Alg. 1 (an extension
  * beyond the paper): n_fine fine Galerkin steps from the current state, with
  * the adaptation events that fall due (coarse backward-Euler step of y_corr,

@@ -3,9 +3,16 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <string>
 
 #include "internal.h"
+
+// Device scratch of the entry points that allocate nothing
+// (fom_rollout_vjp_noalloc): 32 MiB per device, held until the process ends.
+static constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace romhip {
 
@@ -409,7 +416,8 @@ rom_status offline(rom_batch* h, const void* q0, hipStream_t s) {
   return ROM_OK;
 }
 
-// ---- the rollout adjoint's checkpoint plan and body
+// ---- the rollout adjoint's checkpoint plan and body (shared by the
+// allocating entry point and the one that runs in the static device scratch)
 struct RolloutPlan {
   int64_t T = 0, S = 0, nseg = 0;  // steps, steps per segment, checkpoints
   size_t st = 0;                    // bytes of one state
@@ -471,6 +479,41 @@ rom_status rollout_vjp_impl(rom_batch* h, const void* q0, double dt, const Rollo
   return ROM_OK;
 }
 
+// ---- the static device scratch (top of this file): each device holds its
+// own copy of the array; its address is looked up once per device (with that
+// device current) and kept.  In host code the array's name is not a device
+// address: only the looked-up pointer is passed on.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Look up the scratch address of the current device (once per device).
+rom_status scratch_resolve_current(int* dev_out) {
+  int dev = 0;
+  ROM_HIP_CHECK(hipGetDevice(&dev));
+  ROM_REQUIRE(dev >= 0 && dev < kMaxDevices, ROM_E_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    ROM_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    ROM_REQUIRE(p, ROM_E_DEVICE, "hipGetSymbolAddress returned no address for the scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  if (dev_out) *dev_out = dev;
+  return ROM_OK;
+}
+
+// The scratch of the device the handle was created on (resolved at rom_create).
+rom_status scratch_of_handle(const rom_batch* h, void** out) {
+  int cur = 0;
+  ROM_HIP_CHECK(hipGetDevice(&cur));
+  ROM_REQUIRE(cur == h->device, ROM_E_STATE, "the handle's device is not the current device");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  ROM_REQUIRE(g_scratch_ptr[h->device], ROM_E_STATE, "device scratch not resolved for this device");
+  *out = g_scratch_ptr[h->device];
+  return ROM_OK;
+}
+
 }  // namespace
 
 rom_status fill_zero(void* p, size_t bytes, hipStream_t s) {
@@ -499,7 +542,8 @@ rom_status rom_create(const rom_config* cfg, const void* q0, void* stream, rom_h
   h->phys.assign(cfg->phys, cfg->phys + (size_t)cfg->n_inst * cfg->n_phys);
   h->cfg.n_cells = nullptr;
   h->cfg.phys = nullptr;
-  rom_status st = setup(h);
+  rom_status st = scratch_resolve_current(&h->device);
+  if (st == ROM_OK) st = setup(h);
   hipStream_t s = (hipStream_t)stream;
   h->last_stream = s;
   if (st == ROM_OK && q0) st = offline(h, q0, s);
@@ -708,6 +752,22 @@ rom_status fom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, double
     h->rvjp_bytes = pl.bytes;
   }
   return rollout_vjp_impl(h, q0, dt, pl, gbar, gq0, (char*)h->rvjp, s);
+}
+
+rom_status fom_rollout_vjp_noalloc(rom_handle h, const void* q0, int32_t n_steps, double dt,
+                                   int32_t n_ckpt, const void* gbar, void* gq0, void* stream) {
+  ROM_TRY(rollout_check(h, q0, n_steps, dt, n_ckpt, gbar, gq0));
+  const RolloutPlan pl = rollout_plan(h, n_steps, n_ckpt);
+  if (pl.bytes > kScratchBytes) {
+    set_error("fom_rollout_vjp_noalloc: the checkpoints need " + std::to_string(pl.bytes) +
+              " bytes, more than the " + std::to_string(kScratchBytes) + "-byte device scratch");
+    return ROM_E_INVAL;
+  }
+  void* ws = nullptr;
+  ROM_TRY(scratch_of_handle(h, &ws));
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  return rollout_vjp_impl(h, q0, dt, pl, gbar, gq0, (char*)ws, s);
 }
 
 rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const void* qbar,

@@ -95,6 +95,7 @@ struct rom_batch {
   romhip::Tile* d_btiles2 = nullptr; // kBigTile/2-cell tiles
   int n_btiles2 = 0;
   int n_cu = 256;                    // compute units of the device
+  int device = 0;                    // HIP device the handle was created on
   int tune_residual = 0;             // chosen launch shape of the streaming residual
   romhip::Tile* d_ptiles = nullptr;  // row tiles of kPassRows basis rows
   int n_ptiles = 0;

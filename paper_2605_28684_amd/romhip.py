@@ -74,6 +74,7 @@ def _load():
         "fom_residual_vjp": [vp, vp, vp, d, vp, vp, vp, vp],
         "fom_step_vjp": [vp, vp, d, vp, vp, vp],
         "fom_rollout_vjp": [vp, vp, i32, d, i32, vp, vp, vp],
+        "fom_rollout_vjp_noalloc": [vp, vp, i32, d, i32, vp, vp, vp],
         "rom_online_vjp": [vp, i32, i32, vp, vp, vp, vp, vp, vp],
         "rom_autotune": [vp, i32, vp, ctypes.POINTER(i32), vp],
         "rom_set_tuning": [vp, i32, i32, ctypes.POINTER(i32)],
@@ -93,7 +94,8 @@ def _load():
 LIB = _load()
 SYMBOLS = ("rom_create", "rom_destroy", "fom_residual", "fom_step", "isvd_update", "rom_rebuild",
            "rom_step", "rom_get", "rom_set", "rom_get_status", "rom_clear_status",
-           "fom_residual_vjp", "fom_step_vjp", "fom_rollout_vjp", "rom_online_vjp", "rom_autotune",
+           "fom_residual_vjp", "fom_step_vjp", "fom_rollout_vjp", "fom_rollout_vjp_noalloc",
+           "rom_online_vjp", "rom_autotune",
            "rom_set_tuning", "rom_query", "rom_profile", "rom_last_error")
 TUNE_RESIDUAL = 0
 PROF_RESIDUAL, PROF_GALERKIN_PASS, PROF_ISVD_PROJECT, PROF_RESIDUAL_VJP, PROF_FOM_STEP = range(5)
@@ -205,6 +207,15 @@ class RomBatch:
         out = self._new(self.total_dof) if out is None else out
         _check(LIB.fom_rollout_vjp(self.h, _ptr(q0), int(n_steps), float(dt), int(n_ckpt),
                                    _ptr(gbar), _ptr(out), _stream()))
+        return out
+
+    def fom_rollout_vjp_noalloc(self, q0, n_steps, dt, gbar, n_ckpt=0, out=None):
+        """fom_rollout_vjp with its checkpoints in the library's static device
+        array (no allocation inside the call; out must be given to allocate
+        nothing at all)."""
+        out = self._new(self.total_dof) if out is None else out
+        _check(LIB.fom_rollout_vjp_noalloc(self.h, _ptr(q0), int(n_steps), float(dt), int(n_ckpt),
+                                           _ptr(gbar), _ptr(out), _stream()))
         return out
 
     def online_vjp(self, n_fine, qbar, n_ckpt=0):
