@@ -114,7 +114,10 @@ enum {
   ROM_GET_QREF = 6,    /* T[total_dof]           reference state             */
   ROM_GET_DVAR = 7,    /* double[n_inst * n_var] diagonal of D per variable  */
   ROM_GET_PINV = 8,    /* double[n_inst * r * n_s] (P^T Phi)^+ row-major     */
-  ROM_GET_COUNTERS = 9 /* int64[4] host: fine step n, updates k, events, reorths */
+  ROM_GET_COUNTERS = 9, /* int64[4] host: fine step n, updates k, events, reorths */
+  ROM_GET_UBAR = 10    /* double[n_inst * (r+1) * (r+1)] (get only) left singular vectors
+                          of the last update's core K (eq. isvd_core_matrix), row-major,
+                          columns in descending order of the singular values */
 };
 
 /*
@@ -186,6 +189,39 @@ rom_status rom_step(rom_handle h, int32_t n_fine, void* stream);
 /* copy a handle quantity to (get) or from (set) caller device memory; see ROM_GET_* */
 rom_status rom_get(rom_handle h, int32_t what, void* dst, void* stream);
 rom_status rom_set(rom_handle h, int32_t what, const void* src, void* stream);
+
+/*
+ * rom_save / rom_load - the whole state the online loop of Alg. 1 carries from
+ * one fine step to the next, so that a run can stop and resume (or fork) with
+ * the same bits: the basis Phi, sigma, the reduced coordinates a, the
+ * correction state y_corr (Alg. 1 keeps it between events), q_ref, the
+ * diagonal of D, the flag words, the sample rows P and (P^T Phi)^+, and the
+ * host counters (fine step n, updates, events, re-orthonormalisations).
+ * Format: a 128-byte header of int64 words (magic "ROMHIPS1", version,
+ * problem, precision, n_inst, total_dof, r, n_s, n_var, a hash of the
+ * instance sizes, the four counters, total bytes, hyper), then the sections in
+ * the order above, each on a 256-byte boundary, in the handle's element types.
+ *
+ * rom_save(h, dst, &bytes, stream): dst == NULL only stores the size needed in
+ *   *bytes.  Otherwise dst is caller-owned device memory of at least *bytes
+ *   (8-byte aligned); the copies are enqueued on stream (kernels only, no
+ *   synchronisation) and *bytes receives the size written.
+ *   Errors: ROM_E_INVAL (NULL handle or bytes, dst too small or misaligned),
+ *   ROM_E_STATE (no reduced state).
+ * rom_load(h, src, bytes, stream): src is device memory written by rom_save
+ *   for a handle of the same configuration and instance sizes.  The call
+ *   synchronises the stream, reads and checks the header, then enqueues the
+ *   copies and, with DEIM, a rebuild from the restored basis (the sample mesh
+ *   and the column-major basis copy are derived data; the rebuild recomputes
+ *   them with the same kernels, so P and (P^T Phi)^+ come back bit for bit).
+ *   Window graphs captured earlier are discarded.  A handle created with
+ *   q0 == NULL becomes usable for rom_step after a load.
+ *   Errors: ROM_E_INVAL (NULL arguments, bytes too small, misaligned, not a
+ *   saved state of this version, or a different configuration or layout):
+ *   the handle is left unchanged.
+ */
+rom_status rom_save(rom_handle h, void* dst, size_t* bytes, void* stream);
+rom_status rom_load(rom_handle h, const void* src, size_t bytes, void* stream);
 
 /* synchronise the handle's last stream and copy the per-instance flag words to host */
 rom_status rom_get_status(rom_handle h, uint32_t* host_flags);

@@ -514,6 +514,67 @@ rom_status scratch_of_handle(const rom_batch* h, void** out) {
   return ROM_OK;
 }
 
+// ---- saved handle state (rom_save / rom_load): a 128-byte header of int64
+// words, then the sections below, each starting on a 256-byte boundary.
+constexpr int64_t kSaveMagic = 0x31535049484d4f52ll;  // "ROMHIPS1"
+constexpr int64_t kSaveVersion = 1;
+enum { kSecPhi, kSecSigma, kSecA, kSecYcorr, kSecQref, kSecDvar, kSecFlags, kSecP, kSecM, kNumSec };
+struct SaveHeader { int64_t w[16]; };
+struct SaveLayout {
+  size_t off[kNumSec];
+  size_t len[kNumSec];
+  size_t total;
+};
+
+SaveLayout save_layout(const rom_batch* h) {
+  const size_t B = h->cfg.n_inst, r = h->cfg.r, td = h->total_dof;
+  const size_t ns = std::max(h->cfg.n_s, 1);
+  SaveLayout L;
+  L.len[kSecPhi] = h->esz * td * r;
+  L.len[kSecSigma] = 8 * B * r;
+  L.len[kSecA] = 8 * B * r;
+  L.len[kSecYcorr] = h->esz * td;
+  L.len[kSecQref] = h->esz * td;
+  L.len[kSecDvar] = 8 * B * h->nv;
+  L.len[kSecFlags] = 4 * B;
+  L.len[kSecP] = 4 * B * ns;
+  L.len[kSecM] = 8 * B * r * ns;
+  size_t o = sizeof(SaveHeader);
+  for (int i = 0; i < kNumSec; ++i) {
+    o = (o + 255) & ~(size_t)255;
+    L.off[i] = o;
+    o += L.len[i];
+  }
+  L.total = o;
+  return L;
+}
+
+// FNV-1a over the instance sizes: a loaded state must come from the same layout.
+int64_t layout_hash(const rom_batch* h) {
+  uint64_t x = 1469598103934665603ull;
+  for (int64_t n : h->n_cells) {
+    for (int k = 0; k < 8; ++k) {
+      x ^= (uint64_t)((n >> (8 * k)) & 0xff);
+      x *= 1099511628211ull;
+    }
+  }
+  return (int64_t)(x >> 1);
+}
+
+SaveHeader save_header(const rom_batch* h, const SaveLayout& L) {
+  SaveHeader hd{};
+  const rom_config& c = h->cfg;
+  const int64_t v[16] = {kSaveMagic, kSaveVersion, c.problem, c.precision, c.n_inst, h->total_dof,
+                         c.r, c.n_s, h->nv, layout_hash(h), h->n_fine, h->n_update, h->n_events,
+                         h->n_reorth, (int64_t)L.total, c.hyper};
+  for (int i = 0; i < 16; ++i) hd.w[i] = v[i];
+  return hd;
+}
+
+__global__ void k_write_header(SaveHeader hd, int64_t* dst) {
+  if (threadIdx.x < 16) dst[threadIdx.x] = hd.w[threadIdx.x];
+}
+
 }  // namespace
 
 rom_status fill_zero(void* p, size_t bytes, hipStream_t s) {
@@ -670,6 +731,7 @@ rom_status rom_get(rom_handle h, int32_t what, void* dst, void* stream) {
     case ROM_GET_QREF: return copy_words(h->q_ref, dst, h->esz * td, s);
     case ROM_GET_DVAR: return copy_words(h->d_var, dst, 8 * (size_t)B * h->nv, s);
     case ROM_GET_PINV: return copy_words(h->M, dst, 8 * (size_t)B * r * std::max(h->cfg.n_s, 1), s);
+    case ROM_GET_UBAR: return copy_words(h->ubar, dst, 8 * (size_t)B * (r + 1) * (r + 1), s);
     case ROM_GET_COUNTERS: {
       int64_t* o = (int64_t*)dst;
       o[0] = h->n_fine; o[1] = h->n_update; o[2] = h->n_events; o[3] = h->n_reorth;
@@ -703,6 +765,64 @@ rom_status rom_set(rom_handle h, int32_t what, const void* src, void* stream) {
   }
   set_error("quantity cannot be set");
   return ROM_E_INVAL;
+}
+
+rom_status rom_save(rom_handle h, void* dst, size_t* bytes, void* stream) {
+  ROM_REQUIRE(h && bytes, ROM_E_INVAL, "handle and bytes are required");
+  const SaveLayout L = save_layout(h);
+  if (!dst) {
+    *bytes = L.total;
+    return ROM_OK;
+  }
+  ROM_REQUIRE(*bytes >= L.total, ROM_E_INVAL, "dst is smaller than the saved state");
+  ROM_REQUIRE(h->has_rom, ROM_E_STATE, "no reduced state to save");
+  ROM_REQUIRE(((uintptr_t)dst & 7) == 0, ROM_E_INVAL, "dst must be 8-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  char* d = (char*)dst;
+  hipLaunchKernelGGL(k_write_header, dim3(1), dim3(64), 0, s, save_header(h, L), (int64_t*)d);
+  const void* src[kNumSec] = {h->Phi, h->sigma, h->a, h->y_corr, h->q_ref, h->d_var, h->flags,
+                              h->P, h->M};
+  for (int i = 0; i < kNumSec; ++i) ROM_TRY(copy_words(src[i], d + L.off[i], L.len[i], s));
+  *bytes = L.total;
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+rom_status rom_load(rom_handle h, const void* src, size_t bytes, void* stream) {
+  ROM_REQUIRE(h && src, ROM_E_INVAL, "handle and src are required");
+  ROM_REQUIRE(((uintptr_t)src & 7) == 0, ROM_E_INVAL, "src must be 8-byte aligned");
+  const SaveLayout L = save_layout(h);
+  ROM_REQUIRE(bytes >= L.total, ROM_E_INVAL, "src is smaller than this handle's saved state");
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  SaveHeader got{};
+  ROM_HIP_CHECK(hipStreamSynchronize(s));
+  ROM_HIP_CHECK(hipMemcpy(got.w, src, sizeof(got.w), hipMemcpyDeviceToHost));
+  const SaveHeader want = save_header(h, L);
+  ROM_REQUIRE(got.w[0] == kSaveMagic && got.w[1] == kSaveVersion, ROM_E_INVAL,
+              "src does not hold a saved romhip state of this version");
+  for (int i = 2; i < 10; ++i)
+    ROM_REQUIRE(got.w[i] == want.w[i], ROM_E_INVAL,
+                "the saved state comes from a different configuration or layout");
+  ROM_REQUIRE(got.w[14] == (int64_t)L.total && got.w[15] == want.w[15], ROM_E_INVAL,
+              "the saved state comes from a different configuration");
+  for (auto& g : h->win_exec)
+    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+  const char* p = (const char*)src;
+  void* dst[kNumSec] = {h->Phi, h->sigma, h->a, h->y_corr, h->q_ref, h->d_var, h->flags,
+                        h->P, h->M};
+  for (int i = 0; i < kNumSec; ++i) ROM_TRY(copy_words(p + L.off[i], dst[i], L.len[i], s));
+  h->n_fine = got.w[10];
+  h->n_update = got.w[11];
+  h->n_events = got.w[12];
+  h->n_reorth = got.w[13];
+  h->has_rom = true;
+  // the sample mesh and the column-major copy are derived from the basis:
+  // the rebuild recomputes them (and P, (P^T Phi)^+) with the same kernels
+  ROM_TRY(launch_rebuild(h, s));
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
 }
 
 rom_status rom_get_status(rom_handle h, uint32_t* host_flags) {

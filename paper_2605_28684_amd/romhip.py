@@ -29,7 +29,7 @@ STATUS = {0: "ROM_OK", -1: "ROM_E_INVAL", -2: "ROM_E_NOMEM", -3: "ROM_E_DEVICE",
 FLAG_NEWTON_NOCONV, FLAG_FLOOR, FLAG_NONFINITE, FLAG_RHO_ZERO = 1, 2, 4, 8
 FLAG_SINGULAR, FLAG_ROM_NOCONV, FLAG_REORTH = 16, 32, 64
 GET_BASIS, GET_SIGMA, GET_A, GET_QTILDE, GET_SAMPLES, GET_YCORR = 0, 1, 2, 3, 4, 5
-GET_QREF, GET_DVAR, GET_PINV, GET_COUNTERS = 6, 7, 8, 9
+GET_QREF, GET_DVAR, GET_PINV, GET_COUNTERS, GET_UBAR = 6, 7, 8, 9, 10
 
 
 class RomError(RuntimeError):
@@ -70,6 +70,8 @@ def _load():
         "rom_get": [vp, i32, vp, vp],
         "rom_set": [vp, i32, vp, vp],
         "rom_get_status": [vp, vp],
+        "rom_save": [vp, vp, ctypes.POINTER(ctypes.c_size_t), vp],
+        "rom_load": [vp, vp, ctypes.c_size_t, vp],
         "rom_clear_status": [vp, vp],
         "fom_residual_vjp": [vp, vp, vp, d, vp, vp, vp, vp],
         "fom_step_vjp": [vp, vp, d, vp, vp, vp],
@@ -93,7 +95,7 @@ def _load():
 
 LIB = _load()
 SYMBOLS = ("rom_create", "rom_destroy", "fom_residual", "fom_step", "isvd_update", "rom_rebuild",
-           "rom_step", "rom_get", "rom_set", "rom_get_status", "rom_clear_status",
+           "rom_step", "rom_get", "rom_set", "rom_save", "rom_load", "rom_get_status", "rom_clear_status",
            "fom_residual_vjp", "fom_step_vjp", "fom_rollout_vjp", "fom_rollout_vjp_noalloc",
            "rom_online_vjp", "rom_autotune",
            "rom_set_tuning", "rom_query", "rom_profile", "rom_last_error")
@@ -245,13 +247,15 @@ class RomBatch:
 
     _SIZES = {GET_BASIS: ("T", "dof*r"), GET_SIGMA: ("f64", "B*r"), GET_A: ("f64", "B*r"),
               GET_QTILDE: ("T", "dof"), GET_SAMPLES: ("i32", "B*ns"), GET_YCORR: ("T", "dof"),
-              GET_QREF: ("T", "dof"), GET_DVAR: ("f64", "B*nv"), GET_PINV: ("f64", "B*r*ns")}
+              GET_QREF: ("T", "dof"), GET_DVAR: ("f64", "B*nv"), GET_PINV: ("f64", "B*r*ns"),
+              GET_UBAR: ("f64", "B*n*n")}
 
     def _shape(self, what):
         kind, n = self._SIZES[what]
         size = {"dof*r": self.total_dof * self.r, "B*r": self.n_inst * self.r,
                 "dof": self.total_dof, "B*ns": self.n_inst * max(self.n_s, 1),
-                "B*nv": self.n_inst * self.n_var, "B*r*ns": self.n_inst * self.r * max(self.n_s, 1)}[n]
+                "B*nv": self.n_inst * self.n_var, "B*r*ns": self.n_inst * self.r * max(self.n_s, 1),
+                "B*n*n": self.n_inst * (self.r + 1) ** 2}[n]
         dt = {"T": self.dtype, "f64": torch.float64, "i32": torch.int32}[kind]
         return size, dt
 
@@ -276,6 +280,20 @@ class RomBatch:
             raise ValueError("expected %d elements, got %d" % (n, src.numel()))
         _check(LIB.rom_set(self.h, what, _ptr(src), _stream()))
         torch.cuda.current_stream().synchronize()
+
+    def save(self, out=None):
+        """The handle's online state as a device byte tensor (rom_save)."""
+        n = ctypes.c_size_t(0)
+        _check(LIB.rom_save(self.h, None, ctypes.byref(n), _stream()))
+        if out is None:
+            out = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        n = ctypes.c_size_t(out.numel())
+        _check(LIB.rom_save(self.h, _ptr(out), ctypes.byref(n), _stream()))
+        return out
+
+    def load(self, blob):
+        """Restore a state written by save() (rom_load; synchronises the stream)."""
+        _check(LIB.rom_load(self.h, _ptr(blob), ctypes.c_size_t(blob.numel()), _stream()))
 
     def autotune(self, what, q):
         """Pick the fastest result-invariant launch shape; returns its index."""
