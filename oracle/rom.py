@@ -9,6 +9,7 @@ Each function follows one passage of the paper, in its order and notation:
   isvd_update         Alg. 2 with eqs. isvd_residual .. isvd_truncation; p by
                       classical Gram-Schmidt applied twice (equals Phi^+ y for
                       orthonormal Phi); rho -> 0 guard; SVD of the core K
+                      (isvd_core), then the rotation and truncation (isvd_rotate)
   reorth              re-orthonormalisation schedule (not in the paper, which
                       states none is needed; kept as a guard for FP32 storage)
   deim_greedy         greedy DEIM (the interpolation-residual argmax rule of the
@@ -63,13 +64,13 @@ def pod(Xhat, r):
 
 
 # ------------------------------------------------------------------ Alg. 2
-def isvd_update(Phi, sigma, yhat, lam, r, tau_rho=1e-12):
-    """One Brand update with forgetting factor lam (Alg. 2).
-
-    Returns (Phi_new, sigma_new, info) where info holds p, rho, the core K and its
-    left singular vectors Ubar (sign-fixed, descending order)."""
+def isvd_core(Phi, sigma, yhat, lam, tau_rho=1e-12):
+    """The first half of one Brand update (Alg. 2): the projection p and the
+    residual q by two passes of classical Gram-Schmidt (p = Phi^+ yhat for
+    orthonormal Phi, eq. isvd_residual), rho = ||q|| with the rho -> 0 guard,
+    the core K (eq. isvd_core_matrix) and its left singular vectors Ubar
+    (sign-fixed, descending order) and values sbar.  Returns a dict."""
     N, k = Phi.shape
-    # p = Phi^+ yhat by two passes of classical Gram-Schmidt (orthonormal Phi)
     p = Phi.T @ yhat
     q = yhat - Phi @ p
     p2 = Phi.T @ q
@@ -79,9 +80,6 @@ def isvd_update(Phi, sigma, yhat, lam, r, tau_rho=1e-12):
     degenerate = rho <= tau_rho * np.linalg.norm(yhat)
     if degenerate:
         rho = 0.0
-        j = np.zeros(N)
-    else:
-        j = q / rho
     K = np.zeros((k + 1, k + 1))
     K[:k, :k] = lam * np.diag(sigma)
     K[:k, k] = p
@@ -97,10 +95,25 @@ def isvd_update(Phi, sigma, yhat, lam, r, tau_rho=1e-12):
     else:
         Ub, sb, _ = np.linalg.svd(K)
         Ub = sign_fix(Ub)
-    Phi_t = np.concatenate([Phi, j[:, None]], axis=1) @ Ub
-    r_out = min(r, k + 1)
-    info = dict(p=p, rho=rho, K=K, Ubar=Ub, sbar=sb, degenerate=degenerate)
-    return Phi_t[:, :r_out], sb[:r_out].copy(), info
+    return dict(p=p, q=q, rho=rho, K=K, Ubar=Ub, sbar=sb, degenerate=degenerate)
+
+
+def isvd_rotate(Phi, q, rho, Ubar, r):
+    """The second half of Alg. 2: [Phi, q/rho] Ubar (eq. isvd_updated_basis_full)
+    truncated to its leading r columns (eq. isvd_truncation); the residual
+    direction is zero when rho = 0."""
+    j = q / rho if rho > 0.0 else np.zeros(Phi.shape[0])
+    Phi_t = np.concatenate([Phi, j[:, None]], axis=1) @ Ubar
+    return Phi_t[:, :min(r, Phi.shape[1] + 1)]
+
+
+def isvd_update(Phi, sigma, yhat, lam, r, tau_rho=1e-12):
+    """One Brand update with forgetting factor lam (Alg. 2): isvd_core, then
+    isvd_rotate.  Returns (Phi_new, sigma_new, info) where info holds p, q,
+    rho, the core K, Ubar and sbar."""
+    info = isvd_core(Phi, sigma, yhat, lam, tau_rho)
+    Phi_new = isvd_rotate(Phi, info["q"], info["rho"], info["Ubar"], r)
+    return Phi_new, info["sbar"][:Phi_new.shape[1]].copy(), info
 
 
 def reorth(Phi, tau_orth):
