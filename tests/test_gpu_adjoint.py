@@ -95,10 +95,12 @@ def test_online_vjp_matches_oracle_fp64():
                                       qbar[sl])
         # measured: a ~1e-13, Phi and y_corr ~5e-12; sigma's gradient is ~1e-7 the
         # size of the others, so its FP64 round-off shows as ~2e-9 relative
-        assert G.relerr(ab[b * R:(b + 1) * R], ra) < 1e-10, (b, G.relerr(ab[b * R:(b + 1) * R], ra))
-        assert G.relerr(pb[off[b] * R:off[b + 1] * R], rP.reshape(-1)) < 1e-10, b
-        assert G.relerr(sb[b * R:(b + 1) * R], rs) < 1e-8, (b, sb[b * R:(b + 1) * R], rs)
-        assert G.relerr(yb[sl], ry) < 1e-10, (b, G.relerr(yb[sl], ry))
+        G.assert_close(ab[b * R:(b + 1) * R], ra, 1e-11, what=str(b))
+        G.assert_close(pb[off[b] * R:off[b + 1] * R], rP.reshape(-1), 1e-11, what=str(b))
+        # sigma-bar is small and formed by cancellation over a few steps
+        # (measured 2e-9 relative to its own size); the bound is 1e-8
+        G.assert_close(sb[b * R:(b + 1) * R], rs, 1e-8, what=str(b))
+        G.assert_close(yb[sl], ry, 1e-11, what=str(b))
 
 
 def test_online_vjp_fp32_storage_near_oracle():
@@ -121,7 +123,7 @@ def test_online_vjp_fp32_storage_near_oracle():
         for got, ref in ((ab[b * R:(b + 1) * R], ra), (pb[off[b] * R:off[b + 1] * R], rP.reshape(-1)),
                          (sb[b * R:(b + 1) * R], rs), (yb[sl], ry)):
             assert np.all(np.isfinite(got))
-            assert G.relerr(got, ref) < 1e-2, (b, G.relerr(got, ref))
+            G.assert_close(got, ref, 1e-2, what=str((b, G.relerr(got, ref))))
 
 
 def test_online_vjp_checkpoint_invariance_and_end_state():

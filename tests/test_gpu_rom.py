@@ -76,14 +76,14 @@ def test_isvd_update_parity(precision, lam, r):
         Pr, sr, info = O.isvd_update(Phis[b], sig[b], yhat, lam, r, tau_rho=w.tau_rho)
         ar = O.transfer(Phis[b], Pr, a[b])
         Pg = P2[off[b] * r:off[b + 1] * r].reshape(n, r)
-        assert G.relerr(s2[b * r:(b + 1) * r], sr) < tol
+        G.assert_close(s2[b * r:(b + 1) * r], sr, tol)
         # vectors are determined (up to sign) only for simple nonzero singular values;
         # with lambda = 0 the core has rank one and only the first column is
         keep = 1 if lam == 0.0 else r
         Pa = G.align_signs(Pg[:, :keep], Pr[:, :keep])
-        assert G.relerr(Pa, Pr[:, :keep]) < 50 * tol, b
+        G.assert_close(Pa, Pr[:, :keep], tol, what=str(b))
         sg = np.sign(np.sum(Pg[:, :keep] * Pr[:, :keep], axis=0))
-        assert G.relerr(sg * a2[b * r:b * r + keep], ar[:keep]) < 50 * tol, b
+        G.assert_close(sg * a2[b * r:b * r + keep], ar[:keep], tol, what=str(b))
 
 
 def test_reorth_parity_fp32():
@@ -115,11 +115,11 @@ def test_reorth_parity_fp32():
         Pr2, L = O.reorth(Pr, w.tau_orth)
         assert L is not None
         # same span
-        assert G.relerr(Pg @ (Pg.T @ Pr2), Pr2) < 1e-5
+        G.assert_close(Pg @ (Pg.T @ Pr2), Pr2, 1e-5)
         # the carried coordinates keep the lifted state: closed-form transfer
         # Ubar[:r,:r]^T a, then L^T for the re-orthonormalised basis
         a_ref = L.T @ (info["Ubar"][:r, :r].T @ a[b])
-        assert G.relerr(Pg @ a2[b * r:(b + 1) * r], Pr2 @ a_ref) < 1e-5
+        G.assert_close(Pg @ a2[b * r:(b + 1) * r], Pr2 @ a_ref, 1e-5)
     assert np.all(h.status() & 64)
 
 
@@ -131,15 +131,16 @@ def test_offline_stage_parity_fp64():
     h = _handle(w, q0=G.to_dev(w.q0, W.F64))
     st = O.offline(W.BURGERS, w.phys[0], w.q0, w.params())
     assert G.relerr(G.host(h.get(R.GET_QREF)), st["q_ref"]) == 0.0
-    assert G.relerr(G.host(h.get(R.GET_DVAR)), st["d_var"]) < 1e-12
-    assert G.relerr(G.host(h.get(R.GET_SIGMA)), st["sigma"]) < 1e-11
+    G.assert_close(G.host(h.get(R.GET_DVAR)), st["d_var"], 1e-12)
+    G.assert_close(G.host(h.get(R.GET_SIGMA)), st["sigma"], 1e-11)
     Pg = G.host(h.get(R.GET_BASIS)).reshape(256, 6)
     # both sides are exact SVDs; the column signs are fixed on different factors,
-    # so compare after aligning signs (q~ = q_ref + D^-1 Phi a is sign-invariant)
+    # so compare after aligning signs (q~ = q_ref + D^-1 Phi a is sign-invariant);
+    # measured 3e-12 elementwise
     sg = np.sign(np.sum(Pg * st["Phi"], axis=0))
-    assert G.relerr(Pg * sg, st["Phi"]) < 1e-9
-    assert G.relerr(G.host(h.get(R.GET_A)) * sg, st["a"]) < 1e-9
-    assert G.relerr(G.host(h.get(R.GET_YCORR)), st["y_corr"]) < 1e-11
+    G.assert_close(Pg * sg, st["Phi"], 1e-11)
+    G.assert_close(G.host(h.get(R.GET_A)) * sg, st["a"], 1e-11)
+    G.assert_close(G.host(h.get(R.GET_YCORR)), st["y_corr"], 1e-11)
 
 
 def test_galerkin_steps_and_events_parity_fp64():
@@ -166,8 +167,8 @@ def test_galerkin_steps_and_events_parity_fp64():
         ag = G.host(h.get(R.GET_A))
         ref = O.reconstruct(st["q_ref"], st["d"], st["Phi"], st["a"])
         qg = G.host(h.get(R.GET_QTILDE))
-        assert G.relerr(qg, ref) < 1e-10, (k, G.relerr(qg, ref))
-        assert G.relerr(G.host(h.get(R.GET_SIGMA)), st["sigma"]) < 1e-10
+        G.assert_close(qg, ref, 1e-11, what=str(k))
+        G.assert_close(G.host(h.get(R.GET_SIGMA)), st["sigma"], 1e-11)
     assert h.get(R.GET_COUNTERS)[2] == 2
 
 
@@ -209,11 +210,11 @@ def test_isvd_update_clustered_sigma_and_zero_weights_fp64():
         Pg = P2[off[b] * r:off[b + 1] * r].reshape(n, r)
         sg = s2[b * r:(b + 1) * r]
         Po, so, info = O.isvd_update(Phis[b], sigs[b], ys[b], w.lam, r, w.tau_rho)
-        assert G.relerr(sg, so) < 1e-12, b
+        G.assert_close(sg, so, 1e-12, what=str(b))
         assert np.max(np.abs(Pg.T @ Pg - np.eye(r))) < 1e-12, b
         Cg = (Pg * sg ** 2) @ Pg.T
         Co = (Po * so ** 2) @ Po.T
-        assert G.relerr(Cg, Co) < 1e-11, b
+        G.assert_close(Cg, Co, 1e-11, what=str(b))
 
 
 @pytest.mark.parametrize("problem", [W.EULER_HLLC, W.REACT])
@@ -254,8 +255,8 @@ def test_hr_lspg_steps_and_events_parity_fp64(problem):
             np.testing.assert_array_equal(h.get(R.GET_SAMPLES).cpu().numpy(), st["P"])
         ref = O.reconstruct(st["q_ref"], st["d"], st["Phi"], st["a"])
         qg = G.host(h.get(R.GET_QTILDE))
-        assert G.relerr(qg, ref) < 1e-10, (k, G.relerr(qg, ref))
-        assert G.relerr(G.host(h.get(R.GET_SIGMA)), st["sigma"]) < 1e-10, k
+        G.assert_close(qg, ref, 1e-11, what=str(k))
+        G.assert_close(G.host(h.get(R.GET_SIGMA)), st["sigma"], 1e-11, what=str(k))
     assert events == 3 and h.get(R.GET_COUNTERS)[2] == 3
     assert not (h.status() & (4 | 16 | 32)).any()
 
@@ -287,8 +288,8 @@ def test_hr_lspg_fine_steps_at_reacting_sizes_fp64():
         O.rom_fine_step(W.REACT, w.phys[0], st, prm)
         ref = O.reconstruct(st["q_ref"], st["d"], st["Phi"], st["a"])
         qg = G.host(h.get(R.GET_QTILDE))
-        assert G.relerr(qg, ref) < 1e-10, (k, G.relerr(qg, ref))
-        assert G.relerr(G.host(h.get(R.GET_A)), st["a"]) < 1e-9, k
+        G.assert_close(qg, ref, 1e-11, what=str(k))
+        G.assert_close(G.host(h.get(R.GET_A)), st["a"], 1e-11, what=str(k))
     assert not (h.status() & (4 | 16 | 32)).any()
 
 
@@ -312,7 +313,7 @@ def test_deim_rows_bit_exact_and_pinv(precision):
     for b in range(2):
         ref = O.deim_greedy(Phis[b], ns)
         np.testing.assert_array_equal(P[b], ref)
-        assert G.relerr(M[b], O.rebuild(Phis[b], ref)) < 1e-12
+        G.assert_close(M[b], O.rebuild(Phis[b], ref), 1e-12)
 
 
 @pytest.mark.parametrize("precision", [W.F64, W.F32])
@@ -341,7 +342,7 @@ def test_deim_rows_bit_exact_at_maximum_sizes(precision):
         ref = O.deim_greedy(Phis[b], ns)
         np.testing.assert_array_equal(P[b], ref)
         assert len(set(P[b].tolist())) == ns
-        assert G.relerr(M[b], O.rebuild(Phis[b], ref)) < 1e-11
+        G.assert_close(M[b], O.rebuild(Phis[b], ref), 1e-11)
     assert not (h.status() & 16).any()
 
 
@@ -410,7 +411,7 @@ def test_hr_lspg_step_parity(problem):
     h.rom_step(1)
     a1, it, ok = O.hr_lspg_step(problem, phys, q_ref, d, Phi, P, M, a, dt, w.rom_tol, w.rom_max)
     assert ok
-    assert G.relerr(G.host(h.get(R.GET_A)), a1) < 1e-11
+    G.assert_close(G.host(h.get(R.GET_A)), a1, 1e-11)
 
 
 @pytest.mark.parametrize("r", [32, 64])
@@ -449,7 +450,7 @@ def test_galerkin_step_tail_iterations_fp32(r):
         d = np.full(n, dv[b][0])
         ar, it, ok = O.galerkin_step(W.BURGERS, w.phys[b], qref[sl], d, Phis[b], a[b], w.dt,
                                      1e-12, w.rom_max)
-        assert G.relerr(ag[b * r:(b + 1) * r], ar) < 1e-5, b
+        G.assert_close(ag[b * r:(b + 1) * r], ar, 1e-5, what=str(b))
 
 
 @pytest.mark.parametrize("r", [8, 32, 64])
@@ -485,7 +486,7 @@ def test_galerkin_fine_step_parity_fp32(r):
         ar, it, ok = O.galerkin_step(W.BURGERS, w.phys[b], qref[sl], d, Phis[b], a[b], w.dt,
                                      w.rom_tol, w.rom_max)
         assert ok
-        assert G.relerr(ag[b * r:(b + 1) * r], ar) < 1e-5, b
+        G.assert_close(ag[b * r:(b + 1) * r], ar, 1e-5, what=str(b))
 
 
 def test_graph_windows_overlap_bitwise_eager_and_oracle_fp32():
@@ -540,6 +541,6 @@ def test_graph_windows_overlap_bitwise_eager_and_oracle_fp32():
                 O.adaptation_event(W.BURGERS, w.phys[b], st, prm)
         sl = slice(off[b], off[b + 1])
         ref = O.reconstruct(st["q_ref"], st["d"], st["Phi"], st["a"])
-        assert G.relerr(out[True]["GET_QTILDE"][sl], ref) < 1e-5, b
-        assert G.relerr(out[True]["GET_YCORR"][sl], st["y_corr"]) < 1e-5, b
-        assert G.relerr(out[True]["GET_SIGMA"][b * 32:(b + 1) * 32], st["sigma"]) < 1e-5, b
+        G.assert_close(out[True]["GET_QTILDE"][sl], ref, 1e-5, what=str(b))
+        G.assert_close(out[True]["GET_YCORR"][sl], st["y_corr"], 1e-5, what=str(b))
+        G.assert_close(out[True]["GET_SIGMA"][b * 32:(b + 1) * 32], st["sigma"], 1e-5, what=str(b))
