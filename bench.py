@@ -17,7 +17,8 @@ roofline     = dominant kernel of the step, timed live with HIP events on the
                launch stream, against the 8 TB/s HBM peak
 fom_residual = R(q) on the 64 x 262,144-cell Euler (Rusanov, FP32) shape:
                cell-updates/s and fraction of the HBM roofline (24 B/cell)
-cpu_baseline = the FP64 CPU checker timed on a bounded sample of the same workload
+cpu_baseline = the FP64 CPU oracle timed on a bounded sample of the same workload
+               (cores = BLAS threads it used; affinity_cores and cpu_model describe the host)
 """
 import argparse
 import json
@@ -40,9 +41,21 @@ MFMA_F32_TFLOPS = 157.3
 # summaries of those runs are kept in the profiles directory.
 COPY_SCALE = {"fetch": 524288.0 / 262157.4, "write": 1.0}
 MEASURED_KIB = {
-    "k_galerkin_pass": {"fetch": 133474.3, "write": 4245.8},
-    # streaming Euler residual, shape 8 (512-cell tiles, 7 blocks/CU, non-temporal)
-    "k_residual_euler/8": {"fetch": 105506.6, "write": 196608.0},
+    "k_galerkin_mfma<32>": {"fetch": 133474.3, "write": 4245.8},
+    # streaming Euler residual on the 64 x 262,144-cell shape, every launch shape
+    # of the autotuner (bench.py --only residual walks them in order)
+    "k_residual_euler/0": {"fetch": 101935.9, "write": 196608.0},
+    "k_residual_euler/1": {"fetch": 101933.5, "write": 196608.0},
+    "k_residual_euler/2": {"fetch": 105501.6, "write": 196608.0},
+    "k_residual_euler/3": {"fetch": 105501.6, "write": 196608.0},
+    "k_residual_euler/4": {"fetch": 105501.5, "write": 196608.0},
+    "k_residual_euler/5": {"fetch": 112663.1, "write": 196608.0},
+    "k_residual_euler/6": {"fetch": 112668.1, "write": 196608.0},
+    "k_residual_euler/7": {"fetch": 101936.4, "write": 196608.0},
+    "k_residual_euler/8": {"fetch": 105509.0, "write": 196608.1},
+    "k_residual_euler/9": {"fetch": 105508.9, "write": 196608.0},
+    "k_residual_euler/10": {"fetch": 112663.9, "write": 196608.0},
+    "k_residual_euler/11": {"fetch": 112664.5, "write": 196608.0},
 }
 
 
@@ -114,9 +127,21 @@ def cpu_baseline(w, budget_s):
     per_cell_step = t_total / cells
     value = 1.0 / (per_cell_step * mean_cells)
     return dict(value=value, unit="steps/s", cores=int(threads), kind="oracle",
+                affinity_cores=len(os.sched_getaffinity(0)), cpu_model=_cpu_model(),
                 sample="%d instance-steps of 4 instances (N=%s) in whole windows, %.1f s; "
                        "scaled by mean N of the batch" % (steps, [w.n_cells[b] for b in picks],
                                                          t_total))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def _timed(torch, fn, reps):
@@ -265,13 +290,16 @@ def profile_only(args, torch, W, R):
             h.close()
         log("galerkin pass: %.5f ms per launch" % ms)
     else:
+        # every launch shape in turn, reps launches each (dispatch order: shape
+        # 0's launches first), so counter runs give the traffic of each shape
         we = W.euler_adjoint_f32(n_inst=64, n=262144)
         he = R.RomBatch(we, q0=None, use_graph=False)
         qe = torch.as_tensor(we.q0, dtype=torch.float32, device="cuda")
-        he.autotune(R.TUNE_RESIDUAL, qe)
-        ms = he.profile(R.PROF_RESIDUAL, reps, qe)
+        for i in range(he.set_tuning(R.TUNE_RESIDUAL, -1)):
+            he.set_tuning(R.TUNE_RESIDUAL, i)
+            ms = he.profile(R.PROF_RESIDUAL, reps, qe)
+            log("residual shape %d: %.5f ms per launch" % (i, ms))
         he.close()
-        log("residual: %.5f ms per launch" % ms)
     return 0
 
 
@@ -323,13 +351,14 @@ def main():
         tot = h.total_dof
         bytes_pass = tot * r * 4 + tot * 4 + 2 * 2 * r * 4 * w.n_inst  # basis, q_ref, halo rows
         achieved = bytes_pass / (ms_pass * 1e-3) / 1e9
-        roofline = dict(kernel="k_galerkin_pass", bound="hbm", achieved=round(achieved, 1),
+        kname = "k_galerkin_mfma<%d>" % r          # the name kernel traces give it
+        roofline = dict(kernel=kname, bound="hbm", achieved=round(achieved, 1),
                         peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                        traffic=traffic_bytes("k_galerkin_pass"), ms_per_launch=round(ms_pass, 5),
+                        traffic=traffic_bytes(kname), ms_per_launch=round(ms_pass, 5),
                         bytes_per_launch=int(bytes_pass))
         # the same pass against the FP32 MFMA peak: 2 N r^2 flops per launch
         flops_pass = 2.0 * tot * r * r
-        roofline_mfma = dict(kernel="k_galerkin_pass", bound="mfma",
+        roofline_mfma = dict(kernel=kname, bound="mfma",
                              achieved=round(flops_pass / (ms_pass * 1e-3) / 1e12, 2),
                              peak=MFMA_F32_TFLOPS, unit="TFLOP/s",
                              frac=round(flops_pass / (ms_pass * 1e-3) / 1e12 / MFMA_F32_TFLOPS, 4))
