@@ -18,6 +18,9 @@ Each function follows one passage of the paper, in its order and notation:
   rebuild             (P^T Phi)^+ (eq. qdeim_approximation_phi)
   galerkin_step       backward Euler applied to eq. galerkin_continuous_rom
   hr_lspg_step        Gauss-Newton on eq. hyperreduced_lspg
+  wsvd_update         App. A, Alg. A.1 (windowed SVD over the last w snapshots)
+  direct_update       App. A, Alg. A.2 (the Direct rule), with orth() read as the
+                      left singular vectors of its argument
   transfer            Alg. 1 state transfer a <- Phi_new^T D (q~ - q_ref)
   adaptive_rom        Alg. 1
 
@@ -127,6 +130,34 @@ def reorth(Phi, tau_orth):
     return np.linalg.solve(L, Phi.T).T, L
 
 
+# ------------------------------------------------------------------ App. A: windowed rules
+def window_matrix(window):
+    """The preprocessed window (eq. wsvd_window_matrix): columns oldest first."""
+    return np.stack(window, axis=1)
+
+
+def wsvd_update(Yw, r):
+    """Windowed SVD (App. A, Alg. A.1): the leading r left singular vectors of the
+    window matrix and its leading r singular values (eq. wsvd_update)."""
+    U, s, _ = np.linalg.svd(Yw, full_matrices=False)
+    return sign_fix(U[:, :r]), s[:r].copy()
+
+
+def orth(A):
+    """orth(.) of Alg. A.2, read as an orthonormal basis of range(A) from the
+    SVD: the left singular vectors, in descending order, sign-fixed."""
+    U, _, _ = np.linalg.svd(A, full_matrices=False)
+    return sign_fix(U)
+
+
+def direct_update(Phi, Yw):
+    """Direct update (App. A, Alg. A.2; eqs. direct_optimization and
+    direct_update): Z = Phi^+ Yw with Phi^+ = Phi^T for the orthonormal basis,
+    Phi~ = Yw Z^+ (pseudo-inverse with numpy's default cut-off), then orth."""
+    Z = Phi.T @ Yw
+    return orth(Yw @ np.linalg.pinv(Z))
+
+
 # ------------------------------------------------------------------ Sec. 3.2 sampling
 def deim_greedy(Phi, n_s):
     """Greedy DEIM row selection with oversampling.
@@ -233,7 +264,7 @@ def default_params(**kw):
     p = dict(r=4, n_s=4, w_init=4, N_t=20, z=2, lam=0.5, dt=1e-3,
              newton_tol=1e-8, newton_max=10, rom_tol=1e-12, rom_max=10,
              reorth_every=16, tau_orth=1e-12, tau_rho=1e-12,
-             projection="galerkin", hyper="none")
+             projection="galerkin", hyper="none", update="isvd", window=0)
     p.update(kw)
     return p
 
@@ -255,6 +286,11 @@ def offline(problem, phys, q0, prm):
     y_corr, _, _ = F.newton_be_step(problem, q_last, z * dt, phys, tol, mx)
     st = dict(q_ref=q_ref, d_var=d_var, d=d, Phi=Phi, sigma=sigma, a=a,
               y_corr=y_corr, n_update=0, Q_train=Q_train, P=None, M=None)
+    if prm.get("update", "isvd") != "isvd":
+        # the window starts from the last training snapshots (at most w of them)
+        w = prm["window"]
+        st["window"] = [d * (Q_train[:, j] - q_ref)
+                        for j in range(max(0, Q_train.shape[1] - w), Q_train.shape[1])]
     if prm["hyper"] == "deim":
         st["P"] = deim_greedy(Phi, prm["n_s"])
         st["M"] = rebuild(Phi, st["P"])
@@ -268,8 +304,23 @@ def adaptation_event(problem, phys, st, prm):
                                           prm["newton_tol"], prm["newton_max"])
     yhat = st["d"] * (st["y_corr"] - st["q_ref"])
     Phi_old = st["Phi"]
-    Phi, sigma, info = isvd_update(Phi_old, st["sigma"], yhat, prm["lam"], prm["r"],
-                                   prm["tau_rho"])
+    rule = prm.get("update", "isvd")
+    if rule == "isvd":
+        Phi, sigma, info = isvd_update(Phi_old, st["sigma"], yhat, prm["lam"], prm["r"],
+                                       prm["tau_rho"])
+    else:
+        # the oldest snapshot leaves the window once it holds w
+        st["window"].append(yhat)
+        if len(st["window"]) > prm["window"]:
+            st["window"].pop(0)
+        Yw = window_matrix(st["window"])
+        info = None
+        if rule == "wsvd":
+            Phi, sigma = wsvd_update(Yw, prm["r"])
+        elif rule == "direct":
+            Phi, sigma = direct_update(Phi_old, Yw), st["sigma"]
+        else:
+            raise ValueError("unknown update rule %r" % (rule,))
     st["n_update"] += 1
     if prm["reorth_every"] > 0 and st["n_update"] % prm["reorth_every"] == 0:
         Phi, _ = reorth(Phi, prm["tau_orth"])

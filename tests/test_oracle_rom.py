@@ -330,3 +330,72 @@ def test_burgers_512_trajectory_is_sensitive_to_basis_rounding():
     assert s1["sigma"][-1] / s1["sigma"][0] < 1e-12
     assert drift[0] < 1e-13
     assert 1e-10 < max(drift) < 1e-7
+
+
+# ---------------------------------------------------------------- App. A rules
+def test_wsvd_is_the_best_rank_r_approximation_of_the_window():
+    """Alg. A.1: the captured energy equals the Eckart-Young optimum, computed
+    here from the eigenvalues of the window's Gram matrix (a different route
+    than the SVD the rule uses); the basis is orthonormal; rank-r data is
+    reproduced exactly."""
+    rng = np.random.default_rng(31)
+    N, m, r = 300, 9, 4
+    Yw = rng.normal(size=(N, m)) @ np.diag(np.linspace(3, 0.2, m))
+    Phi, s = O.wsvd_update(Yw, r)
+    lam = np.sort(np.linalg.eigvalsh(Yw.T @ Yw))[::-1]
+    resid = np.linalg.norm(Yw - Phi @ (Phi.T @ Yw)) ** 2
+    assert abs(resid - lam[r:].sum()) <= 1e-10 * lam.sum()
+    assert np.allclose(s ** 2, lam[:r], rtol=1e-12)
+    assert np.max(np.abs(Phi.T @ Phi - np.eye(r))) < 1e-13
+    A = rng.normal(size=(N, r))
+    Phi2, _ = O.wsvd_update(A @ rng.normal(size=(r, m)), r)
+    Pa = A @ np.linalg.solve(A.T @ A, A.T)
+    assert np.max(np.abs(Phi2 @ Phi2.T - Pa)) < 1e-12
+
+
+def test_direct_update_normal_equations_and_fixed_point():
+    """Alg. A.2: Phi~ = Yw Z^+ solves the least-squares problem of eq.
+    direct_optimization, so its residual satisfies the normal equations
+    (Phi~ Z - Yw) Z^T = 0; the new basis is orthonormal, spans range(Phi~) and
+    diagonalises Phi~ Phi~^T; a window inside span(Phi) leaves the subspace
+    unchanged."""
+    rng = np.random.default_rng(32)
+    N, r, m = 250, 4, 7
+    Phi, _ = np.linalg.qr(rng.normal(size=(N, r)))
+    Yw = rng.normal(size=(N, m))
+    Z = Phi.T @ Yw
+    Phit = Yw @ np.linalg.pinv(Z)
+    assert np.max(np.abs((Phit @ Z - Yw) @ Z.T)) < 1e-10 * np.linalg.norm(Yw) ** 2
+    P1 = O.direct_update(Phi, Yw)
+    assert np.max(np.abs(P1.T @ P1 - np.eye(r))) < 1e-13
+    assert np.max(np.abs(P1 @ (P1.T @ Phit) - Phit)) < 1e-12 * np.linalg.norm(Phit)
+    # orth() gives the left singular vectors of Phi~: they diagonalise its Gram
+    # matrix, largest first (another basis of the same range would not)
+    G = (P1.T @ Phit) @ (Phit.T @ P1)
+    off = G - np.diag(np.diag(G))
+    assert np.max(np.abs(off)) < 1e-10 * np.max(np.abs(G))
+    assert np.all(np.diff(np.diag(G)) < 0)
+    Yin = Phi @ rng.normal(size=(r, m))
+    P2 = O.direct_update(Phi, Yin)
+    assert np.max(np.abs(P2 @ P2.T - Phi @ Phi.T)) < 1e-12
+
+
+@pytest.mark.parametrize("rule", ["wsvd", "direct"])
+def test_windowed_rules_in_alg1_roll_the_window(rule):
+    """The driver keeps the last w preprocessed correction snapshots: it starts
+    from the last training snapshots and drops the oldest at each event; the
+    basis stays orthonormal and the transfer keeps the lifted state's
+    projection."""
+    w = W.burgers_512_f64(n=96, N_t=40, w_init=6, r=4, z=3)
+    prm = w.params()
+    prm.update(update=rule, window=5)
+    st = O.offline(W.BURGERS, w.phys[0], w.q0, prm)
+    assert len(st["window"]) == 5
+    assert np.allclose(st["window"][-1], st["d"] * (st["Q_train"][:, -1] - st["q_ref"]))
+    for k in range(4):
+        Phi_old, a_old = st["Phi"], st["a"].copy()
+        O.adaptation_event(W.BURGERS, w.phys[0], st, prm)
+        assert len(st["window"]) == 5
+        assert np.allclose(st["window"][-1], st["d"] * (st["y_corr"] - st["q_ref"]))
+        assert np.max(np.abs(st["Phi"].T @ st["Phi"] - np.eye(4))) < 1e-12
+        assert np.allclose(st["a"], st["Phi"].T @ (Phi_old @ a_old))
