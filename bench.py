@@ -226,6 +226,22 @@ def config_measurements(torch, W, R):
             note="backward-Euler Newton steps at dt = 0.064/N; the adjoint call runs the "
                  "forward pass, the checkpointed recomputation and the transposed solves")
         h.close()
+        # cost of one basis update per rule (App. A) on the batched Burgers shape
+        # and the Sod shape: iSVD (Alg. 2), windowed SVD (Alg. A.1), Direct (Alg. A.2)
+        rules = {}
+        for name, mk, window in (("C2_burgers_batch_f32", W.burgers_batch_f32, 40),
+                                 ("C3_sod_hllc_65536_f32", W.sod_hllc_f32, 48)):
+            per = {}
+            for rule in ("isvd", "wsvd", "direct"):
+                w = mk()
+                w.update, w.window = rule, window
+                h = R.RomBatch(w, q0=torch.as_tensor(w.q0, dtype=torch.float32, device="cuda"),
+                               use_graph=False)
+                y = h.get(R.GET_YCORR).clone()
+                per[rule] = round(_timed(torch, lambda: h.isvd_update(y), 3), 4)
+                h.close()
+            rules[name] = dict(ms_per_update=per, window=window, r=mk().r)
+        out["update_rules"] = rules
     return out
 
 
@@ -322,6 +338,29 @@ def main():
     z = w.z
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
+        # FOM residual roofline on the 64 x 262,144 Euler shape (403 MB per evaluation),
+        # measured first, on a GPU that has not yet run the minute of batched work
+        # below (measured later in the run, the same launches take about 3% longer)
+        we = W.euler_adjoint_f32(n_inst=64, n=262144)
+        he = R.RomBatch(we, q0=None, use_graph=False)
+        qe = torch.as_tensor(we.q0, dtype=torch.float32, device="cuda")
+        shape = he.autotune(R.TUNE_RESIDUAL, qe)
+        he.profile(R.PROF_RESIDUAL, 3, qe)
+        ms_res = he.profile(R.PROF_RESIDUAL, 50, qe)
+        cells = 64 * 262144
+        res_bytes = cells * 3 * 4 * 2
+        res_gbs = res_bytes / (ms_res * 1e-3) / 1e9
+        fom = dict(workload="euler_rusanov_64x262144_f32", ms_per_launch=round(ms_res, 5),
+                   cell_updates_per_s=cells / (ms_res * 1e-3), achieved_GBs=round(res_gbs, 1),
+                   frac_hbm=round(res_gbs / HBM_PEAK_GBS, 4), bytes_per_launch=res_bytes,
+                   tuned_shape=int(shape), traffic=traffic_bytes("k_residual_euler/%d" % shape))
+        ms_vjp = he.profile(R.PROF_RESIDUAL_VJP, 20, qe)
+        fom["vjp_ms_per_launch"] = round(ms_vjp, 5)
+        fom["vjp_frac_hbm"] = round(cells * 3 * 4 * 3 / (ms_vjp * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        he.close()
+        log("R(q): %.4f ms, %.3g cell-updates/s, %.1f%% of HBM" % (ms_res, fom["cell_updates_per_s"],
+                                                                100 * fom["frac_hbm"]))
+
         q0 = torch.as_tensor(w.q0, dtype=torch.float32, device="cuda")
         t0 = time.time()
         h = R.RomBatch(w, q0=q0, use_graph=True)
@@ -400,27 +439,6 @@ def main():
             for hb in hs:
                 hb.close()
             log("plain: %.4g instance-steps/s (speed-up %.2fx)" % (plain_value, value / plain_value))
-
-        # FOM residual roofline on the 64 x 262,144 Euler shape (403 MB per evaluation)
-        we = W.euler_adjoint_f32(n_inst=64, n=262144)
-        he = R.RomBatch(we, q0=None, use_graph=False)
-        qe = torch.as_tensor(we.q0, dtype=torch.float32, device="cuda")
-        shape = he.autotune(R.TUNE_RESIDUAL, qe)
-        he.profile(R.PROF_RESIDUAL, 3, qe)
-        ms_res = he.profile(R.PROF_RESIDUAL, 50, qe)
-        cells = 64 * 262144
-        res_bytes = cells * 3 * 4 * 2
-        res_gbs = res_bytes / (ms_res * 1e-3) / 1e9
-        fom = dict(workload="euler_rusanov_64x262144_f32", ms_per_launch=round(ms_res, 5),
-                   cell_updates_per_s=cells / (ms_res * 1e-3), achieved_GBs=round(res_gbs, 1),
-                   frac_hbm=round(res_gbs / HBM_PEAK_GBS, 4), bytes_per_launch=res_bytes,
-                   tuned_shape=int(shape), traffic=traffic_bytes("k_residual_euler/%d" % shape))
-        ms_vjp = he.profile(R.PROF_RESIDUAL_VJP, 20, qe)
-        fom["vjp_ms_per_launch"] = round(ms_vjp, 5)
-        fom["vjp_frac_hbm"] = round(cells * 3 * 4 * 3 / (ms_vjp * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-        he.close()
-        log("R(q): %.4f ms, %.3g cell-updates/s, %.1f%% of HBM" % (ms_res, fom["cell_updates_per_s"],
-                                                                100 * fom["frac_hbm"]))
 
     configs = None
     if not args.no_configs:

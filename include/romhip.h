@@ -71,6 +71,7 @@ enum { ROM_BURGERS = 0, ROM_EULER_RUSANOV = 1, ROM_EULER_HLLC = 2, ROM_REACT = 3
 enum { ROM_F32 = 0, ROM_F64 = 1 };
 enum { ROM_GALERKIN = 0, ROM_LSPG = 1 };
 enum { ROM_HR_NONE = 0, ROM_HR_DEIM = 1 };
+enum { ROM_UPDATE_ISVD = 0, ROM_UPDATE_WSVD = 1, ROM_UPDATE_DIRECT = 2 };
 
 /*
  * Batch configuration (Alg. 1 inputs: r, n_s, w_init, z, lambda; the time step
@@ -90,6 +91,19 @@ enum { ROM_HR_NONE = 0, ROM_HR_DEIM = 1 };
  *   tau_rho:    iSVD residual norm below tau_rho * ||y^|| is treated as zero
  *   use_graph:  rom_step captures each adaptation window (z fine steps plus the
  *               event) into a HIP graph on first use and replays it afterwards
+ *               (iSVD rule only; the windowed rules run their windows eagerly,
+ *               because the window's fill level is host state)
+ *   update_rule: the basis update of an adaptation event:
+ *               ROM_UPDATE_ISVD   Brand's incremental SVD (Alg. 2; the method)
+ *               ROM_UPDATE_WSVD   windowed SVD: the leading r left singular
+ *                                 vectors of the last `window` preprocessed
+ *                                 correction snapshots (App. A, Alg. A.1)
+ *               ROM_UPDATE_DIRECT the Direct rule (App. A, Alg. A.2):
+ *                                 Z = Phi^T Y, Phi~ = Y Z^+, Phi <- orth(Phi~)
+ *               The windowed rules keep the raw snapshots of a window of
+ *               `window` columns (r <= window <= 64); it starts from the last
+ *               min(window, w_init) training snapshots.  The state transfer is
+ *               Alg. 1's a <- Phi_new^T D (q~ - q_ref), formed in FP64.
  */
 typedef struct {
   int32_t problem, precision, projection, hyper;
@@ -100,6 +114,7 @@ typedef struct {
   int32_t r, n_s, w_init, z;
   int32_t newton_max, rom_max, reorth_every;
   int32_t use_graph;
+  int32_t update_rule, window;
   double lambda, dt, newton_tol, rom_tol, tau_orth, tau_rho;
 } rom_config;
 
@@ -114,10 +129,14 @@ enum {
   ROM_GET_QREF = 6,    /* T[total_dof]           reference state             */
   ROM_GET_DVAR = 7,    /* double[n_inst * n_var] diagonal of D per variable  */
   ROM_GET_PINV = 8,    /* double[n_inst * r * n_s] (P^T Phi)^+ row-major     */
-  ROM_GET_COUNTERS = 9, /* int64[4] host: fine step n, updates k, events, reorths */
-  ROM_GET_UBAR = 10    /* double[n_inst * (r+1) * (r+1)] (get only) left singular vectors
+  ROM_GET_COUNTERS = 9, /* int64[6] host: fine step n, updates k, events, reorths,
+                          window fill level, next window slot */
+  ROM_GET_UBAR = 10,   /* double[n_inst * (r+1) * (r+1)] (get only) left singular vectors
                           of the last update's core K (eq. isvd_core_matrix), row-major,
                           columns in descending order of the singular values */
+  ROM_GET_WINDOW = 11  /* T[window * total_dof] raw correction snapshots of the windowed
+                          rules, slot j at j * total_dof (slots in storage order; the
+                          fill level and next slot are in ROM_GET_COUNTERS) */
 };
 
 /*
@@ -197,10 +216,14 @@ rom_status rom_set(rom_handle h, int32_t what, const void* src, void* stream);
  * correction state y_corr (Alg. 1 keeps it between events), q_ref, the
  * diagonal of D, the flag words, the sample rows P and (P^T Phi)^+, and the
  * host counters (fine step n, updates, events, re-orthonormalisations).
- * Format: a 128-byte header of int64 words (magic "ROMHIPS1", version,
+ * With a windowed update rule the snapshot window and its fill level and
+ * next slot are part of the state too.
+ * Format: a 256-byte header of 32 int64 words (magic "ROMHIPS1", version,
  * problem, precision, n_inst, total_dof, r, n_s, n_var, a hash of the
- * instance sizes, the four counters, total bytes, hyper), then the sections in
- * the order above, each on a 256-byte boundary, in the handle's element types.
+ * instance sizes, the four counters, total bytes, hyper, update rule, window,
+ * window fill level, next window slot, then zeros), then the sections in the
+ * order above and the window last, each on a 256-byte boundary, in the
+ * handle's element types.
  *
  * rom_save(h, dst, &bytes, stream): dst == NULL only stores the size needed in
  *   *bytes.  Otherwise dst is caller-owned device memory of at least *bytes

@@ -20,7 +20,7 @@ Each function follows one passage of the paper, in its order and notation:
   hr_lspg_step        Gauss-Newton on eq. hyperreduced_lspg
   wsvd_update         App. A, Alg. A.1 (windowed SVD over the last w snapshots)
   direct_update       App. A, Alg. A.2 (the Direct rule), with orth() read as the
-                      left singular vectors of its argument
+                      Q factor of the thin QR with a positive diagonal of R
   transfer            Alg. 1 state transfer a <- Phi_new^T D (q~ - q_ref)
   adaptive_rom        Alg. 1
 
@@ -144,18 +144,23 @@ def wsvd_update(Yw, r):
 
 
 def orth(A):
-    """orth(.) of Alg. A.2, read as an orthonormal basis of range(A) from the
-    SVD: the left singular vectors, in descending order, sign-fixed."""
-    U, _, _ = np.linalg.svd(A, full_matrices=False)
-    return sign_fix(U)
+    """orth(.) of Alg. A.2, read as Gram-Schmidt orthonormalisation of the
+    columns: the Q factor of the thin QR factorisation with a positive diagonal
+    of R (unique for full column rank, and stable when A is nearly orthonormal,
+    as Phi~ is when the window lies near span(Phi))."""
+    Q, R = np.linalg.qr(A)
+    s = np.sign(np.diag(R))
+    s[s == 0] = 1.0
+    return Q * s[None, :]
 
 
 def direct_update(Phi, Yw):
     """Direct update (App. A, Alg. A.2; eqs. direct_optimization and
     direct_update): Z = Phi^+ Yw with Phi^+ = Phi^T for the orthonormal basis,
-    Phi~ = Yw Z^+ (pseudo-inverse with numpy's default cut-off), then orth."""
+    Phi~ = Yw Z^+ (pseudo-inverse: singular values below 1e-15 of the largest are
+    dropped), then orth."""
     Z = Phi.T @ Yw
-    return orth(Yw @ np.linalg.pinv(Z))
+    return orth(Yw @ np.linalg.pinv(Z, rcond=1e-15))
 
 
 # ------------------------------------------------------------------ Sec. 3.2 sampling

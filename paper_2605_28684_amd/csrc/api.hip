@@ -123,6 +123,11 @@ rom_status validate(const rom_config* c) {
   ROM_REQUIRE(c->rom_max >= 1 && c->rom_max <= 50, ROM_E_INVAL, "rom_max in [1, 50]");
   ROM_REQUIRE(c->newton_tol > 0.0 && c->rom_tol > 0.0, ROM_E_INVAL, "tolerances must be positive");
   ROM_REQUIRE(c->reorth_every >= 0, ROM_E_INVAL, "reorth_every must be >= 0");
+  ROM_REQUIRE(c->update_rule >= ROM_UPDATE_ISVD && c->update_rule <= ROM_UPDATE_DIRECT,
+              ROM_E_INVAL, "unknown update rule");
+  if (c->update_rule != ROM_UPDATE_ISVD)
+    ROM_REQUIRE(c->window >= c->r && c->window <= 64, ROM_E_INVAL,
+                "the windowed rules need r <= window <= 64");
   if (c->hyper == ROM_HR_DEIM) {
     ROM_REQUIRE(c->n_s >= c->r && c->n_s <= 2 * c->r && c->n_s <= kMaxNs, ROM_E_INVAL,
                 "n_s must be in [r, 2r] with DEIM");
@@ -147,12 +152,6 @@ rom_status alloc(T** p, size_t count) {
   return ROM_OK;
 }
 
-#define ROM_TRY(x)                 \
-  do {                             \
-    rom_status _s = (x);           \
-    if (_s != ROM_OK) return _s;   \
-  } while (0)
-
 void free_all(rom_batch* h) {
   void* ps[] = {h->d_dof_off, h->d_cell_off, h->d_phys, h->d_tiles, h->d_btiles, h->d_btiles2, h->d_ptiles, h->d_ptile_first,
                 h->Phi, h->sigma, h->a, h->a_prev, h->q_ref, h->d_var, h->y_corr, h->flags, h->P,
@@ -160,6 +159,9 @@ void free_all(rom_batch* h) {
                 h->active, h->iters, h->norms, h->rstate, h->qtmp, h->mpart, h->fq, h->fq_prev, h->vjp_tmp,
                 h->d_epoch, h->rvjp, h->epart, h->ev_iters, h->phi_cm, h->Phi_alt, h->hr_as, h->hr_cnt};
   for (void* p : ps) (void)hipFree(p);
+  void* pw[] = {h->win, h->lift, h->zmat, h->zpinv, h->phit, h->sig_scratch};
+  for (void* p : pw) (void)hipFree(p);
+  pod_ws_free(&h->podws);
   bt_free(h);
   for (auto& g : h->win_exec) if (g) (void)hipGraphExecDestroy(g);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
@@ -174,7 +176,8 @@ void free_all(rom_batch* h) {
 // coarse step is the one-workgroup kernel (its counters in ev_iters).  Only
 // the state transfer and the rotation of Phi need the fine steps done.
 bool window_split_ok(const rom_batch* h) {
-  return h->cfg.hyper == ROM_HR_NONE && mfma_ok(h) && h->fom_block;
+  return h->cfg.hyper == ROM_HR_NONE && h->cfg.update_rule == ROM_UPDATE_ISVD && mfma_ok(h) &&
+         h->fom_block;
 }
 
 rom_status setup(rom_batch* h) {
@@ -281,6 +284,15 @@ rom_status setup(rom_batch* h) {
   ROM_HIP_CHECK(hipMemset(h->P, 0, 4 * (size_t)B * ns));
   ROM_HIP_CHECK(hipMemset(h->a, 0, 8 * (size_t)B * r));
   ROM_HIP_CHECK(hipMemset(h->sigma, 0, 8 * (size_t)B * r));
+  if (c.update_rule != ROM_UPDATE_ISVD) {
+    ROM_TRY(alloc((char**)&h->win, es * td * c.window));
+    ROM_TRY(alloc(&h->lift, (size_t)td));
+    ROM_TRY(alloc(&h->zmat, (size_t)B * 64 * (r + 1)));
+    ROM_TRY(alloc(&h->zpinv, (size_t)B * 64 * r));
+    ROM_TRY(alloc((char**)&h->phit, es * td * r));
+    ROM_TRY(alloc(&h->sig_scratch, (size_t)B * r));
+    ROM_TRY(pod_ws_alloc(h, std::max(c.window, r), &h->podws));
+  }
   ROM_TRY(bt_setup(h));
   h->fom_block = fom_block_ok(h);
   if (window_split_ok(h)) {  // the second stream of a window (created outside any capture)
@@ -339,7 +351,8 @@ rom_status fom_step_impl(rom_batch* h, const void* q_prev, double dt, void* q_ou
 }
 
 rom_status isvd_impl(rom_batch* h, const void* y, hipStream_t s) {
-  ROM_TRY(launch_isvd(h, y, s));
+  if (h->cfg.update_rule == ROM_UPDATE_ISVD) ROM_TRY(launch_isvd(h, y, s));
+  else ROM_TRY(launch_windowed_update(h, y, s));
   h->n_update += 1;
   if (h->cfg.reorth_every > 0 && h->n_update % h->cfg.reorth_every == 0) {
     ROM_TRY(launch_reorth(h, s));
@@ -403,6 +416,7 @@ rom_status offline(rom_batch* h, const void* q0, hipStream_t s) {
   }
   if (st == ROM_OK) st = launch_preprocess(h, q0, Q, w, s);
   if (st == ROM_OK) st = launch_pod(h, Q, w, s);
+  if (st == ROM_OK && h->cfg.update_rule != ROM_UPDATE_ISVD) st = launch_window_init(h, Q, w, s);
   const void* qlast = Q + bytes * (w - 1);
   if (st == ROM_OK) st = launch_project_state(h, qlast, s);
   if (st == ROM_OK) st = fom_step_impl(h, qlast, h->cfg.z * h->cfg.dt, h->y_corr, nullptr, s);
@@ -514,12 +528,14 @@ rom_status scratch_of_handle(const rom_batch* h, void** out) {
   return ROM_OK;
 }
 
-// ---- saved handle state (rom_save / rom_load): a 128-byte header of int64
+// ---- saved handle state (rom_save / rom_load): a 256-byte header of int64
 // words, then the sections below, each starting on a 256-byte boundary.
 constexpr int64_t kSaveMagic = 0x31535049484d4f52ll;  // "ROMHIPS1"
 constexpr int64_t kSaveVersion = 1;
-enum { kSecPhi, kSecSigma, kSecA, kSecYcorr, kSecQref, kSecDvar, kSecFlags, kSecP, kSecM, kNumSec };
-struct SaveHeader { int64_t w[16]; };
+enum { kSecPhi, kSecSigma, kSecA, kSecYcorr, kSecQref, kSecDvar, kSecFlags, kSecP, kSecM, kSecWin,
+       kNumSec };
+constexpr int kHdrWords = 32;
+struct SaveHeader { int64_t w[kHdrWords]; };
 struct SaveLayout {
   size_t off[kNumSec];
   size_t len[kNumSec];
@@ -539,6 +555,7 @@ SaveLayout save_layout(const rom_batch* h) {
   L.len[kSecFlags] = 4 * B;
   L.len[kSecP] = 4 * B * ns;
   L.len[kSecM] = 8 * B * r * ns;
+  L.len[kSecWin] = h->win ? h->esz * td * h->cfg.window : 0;
   size_t o = sizeof(SaveHeader);
   for (int i = 0; i < kNumSec; ++i) {
     o = (o + 255) & ~(size_t)255;
@@ -564,15 +581,16 @@ int64_t layout_hash(const rom_batch* h) {
 SaveHeader save_header(const rom_batch* h, const SaveLayout& L) {
   SaveHeader hd{};
   const rom_config& c = h->cfg;
-  const int64_t v[16] = {kSaveMagic, kSaveVersion, c.problem, c.precision, c.n_inst, h->total_dof,
+  const int64_t v[20] = {kSaveMagic, kSaveVersion, c.problem, c.precision, c.n_inst, h->total_dof,
                          c.r, c.n_s, h->nv, layout_hash(h), h->n_fine, h->n_update, h->n_events,
-                         h->n_reorth, (int64_t)L.total, c.hyper};
-  for (int i = 0; i < 16; ++i) hd.w[i] = v[i];
+                         h->n_reorth, (int64_t)L.total, c.hyper, c.update_rule, c.window,
+                         h->win_count, h->win_head};
+  for (int i = 0; i < 20; ++i) hd.w[i] = v[i];
   return hd;
 }
 
 __global__ void k_write_header(SaveHeader hd, int64_t* dst) {
-  if (threadIdx.x < 16) dst[threadIdx.x] = hd.w[threadIdx.x];
+  if (threadIdx.x < kHdrWords) dst[threadIdx.x] = hd.w[threadIdx.x];
 }
 
 }  // namespace
@@ -673,7 +691,9 @@ rom_status rom_step(rom_handle h, int32_t n_fine, void* stream) {
   h->last_stream = s;
   const int z = h->cfg.z;
   int done = 0;
-  const bool graphs = h->cfg.use_graph && s != nullptr;
+  // the windowed rules keep their window's fill level and next slot on the
+  // host, so their windows run eagerly
+  const bool graphs = h->cfg.use_graph && s != nullptr && h->cfg.update_rule == ROM_UPDATE_ISVD;
   while (done < n_fine) {
     const int64_t pos = (h->n_fine - h->cfg.w_init) % z;  // steps since the last event
     const bool aligned = pos == 0 && n_fine - done >= z;
@@ -732,9 +752,13 @@ rom_status rom_get(rom_handle h, int32_t what, void* dst, void* stream) {
     case ROM_GET_DVAR: return copy_words(h->d_var, dst, 8 * (size_t)B * h->nv, s);
     case ROM_GET_PINV: return copy_words(h->M, dst, 8 * (size_t)B * r * std::max(h->cfg.n_s, 1), s);
     case ROM_GET_UBAR: return copy_words(h->ubar, dst, 8 * (size_t)B * (r + 1) * (r + 1), s);
+    case ROM_GET_WINDOW:
+      ROM_REQUIRE(h->win, ROM_E_STATE, "the handle keeps no snapshot window (iSVD rule)");
+      return copy_words(h->win, dst, h->esz * td * h->cfg.window, s);
     case ROM_GET_COUNTERS: {
       int64_t* o = (int64_t*)dst;
       o[0] = h->n_fine; o[1] = h->n_update; o[2] = h->n_events; o[3] = h->n_reorth;
+      o[4] = h->win_count; o[5] = h->win_head;
       return ROM_OK;
     }
   }
@@ -757,9 +781,16 @@ rom_status rom_set(rom_handle h, int32_t what, const void* src, void* stream) {
     case ROM_GET_YCORR: return copy_words(src, h->y_corr, h->esz * td, s);
     case ROM_GET_QREF: return copy_words(src, h->q_ref, h->esz * td, s);
     case ROM_GET_DVAR: return copy_words(src, h->d_var, 8 * (size_t)B * h->nv, s);
+    case ROM_GET_WINDOW:
+      ROM_REQUIRE(h->win, ROM_E_STATE, "the handle keeps no snapshot window (iSVD rule)");
+      return copy_words(src, h->win, h->esz * td * h->cfg.window, s);
     case ROM_GET_COUNTERS: {
       const int64_t* o = (const int64_t*)src;
+      if (h->win)
+        ROM_REQUIRE(o[4] >= 0 && o[4] <= h->cfg.window && o[5] >= 0 && o[5] < h->cfg.window,
+                    ROM_E_INVAL, "window fill level or slot out of range");
       h->n_fine = o[0]; h->n_update = o[1]; h->n_events = o[2]; h->n_reorth = o[3];
+      if (h->win) { h->win_count = (int)o[4]; h->win_head = (int)o[5]; }
       return ROM_OK;
     }
   }
@@ -782,7 +813,7 @@ rom_status rom_save(rom_handle h, void* dst, size_t* bytes, void* stream) {
   char* d = (char*)dst;
   hipLaunchKernelGGL(k_write_header, dim3(1), dim3(64), 0, s, save_header(h, L), (int64_t*)d);
   const void* src[kNumSec] = {h->Phi, h->sigma, h->a, h->y_corr, h->q_ref, h->d_var, h->flags,
-                              h->P, h->M};
+                              h->P, h->M, h->win};
   for (int i = 0; i < kNumSec; ++i) ROM_TRY(copy_words(src[i], d + L.off[i], L.len[i], s));
   *bytes = L.total;
   ROM_HIP_CHECK(hipGetLastError());
@@ -805,18 +836,24 @@ rom_status rom_load(rom_handle h, const void* src, size_t bytes, void* stream) {
   for (int i = 2; i < 10; ++i)
     ROM_REQUIRE(got.w[i] == want.w[i], ROM_E_INVAL,
                 "the saved state comes from a different configuration or layout");
-  ROM_REQUIRE(got.w[14] == (int64_t)L.total && got.w[15] == want.w[15], ROM_E_INVAL,
-              "the saved state comes from a different configuration");
+  ROM_REQUIRE(got.w[14] == (int64_t)L.total && got.w[15] == want.w[15] &&
+                  got.w[16] == want.w[16] && got.w[17] == want.w[17],
+              ROM_E_INVAL, "the saved state comes from a different configuration");
+  if (h->win)
+    ROM_REQUIRE(got.w[18] >= 0 && got.w[18] <= h->cfg.window && got.w[19] >= 0 &&
+                    got.w[19] < h->cfg.window,
+                ROM_E_INVAL, "damaged window counters in the saved state");
   for (auto& g : h->win_exec)
     if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
   const char* p = (const char*)src;
   void* dst[kNumSec] = {h->Phi, h->sigma, h->a, h->y_corr, h->q_ref, h->d_var, h->flags,
-                        h->P, h->M};
+                        h->P, h->M, h->win};
   for (int i = 0; i < kNumSec; ++i) ROM_TRY(copy_words(p + L.off[i], dst[i], L.len[i], s));
   h->n_fine = got.w[10];
   h->n_update = got.w[11];
   h->n_events = got.w[12];
   h->n_reorth = got.w[13];
+  if (h->win) { h->win_count = (int)got.w[18]; h->win_head = (int)got.w[19]; }
   h->has_rom = true;
   // the sample mesh and the column-major copy are derived from the basis:
   // the rebuild recomputes them (and P, (P^T Phi)^+) with the same kernels
@@ -900,6 +937,8 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
   ROM_REQUIRE(h->has_rom, ROM_E_STATE, "no reduced state");
   ROM_REQUIRE(h->cfg.hyper == ROM_HR_NONE && h->cfg.problem == ROM_BURGERS, ROM_E_UNSUPPORTED,
               "the online adjoint covers the Galerkin (Burgers) path only");
+  ROM_REQUIRE(h->cfg.update_rule == ROM_UPDATE_ISVD, ROM_E_UNSUPPORTED,
+              "the online adjoint covers the iSVD update only");
   const rom_config& c = h->cfg;
   const int B = c.n_inst, r = c.r, n = r + 1, z = c.z;
   const int64_t T = n_fine;

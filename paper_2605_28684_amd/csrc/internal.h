@@ -22,6 +22,12 @@ void set_error(const std::string& msg);
     }                                                                              \
   } while (0)
 
+#define ROM_TRY(x)                 \
+  do {                             \
+    rom_status _s = (x);           \
+    if (_s != ROM_OK) return _s;   \
+  } while (0)
+
 #define ROM_REQUIRE(cond, code, msg)      \
   do {                                    \
     if (!(cond)) {                        \
@@ -46,6 +52,18 @@ struct Tile {
 };
 
 constexpr int kBigTile = 1024;      // cells per block of the streaming Euler residual
+
+// Workspace of the batched thin SVD of N x w column matrices (CGS2-QR, then the
+// SVD of R): Q T[total_dof * wmax], R and U [n_inst * wmax^2], the per-instance
+// reductions and projection coefficients.
+struct PodWs {
+  void* Q = nullptr;
+  double* R = nullptr;
+  double* U = nullptr;
+  double* red = nullptr;
+  double* pr = nullptr;
+  int wmax = 0;
+};
 
 // One level of the recursive block-tridiagonal (Schur complement) solver.
 struct BtLevel {
@@ -145,6 +163,17 @@ struct rom_batch {
   void* rvjp = nullptr;      // rollout-adjoint checkpoints and segment states
   size_t rvjp_bytes = 0;
 
+  // windowed basis update rules (App. A)
+  void* win = nullptr;         // T[window * total_dof] raw correction snapshots (ring)
+  int win_count = 0;           // snapshots held
+  int win_head = 0;            // next slot written
+  double* lift = nullptr;      // [total_dof] Phi a before the update (FP64)
+  romhip::PodWs podws;         // thin-SVD workspace (wmax = max(window, r))
+  double* zmat = nullptr;      // [n_inst * 64 * (r+1)] Z = Phi^T Y by columns (Direct)
+  double* zpinv = nullptr;     // [n_inst * 64 * r] Z^+ (Direct)
+  void* phit = nullptr;        // T[r * total_dof] Y Z^+ by columns (Direct)
+  double* sig_scratch = nullptr; // [n_inst * r] singular values of Y Z^+ (Direct)
+
   // host counters
   int64_t n_fine = 0;        // fine step index n of Alg. 1 (starts at w_init)
   int64_t n_update = 0;      // iSVD updates done
@@ -217,6 +246,12 @@ rom_status convert_words(const void* src, bool src_f64, void* dst, bool dst_f64,
 rom_status adjoint_kernels_prepare();
 rom_status launch_reorth(rom_batch* h, hipStream_t s);
 rom_status launch_pod(rom_batch* h, const void* Q, int w, hipStream_t s);  // Q: T[w * total_dof]
+rom_status pod_ws_alloc(rom_batch* h, int wmax, PodWs* ws);
+// the windowed basis update rules (App. A) of an adaptation event, and the
+// window at the end of the offline stage
+rom_status launch_windowed_update(rom_batch* h, const void* y, hipStream_t s);
+rom_status launch_window_init(rom_batch* h, const void* Q, int w, hipStream_t s);
+void pod_ws_free(PodWs* ws);
 rom_status launch_preprocess(rom_batch* h, const void* q0, const void* Q, int w, hipStream_t s);
 rom_status launch_project_state(rom_batch* h, const void* q, hipStream_t s);  // a = Phi^T D (q - q_ref)
 

@@ -1,3 +1,4 @@
+#include <algorithm>
 // Incremental SVD (Alg. 2) and the offline POD / preprocessing on the device.
 //
 // Tall-skinny passes: a block owns a row tile (<= kPassRows rows of one
@@ -874,7 +875,7 @@ __global__ __launch_bounds__(256) void k_pod_write(const Tile* __restrict__ tile
     const int64_t lr = t.cell0 + rr, g = base + lr;
     double v;
     if (k == 0) {
-      v = yhat_of(y, qref, dvar + (size_t)b * nv, nv, g, lr);
+      v = qref ? yhat_of(y, qref, dvar + (size_t)b * nv, nv, g, lr) : (double)y[g];
     } else {
       double d2 = 0.0;
       for (int c = 0; c < k; ++c) d2 += (double)Q[g * w + c] * p[kMaxK + c];
@@ -1072,34 +1073,76 @@ rom_status reorth_t(rom_batch* h, hipStream_t s) {
   return ROM_OK;
 }
 
+}  // namespace
+
+rom_status pod_ws_alloc(rom_batch* h, int wmax, PodWs* ws) {
+  const size_t B = h->cfg.n_inst;
+  *ws = PodWs{};
+  ws->wmax = wmax;
+  const size_t ldr = 2 * kMaxK + 4, ldpr = 2 * kMaxK + 2;
+  if (hipMalloc(&ws->Q, h->esz * (size_t)h->total_dof * wmax) != hipSuccess ||
+      hipMalloc((void**)&ws->R, sizeof(double) * B * wmax * wmax) != hipSuccess ||
+      hipMalloc((void**)&ws->U, sizeof(double) * B * wmax * wmax) != hipSuccess ||
+      hipMalloc((void**)&ws->red, sizeof(double) * B * ldr) != hipSuccess ||
+      hipMalloc((void**)&ws->pr, sizeof(double) * B * ldpr) != hipSuccess) {
+    pod_ws_free(ws);
+    set_error("hipMalloc failed (thin-SVD workspace)");
+    return ROM_E_NOMEM;
+  }
+  return ROM_OK;
+}
+
+void pod_ws_free(PodWs* ws) {
+  (void)hipFree(ws->Q);
+  (void)hipFree(ws->R);
+  (void)hipFree(ws->U);
+  (void)hipFree(ws->red);
+  (void)hipFree(ws->pr);
+  *ws = PodWs{};
+}
+
+namespace {
+
 template <typename T>
-rom_status pod_t(rom_batch* h, const void* Qtrain, int w, hipStream_t s) {
+__global__ __launch_bounds__(256) void k_copy_t(const T* __restrict__ src, T* __restrict__ dst,
+                                                int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+// Left singular vectors of a batch of N x w column matrices by CGS2-QR (FP64
+// norms and the stored first-pass residual), then the Jacobi SVD of R and
+// the rotation Q U[:, :r] into phi_out, leading singular values into sigma_out
+// (reading R1).  Without svd (w == r) the Gram-Schmidt basis Q itself is the
+// result (R has a positive diagonal).  cols: T[w * total_dof], column j of every instance at
+// j * total_dof + dof_off[b]; with pre the columns are preprocessed on the
+// fly (D (y - q_ref)), otherwise taken as they are.  Kernels only (no
+// allocation, no memset, no synchronisation): usable inside a captured graph.
+template <typename T>
+rom_status pod_core_t(rom_batch* h, const void* cols, int w, bool pre, bool svd, const PodWs& ws,
+                      double* sigma_out, void* phi_out, hipStream_t s) {
   const int r = h->cfg.r, B = h->cfg.n_inst;
   const int64_t tot = h->total_dof;
-  T* Q = nullptr;
-  double* R = nullptr;
-  double* U = nullptr;
-  double* redp = nullptr;
-  double* prp = nullptr;
-  ROM_HIP_CHECK(hipMalloc((void**)&Q, sizeof(T) * tot * w));
-  ROM_HIP_CHECK(hipMalloc((void**)&R, sizeof(double) * B * w * w));
-  ROM_HIP_CHECK(hipMalloc((void**)&U, sizeof(double) * B * w * w));
+  T* Q = (T*)ws.Q;
+  double* R = ws.R;
+  double* U = ws.U;
+  double* redp = ws.red;
+  double* prp = ws.pr;
   const int ldr = 2 * kMaxK + 4;
-  ROM_HIP_CHECK(hipMalloc((void**)&redp, sizeof(double) * B * ldr));
-  ROM_HIP_CHECK(hipMalloc((void**)&prp, sizeof(double) * B * (2 * kMaxK + 2)));
-  ROM_HIP_CHECK(hipMemsetAsync(R, 0, sizeof(double) * B * w * w, s));
+  const T* qref = pre ? (const T*)h->q_ref : nullptr;
+  ROM_TRY(fill_zero(R, sizeof(double) * B * w * w, s));
   for (int k = 0; k < w; ++k) {
-    const T* yk = (const T*)Qtrain + (size_t)k * tot;
+    const T* yk = (const T*)cols + (size_t)k * tot;
     if (k > 0) {
-      project_t<T>(h, Q, w, k, yk, h->q_ref, nullptr, 0, 1, redp, ldr, s);
-      project_t<T>(h, Q, w, k, yk, h->q_ref, redp, ldr, 2, redp + kMaxK + 1, ldr, s, h->qtmp);
+      project_t<T>(h, Q, w, k, yk, qref, nullptr, 0, 1, redp, ldr, s);
+      project_t<T>(h, Q, w, k, yk, qref, redp, ldr, 2, redp + kMaxK + 1, ldr, s, h->qtmp);
     } else {
-      project_t<T>(h, Q, w, 0, yk, h->q_ref, nullptr, 0, 1, redp, ldr, s);
+      project_t<T>(h, Q, w, 0, yk, qref, nullptr, 0, 1, redp, ldr, s);
     }
     hipLaunchKernelGGL(k_pod_column, dim3(B), dim3(128), 0, s, k, w, redp, ldr, R, prp,
                        2 * kMaxK + 2);
     hipLaunchKernelGGL((k_pod_write<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
-                       h->d_dof_off, Q, w, k, yk, (const T*)h->q_ref, h->d_var, h->nv, prp,
+                       h->d_dof_off, Q, w, k, yk, qref, h->d_var, h->nv, prp,
                        2 * kMaxK + 2, h->qtmp, h->part);
     hipLaunchKernelGGL(k_reduce_tiles, dim3(B), dim3(128), 0, s, h->d_ptile_first, h->part, 0,
                        redp, ldr);
@@ -1107,18 +1150,191 @@ rom_status pod_t(rom_batch* h, const void* Qtrain, int w, hipStream_t s) {
     hipLaunchKernelGGL((k_pod_scale<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                        h->d_dof_off, Q, w, k, prp, 2 * kMaxK + 2);
   }
+  if (!svd) {   // the Gram-Schmidt basis itself (w == r columns, same row layout)
+    hipLaunchKernelGGL((k_copy_t<T>), dim3((unsigned)((tot * w + 255) / 256)), dim3(256), 0, s,
+                       (const T*)Q, (T*)phi_out, tot * w);
+    ROM_HIP_CHECK(hipGetLastError());
+    return ROM_OK;
+  }
   const size_t shm = sizeof(double) * (2 * w * w + 2 * w) + sizeof(int) * w;
-  hipLaunchKernelGGL(k_pod_svd, dim3(B), dim3(64), shm, s, w, r, R, U, h->sigma, 1);
+  hipLaunchKernelGGL(k_pod_svd, dim3(B), dim3(64), shm, s, w, r, R, U, sigma_out, 1);
   hipLaunchKernelGGL((k_rotate<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
-                     h->d_dof_off, (const T*)Q, w, w, (T*)h->Phi, r, r, U, w, (size_t)w * w, 0,
+                     h->d_dof_off, (const T*)Q, w, w, (T*)phi_out, r, r, U, w, (size_t)w * w, 0,
                      nullptr, nullptr, 0, nullptr);
   ROM_HIP_CHECK(hipGetLastError());
-  ROM_HIP_CHECK(hipStreamSynchronize(s));
-  ROM_HIP_CHECK(hipFree(Q));
-  ROM_HIP_CHECK(hipFree(R));
-  ROM_HIP_CHECK(hipFree(U));
-  ROM_HIP_CHECK(hipFree(redp));
-  ROM_HIP_CHECK(hipFree(prp));
+  return ROM_OK;
+}
+
+// ------------------------------------------------------------------ windowed rules
+// (App. A: the windowed SVD of Alg. A.1 and the Direct rule of Alg. A.2)
+constexpr int kMaxWin = 64;   // widest snapshot window
+
+// v = Phi a in FP64, row by row (the lifted state before the basis changes)
+template <typename T>
+__global__ __launch_bounds__(256) void k_lift(const Tile* __restrict__ tiles,
+                                              const int64_t* __restrict__ dof_off,
+                                              const T* __restrict__ Phi, int r,
+                                              const double* __restrict__ a,
+                                              double* __restrict__ v) {
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  const int64_t base = dof_off[b];
+  const double* ab = a + (size_t)b * r;
+  for (int64_t rr = threadIdx.x; rr < t.ncell; rr += blockDim.x) {
+    const int64_t g = base + t.cell0 + rr;
+    double s = 0.0;
+    for (int c = 0; c < r; ++c) s += (double)Phi[g * r + c] * ab[c];
+    v[g] = s;
+  }
+}
+
+// per-tile partials of Phi^T v (v FP64), same lane layout and summation order
+// as the projection pass: four row groups, lanes over columns
+template <typename T>
+__global__ __launch_bounds__(256) void k_project_vec(const Tile* __restrict__ tiles,
+                                                     const int64_t* __restrict__ dof_off,
+                                                     const T* __restrict__ Phi, int r,
+                                                     const double* __restrict__ v,
+                                                     double* __restrict__ part) {
+  __shared__ double red[4][kMaxR];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst, tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
+  const int64_t base = dof_off[b];
+  double acc = 0.0;
+  for (int64_t rr = grp; rr < t.ncell; rr += 4) {
+    const int64_t g = base + t.cell0 + rr;
+    if (lane < r) acc += (double)Phi[g * r + lane] * v[g];
+  }
+  if (lane < r) red[grp][lane] = acc;
+  __syncthreads();
+  for (int c = tid; c < r; c += blockDim.x)
+    part[(size_t)blockIdx.x * kPst + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+}
+
+// Z^+ (m x r) of Z = Phi^T Y (r x m, column j of instance b at
+// Z[(b * ldz + j) * (r + 1) + c]) by one-sided Jacobi on the rows of the
+// zero-padded m x m matrix [Z; 0]: after the sweeps G [Z; 0] has orthogonal
+// rows g_i with norms s_i, and Z^+ = sum_i g_i^T G[i, :r] / s_i^2 over the
+// values above 1e-15 of the largest.  One wavefront per instance.
+__global__ __launch_bounds__(64) void k_direct_pinv(int r, int m, const double* __restrict__ Z,
+                                                    int ldz, double* __restrict__ Zp,
+                                                    double* __restrict__ Uscr) {
+  extern __shared__ double sm[];
+  const int b = blockIdx.x, tid = threadIdx.x, n = m, ld = m;
+  double* K = sm;
+  double* G = K + n * ld;
+  double* nrm = G + n * ld;
+  double* sv = nrm + n;
+  int* rank = (int*)(sv + n);
+  for (int e = tid; e < n * ld; e += 64) {
+    const int i = e / ld, j = e % ld;
+    K[e] = i < r ? Z[((size_t)b * ldz + j) * (r + 1) + i] : 0.0;
+  }
+  __syncthreads();
+  jacobi_rows(K, G, n, ld, Uscr + (size_t)b * n * n, sv, nrm, rank);
+  double smax = 0.0;
+  for (int i = 0; i < n; ++i) smax = fmax(smax, nrm[i]);
+  const double cut = 1e-15 * smax;
+  for (int e = tid; e < m * r; e += 64) {
+    const int j = e / r, c = e % r;
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i)
+      if (nrm[i] > cut) acc += K[i * ld + j] * G[i * ld + c] / (nrm[i] * nrm[i]);
+    Zp[((size_t)b * ldz + j) * r + c] = acc;
+  }
+}
+
+// Phi~ = Y Z^+ with Y the preprocessed window (slot j of instance b's rows at
+// j * total + g), written column-major: out[c * total + g]
+template <typename T>
+__global__ __launch_bounds__(256) void k_direct_combine(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off,
+    const T* __restrict__ win, int64_t total, int m, const T* __restrict__ qref,
+    const double* __restrict__ dvar, int nv, const double* __restrict__ Zp, int ldz, int r,
+    T* __restrict__ out) {
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  const int64_t base = dof_off[b];
+  const double* Zb = Zp + (size_t)b * ldz * r;
+  for (int64_t rr = threadIdx.x; rr < t.ncell; rr += blockDim.x) {
+    const int64_t lr = t.cell0 + rr, g = base + lr;
+    double yh[kMaxWin];
+#pragma unroll
+    for (int j = 0; j < kMaxWin; ++j)
+      yh[j] = j < m ? yhat_of(win + (size_t)j * total, qref, dvar + (size_t)b * nv, nv, g, lr)
+                    : 0.0;
+    for (int c = 0; c < r; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < kMaxWin; ++j)
+        if (j < m) acc += yh[j] * Zb[j * r + c];
+      out[(size_t)c * total + g] = (T)acc;
+    }
+  }
+}
+
+template <typename T>
+rom_status pod_t(rom_batch* h, const void* Qtrain, int w, hipStream_t s) {
+  PodWs ws;
+  rom_status st = pod_ws_alloc(h, w, &ws);
+  if (st == ROM_OK) st = pod_core_t<T>(h, Qtrain, w, true, true, ws, h->sigma, h->Phi, s);
+  hipError_t e = hipStreamSynchronize(s);
+  pod_ws_free(&ws);
+  if (st != ROM_OK) return st;
+  ROM_HIP_CHECK(e);
+  return ROM_OK;
+}
+
+// One windowed basis update (App. A): the raw snapshot y joins the window
+// (replacing the oldest once it holds `window`), the lifted state v = Phi a is
+// kept in FP64, the basis is rebuilt by the rule, and a = Phi_new^T v.
+template <typename T>
+rom_status windowed_t(rom_batch* h, const void* y, hipStream_t s) {
+  const int r = h->cfg.r, B = h->cfg.n_inst, w = h->cfg.window;
+  const int64_t tot = h->total_dof;
+  T* win = (T*)h->win;
+  hipLaunchKernelGGL((k_copy_t<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                     (const T*)y, win + (size_t)h->win_head * tot, tot);
+  h->win_head = (h->win_head + 1) % w;
+  h->win_count = h->win_count < w ? h->win_count + 1 : w;
+  const int m = h->win_count;
+  hipLaunchKernelGGL((k_lift<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                     h->d_dof_off, (const T*)h->Phi, r, h->a, h->lift);
+  if (h->cfg.update_rule == ROM_UPDATE_WSVD) {
+    ROM_TRY(pod_core_t<T>(h, win, m, true, true, h->podws, h->sigma, h->Phi, s));
+  } else {
+    const int ldz = kMaxWin;
+    for (int j = 0; j < m; ++j)
+      project_t<T>(h, h->Phi, r, r, win + (size_t)j * tot, h->q_ref, nullptr, 0, 1,
+                   h->zmat + (size_t)j * (r + 1), ldz * (r + 1), s);
+    const size_t shm = sizeof(double) * (2 * m * m + 2 * m) + sizeof(int) * m;
+    hipLaunchKernelGGL(k_direct_pinv, dim3(B), dim3(64), shm, s, r, m, h->zmat, ldz, h->zpinv,
+                       h->podws.U);
+    hipLaunchKernelGGL((k_direct_combine<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                       h->d_dof_off, (const T*)win, tot, m, (const T*)h->q_ref, h->d_var, h->nv,
+                       h->zpinv, ldz, r, (T*)h->phit);
+    ROM_TRY(pod_core_t<T>(h, h->phit, r, false, false, h->podws, h->sig_scratch, h->Phi, s));
+  }
+  hipLaunchKernelGGL((k_project_vec<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                     h->d_dof_off, (const T*)h->Phi, r, h->lift, h->part);
+  hipLaunchKernelGGL(k_reduce_tiles, dim3(B), dim3(128), 0, s, h->d_ptile_first, h->part, r - 1,
+                     h->a, r);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+// The window at the end of the offline stage: the last min(window, w) training
+// snapshots (Q: T[w * total_dof]), oldest first.
+template <typename T>
+rom_status window_init_t(rom_batch* h, const void* Q, int w, hipStream_t s) {
+  const int64_t tot = h->total_dof;
+  const int m = std::min(h->cfg.window, w);
+  const T* src = (const T*)Q + (size_t)(w - m) * tot;
+  hipLaunchKernelGGL((k_copy_t<T>), dim3((unsigned)((tot * m + 255) / 256)), dim3(256), 0, s, src,
+                     (T*)h->win, tot * m);
+  h->win_count = m;
+  h->win_head = m % h->cfg.window;
+  ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
 }
 
@@ -1154,6 +1370,7 @@ rom_status isvd_kernels_prepare() {
   const int big = 160 * 1024 - 1024;
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_isvd_core<true>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_pod_svd, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_direct_pinv, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   return ROM_OK;
 }
 
@@ -1197,6 +1414,13 @@ rom_status launch_pod(rom_batch* h, const void* Q, int w, hipStream_t s) {
 rom_status launch_preprocess(rom_batch* h, const void* q0, const void* Q, int w, hipStream_t s) {
   return h->cfg.precision == ROM_F64 ? preprocess_t<double>(h, q0, Q, w, s)
                                      : preprocess_t<float>(h, q0, Q, w, s);
+}
+rom_status launch_windowed_update(rom_batch* h, const void* y, hipStream_t s) {
+  return h->cfg.precision == ROM_F64 ? windowed_t<double>(h, y, s) : windowed_t<float>(h, y, s);
+}
+rom_status launch_window_init(rom_batch* h, const void* Q, int w, hipStream_t s) {
+  return h->cfg.precision == ROM_F64 ? window_init_t<double>(h, Q, w, s)
+                                     : window_init_t<float>(h, Q, w, s);
 }
 rom_status launch_project_state(rom_batch* h, const void* q, hipStream_t s) {
   return h->cfg.precision == ROM_F64 ? project_state_t<double>(h, q, s)

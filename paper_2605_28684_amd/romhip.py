@@ -29,7 +29,9 @@ STATUS = {0: "ROM_OK", -1: "ROM_E_INVAL", -2: "ROM_E_NOMEM", -3: "ROM_E_DEVICE",
 FLAG_NEWTON_NOCONV, FLAG_FLOOR, FLAG_NONFINITE, FLAG_RHO_ZERO = 1, 2, 4, 8
 FLAG_SINGULAR, FLAG_ROM_NOCONV, FLAG_REORTH = 16, 32, 64
 GET_BASIS, GET_SIGMA, GET_A, GET_QTILDE, GET_SAMPLES, GET_YCORR = 0, 1, 2, 3, 4, 5
-GET_QREF, GET_DVAR, GET_PINV, GET_COUNTERS, GET_UBAR = 6, 7, 8, 9, 10
+GET_QREF, GET_DVAR, GET_PINV, GET_COUNTERS, GET_UBAR, GET_WINDOW = 6, 7, 8, 9, 10, 11
+UPDATE_ISVD, UPDATE_WSVD, UPDATE_DIRECT = 0, 1, 2
+N_COUNTERS = 6
 
 
 class RomError(RuntimeError):
@@ -49,6 +51,7 @@ class rom_config(ctypes.Structure):
                 ("z", ctypes.c_int32),
                 ("newton_max", ctypes.c_int32), ("rom_max", ctypes.c_int32),
                 ("reorth_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("update_rule", ctypes.c_int32), ("window", ctypes.c_int32),
                 ("lambda_", ctypes.c_double), ("dt", ctypes.c_double),
                 ("newton_tol", ctypes.c_double), ("rom_tol", ctypes.c_double),
                 ("tau_orth", ctypes.c_double), ("tau_rho", ctypes.c_double)]
@@ -137,6 +140,8 @@ def make_config(w: W.Workload, use_graph=True, precision=None, **over):
     cfg.r, cfg.n_s, cfg.w_init, cfg.z = w.r, w.n_s, w.w_init, w.z
     cfg.newton_max, cfg.rom_max, cfg.reorth_every = w.newton_max, w.rom_max, w.reorth_every
     cfg.use_graph = 1 if use_graph else 0
+    cfg.update_rule = {"isvd": UPDATE_ISVD, "wsvd": UPDATE_WSVD, "direct": UPDATE_DIRECT}[w.update]
+    cfg.window = w.window
     cfg.lambda_, cfg.dt = w.lam, w.dt
     cfg.newton_tol, cfg.rom_tol = w.newton_tol, w.rom_tol
     cfg.tau_orth, cfg.tau_rho = w.tau_orth, w.tau_rho
@@ -248,20 +253,21 @@ class RomBatch:
     _SIZES = {GET_BASIS: ("T", "dof*r"), GET_SIGMA: ("f64", "B*r"), GET_A: ("f64", "B*r"),
               GET_QTILDE: ("T", "dof"), GET_SAMPLES: ("i32", "B*ns"), GET_YCORR: ("T", "dof"),
               GET_QREF: ("T", "dof"), GET_DVAR: ("f64", "B*nv"), GET_PINV: ("f64", "B*r*ns"),
-              GET_UBAR: ("f64", "B*n*n")}
+              GET_UBAR: ("f64", "B*n*n"), GET_WINDOW: ("T", "w*dof")}
 
     def _shape(self, what):
         kind, n = self._SIZES[what]
         size = {"dof*r": self.total_dof * self.r, "B*r": self.n_inst * self.r,
                 "dof": self.total_dof, "B*ns": self.n_inst * max(self.n_s, 1),
                 "B*nv": self.n_inst * self.n_var, "B*r*ns": self.n_inst * self.r * max(self.n_s, 1),
-                "B*n*n": self.n_inst * (self.r + 1) ** 2}[n]
+                "B*n*n": self.n_inst * (self.r + 1) ** 2,
+                "w*dof": max(self.cfg.window, 0) * self.total_dof}[n]
         dt = {"T": self.dtype, "f64": torch.float64, "i32": torch.int32}[kind]
         return size, dt
 
     def get(self, what):
         if what == GET_COUNTERS:
-            buf = (ctypes.c_int64 * 4)()
+            buf = (ctypes.c_int64 * N_COUNTERS)()
             _check(LIB.rom_get(self.h, what, ctypes.cast(buf, ctypes.c_void_p), _stream()))
             return list(buf)
         n, dt = self._shape(what)
@@ -271,7 +277,9 @@ class RomBatch:
 
     def set(self, what, src):
         if what == GET_COUNTERS:
-            buf = (ctypes.c_int64 * 4)(*[int(x) for x in src])
+            vals = [int(x) for x in src]
+            cur = self.get(GET_COUNTERS)
+            buf = (ctypes.c_int64 * N_COUNTERS)(*(vals + cur[len(vals):]))
             _check(LIB.rom_set(self.h, what, ctypes.cast(buf, ctypes.c_void_p), _stream()))
             return
         n, dt = self._shape(what)

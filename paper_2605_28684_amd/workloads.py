@@ -50,6 +50,8 @@ class Workload:
     reorth_every: int = 16
     tau_orth: float = 1e-12
     tau_rho: float = 1e-12
+    update: str = "isvd"           # basis update rule: isvd | wsvd | direct
+    window: int = 0                # snapshot window of the windowed rules
     extra: dict = field(default_factory=dict)
 
     @property
@@ -95,7 +97,7 @@ class Workload:
                     lam=self.lam, dt=self.dt, newton_tol=self.newton_tol,
                     newton_max=self.newton_max, rom_tol=self.rom_tol, rom_max=self.rom_max,
                     reorth_every=self.reorth_every, tau_orth=self.tau_orth,
-                    tau_rho=self.tau_rho,
+                    tau_rho=self.tau_rho, update=self.update, window=self.window,
                     projection="lspg" if self.projection == LSPG else "galerkin",
                     hyper="deim" if self.hyper == HR_DEIM else "none")
 

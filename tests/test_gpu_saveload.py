@@ -1,7 +1,8 @@
 """rom_save / rom_load: a saved state resumed on a new handle (or rewound on
 the same one) continues with the same bits as the uninterrupted run, on the
 overlapped Galerkin windows (FP32, graphs), on hyper-reduced LSPG windows
-(FP32, DEIM, graphs) and on eager FP64 Galerkin steps; mismatched or damaged
+(FP32, DEIM, graphs), on eager FP64 Galerkin steps and with the Direct rule
+(whose snapshot window is part of the state); mismatched or damaged
 states are refused without touching the handle."""
 import numpy as np
 import pytest
@@ -22,6 +23,8 @@ def _case(kind):
     if kind == "sod_hr_f32_graph":
         return W.sod_hllc_f32(n=1500, r=12, n_s=20, z=3, precision=W.F32), True
     w = W.burgers_512_f64(n=256, N_t=200, w_init=20, r=6, z=5)
+    if kind == "burgers_direct_f64":
+        w.update, w.window = "direct", 8
     return w, False
 
 
@@ -34,10 +37,13 @@ def _state(h):
                      "GET_PINV")}
     out["counters"] = list(h.get(R.GET_COUNTERS))
     out["flags"] = h.status().copy()
+    if h.cfg.update_rule != R.UPDATE_ISVD:
+        out["window"] = h.get(R.GET_WINDOW).cpu().numpy().copy()
     return out
 
 
-@pytest.mark.parametrize("kind", ["burgers_f32_graph", "sod_hr_f32_graph", "burgers_f64_eager"])
+@pytest.mark.parametrize("kind", ["burgers_f32_graph", "sod_hr_f32_graph", "burgers_f64_eager",
+                                  "burgers_direct_f64"])
 def test_save_load_resume_is_bitwise(kind):
     import torch
     from paper_2605_28684_amd import romhip as R

@@ -357,8 +357,8 @@ def test_direct_update_normal_equations_and_fixed_point():
     """Alg. A.2: Phi~ = Yw Z^+ solves the least-squares problem of eq.
     direct_optimization, so its residual satisfies the normal equations
     (Phi~ Z - Yw) Z^T = 0; the new basis is orthonormal, spans range(Phi~) and
-    diagonalises Phi~ Phi~^T; a window inside span(Phi) leaves the subspace
-    unchanged."""
+    is Phi~'s Gram-Schmidt basis (P1^T Phi~ upper triangular, positive
+    diagonal); a window inside span(Phi) leaves the subspace unchanged."""
     rng = np.random.default_rng(32)
     N, r, m = 250, 4, 7
     Phi, _ = np.linalg.qr(rng.normal(size=(N, r)))
@@ -369,12 +369,12 @@ def test_direct_update_normal_equations_and_fixed_point():
     P1 = O.direct_update(Phi, Yw)
     assert np.max(np.abs(P1.T @ P1 - np.eye(r))) < 1e-13
     assert np.max(np.abs(P1 @ (P1.T @ Phit) - Phit)) < 1e-12 * np.linalg.norm(Phit)
-    # orth() gives the left singular vectors of Phi~: they diagonalise its Gram
-    # matrix, largest first (another basis of the same range would not)
-    G = (P1.T @ Phit) @ (Phit.T @ P1)
-    off = G - np.diag(np.diag(G))
-    assert np.max(np.abs(off)) < 1e-10 * np.max(np.abs(G))
-    assert np.all(np.diff(np.diag(G)) < 0)
+    # orth() is Gram-Schmidt on the columns of Phi~: R = P1^T Phi~ is upper
+    # triangular with a positive diagonal (another basis of the same range,
+    # or Gram-Schmidt of another matrix with that range, would not give that)
+    Rm = P1.T @ Phit
+    assert np.max(np.abs(np.tril(Rm, -1))) < 1e-12 * np.max(np.abs(Rm))
+    assert np.all(np.diag(Rm) > 0)
     Yin = Phi @ rng.normal(size=(r, m))
     P2 = O.direct_update(Phi, Yin)
     assert np.max(np.abs(P2 @ P2.T - Phi @ Phi.T)) < 1e-12
