@@ -15,6 +15,9 @@ Each function follows one passage of the paper, in its order and notation:
   deim_greedy         greedy DEIM (the interpolation-residual argmax rule of the
                       DEIM reference cited in Sec. 3.2), oversampled to n_s rows
                       by a second least-squares greedy round
+  qdeim               QDEIM: pivots of the column-pivoted QR of Phi^T (eq. qdeim_qr)
+  fgs                 feature-guided sampling: QDEIM plus the cells of largest
+                      feature gradient of the estimated future state (eq. fgs_selection)
   rebuild             (P^T Phi)^+ (eq. qdeim_approximation_phi)
   galerkin_step       backward Euler applied to eq. galerkin_continuous_rom
   hr_lspg_step        Gauss-Newton on eq. hyperreduced_lspg
@@ -199,6 +202,84 @@ def deim_greedy(Phi, n_s):
     return np.array(P, dtype=np.int64)
 
 
+def qdeim(Phi, m):
+    """QDEIM (Sec. 3.2, eq. qdeim_qr): the first m pivots of the column-pivoted
+    QR factorisation of Phi^T.  Pivoted QR picks, at step k, the column of the
+    trailing block of largest norm, which is the row phi_i of Phi farthest from
+    the span of the rows already chosen; that distance is formed here
+    explicitly (Gram-Schmidt twice on the chosen rows, FP64).  Ties go to the
+    lowest row index."""
+    N, r = Phi.shape
+    if not (1 <= m <= r):
+        raise ValueError("QDEIM gives at most r rows")
+    Q = np.zeros((r, 0))
+    chosen = np.zeros(N, dtype=bool)
+    P = []
+    for _ in range(m):
+        R = Phi - (Phi @ Q) @ Q.T
+        dist = np.where(chosen, -1.0, np.sum(R * R, axis=1))
+        i = int(np.argmax(dist))
+        chosen[i] = True
+        P.append(i)
+        v = Phi[i].copy()
+        for _ in range(2):
+            v = v - Q @ (Q.T @ v)
+        Q = np.concatenate([Q, (v / np.linalg.norm(v))[:, None]], axis=1)
+    return np.array(P, dtype=np.int64)
+
+
+# feature map Theta of feature-guided sampling, per problem (variable index):
+# Burgers u, Euler density, reacting model temperature
+FGS_FEATURE = {F.BURGERS: 0, F.EULER_RUSANOV: 0, F.EULER_HLLC: 0, F.REACT: 10}
+
+
+def feature_gradient2(problem, y):
+    """||grad theta||^2 per cell for theta = Theta(y), the feature variable of
+    the problem, by central differences on the unit interval (periodic wrap,
+    or the zero-gradient ghosts at the walls of the Euler problems)."""
+    nv = F.NVAR[problem]
+    th = y.reshape(-1, nv)[:, FGS_FEATURE[problem]]
+    n = th.shape[0]
+    if F.PERIODIC[problem]:
+        tp, tm = np.roll(th, -1), np.roll(th, 1)
+    else:
+        tp = np.concatenate([th[1:], th[-1:]])
+        tm = np.concatenate([th[:1], th[:-1]])
+    g = (tp - tm) * (n / 2.0)
+    return g * g
+
+
+def fgs(problem, Phi, y, n_s):
+    """Feature-guided sampling (Sec. 3.2, eq. fgs_selection): QDEIM's r rows,
+    then the n_s - r cells of largest ||grad theta||^2 (theta of the estimated
+    future state y), each contributing its feature-variable row; cells whose
+    feature row is already chosen are skipped; ties go to the lowest cell."""
+    N, r = Phi.shape
+    nv = F.NVAR[problem]
+    P = list(qdeim(Phi, r))
+    g = feature_gradient2(problem, y)
+    taken = set(P)
+    for c in np.argsort(-g, kind="stable"):
+        if len(P) == n_s:
+            break
+        row = int(c) * nv + FGS_FEATURE[problem]
+        if row not in taken:
+            P.append(row)
+            taken.add(row)
+    return np.array(P, dtype=np.int64)
+
+
+def sample_rows(problem, Phi, y_corr, prm):
+    """The sampling rule of the configuration: greedy DEIM, QDEIM or QDEIM + FGS."""
+    if prm["hyper"] == "deim":
+        return deim_greedy(Phi, prm["n_s"])
+    if prm["hyper"] == "qdeim":
+        return qdeim(Phi, prm["n_s"])
+    if prm["hyper"] == "qdeim_fgs":
+        return fgs(problem, Phi, y_corr, prm["n_s"])
+    raise ValueError("unknown sampling %r" % (prm["hyper"],))
+
+
 def rebuild(Phi, P):
     """(P^T Phi)^+, r x n_s (eq. qdeim_approximation_phi)."""
     return np.linalg.pinv(Phi[P, :])
@@ -296,8 +377,8 @@ def offline(problem, phys, q0, prm):
         w = prm["window"]
         st["window"] = [d * (Q_train[:, j] - q_ref)
                         for j in range(max(0, Q_train.shape[1] - w), Q_train.shape[1])]
-    if prm["hyper"] == "deim":
-        st["P"] = deim_greedy(Phi, prm["n_s"])
+    if prm["hyper"] != "none":
+        st["P"] = sample_rows(problem, Phi, y_corr, prm)
         st["M"] = rebuild(Phi, st["P"])
     return st
 
@@ -330,15 +411,15 @@ def adaptation_event(problem, phys, st, prm):
     if prm["reorth_every"] > 0 and st["n_update"] % prm["reorth_every"] == 0:
         Phi, _ = reorth(Phi, prm["tau_orth"])
     st["Phi"], st["sigma"] = Phi, sigma
-    if prm["hyper"] == "deim":
-        st["P"] = deim_greedy(Phi, prm["n_s"])
+    if prm["hyper"] != "none":
+        st["P"] = sample_rows(problem, Phi, st["y_corr"], prm)
         st["M"] = rebuild(Phi, st["P"])
     st["a"] = transfer(Phi_old, Phi, st["a"])
     return info
 
 
 def rom_fine_step(problem, phys, st, prm):
-    if prm["hyper"] == "deim":
+    if prm["hyper"] != "none":
         a, it, ok = hr_lspg_step(problem, phys, st["q_ref"], st["d"], st["Phi"], st["P"],
                                  st["M"], st["a"], prm["dt"], prm["rom_tol"], prm["rom_max"])
     else:

@@ -20,7 +20,7 @@ BURGERS, EULER_RUSANOV, EULER_HLLC, REACT = 0, 1, 2, 3
 NVAR = {BURGERS: 1, EULER_RUSANOV: 3, EULER_HLLC: 3, REACT: 12}
 F32, F64 = 0, 1
 GALERKIN, LSPG = 0, 1
-HR_NONE, HR_DEIM = 0, 1
+HR_NONE, HR_DEIM, HR_QDEIM, HR_QDEIM_FGS = 0, 1, 2, 3
 
 # packed per-instance constant vector layout of the reacting model
 REACT_NPHYS = 6 + 10 + 6 * 12
@@ -99,7 +99,8 @@ class Workload:
                     reorth_every=self.reorth_every, tau_orth=self.tau_orth,
                     tau_rho=self.tau_rho, update=self.update, window=self.window,
                     projection="lspg" if self.projection == LSPG else "galerkin",
-                    hyper="deim" if self.hyper == HR_DEIM else "none")
+                    hyper={HR_NONE: "none", HR_DEIM: "deim", HR_QDEIM: "qdeim",
+                           HR_QDEIM_FGS: "qdeim_fgs"}[self.hyper])
 
 
 def centres(n):

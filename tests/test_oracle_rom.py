@@ -399,3 +399,74 @@ def test_windowed_rules_in_alg1_roll_the_window(rule):
         assert np.allclose(st["window"][-1], st["d"] * (st["y_corr"] - st["q_ref"]))
         assert np.max(np.abs(st["Phi"].T @ st["Phi"] - np.eye(4))) < 1e-12
         assert np.allclose(st["a"], st["Phi"].T @ (Phi_old @ a_old))
+
+
+# ---------------------------------------------------------------- QDEIM and FGS (Sec. 3.2)
+@pytest.mark.parametrize("seed", range(6))
+def test_qdeim_equals_pivoted_qr_of_phi_transpose(seed):
+    """eq. qdeim_qr: the rows equal LAPACK's column pivots of Phi^T (scipy),
+    on random bases where no two candidate norms are close."""
+    rng = np.random.default_rng(400 + seed)
+    N, r = 60 + 10 * seed, 3 + seed
+    Phi, _ = np.linalg.qr(rng.normal(size=(N, r)) * rng.uniform(0.2, 2.0, size=(N, 1)))
+    piv = sla.qr(Phi.T, pivoting=True)[2][:r]
+    np.testing.assert_array_equal(O.qdeim(Phi, r), piv)
+
+
+def test_qdeim_interpolation_bound_and_brute_force():
+    """The sampled block is invertible and obeys QDEIM's bound
+    ||(P^T Phi)^-1||_2 <= sqrt(N - r + 1) sqrt(4^r + 6r - 1) / 3; on a tiny
+    basis the first pick is the row of largest norm and every later pick is
+    the row farthest from the span of the chosen ones (brute force)."""
+    rng = np.random.default_rng(41)
+    N, r = 200, 6
+    Phi, _ = np.linalg.qr(rng.normal(size=(N, r)))
+    P = O.qdeim(Phi, r)
+    inv = np.linalg.norm(np.linalg.inv(Phi[P, :]), 2)
+    assert inv <= np.sqrt(N - r + 1) * np.sqrt(4 ** r + 6 * r - 1) / 3
+    small, _ = np.linalg.qr(rng.normal(size=(9, 3)))
+    Ps = O.qdeim(small, 3)
+    assert Ps[0] == np.argmax(np.sum(small ** 2, axis=1))
+    for k in range(1, 3):
+        B = small[Ps[:k]].T                                   # chosen rows as columns
+        proj = B @ np.linalg.lstsq(B, small.T, rcond=None)[0]
+        dist = np.sum((small.T - proj) ** 2, axis=0)
+        dist[Ps[:k]] = -1.0
+        assert Ps[k] == np.argmax(dist)
+
+
+@pytest.mark.parametrize("problem", [W.BURGERS, W.EULER_RUSANOV, W.REACT])
+def test_fgs_adds_the_steepest_feature_cells(problem):
+    """eq. fgs_selection: after QDEIM's r rows come the feature rows of the
+    n_s - r cells of largest squared feature gradient (brute force), the first
+    of them at the sharp front of the test state; the gradient is the centred
+    difference of
+    the feature (periodic, or zero-gradient at the Euler walls)."""
+    n = 64
+    nv = F.NVAR[problem]
+    x = W.centres(n)
+    y = np.ones((n, nv)) * 0.5
+    feat = O.FGS_FEATURE[problem]
+    # a sharp front at x = 0.4 and a gentle return near x = 0.9 (so that the
+    # periodic wrap adds no jump)
+    y[:, feat] = 1.0 + 0.5 * (np.tanh((x - 0.4) / 0.01) - np.tanh((x - 0.9) / 0.1))
+    y = y.reshape(-1)
+    g = O.feature_gradient2(problem, y)
+    th = y.reshape(n, nv)[:, feat]
+    i = 20
+    assert np.isclose(g[i], ((th[i + 1] - th[i - 1]) * n / 2) ** 2)
+    if F.PERIODIC[problem]:
+        assert np.isclose(g[0], ((th[1] - th[-1]) * n / 2) ** 2)
+    else:
+        assert np.isclose(g[0], ((th[1] - th[0]) * n / 2) ** 2)
+    rng = np.random.default_rng(43)
+    Phi, _ = np.linalg.qr(rng.normal(size=(n * nv, 4)))
+    P = O.fgs(problem, Phi, y, 8)
+    assert len(set(P.tolist())) == 8
+    np.testing.assert_array_equal(P[:4], O.qdeim(Phi, 4))
+    extra = P[4:]
+    assert all(p % nv == feat for p in extra)
+    cells = extra // nv
+    rest = np.setdiff1d(np.arange(n), cells)
+    assert g[cells].min() >= g[rest].max() or any((c * nv + feat) in P[:4] for c in rest)
+    assert abs(x[cells[0]] - 0.4) < 0.02          # the steepest cell is at the front
