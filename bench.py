@@ -242,6 +242,21 @@ def config_measurements(torch, W, R):
                 h.close()
             rules[name] = dict(ms_per_update=per, window=window, r=mk().r)
         out["update_rules"] = rules
+        # cost of one rebuild per sampling rule (Sec. 3.2) on the Sod and reacting shapes
+        samplers = {}
+        for name, mk, r in (("C3_sod_hllc_65536_f32", W.sod_hllc_f32, 40),
+                            ("C5_react10_32x32768_f32", W.react10_f32, 64)):
+            per = {}
+            for label, hyper, n_s in (("deim", W.HR_DEIM, 2 * r), ("qdeim", W.HR_QDEIM, r),
+                                      ("qdeim_fgs", W.HR_QDEIM_FGS, 2 * r)):
+                w = mk()
+                w.hyper, w.n_s = hyper, n_s
+                h = R.RomBatch(w, q0=torch.as_tensor(w.q0, dtype=torch.float32, device="cuda"),
+                               use_graph=False)
+                per[label] = dict(n_s=n_s, ms_per_rebuild=round(_timed(torch, h.rom_rebuild, 3), 4))
+                h.close()
+            samplers[name] = per
+        out["samplers"] = samplers
     return out
 
 

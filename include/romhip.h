@@ -70,7 +70,7 @@ enum {
 enum { ROM_BURGERS = 0, ROM_EULER_RUSANOV = 1, ROM_EULER_HLLC = 2, ROM_REACT = 3 };
 enum { ROM_F32 = 0, ROM_F64 = 1 };
 enum { ROM_GALERKIN = 0, ROM_LSPG = 1 };
-enum { ROM_HR_NONE = 0, ROM_HR_DEIM = 1 };
+enum { ROM_HR_NONE = 0, ROM_HR_DEIM = 1, ROM_HR_QDEIM = 2, ROM_HR_QDEIM_FGS = 3 };
 enum { ROM_UPDATE_ISVD = 0, ROM_UPDATE_WSVD = 1, ROM_UPDATE_DIRECT = 2 };
 
 /*
@@ -188,10 +188,20 @@ rom_status fom_step(rom_handle h, const void* q_prev, double dt, void* q_out, in
 rom_status isvd_update(rom_handle h, const void* y, void* stream);
 
 /*
- * rom_rebuild - refresh every basis-dependent quantity: with DEIM, the greedy
- * sample rows (n_s = r .. 2r), the sample mesh (the sampled cells and their
- * two neighbours), the gathered basis / q_ref rows and (P^T Phi)^+ in FP64
- * (Alg. 1 sampling and operator update; eq. qdeim_approximation_phi).
+ * rom_rebuild - refresh every basis-dependent quantity (Alg. 1 sampling and
+ * operator update; eq. qdeim_approximation_phi): the sample rows, the sample
+ * mesh (the sampled cells and their two neighbours), the gathered basis /
+ * q_ref rows and (P^T Phi)^+ in FP64.  The rows come from cfg.hyper:
+ *   ROM_HR_DEIM       greedy DEIM, n_s = r .. 2r (two rounds, Sec. 3.2)
+ *   ROM_HR_QDEIM      QDEIM, n_s = r: the pivots of the column-pivoted QR of
+ *                     Phi^T (eq. qdeim_qr); ties go to the lowest row
+ *   ROM_HR_QDEIM_FGS  QDEIM's r rows, then feature-guided sampling (eq.
+ *                     fgs_selection): the n_s - r cells (r < n_s <= 2r) of
+ *                     largest squared centred-difference gradient of a
+ *                     feature of y_corr (Burgers u, Euler density, reacting
+ *                     model temperature), each adding its feature row; cells
+ *                     whose feature row is already chosen are skipped
+ * All three use the hyper-reduced LSPG step.
  */
 rom_status rom_rebuild(rom_handle h, void* stream);
 

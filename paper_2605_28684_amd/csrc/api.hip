@@ -101,7 +101,7 @@ rom_status validate(const rom_config* c) {
   ROM_REQUIRE(c->precision == ROM_F32 || c->precision == ROM_F64, ROM_E_INVAL, "bad precision");
   ROM_REQUIRE(c->projection == ROM_GALERKIN || c->projection == ROM_LSPG, ROM_E_INVAL,
               "bad projection");
-  ROM_REQUIRE(c->hyper == ROM_HR_NONE || c->hyper == ROM_HR_DEIM, ROM_E_INVAL, "bad hyper");
+  ROM_REQUIRE(c->hyper >= ROM_HR_NONE && c->hyper <= ROM_HR_QDEIM_FGS, ROM_E_INVAL, "bad hyper");
   ROM_REQUIRE(c->n_inst >= 1, ROM_E_INVAL, "n_inst must be >= 1");
   ROM_REQUIRE(c->n_cells && c->phys, ROM_E_INVAL, "n_cells and phys are required");
   const int need = c->problem == ROM_REACT ? 88 : 1;
@@ -132,6 +132,12 @@ rom_status validate(const rom_config* c) {
     ROM_REQUIRE(c->n_s >= c->r && c->n_s <= 2 * c->r && c->n_s <= kMaxNs, ROM_E_INVAL,
                 "n_s must be in [r, 2r] with DEIM");
     ROM_REQUIRE(c->n_s <= mn * nv, ROM_E_INVAL, "n_s exceeds the smallest instance");
+  } else if (c->hyper == ROM_HR_QDEIM) {
+    ROM_REQUIRE(c->n_s == c->r, ROM_E_INVAL, "QDEIM gives n_s = r rows");
+  } else if (c->hyper == ROM_HR_QDEIM_FGS) {
+    ROM_REQUIRE(c->n_s > c->r && c->n_s <= 2 * c->r, ROM_E_INVAL,
+                "feature-guided sampling adds 1 .. r rows to QDEIM's r (r < n_s <= 2r)");
+    ROM_REQUIRE(c->n_s - c->r <= mn, ROM_E_INVAL, "more feature rows than cells");
   } else {
     ROM_REQUIRE(c->problem == ROM_BURGERS, ROM_E_UNSUPPORTED,
                 "the full Galerkin ROM (no hyper-reduction) is implemented for Burgers");
@@ -159,7 +165,8 @@ void free_all(rom_batch* h) {
                 h->active, h->iters, h->norms, h->rstate, h->qtmp, h->mpart, h->fq, h->fq_prev, h->vjp_tmp,
                 h->d_epoch, h->rvjp, h->epart, h->ev_iters, h->phi_cm, h->Phi_alt, h->hr_as, h->hr_cnt};
   for (void* p : ps) (void)hipFree(p);
-  void* pw[] = {h->win, h->lift, h->zmat, h->zpinv, h->phit, h->sig_scratch};
+  void* pw[] = {h->win, h->lift, h->zmat, h->zpinv, h->phit, h->sig_scratch, h->qdeim_q,
+                h->fgs_g, h->d_tile_first};
   for (void* p : pw) (void)hipFree(p);
   pod_ws_free(&h->podws);
   bt_free(h);
@@ -197,8 +204,10 @@ rom_status setup(rom_batch* h) {
   // stencil tiles (cells) and pass tiles (basis rows)
   std::vector<Tile> tiles, ptiles, btiles, btiles2;
   h->ptile_first.assign(B + 1, 0);
+  std::vector<int> tile_first(B + 1, 0);
   for (int b = 0; b < B; ++b) {
     const int64_t nb = h->n_cells[b], base = h->dof_off[b];
+    tile_first[b] = (int)tiles.size();
     for (int64_t c0 = 0; c0 < nb; c0 += kTile)
       tiles.push_back(Tile{b, 0, c0, std::min<int64_t>(kTile, nb - c0), nb, base});
     for (int64_t c0 = 0; c0 < nb; c0 += kBigTile)
@@ -211,6 +220,7 @@ rom_status setup(rom_batch* h) {
       ptiles.push_back(Tile{b, 0, r0, std::min<int64_t>(kPassRows, rows - r0), nb, base});
   }
   h->ptile_first[B] = (int)ptiles.size();
+  tile_first[B] = (int)tiles.size();
   h->n_tiles = (int)tiles.size();
   h->n_btiles = (int)btiles.size();
   h->n_btiles2 = (int)btiles2.size();
@@ -225,6 +235,9 @@ rom_status setup(rom_batch* h) {
   ROM_TRY(alloc(&h->d_btiles2, btiles2.size()));
   ROM_TRY(alloc(&h->d_ptiles, ptiles.size()));
   ROM_TRY(alloc(&h->d_ptile_first, B + 1));
+  ROM_TRY(alloc(&h->d_tile_first, B + 1));
+  ROM_HIP_CHECK(hipMemcpy(h->d_tile_first, tile_first.data(), sizeof(int) * (B + 1),
+                          hipMemcpyHostToDevice));
   ROM_HIP_CHECK(hipMemcpy(h->d_dof_off, h->dof_off.data(), 8 * (B + 1), hipMemcpyHostToDevice));
   ROM_HIP_CHECK(hipMemcpy(h->d_cell_off, h->cell_off.data(), 8 * (B + 1), hipMemcpyHostToDevice));
   ROM_HIP_CHECK(hipMemcpy(h->d_phys, h->phys.data(), 8 * h->phys.size(), hipMemcpyHostToDevice));
@@ -260,8 +273,11 @@ rom_status setup(rom_batch* h) {
   ROM_TRY(alloc(&h->mesh_qref, (size_t)B * ns * 3 * h->nv));
   ROM_TRY(alloc(&h->chosen, (size_t)td));
   if (c.hyper == ROM_HR_DEIM) ROM_TRY(alloc((char**)&h->phi_cm, es * td * r));
-  if (c.hyper == ROM_HR_DEIM) ROM_TRY(alloc(&h->hr_as, (size_t)B * (ns + r) * (r + 1)));
-  if (c.hyper == ROM_HR_DEIM) {
+  if (c.hyper != ROM_HR_NONE) ROM_TRY(alloc(&h->hr_as, (size_t)B * (ns + r) * (r + 1)));
+  if (c.hyper == ROM_HR_QDEIM || c.hyper == ROM_HR_QDEIM_FGS)
+    ROM_TRY(alloc(&h->qdeim_q, (size_t)B * kMaxR * kMaxR));
+  if (c.hyper == ROM_HR_QDEIM_FGS) ROM_TRY(alloc(&h->fgs_g, (size_t)h->total_cells));
+  if (c.hyper != ROM_HR_NONE) {
     ROM_TRY(alloc(&h->hr_cnt, (size_t)B));
     ROM_HIP_CHECK(hipMemset(h->hr_cnt, 0, sizeof(int32_t) * B));
   }

@@ -108,6 +108,7 @@ struct rom_batch {
   double* d_phys = nullptr;
   romhip::Tile* d_tiles = nullptr;
   int n_tiles = 0;
+  int* d_tile_first = nullptr;       // first cell tile of each instance [n_inst+1]
   romhip::Tile* d_btiles = nullptr;  // kBigTile-cell tiles
   int n_btiles = 0;
   romhip::Tile* d_btiles2 = nullptr; // kBigTile/2-cell tiles
@@ -138,6 +139,8 @@ struct rom_batch {
   double* hr_as = nullptr;     // [n_inst * (n_s + r) * (r + 1)]: rows of [A_s | b], then [M A_s | -M b] (DEIM only)
   int32_t* hr_cnt = nullptr;   // [n_inst]: arrival counters of the HR reduction blocks (zero between launches)
   uint32_t deim_epoch = 0;
+  double* qdeim_q = nullptr;   // [n_inst * kMaxR * kMaxR] QDEIM's orthonormal directions (QDEIM only)
+  double* fgs_g = nullptr;     // [total_cells] squared feature gradient (feature-guided sampling)
 
   // iSVD workspace
   double* part = nullptr;    // block partial sums [n_ptiles * (r*r + 2r + 4)]
@@ -273,6 +276,9 @@ rom_status prepare_galerkin_pass(rom_batch* h, hipStream_t s);
 rom_status launch_galerkin_pass(rom_batch* h, hipStream_t s);  // one pass, every instance active
 rom_status launch_isvd_project(rom_batch* h, const void* y, hipStream_t s);  // pass A only
 rom_status launch_rebuild(rom_batch* h, hipStream_t s);
+// ---- sample.hip: QDEIM picks (and feature-guided sampling) into P
+rom_status launch_qdeim(rom_batch* h, hipStream_t s);
+int fgs_feature(int problem);
 rom_status launch_reconstruct(rom_batch* h, void* out, hipStream_t s);
 rom_status rom_kernels_prepare();
 rom_status isvd_kernels_prepare();

@@ -1308,7 +1308,16 @@ rom_status hr_step(rom_batch* h, hipStream_t s) {
 template <typename T>
 rom_status rebuild_t(rom_batch* h, hipStream_t s) {
   const int r = h->cfg.r, ns = h->cfg.n_s, B = h->cfg.n_inst;
-  if (h->cfg.hyper != ROM_HR_DEIM) return ROM_OK;
+  if (h->cfg.hyper == ROM_HR_NONE) return ROM_OK;
+  if (h->cfg.hyper != ROM_HR_DEIM) {   // QDEIM (and feature-guided sampling) in sample.hip
+    ROM_TRY(launch_qdeim(h, s));
+    hipLaunchKernelGGL((k_rebuild<T>), dim3(B), dim3(256), rebuild_shm(), s, r, ns, h->nv,
+                       (h->cfg.problem == ROM_BURGERS || h->cfg.problem == ROM_REACT) ? 1 : 0,
+                       h->d_dof_off, h->d_cell_off, (const T*)h->Phi, (const T*)h->q_ref, h->P,
+                       h->M, h->mesh_phi, h->mesh_qref, h->flags);
+    ROM_HIP_CHECK(hipGetLastError());
+    return ROM_OK;
+  }
   hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, s, h->d_epoch);
   hipLaunchKernelGGL((k_cols_transpose<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                      h->d_dof_off, (const T*)h->Phi, r, (T*)h->phi_cm);
@@ -1360,7 +1369,7 @@ rom_status rom_kernels_prepare() {
 }
 
 rom_status launch_rom_fine_step(rom_batch* h, hipStream_t s) {
-  if (h->cfg.hyper == ROM_HR_DEIM) return hr_step(h, s);
+  if (h->cfg.hyper != ROM_HR_NONE) return hr_step(h, s);
   if (h->cfg.problem != ROM_BURGERS) {
     set_error("the full (non-hyper-reduced) Galerkin step is implemented for Burgers only");
     return ROM_E_UNSUPPORTED;
