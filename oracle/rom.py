@@ -24,6 +24,8 @@ Each function follows one passage of the paper, in its order and notation:
   wsvd_update         App. A, Alg. A.1 (windowed SVD over the last w snapshots)
   direct_update       App. A, Alg. A.2 (the Direct rule), with orth() read as the
                       Q factor of the thin QR with a positive diagonal of R
+  coarse_step         eq. coarse_fom_backward_euler, or the explicit path's SSPRK(4,3)
+                      step of size z dt (explicit.py)
   transfer            Alg. 1 state transfer a <- Phi_new^T D (q~ - q_ref)
   adaptive_rom        Alg. 1
 
@@ -32,6 +34,7 @@ made positive (lowest index on ties).  Descending singular values.
 """
 import numpy as np
 
+from . import explicit as X
 from . import fom as F
 
 
@@ -350,7 +353,7 @@ def default_params(**kw):
     p = dict(r=4, n_s=4, w_init=4, N_t=20, z=2, lam=0.5, dt=1e-3,
              newton_tol=1e-8, newton_max=10, rom_tol=1e-12, rom_max=10,
              reorth_every=16, tau_orth=1e-12, tau_rho=1e-12,
-             projection="galerkin", hyper="none", update="isvd", window=0)
+             projection="galerkin", hyper="none", update="isvd", window=0, scheme="be")
     p.update(kw)
     return p
 
@@ -362,14 +365,18 @@ def offline(problem, phys, q0, prm):
     n_cell = q0.shape[0] // nv
     dt, z = prm["dt"], prm["z"]
     tol, mx = prm["newton_tol"], prm["newton_max"]
-    Q = F.fom_trajectory(problem, q0, dt, prm["w_init"], phys, tol, mx)
+    explicit = prm.get("scheme", "be") == "ssprk43"
+    if explicit:
+        Q = X.fom_trajectory_explicit(problem, q0, dt, prm["w_init"], phys)
+    else:
+        Q = F.fom_trajectory(problem, q0, dt, prm["w_init"], phys, tol, mx)
     Q_train = Q[:, 1:]
     q_ref, d_var = preprocess(Q_train, q0, nv)
     d = dfull(d_var, n_cell)
     Phi, sigma = pod(d[:, None] * (Q_train - q_ref[:, None]), prm["r"])
     q_last = Q_train[:, -1]
     a = Phi.T @ (d * (q_last - q_ref))
-    y_corr, _, _ = F.newton_be_step(problem, q_last, z * dt, phys, tol, mx)
+    y_corr = coarse_step(problem, phys, q_last, prm)
     st = dict(q_ref=q_ref, d_var=d_var, d=d, Phi=Phi, sigma=sigma, a=a,
               y_corr=y_corr, n_update=0, Q_train=Q_train, P=None, M=None)
     if prm.get("update", "isvd") != "isvd":
@@ -386,8 +393,7 @@ def offline(problem, phys, q0, prm):
 def adaptation_event(problem, phys, st, prm):
     """Alg. 1 event: coarse step, preprocess, iSVD, (re-orth), sampling, rebuild, transfer."""
     dt, z = prm["dt"], prm["z"]
-    st["y_corr"], _, _ = F.newton_be_step(problem, st["y_corr"], z * dt, phys,
-                                          prm["newton_tol"], prm["newton_max"])
+    st["y_corr"] = coarse_step(problem, phys, st["y_corr"], prm)
     yhat = st["d"] * (st["y_corr"] - st["q_ref"])
     Phi_old = st["Phi"]
     rule = prm.get("update", "isvd")
@@ -418,7 +424,22 @@ def adaptation_event(problem, phys, st, prm):
     return info
 
 
+def coarse_step(problem, phys, y, prm):
+    """The coarse correction step of eq. coarse_fom_backward_euler (step z dt):
+    backward Euler by Newton, or, on the explicit path, one SSPRK(4,3) step of
+    the limited second-order full-order model."""
+    if prm.get("scheme", "be") == "ssprk43":
+        return X.fom_step_explicit(problem, y, prm["z"] * prm["dt"], phys)
+    y1, _, _ = F.newton_be_step(problem, y, prm["z"] * prm["dt"], phys, prm["newton_tol"],
+                                prm["newton_max"])
+    return y1
+
+
 def rom_fine_step(problem, phys, st, prm):
+    if prm.get("scheme", "be") == "ssprk43":
+        st["a"] = X.galerkin_hr_explicit_step(problem, phys, st["q_ref"], st["d"], st["Phi"],
+                                              st["P"], st["M"], st["a"], prm["dt"])
+        return 4, True
     if prm["hyper"] != "none":
         a, it, ok = hr_lspg_step(problem, phys, st["q_ref"], st["d"], st["Phi"], st["P"],
                                  st["M"], st["a"], prm["dt"], prm["rom_tol"], prm["rom_max"])

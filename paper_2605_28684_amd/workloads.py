@@ -52,6 +52,7 @@ class Workload:
     tau_rho: float = 1e-12
     update: str = "isvd"           # basis update rule: isvd | wsvd | direct
     window: int = 0                # snapshot window of the windowed rules
+    scheme: str = "be"             # time scheme: be (backward Euler) | ssprk43 (explicit path)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -98,6 +99,7 @@ class Workload:
                     newton_max=self.newton_max, rom_tol=self.rom_tol, rom_max=self.rom_max,
                     reorth_every=self.reorth_every, tau_orth=self.tau_orth,
                     tau_rho=self.tau_rho, update=self.update, window=self.window,
+                    scheme=self.scheme,
                     projection="lspg" if self.projection == LSPG else "galerkin",
                     hyper={HR_NONE: "none", HR_DEIM: "deim", HR_QDEIM: "qdeim",
                            HR_QDEIM_FGS: "qdeim_fgs"}[self.hyper])
