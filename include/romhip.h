@@ -72,6 +72,7 @@ enum { ROM_F32 = 0, ROM_F64 = 1 };
 enum { ROM_GALERKIN = 0, ROM_LSPG = 1 };
 enum { ROM_HR_NONE = 0, ROM_HR_DEIM = 1, ROM_HR_QDEIM = 2, ROM_HR_QDEIM_FGS = 3 };
 enum { ROM_UPDATE_ISVD = 0, ROM_UPDATE_WSVD = 1, ROM_UPDATE_DIRECT = 2 };
+enum { ROM_SCHEME_BE = 0, ROM_SCHEME_SSPRK43 = 1 };
 
 /*
  * Batch configuration (Alg. 1 inputs: r, n_s, w_init, z, lambda; the time step
@@ -104,6 +105,21 @@ enum { ROM_UPDATE_ISVD = 0, ROM_UPDATE_WSVD = 1, ROM_UPDATE_DIRECT = 2 };
  *               `window` columns (r <= window <= 64); it starts from the last
  *               min(window, w_init) training snapshots.  The state transfer is
  *               Alg. 1's a <- Phi_new^T D (q~ - q_ref), formed in FP64.
+ *   scheme:     the time discretisation of the full and reduced models:
+ *               ROM_SCHEME_BE      backward Euler on the first-order finite
+ *                                  volume f (implicit; Secs. 5.1-5.2)
+ *               ROM_SCHEME_SSPRK43 the explicit structure of the detonation
+ *                                  case (Sec. 5.3, App. D): four-stage
+ *                                  third-order SSP Runge-Kutta on the
+ *                                  second-order f with Barth-Jespersen limited
+ *                                  face states.  fom_step is one such step
+ *                                  (the coarse correction one of size z dt),
+ *                                  the fine step the DEIM-Galerkin ROM of eq.
+ *                                  deim_galerkin_rom advanced by the same
+ *                                  scheme.  Needs ROM_GALERKIN and a sampler
+ *                                  (hyper != ROM_HR_NONE); newton_* and
+ *                                  rom_* settings are unused; the adjoint
+ *                                  entry points return ROM_E_UNSUPPORTED.
  */
 typedef struct {
   int32_t problem, precision, projection, hyper;
@@ -115,6 +131,7 @@ typedef struct {
   int32_t newton_max, rom_max, reorth_every;
   int32_t use_graph;
   int32_t update_rule, window;
+  int32_t scheme;
   double lambda, dt, newton_tol, rom_tol, tau_orth, tau_rho;
 } rom_config;
 
@@ -159,6 +176,8 @@ rom_status rom_destroy(rom_handle h);
  *   q_prev == NULL: out = f(q)                       (Sec. 2 eq. fom_continuous)
  *   otherwise:      out = q - q_prev - dt f(q)       (backward-Euler residual,
  *                                                    eq. be_residual_rom_section)
+ *   With ROM_SCHEME_SSPRK43, f is the limited second-order f and q_prev must
+ *   be NULL (ROM_E_INVAL otherwise).
  *   q, q_prev, out: device, T[total_dof]; out must not alias q or q_prev.
  */
 rom_status fom_residual(rom_handle h, const void* q, const void* q_prev, double dt, void* out,
@@ -169,8 +188,12 @@ rom_status fom_residual(rom_handle h, const void* q, const void* q_prev, double 
  * Newton on q - q_prev - dt f(q) = 0 from q = q_prev with the exact banded
  * Jacobian and a direct block-tridiagonal solve; stops per instance when
  * max|r| <= newton_tol, at most newton_max solves (Sec. 5.1 setup; App. B).
+ * With ROM_SCHEME_SSPRK43 it is one SSPRK(4,3) step of the limited
+ * second-order model (App. D): four evaluations of f, the stage combinations
+ * formed in FP64.
  *   q_prev, q_out: device, T[total_dof]; may alias.
- *   iters (optional): device int32[n_inst], Newton solves used per instance.
+ *   iters (optional): device int32[n_inst], Newton solves used per instance
+ *   (4, the stage count, on the explicit path).
  */
 rom_status fom_step(rom_handle h, const void* q_prev, double dt, void* q_out, int32_t* iters,
                     void* stream);
@@ -388,10 +411,12 @@ rom_status rom_set_tuning(rom_handle h, int32_t what, int32_t choice, int32_t* n
  * the mean milliseconds per launch are written to *ms.  The handle's reduced
  * state is not modified.
  *   ROM_PROF_RESIDUAL       f(q) for the batch (one launch), q: device T[total_dof]
+ *                           (the limited second-order f with ROM_SCHEME_SSPRK43)
  *   ROM_PROF_GALERKIN_PASS  one fused Galerkin pass over the basis (all instances)
  *   ROM_PROF_ISVD_PROJECT   one iSVD projection pass over the basis with snapshot q
  *   ROM_PROF_RESIDUAL_VJP   J_f(q)^T q for the batch
- *   ROM_PROF_FOM_STEP       one full backward-Euler Newton step from q (dt = cfg.dt)
+ *   ROM_PROF_FOM_STEP       one full backward-Euler Newton step from q (dt = cfg.dt),
+ *                           or one SSPRK(4,3) step with ROM_SCHEME_SSPRK43
  * Synchronises the stream.  Errors: ROM_E_INVAL for an unknown stage or reps < 1.
  */
 enum { ROM_PROF_RESIDUAL = 0, ROM_PROF_GALERKIN_PASS = 1, ROM_PROF_ISVD_PROJECT = 2,

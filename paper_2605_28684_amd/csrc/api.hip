@@ -128,6 +128,14 @@ rom_status validate(const rom_config* c) {
   if (c->update_rule != ROM_UPDATE_ISVD)
     ROM_REQUIRE(c->window >= c->r && c->window <= 64, ROM_E_INVAL,
                 "the windowed rules need r <= window <= 64");
+  ROM_REQUIRE(c->scheme == ROM_SCHEME_BE || c->scheme == ROM_SCHEME_SSPRK43, ROM_E_INVAL,
+              "unknown scheme");
+  if (c->scheme == ROM_SCHEME_SSPRK43) {
+    ROM_REQUIRE(c->projection == ROM_GALERKIN, ROM_E_UNSUPPORTED,
+                "the explicit scheme runs the (DEIM-)Galerkin ROM");
+    ROM_REQUIRE(c->hyper != ROM_HR_NONE, ROM_E_UNSUPPORTED,
+                "the explicit scheme runs the hyper-reduced Galerkin ROM (hyper != none)");
+  }
   if (c->hyper == ROM_HR_DEIM) {
     ROM_REQUIRE(c->n_s >= c->r && c->n_s <= 2 * c->r && c->n_s <= kMaxNs, ROM_E_INVAL,
                 "n_s must be in [r, 2r] with DEIM");
@@ -166,7 +174,7 @@ void free_all(rom_batch* h) {
                 h->d_epoch, h->rvjp, h->epart, h->ev_iters, h->phi_cm, h->Phi_alt, h->hr_as, h->hr_cnt};
   for (void* p : ps) (void)hipFree(p);
   void* pw[] = {h->win, h->lift, h->zmat, h->zpinv, h->phit, h->sig_scratch, h->qdeim_q,
-                h->fgs_g, h->d_tile_first};
+                h->fgs_g, h->d_tile_first, h->mesh5_phi, h->mesh5_qref};
   for (void* p : pw) (void)hipFree(p);
   pod_ws_free(&h->podws);
   bt_free(h);
@@ -277,6 +285,10 @@ rom_status setup(rom_batch* h) {
   if (c.hyper == ROM_HR_QDEIM || c.hyper == ROM_HR_QDEIM_FGS)
     ROM_TRY(alloc(&h->qdeim_q, (size_t)B * kMaxR * kMaxR));
   if (c.hyper == ROM_HR_QDEIM_FGS) ROM_TRY(alloc(&h->fgs_g, (size_t)h->total_cells));
+  if (c.scheme == ROM_SCHEME_SSPRK43) {
+    ROM_TRY(alloc(&h->mesh5_phi, (size_t)B * ns * 5 * h->nv * r));
+    ROM_TRY(alloc(&h->mesh5_qref, (size_t)B * ns * 5 * h->nv));
+  }
   if (c.hyper != ROM_HR_NONE) {
     ROM_TRY(alloc(&h->hr_cnt, (size_t)B));
     ROM_HIP_CHECK(hipMemset(h->hr_cnt, 0, sizeof(int32_t) * B));
@@ -310,7 +322,7 @@ rom_status setup(rom_batch* h) {
     ROM_TRY(pod_ws_alloc(h, std::max(c.window, r), &h->podws));
   }
   ROM_TRY(bt_setup(h));
-  h->fom_block = fom_block_ok(h);
+  h->fom_block = c.scheme == ROM_SCHEME_BE && fom_block_ok(h);
   if (window_split_ok(h)) {  // the second stream of a window (created outside any capture)
     ROM_TRY(alloc((char**)&h->Phi_alt, es * td * r));
     ROM_HIP_CHECK(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
@@ -320,6 +332,7 @@ rom_status setup(rom_batch* h) {
   ROM_TRY(isvd_kernels_prepare());
   ROM_TRY(adjoint_kernels_prepare());
   ROM_TRY(rom_kernels_prepare());
+  ROM_TRY(explicit_kernels_prepare());
   ROM_HIP_CHECK(hipDeviceSynchronize());
   return ROM_OK;
 }
@@ -331,6 +344,13 @@ rom_status fom_step_impl(rom_batch* h, const void* q_prev, double dt, void* q_ou
   const int B = h->cfg.n_inst;
   const size_t bytes = h->esz * h->total_dof;
   const bool f64 = h->cfg.precision == ROM_F64;
+  if (h->cfg.scheme == ROM_SCHEME_SSPRK43) {
+    ROM_TRY(fom_step_explicit(h, q_prev, dt, q_out, s));
+    if (iters_out)
+      hipLaunchKernelGGL(k_fill_i32v, dim3(nblk(B)), dim3(256), 0, s, iters_out, 4, (int64_t)B);
+    ROM_HIP_CHECK(hipGetLastError());
+    return ROM_OK;
+  }
   if (h->fom_block) {
     ROM_TRY(launch_fom_block(h, q_prev, dt, q_out, h->iters, s));
     if (iters_out) ROM_TRY(copy_words(h->iters, iters_out, 4 * (size_t)B, s));
@@ -460,6 +480,8 @@ rom_status rollout_check(rom_batch* h, const void* q0, int32_t n_steps, double d
   ROM_REQUIRE(n_steps >= 1, ROM_E_INVAL, "n_steps must be >= 1");
   ROM_REQUIRE(n_ckpt >= 0, ROM_E_INVAL, "n_ckpt must be >= 0");
   ROM_REQUIRE(dt > 0.0 && std::isfinite(dt), ROM_E_INVAL, "dt must be positive");
+  ROM_REQUIRE(h->cfg.scheme == ROM_SCHEME_BE, ROM_E_UNSUPPORTED,
+              "the full-order adjoint covers the backward-Euler scheme");
   return ROM_OK;
 }
 
@@ -597,11 +619,11 @@ int64_t layout_hash(const rom_batch* h) {
 SaveHeader save_header(const rom_batch* h, const SaveLayout& L) {
   SaveHeader hd{};
   const rom_config& c = h->cfg;
-  const int64_t v[20] = {kSaveMagic, kSaveVersion, c.problem, c.precision, c.n_inst, h->total_dof,
+  const int64_t v[21] = {kSaveMagic, kSaveVersion, c.problem, c.precision, c.n_inst, h->total_dof,
                          c.r, c.n_s, h->nv, layout_hash(h), h->n_fine, h->n_update, h->n_events,
                          h->n_reorth, (int64_t)L.total, c.hyper, c.update_rule, c.window,
-                         h->win_count, h->win_head};
-  for (int i = 0; i < 20; ++i) hd.w[i] = v[i];
+                         h->win_count, h->win_head, c.scheme};
+  for (int i = 0; i < 21; ++i) hd.w[i] = v[i];
   return hd;
 }
 
@@ -674,6 +696,10 @@ rom_status fom_residual(rom_handle h, const void* q, const void* q_prev, double 
   ROM_REQUIRE(out != q && out != q_prev, ROM_E_INVAL, "out must not alias q or q_prev");
   ROM_REQUIRE(std::isfinite(dt), ROM_E_INVAL, "dt must be finite");
   h->last_stream = (hipStream_t)stream;
+  if (h->cfg.scheme == ROM_SCHEME_SSPRK43) {
+    ROM_REQUIRE(!q_prev, ROM_E_INVAL, "the explicit scheme has no backward-Euler residual");
+    return launch_residual2(h, q, out, (hipStream_t)stream);
+  }
   return launch_residual(h, q, q_prev, dt, out, (hipStream_t)stream);
 }
 
@@ -853,7 +879,7 @@ rom_status rom_load(rom_handle h, const void* src, size_t bytes, void* stream) {
     ROM_REQUIRE(got.w[i] == want.w[i], ROM_E_INVAL,
                 "the saved state comes from a different configuration or layout");
   ROM_REQUIRE(got.w[14] == (int64_t)L.total && got.w[15] == want.w[15] &&
-                  got.w[16] == want.w[16] && got.w[17] == want.w[17],
+                  got.w[16] == want.w[16] && got.w[17] == want.w[17] && got.w[20] == want.w[20],
               ROM_E_INVAL, "the saved state comes from a different configuration");
   if (h->win)
     ROM_REQUIRE(got.w[18] >= 0 && got.w[18] <= h->cfg.window && got.w[19] >= 0 &&
@@ -894,6 +920,8 @@ rom_status fom_residual_vjp(rom_handle h, const void* q, const void* q_prev, dou
                             const void* gbar, void* gq, void* gq_prev, void* stream) {
   ROM_REQUIRE(h && q && gbar && gq, ROM_E_INVAL, "handle, q, gbar and gq are required");
   ROM_REQUIRE(gq != gbar && gq != q, ROM_E_INVAL, "gq must not alias q or gbar");
+  ROM_REQUIRE(h->cfg.scheme == ROM_SCHEME_BE, ROM_E_UNSUPPORTED,
+              "the residual adjoint covers the backward-Euler scheme");
   h->last_stream = (hipStream_t)stream;
   return launch_residual_vjp(h, q, q_prev, dt, gbar, gq, gq_prev, (hipStream_t)stream);
 }
@@ -902,6 +930,8 @@ rom_status fom_step_vjp(rom_handle h, const void* q, double dt, const void* gbar
                         void* stream) {
   ROM_REQUIRE(h && q && gbar && gq_prev, ROM_E_INVAL, "handle, q, gbar and gq_prev are required");
   ROM_REQUIRE(dt > 0.0 && std::isfinite(dt), ROM_E_INVAL, "dt must be positive");
+  ROM_REQUIRE(h->cfg.scheme == ROM_SCHEME_BE, ROM_E_UNSUPPORTED,
+              "the step adjoint covers the backward-Euler scheme");
   hipStream_t s = (hipStream_t)stream;
   h->last_stream = s;
   ROM_TRY(launch_assemble_adjoint(h, q, dt, gbar, s));
@@ -1146,6 +1176,8 @@ rom_status rom_profile(rom_handle h, int32_t stage, int32_t reps, const void* q,
   ROM_REQUIRE(reps >= 1, ROM_E_INVAL, "reps must be >= 1");
   ROM_REQUIRE(stage >= ROM_PROF_RESIDUAL && stage <= ROM_PROF_FOM_STEP, ROM_E_INVAL, "unknown stage");
   ROM_REQUIRE(q || stage == ROM_PROF_GALERKIN_PASS, ROM_E_INVAL, "q is required for this stage");
+  ROM_REQUIRE(h->cfg.scheme == ROM_SCHEME_BE || stage != ROM_PROF_RESIDUAL_VJP, ROM_E_UNSUPPORTED,
+              "the explicit scheme has no residual adjoint");
   hipStream_t s = (hipStream_t)stream;
   h->last_stream = s;
   // the Galerkin pass writes only scratch: a and the flags stay intact
@@ -1157,7 +1189,11 @@ rom_status rom_profile(rom_handle h, int32_t stage, int32_t reps, const void* q,
   ROM_HIP_CHECK(hipEventRecord(e0, s));
   for (int i = 0; i < reps && st == ROM_OK; ++i) {
     switch (stage) {
-      case ROM_PROF_RESIDUAL: st = launch_residual(h, q, nullptr, 0.0, h->vjp_tmp, s); break;
+      case ROM_PROF_RESIDUAL:
+        st = h->cfg.scheme == ROM_SCHEME_SSPRK43
+                 ? launch_residual2(h, q, h->vjp_tmp, s)
+                 : launch_residual(h, q, nullptr, 0.0, h->vjp_tmp, s);
+        break;
       case ROM_PROF_GALERKIN_PASS: st = launch_galerkin_pass(h, s); break;
       case ROM_PROF_ISVD_PROJECT: st = launch_isvd_project(h, q, s); break;
       case ROM_PROF_RESIDUAL_VJP:

@@ -134,6 +134,8 @@ struct rom_batch {
   double* M = nullptr;       // [n_inst * r * n_s]
   double* mesh_phi = nullptr;  // [n_inst * n_s * 3 * nv * r]
   double* mesh_qref = nullptr; // [n_inst * n_s * 3 * nv]
+  double* mesh5_phi = nullptr;  // [n_inst * n_s * 5 * nv * r]: five-cell mesh (explicit scheme)
+  double* mesh5_qref = nullptr; // [n_inst * n_s * 5 * nv]
   uint32_t* chosen = nullptr;  // [total_dof] epoch marks for DEIM
   void* phi_cm = nullptr;      // T[total_dof * r]: Phi by columns per instance (DEIM only)
   double* hr_as = nullptr;     // [n_inst * (n_s + r) * (r + 1)]: rows of [A_s | b], then [M A_s | -M b] (DEIM only)
@@ -291,6 +293,15 @@ rom_status launch_galerkin_tail(rom_batch* h, int it0, hipStream_t s);
 rom_status launch_rotate_mfma(rom_batch* h, const double* pr, void* dst, hipStream_t s);
 rom_status launch_project_fast(rom_batch* h, const void* y, const double* p1, int ldp, int mode,
                                double* part, int pst, double* q1out, hipStream_t s);
+
+// ---- explicit.hip: the SSPRK(4,3) path (limited second-order residual)
+rom_status launch_residual2(rom_batch* h, const void* q, void* out, hipStream_t s);
+// one SSPRK(4,3) full-order step; uses fq_prev, fq and vjp_tmp as stage buffers
+rom_status fom_step_explicit(rom_batch* h, const void* q_prev, double dt, void* q_out,
+                             hipStream_t s);
+rom_status launch_mesh5(rom_batch* h, hipStream_t s);  // after every rebuild of P
+rom_status launch_hr_explicit_step(rom_batch* h, hipStream_t s);
+rom_status explicit_kernels_prepare();
 
 // ---- small helpers (api.cpp)
 rom_status fill_zero(void* p, size_t bytes, hipStream_t s);

@@ -1369,6 +1369,7 @@ rom_status rom_kernels_prepare() {
 }
 
 rom_status launch_rom_fine_step(rom_batch* h, hipStream_t s) {
+  if (h->cfg.scheme == ROM_SCHEME_SSPRK43) return launch_hr_explicit_step(h, s);
   if (h->cfg.hyper != ROM_HR_NONE) return hr_step(h, s);
   if (h->cfg.problem != ROM_BURGERS) {
     set_error("the full (non-hyper-reduced) Galerkin step is implemented for Burgers only");
@@ -1406,7 +1407,9 @@ rom_status launch_galerkin_pass(rom_batch* h, hipStream_t s) {
 }
 
 rom_status launch_rebuild(rom_batch* h, hipStream_t s) {
-  return h->cfg.precision == ROM_F64 ? rebuild_t<double>(h, s) : rebuild_t<float>(h, s);
+  ROM_TRY(h->cfg.precision == ROM_F64 ? rebuild_t<double>(h, s) : rebuild_t<float>(h, s));
+  if (h->cfg.scheme == ROM_SCHEME_SSPRK43) ROM_TRY(launch_mesh5(h, s));
+  return ROM_OK;
 }
 
 rom_status launch_reconstruct(rom_batch* h, void* out, hipStream_t s) {

@@ -31,6 +31,7 @@ FLAG_SINGULAR, FLAG_ROM_NOCONV, FLAG_REORTH = 16, 32, 64
 GET_BASIS, GET_SIGMA, GET_A, GET_QTILDE, GET_SAMPLES, GET_YCORR = 0, 1, 2, 3, 4, 5
 GET_QREF, GET_DVAR, GET_PINV, GET_COUNTERS, GET_UBAR, GET_WINDOW = 6, 7, 8, 9, 10, 11
 UPDATE_ISVD, UPDATE_WSVD, UPDATE_DIRECT = 0, 1, 2
+SCHEME_BE, SCHEME_SSPRK43 = 0, 1
 N_COUNTERS = 6
 
 
@@ -52,6 +53,7 @@ class rom_config(ctypes.Structure):
                 ("newton_max", ctypes.c_int32), ("rom_max", ctypes.c_int32),
                 ("reorth_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("update_rule", ctypes.c_int32), ("window", ctypes.c_int32),
+                ("scheme", ctypes.c_int32),
                 ("lambda_", ctypes.c_double), ("dt", ctypes.c_double),
                 ("newton_tol", ctypes.c_double), ("rom_tol", ctypes.c_double),
                 ("tau_orth", ctypes.c_double), ("tau_rho", ctypes.c_double)]
@@ -142,6 +144,7 @@ def make_config(w: W.Workload, use_graph=True, precision=None, **over):
     cfg.use_graph = 1 if use_graph else 0
     cfg.update_rule = {"isvd": UPDATE_ISVD, "wsvd": UPDATE_WSVD, "direct": UPDATE_DIRECT}[w.update]
     cfg.window = w.window
+    cfg.scheme = {"be": SCHEME_BE, "ssprk43": SCHEME_SSPRK43}[w.scheme]
     cfg.lambda_, cfg.dt = w.lam, w.dt
     cfg.newton_tol, cfg.rom_tol = w.newton_tol, w.rom_tol
     cfg.tau_orth, cfg.tau_rho = w.tau_orth, w.tau_rho
