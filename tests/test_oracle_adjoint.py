@@ -83,3 +83,73 @@ def test_adjoint_sigma_and_ycorr_unused_without_events():
 
 def test_adjoint_non_orthonormal_basis():
     _fd_check(n_steps=7, phi_noise=0.3)
+
+
+# ---------------------------------------------------------------- whole rollout
+def _rollout_case(w_init=5, r=3, n_s=6, hyper="deim", n=48, z=2):
+    w = W.euler_adjoint_f32(n_inst=1, n=n, r=r, n_s=n_s, z=z, N_t=20, precision=W.F64)
+    prm = w.params()
+    prm.update(reorth_every=0, newton_tol=1e-13, rom_tol=1e-14, rom_max=30, newton_max=30,
+               w_init=w_init, hyper=hyper)
+    return prm, w.phys[0], w.q0.copy(), w.extra["target"][:w.q0.shape[0]]
+
+
+@pytest.mark.parametrize("case", ["deim_truncated_pod", "deim_w_init_eq_r", "qdeim"])
+def test_rollout_vjp_matches_central_differences(case):
+    """d L / d q0 through Alg. 1 as a whole (training BE steps, preprocessing,
+    POD, a^{w_init}, the first coarse step; then HR-LSPG steps and events), with
+    L = 1/2 |q~_end - q_tgt|^2 on the perturbed-Sod recipe of the adjoint
+    configuration at 48 cells, against central differences (h = 1e-7) of the
+    oracle's own forward with the recorded sample schedule: relative error
+    <= 1e-6 on three random directions (measured about 1e-8).  Planted
+    mistakes in any single term (the (P^T Phi)^+ adjoint, the D or q_ref terms
+    of a step, an event or the seed, the POD's out-of-span term or its sigma
+    term, the preprocessing's scale, the first coarse step, an untransposed
+    step solve) give 2e-3 or more."""
+    kw = dict(deim_truncated_pod={}, deim_w_init_eq_r=dict(w_init=3),
+              qdeim=dict(hyper="qdeim", n_s=3))[case]
+    prm, phys, q0, tgt = _rollout_case(**kw)
+    n_steps = 6
+    st, _, sched = A.rollout_forward(W.EULER_RUSANOV, phys, q0, prm, n_steps)
+    qt = O.reconstruct(st["q_ref"], st["d"], st["Phi"], st["a"])
+    g, _ = A.rollout_vjp(W.EULER_RUSANOV, phys, q0, prm, n_steps, qt - tgt, sched)
+    rng = np.random.default_rng(31)
+    h = 1e-7
+    for _ in range(3):
+        v = rng.normal(size=q0.shape)
+        Lp = A.rollout_loss(W.EULER_RUSANOV, phys, q0 + h * v, prm, n_steps, tgt, sched)
+        Lm = A.rollout_loss(W.EULER_RUSANOV, phys, q0 - h * v, prm, n_steps, tgt, sched)
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - g @ v) <= 1e-6 * abs(fd), (fd, g @ v)
+
+
+def test_pinv_vjp_matches_central_differences():
+    """The adjoint of M = A^+ (full column rank, n_s > r) against central
+    differences of numpy's pinv, on random A, Mbar and directions."""
+    rng = np.random.default_rng(5)
+    A_ = rng.normal(size=(9, 4))
+    Mb = rng.normal(size=(4, 9))
+    Ab = A._pinv_vjp(A_, np.linalg.pinv(A_), Mb)
+    for _ in range(3):
+        V = rng.normal(size=A_.shape)
+        h = 1e-6
+        fd = np.sum(Mb * (np.linalg.pinv(A_ + h * V) - np.linalg.pinv(A_ - h * V))) / (2 * h)
+        assert abs(fd - np.sum(Ab * V)) <= 1e-8 * abs(fd)
+
+
+def test_pod_vjp_matches_central_differences():
+    """The adjoint of the truncated, sign-fixed POD (leading r = 3 of w = 6
+    columns) against central differences of the oracle's pod."""
+    rng = np.random.default_rng(6)
+    X = rng.normal(size=(40, 6)) * np.array([5.0, 3.0, 2.0, 1.0, 0.5, 0.2])
+    Phi, s = O.pod(X, 3)
+    Pb = rng.normal(size=Phi.shape)
+    sb = rng.normal(size=3)
+    Xb = A._pod_vjp(X, Phi, Pb, sb)
+    for _ in range(3):
+        V = rng.normal(size=X.shape)
+        h = 1e-6
+        Pp, sp_ = O.pod(X + h * V, 3)
+        Pm, sm_ = O.pod(X - h * V, 3)
+        fd = (np.sum(Pb * (Pp - Pm)) + sb @ (sp_ - sm_)) / (2 * h)
+        assert abs(fd - np.sum(Xb * V)) <= 1e-6 * abs(fd)
