@@ -350,6 +350,43 @@ rom_status fom_rollout_vjp_noalloc(rom_handle h, const void* q0, int32_t n_steps
                                    int32_t n_ckpt, const void* gbar, void* gq0, void* stream);
 
 /*
+ * rom_offline - run Alg. 1's offline stage from q0 on an existing handle (the
+ * same work as rom_create with q0: w_init training BE steps, preprocessing,
+ * POD, a^{w_init}, the first coarse step, sampling and rebuild); the counters
+ * restart (fine step n = w_init, no updates or events).
+ *   q0: device, T[total_dof].  Errors: ROM_E_INVAL (NULL handle or q0).
+ */
+rom_status rom_offline(rom_handle h, const void* q0, void* stream);
+
+/*
+ * rom_rollout_vjp - gradient of <gbar, q~_end> with respect to the initial
+ * state q0 through Alg. 1 as a whole: the offline stage (training BE steps,
+ * preprocessing with q_ref = q0 and D, the POD, a^{w_init}, the first coarse
+ * step) and n_steps fine hyper-reduced LSPG steps with their events, where
+ * q~_end = q_ref + D^-1 Phi a after those steps.  The sample rows are
+ * piecewise constant in q0: the forward run's rows are held fixed, and their
+ * (P^T Phi)^+ is differentiated.  An HR-LSPG step is differentiated by the
+ * implicit-function theorem on its vanishing weighted residual (no second
+ * derivatives); events as in rom_online_vjp, plus the q_ref and D terms of
+ * the preprocessing; the POD through the SVD adjoint of the training matrix
+ * (distinct singular values).  The online loop keeps checkpoints at segment
+ * starts (n_ckpt of them, or ceil(sqrt(n_steps)) for 0) and recomputes each
+ * segment; the offline stage keeps its w_init training states.  An extension:
+ * the paper differentiates nothing.
+ *   q0, gbar, gq0: device, T[total_dof], caller-owned; gq0 receives dL/dq0.
+ *   The handle ends at the rollout's end state (as after rom_offline and
+ *   rom_step(n_steps)).  Allocates its workspace for the call.  Synchronises
+ *   the stream.
+ * Errors: ROM_E_INVAL (NULL pointers, n_steps < 1, n_ckpt < 0),
+ * ROM_E_UNSUPPORTED (no hyper-reduction, the Galerkin projection, a windowed
+ * update rule, the explicit scheme, or a re-orthonormalisation inside the
+ * rollout), ROM_E_NOMEM.  A singular Gauss-Newton matrix or rho = 0 at an event
+ * sets ROM_FLAG_SINGULAR for the instance.
+ */
+rom_status rom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, int32_t n_ckpt,
+                           const void* gbar, void* gq0, void* stream);
+
+/*
  * rom_online_vjp - gradient through the online part of Alg. 1 (an extension
  * beyond the paper): n_fine fine Galerkin steps from the current state, with
  * the adaptation events that fall due (coarse backward-Euler step of y_corr,

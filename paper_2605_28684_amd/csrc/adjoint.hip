@@ -68,24 +68,40 @@ template <typename T>
 __global__ __launch_bounds__(kAT) void k_online_seed(
     int r, const int64_t* __restrict__ dof_off, const double* __restrict__ dvar,
     const T* __restrict__ Phi, const double* __restrict__ a, const T* __restrict__ qbar,
-    double* __restrict__ abar, double* __restrict__ phibar) {
+    double* __restrict__ abar, double* __restrict__ phibar, int nv, double* __restrict__ qrbar,
+    double* __restrict__ dvbar) {
   __shared__ double cP[kSC * kMaxR];
   __shared__ double cq[kSC];
+  __shared__ double red[kAT / 64];
   const int b = blockIdx.x, tid = threadIdx.x;
   const int64_t base = dof_off[b], n = dof_off[b + 1] - base;
-  const double dinv = 1.0 / dvar[b];
+  const double* dvb = dvar + (size_t)b * nv;
+  double dva[12];
+  for (int v = 0; v < 12; ++v) dva[v] = 0.0;
   // (Phi^T qbar)_c: G row groups of r threads, their sums added in group order
   const int G = kAT / r, gq = tid / r, gc = tid - (tid / r) * r;
   double acc = 0.0;
   for (int64_t r0 = 0; r0 < n; r0 += kSC) {
     const int nr = (int)(n - r0 < kSC ? n - r0 : kSC);
     for (int e = tid; e < nr * r; e += kAT) cP[e] = (double)Phi[(base + r0) * r + e];
-    for (int k = tid; k < nr; k += kAT) cq[k] = (double)qbar[base + r0 + k];
+    // cq holds D^-1 qbar
+    for (int k = tid; k < nr; k += kAT)
+      cq[k] = (double)qbar[base + r0 + k] / dvb[(r0 + k) % nv];
     __syncthreads();
     if (gq < G)
       for (int k = gq; k < nr; k += G) acc += cP[k * r + gc] * cq[k];
     for (int e = tid; e < nr * r; e += kAT)
-      phibar[(base + r0) * r + e] = cq[e / r] * dinv * a[(size_t)b * r + e % r];
+      phibar[(base + r0) * r + e] = cq[e / r] * a[(size_t)b * r + e % r];
+    // q_ref and D terms: qrbar = qbar, dvbar[v] -= sum qbar (Phi a) / d^2
+    if (qrbar)
+      for (int k = tid; k < nr; k += kAT) {
+        const int v = (int)((r0 + k) % nv);
+        double pa = 0.0;
+        for (int c = 0; c < r; ++c) pa += cP[k * r + c] * a[(size_t)b * r + c];
+        qrbar[base + r0 + k] = (double)qbar[base + r0 + k];
+        for (int u = 0; u < 12; ++u)
+          if (u == v) dva[u] -= cq[k] * pa / dvb[v];
+      }
     __syncthreads();
   }
   if (gq < G) cP[gq * r + gc] = acc;
@@ -93,7 +109,13 @@ __global__ __launch_bounds__(kAT) void k_online_seed(
   if (tid < r) {
     double s = 0.0;
     for (int g = 0; g < G; ++g) s += cP[g * r + tid];
-    abar[(size_t)b * r + tid] = s * dinv;
+    abar[(size_t)b * r + tid] = s;
+  }
+  if (qrbar) {
+    for (int v = 0; v < nv; ++v) {
+      const double sv_ = block_sum(dva[v], red);
+      if (tid == 0) dvbar[(size_t)b * nv + v] = sv_;
+    }
   }
 }
 
@@ -251,7 +273,8 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
     const double* __restrict__ ubar, const double* __restrict__ prs,
     const double* __restrict__ sig_new, double* __restrict__ abar,
     double* __restrict__ phibar, double* __restrict__ sigbar, double* __restrict__ ybar,
-    double* __restrict__ qs, double* __restrict__ js, uint32_t* flags) {
+    double* __restrict__ qs, double* __restrict__ js, uint32_t* flags, int nv,
+    double* __restrict__ qrbar, double* __restrict__ dvbar) {
   extern __shared__ double sm[];
   __shared__ double red[kET / 64];
   __shared__ double vr[7][kMaxR + 1];  // p1, p2, abar', pbar (rhobar in [r]), p1bar, p2bar, wr
@@ -276,7 +299,7 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
   double* p2b = vr[5];
   double* wr = vr[6];
   const int64_t base = dof_off[b], nd = dof_off[b + 1] - base;
-  const double d = dvar[b];
+  const double* dvb = dvar + (size_t)b * nv;   // D per variable; row i has variable i mod nv
   const double* pr = prs + (size_t)b * (2 * r + 2);
   const double irho = pr[2 * r];
   if (irho == 0.0) {   // rho = 0: the update is not differentiable there
@@ -336,7 +359,7 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
     __syncthreads();
     if (r0 + CH < nd) chunk_fetch(Phi, phibar, (base + r0 + CH) * r, chunk_ne(r0 + CH), true, rp, rb);
     for (int k = tid; k < nr; k += kET) {
-      double q = d * ((double)ynew[base + r0 + k] - (double)qref[base + r0 + k]);
+      double q = dvb[(r0 + k) % nv] * ((double)ynew[base + r0 + k] - (double)qref[base + r0 + k]);
       for (int c = 0; c < r; ++c) q -= cP[k * LDR + c] * (p1[c] + p2[c]);
       c0[k] = q;
       qs[base + r0 + k] = q;
@@ -523,7 +546,7 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
     if (r0 + CH < nd) chunk_fetch(Phi, phibar, (base + r0 + CH) * r, chunk_ne(r0 + CH), true, rp, rb);
     for (int k = tid; k < nr; k += kET) {
       const int64_t g = base + r0 + k;
-      double q1 = d * ((double)ynew[g] - (double)qref[g]);
+      double q1 = dvb[(r0 + k) % nv] * ((double)ynew[g] - (double)qref[g]);
       double t = 0.0;
       for (int c = 0; c < r; ++c) {
         q1 -= cP[k * LDR + c] * p1[c];
@@ -546,7 +569,10 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
   }
   group_sum(acc, p1b);
   // pass D: Phibar_old += -q1bar p1^T + yhat p1bar^T; yhatbar = q1bar + Phi p1bar;
-  // ybar += D yhatbar
+  // ybar += D yhatbar; with qrbar: qrbar -= D yhatbar, and dvbar[v] += the sum
+  // of yhatbar (y - q_ref) over the rows of variable v
+  double dva[12];
+  for (int v = 0; v < 12; ++v) dva[v] = 0.0;
   if (nd > 0) chunk_fetch(Phi, phibar, base * r, chunk_ne(0), true, rp, rb);
   for (int64_t r0 = 0; r0 < nd; r0 += CH) {
     const int nr = (int)(nd - r0 < CH ? nd - r0 : CH);
@@ -555,13 +581,21 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
     if (r0 + CH < nd) chunk_fetch(Phi, phibar, (base + r0 + CH) * r, chunk_ne(r0 + CH), true, rp, rb);
     for (int k = tid; k < nr; k += kET) {
       const int64_t g = base + r0 + k;
-      const double yh = d * ((double)ynew[g] - (double)qref[g]);
+      const int v = (int)((r0 + k) % nv);
+      const double d = dvb[v];
+      const double dy = (double)ynew[g] - (double)qref[g];
+      const double yh = d * dy;
       const double q1b = js[g];
       double t = 0.0;
       for (int c = 0; c < r; ++c) t += cP[k * LDR + c] * p1b[c];
       c0[k] = q1b;
       c1[k] = yh;
       ybar[g] += d * (q1b + t);
+      if (qrbar) {
+        qrbar[g] -= d * (q1b + t);
+        for (int u = 0; u < 12; ++u)
+          if (u == v) dva[u] += (q1b + t) * dy;
+      }
     }
     __syncthreads();
     for (int e = tid; e < nr * r; e += kET) {
@@ -569,6 +603,12 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
       phibar[(base + r0) * r + e] = cB[k * LDR + c] - c0[k] * p1[c] + c1[k] * p1b[c];
     }
     __syncthreads();
+  }
+  if (qrbar) {
+    for (int v = 0; v < nv; ++v) {
+      const double sv_ = block_sum(dva[v], red);
+      if (tid == 0) dvbar[(size_t)b * nv + v] += sv_;
+    }
   }
 }
 
@@ -584,14 +624,16 @@ __global__ void k_to_float(const double* __restrict__ x, float* __restrict__ y, 
 }  // namespace
 
 rom_status launch_online_seed(rom_batch* h, const void* qbar, double* abar, double* phibar,
-                              hipStream_t s) {
+                              hipStream_t s, double* qrbar, double* dvbar) {
   const int B = h->cfg.n_inst, r = h->cfg.r;
   if (h->cfg.precision == ROM_F64)
     hipLaunchKernelGGL((k_online_seed<double>), dim3(B), dim3(kAT), 0, s, r, h->d_dof_off,
-                       h->d_var, (const double*)h->Phi, h->a, (const double*)qbar, abar, phibar);
+                       h->d_var, (const double*)h->Phi, h->a, (const double*)qbar, abar, phibar,
+                       h->nv, qrbar, dvbar);
   else
     hipLaunchKernelGGL((k_online_seed<float>), dim3(B), dim3(kAT), 0, s, r, h->d_dof_off,
-                       h->d_var, (const float*)h->Phi, h->a, (const float*)qbar, abar, phibar);
+                       h->d_var, (const float*)h->Phi, h->a, (const float*)qbar, abar, phibar,
+                       h->nv, qrbar, dvbar);
   ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
 }
@@ -622,19 +664,19 @@ rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new
                             const double* sig_old, const double* a_old, const double* ubar,
                             const double* pr, const double* sig_new, double* abar,
                             double* phibar, double* sigbar, double* ybar, double* qs, double* js,
-                            hipStream_t s) {
+                            hipStream_t s, double* qrbar, double* dvbar) {
   const int B = h->cfg.n_inst, r = h->cfg.r;
   const size_t shm = event_vjp_shm(r);
   if (h->cfg.precision == ROM_F64)
     hipLaunchKernelGGL((k_event_vjp<double>), dim3(B), dim3(kET), shm, s, r, h->cfg.lambda,
                        h->d_dof_off, h->d_var, (const double*)Phi_old, (const double*)y_new,
                        (const double*)h->q_ref, sig_old, a_old, ubar, pr, sig_new, abar, phibar,
-                       sigbar, ybar, qs, js, h->flags);
+                       sigbar, ybar, qs, js, h->flags, h->nv, qrbar, dvbar);
   else
     hipLaunchKernelGGL((k_event_vjp<float>), dim3(B), dim3(kET), shm, s, r, h->cfg.lambda,
                        h->d_dof_off, h->d_var, (const float*)Phi_old, (const float*)y_new,
                        (const float*)h->q_ref, sig_old, a_old, ubar, pr, sig_new, abar, phibar,
-                       sigbar, ybar, qs, js, h->flags);
+                       sigbar, ybar, qs, js, h->flags, h->nv, qrbar, dvbar);
   ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
 }

@@ -973,6 +973,245 @@ rom_status fom_rollout_vjp_noalloc(rom_handle h, const void* q0, int32_t n_steps
   return rollout_vjp_impl(h, q0, dt, pl, gbar, gq0, (char*)ws, s);
 }
 
+rom_status rom_offline(rom_handle h, const void* q0, void* stream) {
+  ROM_REQUIRE(h && q0, ROM_E_INVAL, "handle and q0 are required");
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  h->n_update = 0;
+  h->n_events = 0;
+  h->n_reorth = 0;
+  h->win_count = 0;
+  h->win_head = 0;
+  return offline(h, q0, s);
+}
+
+rom_status rom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, int32_t n_ckpt,
+                           const void* gbar, void* gq0, void* stream) {
+  ROM_REQUIRE(h && q0 && gbar && gq0, ROM_E_INVAL, "handle, q0, gbar and gq0 are required");
+  ROM_REQUIRE(n_steps >= 1, ROM_E_INVAL, "n_steps must be >= 1");
+  ROM_REQUIRE(n_ckpt >= 0, ROM_E_INVAL, "n_ckpt must be >= 0");
+  const rom_config& c = h->cfg;
+  ROM_REQUIRE(c.hyper != ROM_HR_NONE && c.projection == ROM_LSPG, ROM_E_UNSUPPORTED,
+              "the rollout adjoint covers the hyper-reduced LSPG path");
+  ROM_REQUIRE(c.update_rule == ROM_UPDATE_ISVD && c.scheme == ROM_SCHEME_BE, ROM_E_UNSUPPORTED,
+              "the rollout adjoint covers the iSVD update and backward-Euler steps");
+  const int B = c.n_inst, r = c.r, n = r + 1, z = c.z, w = c.w_init, ns = c.n_s;
+  const int64_t T = n_steps;
+  auto due = [&](int64_t nf) { return (nf + 1 - w) % z == 0; };
+  {  // no re-orthonormalisation may fall inside the rollout
+    int64_t nu = 0;
+    for (int64_t k = 0; k < T; ++k)
+      if (due(w + k)) {
+        ++nu;
+        ROM_REQUIRE(!(c.reorth_every > 0 && nu % c.reorth_every == 0), ROM_E_UNSUPPORTED,
+                    "a re-orthonormalisation falls inside the rollout");
+      }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  const bool f64 = c.precision == ROM_F64;
+  const int64_t td = h->total_dof;
+  int64_t C = n_ckpt > 0 ? n_ckpt : (int64_t)std::ceil(std::sqrt((double)T));
+  if (C > T) C = T;
+  const int64_t S = (T + C - 1) / C;
+  const int64_t nseg = (T + S - 1) / S;
+  const int64_t E = S / z + 1;
+  const size_t phi_b = h->esz * (size_t)td * r, y_b = h->esz * (size_t)td;
+  const size_t br = 8 * (size_t)B * r;
+  const size_t state_b = phi_b + y_b + 2 * br;
+  const size_t ev_b = phi_b + y_b + 3 * br + 8 * (size_t)B * n * n + 8 * (size_t)B * (2 * r + 2);
+  const size_t winp_b = 4 * (size_t)B * ns, winm_b = 8 * (size_t)B * r * ns;
+  const size_t td8 = 8 * (size_t)td;
+  const size_t part_n = offline_vjp_part_doubles(h, w);
+  const size_t small_n = (size_t)B * ((size_t)w * r + (size_t)w * w + (size_t)r * w + 3 * (size_t)w * w);
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off += al(bytes); return o; };
+  const size_t o_ck = take((size_t)(nseg + 1) * state_b);
+  const size_t o_reca = take((size_t)S * br);
+  const size_t o_ev = take((size_t)E * ev_b);
+  const size_t o_winp = take((size_t)(E + 1) * winp_b);
+  const size_t o_winm = take((size_t)(E + 1) * winm_b);
+  const size_t o_scr0 = take(td8), o_scr1 = take(td8);
+  const size_t o_rhs = take(y_b), o_out = take(y_b);
+  const size_t o_qtr = take((size_t)w * y_b);
+  const size_t o_phi0 = take(phi_b), o_y0 = take(y_b);
+  const size_t o_ab = take(br), o_sb = take(br), o_pb = take(8 * (size_t)td * r);
+  const size_t o_yb = take(td8), o_qrb = take(td8), o_dvb = take(8 * (size_t)B * h->nv);
+  const size_t o_qb = take((size_t)(w + 1) * td8);
+  const size_t o_part = take(8 * part_n), o_small = take(8 * small_n);
+  char* ws = nullptr;
+  ROM_TRY(alloc(&ws, off));
+  PodWs pws;
+  rom_status st = pod_ws_alloc(h, w, &pws);
+  if (st != ROM_OK) { (void)hipFree(ws); return st; }
+  char* ck = ws + o_ck;
+  char* rec_a = ws + o_reca;
+  char* ev = ws + o_ev;
+  int32_t* winP = (int32_t*)(ws + o_winp);
+  double* winM = (double*)(ws + o_winm);
+  double* scr0 = (double*)(ws + o_scr0);
+  double* scr1 = (double*)(ws + o_scr1);
+  char* rhs = ws + o_rhs;
+  char* out = ws + o_out;
+  char* Qtr = ws + o_qtr;
+  char* phi0 = ws + o_phi0;
+  char* y0 = ws + o_y0;
+  double* abar = (double*)(ws + o_ab);
+  double* sigbar = (double*)(ws + o_sb);
+  double* phibar = (double*)(ws + o_pb);
+  double* ycbar = (double*)(ws + o_yb);
+  double* qrbar = (double*)(ws + o_qrb);
+  double* dvbar = (double*)(ws + o_dvb);
+  double* qb = (double*)(ws + o_qb);
+  double* part = (double*)(ws + o_part);
+  double* small = (double*)(ws + o_small);
+  struct Host { int64_t nf, nu, ne; };
+  std::vector<Host> hc(nseg + 1);
+  auto save = [&](int64_t j) -> rom_status {
+    char* p = ck + (size_t)j * state_b;
+    ROM_TRY(copy_words(h->Phi, p, phi_b, s));
+    ROM_TRY(copy_words(h->y_corr, p + phi_b, y_b, s));
+    ROM_TRY(copy_words(h->sigma, p + phi_b + y_b, br, s));
+    ROM_TRY(copy_words(h->a, p + phi_b + y_b + br, br, s));
+    hc[j] = Host{h->n_fine, h->n_update, h->n_events};
+    return ROM_OK;
+  };
+  // restoring a checkpoint also rebuilds P, (P^T Phi)^+ and the sample mesh:
+  // the kernels are deterministic, so they equal those of the forward run
+  auto restore = [&](int64_t j) -> rom_status {
+    const char* p = ck + (size_t)j * state_b;
+    ROM_TRY(copy_words(p, h->Phi, phi_b, s));
+    ROM_TRY(copy_words(p + phi_b, h->y_corr, y_b, s));
+    ROM_TRY(copy_words(p + phi_b + y_b, h->sigma, br, s));
+    ROM_TRY(copy_words(p + phi_b + y_b + br, h->a, br, s));
+    h->n_fine = hc[j].nf;
+    h->n_update = hc[j].nu;
+    h->n_events = hc[j].ne;
+    return launch_rebuild(h, s);
+  };
+  auto ev_phi = [&](int64_t e) { return ev + (size_t)e * ev_b; };
+  auto ev_y = [&](int64_t e) { return ev_phi(e) + phi_b; };
+  auto ev_sold = [&](int64_t e) { return (double*)(ev_y(e) + y_b); };
+  auto ev_aold = [&](int64_t e) { return ev_sold(e) + (size_t)B * r; };
+  auto ev_snew = [&](int64_t e) { return ev_aold(e) + (size_t)B * r; };
+  auto ev_u = [&](int64_t e) { return ev_snew(e) + (size_t)B * r; };
+  auto ev_pr = [&](int64_t e) { return ev_u(e) + (size_t)B * n * n; };
+  auto win_save = [&](int64_t k) -> rom_status {
+    ROM_TRY(copy_words(h->P, winP + (size_t)k * B * ns, winp_b, s));
+    return copy_words(h->M, winM + (size_t)k * B * r * ns, winm_b, s);
+  };
+  // ---- forward: the offline stage, keeping the training states and the QR
+  // of the POD, then the online loop with checkpoints at segment starts
+  for (int j = 0; j < w && st == ROM_OK; ++j)
+    st = fom_step_impl(h, j == 0 ? q0 : (const void*)(Qtr + (size_t)(j - 1) * y_b), c.dt,
+                       Qtr + (size_t)j * y_b, nullptr, s);
+  if (st == ROM_OK) st = launch_preprocess(h, q0, Qtr, w, s);
+  if (st == ROM_OK) st = launch_pod_ws(h, Qtr, w, pws, s);
+  const void* qlast = Qtr + (size_t)(w - 1) * y_b;
+  if (st == ROM_OK) st = launch_project_state(h, qlast, s);
+  if (st == ROM_OK) st = fom_step_impl(h, qlast, z * c.dt, h->y_corr, nullptr, s);
+  if (st == ROM_OK) st = launch_rebuild(h, s);
+  if (st == ROM_OK) st = copy_words(h->Phi, phi0, phi_b, s);
+  if (st == ROM_OK) st = copy_words(h->y_corr, y0, y_b, s);
+  h->n_fine = w;
+  h->n_update = 0;
+  h->n_events = 0;
+  h->n_reorth = 0;
+  h->has_rom = true;
+  for (int64_t j = 0; j < nseg && st == ROM_OK; ++j) {
+    st = save(j);
+    const int64_t L = std::min(S, T - j * S);
+    for (int64_t k = 0; k < L && st == ROM_OK; ++k) st = fine_step_impl(h, s);
+  }
+  if (st == ROM_OK) st = save(nseg);
+  // ---- seed at the end state (with the q_ref and D terms)
+  if (st == ROM_OK) st = launch_online_seed(h, gbar, abar, phibar, s, qrbar, dvbar);
+  if (st == ROM_OK) st = fill_zero(sigbar, br, s);
+  if (st == ROM_OK) st = fill_zero(ycbar, td8, s);
+  // ---- the online loop backward, one segment at a time
+  for (int64_t j = nseg - 1; j >= 0 && st == ROM_OK; --j) {
+    st = restore(j);
+    if (st == ROM_OK) st = win_save(0);
+    const int64_t L = std::min(S, T - j * S);
+    std::vector<int64_t> after;
+    for (int64_t k = 0; k < L && st == ROM_OK; ++k) {
+      st = launch_rom_fine_step(h, s);
+      if (st == ROM_OK) st = copy_words(h->a, rec_a + (size_t)k * br, br, s);
+      if (st == ROM_OK && due(h->n_fine)) {
+        const int64_t e = (int64_t)after.size();
+        after.push_back(k);
+        st = copy_words(h->Phi, ev_phi(e), phi_b, s);
+        if (st == ROM_OK) st = copy_words(h->sigma, ev_sold(e), br, s);
+        if (st == ROM_OK) st = copy_words(h->a, ev_aold(e), br, s);
+        if (st == ROM_OK) st = fom_step_impl(h, h->y_corr, z * c.dt, h->y_corr, nullptr, s);
+        if (st == ROM_OK) st = copy_words(h->y_corr, ev_y(e), y_b, s);
+        if (st == ROM_OK) st = launch_isvd_core(h, h->y_corr, h->part, s);
+        if (st == ROM_OK) st = copy_words(h->ubar, ev_u(e), 8 * (size_t)B * n * n, s);
+        if (st == ROM_OK) st = copy_words(h->rstate, ev_pr(e), 8 * (size_t)B * (2 * r + 2), s);
+        if (st == ROM_OK) st = copy_words(h->sigma, ev_snew(e), br, s);
+        if (st == ROM_OK) st = launch_isvd_apply(h, s);
+        h->n_update += 1;
+        if (st == ROM_OK) st = launch_rebuild(h, s);
+        if (st == ROM_OK) st = win_save(e + 1);
+        h->n_events += 1;
+      }
+      h->n_fine += 1;
+    }
+    for (int64_t k = L - 1; k >= 0 && st == ROM_OK; --k) {
+      int64_t e_next = -1;   // first event at or after step k: its Phi_old is step k's basis
+      for (int64_t e = 0; e < (int64_t)after.size(); ++e)
+        if (after[e] >= k) { e_next = e; break; }
+      if (e_next >= 0 && after[e_next] == k) {
+        const int64_t e = e_next;
+        st = launch_event_vjp(h, ev_phi(e), ev_y(e), ev_sold(e), ev_aold(e), ev_u(e), ev_pr(e),
+                              ev_snew(e), abar, phibar, sigbar, ycbar, scr0, scr1, s, qrbar,
+                              dvbar);
+        if (st == ROM_OK) st = convert_words(ycbar, true, rhs, f64, td, s);
+        if (st == ROM_OK) st = launch_assemble_adjoint(h, ev_y(e), z * c.dt, rhs, s);
+        if (st == ROM_OK) st = bt_solve(h, -1, nullptr, out, s);
+        if (st == ROM_OK) st = convert_words(out, f64, ycbar, true, td, s);
+      }
+      if (st != ROM_OK) break;
+      const int64_t wi = e_next >= 0 ? e_next : (int64_t)after.size();
+      const void* phi_k = e_next >= 0 ? (const void*)ev_phi(e_next) : (const void*)h->Phi;
+      st = launch_hr_step_vjp(h, phi_k, winP + (size_t)wi * B * ns, winM + (size_t)wi * B * r * ns,
+                              (const double*)(rec_a + (size_t)k * br), abar, phibar, qrbar, dvbar,
+                              s);
+    }
+  }
+  // ---- the offline stage backward
+  if (st == ROM_OK) st = fill_zero(qb, (size_t)(w + 1) * td8, s);
+  double* qbw = qb + (size_t)w * td;
+  if (st == ROM_OK)
+    st = launch_offline_a_vjp(h, phi0, qlast, abar, phibar, qbw, qrbar, dvbar, part, s);
+  // y_corr^{w_init} = BE(q_w) over z dt
+  if (st == ROM_OK) st = convert_words(ycbar, true, rhs, f64, td, s);
+  if (st == ROM_OK) st = launch_assemble_adjoint(h, y0, z * c.dt, rhs, s);
+  if (st == ROM_OK) st = bt_solve(h, -1, nullptr, out, s);
+  if (st == ROM_OK) st = add_to_double(h, out, qbw, s);
+  if (st == ROM_OK)
+    st = launch_offline_pod_vjp(h, pws, w, Qtr, phibar, sigbar, qb, qrbar, dvbar, part, small, s);
+  // training steps q_j = BE(q_{j-1}), j = w .. 1
+  for (int j = w; j >= 1 && st == ROM_OK; --j) {
+    st = convert_words(qb + (size_t)j * td, true, rhs, f64, td, s);
+    if (st == ROM_OK)
+      st = launch_assemble_adjoint(h, Qtr + (size_t)(j - 1) * y_b, c.dt, rhs, s);
+    if (st == ROM_OK) st = bt_solve(h, -1, nullptr, out, s);
+    if (st == ROM_OK) st = add_to_double(h, out, qb + (size_t)(j - 1) * td, s);
+  }
+  // q_ref = q0
+  if (st == ROM_OK) st = sum_to_state(h, qb, qrbar, gq0, s);
+  // the handle ends at the rollout's end state
+  if (st == ROM_OK) st = restore(nseg);
+  hipError_t e = hipStreamSynchronize(s);
+  pod_ws_free(&pws);
+  (void)hipFree(ws);
+  ROM_TRY(st);
+  if (e != hipSuccess) { set_error(hipGetErrorString(e)); return ROM_E_DEVICE; }
+  return ROM_OK;
+}
+
 rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const void* qbar,
                           double* abar, double* phibar, double* sigbar, double* ycbar,
                           void* stream) {

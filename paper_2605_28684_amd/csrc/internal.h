@@ -237,15 +237,18 @@ rom_status launch_isvd_transfer(rom_batch* h, hipStream_t s);
 // Online-loop adjoint pieces (adjoint.hip): the loss seed at the end state,
 // one fine step backward (after a Galerkin pass at its converged state), one
 // event backward down to yhat, FP32/FP64 conversion of device vectors.
+// With qrbar (FP64 [total_dof]) and dvbar (FP64 [n_inst * nv]) the seed and the
+// event also give the gradients of q_ref and of D's diagonal per variable (the
+// seed writes them, the event adds to them).
 rom_status launch_online_seed(rom_batch* h, const void* qbar, double* abar, double* phibar,
-                              hipStream_t s);
+                              hipStream_t s, double* qrbar = nullptr, double* dvbar = nullptr);
 rom_status launch_step_vjp(rom_batch* h, const void* Phi, const double* a1, double* abar,
                            double* phibar, hipStream_t s);
 rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new,
                             const double* sig_old, const double* a_old, const double* ubar,
                             const double* pr, const double* sig_new, double* abar,
                             double* phibar, double* sigbar, double* ybar, double* qs, double* js,
-                            hipStream_t s);
+                            hipStream_t s, double* qrbar = nullptr, double* dvbar = nullptr);
 rom_status convert_words(const void* src, bool src_f64, void* dst, bool dst_f64, int64_t n,
                          hipStream_t s);
 rom_status adjoint_kernels_prepare();
@@ -302,6 +305,29 @@ rom_status fom_step_explicit(rom_batch* h, const void* q_prev, double dt, void* 
 rom_status launch_mesh5(rom_batch* h, hipStream_t s);  // after every rebuild of P
 rom_status launch_hr_explicit_step(rom_batch* h, hipStream_t s);
 rom_status explicit_kernels_prepare();
+
+// ---- the rollout adjoint (gradient with respect to q0 through Alg. 1)
+// one HR-LSPG step backward with the window's P and M held fixed (rom.hip)
+rom_status launch_hr_step_vjp(rom_batch* h, const void* Phi, const int32_t* P, const double* M,
+                              const double* a1, double* abar, double* phibar, double* qrbar,
+                              double* dvbar, hipStream_t s);
+// the POD with a caller-owned workspace that keeps Q_pod and R (isvd.hip)
+rom_status launch_pod_ws(rom_batch* h, const void* Q, int w, const PodWs& ws, hipStream_t s);
+rom_status launch_pod_vjp_small(rom_batch* h, const double* R, int w, const double* Z,
+                                const double* sigbar, double* Cm, double* Em, double* scr,
+                                hipStream_t s);
+// the offline stage backward (rollout.hip); part: offline_vjp_part_doubles
+// doubles; small: n_inst (w r + w w + r w + 3 w w) doubles
+size_t offline_vjp_part_doubles(const rom_batch* h, int w);
+rom_status launch_offline_a_vjp(rom_batch* h, const void* Phi0, const void* qw, const double* abar,
+                                double* phibar, double* qbw, double* qrbar, double* dvbar,
+                                double* part, hipStream_t s);
+rom_status launch_offline_pod_vjp(rom_batch* h, const PodWs& ws, int w, const void* Qtr,
+                                  const double* phibar, const double* sigbar, double* qb,
+                                  double* qrbar, double* dvbar, double* part, double* small,
+                                  hipStream_t s);
+rom_status add_to_double(rom_batch* h, const void* src, double* dst, hipStream_t s);
+rom_status sum_to_state(rom_batch* h, const double* x, const double* y, void* out, hipStream_t s);
 
 // ---- small helpers (api.cpp)
 rom_status fill_zero(void* p, size_t bytes, hipStream_t s);

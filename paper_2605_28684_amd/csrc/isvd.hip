@@ -936,6 +936,90 @@ __global__ __launch_bounds__(64) void k_pod_svd(int w, int r, const double* __re
   (void)use_lds;
 }
 
+// The small matrices of the POD's backward pass (see rollout.hip), one
+// wavefront per instance: the SVD of R again (the same kernel path as the
+// forward, so U_R and the singular values are the forward's), then
+// V = R^T U_R S^-1, Mm = U_R^T Z (Z = Q_pod^T Phibar, w x r),
+// G = F o (Mm_pad - Mm_pad^T) S + diag(sbar_pad), C = U_R G V^T - Z S_r^-1 V_r^T
+// and E = S_r^-1 V_r^T.  Zero singular values carry no gradient.
+// scr: [B][3 w w] global scratch (U_R, V, G V^T).
+__global__ __launch_bounds__(64) void k_pod_vjp_small(int w, int r, const double* __restrict__ R,
+                                                      const double* __restrict__ Z,
+                                                      const double* __restrict__ sigbar,
+                                                      double* __restrict__ Cm,
+                                                      double* __restrict__ Em,
+                                                      double* __restrict__ scr) {
+  extern __shared__ double sm[];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int n = w, ld = w;
+  double* K = sm;
+  double* G = K + n * ld;
+  double* nrm = G + n * ld;
+  double* sv = nrm + n;
+  int* rank = (int*)(sv + n);
+  double* U = scr + (size_t)b * 3 * w * w;
+  double* V = U + w * w;
+  double* GV = V + w * w;
+  const double* Rb = R + (size_t)b * w * w;
+  const double* Zb = Z + (size_t)b * w * r;
+  for (int e = tid; e < n * n; e += blockDim.x) K[e] = Rb[e];
+  __syncthreads();
+  jacobi_rows(K, G, n, ld, U, sv, nrm, rank);
+  __threadfence_block();
+  __syncthreads();
+  auto inv = [&](int j) { return sv[j] > 0.0 ? 1.0 / sv[j] : 0.0; };
+  // V[i][j] = sum_k R[k][i] U[k][j] / s_j
+  for (int e = tid; e < w * w; e += blockDim.x) {
+    const int i = e / w, j = e % w;
+    double acc = 0.0;
+    for (int k = 0; k < w; ++k) acc += Rb[k * w + i] * U[k * w + j];
+    V[e] = acc * inv(j);
+  }
+  // G (into K): Mm_ij = (U^T Z)_ij for j < r
+  for (int e = tid; e < w * w; e += blockDim.x) {
+    const int i = e / w, j = e % w;
+    double g = 0.0;
+    if (i == j) {
+      g = i < r ? sigbar[(size_t)b * r + i] : 0.0;
+    } else {
+      double mij = 0.0, mji = 0.0;
+      if (j < r)
+        for (int k = 0; k < w; ++k) mij += U[k * w + i] * Zb[k * r + j];
+      if (i < r)
+        for (int k = 0; k < w; ++k) mji += U[k * w + j] * Zb[k * r + i];
+      const double den = sv[j] * sv[j] - sv[i] * sv[i];
+      if (sv[j] > 0.0 && den != 0.0) g = (mij - mji) * sv[j] / den;
+    }
+    K[e] = g;
+  }
+  __threadfence_block();
+  __syncthreads();
+  // GV = G V^T
+  for (int e = tid; e < w * w; e += blockDim.x) {
+    const int i = e / w, j = e % w;
+    double acc = 0.0;
+    for (int l = 0; l < w; ++l) acc += K[i * w + l] * V[j * w + l];
+    GV[e] = acc;
+  }
+  __threadfence_block();
+  __syncthreads();
+  // C = U_R GV - Z S_r^-1 V_r^T; E = S_r^-1 V_r^T
+  double* Cb = Cm + (size_t)b * w * w;
+  for (int e = tid; e < w * w; e += blockDim.x) {
+    const int k = e / w, j = e % w;
+    double acc = 0.0;
+    for (int i = 0; i < w; ++i) acc += U[k * w + i] * GV[i * w + j];
+    double t = 0.0;
+    for (int c = 0; c < r; ++c) t += Zb[k * r + c] * V[j * w + c] * inv(c);
+    Cb[e] = acc - t;
+  }
+  double* Eb = Em + (size_t)b * r * w;
+  for (int e = tid; e < r * w; e += blockDim.x) {
+    const int c = e / w, j = e % w;
+    Eb[e] = V[j * w + c] * inv(c);
+  }
+}
+
 // preprocessing: sum over cells and snapshots of (Q - q_ref)^2 per variable
 template <typename T>
 __global__ __launch_bounds__(256) void k_sqdev(const Tile* __restrict__ tiles,
@@ -1285,6 +1369,26 @@ rom_status pod_t(rom_batch* h, const void* Qtrain, int w, hipStream_t s) {
   return ROM_OK;
 }
 
+}  // namespace
+
+rom_status launch_pod_ws(rom_batch* h, const void* Q, int w, const PodWs& ws, hipStream_t s) {
+  if (h->cfg.precision == ROM_F64)
+    return pod_core_t<double>(h, Q, w, true, true, ws, h->sigma, h->Phi, s);
+  return pod_core_t<float>(h, Q, w, true, true, ws, h->sigma, h->Phi, s);
+}
+
+rom_status launch_pod_vjp_small(rom_batch* h, const double* R, int w, const double* Z,
+                                const double* sigbar, double* Cm, double* Em, double* scr,
+                                hipStream_t s) {
+  const size_t shm = sizeof(double) * (2 * w * w + 2 * w) + sizeof(int) * w;
+  hipLaunchKernelGGL(k_pod_vjp_small, dim3(h->cfg.n_inst), dim3(64), shm, s, w, h->cfg.r, R, Z,
+                     sigbar, Cm, Em, scr);
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
+namespace {
+
 // One windowed basis update (App. A): the raw snapshot y joins the window
 // (replacing the oldest once it holds `window`), the lifted state v = Phi a is
 // kept in FP64, the basis is rebuilt by the rule, and a = Phi_new^T v.
@@ -1370,6 +1474,7 @@ rom_status isvd_kernels_prepare() {
   const int big = 160 * 1024 - 1024;
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_isvd_core<true>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_pod_svd, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_pod_vjp_small, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_direct_pinv, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   return ROM_OK;
 }

@@ -453,6 +453,82 @@ DEV void wave_lu_solve(const double* A, int ld, double* bvec, int n, int* ok) {
 }
 
 // ------------------------------------------------------------------ HR-LSPG step
+// f_v and row v of the three Jacobian blocks (cells c-1, c, c+1) of J_f at a
+// sampled row (cell c, variable v) of an instance of n cells, from the three
+// stencil states q3 (FP64).  Walls fold the ghost's column into the centre
+// block.  Shared by the HR-LSPG step and its adjoint.
+template <class Mdl>
+DEV void hr_row(const Mdl& m, const double* q3, int64_t c, int v, int64_t n, double& fv,
+                double* jm, double* j0, double* jp, unsigned& fl) {
+  constexpr int NV = Mdl::NV;
+  constexpr int NN = NV * NV;
+  const bool lw = !Mdl::periodic && c == 0, rw = !Mdl::periodic && c == n - 1;
+  const double inv = (double)n, inv2 = (double)n * (double)n;
+  if constexpr (NV >= 8) {
+    // large blocks: only row v is formed (the model's row methods)
+    double hl, hr, dll[NV], drl[NV], dlr[NV], drr[NV];
+    m.face_jac_row(&q3[0], &q3[NV], v, hl, dll, drl);
+    m.face_jac_row(&q3[NV], &q3[2 * NV], v, hr, dlr, drr);
+    fv = -(hr - hl) * inv;
+    for (int w = 0; w < NV; ++w) {
+      jm[w] = dll[w] * inv; j0[w] = (drl[w] - dlr[w]) * inv; jp[w] = -drr[w] * inv;
+    }
+    if (lw) for (int w = 0; w < NV; ++w) { j0[w] += jm[w]; jm[w] = 0.0; }
+    if (rw) for (int w = 0; w < NV; ++w) { j0[w] += jp[w]; jp[w] = 0.0; }
+    const double kap = m.kappa(v);
+    if (kap != 0.0) {
+      fv += kap * ((q3[2 * NV + v] - q3[NV + v]) - (q3[NV + v] - q3[v])) * inv2;
+      const double cc = kap * inv2;
+      for (int w = 0; w < NV; ++w)
+        if (w == v) {
+          jm[w] += lw ? 0.0 : cc;
+          jp[w] += rw ? 0.0 : cc;
+          j0[w] += -2.0 * cc + (lw ? cc : 0.0) + (rw ? cc : 0.0);
+        }
+    }
+    if (Mdl::has_source) {
+      double sv_, ds[NV];
+      m.source_jac_row(&q3[NV], ((double)c + 0.5) / (double)n, v, sv_, ds, fl);
+      fv += sv_;
+      for (int w = 0; w < NV; ++w) j0[w] += ds[w];
+    }
+  } else {
+    double f[NV], Jm[NN], J0[NN], Jp[NN];
+    {
+      // cell_jacobian for one cell (FP64), inlined to avoid a cross-file template
+      double HL[NV], HR[NV], DLl[NN], DRl[NN], DLr[NN], DRr[NN];
+      m.face_jac(&q3[0], &q3[NV], HL, DLl, DRl, fl);
+      m.face_jac(&q3[NV], &q3[2 * NV], HR, DLr, DRr, fl);
+      for (int w = 0; w < NV; ++w) f[w] = -(HR[w] - HL[w]) * inv;
+      for (int e = 0; e < NN; ++e) {
+        Jm[e] = DLl[e] * inv; J0[e] = (DRl[e] - DLr[e]) * inv; Jp[e] = -DRr[e] * inv;
+      }
+      if (lw) for (int e = 0; e < NN; ++e) { J0[e] += Jm[e]; Jm[e] = 0.0; }
+      if (rw) for (int e = 0; e < NN; ++e) { J0[e] += Jp[e]; Jp[e] = 0.0; }
+      for (int w = 0; w < NV; ++w) {
+        const double kap = m.kappa(w);
+        if (kap != 0.0) {
+          f[w] += kap * ((q3[2 * NV + w] - q3[NV + w]) - (q3[NV + w] - q3[w])) * inv2;
+          const double cc = kap * inv2;
+          Jm[w * NV + w] += lw ? 0.0 : cc;
+          Jp[w * NV + w] += rw ? 0.0 : cc;
+          J0[w * NV + w] += -2.0 * cc + (lw ? cc : 0.0) + (rw ? cc : 0.0);
+        }
+      }
+      if (Mdl::has_source) {
+        double S[NV], DS[NN];
+        m.source_jac(&q3[NV], ((double)c + 0.5) / (double)n, S, DS, fl);
+        for (int w = 0; w < NV; ++w) f[w] += S[w];
+        for (int e = 0; e < NN; ++e) J0[e] += DS[e];
+      }
+    }
+    fv = f[v];
+    for (int w = 0; w < NV; ++w) {
+      jm[w] = Jm[v * NV + w]; j0[w] = J0[v * NV + w]; jp[w] = Jp[v * NV + w];
+    }
+  }
+}
+
 // One Gauss-Newton iteration is two launches: k_hr_eval spreads the sampled
 // rows of every instance over blocks of kHrRows rows (stencil states, the
 // sampled Jacobian rows, the rows of A_s and b); k_hr_reduce_solve forms M A_s
@@ -534,77 +610,10 @@ __global__ __launch_bounds__(kHrEvalThreads) void k_hr_eval(
     const int p = P[(size_t)b * ns + s0 + s];
     const int64_t c = p / NV;
     const int v = p % NV;
-    const bool lw = !Mdl::periodic && c == 0, rw = !Mdl::periodic && c == n - 1;
-    const double inv = (double)n, inv2 = (double)n * (double)n;
+    const double* q3 = sq3 + s * E3;
     double fv, jm[NV], j0[NV], jp[NV];   // f_v and row v of the three Jacobian blocks
     unsigned fl = 0;
-    if constexpr (NV >= 8) {
-      // large blocks: only row v is formed (the model's row methods), reading
-      // the stencil states from LDS
-      const double* q3 = sq3 + s * E3;
-      double hl, hr, dll[NV], drl[NV], dlr[NV], drr[NV];
-      m.face_jac_row(&q3[0], &q3[NV], v, hl, dll, drl);
-      m.face_jac_row(&q3[NV], &q3[2 * NV], v, hr, dlr, drr);
-      fv = -(hr - hl) * inv;
-      for (int w = 0; w < NV; ++w) {
-        jm[w] = dll[w] * inv; j0[w] = (drl[w] - dlr[w]) * inv; jp[w] = -drr[w] * inv;
-      }
-      if (lw) for (int w = 0; w < NV; ++w) { j0[w] += jm[w]; jm[w] = 0.0; }
-      if (rw) for (int w = 0; w < NV; ++w) { j0[w] += jp[w]; jp[w] = 0.0; }
-      const double kap = m.kappa(v);
-      if (kap != 0.0) {
-        fv += kap * ((q3[2 * NV + v] - q3[NV + v]) - (q3[NV + v] - q3[v])) * inv2;
-        const double cc = kap * inv2;
-        for (int w = 0; w < NV; ++w)
-          if (w == v) {
-            jm[w] += lw ? 0.0 : cc;
-            jp[w] += rw ? 0.0 : cc;
-            j0[w] += -2.0 * cc + (lw ? cc : 0.0) + (rw ? cc : 0.0);
-          }
-      }
-      if (Mdl::has_source) {
-        double sv_, ds[NV];
-        m.source_jac_row(&q3[NV], ((double)c + 0.5) / (double)n, v, sv_, ds, fl);
-        fv += sv_;
-        for (int w = 0; w < NV; ++w) j0[w] += ds[w];
-      }
-    } else {
-      double q3[E3];
-      for (int e = 0; e < E3; ++e) q3[e] = sq3[s * E3 + e];
-      double f[NV], Jm[NN], J0[NN], Jp[NN];
-      {
-        // cell_jacobian for one cell (FP64), inlined to avoid a cross-file template
-        double HL[NV], HR[NV], DLl[NN], DRl[NN], DLr[NN], DRr[NN];
-        m.face_jac(&q3[0], &q3[NV], HL, DLl, DRl, fl);
-        m.face_jac(&q3[NV], &q3[2 * NV], HR, DLr, DRr, fl);
-        for (int w = 0; w < NV; ++w) f[w] = -(HR[w] - HL[w]) * inv;
-        for (int e = 0; e < NN; ++e) {
-          Jm[e] = DLl[e] * inv; J0[e] = (DRl[e] - DLr[e]) * inv; Jp[e] = -DRr[e] * inv;
-        }
-        if (lw) for (int e = 0; e < NN; ++e) { J0[e] += Jm[e]; Jm[e] = 0.0; }
-        if (rw) for (int e = 0; e < NN; ++e) { J0[e] += Jp[e]; Jp[e] = 0.0; }
-        for (int w = 0; w < NV; ++w) {
-          const double kap = m.kappa(w);
-          if (kap != 0.0) {
-            f[w] += kap * ((q3[2 * NV + w] - q3[NV + w]) - (q3[NV + w] - q3[w])) * inv2;
-            const double cc = kap * inv2;
-            Jm[w * NV + w] += lw ? 0.0 : cc;
-            Jp[w * NV + w] += rw ? 0.0 : cc;
-            J0[w * NV + w] += -2.0 * cc + (lw ? cc : 0.0) + (rw ? cc : 0.0);
-          }
-        }
-        if (Mdl::has_source) {
-          double S[NV], DS[NN];
-          m.source_jac(&q3[NV], ((double)c + 0.5) / (double)n, S, DS, fl);
-          for (int w = 0; w < NV; ++w) f[w] += S[w];
-          for (int e = 0; e < NN; ++e) J0[e] += DS[e];
-        }
-      }
-      fv = f[v];
-      for (int w = 0; w < NV; ++w) {
-        jm[w] = Jm[v * NV + w]; j0[w] = J0[v * NV + w]; jp[w] = Jp[v * NV + w];
-      }
-    }
+    hr_row(m, q3, c, v, n, fv, jm, j0, jp, fl);
     if (fl) atomicOr(&flacc, fl);
     const double dp = dv[v];
     double bsum = 0.0;
@@ -1269,6 +1278,197 @@ rom_status galerkin_step_t(rom_batch* h, hipStream_t s) {
   return ROM_OK;
 }
 
+
+// ------------------------------------------------------------------ HR-LSPG step adjoint
+// One HR-LSPG step backward (the sample rows P and M = (P^T Phi)^+ of its
+// window held fixed).  At the converged a1 = a_{n+1} the weighted residual
+// b(a) = M P^T D r(q~(a)) vanishes, and since M P^T Phi = I it equals
+// (a - a_n) - dt M g(a) with g = P^T D f(q~).  The implicit-function theorem
+// gives lambda = J_b^-T abar with the Gauss-Newton matrix J_b = M A_s,
+// A_s = P^T D J_r D^-1 Phi; abar_n = lambda, and Phi, q_ref and D receive
+// dt (d(M g)/d theta)^T lambda:
+//   through M:  Abar = -M^T Mbar M^T + (I - A M) Mbar^T M M^T with Mbar = dt lambda g^T
+//               and A = P^T Phi, i.e. dt (-(M^T lambda)(M g)^T + (g - A M g)(M M^T lambda)^T)
+//               on the sampled rows of Phibar;
+//   through g:  gbar = dt M^T lambda; dvbar[v_s] += gbar_s f_s; fbar_s = gbar_s d_s,
+//               q~bar = J_f^T fbar on the three-cell mesh of each sampled row, and
+//               q~ = q_ref + D^-1 Phi a1 gives qrbar += q~bar,
+//               Phibar += D^-1 q~bar a1^T, dvbar[v] -= sum q~bar (Phi a1) / d^2.
+// One block per instance.  Every mesh row is updated by one thread, which sums
+// the contributions of the sampled rows in their order, so the result does
+// not depend on scheduling.  as_ws: FP64 [n_inst][ns][r] scratch for A_s.
+// Dynamic LDS: 2 ns 3 NV + r^2 + 4 ns + 3 r doubles.
+template <class Mdl, typename T>
+__global__ __launch_bounds__(256) void k_hr_step_vjp(
+    int r, int ns, const int64_t* __restrict__ dof_off, const int64_t* __restrict__ cell_off,
+    const double* __restrict__ phys, int nphys, const double* __restrict__ dvar,
+    const T* __restrict__ Phi, const T* __restrict__ qref, const int32_t* __restrict__ P,
+    const double* __restrict__ M, const double* __restrict__ a1, double dt,
+    double* __restrict__ abar, double* __restrict__ phibar, double* __restrict__ qrbar,
+    double* __restrict__ dvbar, double* __restrict__ as_ws, uint32_t* flags) {
+  constexpr int NV = Mdl::NV;
+  constexpr int E3 = 3 * NV;
+  extern __shared__ double sm[];
+  __shared__ double sa[kMaxR], red[4];
+  __shared__ unsigned flacc;
+  double* sq3 = sm;                 // mesh states
+  double* sj = sq3 + ns * E3;       // J_f row entries of each sampled row
+  double* Jt = sj + ns * E3;        // J_b^T, r x r
+  double* sf = Jt + r * r;          // f at the sampled rows
+  double* su = sf + ns;             // M^T lambda
+  double* se = su + ns;             // g - A M g
+  double* sg = se + ns;             // g = d f
+  double* lam = sg + ns;            // lambda
+  double* mg = lam + r;             // M g
+  double* wv = mg + r;              // M M^T lambda
+  const int b = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int64_t base = dof_off[b];
+  const int64_t n = cell_off[b + 1] - cell_off[b];
+  Mdl m(phys + (size_t)b * nphys);
+  const double* dv = dvar + (size_t)b * NV;
+  const int32_t* Pb = P + (size_t)b * ns;
+  const double* Mb = M + (size_t)b * r * ns;
+  double* Ab = as_ws + (size_t)b * ns * r;
+  auto mesh_cell = [&](int s_, int o) -> int64_t {
+    int64_t c = Pb[s_] / NV - 1 + o;
+    if (Mdl::periodic) c = c < 0 ? c + n : (c >= n ? c - n : c);
+    else c = c < 0 ? 0 : (c >= n ? n - 1 : c);
+    return c;
+  };
+  for (int k = tid; k < r; k += nt) sa[k] = a1[(size_t)b * r + k];
+  if (tid == 0) flacc = 0;
+  __syncthreads();
+  // mesh states q~ = q_ref + D^-1 Phi a1
+  for (int idx = tid; idx < ns * E3; idx += nt) {
+    const int s_ = idx / E3, e = idx - s_ * E3, o = e / NV, w = e - o * NV;
+    const int64_t g = base + mesh_cell(s_, o) * NV + w;
+    double acc = 0.0;
+    for (int k = 0; k < r; ++k) acc += (double)Phi[g * r + k] * sa[k];
+    sq3[idx] = (double)qref[g] + acc / dv[w];
+  }
+  __syncthreads();
+  // f and the J_f row of each sampled row
+  for (int s_ = tid; s_ < ns; s_ += nt) {
+    const int p = Pb[s_];
+    double fv, jm[NV], j0[NV], jp[NV];
+    unsigned fl = 0;
+    hr_row(m, sq3 + s_ * E3, (int64_t)(p / NV), p % NV, n, fv, jm, j0, jp, fl);
+    if (fl) atomicOr(&flacc, fl);
+    sf[s_] = fv;
+    sg[s_] = dv[p % NV] * fv;
+    for (int w = 0; w < NV; ++w) {
+      sj[s_ * E3 + w] = jm[w];
+      sj[s_ * E3 + NV + w] = j0[w];
+      sj[s_ * E3 + 2 * NV + w] = jp[w];
+    }
+  }
+  __syncthreads();
+  // A_s = P^T Phi - dt P^T D J_f D^-1 Phi (rows of the mesh)
+  for (int idx = tid; idx < ns * r; idx += nt) {
+    const int s_ = idx / r, k = idx - s_ * r;
+    const int p = Pb[s_];
+    double acc = 0.0;
+    for (int o = 0; o < 3; ++o) {
+      const int64_t g0 = base + mesh_cell(s_, o) * NV;
+      for (int w = 0; w < NV; ++w)
+        acc += sj[s_ * E3 + o * NV + w] * ((double)Phi[(g0 + w) * r + k] / dv[w]);
+    }
+    Ab[idx] = (double)Phi[(base + p) * r + k] - dt * dv[p % NV] * acc;
+  }
+  __syncthreads();
+  // J_b^T = (M A_s)^T, lambda = J_b^-T abar
+  for (int idx = tid; idx < r * r; idx += nt) {
+    const int i = idx / r, k = idx - i * r;
+    double acc = 0.0;
+    for (int s_ = 0; s_ < ns; ++s_) acc += Mb[(size_t)i * ns + s_] * Ab[(size_t)s_ * r + k];
+    Jt[k * r + i] = acc;
+  }
+  for (int k = tid; k < r; k += nt) lam[k] = abar[(size_t)b * r + k];
+  __syncthreads();
+  const int ok = block_lu_solve(Jt, r, lam, r);
+  if (!ok && tid == 0) atomicOr(&flacc, (unsigned)ROM_FLAG_SINGULAR);
+  // M g, M^T lambda, g - A M g, M M^T lambda
+  for (int i = tid; i < r; i += nt) {
+    double acc = 0.0;
+    for (int s_ = 0; s_ < ns; ++s_) acc += Mb[(size_t)i * ns + s_] * sg[s_];
+    mg[i] = acc;
+  }
+  for (int s_ = tid; s_ < ns; s_ += nt) {
+    double acc = 0.0;
+    for (int i = 0; i < r; ++i) acc += Mb[(size_t)i * ns + s_] * lam[i];
+    su[s_] = acc;
+  }
+  __syncthreads();
+  for (int s_ = tid; s_ < ns; s_ += nt) {
+    const int64_t g = base + Pb[s_];
+    double acc = 0.0;
+    for (int k = 0; k < r; ++k) acc += (double)Phi[g * r + k] * mg[k];
+    se[s_] = sg[s_] - acc;
+  }
+  for (int i = tid; i < r; i += nt) {
+    double acc = 0.0;
+    for (int s_ = 0; s_ < ns; ++s_) acc += Mb[(size_t)i * ns + s_] * su[s_];
+    wv[i] = acc;
+  }
+  __syncthreads();
+  // the mesh rows: each distinct mesh cell (its first occurrence in sampled-row,
+  // slot order) is handled by one thread, over its NV rows
+  double dva[12];
+  for (int w = 0; w < 12; ++w) dva[w] = 0.0;
+  for (int j = tid; j < ns * 3; j += nt) {
+    const int sj0 = j / 3, oj = j - sj0 * 3;
+    const int64_t cell = mesh_cell(sj0, oj);
+    bool first = true;
+    for (int i = 0; i < j && first; ++i)
+      if (mesh_cell(i / 3, i - (i / 3) * 3) == cell) first = false;
+    if (!first) continue;
+    for (int w = 0; w < NV; ++w) {
+      const int64_t lr = cell * NV + w, g = base + lr;
+      double coef = 0.0;     // q~bar of this row
+      int own = -1;          // the sampled row at this DOF, if any
+      for (int s_ = 0; s_ < ns; ++s_) {
+        const double fb = dt * su[s_] * dv[Pb[s_] % NV];
+        for (int o = 0; o < 3; ++o)
+          if (mesh_cell(s_, o) == cell) coef += fb * sj[s_ * E3 + o * NV + w];
+        if (Pb[s_] == lr) own = s_;
+      }
+      double pa = 0.0;
+      for (int k = 0; k < r; ++k) pa += (double)Phi[g * r + k] * sa[k];
+      qrbar[g] += coef;
+      for (int u = 0; u < 12; ++u)
+        if (u == w) dva[u] -= coef * pa / (dv[w] * dv[w]);
+      const double cd = coef / dv[w];
+      for (int k = 0; k < r; ++k) {
+        double add = cd * sa[k];
+        if (own >= 0) add += dt * (-su[own] * mg[k] + se[own] * wv[k]);
+        phibar[g * r + k] += add;
+      }
+      if (own >= 0)
+        for (int u = 0; u < 12; ++u)
+          if (u == w) dva[u] += dt * su[own] * sf[own];
+    }
+  }
+  for (int w = 0; w < NV; ++w) {
+    double v = dva[w];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+      double s2 = 0.0;
+      for (int q = 0; q < (nt >> 6); ++q) s2 += red[q];
+      dvbar[(size_t)b * NV + w] += s2;
+    }
+  }
+  for (int k = tid; k < r; k += nt) abar[(size_t)b * r + k] = lam[k];
+  if (tid == 0 && flacc) atomicOr(&flags[b], flacc);
+}
+
+size_t hr_step_vjp_shm(int r, int ns, int nv) {
+  return sizeof(double) * ((size_t)2 * ns * 3 * nv + (size_t)r * r + 4 * (size_t)ns + 3 * (size_t)r);
+}
+
 rom_status hr_step(rom_batch* h, hipStream_t s) {
   const int B = h->cfg.n_inst, r = h->cfg.r, ns = h->cfg.n_s;
   const int gpi = (ns + kHrRows - 1) / kHrRows;         // evaluation blocks per instance
@@ -1363,9 +1563,47 @@ rom_status reconstruct_t(rom_batch* h, void* out, hipStream_t s) {
 
 rom_status rom_kernels_prepare() {
   const int big = 160 * 1024 - 1024;
+  auto vjp_attr = [&](const void* f) {
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  };
+  ROM_HIP_CHECK(vjp_attr((const void*)k_hr_step_vjp<BurgersModel<double>, float>));
+  ROM_HIP_CHECK(vjp_attr((const void*)k_hr_step_vjp<BurgersModel<double>, double>));
+  ROM_HIP_CHECK(vjp_attr((const void*)k_hr_step_vjp<EulerModel<double, false>, float>));
+  ROM_HIP_CHECK(vjp_attr((const void*)k_hr_step_vjp<EulerModel<double, false>, double>));
+  ROM_HIP_CHECK(vjp_attr((const void*)k_hr_step_vjp<EulerModel<double, true>, float>));
+  ROM_HIP_CHECK(vjp_attr((const void*)k_hr_step_vjp<EulerModel<double, true>, double>));
+  ROM_HIP_CHECK(vjp_attr((const void*)k_hr_step_vjp<ReactModel<double>, float>));
+  ROM_HIP_CHECK(vjp_attr((const void*)k_hr_step_vjp<ReactModel<double>, double>));
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_rebuild<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_rebuild<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   return ROM_OK;
+}
+
+rom_status launch_hr_step_vjp(rom_batch* h, const void* Phi, const int32_t* P, const double* M,
+                              const double* a1, double* abar, double* phibar, double* qrbar,
+                              double* dvbar, hipStream_t s) {
+  const int B = h->cfg.n_inst, r = h->cfg.r, ns = h->cfg.n_s;
+  const size_t shm = hr_step_vjp_shm(r, ns, h->nv);
+  auto go = [&](auto tagT) -> rom_status {
+    using T = typename decltype(tagT)::type;
+    auto run = [&](auto tag) {
+      using Mdl = typename decltype(tag)::type;
+      hipLaunchKernelGGL((k_hr_step_vjp<Mdl, T>), dim3(B), dim3(256), shm, s, r, ns,
+                         h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, h->d_var,
+                         (const T*)Phi, (const T*)h->q_ref, P, M, a1, h->cfg.dt, abar, phibar,
+                         qrbar, dvbar, h->hr_as, h->flags);
+    };
+    switch (h->cfg.problem) {
+      case ROM_BURGERS: run(Tag<BurgersModel<double>>{}); break;
+      case ROM_EULER_RUSANOV: run(Tag<EulerModel<double, false>>{}); break;
+      case ROM_EULER_HLLC: run(Tag<EulerModel<double, true>>{}); break;
+      default: run(Tag<ReactModel<double>>{}); break;
+    }
+    ROM_HIP_CHECK(hipGetLastError());
+    return ROM_OK;
+  };
+  if (h->cfg.precision == ROM_F64) return go(Tag<double>{});
+  return go(Tag<float>{});
 }
 
 rom_status launch_rom_fine_step(rom_batch* h, hipStream_t s) {

@@ -83,6 +83,8 @@ def _load():
         "fom_rollout_vjp": [vp, vp, i32, d, i32, vp, vp, vp],
         "fom_rollout_vjp_noalloc": [vp, vp, i32, d, i32, vp, vp, vp],
         "rom_online_vjp": [vp, i32, i32, vp, vp, vp, vp, vp, vp],
+        "rom_offline": [vp, vp, vp],
+        "rom_rollout_vjp": [vp, vp, i32, i32, vp, vp, vp],
         "rom_autotune": [vp, i32, vp, ctypes.POINTER(i32), vp],
         "rom_set_tuning": [vp, i32, i32, ctypes.POINTER(i32)],
         "rom_query": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -102,7 +104,7 @@ LIB = _load()
 SYMBOLS = ("rom_create", "rom_destroy", "fom_residual", "fom_step", "isvd_update", "rom_rebuild",
            "rom_step", "rom_get", "rom_set", "rom_save", "rom_load", "rom_get_status", "rom_clear_status",
            "fom_residual_vjp", "fom_step_vjp", "fom_rollout_vjp", "fom_rollout_vjp_noalloc",
-           "rom_online_vjp", "rom_autotune",
+           "rom_online_vjp", "rom_offline", "rom_rollout_vjp", "rom_autotune",
            "rom_set_tuning", "rom_query", "rom_profile", "rom_last_error")
 TUNE_RESIDUAL = 0
 PROF_RESIDUAL, PROF_GALERKIN_PASS, PROF_ISVD_PROJECT, PROF_RESIDUAL_VJP, PROF_FOM_STEP = range(5)
@@ -243,6 +245,19 @@ class RomBatch:
                                   _ptr(pb), _ptr(sb), _ptr(yb), _stream()))
         return ab, pb, sb, yb
 
+    def offline(self, q0):
+        """Alg. 1's offline stage from q0 on this handle (as rom_create with q0)."""
+        _check(LIB.rom_offline(self.h, _ptr(q0), _stream()))
+
+    def rollout_vjp(self, q0, n_steps, gbar, n_ckpt=0, out=None):
+        """Gradient of <gbar, q~_end> with respect to q0 through the offline
+        stage and n_steps HR-LSPG fine steps (events included), the sample rows
+        of the forward run held fixed.  Leaves the handle at the end state."""
+        out = self._new(self.total_dof) if out is None else out
+        _check(LIB.rom_rollout_vjp(self.h, _ptr(q0), int(n_steps), int(n_ckpt), _ptr(gbar),
+                                   _ptr(out), _stream()))
+        return out
+
     # ---- reduced model
     def isvd_update(self, y):
         _check(LIB.isvd_update(self.h, _ptr(y), _stream()))
@@ -370,6 +385,30 @@ class FomRollout(torch.autograd.Function):
         (q0,) = ctx.saved_tensors
         gq0 = ctx.handle.fom_rollout_vjp(q0, ctx.n_steps, ctx.dt, g.contiguous(), ctx.n_ckpt)
         return gq0, None, None, None, None
+
+
+class RomRollout(torch.autograd.Function):
+    """q~ after Alg. 1 run from the initial state q0: the offline stage, then
+    n_steps hyper-reduced LSPG fine steps with their events.  The backward pass
+    is rom_rollout_vjp (the sample rows of the run held fixed), which reruns
+    the rollout from q0 with checkpoints.  The handle's state is overwritten."""
+
+    @staticmethod
+    def forward(ctx, q0, handle, n_steps, n_ckpt=0):
+        qd = q0.detach().contiguous().to(handle.dtype)
+        handle.offline(qd)
+        handle.rom_step(int(n_steps))
+        q = handle.get(GET_QTILDE).clone()
+        ctx.save_for_backward(qd)
+        ctx.handle, ctx.n_steps, ctx.n_ckpt, ctx.dtype = handle, int(n_steps), int(n_ckpt), q0.dtype
+        return q.to(q0.dtype)
+
+    @staticmethod
+    def backward(ctx, g):
+        (qd,) = ctx.saved_tensors
+        h = ctx.handle
+        gq = h.rollout_vjp(qd, ctx.n_steps, g.contiguous().to(h.dtype), ctx.n_ckpt)
+        return gq.to(ctx.dtype), None, None, None
 
 
 class RomOnline(torch.autograd.Function):
