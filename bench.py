@@ -158,6 +158,25 @@ def _timed(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def _or_all(flags):
+    acc = 0
+    for x in flags:
+        acc |= int(x)
+    return acc
+
+
+def _timed_once(torch, fn):
+    """ms of one call of fn (enqueued on the current stream)."""
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
 def config_measurements(torch, W, R):
     """The other configurations' figures: C1 (the FP64 parity anchor, steps/s), C3
     (one Sod/HLLC instance with HR-LSPG: windows and the cost split of an event),
@@ -226,6 +245,55 @@ def config_measurements(torch, W, R):
             note="backward-Euler Newton steps at dt = 0.064/N; the adjoint call runs the "
                  "forward pass, the checkpointed recomputation and the transposed solves")
         h.close()
+        # the adaptive ROM's rollout adjoint at the full horizon: dL/dq0 through the
+        # offline stage (10 training steps, POD) and 990 HR-LSPG steps with 99
+        # events, 32 checkpoint segments (re-orthonormalisation off, so that no
+        # update falls outside what the adjoint differentiates)
+        w.reorth_every = 0
+        h = R.RomBatch(w, q0=None, use_graph=False)
+        T = w.N_t - w.w_init
+        tgt = torch.as_tensor(w.extra["target"], dtype=torch.float32, device="cuda")
+
+        def forward():
+            h.offline(q0)
+            h.rom_step(T)
+
+        forward()   # warm-up
+        torch.cuda.synchronize()
+        ms_fwd = _timed_once(torch, forward)
+        gq_rom = torch.empty_like(q0)
+        gb = (h.get(R.GET_QTILDE) - tgt).contiguous()
+        ms_adj = _timed_once(torch, lambda: h.rollout_vjp(q0, T, gb, n_ckpt=32, out=gq_rom))
+        fl = h.status()
+        out["C4_euler_rusanov_64x262144_f32"].update(
+            rom_rollout_forward_ms=round(ms_fwd, 2), rom_rollout_vjp_ms=round(ms_adj, 2),
+            rom_rollout_steps=T, rom_rollout_events=T // w.z, rom_rollout_segments=32,
+            rom_rollout_vjp_over_forward=round(ms_adj / ms_fwd, 3),
+            rom_rollout_flags_or=_or_all(fl),
+            rom_rollout_note="dL/dq0 through Alg. 1 (offline stage, HR-LSPG steps with "
+                             "greedy DEIM rows held fixed, iSVD events); the adjoint call "
+                             "includes its own forward pass and the recomputation")
+        h.close()
+        # the explicit path (Sec. 5.3, App. D) on the reacting shape: SSPRK(4,3)
+        # DEIM-Galerkin fine steps on the limited second-order f, QDEIM + FGS rows
+        # (n_s = 2r), coarse SSPRK(4,3) steps of z dt; iSVD against Direct updates
+        # (the comparison of the paper's detonation timing table).  dt is set
+        # inside the explicit stability limit of 32,768 cells with diffusion 1e-3.
+        expl = {}
+        for rule in ("isvd", "direct"):
+            w = W.react10_f32()
+            w.projection, w.scheme, w.hyper = W.GALERKIN, "ssprk43", W.HR_QDEIM_FGS
+            w.dt = 2e-8
+            w.update, w.window = rule, (w.r if rule == "direct" else 0)
+            h = R.RomBatch(w, q0=torch.as_tensor(w.q0, dtype=torch.float32, device="cuda"),
+                           use_graph=rule == "isvd")
+            ms = _timed(torch, lambda: h.rom_step(w.z * 3), 1) / 3
+            expl[rule] = dict(ms_per_window=round(ms, 4),
+                              instance_steps_per_s=w.n_inst * w.z / (ms * 1e-3),
+                              flags_or=_or_all(h.status()))
+            h.close()
+        out["explicit_path_react10_32x32768_f32"] = dict(
+            expl, dt=2e-8, r=64, n_s=128, z=10, direct_window=64)
         # cost of one basis update per rule (App. A) on the batched Burgers shape
         # and the Sod shape: iSVD (Alg. 2), windowed SVD (Alg. A.1), Direct (Alg. A.2)
         rules = {}
