@@ -78,13 +78,15 @@ def parse():
     p.add_argument("--no-configs", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--only", choices=["all", "copy", "galerkin", "residual", "windows", "adjoint",
-                                      "configs"],
+                                      "rollout", "configs"],
                    default="all",
                    help="profiling runs: 'copy' times a plain 512 MiB device copy (the "
                         "reference for counter scaling), 'galerkin' only the Galerkin pass, "
                         "'residual' only R(q), 'windows' the offline stage plus --warmup and "
-                        "--steps adaptation windows, 'adjoint' the online adjoint, 'configs' "
-                        "the other configurations' figures; 'all' is the benchmark")
+                        "--steps adaptation windows, 'adjoint' the online adjoint, 'rollout' "
+                        "the 64 x 262,144 Euler rollout adjoint through Alg. 1 over --steps "
+                        "fine steps (0: the full 990), 'configs' the other configurations' "
+                        "figures; 'all' is the benchmark")
     return p.parse_args()
 
 
@@ -379,6 +381,22 @@ def profile_only(args, torch, W, R):
             ms = adjoint_ms(torch, h, w, max(args.steps, 1))
             h.close()
         log("online adjoint: %d window(s), %.3f ms per window" % (max(args.steps, 1), ms))
+    elif args.only == "rollout":
+        w = W.euler_adjoint_f32(n_inst=64, n=262144)
+        w.reorth_every = 0
+        T = args.steps if args.steps > 0 else w.N_t - w.w_init
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            h = R.RomBatch(w, q0=None, use_graph=False)
+            q0 = torch.as_tensor(w.q0, dtype=torch.float32, device="cuda")
+            tgt = torch.as_tensor(w.extra["target"], dtype=torch.float32, device="cuda")
+            h.offline(q0)
+            h.rom_step(T)
+            gb = (h.get(R.GET_QTILDE) - tgt).contiguous()
+            gq = torch.empty_like(q0)
+            ms = _timed_once(torch, lambda: h.rollout_vjp(q0, T, gb, out=gq))
+            h.close()
+        log("rollout adjoint: %d fine steps, %.2f ms" % (T, ms))
     elif args.only == "galerkin":
         w = W.burgers_batch_f32()
         s = torch.cuda.Stream()

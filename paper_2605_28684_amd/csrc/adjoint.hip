@@ -13,14 +13,16 @@
 //    Phibar += dt (D f) lambda^T + dt D^-1 J_f^T (D Phi lambda) a_{n+1}^T.
 //    J_g = I - dt Phi^T J_f Phi comes from the Galerkin pass's tile partials;
 //    the r x r solve runs per instance, the Phibar update per pass tile.
-//  * k_event_vjp: one event from the transfer back to yhat = D (y - q_ref):
+//  * k_ev_a, k_ev_core, k_ev_b, k_ev_c, k_ev_d: one event from the transfer back
+//    to yhat = D (y - q_ref):
 //    transfer a' = Ubar[:r, :r]^T a, rotation Phi' = [Phi, q / rho] Ubar[:, :r],
 //    truncation sigma' = Sbar[:r], the SVD of the core K (distinct singular
 //    values: Kbar = Ubar G Vbar^T with G_ii = sbar_i and
 //    G_ij = s_j (M_ij - M_ji) / (s_j^2 - s_i^2), M = Ubar^T Ubarbar), the core's
 //    entries lambda sigma, p = p1 + p2 and rho = |q|, and the two classical
-//    Gram-Schmidt passes, one workgroup per instance.  The coarse step's
-//    transposed solve is done by the banded solver outside.
+//    Gram-Schmidt passes: four passes over the rows by pass tiles, with the
+//    per-instance work between them.  The coarse step's transposed solve is
+//    done by the banded solver outside.
 #include "internal.h"
 #include "linalg.h"
 #include "physics.h"
@@ -205,189 +207,173 @@ __global__ __launch_bounds__(kRT) void k_step_vjp_rows(
   }
 }
 
-constexpr int kET = 512;  // threads of the event adjoint
+// ---- one event backward over pass tiles.  The passes over the rows of an
+// instance (A: the transfer and rotation adjoints and the Ubar partials; B:
+// Phi^T qbar; C: the second Gram-Schmidt pass; D: the first pass and yhat) run
+// one block per pass tile and write per-tile partial sums; between them a
+// block per instance sums the partials in tile order and does the small work
+// (the core SVD's adjoint, pbar, p2bar, p1bar).  Rows are staged through LDS in
+// chunks of rows padded to r + 1 (as many as the LDS budget kEVLds holds).
+constexpr int kEV = 256;   // threads of the event adjoint's kernels
+constexpr int kEC = 32;    // rows of a staged chunk, at least
+constexpr int kETI = 4, kETJ = 4;   // register tile of the Ubar partials
+constexpr int kEVLds = 4352;    // doubles of LDS for the staged chunks (34 KB)
 
-constexpr int kEChunk = 8192;   // elements of a staged chunk (rows x r), at most
-constexpr int kELds = 19200;    // doubles of dynamic LDS, at most (150 KB)
-
-// Rows of a staged chunk: as many as the LDS left after the three n x n core
-// matrices holds (two rows x (r + 1) arrays, rows padded by one double so that
-// lanes walking rows hit distinct banks, and four per-row scalars), at most
-// 1024 rows and kEChunk elements.
-DEV_HOST_INLINE int event_chunk_rows(int r) {
-  const int n = r + 1;
-  int c = (kELds - 3 * n * n - n) / (2 * (r + 1) + 4);
-  if (c > kEChunk / r) c = kEChunk / r;
-  return c > 1024 ? 1024 : c;
+// rows of a staged chunk: as many as kEVLds holds (two row arrays padded to
+// r + 1 and three per-row scalars), at most one per thread
+DEV_HOST_INLINE int ev_chunk(int r) {
+  int c = kEVLds / (2 * (r + 1) + 3);
+  c = c > kEV ? kEV : c;
+  return c < kEC ? kEC : c;
 }
 
-constexpr int kEPF = (kEChunk + kET - 1) / kET;   // chunk elements per thread
+// per-instance vector between the passes: pbar[0..r), rhobar, p2bar[0..r), p1bar[0..r)
+DEV_HOST_INLINE int evs_ld(int r) { return 3 * r + 2; }
+// partial sums per pass tile
+DEV_HOST_INLINE int evp_ld(int r) { return (r + 1) * r + 1 > 12 ? (r + 1) * r + 1 : 12; }
+DEV_HOST_INLINE int ev_ntl(int r) {
+  return ((r + 1 + kETI - 1) / kETI) * ((r + kETJ - 1) / kETJ);
+}
 
-// Loads of one chunk (ne <= kEChunk elements from offset off) into registers, so that the
-// next chunk is in flight while the current one is processed from LDS.
+// Stage nr rows of Phi (and of phibar) into LDS: each thread issues a batch of
+// eight loads before it writes any of them, so loads overlap.
 template <typename T>
-DEV void chunk_fetch(const T* __restrict__ Phi, const double* __restrict__ pb, int64_t off, int ne,
-                     bool with_b, double (&rp)[kEPF], double (&rb)[kEPF]) {
-  const int tid = threadIdx.x;
+DEV void ev_stage(const T* __restrict__ Phi, const double* __restrict__ pb, int64_t g0, int nr,
+                  int r, double* cP, double* cB) {
+  constexpr int NB = 8;
+  const int LDR = r + 1, ne = nr * r, tid = threadIdx.x;
+  for (int e0 = 0; e0 < ne; e0 += NB * kEV) {
+    double vp[NB], vb[NB];
 #pragma unroll
-  for (int u = 0; u < kEPF; ++u) {
-    const int e = tid + u * kET;
-    if (e < ne) {
-      rp[u] = (double)Phi[off + e];
-      if (with_b) rb[u] = pb[off + e];
+    for (int u = 0; u < NB; ++u) {
+      const int e = e0 + u * kEV + tid;
+      if (e < ne) {
+        vp[u] = (double)Phi[g0 * r + e];
+        if (cB) vb[u] = pb[g0 * r + e];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = e0 + u * kEV + tid;
+      if (e < ne) {
+        const int k = e / r, c = e - k * r;
+        cP[k * LDR + c] = vp[u];
+        if (cB) cB[k * LDR + c] = vb[u];
+      }
     }
   }
 }
 
-// Element e = k r + c of the chunk goes to row k, column c of the padded LDS
-// copy (row stride r + 1).
-DEV void chunk_put(double* cP, double* cB, int ne, int r, bool with_b, const double (&rp)[kEPF],
-                   const double (&rb)[kEPF]) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int u = 0; u < kEPF; ++u) {
-    const int e = tid + u * kET;
-    if (e < ne) {
-      const int k = e / r;
-      const int o = e + k;   // k (r + 1) + (e - k r)
-      cP[o] = rp[u];
-      if (with_b) cB[o] = rb[u];
-    }
+// column sums over the chunk rows by G = kEV / r row groups of r threads;
+// acc holds the thread's running sum
+DEV void ev_colsum(const double* cP, const double* w, int nr, int r, double& acc) {
+  const int G = kEV / r, tid = threadIdx.x;
+  const int gq = tid / r, gc = tid - (tid / r) * r;
+  if (gq < G)
+    for (int k = gq; k < nr; k += G) acc += cP[k * (r + 1) + gc] * w[k];
+}
+
+// the groups' sums, added in group order, into out[0..r)
+DEV void ev_colsum_out(double acc, int r, double* scratch, double* out) {
+  const int G = kEV / r, tid = threadIdx.x;
+  const int gq = tid / r, gc = tid - (tid / r) * r;
+  __syncthreads();
+  if (gq < G) scratch[gq * r + gc] = acc;
+  __syncthreads();
+  if (tid < r) {
+    double s = 0.0;
+    for (int g = 0; g < G; ++g) s += scratch[g * r + tid];
+    out[tid] = s;
   }
 }
 
-// One event backward, from the transfer down to yhat (the coarse step's
-// transposed solve follows outside).  Inputs recorded in the forward pass:
-// Phi_old, y_new (after the coarse step), sigma_old, a_old (before the
-// transfer), Ubar (n x n), pr = (p1, p2, 1/rho, s_n).  abar, sigbar and the
-// rows of phibar are replaced by the adjoints of the pre-event state; ybar
-// receives D yhatbar.  Rows are streamed in chunks staged in LDS (Phi as FP64
-// and the matching rows of phibar, rows padded to r + 1); dynamic LDS:
-// 3 n^2 + 2 C (r + 1) + 4 C + n
-// doubles for C = event_chunk_rows(r).
+// Pass A: q = yhat - Phi (p1 + p2) (into qs); the rows of Phibar_old =
+// Phibar' U[:r, :r]^T and jbar = Phibar' U[r, :r]^T (into js); partials of
+// Ubar[:r, :r] += Phi^T Phibar', Ubar[r, :r] += (q / rho)^T Phibar' and of
+// jq = jbar . q.  Dynamic LDS: n^2 + max(CH (2 (r + 1) + 1), 16 max(kEV, NTL)).
 template <typename T>
-__global__ __launch_bounds__(kET) void k_event_vjp(
-    int r, double lam_f, const int64_t* __restrict__ dof_off, const double* __restrict__ dvar,
-    const T* __restrict__ Phi, const T* __restrict__ ynew, const T* __restrict__ qref,
-    const double* __restrict__ sig_old, const double* __restrict__ a_old,
-    const double* __restrict__ ubar, const double* __restrict__ prs,
-    const double* __restrict__ sig_new, double* __restrict__ abar,
-    double* __restrict__ phibar, double* __restrict__ sigbar, double* __restrict__ ybar,
-    double* __restrict__ qs, double* __restrict__ js, uint32_t* flags, int nv,
-    double* __restrict__ qrbar, double* __restrict__ dvbar) {
+__global__ __launch_bounds__(kEV) void k_ev_a(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off, int r, int nv,
+    const double* __restrict__ dvar, const T* __restrict__ Phi, const T* __restrict__ ynew,
+    const T* __restrict__ qref, const double* __restrict__ ubar, const double* __restrict__ prs,
+    double* __restrict__ phibar, double* __restrict__ qs, double* __restrict__ js,
+    double* __restrict__ part) {
   extern __shared__ double sm[];
-  __shared__ double red[kET / 64];
-  __shared__ double vr[7][kMaxR + 1];  // p1, p2, abar', pbar (rhobar in [r]), p1bar, p2bar, wr
-  __shared__ double sv[kMaxR + 1];
-  const int n = r + 1, tid = threadIdx.x, b = blockIdx.x;
-  const int CH = event_chunk_rows(r);
-  double* U = sm;               // Ubar
-  double* Ub = U + n * n;       // its adjoint, then G
-  double* X = Ub + n * n;       // U^T Ub, then V
-  const int LDR = r + 1;         // padded row stride of the staged chunk
-  double* cP = X + n * n;       // chunk of Phi rows (FP64)
-  double* cB = cP + CH * LDR;   // the same rows of phibar
-  double* c0 = cB + CH * LDR;   // per-row scalars of the chunk
-  double* c1 = c0 + CH;
-  double* c2 = c1 + CH;
-  double* c3 = c2 + CH;
-  double* p1 = vr[0];
-  double* p2 = vr[1];
-  double* ab = vr[2];
-  double* pb = vr[3];
-  double* p1b = vr[4];
-  double* p2b = vr[5];
-  double* wr = vr[6];
-  const int64_t base = dof_off[b], nd = dof_off[b + 1] - base;
-  const double* dvb = dvar + (size_t)b * nv;   // D per variable; row i has variable i mod nv
+  __shared__ double red[kEV / 64];
+  __shared__ double sp[kMaxR];
+  const int n = r + 1, LDR = r + 1, tid = threadIdx.x;
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
   const double* pr = prs + (size_t)b * (2 * r + 2);
   const double irho = pr[2 * r];
-  if (irho == 0.0) {   // rho = 0: the update is not differentiable there
-    if (tid == 0) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
-    return;
-  }
-  const double rho = 1.0 / irho;
-  for (int e = tid; e < n * n; e += kET) {
-    U[e] = ubar[(size_t)b * n * n + e];
-    Ub[e] = 0.0;
-  }
-  for (int c = tid; c < r; c += kET) {
-    p1[c] = pr[c];
-    p2[c] = pr[r + c];
-    ab[c] = abar[(size_t)b * r + c];
-    sv[c] = sig_new[(size_t)b * r + c];
-  }
-  if (tid == 0) sv[r] = pr[2 * r + 1];
-  __syncthreads();
-  // transfer a' = U[:r, :r]^T a: abar_old = U[:r, :r] abar, Ubar[:r, :r] += a_old abar^T
-  for (int c = tid; c < r; c += kET) {
-    double s = 0.0;
-    for (int k = 0; k < r; ++k) s += U[c * n + k] * ab[k];
-    abar[(size_t)b * r + c] = s;
-  }
-  for (int e = tid; e < r * r; e += kET) {
-    const int i = e / r, j = e % r;
-    Ub[i * n + j] += a_old[(size_t)b * r + i] * ab[j];
-  }
-  __syncthreads();
-  // pass A: q = yhat - Phi (p1 + p2); rotation adjoint Ubar[:r, :r] += Phi^T Phibar',
-  // Ubar[r, :r] += (q / rho)^T Phibar'; rows Phibar_old = Phibar' U[:r, :r]^T and
-  // jbar = Phibar' U[r, :r]^T; jq = jbar . q
+  if (irho == 0.0) return;   // rho = 0: the instance is flagged and skipped
+  const int CH = ev_chunk(r);
+  double* U = sm;
+  double* cP = U + n * n;
+  double* cB = cP + CH * LDR;
+  double* c0 = cB + CH * LDR;
+  double* tp = cP;           // the threads' Ubar tile sums, after the last chunk
+  for (int e = tid; e < n * n; e += kEV) U[e] = ubar[(size_t)b * n * n + e];
+  for (int c = tid; c < r; c += kEV) sp[c] = pr[c] + pr[r + c];
+  const int64_t base = dof_off[b];
+  const double* dvb = dvar + (size_t)b * nv;
+  const int NJ = (r + kETJ - 1) / kETJ, NTL = ev_ntl(r);
+  const int nslot = (NTL + kEV - 1) / kEV;            // 1, or 2 for the widest bases
+  const int KS = nslot == 1 ? kEV / NTL : 1;          // row groups per tile
+  const int ks = nslot == 1 ? tid / NTL : 0;
+  const bool tl_on = nslot == 1 ? tid < KS * NTL : true;
+  double ta[2][kETI][kETJ];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int a = 0; a < kETI; ++a)
+#pragma unroll
+      for (int c = 0; c < kETJ; ++c) ta[m][a][c] = 0.0;
   double jq = 0.0;
-  double rp[kEPF], rb[kEPF];
-  auto chunk_ne = [&](int64_t r0) { return (int)((nd - r0 < CH ? nd - r0 : CH) * r); };
-  // Ubar rows 0..r (row r from q / rho) against the r columns of Phibar', in
-  // 4 x 4 register tiles; KS thread groups split the rows of each chunk and
-  // keep their sums over the whole pass, added in group order at the end
-  constexpr int TI = 4, TJ = 4;
-  const int NI = (n + TI - 1) / TI, NJ = (r + TJ - 1) / TJ, NTL = NI * NJ;
-  int KS = kET / NTL;
-  if (KS * NTL * TI * TJ > 2 * CH * LDR) KS = 2 * CH * LDR / (NTL * TI * TJ);
-  if (KS < 1) KS = 1;
-  const bool tl_on = tid < NTL * KS;
-  const int ks = tid / NTL, tt = tid - (tid / NTL) * NTL;
-  const int i0 = (tt / NJ) * TI, j0 = (tt - (tt / NJ) * NJ) * TJ;
-  double ta[TI][TJ];
-#pragma unroll
-  for (int a = 0; a < TI; ++a)
-#pragma unroll
-    for (int c = 0; c < TJ; ++c) ta[a][c] = 0.0;
-  if (nd > 0) chunk_fetch(Phi, phibar, base * r, chunk_ne(0), true, rp, rb);
-  for (int64_t r0 = 0; r0 < nd; r0 += CH) {
-    const int nr = (int)(nd - r0 < CH ? nd - r0 : CH);
-    chunk_put(cP, cB, nr * r, r, true, rp, rb);
+  for (int64_t r0 = 0; r0 < t.ncell; r0 += CH) {
+    const int nr = (int)(t.ncell - r0 < CH ? t.ncell - r0 : CH);
+    const int64_t g0 = base + t.cell0 + r0;
     __syncthreads();
-    if (r0 + CH < nd) chunk_fetch(Phi, phibar, (base + r0 + CH) * r, chunk_ne(r0 + CH), true, rp, rb);
-    for (int k = tid; k < nr; k += kET) {
-      double q = dvb[(r0 + k) % nv] * ((double)ynew[base + r0 + k] - (double)qref[base + r0 + k]);
-      for (int c = 0; c < r; ++c) q -= cP[k * LDR + c] * (p1[c] + p2[c]);
+    ev_stage(Phi, phibar, g0, nr, r, cP, cB);
+    __syncthreads();
+    for (int k = tid; k < nr; k += kEV) {
+      const int64_t g = g0 + k;
+      double q = dvb[(t.cell0 + r0 + k) % nv] * ((double)ynew[g] - (double)qref[g]);
+      for (int c = 0; c < r; ++c) q -= cP[k * LDR + c] * sp[c];
       c0[k] = q;
-      qs[base + r0 + k] = q;
+      qs[g] = q;
     }
     __syncthreads();
     if (tl_on) {
-      for (int k = ks; k < nr; k += KS) {
-        double av[TI], bv[TJ];
 #pragma unroll
-        for (int a = 0; a < TI; ++a) {
-          const int i = i0 + a;
-          av[a] = i < r ? cP[k * LDR + i] : (i == r ? c0[k] * irho : 0.0);
+      for (int m = 0; m < 2; ++m) {
+        if (m >= nslot) continue;
+        const int tt = nslot == 1 ? tid - ks * NTL : tid + m * kEV;
+        if (tt >= NTL) continue;
+        const int i0 = (tt / NJ) * kETI, j0 = (tt - (tt / NJ) * NJ) * kETJ;
+        for (int k = ks; k < nr; k += KS) {
+          double av[kETI], bv[kETJ];
+#pragma unroll
+          for (int a = 0; a < kETI; ++a) {
+            const int i = i0 + a;
+            av[a] = i < r ? cP[k * LDR + i] : (i == r ? c0[k] * irho : 0.0);
+          }
+#pragma unroll
+          for (int c = 0; c < kETJ; ++c) bv[c] = j0 + c < r ? cB[k * LDR + j0 + c] : 0.0;
+#pragma unroll
+          for (int a = 0; a < kETI; ++a)
+#pragma unroll
+            for (int c = 0; c < kETJ; ++c) ta[m][a][c] += av[a] * bv[c];
         }
-#pragma unroll
-        for (int c = 0; c < TJ; ++c) bv[c] = j0 + c < r ? cB[k * LDR + j0 + c] : 0.0;
-#pragma unroll
-        for (int a = 0; a < TI; ++a)
-#pragma unroll
-          for (int c = 0; c < TJ; ++c) ta[a][c] += av[a] * bv[c];
       }
     }
-    // rows of Phibar_old = Phibar' U[:r, :r]^T and jbar = Phibar' U[r, :r]^T in 4 x 3
-    // register tiles (each output summed over m in order by one thread)
+    // rows of Phibar_old and jbar in 4 x 3 register tiles (each output summed
+    // over m in order by one thread)
     {
       constexpr int TR = 4, TC = 3;
       const int NR = (nr + TR - 1) / TR, NC = (n + TC - 1) / TC;
-      for (int e = tid; e < NR * NC; e += kET) {
-        const int k0 = (e / NC) * TR, c0t = (e - (e / NC) * NC) * TC;
+      for (int e = tid; e < NR * NC; e += kEV) {
+        const int k0 = (e / NC) * TR, ct = (e - (e / NC) * NC) * TC;
         double o[TR][TC];
 #pragma unroll
         for (int a = 0; a < TR; ++a)
@@ -398,7 +384,7 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
 #pragma unroll
           for (int a = 0; a < TR; ++a) bv[a] = k0 + a < nr ? cB[(k0 + a) * LDR + m] : 0.0;
 #pragma unroll
-          for (int c = 0; c < TC; ++c) uv[c] = c0t + c < n ? U[(c0t + c) * n + m] : 0.0;
+          for (int c = 0; c < TC; ++c) uv[c] = ct + c < n ? U[(ct + c) * n + m] : 0.0;
 #pragma unroll
           for (int a = 0; a < TR; ++a)
 #pragma unroll
@@ -410,48 +396,109 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
           if (k >= nr) continue;
 #pragma unroll
           for (int c = 0; c < TC; ++c) {
-            const int cc = c0t + c;
-            if (cc < r) phibar[(base + r0 + k) * r + cc] = o[a][c];
+            const int cc = ct + c;
+            if (cc < r) phibar[(g0 + k) * r + cc] = o[a][c];
             else if (cc == r) {
-              js[base + r0 + k] = o[a][c];
+              js[g0 + k] = o[a][c];
               jq += o[a][c] * c0[k];
             }
           }
         }
       }
     }
-    __syncthreads();
   }
-  // the row groups' sums of the Ubar tiles, added in group order (the chunk area is free)
-  {
-    double* part = cP;
-    if (tl_on) {
+  __syncthreads();
+  // the tile's partials: Ubar entries summed over the row groups in order, then jq
+  if (tl_on) {
 #pragma unroll
-      for (int a = 0; a < TI; ++a)
+    for (int m = 0; m < 2; ++m) {
+      if (m >= nslot) continue;
+      const int tt = nslot == 1 ? tid - ks * NTL : tid + m * kEV;
+      if (tt >= NTL) continue;
+      const int slot = nslot == 1 ? ks * NTL + tt : tt;
 #pragma unroll
-        for (int c = 0; c < TJ; ++c) part[((size_t)ks * NTL + tt) * (TI * TJ) + a * TJ + c] = ta[a][c];
+      for (int a = 0; a < kETI; ++a)
+#pragma unroll
+        for (int c = 0; c < kETJ; ++c) tp[(size_t)slot * (kETI * kETJ) + a * kETJ + c] = ta[m][a][c];
     }
-    __syncthreads();
-    for (int e = tid; e < n * r; e += kET) {
-      const int i = e / r, j = e % r;
-      const int t2 = (i / TI) * NJ + j / TJ, w = (i % TI) * TJ + j % TJ;
-      double sacc = 0.0;
-      for (int g = 0; g < KS; ++g) sacc += part[((size_t)g * NTL + t2) * (TI * TJ) + w];
-      Ub[i * n + j] += sacc;
-    }
-    __syncthreads();
+  }
+  __syncthreads();
+  double* out = part + (size_t)blockIdx.x * evp_ld(r);
+  for (int e = tid; e < n * r; e += kEV) {
+    const int i = e / r, j = e % r;
+    const int t2 = (i / kETI) * NJ + j / kETJ, w = (i % kETI) * kETJ + j % kETJ;
+    double s = 0.0;
+    for (int g = 0; g < KS; ++g) s += tp[((size_t)g * NTL + t2) * (kETI * kETJ) + w];
+    out[e] = s;
   }
   jq = block_sum(jq, red);
-  // SVD of K: M = U^T Ub (in X), G (in Ub), V = K^T U / s (in X), then the entries of
-  // Kbar = U G V^T that K depends on: lambda sigma (diagonal), p (last column), rho
-  for (int e = tid; e < n * n; e += kET) {
+  if (tid == 0) out[n * r] = jq;
+}
+
+// After pass A, one block per instance: the transfer adjoint (abar <- U[:r, :r]
+// abar, Ubar[:r, :r] += a_old abar^T), the tiles' Ubar partials in tile order,
+// then the adjoint of the core SVD and of K's entries: sigbar, pbar, rhobar.
+// Dynamic LDS: 4 n^2 + n doubles.
+__global__ __launch_bounds__(kEV) void k_ev_core(
+    int r, double lam_f, const int* __restrict__ tfirst, const double* __restrict__ part,
+    const double* __restrict__ sig_old, const double* __restrict__ a_old,
+    const double* __restrict__ ubar, const double* __restrict__ prs,
+    const double* __restrict__ sig_new, double* __restrict__ abar,
+    double* __restrict__ sigbar, double* __restrict__ evs, uint32_t* flags) {
+  extern __shared__ double sm[];
+  __shared__ double sv[kMaxR + 1], ab[kMaxR], p1[kMaxR], p2[kMaxR], wr[kMaxR + 1],
+      pb[kMaxR + 1];
+  __shared__ double jqs;
+  const int n = r + 1, tid = threadIdx.x, b = blockIdx.x;
+  const double* pr = prs + (size_t)b * (2 * r + 2);
+  const double irho = pr[2 * r];
+  if (irho == 0.0) {
+    if (tid == 0) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
+    return;
+  }
+  const double rho = 1.0 / irho;
+  double* U = sm;
+  double* Ub = U + n * n;
+  double* X = Ub + n * n;
+  double* GVt = X + n * n;
+  for (int e = tid; e < n * n; e += kEV) U[e] = ubar[(size_t)b * n * n + e];
+  for (int c = tid; c < r; c += kEV) {
+    ab[c] = abar[(size_t)b * r + c];
+    p1[c] = pr[c];
+    p2[c] = pr[r + c];
+    sv[c] = sig_new[(size_t)b * r + c];
+  }
+  if (tid == 0) sv[r] = pr[2 * r + 1];
+  __syncthreads();
+  for (int c = tid; c < r; c += kEV) {
+    double s = 0.0;
+    for (int k = 0; k < r; ++k) s += U[c * n + k] * ab[k];
+    abar[(size_t)b * r + c] = s;
+  }
+  const int ld = evp_ld(r);
+  for (int e = tid; e < n * n; e += kEV) {
+    const int i = e / n, j = e % n;
+    double s = (i < r && j < r) ? a_old[(size_t)b * r + i] * ab[j] : 0.0;
+    if (j < r)
+      for (int tt = tfirst[b]; tt < tfirst[b + 1]; ++tt) s += part[(size_t)tt * ld + i * r + j];
+    Ub[e] = s;
+  }
+  if (tid == 0) {
+    double s = 0.0;
+    for (int tt = tfirst[b]; tt < tfirst[b + 1]; ++tt) s += part[(size_t)tt * ld + n * r];
+    jqs = s;
+  }
+  __syncthreads();
+  // SVD of K: M = U^T Ub (in X), G (in Ub), V = K^T U / s (in X); the entries
+  // of Kbar = U G V^T that K depends on: lambda sigma (diagonal), p (last column), rho
+  for (int e = tid; e < n * n; e += kEV) {
     const int i = e / n, j = e % n;
     double s = 0.0;
     for (int k = 0; k < n; ++k) s += U[k * n + i] * Ub[k * n + j];
     X[e] = s;
   }
   __syncthreads();
-  for (int e = tid; e < n * n; e += kET) {
+  for (int e = tid; e < n * n; e += kEV) {
     const int i = e / n, j = e % n;
     double g;
     if (i == j) g = i < r ? sigbar[(size_t)b * r + i] : 0.0;
@@ -460,7 +507,7 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
     Ub[e] = g;
   }
   __syncthreads();
-  for (int e = tid; e < n * n; e += kET) {
+  for (int e = tid; e < n * n; e += kEV) {
     const int k = e / n, j = e % n;   // V[k][j]
     double v = 0.0;
     if (sv[j] > 0.0) {
@@ -476,139 +523,224 @@ __global__ __launch_bounds__(kET) void k_event_vjp(
     X[e] = v;
   }
   __syncthreads();
-  for (int k = tid; k < n; k += kET) {   // wr = G V[r, :]^T
+  for (int k = tid; k < n; k += kEV) {   // wr = G V[r, :]^T
     double s = 0.0;
     for (int m = 0; m < n; ++m) s += Ub[k * n + m] * X[r * n + m];
     wr[k] = s;
   }
-  __syncthreads();
-  double* GVt = cP;   // (G V^T)[k][c], in the chunk area (at least n^2 doubles)
-  for (int e = tid; e < n * n; e += kET) {
+  for (int e = tid; e < n * n; e += kEV) {
     const int k = e / n, c = e - (e / n) * n;
     double gv = 0.0;
     for (int m = 0; m < n; ++m) gv += Ub[k * n + m] * X[c * n + m];
     GVt[e] = gv;
   }
   __syncthreads();
-  for (int c = tid; c < n; c += kET) {
+  for (int c = tid; c < n; c += kEV) {
     double kd = 0.0, kc = 0.0;
     for (int k = 0; k < n; ++k) {
       kd += U[c * n + k] * GVt[k * n + c];
       kc += U[c * n + k] * wr[k];
     }
-    if (c < r) {
-      sigbar[(size_t)b * r + c] = lam_f * kd;
-      pb[c] = kc;
-    } else {
-      pb[r] = kc;
-    }
+    if (c < r) sigbar[(size_t)b * r + c] = lam_f * kd;
+    pb[c] = kc;
   }
   __syncthreads();
+  double* e_out = evs + (size_t)b * evs_ld(r);
+  for (int c = tid; c < r; c += kEV) e_out[c] = pb[c];
   // j = q / rho, rho = |q|: qbar = (jbar + rhobar q) / rho
-  const double rhob = pb[r] - jq * irho * irho;
-  // pass B: p2bar = pbar - Phi^T qbar (G row groups of r threads; their sums
-  // are added in group order)
-  const int G = kET / r;
-  const int gq = tid / r, gc = tid - (tid / r) * r;
-  auto group_sum = [&](double acc, double* out) {
-    __syncthreads();
-    if (gq < G) cP[gq * r + gc] = acc;
-    __syncthreads();
-    if (tid < r) {
-      double sacc = 0.0;
-      for (int g = 0; g < G; ++g) sacc += cP[g * r + tid];
-      out[tid] = pb[tid] - sacc;
-    }
-    __syncthreads();
-  };
+  if (tid == 0) e_out[r] = pb[r] - jqs * irho * irho;
+}
+
+// Pass B: partials of Phi^T qbar with qbar = (jbar + rhobar q) / rho.
+template <typename T>
+__global__ __launch_bounds__(kEV) void k_ev_b(const Tile* __restrict__ tiles,
+                                              const int64_t* __restrict__ dof_off, int r,
+                                              const T* __restrict__ Phi,
+                                              const double* __restrict__ prs,
+                                              const double* __restrict__ evs,
+                                              const double* __restrict__ qs,
+                                              const double* __restrict__ js,
+                                              double* __restrict__ part) {
+  extern __shared__ double sm[];
+  const int LDR = r + 1, tid = threadIdx.x;
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  const double irho = prs[(size_t)b * (2 * r + 2) + 2 * r];
+  if (irho == 0.0) return;
+  const double rhob = evs[(size_t)b * evs_ld(r) + r];
+  const int CH = ev_chunk(r);
+  double* cP = sm;
+  double* c0 = cP + CH * LDR;
+  double* scr = c0 + CH;
+  const int64_t base = dof_off[b];
   double acc = 0.0;
-  if (nd > 0) chunk_fetch(Phi, phibar, base * r, chunk_ne(0), false, rp, rb);
-  for (int64_t r0 = 0; r0 < nd; r0 += CH) {
-    const int nr = (int)(nd - r0 < CH ? nd - r0 : CH);
-    chunk_put(cP, cB, nr * r, r, false, rp, rb);
-    if (r0 + CH < nd) chunk_fetch(Phi, phibar, (base + r0 + CH) * r, chunk_ne(r0 + CH), false, rp, rb);
-    for (int k = tid; k < nr; k += kET)
-      c0[k] = (js[base + r0 + k] + rhob * qs[base + r0 + k]) * irho;
+  for (int64_t r0 = 0; r0 < t.ncell; r0 += CH) {
+    const int nr = (int)(t.ncell - r0 < CH ? t.ncell - r0 : CH);
+    const int64_t g0 = base + t.cell0 + r0;
     __syncthreads();
-    if (gq < G)
-      for (int k = gq; k < nr; k += G) acc += cP[k * LDR + gc] * c0[k];
+    ev_stage(Phi, (const double*)nullptr, g0, nr, r, cP, nullptr);
+    for (int k = tid; k < nr; k += kEV) c0[k] = (js[g0 + k] + rhob * qs[g0 + k]) * irho;
     __syncthreads();
+    ev_colsum(cP, c0, nr, r, acc);
   }
-  group_sum(acc, p2b);
-  // pass C: q1 = yhat - Phi p1, q1bar = qbar + Phi p2bar (into js);
-  // Phibar_old += -qbar p2^T + q1 p2bar^T; p1bar = pbar - Phi^T q1bar
-  acc = 0.0;
-  if (nd > 0) chunk_fetch(Phi, phibar, base * r, chunk_ne(0), true, rp, rb);
-  for (int64_t r0 = 0; r0 < nd; r0 += CH) {
-    const int nr = (int)(nd - r0 < CH ? nd - r0 : CH);
-    chunk_put(cP, cB, nr * r, r, true, rp, rb);
+  ev_colsum_out(acc, r, scr, part + (size_t)blockIdx.x * evp_ld(r));
+}
+
+// Pass C: q1 = yhat - Phi p1; q1bar = qbar + Phi p2bar (into js);
+// Phibar_old += -qbar p2^T + q1 p2bar^T; partials of Phi^T q1bar.
+template <typename T>
+__global__ __launch_bounds__(kEV) void k_ev_c(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off, int r, int nv,
+    const double* __restrict__ dvar, const T* __restrict__ Phi, const T* __restrict__ ynew,
+    const T* __restrict__ qref, const double* __restrict__ prs, const double* __restrict__ evs,
+    const double* __restrict__ qs, double* __restrict__ js, double* __restrict__ phibar,
+    double* __restrict__ part) {
+  extern __shared__ double sm[];
+  __shared__ double p1[kMaxR], p2[kMaxR], p2b[kMaxR];
+  const int LDR = r + 1, tid = threadIdx.x;
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  const double* pr = prs + (size_t)b * (2 * r + 2);
+  const double irho = pr[2 * r];
+  if (irho == 0.0) return;
+  const double* e_in = evs + (size_t)b * evs_ld(r);
+  const double rhob = e_in[r];
+  for (int c = tid; c < r; c += kEV) {
+    p1[c] = pr[c];
+    p2[c] = pr[r + c];
+    p2b[c] = e_in[r + 1 + c];
+  }
+  const int CH = ev_chunk(r);
+  double* cP = sm;
+  double* cB = cP + CH * LDR;
+  double* c0 = cB + CH * LDR;
+  double* c1 = c0 + CH;
+  double* c2 = c1 + CH;
+  double* scr = c2 + CH;
+  const int64_t base = dof_off[b];
+  const double* dvb = dvar + (size_t)b * nv;
+  double acc = 0.0;
+  for (int64_t r0 = 0; r0 < t.ncell; r0 += CH) {
+    const int nr = (int)(t.ncell - r0 < CH ? t.ncell - r0 : CH);
+    const int64_t g0 = base + t.cell0 + r0;
     __syncthreads();
-    if (r0 + CH < nd) chunk_fetch(Phi, phibar, (base + r0 + CH) * r, chunk_ne(r0 + CH), true, rp, rb);
-    for (int k = tid; k < nr; k += kET) {
-      const int64_t g = base + r0 + k;
-      double q1 = dvb[(r0 + k) % nv] * ((double)ynew[g] - (double)qref[g]);
-      double t = 0.0;
+    ev_stage(Phi, phibar, g0, nr, r, cP, cB);
+    __syncthreads();
+    for (int k = tid; k < nr; k += kEV) {
+      const int64_t g = g0 + k;
+      double q1 = dvb[(t.cell0 + r0 + k) % nv] * ((double)ynew[g] - (double)qref[g]);
+      double tt = 0.0;
       for (int c = 0; c < r; ++c) {
         q1 -= cP[k * LDR + c] * p1[c];
-        t += cP[k * LDR + c] * p2b[c];
+        tt += cP[k * LDR + c] * p2b[c];
       }
       const double qb = (js[g] + rhob * qs[g]) * irho;
       c0[k] = qb;
       c1[k] = q1;
-      c2[k] = qb + t;   // q1bar
-      js[g] = qb + t;
+      c2[k] = qb + tt;   // q1bar
+      js[g] = qb + tt;
     }
     __syncthreads();
-    for (int e = tid; e < nr * r; e += kET) {
+    for (int e = tid; e < nr * r; e += kEV) {
       const int k = e / r, c = e % r;
-      phibar[(base + r0) * r + e] = cB[k * LDR + c] - c0[k] * p2[c] + c1[k] * p2b[c];
+      phibar[g0 * r + e] = cB[k * LDR + c] - c0[k] * p2[c] + c1[k] * p2b[c];
     }
-    if (gq < G)
-      for (int k = gq; k < nr; k += G) acc += cP[k * LDR + gc] * c2[k];
-    __syncthreads();
+    ev_colsum(cP, c2, nr, r, acc);
   }
-  group_sum(acc, p1b);
-  // pass D: Phibar_old += -q1bar p1^T + yhat p1bar^T; yhatbar = q1bar + Phi p1bar;
-  // ybar += D yhatbar; with qrbar: qrbar -= D yhatbar, and dvbar[v] += the sum
-  // of yhatbar (y - q_ref) over the rows of variable v
+  ev_colsum_out(acc, r, scr, part + (size_t)blockIdx.x * evp_ld(r));
+}
+
+// Pass D: Phibar_old += -q1bar p1^T + yhat p1bar^T; yhatbar = q1bar + Phi p1bar;
+// ybar += D yhatbar; with qrbar: qrbar -= D yhatbar and partials of
+// sum yhatbar (y - q_ref) per variable.
+template <typename T>
+__global__ __launch_bounds__(kEV) void k_ev_d(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off, int r, int nv,
+    const double* __restrict__ dvar, const T* __restrict__ Phi, const T* __restrict__ ynew,
+    const T* __restrict__ qref, const double* __restrict__ prs, const double* __restrict__ evs,
+    const double* __restrict__ js, double* __restrict__ phibar, double* __restrict__ ybar,
+    double* __restrict__ qrbar, double* __restrict__ part) {
+  extern __shared__ double sm[];
+  __shared__ double p1[kMaxR], p1b[kMaxR];
+  __shared__ double red[kEV / 64];
+  const int LDR = r + 1, tid = threadIdx.x;
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  const double* pr = prs + (size_t)b * (2 * r + 2);
+  if (pr[2 * r] == 0.0) return;
+  const double* e_in = evs + (size_t)b * evs_ld(r);
+  for (int c = tid; c < r; c += kEV) {
+    p1[c] = pr[c];
+    p1b[c] = e_in[2 * r + 1 + c];
+  }
+  const int CH = ev_chunk(r);
+  double* cP = sm;
+  double* cB = cP + CH * LDR;
+  double* c0 = cB + CH * LDR;
+  double* c1 = c0 + CH;
+  const int64_t base = dof_off[b];
+  const double* dvb = dvar + (size_t)b * nv;
   double dva[12];
   for (int v = 0; v < 12; ++v) dva[v] = 0.0;
-  if (nd > 0) chunk_fetch(Phi, phibar, base * r, chunk_ne(0), true, rp, rb);
-  for (int64_t r0 = 0; r0 < nd; r0 += CH) {
-    const int nr = (int)(nd - r0 < CH ? nd - r0 : CH);
-    chunk_put(cP, cB, nr * r, r, true, rp, rb);
+  for (int64_t r0 = 0; r0 < t.ncell; r0 += CH) {
+    const int nr = (int)(t.ncell - r0 < CH ? t.ncell - r0 : CH);
+    const int64_t g0 = base + t.cell0 + r0;
     __syncthreads();
-    if (r0 + CH < nd) chunk_fetch(Phi, phibar, (base + r0 + CH) * r, chunk_ne(r0 + CH), true, rp, rb);
-    for (int k = tid; k < nr; k += kET) {
-      const int64_t g = base + r0 + k;
-      const int v = (int)((r0 + k) % nv);
+    ev_stage(Phi, phibar, g0, nr, r, cP, cB);
+    __syncthreads();
+    for (int k = tid; k < nr; k += kEV) {
+      const int64_t g = g0 + k;
+      const int v = (int)((t.cell0 + r0 + k) % nv);
       const double d = dvb[v];
       const double dy = (double)ynew[g] - (double)qref[g];
-      const double yh = d * dy;
       const double q1b = js[g];
-      double t = 0.0;
-      for (int c = 0; c < r; ++c) t += cP[k * LDR + c] * p1b[c];
+      double tt = 0.0;
+      for (int c = 0; c < r; ++c) tt += cP[k * LDR + c] * p1b[c];
       c0[k] = q1b;
-      c1[k] = yh;
-      ybar[g] += d * (q1b + t);
+      c1[k] = d * dy;
+      ybar[g] += d * (q1b + tt);
       if (qrbar) {
-        qrbar[g] -= d * (q1b + t);
+        qrbar[g] -= d * (q1b + tt);
         for (int u = 0; u < 12; ++u)
-          if (u == v) dva[u] += (q1b + t) * dy;
+          if (u == v) dva[u] += (q1b + tt) * dy;
       }
     }
     __syncthreads();
-    for (int e = tid; e < nr * r; e += kET) {
+    for (int e = tid; e < nr * r; e += kEV) {
       const int k = e / r, c = e % r;
-      phibar[(base + r0) * r + e] = cB[k * LDR + c] - c0[k] * p1[c] + c1[k] * p1b[c];
+      phibar[g0 * r + e] = cB[k * LDR + c] - c0[k] * p1[c] + c1[k] * p1b[c];
     }
-    __syncthreads();
   }
   if (qrbar) {
+    double* out = part + (size_t)blockIdx.x * evp_ld(r);
     for (int v = 0; v < nv; ++v) {
-      const double sv_ = block_sum(dva[v], red);
-      if (tid == 0) dvbar[(size_t)b * nv + v] += sv_;
+      const double s = block_sum(dva[v], red);
+      if (tid == 0) out[v] = s;
     }
+  }
+}
+
+// Between the passes: dst[c] = pbar[c] - sum over the tiles (in order) of the
+// partials; the last step adds the D partials to dvbar instead.
+__global__ void k_ev_vec(int r, const int* __restrict__ tfirst, const double* __restrict__ prs,
+                         const double* __restrict__ part, double* __restrict__ evs, int dst_off,
+                         int nv, double* __restrict__ dvbar) {
+  const int b = blockIdx.x;
+  if (prs[(size_t)b * (2 * r + 2) + 2 * r] == 0.0) return;
+  const int ld = evp_ld(r);
+  double* e = evs + (size_t)b * evs_ld(r);
+  if (dvbar) {
+    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+      double s = 0.0;
+      for (int tt = tfirst[b]; tt < tfirst[b + 1]; ++tt) s += part[(size_t)tt * ld + v];
+      dvbar[(size_t)b * nv + v] += s;
+    }
+    return;
+  }
+  for (int c = threadIdx.x; c < r; c += blockDim.x) {
+    double s = 0.0;
+    for (int tt = tfirst[b]; tt < tfirst[b + 1]; ++tt) s += part[(size_t)tt * ld + c];
+    e[dst_off + c] = e[c] - s;
   }
 }
 
@@ -655,28 +787,54 @@ rom_status launch_step_vjp(rom_batch* h, const void* Phi, const double* a1, doub
   return ROM_OK;
 }
 
-size_t event_vjp_shm(int r) {
-  const size_t n = (size_t)r + 1, C = (size_t)event_chunk_rows(r);
-  return sizeof(double) * (3 * n * n + 2 * C * (r + 1) + 4 * C + n);
+size_t event_vjp_scratch_doubles(const rom_batch* h) {
+  const int r = h->cfg.r;
+  return (size_t)std::max(h->n_ptiles, 1) * evp_ld(r) + (size_t)h->cfg.n_inst * evs_ld(r);
 }
 
 rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new,
                             const double* sig_old, const double* a_old, const double* ubar,
                             const double* pr, const double* sig_new, double* abar,
                             double* phibar, double* sigbar, double* ybar, double* qs, double* js,
-                            hipStream_t s, double* qrbar, double* dvbar) {
-  const int B = h->cfg.n_inst, r = h->cfg.r;
-  const size_t shm = event_vjp_shm(r);
-  if (h->cfg.precision == ROM_F64)
-    hipLaunchKernelGGL((k_event_vjp<double>), dim3(B), dim3(kET), shm, s, r, h->cfg.lambda,
-                       h->d_dof_off, h->d_var, (const double*)Phi_old, (const double*)y_new,
-                       (const double*)h->q_ref, sig_old, a_old, ubar, pr, sig_new, abar, phibar,
-                       sigbar, ybar, qs, js, h->flags, h->nv, qrbar, dvbar);
-  else
-    hipLaunchKernelGGL((k_event_vjp<float>), dim3(B), dim3(kET), shm, s, r, h->cfg.lambda,
-                       h->d_dof_off, h->d_var, (const float*)Phi_old, (const float*)y_new,
-                       (const float*)h->q_ref, sig_old, a_old, ubar, pr, sig_new, abar, phibar,
-                       sigbar, ybar, qs, js, h->flags, h->nv, qrbar, dvbar);
+                            double* evscr, hipStream_t s, double* qrbar, double* dvbar) {
+  const int B = h->cfg.n_inst, r = h->cfg.r, n = r + 1, nv = h->nv;
+  double* part = evscr;
+  double* evs = evscr + (size_t)std::max(h->n_ptiles, 1) * evp_ld(r);
+  const size_t ntl = (size_t)ev_ntl(r);
+  const size_t ch = (size_t)ev_chunk(r);
+  const size_t shm_a = sizeof(double) * ((size_t)n * n + std::max(ch * (2 * (r + 1) + 1),
+                                                                   16 * std::max((size_t)kEV, ntl)));
+  const size_t shm_core = sizeof(double) * 4 * (size_t)n * n;
+  const size_t shm_b = sizeof(double) * (ch * (r + 1) + ch + kEV);
+  const size_t shm_c = sizeof(double) * (2 * ch * (r + 1) + 3 * ch + kEV);
+  const size_t shm_d = sizeof(double) * (2 * ch * (r + 1) + 2 * ch);
+  const unsigned nt = (unsigned)h->n_ptiles;
+  auto go = [&](auto tag) {
+    using T = decltype(tag);
+    hipLaunchKernelGGL((k_ev_a<T>), dim3(nt), dim3(kEV), shm_a, s, h->d_ptiles, h->d_dof_off, r,
+                       nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref, ubar,
+                       pr, phibar, qs, js, part);
+    hipLaunchKernelGGL(k_ev_core, dim3(B), dim3(kEV), shm_core, s, r, h->cfg.lambda,
+                       h->d_ptile_first, part, sig_old, a_old, ubar, pr, sig_new, abar, sigbar,
+                       evs, h->flags);
+    hipLaunchKernelGGL((k_ev_b<T>), dim3(nt), dim3(kEV), shm_b, s, h->d_ptiles, h->d_dof_off, r,
+                       (const T*)Phi_old, pr, evs, qs, js, part);
+    hipLaunchKernelGGL(k_ev_vec, dim3(B), dim3(64), 0, s, r, h->d_ptile_first, pr, part, evs,
+                       r + 1, nv, (double*)nullptr);
+    hipLaunchKernelGGL((k_ev_c<T>), dim3(nt), dim3(kEV), shm_c, s, h->d_ptiles, h->d_dof_off, r,
+                       nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref, pr,
+                       evs, qs, js, phibar, part);
+    hipLaunchKernelGGL(k_ev_vec, dim3(B), dim3(64), 0, s, r, h->d_ptile_first, pr, part, evs,
+                       2 * r + 1, nv, (double*)nullptr);
+    hipLaunchKernelGGL((k_ev_d<T>), dim3(nt), dim3(kEV), shm_d, s, h->d_ptiles, h->d_dof_off, r,
+                       nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref, pr,
+                       evs, js, phibar, ybar, qrbar, part);
+    if (qrbar)
+      hipLaunchKernelGGL(k_ev_vec, dim3(B), dim3(64), 0, s, r, h->d_ptile_first, pr, part, evs,
+                         0, nv, dvbar);
+  };
+  if (h->cfg.precision == ROM_F64) go(double{});
+  else go(float{});
   ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
 }
@@ -697,11 +855,24 @@ rom_status convert_words(const void* src, bool src_f64, void* dst, bool dst_f64,
 }
 
 rom_status adjoint_kernels_prepare() {
-  const int big = (int)(sizeof(double) * kELds);   // bound of event_vjp_shm(r) for every r
-  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_event_vjp<float>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_event_vjp<double>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  // the largest dynamic LDS of each kernel (r = 64, n = 65)
+  constexpr int n = kMaxR + 1;
+  const int big_a = (int)(sizeof(double) * (n * n + std::max(kEVLds + 2 * kEC, 16 * 272)));
+  const int big_c = (int)(sizeof(double) * (kEVLds + kEV));
+  const int big_core = (int)(sizeof(double) * 4 * n * n);
+  static_assert(((kMaxR + 1 + kETI - 1) / kETI) * ((kMaxR + kETJ - 1) / kETJ) <= 272,
+                "tile count bound of the pass A partials");
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_ev_a<float>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, big_a));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_ev_a<double>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, big_a));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_ev_core,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, big_core));
+  const void* chunked[] = {(const void*)k_ev_b<float>, (const void*)k_ev_b<double>,
+                           (const void*)k_ev_c<float>, (const void*)k_ev_c<double>,
+                           (const void*)k_ev_d<float>, (const void*)k_ev_d<double>};
+  for (const void* f : chunked)
+    ROM_HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big_c));
   return ROM_OK;
 }
 

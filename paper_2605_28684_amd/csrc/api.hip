@@ -1040,6 +1040,7 @@ rom_status rom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, int32_
   const size_t o_yb = take(td8), o_qrb = take(td8), o_dvb = take(8 * (size_t)B * h->nv);
   const size_t o_qb = take((size_t)(w + 1) * td8);
   const size_t o_part = take(8 * part_n), o_small = take(8 * small_n);
+  const size_t o_evscr = take(8 * event_vjp_scratch_doubles(h));
   char* ws = nullptr;
   ROM_TRY(alloc(&ws, off));
   PodWs pws;
@@ -1066,6 +1067,7 @@ rom_status rom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, int32_
   double* qb = (double*)(ws + o_qb);
   double* part = (double*)(ws + o_part);
   double* small = (double*)(ws + o_small);
+  double* evscr = (double*)(ws + o_evscr);
   struct Host { int64_t nf, nu, ne; };
   std::vector<Host> hc(nseg + 1);
   auto save = [&](int64_t j) -> rom_status {
@@ -1165,8 +1167,8 @@ rom_status rom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, int32_
       if (e_next >= 0 && after[e_next] == k) {
         const int64_t e = e_next;
         st = launch_event_vjp(h, ev_phi(e), ev_y(e), ev_sold(e), ev_aold(e), ev_u(e), ev_pr(e),
-                              ev_snew(e), abar, phibar, sigbar, ycbar, scr0, scr1, s, qrbar,
-                              dvbar);
+                              ev_snew(e), abar, phibar, sigbar, ycbar, scr0, scr1, evscr, s,
+                              qrbar, dvbar);
         if (st == ROM_OK) st = convert_words(ycbar, true, rhs, f64, td, s);
         if (st == ROM_OK) st = launch_assemble_adjoint(h, ev_y(e), z * c.dt, rhs, s);
         if (st == ROM_OK) st = bt_solve(h, -1, nullptr, out, s);
@@ -1250,8 +1252,9 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
   const size_t state_b = phi_b + y_b + 2 * br;        // Phi, y_corr, sigma, a
   const size_t ev_b = phi_b + y_b + 3 * br + 8 * (size_t)B * n * n + 8 * (size_t)B * (2 * r + 2);
   const size_t td8 = 8 * (size_t)h->total_dof;
+  const size_t evscr_b = 8 * event_vjp_scratch_doubles(h);
   const size_t need = (size_t)(nseg + 1) * state_b + (size_t)S * br + (size_t)E * ev_b +
-                      2 * td8 + 2 * y_b + 1024;
+                      2 * td8 + 2 * y_b + evscr_b + 1024;
   char* ws = nullptr;
   ROM_TRY(alloc(&ws, need));
   struct Host { int64_t nf, nu, ne; };
@@ -1263,6 +1266,7 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
   double* scr1 = scr0 + h->total_dof;
   char* rhs = (char*)(scr1 + h->total_dof);
   char* out = rhs + y_b;
+  double* evscr = (double*)(((uintptr_t)(out + y_b) + 7) & ~(uintptr_t)7);
   auto save = [&](int64_t j) -> rom_status {
     char* p = ck + (size_t)j * state_b;
     ROM_TRY(copy_words(h->Phi, p, phi_b, s));
@@ -1337,7 +1341,7 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
       if (e_next >= 0 && after[e_next] == k) {
         const int64_t e = e_next;
         st = launch_event_vjp(h, ev_phi(e), ev_y(e), ev_sold(e), ev_aold(e), ev_u(e), ev_pr(e),
-                              ev_snew(e), abar, phibar, sigbar, ycbar, scr0, scr1, s);
+                              ev_snew(e), abar, phibar, sigbar, ycbar, scr0, scr1, evscr, s);
         // coarse step y_new = BE(y_prev) over z dt: ybar <- J_r(y_new)^-T ybar
         if (st == ROM_OK) st = convert_words(ycbar, true, rhs, f64, h->total_dof, s);
         if (st == ROM_OK) st = launch_assemble_adjoint(h, ev_y(e), z * c.dt, rhs, s);

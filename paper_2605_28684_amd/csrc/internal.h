@@ -248,7 +248,10 @@ rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new
                             const double* sig_old, const double* a_old, const double* ubar,
                             const double* pr, const double* sig_new, double* abar,
                             double* phibar, double* sigbar, double* ybar, double* qs, double* js,
-                            hipStream_t s, double* qrbar = nullptr, double* dvbar = nullptr);
+                            double* evscr, hipStream_t s, double* qrbar = nullptr,
+                            double* dvbar = nullptr);
+// doubles of the event adjoint's scratch (per-tile partials, per-instance vectors)
+size_t event_vjp_scratch_doubles(const rom_batch* h);
 rom_status convert_words(const void* src, bool src_f64, void* dst, bool dst_f64, int64_t n,
                          hipStream_t s);
 rom_status adjoint_kernels_prepare();

@@ -722,6 +722,159 @@ __global__ __launch_bounds__(256) void k_rotate(const Tile* __restrict__ tiles,
   }
 }
 
+// The same projection and rotation for narrow matrices (k, kin, kout <= 16):
+// one row per thread with the row and its sums in registers, so every lane
+// works (the generic kernels above keep one lane per column).  Rows of a tile
+// are visited in the same order by every launch, and the per-column sums are
+// reduced by wavefront shuffles and then over the block's waves in order.
+constexpr int kNarrow = 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_project_small(const Tile* __restrict__ tiles,
+                                                       const int64_t* __restrict__ dof_off,
+                                                       const T* __restrict__ Phi, int ld, int k,
+                                                       const T* __restrict__ y,
+                                                       const T* __restrict__ qref,
+                                                       const double* __restrict__ dvar, int nv,
+                                                       const double* __restrict__ p1, int ldp,
+                                                       int mode, double* __restrict__ part,
+                                                       double* __restrict__ q1out) {
+  __shared__ double red[4][kNarrow + 1];
+  __shared__ double sp[kNarrow];
+  __shared__ T sIn[256 * kNarrow];   // the chunk's rows, loaded contiguously
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst, tid = threadIdx.x;
+  const int64_t base = dof_off[b];
+  const double* dv = dvar ? dvar + (size_t)b * nv : nullptr;
+  if (mode == 2 && tid < k) sp[tid] = p1[(size_t)b * ldp + tid];
+  double acc[kNarrow + 1];
+#pragma unroll
+  for (int c = 0; c <= kNarrow; ++c) acc[c] = 0.0;
+  for (int64_t r0 = 0; r0 < t.ncell; r0 += 256) {
+    const int nr = (int)(t.ncell - r0 < 256 ? t.ncell - r0 : 256);
+    const int64_t g0 = base + t.cell0 + r0;
+    __syncthreads();
+    {
+      T v[kNarrow];   // all loads of the chunk in flight before the LDS writes
+#pragma unroll
+      for (int u = 0; u < kNarrow; ++u) {
+        const int e = u * 256 + tid;
+        if (e < nr * k) {
+          const int rr = e / k;
+          v[u] = Phi[(g0 + rr) * ld + (e - rr * k)];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kNarrow; ++u)
+        if (u * 256 + tid < nr * k) sIn[u * 256 + tid] = v[u];
+    }
+    __syncthreads();
+    if (tid < nr) {
+      const int64_t lr = t.cell0 + r0 + tid, g = g0 + tid;
+      double row[kNarrow];
+#pragma unroll
+      for (int c = 0; c < kNarrow; ++c) row[c] = c < k ? (double)sIn[tid * k + c] : 0.0;
+      double yv = qref ? yhat_of(y, qref, dv, nv, g, lr) : (double)y[g];
+      if (mode == 2) {
+        double d = 0.0;
+#pragma unroll
+        for (int c = 0; c < kNarrow; ++c)
+          if (c < k) d += row[c] * sp[c];
+        yv -= d;
+        if (q1out) q1out[g] = yv;
+      }
+#pragma unroll
+      for (int c = 0; c < kNarrow; ++c)
+        if (c < k) acc[c] += row[c] * yv;
+      acc[kNarrow] += yv * yv;
+    }
+  }
+  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int c = 0; c <= kNarrow; ++c) {
+    double v = acc[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[wv][c] = v;
+  }
+  __syncthreads();
+  double* out = part + (size_t)blockIdx.x * kPst;
+  if (tid < k) out[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+  if (tid == 0)
+    out[k] = red[0][kNarrow] + red[1][kNarrow] + red[2][kNarrow] + red[3][kNarrow];
+}
+
+// mode 0: out_row = in_row U; mode 1: out_row = [in_row, s_row] U with
+// s_row = (q1_row - in_row . p2) / rho (the new direction).  Rows are dense
+// (ld_in = kin, ld_out = kout); a chunk of 256 rows is loaded contiguously,
+// rotated one row per thread, and stored contiguously, all of its loads
+// before any of its stores, so Phi_in may equal Phi_out.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rotate_small(const Tile* __restrict__ tiles,
+                                                      const int64_t* __restrict__ dof_off,
+                                                      const T* Phi_in, int kin, T* Phi_out,
+                                                      int kout, const double* __restrict__ U,
+                                                      int ldu, size_t ustride, int mode,
+                                                      const double* __restrict__ q1,
+                                                      const double* __restrict__ pr, int ldpr,
+                                                      const int32_t* __restrict__ enable) {
+  __shared__ double sU[(kNarrow + 1) * kNarrow];
+  __shared__ double sp[2 * kNarrow + 1];
+  __shared__ T sIn[256 * kNarrow];
+  __shared__ T sOut[256 * kNarrow];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  if (enable && !enable[b]) return;
+  const int tid = threadIdx.x;
+  const int64_t base = dof_off[b];
+  const double* Ub = U + (size_t)b * ustride;
+  const int krow = mode == 1 ? kin + 1 : kin;
+  for (int e = tid; e < krow * kout; e += blockDim.x) {
+    const int c = e / kout, j = e % kout;
+    sU[c * kNarrow + j] = Ub[c * ldu + j];
+  }
+  if (mode == 1)
+    for (int c = tid; c <= 2 * kin; c += blockDim.x) sp[c] = pr[(size_t)b * ldpr + c];
+  for (int64_t r0 = 0; r0 < t.ncell; r0 += 256) {
+    const int nr = (int)(t.ncell - r0 < 256 ? t.ncell - r0 : 256);
+    const int64_t g0 = base + t.cell0 + r0;
+    __syncthreads();
+    {
+      T v[kNarrow];   // all loads of the chunk in flight before the LDS writes
+#pragma unroll
+      for (int u = 0; u < kNarrow; ++u)
+        if (u * 256 + tid < nr * kin) v[u] = Phi_in[g0 * kin + u * 256 + tid];
+#pragma unroll
+      for (int u = 0; u < kNarrow; ++u)
+        if (u * 256 + tid < nr * kin) sIn[u * 256 + tid] = v[u];
+    }
+    __syncthreads();
+    if (tid < nr) {
+      double row[kNarrow];
+#pragma unroll
+      for (int c = 0; c < kNarrow; ++c) row[c] = c < kin ? (double)sIn[tid * kin + c] : 0.0;
+      double sv = 0.0;
+      if (mode == 1) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < kNarrow; ++c)
+          if (c < kin) d2 += row[c] * sp[kin + c];
+        sv = (q1[g0 + tid] - d2) * sp[2 * kin];
+      }
+#pragma unroll 1
+      for (int j = 0; j < kout; ++j) {
+        double acc = mode == 1 ? sv * sU[kin * kNarrow + j] : 0.0;
+#pragma unroll
+        for (int c = 0; c < kNarrow; ++c)
+          if (c < kin) acc += row[c] * sU[c * kNarrow + j];
+        sOut[tid * kout + j] = (T)acc;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < nr * kout; e += 256) Phi_out[g0 * kout + e] = sOut[e];
+  }
+}
+
 // Gram partials G = Phi^T Phi per tile (FP64), lane j accumulates column j.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gram(const Tile* __restrict__ tiles,
@@ -1066,13 +1219,34 @@ __global__ void k_dvar(const int* __restrict__ tfirst, const double* __restrict_
   dvar[(size_t)b * nv + v] = phi == 0.0 ? 1.0 : 1.0 / phi;
 }
 
+// Phi_out = [Phi_in (, new direction)] U over the pass tiles: the narrow kernel
+// when every dimension fits in registers, the generic one otherwise
+template <typename T>
+void rotate_t(rom_batch* h, const T* Phi_in, int ld_in, int kin, T* Phi_out, int ld_out, int kout,
+              const double* U, int ldu, size_t ustride, int mode, const double* q1,
+              const double* pr, int ldpr, const int32_t* enable, hipStream_t s) {
+  if (kin <= kNarrow && kout <= kNarrow && ld_in == kin && ld_out == kout)
+    hipLaunchKernelGGL((k_rotate_small<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                       h->d_dof_off, Phi_in, kin, Phi_out, kout, U, ldu, ustride, mode, q1, pr,
+                       ldpr, enable);
+  else
+    hipLaunchKernelGGL((k_rotate<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                       h->d_dof_off, Phi_in, ld_in, kin, Phi_out, ld_out, kout, U, ldu, ustride,
+                       mode, q1, pr, ldpr, enable);
+}
+
 template <typename T>
 rom_status project_t(rom_batch* h, const void* Phi, int ld, int k, const void* y, const void* qref,
                      const double* p1, int ldp, int mode, double* dst, int ldd, hipStream_t s,
                      double* q1out = nullptr) {
-  hipLaunchKernelGGL((k_project<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
-                     h->d_dof_off, (const T*)Phi, ld, k, (const T*)y, (const T*)qref, h->d_var,
-                     h->nv, p1, ldp, mode, h->part, q1out);
+  if (k <= kNarrow)
+    hipLaunchKernelGGL((k_project_small<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                       h->d_dof_off, (const T*)Phi, ld, k, (const T*)y, (const T*)qref, h->d_var,
+                       h->nv, p1, ldp, mode, h->part, q1out);
+  else
+    hipLaunchKernelGGL((k_project<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+                       h->d_dof_off, (const T*)Phi, ld, k, (const T*)y, (const T*)qref, h->d_var,
+                       h->nv, p1, ldp, mode, h->part, q1out);
   hipLaunchKernelGGL(k_reduce_tiles, dim3(h->cfg.n_inst), dim3(128), 0, s, h->d_ptile_first,
                      h->part, k, dst, ldd);
   return ROM_OK;
@@ -1129,9 +1303,8 @@ rom_status isvd_apply_t(rom_batch* h, hipStream_t s) {
   double* pr = h->rstate;
   hipLaunchKernelGGL(k_isvd_transfer, dim3(B), dim3(64), 0, s, r, h->ubar, h->a);
   if (mfma_ok(h)) return launch_rotate_mfma(h, pr, h->Phi, s);
-  hipLaunchKernelGGL((k_rotate<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
-                     h->d_dof_off, (const T*)h->Phi, r, r, (T*)h->Phi, r, r, h->ubar, n,
-                     (size_t)n * n, 1, h->qtmp, pr, 2 * r + 2, nullptr);
+  rotate_t<T>(h, (const T*)h->Phi, r, r, (T*)h->Phi, r, r, h->ubar, n, (size_t)n * n, 1,
+              h->qtmp, pr, 2 * r + 2, nullptr, s);
   ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
 }
@@ -1150,9 +1323,8 @@ rom_status reorth_t(rom_batch* h, hipStream_t s) {
                      (const T*)h->Phi, r, h->part);
   hipLaunchKernelGGL(k_reorth_decide, dim3(B), dim3(256), 0, s, h->d_ptile_first, h->part, r,
                      h->cfg.tau_orth, h->lmat, h->a, h->active, h->flags);
-  hipLaunchKernelGGL((k_rotate<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
-                     h->d_dof_off, (const T*)h->Phi, r, r, (T*)h->Phi, r, r, h->lmat, r,
-                     (size_t)r * r, 0, nullptr, nullptr, 0, h->active);
+  rotate_t<T>(h, (const T*)h->Phi, r, r, (T*)h->Phi, r, r, h->lmat, r, (size_t)r * r, 0,
+              nullptr, nullptr, 0, h->active, s);
   ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
 }
@@ -1242,9 +1414,8 @@ rom_status pod_core_t(rom_batch* h, const void* cols, int w, bool pre, bool svd,
   }
   const size_t shm = sizeof(double) * (2 * w * w + 2 * w) + sizeof(int) * w;
   hipLaunchKernelGGL(k_pod_svd, dim3(B), dim3(64), shm, s, w, r, R, U, sigma_out, 1);
-  hipLaunchKernelGGL((k_rotate<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
-                     h->d_dof_off, (const T*)Q, w, w, (T*)phi_out, r, r, U, w, (size_t)w * w, 0,
-                     nullptr, nullptr, 0, nullptr);
+  rotate_t<T>(h, (const T*)Q, w, w, (T*)phi_out, r, r, U, w, (size_t)w * w, 0, nullptr,
+              nullptr, 0, nullptr, s);
   ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
 }
