@@ -6,7 +6,8 @@
 // Method: recursive Schur complement on part separators.  Each instance is cut
 // into parts of m consecutive cells whose last cell is a separator.  One thread
 // eliminates the m-1 interior cells of its part by block Thomas, expressing
-// them as x_j = g_j - V_j x_{sep left} - W_j x_{sep right}.  Substituting the
+// them as x_j = g_j - V_j x_{sep left} - W_j x_{sep right} (the first interior
+// cell's expression is accumulated during the same forward sweep).  Substituting the
 // first/last interior expressions into the separator rows gives a system of the
 // same block-tridiagonal (cyclic) form over the separators, which is solved the
 // same way until one cell per instance remains; back-substitution then walks the
@@ -126,8 +127,12 @@ __global__ __launch_bounds__(256) void k_bt_factor(int n_inst, const int64_t* __
   const int64_t len = s - first;  // interior cells
   if (len <= 0) return;
   const int64_t base = cell_off[b];
-  T Ch[NN], Vh[NN], gh[NV], Bt[NN], Bi[NN], tmp[NN], tv[NV];
+  T Ch[NN], Vh[NN], gh[NV], Bt[NN], Bi[NN], tmp[NN], tv[NV], Pm[NN], ga[NV], Va[NN];
   bool ok = true;
+#pragma unroll
+  for (int e = 0; e < NN; ++e) { Pm[e] = (e % (NV + 1)) == 0 ? T(1) : T(0); Va[e] = T(0); }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ga[v] = T(0);
   for (int64_t j = first; j < s; ++j) {
     const T* S = sys + (base + j) * L::SYS;
     const T* A = S;
@@ -160,33 +165,28 @@ __global__ __launch_bounds__(256) void k_bt_factor(int n_inst, const int64_t* __
     for (int e = 0; e < NN; ++e) { F[e] = Ch[e]; F[NN + e] = Vh[e]; }
 #pragma unroll
     for (int v = 0; v < NV; ++v) F[2 * NN + v] = gh[v];
+    // the first interior cell's expression, accumulated on the way forward:
+    // x_first = sum_j P_j (ghat_j - Vhat_j x_L) + P_len x_R with P_0 = I and
+    // P_{j+1} = -P_j Chat_j (Chat of the last interior cell is What_last)
+    mv<T, NV>(Pm, gh, tv);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ga[v] += tv[v];
+    mm<T, NV>(Pm, Vh, tmp);
+#pragma unroll
+    for (int e = 0; e < NN; ++e) Va[e] += tmp[e];
+    mm<T, NV>(Pm, Ch, tmp);
+#pragma unroll
+    for (int e = 0; e < NN; ++e) Pm[e] = -tmp[e];
   }
-  // last interior: Ch holds What_last; backward pass for the first interior cell
-  T g[NV], V[NN], W[NN];
-#pragma unroll
-  for (int e = 0; e < NN; ++e) { V[e] = Vh[e]; W[e] = Ch[e]; }
-#pragma unroll
-  for (int v = 0; v < NV; ++v) g[v] = gh[v];
   T* Pp = prt + (part_off[b] + k) * L::PRT;
 #pragma unroll
-  for (int e = 0; e < NN; ++e) Pp[e] = Ch[e];
-  for (int64_t j = s - 2; j >= first; --j) {
-    const T* F = fwd + (base + j) * L::FWD;
-    // g = ghat_j - Chat_j g ; V = Vhat_j - Chat_j V ; W = -Chat_j W
-    mv<T, NV>(F, g, tv);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) g[v] = F[2 * NN + v] - tv[v];
-    mm<T, NV>(F, V, tmp);
-#pragma unroll
-    for (int e = 0; e < NN; ++e) V[e] = F[NN + e] - tmp[e];
-    mm<T, NV>(F, W, tmp);
-#pragma unroll
-    for (int e = 0; e < NN; ++e) W[e] = -tmp[e];
+  for (int e = 0; e < NN; ++e) {
+    Pp[e] = Ch[e];            // What_last
+    Pp[NN + e] = Va[e];       // V_first
+    Pp[2 * NN + e] = -Pm[e];  // W_first
   }
 #pragma unroll
-  for (int e = 0; e < NN; ++e) { Pp[NN + e] = V[e]; Pp[2 * NN + e] = W[e]; }
-#pragma unroll
-  for (int v = 0; v < NV; ++v) Pp[3 * NN + v] = g[v];
+  for (int v = 0; v < NV; ++v) Pp[3 * NN + v] = ga[v];   // g_first
   if (!ok) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
 }
 
@@ -491,7 +491,7 @@ __global__ __launch_bounds__(256) void k_bt_back(int n_inst, const int64_t* __re
   const int64_t first = k * m;
   const int64_t s = (first + m < n ? first + m : n) - 1;
   T xl[NV], xr[NV], xn[NV], tv[NV], tw[NV];
-  const int64_t kl = (k + P - 1) % P;
+  const int64_t kl = k == 0 ? P - 1 : k - 1;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     xl[v] = xs[(next_off[b] + kl) * NV + v];
@@ -586,12 +586,12 @@ rom_status bt_solve_t(rom_batch* h, int it, void* upd, void* out, hipStream_t s)
       // the plain solve writes the solution in the state layout (cell-major == level-0 layout
       // only when offsets coincide, which holds because level 0 uses the DOF ordering)
     }
+    uint64_t* dn = (last && it >= 0)
+                       ? h->norms + (size_t)(2 * (h->cfg.newton_max + 1) + it) * B
+                       : nullptr;
     hipLaunchKernelGGL((k_bt_back<T, NV>), dim3(nb), dim3(256), 0, s, B, lv.d_cell_off,
-                       lv.d_part_off, h->bt_m, (const T*)lv.fwd, (const T*)lv.part, nx.d_cell_off,
-                       (const T*)nx.x, xout, h->d_dof_off, (T*)upd, mode, act,
-                       (last && it >= 0)
-                           ? h->norms + (size_t)(2 * (h->cfg.newton_max + 1) + it) * B
-                           : nullptr);
+                       lv.d_part_off, h->bt_m, (const T*)lv.fwd, (const T*)lv.part,
+                       nx.d_cell_off, (const T*)nx.x, xout, h->d_dof_off, (T*)upd, mode, act, dn);
   }
   (void)sizeof(L);
   ROM_HIP_CHECK(hipGetLastError());
