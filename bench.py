@@ -207,10 +207,14 @@ def config_measurements(torch, W, R):
         ms_coarse = _timed(torch, lambda: h.fom_step(y, w.z * w.dt, out=y2), 3)
         ms_isvd = _timed(torch, lambda: h.isvd_update(y2), 3)
         ms_rebuild = _timed(torch, lambda: h.rom_rebuild(), 3)
+        split_choice = h.autotune(R.TUNE_DEIM_PASS)
+        ms_rebuild_tuned = _timed(torch, lambda: h.rom_rebuild(), 3)
+        h.set_tuning(R.TUNE_DEIM_PASS, 0)
         out["C3_sod_hllc_65536_f32"] = dict(
             ms_per_window=round(ms_win, 4), steps_per_s=w.z / (ms_win * 1e-3),
             event_split_ms=dict(coarse_step=round(ms_coarse, 4), isvd_update=round(ms_isvd, 4),
-                                deim_rebuild=round(ms_rebuild, 4)))
+                                deim_rebuild=round(ms_rebuild, 4)),
+            deim_pass_tuned=dict(choice=split_choice, rebuild_ms=round(ms_rebuild_tuned, 4)))
         h.close()
         # C5
         w = W.react10_f32()
@@ -236,12 +240,17 @@ def config_measurements(torch, W, R):
         q = q0.clone()
         gq = torch.empty_like(q0)
         ms_step = _timed(torch, lambda: h.fom_step(q, w.dt, out=q), 5)
+        # the solver part size chosen by timing (candidate 0 is the default above)
+        part_choice = h.autotune(R.TUNE_BT_PART, q0)
+        ms_step_tuned = _timed(torch, lambda: h.fom_step(q, w.dt, out=q), 5)
+        h.set_tuning(R.TUNE_BT_PART, 0)
         n_steps, n_ckpt = 16, 4
         ms_vjp = _timed(torch, lambda: h.fom_rollout_vjp(q0, n_steps, w.dt, gbar, n_ckpt=n_ckpt,
                                                      out=gq), 2)
         cells = sum(w.n_cells)
         out["C4_euler_rusanov_64x262144_f32"] = dict(
             fom_step_ms=round(ms_step, 4), fom_step_cell_updates_per_s=cells / (ms_step * 1e-3),
+            fom_step_tuned_part_choice=part_choice, fom_step_tuned_ms=round(ms_step_tuned, 4),
             rollout_vjp_ms_per_step=round(ms_vjp / n_steps, 4),
             rollout_vjp_steps=n_steps, rollout_vjp_checkpoints=n_ckpt,
             note="backward-Euler Newton steps at dt = 0.064/N; the adjoint call runs the "

@@ -421,24 +421,40 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
                           void* stream);
 
 /*
- * Autotuning of launch shapes.  Only shapes that cannot change results are
- * tuned: for ROM_TUNE_RESIDUAL, the streaming residual of the Euler problems
- * (fom_residual, and the residual evaluations inside the grid-wide Newton
- * step) can use tiles of 1024, 512 or 256 cells (4, 2 or 1 cells per thread),
- * a persistent grid of 1..12 resident blocks per compute unit and plain or
- * non-temporal loads and stores of the streamed state; every cell is
- * computed by the same arithmetic in every shape, so outputs are bitwise
- * identical.  Other problems have a single candidate.
+ * Autotuning of launch shapes and solver settings, per handle.
+ *   ROM_TUNE_RESIDUAL  the streaming residual of the Euler problems
+ *       (fom_residual, and the residual evaluations inside the grid-wide
+ *       Newton step): tiles of 1024, 512 or 256 cells (4, 2 or 1 cells per
+ *       thread), a persistent grid of 1..12 resident blocks per compute unit,
+ *       plain or non-temporal loads and stores of the streamed state.  Every
+ *       cell is computed by the same arithmetic in every shape: outputs are
+ *       bitwise identical.  Other problems have a single candidate.
+ *   ROM_TUNE_DEIM_PASS the greedy DEIM pass (hyper = ROM_HR_DEIM): 4, 2 or 8
+ *       candidate rows per 2048-row pass tile.  The argmax over all
+ *       candidates takes the same row (lowest index on ties): P and
+ *       (P^T Phi)^+ are bitwise identical.  One candidate without DEIM.
+ *   ROM_TUNE_BT_PART   the part size m of the block-tridiagonal solver of
+ *       the backward-Euler steps (the separator spacing of its recursive
+ *       Schur complement): 16, 8 or 32 cells for 1- and 3-variable blocks (a
+ *       single candidate, 8, for 12-variable blocks).  Every candidate solves
+ *       the same system exactly in exact arithmetic; results differ at the
+ *       level of rounding.  Changing it re-creates the solver's levels and
+ *       drops captured window graphs.
+ *   Candidate 0 of each target is the default.
  *
- * rom_autotune - time every candidate on the given stream (2 warm-up and 5
- *   timed residual evaluations of q each, HIP events) and keep the fastest for
- *   the handle; *choice (optional) receives its index.  q: device
- *   T[total_dof]; the handle's state is not modified.  Synchronises the stream.
+ * rom_autotune - time every candidate on the given stream and keep the
+ *   fastest for the handle; *choice (optional) receives its index.
+ *   RESIDUAL: 2 warm-up and 5 timed residual evaluations of q; DEIM_PASS:
+ *   1 warm-up and 3 timed rebuilds (needs a reduced state; q unused, may be
+ *   NULL); BT_PART: 1 warm-up and 3 timed backward-Euler steps from q with
+ *   the configured dt.  q: device T[total_dof].  The handle's state is not
+ *   modified.  Synchronises the stream.
  * rom_set_tuning - force candidate `choice` (choice < 0 only queries);
  *   *n_candidates (optional) receives the number of candidates.
- * Errors: ROM_E_INVAL (NULL handle or q, unknown target, choice out of range).
+ * Errors: ROM_E_INVAL (NULL handle, NULL q where it is used, unknown target,
+ * choice out of range), ROM_E_STATE (DEIM_PASS without a reduced state).
  */
-enum { ROM_TUNE_RESIDUAL = 0 };
+enum { ROM_TUNE_RESIDUAL = 0, ROM_TUNE_DEIM_PASS = 1, ROM_TUNE_BT_PART = 2 };
 rom_status rom_autotune(rom_handle h, int32_t what, const void* q, int32_t* choice, void* stream);
 rom_status rom_set_tuning(rom_handle h, int32_t what, int32_t choice, int32_t* n_candidates);
 

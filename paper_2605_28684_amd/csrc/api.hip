@@ -1372,22 +1372,37 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
 
 rom_status rom_autotune(rom_handle h, int32_t what, const void* q, int32_t* choice,
                         void* stream) {
-  ROM_REQUIRE(h && q, ROM_E_INVAL, "handle and q are required");
-  ROM_REQUIRE(what == ROM_TUNE_RESIDUAL, ROM_E_INVAL, "unknown tuning target");
+  ROM_REQUIRE(h, ROM_E_INVAL, "handle is required");
+  ROM_REQUIRE(what >= ROM_TUNE_RESIDUAL && what <= ROM_TUNE_BT_PART, ROM_E_INVAL,
+              "unknown tuning target");
+  ROM_REQUIRE(q || what == ROM_TUNE_DEIM_PASS, ROM_E_INVAL, "q is required for this target");
+  if (what == ROM_TUNE_DEIM_PASS)
+    ROM_REQUIRE(h->has_rom, ROM_E_STATE, "the DEIM pass needs a reduced state");
   hipStream_t s = (hipStream_t)stream;
   h->last_stream = s;
-  const int n = residual_shape_count(h);
+  int n = 0;
+  ROM_TRY(rom_set_tuning(h, what, -1, &n));
   int best = 0;
   if (n > 1) {
     hipEvent_t e0, e1;
     ROM_HIP_CHECK(hipEventCreate(&e0));
     ROM_HIP_CHECK(hipEventCreate(&e1));
+    const int warm = what == ROM_TUNE_RESIDUAL ? 2 : 1, reps = what == ROM_TUNE_RESIDUAL ? 5 : 3;
+    auto run = [&]() -> rom_status {
+      switch (what) {
+        case ROM_TUNE_RESIDUAL: return launch_residual(h, q, nullptr, 0.0, h->vjp_tmp, s);
+        case ROM_TUNE_DEIM_PASS: return launch_rebuild(h, s);
+        default: return fom_step_impl(h, q, h->cfg.dt, h->fq_prev, nullptr, s);
+      }
+    };
     float tbest = 0.f;
-    for (int i = 0; i < n; ++i) {
-      h->tune_residual = i;
-      for (int w = 0; w < 2; ++w) ROM_TRY(launch_residual(h, q, nullptr, 0.0, h->vjp_tmp, s));
+    rom_status st = ROM_OK;
+    for (int i = 0; i < n && st == ROM_OK; ++i) {
+      st = rom_set_tuning(h, what, i, nullptr);
+      for (int w = 0; w < warm && st == ROM_OK; ++w) st = run();
+      if (st != ROM_OK) break;
       ROM_HIP_CHECK(hipEventRecord(e0, s));
-      for (int k = 0; k < 5; ++k) ROM_TRY(launch_residual(h, q, nullptr, 0.0, h->vjp_tmp, s));
+      for (int k = 0; k < reps && st == ROM_OK; ++k) st = run();
       ROM_HIP_CHECK(hipEventRecord(e1, s));
       ROM_HIP_CHECK(hipEventSynchronize(e1));
       float t = 0.f;
@@ -1396,20 +1411,48 @@ rom_status rom_autotune(rom_handle h, int32_t what, const void* q, int32_t* choi
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    ROM_TRY(st);
   }
-  h->tune_residual = best;
+  ROM_TRY(rom_set_tuning(h, what, best, nullptr));
   if (choice) *choice = best;
   return ROM_OK;
 }
 
 rom_status rom_set_tuning(rom_handle h, int32_t what, int32_t choice, int32_t* n_candidates) {
   ROM_REQUIRE(h, ROM_E_INVAL, "handle is required");
-  ROM_REQUIRE(what == ROM_TUNE_RESIDUAL, ROM_E_INVAL, "unknown tuning target");
-  const int n = residual_shape_count(h);
+  ROM_REQUIRE(what >= ROM_TUNE_RESIDUAL && what <= ROM_TUNE_BT_PART, ROM_E_INVAL,
+              "unknown tuning target");
+  static const int kSplits[] = {4, 2, 8};
+  int parts[4] = {0, 0, 0, 0};
+  int n = 1;
+  if (what == ROM_TUNE_RESIDUAL) n = residual_shape_count(h);
+  else if (what == ROM_TUNE_DEIM_PASS) n = h->cfg.hyper == ROM_HR_DEIM ? 3 : 1;
+  else n = bt_part_candidates(h->nv, parts);
   if (n_candidates) *n_candidates = n;
   if (choice < 0) return ROM_OK;  // query only
   ROM_REQUIRE(choice < n, ROM_E_INVAL, "tuning choice out of range");
-  h->tune_residual = choice;
+  if (what == ROM_TUNE_RESIDUAL) {
+    h->tune_residual = choice;
+  } else if (what == ROM_TUNE_DEIM_PASS) {
+    if (h->cfg.hyper == ROM_HR_DEIM && h->deim_split != kSplits[choice]) {
+      // captured windows hold the split as a launch argument
+      ROM_HIP_CHECK(hipStreamSynchronize(h->last_stream));
+      for (auto& g : h->win_exec)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+      h->deim_split = kSplits[choice];
+    }
+  } else if (parts[choice] != h->bt_m) {
+    // the solver's levels depend on the part size: re-create them (captured
+    // windows refer to the old ones)
+    ROM_HIP_CHECK(hipStreamSynchronize(h->last_stream));
+    ROM_HIP_CHECK(hipDeviceSynchronize());
+    for (auto& g : h->win_exec)
+      if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    bt_free(h);
+    h->bt_m_req = parts[choice];
+    ROM_TRY(bt_setup(h));
+    ROM_HIP_CHECK(hipDeviceSynchronize());
+  }
   return ROM_OK;
 }
 

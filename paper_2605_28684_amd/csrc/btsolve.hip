@@ -600,12 +600,23 @@ rom_status bt_solve_t(rom_batch* h, int it, void* upd, void* out, hipStream_t s)
 
 }  // namespace
 
+int bt_part_candidates(int nv, int* out) {
+  if (nv >= 8) {   // the 16-lane row elimination of the 12-variable blocks uses 8
+    out[0] = 8;
+    return 1;
+  }
+  out[0] = 16;
+  out[1] = 8;
+  out[2] = 32;
+  return 3;
+}
+
 rom_status bt_setup(rom_batch* h) {
   const int B = h->cfg.n_inst;
   const size_t es = h->esz;
   const int NV = h->nv;
   const int NN = NV * NV;
-  const int pm = h->bt_m = bt_part_size(NV);
+  const int pm = h->bt_m = h->bt_m_req > 0 ? h->bt_m_req : bt_part_size(NV);
   std::vector<int64_t> n(h->n_cells);
   h->levels.clear();
   while (true) {

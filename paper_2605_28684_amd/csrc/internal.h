@@ -116,6 +116,8 @@ struct rom_batch {
   int n_cu = 256;                    // compute units of the device
   int device = 0;                    // HIP device the handle was created on
   int tune_residual = 0;             // chosen launch shape of the streaming residual
+  int deim_split = 4;                // candidate rows per pass tile of the greedy DEIM pass
+  int bt_m_req = 0;                  // requested solver part size (0: the default)
   romhip::Tile* d_ptiles = nullptr;  // row tiles of kPassRows basis rows
   int n_ptiles = 0;
   std::vector<int> ptile_first;      // first row tile of each instance [n_inst+1]
@@ -219,6 +221,8 @@ rom_status launch_assemble_adjoint(rom_batch* h, const void* q, double dt, const
 
 // ---- btsolve.hip
 rom_status bt_setup(rom_batch* h);
+// part sizes the solver can use for nv-variable blocks (the first is the default)
+int bt_part_candidates(int nv, int* out);
 void bt_free(rom_batch* h);
 // solve the level-0 system; it >= 0: Newton mode (skip inactive instances,
 // converge check against norms[it]; add solution into q); it < 0: plain solve into out

@@ -1521,9 +1521,8 @@ rom_status rebuild_t(rom_batch* h, hipStream_t s) {
   hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, s, h->d_epoch);
   hipLaunchKernelGGL((k_cols_transpose<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                      h->d_dof_off, (const T*)h->Phi, r, (T*)h->phi_cm);
-  // four candidates per pass tile (512 rows per block, 2 per thread)
-  constexpr int S = 4;
-  static_assert(S * 2 <= kMaxR * kMaxR, "tile candidates must fit the partials buffer");
+  // S candidates per pass tile (the tuned split; 4 by default: 512 rows per block)
+  const int S = h->deim_split;
   double* tval = h->part;
   int64_t* tidx = (int64_t*)(h->part + (size_t)S * h->n_ptiles);
   double* coef = h->rstate;  // per instance kMaxR coefficients

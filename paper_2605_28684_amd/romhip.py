@@ -106,7 +106,7 @@ SYMBOLS = ("rom_create", "rom_destroy", "fom_residual", "fom_step", "isvd_update
            "fom_residual_vjp", "fom_step_vjp", "fom_rollout_vjp", "fom_rollout_vjp_noalloc",
            "rom_online_vjp", "rom_offline", "rom_rollout_vjp", "rom_autotune",
            "rom_set_tuning", "rom_query", "rom_profile", "rom_last_error")
-TUNE_RESIDUAL = 0
+TUNE_RESIDUAL, TUNE_DEIM_PASS, TUNE_BT_PART = 0, 1, 2
 PROF_RESIDUAL, PROF_GALERKIN_PASS, PROF_ISVD_PROJECT, PROF_RESIDUAL_VJP, PROF_FOM_STEP = range(5)
 
 
@@ -321,10 +321,11 @@ class RomBatch:
         """Restore a state written by save() (rom_load; synchronises the stream)."""
         _check(LIB.rom_load(self.h, _ptr(blob), ctypes.c_size_t(blob.numel()), _stream()))
 
-    def autotune(self, what, q):
-        """Pick the fastest result-invariant launch shape; returns its index."""
+    def autotune(self, what, q=None):
+        """Pick the fastest candidate of a tuning target; returns its index."""
         c = ctypes.c_int32()
-        _check(LIB.rom_autotune(self.h, int(what), _ptr(q), ctypes.byref(c), _stream()))
+        _check(LIB.rom_autotune(self.h, int(what), _ptr(q) if q is not None else None,
+                                ctypes.byref(c), _stream()))
         return c.value
 
     def set_tuning(self, what, choice):
