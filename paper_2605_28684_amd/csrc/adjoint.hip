@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kAT) void k_online_seed(
 template <typename T>
 __global__ __launch_bounds__(kAT) void k_step_vjp_solve(int r, double dt,
                                                         const int* __restrict__ tfirst,
-                                                        const T* __restrict__ mpart,
+                                                        const T* __restrict__ mpart, int pos32,
                                                         double* __restrict__ abar,
                                                         uint32_t* flags) {
   __shared__ double A[kMaxR * (kMaxR + 1)];
@@ -140,9 +140,10 @@ __global__ __launch_bounds__(kAT) void k_step_vjp_solve(int r, double dt,
   const int ld = r + 1;
   const int t0 = tfirst[b], t1 = tfirst[b + 1];
   for (int e = tid; e < r * r; e += kAT) {
-    double s = 0.0;
-    for (int tt = t0; tt < t1; ++tt) s += (double)mpart[(size_t)tt * kMaxR * kMaxR + e];
     const int i = e / r, j = e % r;
+    const int pe = pos32 ? mpart_pos32(i, j) : e;   // the partials' order (see mpart)
+    double s = 0.0;
+    for (int tt = t0; tt < t1; ++tt) s += (double)mpart[(size_t)tt * kMaxR * kMaxR + pe];
     A[j * ld + i] = (i == j ? 1.0 : 0.0) - dt * s;
   }
   for (int c = tid; c < r; c += kAT) lam[c] = abar[(size_t)b * r + c];
@@ -776,7 +777,8 @@ rom_status launch_step_vjp(rom_batch* h, const void* Phi, const double* a1, doub
   auto go = [&](auto tag) {
     using T = decltype(tag);
     hipLaunchKernelGGL((k_step_vjp_solve<T>), dim3(B), dim3(kAT), 0, s, r, h->cfg.dt,
-                       h->d_ptile_first, (const T*)h->mpart, abar, h->flags);
+                       h->d_ptile_first, (const T*)h->mpart, mfma_ok(h) && r == 32 ? 1 : 0,
+                       abar, h->flags);
     hipLaunchKernelGGL((k_step_vjp_rows<T>), dim3(h->n_ptiles), dim3(kRT), 0, s, h->d_ptiles, r,
                        h->cfg.dt, h->d_dof_off, h->d_phys, h->cfg.n_phys, h->d_var,
                        (const T*)Phi, (const T*)h->q_ref, a1, abar, phibar);

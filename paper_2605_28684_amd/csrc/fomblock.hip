@@ -127,12 +127,14 @@ DEV void newton_row(const Mdl& mdl, T qm, T qc, T qn, T qprev, T dt, T inv, T in
 }
 
 // MM: the largest part length the register arrays hold (N <= 1024 MM).
-// Each Newton iteration sweeps the owned cells three times, recomputing the
+// Each Newton iteration sweeps the owned cells twice, recomputing the
 // Jacobian rows instead of storing them: (i) forward: residual norms, the
-// separator row and the last interior cell's expression in the two
-// separators; (ii) backward: the first interior cell's expression; then the
-// separator system is solved; (iii) forward with the left separator known,
-// keeping (C_j, g_j), and back-substitution from the right separator.
+// separator row, the last interior cell's expression in the two separators
+// and, accumulated along the elimination, the first interior cell's (x_0 =
+// sum_j P_j (g_j - V_j x_left) + P x_right with P_j the product of -C_i over
+// the cells before j); then the separator system is solved; (ii) forward
+// with the left separator known, keeping (C_j, g_j), and back-substitution
+// from the right separator.
 template <class Mdl, typename T, int MM>
 __global__ __launch_bounds__(kFB) void k_fom_newton_block(
     const int64_t* __restrict__ cell_off, const double* __restrict__ phys, int nphys,
@@ -188,6 +190,9 @@ __global__ __launch_bounds__(kFB) void k_fom_newton_block(
     bool rfin = true;
     T As = 0, Bs = 1, Cs = 0, Ds = 0;      // separator row
     T Ch = 0, Vh = 0, gh = 0;              // x_j = gh - Vh x_left - Ch x_{j+1}
+    // the first interior cell in the two separators, accumulated on the way:
+    // x_0 = Ga - Va x_left + Pa x_right with Pa the running product of -Ch
+    T Ga = 0, Va = 0, Pa = 1;
 #pragma unroll
     for (int j = 0; j < MM; ++j) {
       if (j < len) {
@@ -205,6 +210,9 @@ __global__ __launch_bounds__(kFB) void k_fom_newton_block(
           if (j == 0) { gh = Bi * d; Vh = Bi * A; }
           else { gh = Bi * (d - A * gh); Vh = -(Bi * (A * Vh)); }
           Ch = Bi * C;
+          Ga += Pa * gh;
+          Va += Pa * Vh;
+          Pa = -(Pa * Ch);
         }
       }
     }
@@ -216,25 +224,8 @@ __global__ __launch_bounds__(kFB) void k_fom_newton_block(
     if (!conv && sizeof(T) == 4 && it > 0)
       conv = dprev <= 8.0 * 1.1920928955078125e-07 * (1.0 + ynorm);
     if (conv || it == newton_max) break;
-    // (ii) backward sweep: x_j = gr - Ar x_{j-1} - Wr x_right over the
-    //      interior cells, down to the first one
-    T gr = 0, Ar = 0, Wr = 0;
-    if (live && len >= 2) {
-#pragma unroll
-      for (int j = MM - 2; j >= 0; --j) {
-        if (j <= len - 2) {
-          T A, B, C, d;
-          newton_row(mdl, QM(j), q[j], QN(j), qp[j], dt, inv, inv2, A, B, C, d, fl);
-          const T Bt = j < len - 2 ? B - C * Ar : B;
-          if (Bt == T(0)) sing = true;
-          const T Bi = Bt != T(0) ? T(1) / Bt : T(0);
-          if (j == len - 2) { gr = Bi * d; Wr = Bi * C; }
-          else { gr = Bi * (d - C * gr); Wr = -(Bi * (C * Wr)); }
-          Ar = Bi * A;
-        }
-      }
-      sV[tid] = Ar; sW[tid] = Wr; sG[tid] = gr;
-    }
+    // (ii) the first interior cell's expression x_0 = gr - Ar x_left - Wr x_right
+    if (live && len >= 2) { sV[tid] = Va; sW[tid] = -Pa; sG[tid] = Ga; }
     __syncthreads();
     // 4. separator row A x_{s-1} + B x_s + C x_{s+1} = d in the separators:
     //    x_{s-1} = gh - Vh x_left - Ch x_s (forward sweep), and
@@ -247,7 +238,7 @@ __global__ __launch_bounds__(kFB) void k_fom_newton_block(
     __syncthreads();
     if (live) { sa[tid] = al; sb[tid] = be; sc[tid] = ga; sd[tid] = de; }
     if (!cyclic_solve(sa, sb, sc, sd, se, P)) sing = true;
-    // (iii) forward sweep with x_left known, then back-substitution
+    // (ii) forward sweep with x_left known, then back-substitution
     double dmax = 0.0;
     if (live) {
       const T xl = sd[kl], xr = sd[tid];

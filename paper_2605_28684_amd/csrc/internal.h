@@ -41,6 +41,15 @@ constexpr int kPassRows = 2048;     // basis rows per block of the tall-skinny p
 constexpr int kMaxR = 64;           // largest reduced dimension supported
 constexpr int kMaxNs = 2 * kMaxR;   // largest number of DEIM rows
 
+// Position of element (i, j) of one tile's r x r block of Phi^T J_f Phi in the
+// partials the FP32 MFMA pass writes for r = 32.  The single-wave solve keeps
+// row i, columns of parity h, in lane i + 32 h (column j in register j >> 1);
+// this order hands each lane its 16 values as four float4 loads, load u of
+// the wave reading 1 KB contiguous (registers 4u .. 4u + 3 of every lane).
+__host__ __device__ constexpr int mpart_pos32(int i, int j) {
+  return (((j >> 1) >> 2) * 64 + i + 32 * (j & 1)) * 4 + ((j >> 1) & 3);
+}
+
 // A contiguous run of cells of one instance handled by one thread block.
 struct Tile {
   int32_t inst;
@@ -156,7 +165,8 @@ struct rom_batch {
   uint64_t* norms = nullptr; // Newton norms: 3 blocks of (newton_max+1) x n_inst (residual, iterate, update)
   double* rstate = nullptr;  // reduced Newton workspace [n_inst * (r*r + 4r)]
   double* qtmp = nullptr;    // first Gram-Schmidt residual [total_dof] (FP64)
-  void* mpart = nullptr;     // Galerkin block partials of Phi^T J Phi [n_ptiles * kMaxR^2] (T)
+  void* mpart = nullptr;     // Galerkin block partials of Phi^T J Phi [n_ptiles * kMaxR^2] (T;
+                             // mpart_pos32 order when the FP32 MFMA pass wrote them for r = 32)
   double* epart = nullptr;   // projection partials of the event chain [n_ptiles * kMaxR^2]
   int32_t* ev_iters = nullptr; // Newton counters of the event's coarse step [n_inst]
   uint32_t* d_epoch = nullptr; // DEIM epoch counter (device)

@@ -274,7 +274,15 @@ __attribute__((amdgpu_waves_per_eu(RT == 32 ? 4 : 1))) void k_galerkin_mfma(
   for (int c = tid; c < RT; c += NT) L.sa[c] = a[(size_t)b * RT + c];
   galerkin_tile<RT>(t, phys, nphys, Phi, qref, dvar, L);
   float* mo = mpart + (size_t)blockIdx.x * kMaxR * kMaxR;
-  for (int e = tid; e < RT * RT; e += NT) mo[e] = L.redM[e];
+  if (RT == 32) {
+    // in the order of the single-wave solve (mpart_pos32), written contiguously
+    for (int d = tid; d < RT * RT; d += NT) {
+      const int ln = (d >> 2) & 63, jj = 4 * (d >> 8) + (d & 3);
+      mo[d] = L.redM[(ln & 31) * RT + 2 * jj + (ln >> 5)];
+    }
+  } else {
+    for (int e = tid; e < RT * RT; e += NT) mo[e] = L.redM[e];
+  }
   for (int c = tid; c < RT; c += NT) gpart[(size_t)blockIdx.x * kMaxR + c] = L.redG[c];
 }
 
@@ -437,6 +445,91 @@ __global__ __launch_bounds__(256) void k_rotate_mfma(const Tile* __restrict__ ti
   }
 }
 
+// The same rotation for r = 32 with no LDS: since Phi U[:r, :r] + s U[r, :]
+// with s = (q1 - Phi p2) / rho equals Phi U' + (q1 / rho) U[r, :] for
+// U' = U[:r, :r] - p2 U[r, :] / rho, each wave keeps its share of U' in
+// registers (formed once in FP64, rounded to FP32) and feeds the basis rows
+// straight from HBM to the matrix cores.  The MFMA's reduction index (the
+// basis column) is ordered so that lane (c, h) of a 32-row chunk supplies row
+// c, columns 16 h .. 16 h + 15: four float4 loads per lane (the other waves of
+// the SIMD keep memory busy meanwhile; at most 80 registers, so that the
+// fine steps' single-wave solve still finds room beside four of these waves
+// on every SIMD while the rotation runs beside them).  A 17th product adds the
+// rank-one term: lane (c, 0) supplies q1 / rho of row c against U[r, :], lane
+// (c, 1) zero.  dst may be Phi (each wave reads a chunk's rows before it
+// writes them and never touches another wave's rows).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+void k_rotate_mfma_reg(const Tile* __restrict__ tiles,
+                                                         const int64_t* __restrict__ dof_off,
+                                                         const float* Phi, float* dst,
+                                                         const double* __restrict__ U,
+                                                         const double* __restrict__ q1,
+                                                         const double* __restrict__ pr) {
+  constexpr int RT = 32;
+  constexpr int n = RT + 1;   // core size
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int par = lane >> 5, cl = lane & 31;
+  const int64_t base = dof_off[b];
+  const double* Ub = U + (size_t)b * n * n;
+  const double* p2 = pr + (size_t)b * (2 * RT + 2) + RT;
+  const double irho = pr[(size_t)b * (2 * RT + 2) + 2 * RT];
+  // B operands: U'[16 par + s][cl] for s = 0 .. 15, and U[r][cl] for the
+  // rank-one step (lane (c, 1) supplies the zero row)
+  const double ur = Ub[RT * n + cl];
+  float bU[16];
+#pragma unroll
+  for (int s2 = 0; s2 < 16; ++s2) {
+    const int k = 16 * par + s2;
+    bU[s2] = (float)(Ub[k * n + cl] - p2[k] * irho * ur);
+  }
+  const float bR = par == 0 ? (float)ur : 0.f;
+  const int64_t per = ((t.ncell + 4 * kCh - 1) / (4 * kCh)) * kCh;
+  const int64_t lo = wave * per;
+  const int64_t hi = lo + per < t.ncell ? lo + per : t.ncell;
+  if (lo >= hi) return;
+  const float* src = Phi + (base + t.cell0) * RT;
+  const double* q1b = q1 + base + t.cell0;
+  float* out = dst + (base + t.cell0) * RT;
+  // one chunk's operands of this lane: row lo + 32 j + cl, columns 16 par ..
+  auto fetch = [&](int64_t r0, float4 (&v)[4], double& q) {
+    const int64_t row = r0 + cl;
+    if (row < hi) {
+      const float4* p = reinterpret_cast<const float4*>(src + row * RT + 16 * par);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = p[u];
+      q = par == 0 ? q1b[row] : 0.0;
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      q = 0.0;
+    }
+  };
+  for (int64_t r0 = lo; r0 < hi; r0 += kCh) {
+    float4 cur[4];
+    double qc;
+    fetch(r0, cur, qc);
+    f32x16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[u].x, bU[4 * u + 0], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[u].y, bU[4 * u + 1], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[u].z, bU[4 * u + 2], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[u].w, bU[4 * u + 3], acc, 0, 0, 0);
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32((float)(qc * irho), bR, acc, 0, 0, 0);
+    const int nr = (int)(hi - r0 < kCh ? hi - r0 : kCh);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = (v >> 2) * 8 + par * 4 + (v & 3);
+      if (i < nr) out[(r0 + i) * RT + cl] = acc[v];
+    }
+  }
+}
+
 // ------------------------------------------------------------------ projection pass
 // mode 1: part[c] = sum_i Phi_ic y^_i, part[RT] = |y^|^2
 // mode 2: q1_i = y^_i - Phi_i . p1 (stored to q1out); part[c] = sum Phi_ic q1_i, part[RT] = |q1|^2
@@ -541,7 +634,7 @@ rom_status launch_galerkin_tail(rom_batch* h, int it0, hipStream_t s) {
 
 rom_status launch_rotate_mfma(rom_batch* h, const double* pr, void* dst, hipStream_t s) {
   if (h->cfg.r == 32)
-    hipLaunchKernelGGL((k_rotate_mfma<32>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+    hipLaunchKernelGGL(k_rotate_mfma_reg, dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                        h->d_dof_off, (const float*)h->Phi, (float*)dst, h->ubar, h->qtmp, pr);
   else
     hipLaunchKernelGGL((k_rotate_mfma<64>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,

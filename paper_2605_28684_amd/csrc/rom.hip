@@ -199,11 +199,10 @@ __global__ __launch_bounds__(256) void k_galerkin_solve(
   }
 }
 
-// One exchange of a wave max of v: lanes in the rows of ROWMASK combine with
-// the DPP source CTRL, the other lanes keep their own value.  (A compare and
-// select: a NaN never replaces a number, and the maximum of numbers is exact.)
+// The value a DPP move with source CTRL brings to each lane: lanes in the
+// rows of ROWMASK receive it, the other lanes keep their own value.
 template <int CTRL, int ROWMASK>
-DEV double max_dpp(double v) {
+DEV double dpp_move_d(double v) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
   const int lo = (int)(unsigned)u, hi = (int)(unsigned)(u >> 32);
   int olo, ohi;
@@ -214,8 +213,15 @@ DEV double max_dpp(double v) {
     olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
     ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
   }
-  const double o = __builtin_bit_cast(double, ((unsigned long long)(unsigned)ohi << 32) |
-                                                  (unsigned long long)(unsigned)olo);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)ohi << 32) |
+                                        (unsigned long long)(unsigned)olo);
+}
+
+// One exchange of a wave max of v: a compare and select, so a NaN never
+// replaces a number, and the maximum of numbers is exact.
+template <int CTRL, int ROWMASK>
+DEV double max_dpp(double v) {
+  const double o = dpp_move_d<CTRL, ROWMASK>(v);
   return o > v ? o : v;
 }
 
@@ -224,6 +230,18 @@ DEV double readlane_d(double x, int l) {
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
   const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// fmax over the wave, by DPP moves only (no LDS): each 16-lane row, then rows
+// 1 and 3 take rows 0 and 2, then row 3 takes row 1; lane 63 ends with it.
+DEV double wave_fmax_d(double v) {
+  v = fmax(v, dpp_move_d<0xB1, 0xF>(v));    // quad_perm [1,0,3,2]
+  v = fmax(v, dpp_move_d<0x4E, 0xF>(v));    // quad_perm [2,3,0,1]
+  v = fmax(v, dpp_move_d<0x141, 0xF>(v));   // row_half_mirror
+  v = fmax(v, dpp_move_d<0x140, 0xF>(v));   // row_mirror
+  v = fmax(v, dpp_move_d<0x142, 0xA>(v));   // row_bcast:15 into rows 1, 3
+  v = fmax(v, dpp_move_d<0x143, 0xC>(v));   // row_bcast:31 into rows 2, 3
+  return readlane_d(v, 63);
 }
 
 // The value that lane (l & 31) + 32 H holds, for every lane l (H = 0 or 1):
@@ -244,8 +262,9 @@ DEV double half_value(double x) {
 // halves.  LU with partial pivoting runs on the register rows: the pivot of
 // column k is the lowest remaining row attaining max |J_g[:, k]| (a DPP max
 // inside the half that holds column k, then a ballot), each row's
-// column-k entry reaches the other half by a cross-half lane swap, the pivot
-// row is broadcast by lane permutes, and every remaining row is eliminated
+// column-k entry reaches the other half by a cross-half lane swap, each lane
+// reads its columns of the pivot row from lanes p and p + 32 (lane reads,
+// not LDS permutes), and every remaining row is eliminated
 // with the pivot's reciprocal.  No rows move; the pivot order is recorded.
 // Back-substitution walks the pivot order from the last column, each half
 // summing the products of its own columns.
@@ -263,16 +282,17 @@ void k_galerkin_solve_w(
   if (!first && !active[b]) return;
   const int i = lane & 31, h = lane >> 5;
   const int t0 = tfirst[b], t1 = tfirst[b + 1];
-  // Sum the tile partials of Phi^T J_f Phi and Phi^T f.  Each tile's r x r
-  // block is read as 4 KB contiguous (4 float4 per lane) with up to kTG
-  // tiles in flight at once; every element is summed over the tiles in order
-  // in FP64, then the sums go through LDS (rows padded to 33 doubles) into
-  // the row layout of the solve.
-  constexpr int kTG = 4;
-  __shared__ double sM[RT * (RT + 1)];
-  double acc[16];
+  // Sum the tile partials of Phi^T J_f Phi and Phi^T f.  The pass stores each
+  // tile's block in the order of this kernel's registers (mpart_pos32), so
+  // every lane reads its row half as four float4 loads (1 KB contiguous per
+  // load of the wave), up to kTG tiles in flight at once; every element is
+  // summed over the tiles in order in FP64.  No LDS anywhere in the kernel:
+  // the solve shares its compute unit with LDS-heavy kernels of the event
+  // chain and must not queue behind them.
+  constexpr int kTG = 2;
+  double A[NL];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+  for (int jj = 0; jj < NL; ++jj) A[jj] = 0.0;
   double gs = 0.0;
   for (int tt = t0; tt < t1; tt += kTG) {
     float4 v[kTG][4];
@@ -291,30 +311,18 @@ void k_galerkin_solve_w(
       if (tt + g < t1) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          acc[4 * u + 0] += (double)v[g][u].x;
-          acc[4 * u + 1] += (double)v[g][u].y;
-          acc[4 * u + 2] += (double)v[g][u].z;
-          acc[4 * u + 3] += (double)v[g][u].w;
+          A[4 * u + 0] += (double)v[g][u].x;
+          A[4 * u + 1] += (double)v[g][u].y;
+          A[4 * u + 2] += (double)v[g][u].z;
+          A[4 * u + 3] += (double)v[g][u].w;
         }
         gs += gv[g];
       }
     }
   }
-  // element e = 4 (lane + 64 u) + c of the row-major block: row e / 32, column e % 32
+  // register jj of lane (i, h) holds column 2 jj + h of row i
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int e = 4 * (lane + 64 * u) + c;
-      sM[(e / RT) * (RT + 1) + e % RT] = acc[4 * u + c];
-    }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  double A[NL];
-#pragma unroll
-  for (int jj = 0; jj < NL; ++jj)
-    A[jj] = (2 * jj + h == i ? 1.0 : 0.0) - dt * sM[i * (RT + 1) + 2 * jj + h];
+  for (int jj = 0; jj < NL; ++jj) A[jj] = (2 * jj + h == i ? 1.0 : 0.0) - dt * A[jj];
   const double ai = a[(size_t)b * RT + i];
   // the first iteration of a step starts from a_prev = a (and records it)
   if (first && h == 0) a_prev[(size_t)b * RT + i] = ai;
@@ -349,9 +357,13 @@ void k_galerkin_solve_w(
       ord = k;
       myr = rp;
     }
-    const int from = p + 32 * h;   // the pivot row's copy of this lane's columns
+    // the pivot row's copy of this lane's columns: lane p holds the even
+    // ones, lane p + 32 the odd ones
 #pragma unroll
-    for (int jj = kk; jj < NL; ++jj) A[jj] -= f * __shfl(A[jj], from);
+    for (int jj = kk; jj < NL; ++jj) {
+      const double e0 = readlane_d(A[jj], p), e1 = readlane_d(A[jj], p + 32);
+      A[jj] -= f * (h ? e1 : e0);
+    }
     bi -= f * readlane_d(bi, p);
   }
   // a zero pivot leaves a zero reciprocal on its row
@@ -377,12 +389,9 @@ void k_galerkin_solve_w(
     am = fabs(an);
     fin = isfinite(an) ? 1 : 0;
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    dm = fmax(dm, __shfl_xor(dm, off));
-    am = fmax(am, __shfl_xor(am, off));
-    fin &= __shfl_xor(fin, off);
-  }
+  dm = wave_fmax_d(dm);
+  am = wave_fmax_d(am);
+  fin = __ballot(fin == 0) == 0ull ? 1 : 0;
   if (lane == 0) {
     iters[b] = first ? 1 : iters[b] + 1;
     if (!ok) atomicOr(&flags[b], ROM_FLAG_SINGULAR);
