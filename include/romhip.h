@@ -404,10 +404,13 @@ rom_status rom_rollout_vjp(rom_handle h, const void* q0, int32_t n_steps, int32_
  * transfer, the rotation of eq. isvd_updated_basis_full, the SVD of the core
  * matrix of eq. isvd_core_matrix (distinct singular values), the two
  * Gram-Schmidt passes, the preprocessing, and the coarse step (a transposed
- * banded solve).  The forward pass keeps about sqrt(n_fine) checkpoints
- * (n_ckpt > 0 sets their number) and recomputes one segment at a time; the
- * result does not depend on n_ckpt.  The handle is left in the state that
- * rom_step(h, n_fine) would leave.
+ * banded solve).  The forward pass keeps n_ckpt checkpoints at segment
+ * starts and records the last segment as it goes; the backward pass
+ * recomputes every other segment from its checkpoint.  n_ckpt = 0 takes one
+ * segment (nothing recomputed) when its records fit in half of the free
+ * device memory, else ceil(sqrt(n_fine)) checkpoints.  The result does not
+ * depend on n_ckpt.  The handle is left in the state that rom_step(h, n_fine)
+ * would leave.
  *   qbar: device T[total_dof] (not modified).  Workspace is allocated and
  *   freed inside the call (hipMalloc; not for stream capture); the call
  *   synchronises the stream.  An event with rho = 0 (snapshot inside the

@@ -436,6 +436,178 @@ __global__ __launch_bounds__(kEV) void k_ev_a(
   if (tid == 0) out[n * r] = jq;
 }
 
+// Pass A for r = 32 on the FP64 matrix cores (v_mfma_f64_16x16x4f64; lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16], accumulator element v is
+// D[4 v + l / 16][l % 16], checked on the device).  The same quantities as k_ev_a, by one wave per
+// 16-row block of the tile (blocks w, w + 4, ... for wave w), staged through
+// the wave's own LDS slice:
+//   * q = D (yhat - q_ref) - Phi sp and jbar = Phibar' U[r, :r]^T, four lanes
+//     per row with a quad reduction, into qs and js, and jq += jbar q;
+//   * Ubar[:r, :r] partials Phi^T Phibar' as 2 x 2 accumulator tiles over the
+//     wave's rows (four rows per product), Ubar[r, :r] += (q / rho)^T Phibar'
+//     by lane sums;
+//   * Phibar_old = Phibar' U[:r, :r]^T as two 16 x 16 tiles per block (eight
+//     products over m), written over the block's rows of phibar.
+// The four waves' partials are added in wave order; no block barrier inside
+// the row loop.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+constexpr int kEA = 32;        // r of the matrix-core pass A
+constexpr int kEAL = kEA + 1;  // padded row of the staged blocks (doubles)
+
+DEV void ev_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__global__ __launch_bounds__(kEV) __attribute__((amdgpu_waves_per_eu(3))) void k_ev_a_mfma(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off, int nv,
+    const double* __restrict__ dvar, const T* __restrict__ Phi, const T* __restrict__ ynew,
+    const T* __restrict__ qref, const double* __restrict__ ubar, const double* __restrict__ prs,
+    double* __restrict__ phibar, double* __restrict__ qs, double* __restrict__ js,
+    double* __restrict__ part) {
+  constexpr int r = kEA, n = kEA + 1, NW = kEV / 64;
+  __shared__ double U[n * n];                    // U[c][m], row c of Ubar
+  __shared__ double sp[r];
+  __shared__ double wB[NW][16 * kEAL];           // the wave's Phibar' rows
+  __shared__ double wP[NW][16 * kEAL];           // the wave's Phi rows (FP64)
+  __shared__ double wq[NW][16];                  // q of those rows
+  __shared__ double red[kEV / 64];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  const double* pr = prs + (size_t)b * (2 * r + 2);
+  const double irho = pr[2 * r];
+  if (irho == 0.0) return;   // rho = 0: the instance is flagged and skipped
+  for (int e = tid; e < n * n; e += kEV) U[e] = ubar[(size_t)b * n * n + e];
+  for (int c = tid; c < r; c += kEV) sp[c] = pr[c] + pr[r + c];
+  __syncthreads();
+  const int64_t base = dof_off[b] + t.cell0;
+  const double* dvb = dvar + (size_t)b * nv;
+  double* cB = wB[wave];
+  double* cP = wP[wave];
+  double* cq = wq[wave];
+  const int l16 = lane & 15, lk = lane >> 4;     // MFMA row / column and k slot
+  const int qr = lane >> 2, qc = lane & 3;       // row and quarter of the row sums
+  d4_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[a][c] = d4_t{0.0, 0.0, 0.0, 0.0};
+  double ub = 0.0;   // Ubar[r][lane & 31] over the rows of half lane >> 5
+  double jq = 0.0;
+  const int nblk = (int)((t.ncell + 15) / 16);
+  for (int kb = wave; kb < nblk; kb += NW) {
+    const int64_t r0 = (int64_t)kb * 16;
+    const int nr = (int)(t.ncell - r0 < 16 ? t.ncell - r0 : 16);
+    const int64_t g0 = base + r0;
+    // stage 16 rows: eight elements of each array per lane, loads first
+    {
+      double vb[8], vp[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = lane + 64 * u, k = e >> 5;
+        vb[u] = k < nr ? phibar[g0 * r + e] : 0.0;
+        vp[u] = k < nr ? (double)Phi[g0 * r + e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = lane + 64 * u, k = e >> 5, c = e & 31;
+        cB[k * kEAL + c] = vb[u];
+        cP[k * kEAL + c] = vp[u];
+      }
+    }
+    ev_wave_sync();
+    // q and jbar of row qr: lanes 4 qr .. 4 qr + 3 take eight columns each
+    {
+      double sq = 0.0, sj = 0.0;
+#pragma unroll
+      for (int c = 8 * qc; c < 8 * qc + 8; ++c) {
+        sq += cP[qr * kEAL + c] * sp[c];
+        sj += cB[qr * kEAL + c] * U[r * n + c];
+      }
+      sq += __shfl_xor(sq, 1);
+      sq += __shfl_xor(sq, 2);
+      sj += __shfl_xor(sj, 1);
+      sj += __shfl_xor(sj, 2);
+      if (qc == 0) {
+        double q = 0.0;
+        if (qr < nr) {
+          const int64_t g = g0 + qr;
+          q = dvb[(t.cell0 + r0 + qr) % nv] * ((double)ynew[g] - (double)qref[g]) - sq;
+          qs[g] = q;
+          js[g] = sj;
+          jq += sj * q;
+        }
+        cq[qr] = q;
+      }
+    }
+    ev_wave_sync();
+    // Ubar partials: four rows per product, 2 x 2 tiles
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int k = 4 * st + lk;
+      const double a0 = cP[k * kEAL + l16], a1 = cP[k * kEAL + 16 + l16];
+      const double b0 = cB[k * kEAL + l16], b1 = cB[k * kEAL + 16 + l16];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    // Ubar[r, :] += (q / rho)^T Phibar': column lane & 31, rows of half lane >> 5
+    {
+      const int c = lane & 31, h = lane >> 5;
+#pragma unroll
+      for (int k = 8 * h; k < 8 * h + 8; ++k) ub += (cq[k] * irho) * cB[k * kEAL + c];
+    }
+    // Phibar_old rows of the block: D[k][c] = sum_m Phibar'[k][m] U[c][m]
+    {
+      d4_t o0 = d4_t{0.0, 0.0, 0.0, 0.0}, o1 = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int sm = 0; sm < 8; ++sm) {
+        const int m = 4 * sm + lk;
+        const double av = cB[l16 * kEAL + m];
+        o0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, U[l16 * n + m], o0, 0, 0, 0);
+        o1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, U[(16 + l16) * n + m], o1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = 4 * v + lk;
+        if (k < nr) {
+          phibar[(g0 + k) * r + l16] = o0[v];
+          phibar[(g0 + k) * r + 16 + l16] = o1[v];
+        }
+      }
+    }
+    ev_wave_sync();   // the block's rows are read before the next staging
+  }
+  // the tile's partials: the waves' sums added in wave order into wB[0]
+  double* sum = &wB[0][0];   // 33 x 32 doubles (fits the 4 x 16 x 33 staging area)
+  __syncthreads();
+  for (int w = 0; w < NW; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = 16 * a + 4 * v + lk, j = 16 * c + l16;
+            sum[i * r + j] = (w == 0 ? 0.0 : sum[i * r + j]) + acc[a][c][v];
+          }
+      // row r: the two halves of the wave (lanes c and c + 32), in half order
+      const double uh = __shfl_xor(ub, 32);
+      if (lane < 32) sum[r * r + lane] = (w == 0 ? 0.0 : sum[r * r + lane]) + (ub + uh);
+    }
+    __syncthreads();
+  }
+  double* out = part + (size_t)blockIdx.x * evp_ld(r);
+  for (int e = tid; e < n * r; e += kEV) out[e] = sum[e];
+  jq = block_sum(jq, red);
+  if (tid == 0) out[n * r] = jq;
+}
+
 // After pass A, one block per instance: the transfer adjoint (abar <- U[:r, :r]
 // abar, Ubar[:r, :r] += a_old abar^T), the tiles' Ubar partials in tile order,
 // then the adjoint of the core SVD and of K's entries: sigbar, pbar, rhobar.
@@ -813,9 +985,14 @@ rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new
   const unsigned nt = (unsigned)h->n_ptiles;
   auto go = [&](auto tag) {
     using T = decltype(tag);
-    hipLaunchKernelGGL((k_ev_a<T>), dim3(nt), dim3(kEV), shm_a, s, h->d_ptiles, h->d_dof_off, r,
-                       nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref, ubar,
-                       pr, phibar, qs, js, part);
+    if (r == kEA)
+      hipLaunchKernelGGL((k_ev_a_mfma<T>), dim3(nt), dim3(kEV), 0, s, h->d_ptiles, h->d_dof_off,
+                         nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref,
+                         ubar, pr, phibar, qs, js, part);
+    else
+      hipLaunchKernelGGL((k_ev_a<T>), dim3(nt), dim3(kEV), shm_a, s, h->d_ptiles, h->d_dof_off,
+                         r, nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref,
+                         ubar, pr, phibar, qs, js, part);
     hipLaunchKernelGGL(k_ev_core, dim3(B), dim3(kEV), shm_core, s, r, h->cfg.lambda,
                        h->d_ptile_first, part, sig_old, a_old, ubar, pr, sig_new, abar, sigbar,
                        evs, h->flags);

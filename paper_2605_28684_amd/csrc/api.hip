@@ -1242,19 +1242,30 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
   hipStream_t s = (hipStream_t)stream;
   h->last_stream = s;
   const bool f64 = c.precision == ROM_F64;
-  int64_t C = n_ckpt > 0 ? n_ckpt : (int64_t)std::ceil(std::sqrt((double)T));
-  if (C > T) C = T;
-  const int64_t S = (T + C - 1) / C;      // fine steps per segment
-  const int64_t nseg = (T + S - 1) / S;
-  const int64_t E = S / z + 1;            // events per segment, at most
   const size_t phi_b = h->esz * (size_t)h->total_dof * r, y_b = h->esz * (size_t)h->total_dof;
   const size_t br = 8 * (size_t)B * r;
   const size_t state_b = phi_b + y_b + 2 * br;        // Phi, y_corr, sigma, a
   const size_t ev_b = phi_b + y_b + 3 * br + 8 * (size_t)B * n * n + 8 * (size_t)B * (2 * r + 2);
   const size_t td8 = 8 * (size_t)h->total_dof;
   const size_t evscr_b = 8 * event_vjp_scratch_doubles(h);
-  const size_t need = (size_t)(nseg + 1) * state_b + (size_t)S * br + (size_t)E * ev_b +
-                      2 * td8 + 2 * y_b + evscr_b + 1024;
+  auto ws_bytes = [&](int64_t C) {
+    const int64_t S = (T + C - 1) / C, nseg = (T + S - 1) / S, E = S / z + 1;
+    return (size_t)(nseg + 1) * state_b + (size_t)S * br + (size_t)E * ev_b + 2 * td8 +
+           2 * y_b + evscr_b + 1024;
+  };
+  // n_ckpt = 0: one segment (nothing recomputed) when its records fit in half
+  // of the free device memory, else ceil(sqrt(n_fine)) checkpoints
+  int64_t C = n_ckpt;
+  if (C <= 0) {
+    size_t fr = 0, tot = 0;
+    ROM_HIP_CHECK(hipMemGetInfo(&fr, &tot));
+    C = ws_bytes(1) <= fr / 2 ? 1 : (int64_t)std::ceil(std::sqrt((double)T));
+  }
+  if (C > T) C = T;
+  const int64_t S = (T + C - 1) / C;      // fine steps per segment
+  const int64_t nseg = (T + S - 1) / S;
+  const int64_t E = S / z + 1;            // events per segment, at most
+  const size_t need = ws_bytes(C);
   char* ws = nullptr;
   ROM_TRY(alloc(&ws, need));
   struct Host { int64_t nf, nu, ne; };
@@ -1296,22 +1307,11 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
   auto ev_u = [&](int64_t e) { return ev_snew(e) + (size_t)B * r; };
   auto ev_pr = [&](int64_t e) { return ev_u(e) + (size_t)B * n * n; };
   rom_status st = ROM_OK;
-  // forward: checkpoints at segment starts, and the end state
-  for (int64_t j = 0; j < nseg && st == ROM_OK; ++j) {
-    st = save(j);
-    const int64_t L = std::min(S, T - j * S);
-    for (int64_t k = 0; k < L && st == ROM_OK; ++k) st = fine_step_impl(h, s);
-  }
-  if (st == ROM_OK) st = save(nseg);
-  // seed at the end state
-  if (st == ROM_OK) st = launch_online_seed(h, qbar, abar, phibar, s);
-  if (st == ROM_OK) st = fill_zero(sigbar, br, s);
-  if (st == ROM_OK) st = fill_zero(ycbar, td8, s);
-  // backward, one segment at a time
-  for (int64_t j = nseg - 1; j >= 0 && st == ROM_OK; --j) {
-    st = restore(j);
-    const int64_t L = std::min(S, T - j * S);
-    std::vector<int64_t> after;   // event e follows fine step after[e] of the segment
+  // the fine steps of one segment from the handle's state, recording a after
+  // every step and, per event (after[e] = its step), what its adjoint reads
+  auto record = [&](int64_t L, std::vector<int64_t>& after) -> rom_status {
+    rom_status st = ROM_OK;
+    after.clear();
     for (int64_t k = 0; k < L && st == ROM_OK; ++k) {
       st = launch_rom_fine_step(h, s);
       if (st == ROM_OK) st = copy_words(h->a, rec_a + (size_t)k * br, br, s);
@@ -1333,6 +1333,35 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
         h->n_events += 1;
       }
       h->n_fine += 1;
+    }
+    return st;
+  };
+  // forward: checkpoints at segment starts, and the end state; the last
+  // segment is recorded on the way, so the backward pass starts without
+  // recomputing it
+  std::vector<int64_t> after_last;
+  for (int64_t j = 0; j < nseg && st == ROM_OK; ++j) {
+    st = save(j);
+    const int64_t L = std::min(S, T - j * S);
+    if (j + 1 < nseg)
+      for (int64_t k = 0; k < L && st == ROM_OK; ++k) st = fine_step_impl(h, s);
+    else if (st == ROM_OK)
+      st = record(L, after_last);
+  }
+  if (st == ROM_OK) st = save(nseg);
+  // seed at the end state
+  if (st == ROM_OK) st = launch_online_seed(h, qbar, abar, phibar, s);
+  if (st == ROM_OK) st = fill_zero(sigbar, br, s);
+  if (st == ROM_OK) st = fill_zero(ycbar, td8, s);
+  // backward, one segment at a time
+  for (int64_t j = nseg - 1; j >= 0 && st == ROM_OK; --j) {
+    const int64_t L = std::min(S, T - j * S);
+    std::vector<int64_t> after;   // event e follows fine step after[e] of the segment
+    if (j + 1 == nseg) {
+      after = after_last;   // recorded by the forward pass; the handle is at its end
+    } else {
+      st = restore(j);
+      if (st == ROM_OK) st = record(L, after);
     }
     for (int64_t k = L - 1; k >= 0 && st == ROM_OK; --k) {
       int64_t e_next = -1;   // first event at or after step k: its Phi_old is step k's basis

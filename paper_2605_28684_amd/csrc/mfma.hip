@@ -36,6 +36,15 @@ DEV void wave_sync() {
 
 constexpr int kCh = 32;  // rows per wave chunk
 
+// A wave-uniform double moved to scalar registers (frees two vector registers
+// in loops that only read it).
+DEV double uniform_d(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 DEV int64_t wrap_cell(int64_t c, int64_t n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
 // ------------------------------------------------------------------ Galerkin pass
@@ -116,9 +125,10 @@ DEV void galerkin_tile(const Tile& t, const double* __restrict__ phys, int nphys
   const int n = (int)t.n;
   const float* __restrict__ Pb = Phi + t.base * RT;
   const float* __restrict__ qb = qref + t.base;
-  const double nu = phys[(size_t)b * nphys];
-  const double dinv = 1.0 / dvar[b];
-  const double inv = (double)n, inv2 = (double)n * (double)n;
+  // per-instance constants, uniform over the block: kept in scalar registers
+  const double nu = uniform_d(phys[(size_t)b * nphys]);
+  const double dinv = uniform_d(1.0 / dvar[b]);
+  const double inv = uniform_d((double)n), inv2 = uniform_d((double)n * (double)n);
   for (int c = tid; c < RT; c += NT) L.redG[c] = 0.0;
   for (int e = tid; e < RT * RT; e += NT) L.redM[e] = 0.f;
   __syncthreads();

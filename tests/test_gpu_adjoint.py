@@ -204,3 +204,92 @@ def test_rom_online_autograd_function_fp64():
         f2 = (L_at(hstep / 2) - L_at(-hstep / 2)) / hstep
         fd = (4 * f2 - f1) / 3
         assert abs(dot - fd) <= 1e-5 * abs(dot), (idx, dot, fd)
+
+
+def _synthetic(cells, r, precision, seed=5):
+    """A well-conditioned start for a wide basis: a random orthonormal Phi,
+    distinct geometric sigma around |yhat|, random a and smooth q_ref, y_corr
+    (a trajectory's own snapshots at r = 32 are numerically rank-deficient, so
+    its Brand cores have no usable gaps).  Returns the workload, its oracle
+    states and a device handle holding the same state."""
+    import gpu_common as G
+    import torch
+    from paper_2605_28684_amd import romhip as RH
+    prm = O.default_params(r=r, n_s=r, w_init=r, z=3, dt=2e-3, lam=0.7, newton_tol=1e-13,
+                           newton_max=30, rom_tol=1e-14, rom_max=30, reorth_every=0)
+    w = W.burgers_batch_f32(n_inst=len(cells), r=r, z=prm["z"], w_init=prm["w_init"],
+                            precision=precision)
+    rng = np.random.default_rng(seed)
+    w.n_cells = list(cells)
+    w.phys = [dict(nu=float(rng.uniform(0.0002, 0.0006))) for _ in cells]
+    w.q0 = np.concatenate([0.5 + 0.2 * np.sin(2 * np.pi * W.centres(n) + b) for b, n in enumerate(cells)])
+    w.dt, w.lam = prm["dt"], prm["lam"]
+    w.newton_tol, w.newton_max = prm["newton_tol"], prm["newton_max"]
+    w.rom_tol, w.rom_max = prm["rom_tol"], prm["rom_max"]
+    w.reorth_every, w.tau_rho = 0, prm["tau_rho"]
+    if precision == W.F32:
+        w.newton_tol, w.rom_tol = 1e-6, 1e-7
+    sts = []
+    for b, n in enumerate(cells):
+        x = W.centres(n)
+        q_ref = 0.5 + 0.2 * np.sin(2 * np.pi * x + b) + 0.05 * np.cos(6 * np.pi * x)
+        d_var = np.array([1.0 / (0.3 + 0.1 * b)])
+        d = np.full(n, d_var[0])
+        Phi, _ = np.linalg.qr(rng.normal(size=(n, r)))
+        a = rng.normal(size=r) * 0.05 * np.sqrt(n) * d_var[0]
+        y_corr = q_ref + 0.08 * np.sin(4 * np.pi * x + 0.3 * b)
+        ny = np.linalg.norm(d * (y_corr - q_ref))
+        sigma = ny * np.geomspace(2.0, 0.05, r)
+        st = dict(Phi=G.rounded(Phi, precision), sigma=sigma, a=a,
+                  q_ref=G.rounded(q_ref, precision), d_var=d_var, d=d,
+                  y_corr=G.rounded(y_corr, precision))
+        sts.append(st)
+    h = RH.RomBatch(w, q0=G.to_dev(w.q0, precision), use_graph=False)
+    h.set(RH.GET_BASIS, G.to_dev(np.concatenate([s["Phi"].reshape(-1) for s in sts]), precision))
+    h.set(RH.GET_SIGMA, torch.as_tensor(np.concatenate([s["sigma"] for s in sts])))
+    h.set(RH.GET_A, torch.as_tensor(np.concatenate([s["a"] for s in sts])))
+    h.set(RH.GET_QREF, G.to_dev(np.concatenate([s["q_ref"] for s in sts]), precision))
+    h.set(RH.GET_DVAR, torch.as_tensor(np.concatenate([s["d_var"] for s in sts])))
+    h.set(RH.GET_YCORR, G.to_dev(np.concatenate([s["y_corr"] for s in sts]), precision))
+    h.set(RH.GET_COUNTERS, [prm["w_init"], 0, 0, 0])
+    h.clear_status()
+    return w, prm, sts, h
+
+
+@pytest.mark.parametrize("precision", [W.F64, W.F32])
+def test_online_vjp_r32_matches_oracle(precision):
+    """r = 32 (the matrix-core event pass and, in FP32, the MFMA Galerkin pass
+    with its single-wave solve): two instances of 2100 and 150 cells (two pass
+    tiles and a ragged one), 7 fine steps with two events, against the oracle's
+    reverse mode from the same synthetic state.  FP64 within 1e-11 (measured
+    3e-15 .. 4e-13); FP32 storage within 5e-4 (measured 5e-6 .. 5e-5)."""
+    import gpu_common as G
+    cells, r, n_fine = [2100, 150], 32, 7
+    w, prm, sts, h = _synthetic(cells, r, precision)
+    rng = np.random.default_rng(17)
+    off = w.offsets()
+    qbar = []
+    for b, st in enumerate(sts):
+        fin, _ = A.online_forward(W.BURGERS, w.phys[b], st, prm, prm["w_init"], n_fine)
+        qt = O.reconstruct(fin["q_ref"], fin["d"], fin["Phi"], fin["a"])
+        qbar.append(0.05 * rng.normal(size=qt.shape))
+    qbar = np.concatenate(qbar)
+    ab, pb, sb, yb = [G.host(t) for t in h.online_vjp(n_fine, G.to_dev(qbar, precision))]
+    assert not np.any(h.status() & 0x10)
+    f64 = precision == W.F64
+    worst = {}
+    for b, st in enumerate(sts):
+        sl = slice(off[b], off[b + 1])
+        ra, rP, rs, ry = A.online_vjp(W.BURGERS, w.phys[b], st, prm, prm["w_init"], n_fine,
+                                      qbar[sl])
+        tol = 1e-11 if f64 else 5e-4
+        for name, got, ref in (("a", ab[b * r:(b + 1) * r], ra),
+                               ("Phi", pb[off[b] * r:off[b + 1] * r], rP.reshape(-1)),
+                               ("sigma", sb[b * r:(b + 1) * r], rs), ("y", yb[sl], ry)):
+            e = G.relerr(got, ref)
+            worst[name] = max(worst.get(name, 0.0), e)
+            assert np.all(np.isfinite(got))
+            G.assert_close(got, ref, tol, what="%s %d" % (name, b))
+    print("  r = 32 online adjoint vs oracle (%s): %s" % (
+        "FP64" if f64 else "FP32", ", ".join("%s %.2e" % kv for kv in worst.items())))
+    h.close()
