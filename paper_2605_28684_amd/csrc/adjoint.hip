@@ -6,13 +6,14 @@
 //
 //  * k_online_seed: the loss seed at the end, q~ = q_ref + D^-1 Phi a:
 //    abar = Phi^T D^-1 qbar, Phibar = D^-1 qbar a^T.
-//  * k_step_vjp_solve + k_step_vjp_rows: one fine step a_{n+1} = G(a_n, Phi) with
+//  * k_step_vjp_solve + k_step_vjp_uv: one fine step a_{n+1} = G(a_n, Phi) with
 //    g(a) = a - a_n - dt Phi^T D f(q_ref + D^-1 Phi a) = 0, differentiated by
 //    the implicit-function theorem at the converged a_{n+1}:
 //    J_g^T lambda = abar, abar_n = lambda and
 //    Phibar += dt (D f) lambda^T + dt D^-1 J_f^T (D Phi lambda) a_{n+1}^T.
 //    J_g = I - dt Phi^T J_f Phi comes from the Galerkin pass's tile partials;
-//    the r x r solve runs per instance, the Phibar update per pass tile.
+//    the r x r solve runs per instance; the Phibar terms are kept per row and
+//    k_phibar_flush applies a window's steps in one pass over Phibar.
 //  * k_ev_a, k_ev_core, k_ev_b, k_ev_c, k_ev_d: one event from the transfer back
 //    to yhat = D (y - q_ref):
 //    transfer a' = Ubar[:r, :r]^T a, rotation Phi' = [Phi, q / rho] Ubar[:, :r],
@@ -124,10 +125,8 @@ __global__ __launch_bounds__(kAT) void k_online_seed(
 // One fine step backward, in two launches.  k_step_vjp_solve (a workgroup per
 // instance): lambda = J_g^-T abar with J_g = I - dt M, M = Phi^T J_f Phi at a1
 // (= a_{n+1}) summed from the Galerkin pass's tile partials in tile order;
-// abar is replaced by lambda.  k_step_vjp_rows (a workgroup per pass tile):
-// Phibar += dt d f lambda^T + dt (J_f^T Phi lambda) a1^T over the tile's rows,
-// with q~ = q_ref + D^-1 Phi a1 and w = Phi lambda of the rows and their two
-// neighbours kept in LDS (the neighbours are recomputed by each tile).
+// abar is replaced by lambda.  Then k_step_vjp_uv keeps the step's Phibar
+// terms (below).
 template <typename T>
 __global__ __launch_bounds__(kAT) void k_step_vjp_solve(int r, double dt,
                                                         const int* __restrict__ tfirst,
@@ -153,15 +152,21 @@ __global__ __launch_bounds__(kAT) void k_step_vjp_solve(int r, double dt,
   for (int c = tid; c < r; c += kAT) abar[(size_t)b * r + c] = lam[c];
 }
 
-constexpr int kRT = 256;   // threads of k_step_vjp_rows
+constexpr int kRT = 256;   // threads of k_step_vjp_uv and k_phibar_flush
 constexpr int kSL = 8;     // lanes per row (each holds kSL-strided columns)
 
+// k_step_vjp_uv (a workgroup per pass tile): the step's Phibar terms
+//   Phibar += dt d f lambda^T + dt (J_f^T Phi lambda) a1^T
+// kept as two numbers per row, uv[i] = (dt d f_i, dt v_i) with v = J_f^T w,
+// w = Phi lambda, and q~ = q_ref + D^-1 Phi a1 of the rows and their two
+// neighbours in LDS (the neighbours are recomputed by each tile);
+// k_phibar_flush applies the terms of several steps in one pass over Phibar.
 template <typename T>
-__global__ __launch_bounds__(kRT) void k_step_vjp_rows(
+__global__ __launch_bounds__(kRT) void k_step_vjp_uv(
     const Tile* __restrict__ tiles, int r, double dt, const int64_t* __restrict__ dof_off,
     const double* __restrict__ phys, int nphys, const double* __restrict__ dvar,
     const T* __restrict__ Phi, const T* __restrict__ qref, const double* __restrict__ a1,
-    const double* __restrict__ lambda, double* __restrict__ phibar) {
+    const double* __restrict__ lambda, double2* __restrict__ uv) {
   __shared__ double sq[kPassRows + 2], sw[kPassRows + 2];
   __shared__ double lam[kMaxR], sa[kMaxR];
   const Tile t = tiles[blockIdx.x];
@@ -177,7 +182,6 @@ __global__ __launch_bounds__(kRT) void k_step_vjp_rows(
   }
   __syncthreads();
   const int sub = tid % kSL;
-  // q~ and w of rows cell0 - 1 .. cell0 + nt (periodic), each summed over its lanes
   for (int rr = tid / kSL; rr < nt + 2; rr += kRT / kSL) {
     const int64_t i = wrap(t.cell0 - 1 + rr, n);
     const T* pr = Phi + (base + i) * r;
@@ -198,13 +202,43 @@ __global__ __launch_bounds__(kRT) void k_step_vjp_rows(
     }
   }
   __syncthreads();
-  for (int rr = tid / kSL; rr < nt; rr += kRT / kSL) {
-    const int64_t i = t.cell0 + rr;
+  for (int rr = tid; rr < nt; rr += kRT) {
     double f, be, al_next, ga_prev;
     burgers_col(sq[rr], sq[rr + 1], sq[rr + 2], nu, inv, inv2, f, be, al_next, ga_prev);
     const double v = al_next * sw[rr + 2] + be * sw[rr + 1] + ga_prev * sw[rr];
-    double* pb = phibar + (base + i) * r;
-    for (int c = sub; c < r; c += kSL) pb[c] += dt * d * f * lam[c] + dt * v * sa[c];
+    uv[base + t.cell0 + rr] = make_double2(dt * d * f, dt * v);
+  }
+}
+
+// Phibar[i, :] += uv_k[i].x lambda_k + uv_k[i].y a1_k for the pending steps k =
+// 0 .. K-1 in order (the order in which the steps' adjoints ran): one pass
+// over Phibar for all of them.  uv: K slots of total_dof double2; lam, a1: K
+// slots of n_inst * r doubles.
+__global__ __launch_bounds__(kRT) void k_phibar_flush(
+    const Tile* __restrict__ tiles, int r, const int64_t* __restrict__ dof_off, int K,
+    int64_t total, const double2* __restrict__ uv, const double* __restrict__ lam,
+    const double* __restrict__ a1, int64_t n_inst, double* __restrict__ phibar) {
+  constexpr int KM = kPhibarPending;
+  __shared__ double sl[KM][kMaxR], sa[KM][kMaxR];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst, tid = threadIdx.x;
+  for (int e = tid; e < K * r; e += kRT) {
+    const int k = e / r, c = e - k * r;
+    sl[k][c] = lam[((size_t)k * n_inst + b) * r + c];
+    sa[k][c] = a1[((size_t)k * n_inst + b) * r + c];
+  }
+  __syncthreads();
+  const int64_t g0 = dof_off[b] + t.cell0;
+  const int64_t ne = t.ncell * r;
+  for (int64_t e = tid; e < ne; e += kRT) {
+    const int64_t i = e / r;
+    const int c = (int)(e - i * r);
+    double p = phibar[g0 * r + e];
+    for (int k = 0; k < K; ++k) {
+      const double2 w = uv[(size_t)k * total + g0 + i];
+      p += w.x * sl[k][c] + w.y * sa[k][c];
+    }
+    phibar[g0 * r + e] = p;
   }
 }
 
@@ -943,17 +977,17 @@ rom_status launch_online_seed(rom_batch* h, const void* qbar, double* abar, doub
   return ROM_OK;
 }
 
-rom_status launch_step_vjp(rom_batch* h, const void* Phi, const double* a1, double* abar,
-                           double* phibar, hipStream_t s) {
+rom_status launch_step_vjp_deferred(rom_batch* h, const void* Phi, const double* a1,
+                                    double* abar, double2* uv, hipStream_t s) {
   const int B = h->cfg.n_inst, r = h->cfg.r;
   auto go = [&](auto tag) {
     using T = decltype(tag);
     hipLaunchKernelGGL((k_step_vjp_solve<T>), dim3(B), dim3(kAT), 0, s, r, h->cfg.dt,
                        h->d_ptile_first, (const T*)h->mpart, mfma_ok(h) && r == 32 ? 1 : 0,
                        abar, h->flags);
-    hipLaunchKernelGGL((k_step_vjp_rows<T>), dim3(h->n_ptiles), dim3(kRT), 0, s, h->d_ptiles, r,
+    hipLaunchKernelGGL((k_step_vjp_uv<T>), dim3(h->n_ptiles), dim3(kRT), 0, s, h->d_ptiles, r,
                        h->cfg.dt, h->d_dof_off, h->d_phys, h->cfg.n_phys, h->d_var,
-                       (const T*)Phi, (const T*)h->q_ref, a1, abar, phibar);
+                       (const T*)Phi, (const T*)h->q_ref, a1, abar, uv);
   };
   if (h->cfg.precision == ROM_F64) go(double{});
   else go(float{});
@@ -961,59 +995,13 @@ rom_status launch_step_vjp(rom_batch* h, const void* Phi, const double* a1, doub
   return ROM_OK;
 }
 
-size_t event_vjp_scratch_doubles(const rom_batch* h) {
-  const int r = h->cfg.r;
-  return (size_t)std::max(h->n_ptiles, 1) * evp_ld(r) + (size_t)h->cfg.n_inst * evs_ld(r);
-}
-
-rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new,
-                            const double* sig_old, const double* a_old, const double* ubar,
-                            const double* pr, const double* sig_new, double* abar,
-                            double* phibar, double* sigbar, double* ybar, double* qs, double* js,
-                            double* evscr, hipStream_t s, double* qrbar, double* dvbar) {
-  const int B = h->cfg.n_inst, r = h->cfg.r, n = r + 1, nv = h->nv;
-  double* part = evscr;
-  double* evs = evscr + (size_t)std::max(h->n_ptiles, 1) * evp_ld(r);
-  const size_t ntl = (size_t)ev_ntl(r);
-  const size_t ch = (size_t)ev_chunk(r);
-  const size_t shm_a = sizeof(double) * ((size_t)n * n + std::max(ch * (2 * (r + 1) + 1),
-                                                                   16 * std::max((size_t)kEV, ntl)));
-  const size_t shm_core = sizeof(double) * 4 * (size_t)n * n;
-  const size_t shm_b = sizeof(double) * (ch * (r + 1) + ch + kEV);
-  const size_t shm_c = sizeof(double) * (2 * ch * (r + 1) + 3 * ch + kEV);
-  const size_t shm_d = sizeof(double) * (2 * ch * (r + 1) + 2 * ch);
-  const unsigned nt = (unsigned)h->n_ptiles;
-  auto go = [&](auto tag) {
-    using T = decltype(tag);
-    if (r == kEA)
-      hipLaunchKernelGGL((k_ev_a_mfma<T>), dim3(nt), dim3(kEV), 0, s, h->d_ptiles, h->d_dof_off,
-                         nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref,
-                         ubar, pr, phibar, qs, js, part);
-    else
-      hipLaunchKernelGGL((k_ev_a<T>), dim3(nt), dim3(kEV), shm_a, s, h->d_ptiles, h->d_dof_off,
-                         r, nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref,
-                         ubar, pr, phibar, qs, js, part);
-    hipLaunchKernelGGL(k_ev_core, dim3(B), dim3(kEV), shm_core, s, r, h->cfg.lambda,
-                       h->d_ptile_first, part, sig_old, a_old, ubar, pr, sig_new, abar, sigbar,
-                       evs, h->flags);
-    hipLaunchKernelGGL((k_ev_b<T>), dim3(nt), dim3(kEV), shm_b, s, h->d_ptiles, h->d_dof_off, r,
-                       (const T*)Phi_old, pr, evs, qs, js, part);
-    hipLaunchKernelGGL(k_ev_vec, dim3(B), dim3(64), 0, s, r, h->d_ptile_first, pr, part, evs,
-                       r + 1, nv, (double*)nullptr);
-    hipLaunchKernelGGL((k_ev_c<T>), dim3(nt), dim3(kEV), shm_c, s, h->d_ptiles, h->d_dof_off, r,
-                       nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref, pr,
-                       evs, qs, js, phibar, part);
-    hipLaunchKernelGGL(k_ev_vec, dim3(B), dim3(64), 0, s, r, h->d_ptile_first, pr, part, evs,
-                       2 * r + 1, nv, (double*)nullptr);
-    hipLaunchKernelGGL((k_ev_d<T>), dim3(nt), dim3(kEV), shm_d, s, h->d_ptiles, h->d_dof_off, r,
-                       nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref, pr,
-                       evs, js, phibar, ybar, qrbar, part);
-    if (qrbar)
-      hipLaunchKernelGGL(k_ev_vec, dim3(B), dim3(64), 0, s, r, h->d_ptile_first, pr, part, evs,
-                         0, nv, dvbar);
-  };
-  if (h->cfg.precision == ROM_F64) go(double{});
-  else go(float{});
+rom_status launch_phibar_flush(rom_batch* h, int K, const double2* uv, const double* lam,
+                               const double* a1, double* phibar, hipStream_t s) {
+  ROM_REQUIRE(K >= 0 && K <= kPhibarPending, ROM_E_INVAL, "too many pending step terms");
+  if (K == 0) return ROM_OK;
+  hipLaunchKernelGGL(k_phibar_flush, dim3(h->n_ptiles), dim3(kRT), 0, s, h->d_ptiles,
+                     h->cfg.r, h->d_dof_off, K, h->total_dof, uv, lam, a1,
+                     (int64_t)h->cfg.n_inst, phibar);
   ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
 }

@@ -1248,10 +1248,14 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
   const size_t ev_b = phi_b + y_b + 3 * br + 8 * (size_t)B * n * n + 8 * (size_t)B * (2 * r + 2);
   const size_t td8 = 8 * (size_t)h->total_dof;
   const size_t evscr_b = 8 * event_vjp_scratch_doubles(h);
+  // the fine steps' Phibar terms wait for one pass per window: up to
+  // KP = min(z, kPhibarPending) steps of (uv, lambda, a1)
+  const int KP = std::min(z, kPhibarPending);
+  const size_t pend_b = (size_t)KP * (16 * (size_t)h->total_dof + 2 * br);
   auto ws_bytes = [&](int64_t C) {
     const int64_t S = (T + C - 1) / C, nseg = (T + S - 1) / S, E = S / z + 1;
     return (size_t)(nseg + 1) * state_b + (size_t)S * br + (size_t)E * ev_b + 2 * td8 +
-           2 * y_b + evscr_b + 1024;
+           2 * y_b + evscr_b + pend_b + 2048;
   };
   // n_ckpt = 0: one segment (nothing recomputed) when its records fit in half
   // of the free device memory, else ceil(sqrt(n_fine)) checkpoints
@@ -1278,6 +1282,15 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
   char* rhs = (char*)(scr1 + h->total_dof);
   char* out = rhs + y_b;
   double* evscr = (double*)(((uintptr_t)(out + y_b) + 7) & ~(uintptr_t)7);
+  double2* pend_uv = (double2*)(((uintptr_t)((char*)evscr + evscr_b) + 15) & ~(uintptr_t)15);
+  double* pend_lam = (double*)(pend_uv + (size_t)KP * h->total_dof);
+  double* pend_a1 = pend_lam + (size_t)KP * B * r;
+  int npend = 0;
+  auto flush = [&]() -> rom_status {
+    const int K = npend;
+    npend = 0;
+    return launch_phibar_flush(h, K, pend_uv, pend_lam, pend_a1, phibar, s);
+  };
   auto save = [&](int64_t j) -> rom_status {
     char* p = ck + (size_t)j * state_b;
     ROM_TRY(copy_words(h->Phi, p, phi_b, s));
@@ -1369,8 +1382,11 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
         if (after[e] >= k) { e_next = e; break; }
       if (e_next >= 0 && after[e_next] == k) {
         const int64_t e = e_next;
-        st = launch_event_vjp(h, ev_phi(e), ev_y(e), ev_sold(e), ev_aold(e), ev_u(e), ev_pr(e),
-                              ev_snew(e), abar, phibar, sigbar, ycbar, scr0, scr1, evscr, s);
+        st = flush();   // the event reads Phibar
+        if (st == ROM_OK)
+          st = launch_event_vjp(h, ev_phi(e), ev_y(e), ev_sold(e), ev_aold(e), ev_u(e),
+                                ev_pr(e), ev_snew(e), abar, phibar, sigbar, ycbar, scr0, scr1,
+                                evscr, s);
         // coarse step y_new = BE(y_prev) over z dt: ybar <- J_r(y_new)^-T ybar
         if (st == ROM_OK) st = convert_words(ycbar, true, rhs, f64, h->total_dof, s);
         if (st == ROM_OK) st = launch_assemble_adjoint(h, ev_y(e), z * c.dt, rhs, s);
@@ -1388,9 +1404,17 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
       if (st == ROM_OK) st = launch_galerkin_pass(h, s);
       h->Phi = phi_live;
       h->a = a_live;
-      if (st == ROM_OK) st = launch_step_vjp(h, phi_k, a_k, abar, phibar, s);
+      if (st == ROM_OK && npend == KP) st = flush();
+      if (st == ROM_OK) {
+        st = launch_step_vjp_deferred(h, phi_k, a_k, abar, pend_uv + (size_t)npend * h->total_dof,
+                                      s);
+        if (st == ROM_OK) st = copy_words(abar, pend_lam + (size_t)npend * B * r, br, s);
+        if (st == ROM_OK) st = copy_words(a_k, pend_a1 + (size_t)npend * B * r, br, s);
+        ++npend;
+      }
     }
   }
+  if (st == ROM_OK) st = flush();
   if (st == ROM_OK) st = restore(nseg);
   hipError_t e = hipStreamSynchronize(s);
   (void)hipFree(ws);

@@ -40,6 +40,7 @@ constexpr int kTile = 256;          // cells per tile of the stencil kernels
 constexpr int kPassRows = 2048;     // basis rows per block of the tall-skinny passes
 constexpr int kMaxR = 64;           // largest reduced dimension supported
 constexpr int kMaxNs = 2 * kMaxR;   // largest number of DEIM rows
+constexpr int kPhibarPending = 8;   // step terms the online adjoint defers (Phibar flushes)
 
 // Position of element (i, j) of one tile's r x r block of Phi^T J_f Phi in the
 // partials the FP32 MFMA pass writes for r = 32.  The single-wave solve keeps
@@ -256,8 +257,13 @@ rom_status launch_isvd_transfer(rom_batch* h, hipStream_t s);
 // seed writes them, the event adds to them).
 rom_status launch_online_seed(rom_batch* h, const void* qbar, double* abar, double* phibar,
                               hipStream_t s, double* qrbar = nullptr, double* dvbar = nullptr);
-rom_status launch_step_vjp(rom_batch* h, const void* Phi, const double* a1, double* abar,
-                           double* phibar, hipStream_t s);
+// one fine step backward with its Phibar terms kept as uv (the caller keeps
+// lambda = abar and a1 beside it) for launch_phibar_flush, which applies K of
+// them in one pass
+rom_status launch_step_vjp_deferred(rom_batch* h, const void* Phi, const double* a1,
+                                    double* abar, double2* uv, hipStream_t s);
+rom_status launch_phibar_flush(rom_batch* h, int K, const double2* uv, const double* lam,
+                               const double* a1, double* phibar, hipStream_t s);
 rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new,
                             const double* sig_old, const double* a_old, const double* ubar,
                             const double* pr, const double* sig_new, double* abar,
