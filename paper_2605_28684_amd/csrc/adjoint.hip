@@ -977,6 +977,63 @@ rom_status launch_online_seed(rom_batch* h, const void* qbar, double* abar, doub
   return ROM_OK;
 }
 
+size_t event_vjp_scratch_doubles(const rom_batch* h) {
+  const int r = h->cfg.r;
+  return (size_t)std::max(h->n_ptiles, 1) * evp_ld(r) + (size_t)h->cfg.n_inst * evs_ld(r);
+}
+
+rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new,
+                            const double* sig_old, const double* a_old, const double* ubar,
+                            const double* pr, const double* sig_new, double* abar,
+                            double* phibar, double* sigbar, double* ybar, double* qs, double* js,
+                            double* evscr, hipStream_t s, double* qrbar, double* dvbar) {
+  const int B = h->cfg.n_inst, r = h->cfg.r, n = r + 1, nv = h->nv;
+  double* part = evscr;
+  double* evs = evscr + (size_t)std::max(h->n_ptiles, 1) * evp_ld(r);
+  const size_t ntl = (size_t)ev_ntl(r);
+  const size_t ch = (size_t)ev_chunk(r);
+  const size_t shm_a = sizeof(double) * ((size_t)n * n + std::max(ch * (2 * (r + 1) + 1),
+                                                                   16 * std::max((size_t)kEV, ntl)));
+  const size_t shm_core = sizeof(double) * 4 * (size_t)n * n;
+  const size_t shm_b = sizeof(double) * (ch * (r + 1) + ch + kEV);
+  const size_t shm_c = sizeof(double) * (2 * ch * (r + 1) + 3 * ch + kEV);
+  const size_t shm_d = sizeof(double) * (2 * ch * (r + 1) + 2 * ch);
+  const unsigned nt = (unsigned)h->n_ptiles;
+  auto go = [&](auto tag) {
+    using T = decltype(tag);
+    if (r == kEA)
+      hipLaunchKernelGGL((k_ev_a_mfma<T>), dim3(nt), dim3(kEV), 0, s, h->d_ptiles, h->d_dof_off,
+                         nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref,
+                         ubar, pr, phibar, qs, js, part);
+    else
+      hipLaunchKernelGGL((k_ev_a<T>), dim3(nt), dim3(kEV), shm_a, s, h->d_ptiles, h->d_dof_off,
+                         r, nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref,
+                         ubar, pr, phibar, qs, js, part);
+    hipLaunchKernelGGL(k_ev_core, dim3(B), dim3(kEV), shm_core, s, r, h->cfg.lambda,
+                       h->d_ptile_first, part, sig_old, a_old, ubar, pr, sig_new, abar, sigbar,
+                       evs, h->flags);
+    hipLaunchKernelGGL((k_ev_b<T>), dim3(nt), dim3(kEV), shm_b, s, h->d_ptiles, h->d_dof_off, r,
+                       (const T*)Phi_old, pr, evs, qs, js, part);
+    hipLaunchKernelGGL(k_ev_vec, dim3(B), dim3(64), 0, s, r, h->d_ptile_first, pr, part, evs,
+                       r + 1, nv, (double*)nullptr);
+    hipLaunchKernelGGL((k_ev_c<T>), dim3(nt), dim3(kEV), shm_c, s, h->d_ptiles, h->d_dof_off, r,
+                       nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref, pr,
+                       evs, qs, js, phibar, part);
+    hipLaunchKernelGGL(k_ev_vec, dim3(B), dim3(64), 0, s, r, h->d_ptile_first, pr, part, evs,
+                       2 * r + 1, nv, (double*)nullptr);
+    hipLaunchKernelGGL((k_ev_d<T>), dim3(nt), dim3(kEV), shm_d, s, h->d_ptiles, h->d_dof_off, r,
+                       nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref, pr,
+                       evs, js, phibar, ybar, qrbar, part);
+    if (qrbar)
+      hipLaunchKernelGGL(k_ev_vec, dim3(B), dim3(64), 0, s, r, h->d_ptile_first, pr, part, evs,
+                         0, nv, dvbar);
+  };
+  if (h->cfg.precision == ROM_F64) go(double{});
+  else go(float{});
+  ROM_HIP_CHECK(hipGetLastError());
+  return ROM_OK;
+}
+
 rom_status launch_step_vjp_deferred(rom_batch* h, const void* Phi, const double* a1,
                                     double* abar, double2* uv, hipStream_t s) {
   const int B = h->cfg.n_inst, r = h->cfg.r;
