@@ -66,6 +66,7 @@ DEV void burgers_col(double um, double u0, double up, double nu, double inv, dou
 DEV int64_t wrap(int64_t c, int64_t n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
 constexpr int kSC = 64;   // rows of a staged chunk in the seed adjoint
+constexpr int kEV = 256;  // threads of the seed's and the event adjoint's tile kernels
 
 template <typename T>
 __global__ __launch_bounds__(kAT) void k_online_seed(
@@ -122,6 +123,56 @@ __global__ __launch_bounds__(kAT) void k_online_seed(
   }
 }
 
+// The seed without the q_ref and D terms, by pass tiles: Phibar = D^-1 qbar a^T
+// for the tile's rows and the tile's partial of Phi^T D^-1 qbar (G = kEV / r
+// row groups of r threads, thread (g, c) always on column c, so the loads and
+// stores of consecutive threads are consecutive elements); k_seed_abar adds
+// the partials of an instance's tiles in tile order.
+template <typename T>
+__global__ __launch_bounds__(kEV) void k_seed_tile(
+    const Tile* __restrict__ tiles, int r, const int64_t* __restrict__ dof_off,
+    const double* __restrict__ dvar, int nv, const T* __restrict__ Phi,
+    const double* __restrict__ a, const T* __restrict__ qbar, double* __restrict__ phibar,
+    double* __restrict__ part) {
+  __shared__ double sa[kMaxR], red[kEV];
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst, tid = threadIdx.x;
+  const int G = kEV / r, gc = tid % r;
+  const bool on = tid < G * r;
+  for (int c = tid; c < r; c += kEV) sa[c] = a[(size_t)b * r + c];
+  __syncthreads();
+  const int64_t g0 = dof_off[b] + t.cell0;
+  const double* dvb = dvar + (size_t)b * nv;
+  const int64_t ne = t.ncell * r, step = (int64_t)G * r;
+  double acc = 0.0;
+  if (on) {
+#pragma unroll 4
+    for (int64_t e = tid; e < ne; e += step) {
+      const int64_t k = e / r;
+      const double cq = (double)qbar[g0 + k] / dvb[(t.cell0 + k) % nv];
+      acc += (double)Phi[g0 * r + e] * cq;
+      phibar[g0 * r + e] = cq * sa[gc];
+    }
+  }
+  red[tid] = acc;
+  __syncthreads();
+  if (tid < r) {
+    double sum = 0.0;
+    for (int g = 0; g < G; ++g) sum += red[g * r + tid];
+    part[(size_t)blockIdx.x * r + tid] = sum;
+  }
+}
+
+__global__ void k_seed_abar(int r, const int* __restrict__ tfirst, const double* __restrict__ part,
+                            double* __restrict__ abar) {
+  const int b = blockIdx.x;
+  for (int c = threadIdx.x; c < r; c += blockDim.x) {
+    double sum = 0.0;
+    for (int tt = tfirst[b]; tt < tfirst[b + 1]; ++tt) sum += part[(size_t)tt * r + c];
+    abar[(size_t)b * r + c] = sum;
+  }
+}
+
 // One fine step backward, in two launches.  k_step_vjp_solve (a workgroup per
 // instance): lambda = J_g^-T abar with J_g = I - dt M, M = Phi^T J_f Phi at a1
 // (= a_{n+1}) summed from the Galerkin pass's tile partials in tile order;
@@ -142,7 +193,15 @@ __global__ __launch_bounds__(kAT) void k_step_vjp_solve(int r, double dt,
     const int i = e / r, j = e % r;
     const int pe = pos32 ? mpart_pos32(i, j) : e;   // the partials' order (see mpart)
     double s = 0.0;
-    for (int tt = t0; tt < t1; ++tt) s += (double)mpart[(size_t)tt * kMaxR * kMaxR + pe];
+    for (int tt = t0; tt < t1; tt += 8) {   // eight tiles' loads in flight, summed in order
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = tt + u < t1 ? mpart[(size_t)(tt + u) * kMaxR * kMaxR + pe] : T(0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (tt + u < t1) s += (double)v[u];
+    }
     A[j * ld + i] = (i == j ? 1.0 : 0.0) - dt * s;
   }
   for (int c = tid; c < r; c += kAT) lam[c] = abar[(size_t)b * r + c];
@@ -181,24 +240,50 @@ __global__ __launch_bounds__(kRT) void k_step_vjp_uv(
     sa[c] = a1[(size_t)b * r + c];
   }
   __syncthreads();
-  const int sub = tid % kSL;
-  for (int rr = tid / kSL; rr < nt + 2; rr += kRT / kSL) {
-    const int64_t i = wrap(t.cell0 - 1 + rr, n);
-    const T* pr = Phi + (base + i) * r;
-    double sqv = 0.0, swv = 0.0;
-    for (int c = sub; c < r; c += kSL) {
-      const double p = (double)pr[c];
-      sqv += p * sa[c];
-      swv += p * lam[c];
-    }
+  if (sizeof(T) == 4 && r == 32) {
+    // FP32 basis, r = 32: four lanes per row, eight columns (two float4) each
+    const int q = tid & 3;
+#pragma unroll 2
+    for (int rr = tid >> 2; rr < nt + 2; rr += kRT / 4) {
+      const int64_t i = wrap(t.cell0 - 1 + rr, n);
+      const float4* pr = reinterpret_cast<const float4*>(Phi + (base + i) * 32 + 8 * q);
+      const float4 u0 = pr[0], u1 = pr[1];
+      const float pv[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+      double sqv = 0.0, swv = 0.0;
 #pragma unroll
-    for (int off = kSL / 2; off > 0; off >>= 1) {
-      sqv += __shfl_xor(sqv, off);
-      swv += __shfl_xor(swv, off);
+      for (int c = 0; c < 8; ++c) {
+        sqv += (double)pv[c] * sa[8 * q + c];
+        swv += (double)pv[c] * lam[8 * q + c];
+      }
+      sqv += __shfl_xor(sqv, 1);
+      swv += __shfl_xor(swv, 1);
+      sqv += __shfl_xor(sqv, 2);
+      swv += __shfl_xor(swv, 2);
+      if (q == 0) {
+        sq[rr] = (double)qref[base + i] + sqv * dinv;
+        sw[rr] = swv;
+      }
     }
-    if (sub == 0) {
-      sq[rr] = (double)qref[base + i] + sqv * dinv;
-      sw[rr] = swv;
+  } else {
+    const int sub = tid % kSL;
+    for (int rr = tid / kSL; rr < nt + 2; rr += kRT / kSL) {
+      const int64_t i = wrap(t.cell0 - 1 + rr, n);
+      const T* pr = Phi + (base + i) * r;
+      double sqv = 0.0, swv = 0.0;
+      for (int c = sub; c < r; c += kSL) {
+        const double p = (double)pr[c];
+        sqv += p * sa[c];
+        swv += p * lam[c];
+      }
+#pragma unroll
+      for (int off = kSL / 2; off > 0; off >>= 1) {
+        sqv += __shfl_xor(sqv, off);
+        swv += __shfl_xor(swv, off);
+      }
+      if (sub == 0) {
+        sq[rr] = (double)qref[base + i] + sqv * dinv;
+        sw[rr] = swv;
+      }
     }
   }
   __syncthreads();
@@ -249,7 +334,6 @@ __global__ __launch_bounds__(kRT) void k_phibar_flush(
 // block per instance sums the partials in tile order and does the small work
 // (the core SVD's adjoint, pbar, p2bar, p1bar).  Rows are staged through LDS in
 // chunks of rows padded to r + 1 (as many as the LDS budget kEVLds holds).
-constexpr int kEV = 256;   // threads of the event adjoint's kernels
 constexpr int kEC = 32;    // rows of a staged chunk, at least
 constexpr int kETI = 4, kETJ = 4;   // register tile of the Ubar partials
 constexpr int kEVLds = 4352;    // doubles of LDS for the staged chunks (34 KB)
@@ -483,7 +567,8 @@ __global__ __launch_bounds__(kEV) void k_ev_a(
 //   * Phibar_old = Phibar' U[:r, :r]^T as two 16 x 16 tiles per block (eight
 //     products over m), written over the block's rows of phibar.
 // The four waves' partials are added in wave order; no block barrier inside
-// the row loop.
+// the row loop.  Phibar' is first completed by the K pending fine-step terms
+// (those k_phibar_flush would add; K = 0: none).
 typedef double d4_t __attribute__((ext_vector_type(4)));
 constexpr int kEA = 32;        // r of the matrix-core pass A
 constexpr int kEAL = kEA + 1;  // padded row of the staged blocks (doubles)
@@ -500,8 +585,11 @@ __global__ __launch_bounds__(kEV) __attribute__((amdgpu_waves_per_eu(3))) void k
     const double* __restrict__ dvar, const T* __restrict__ Phi, const T* __restrict__ ynew,
     const T* __restrict__ qref, const double* __restrict__ ubar, const double* __restrict__ prs,
     double* __restrict__ phibar, double* __restrict__ qs, double* __restrict__ js,
-    double* __restrict__ part) {
+    double* __restrict__ part, int K, int64_t total, const double2* __restrict__ puv,
+    const double* __restrict__ plam, const double* __restrict__ pa1, int n_inst) {
   constexpr int r = kEA, n = kEA + 1, NW = kEV / 64;
+  __shared__ double pl[kPhibarPending][kEA], pa[kPhibarPending][kEA];
+  __shared__ double2 wU[kEV / 64][kPhibarPending][16];   // the block rows' pending uv
   __shared__ double U[n * n];                    // U[c][m], row c of Ubar
   __shared__ double sp[r];
   __shared__ double wB[NW][16 * kEAL];           // the wave's Phibar' rows
@@ -516,6 +604,11 @@ __global__ __launch_bounds__(kEV) __attribute__((amdgpu_waves_per_eu(3))) void k
   if (irho == 0.0) return;   // rho = 0: the instance is flagged and skipped
   for (int e = tid; e < n * n; e += kEV) U[e] = ubar[(size_t)b * n * n + e];
   for (int c = tid; c < r; c += kEV) sp[c] = pr[c] + pr[r + c];
+  for (int e = tid; e < K * r; e += kEV) {
+    const int k = e / r, c = e - k * r;
+    pl[k][c] = plam[((size_t)k * n_inst + b) * r + c];
+    pa[k][c] = pa1[((size_t)k * n_inst + b) * r + c];
+  }
   __syncthreads();
   const int64_t base = dof_off[b] + t.cell0;
   const double* dvb = dvar + (size_t)b * nv;
@@ -544,6 +637,23 @@ __global__ __launch_bounds__(kEV) __attribute__((amdgpu_waves_per_eu(3))) void k
         const int e = lane + 64 * u, k = e >> 5;
         vb[u] = k < nr ? phibar[g0 * r + e] : 0.0;
         vp[u] = k < nr ? (double)Phi[g0 * r + e] : 0.0;
+      }
+      // the fine steps' pending Phibar terms, in the order k_phibar_flush adds
+      // them; their uv values of the block's rows go through LDS first
+      if (K > 0) {
+        for (int idx = lane; idx < K * 16; idx += 64) {
+          const int kk = idx >> 4, k = idx & 15;
+          wU[wave][kk][k] = k < nr ? puv[(size_t)kk * total + g0 + k] : make_double2(0.0, 0.0);
+        }
+        ev_wave_sync();
+        for (int kk = 0; kk < K; ++kk) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int e = lane + 64 * u, k = e >> 5, c = e & 31;
+            const double2 w = wU[wave][kk][k];
+            vb[u] += w.x * pl[kk][c] + w.y * pa[kk][c];
+          }
+        }
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -965,6 +1075,19 @@ __global__ void k_to_float(const double* __restrict__ x, float* __restrict__ y, 
 rom_status launch_online_seed(rom_batch* h, const void* qbar, double* abar, double* phibar,
                               hipStream_t s, double* qrbar, double* dvbar) {
   const int B = h->cfg.n_inst, r = h->cfg.r;
+  if (!qrbar) {   // no q_ref / D terms: by pass tiles
+    if (h->cfg.precision == ROM_F64)
+      hipLaunchKernelGGL((k_seed_tile<double>), dim3(h->n_ptiles), dim3(kEV), 0, s, h->d_ptiles,
+                         r, h->d_dof_off, h->d_var, h->nv, (const double*)h->Phi, h->a,
+                         (const double*)qbar, phibar, h->part);
+    else
+      hipLaunchKernelGGL((k_seed_tile<float>), dim3(h->n_ptiles), dim3(kEV), 0, s, h->d_ptiles,
+                         r, h->d_dof_off, h->d_var, h->nv, (const float*)h->Phi, h->a,
+                         (const float*)qbar, phibar, h->part);
+    hipLaunchKernelGGL(k_seed_abar, dim3(B), dim3(64), 0, s, r, h->d_ptile_first, h->part, abar);
+    ROM_HIP_CHECK(hipGetLastError());
+    return ROM_OK;
+  }
   if (h->cfg.precision == ROM_F64)
     hipLaunchKernelGGL((k_online_seed<double>), dim3(B), dim3(kAT), 0, s, r, h->d_dof_off,
                        h->d_var, (const double*)h->Phi, h->a, (const double*)qbar, abar, phibar,
@@ -986,8 +1109,10 @@ rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new
                             const double* sig_old, const double* a_old, const double* ubar,
                             const double* pr, const double* sig_new, double* abar,
                             double* phibar, double* sigbar, double* ybar, double* qs, double* js,
-                            double* evscr, hipStream_t s, double* qrbar, double* dvbar) {
+                            double* evscr, hipStream_t s, double* qrbar, double* dvbar,
+                            int K, const double2* puv, const double* plam, const double* pa1) {
   const int B = h->cfg.n_inst, r = h->cfg.r, n = r + 1, nv = h->nv;
+  if (r != kEA) ROM_TRY(launch_phibar_flush(h, K, puv, plam, pa1, phibar, s));
   double* part = evscr;
   double* evs = evscr + (size_t)std::max(h->n_ptiles, 1) * evp_ld(r);
   const size_t ntl = (size_t)ev_ntl(r);
@@ -1004,7 +1129,7 @@ rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new
     if (r == kEA)
       hipLaunchKernelGGL((k_ev_a_mfma<T>), dim3(nt), dim3(kEV), 0, s, h->d_ptiles, h->d_dof_off,
                          nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref,
-                         ubar, pr, phibar, qs, js, part);
+                         ubar, pr, phibar, qs, js, part, K, h->total_dof, puv, plam, pa1, B);
     else
       hipLaunchKernelGGL((k_ev_a<T>), dim3(nt), dim3(kEV), shm_a, s, h->d_ptiles, h->d_dof_off,
                          r, nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref,
@@ -1035,12 +1160,14 @@ rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new
 }
 
 rom_status launch_step_vjp_deferred(rom_batch* h, const void* Phi, const double* a1,
-                                    double* abar, double2* uv, hipStream_t s) {
+                                    double* abar, double2* uv, hipStream_t s,
+                                    const void* mpart) {
+  if (!mpart) mpart = h->mpart;
   const int B = h->cfg.n_inst, r = h->cfg.r;
   auto go = [&](auto tag) {
     using T = decltype(tag);
     hipLaunchKernelGGL((k_step_vjp_solve<T>), dim3(B), dim3(kAT), 0, s, r, h->cfg.dt,
-                       h->d_ptile_first, (const T*)h->mpart, mfma_ok(h) && r == 32 ? 1 : 0,
+                       h->d_ptile_first, (const T*)mpart, mfma_ok(h) && r == 32 ? 1 : 0,
                        abar, h->flags);
     hipLaunchKernelGGL((k_step_vjp_uv<T>), dim3(h->n_ptiles), dim3(kRT), 0, s, h->d_ptiles, r,
                        h->cfg.dt, h->d_dof_off, h->d_phys, h->cfg.n_phys, h->d_var,

@@ -1252,10 +1252,13 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
   // KP = min(z, kPhibarPending) steps of (uv, lambda, a1)
   const int KP = std::min(z, kPhibarPending);
   const size_t pend_b = (size_t)KP * (16 * (size_t)h->total_dof + 2 * br);
+  // per recorded step: the partials of its first Galerkin pass, which is taken
+  // at the previous step's converged state (that step's adjoint reuses them)
+  const size_t tap_b = h->esz * (size_t)std::max(h->n_ptiles, 1) * kMaxR * kMaxR;
   auto ws_bytes = [&](int64_t C) {
     const int64_t S = (T + C - 1) / C, nseg = (T + S - 1) / S, E = S / z + 1;
-    return (size_t)(nseg + 1) * state_b + (size_t)S * br + (size_t)E * ev_b + 2 * td8 +
-           2 * y_b + evscr_b + pend_b + 2048;
+    return (size_t)(nseg + 1) * state_b + (size_t)S * (br + tap_b) + (size_t)E * ev_b +
+           2 * td8 + 2 * y_b + evscr_b + pend_b + 4096;
   };
   // n_ckpt = 0: one segment (nothing recomputed) when its records fit in half
   // of the free device memory, else ceil(sqrt(n_fine)) checkpoints
@@ -1276,7 +1279,8 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
   std::vector<Host> hc(nseg + 1);
   char* ck = ws;
   char* rec_a = ck + (size_t)(nseg + 1) * state_b;
-  char* ev = rec_a + (size_t)S * br;
+  char* taps = rec_a + (size_t)S * br;
+  char* ev = taps + (size_t)S * tap_b;
   double* scr0 = (double*)(ev + (size_t)E * ev_b);
   double* scr1 = scr0 + h->total_dof;
   char* rhs = (char*)(scr1 + h->total_dof);
@@ -1326,7 +1330,9 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
     rom_status st = ROM_OK;
     after.clear();
     for (int64_t k = 0; k < L && st == ROM_OK; ++k) {
+      h->mpart_tap = taps + (size_t)k * tap_b;
       st = launch_rom_fine_step(h, s);
+      h->mpart_tap = nullptr;
       if (st == ROM_OK) st = copy_words(h->a, rec_a + (size_t)k * br, br, s);
       if (st == ROM_OK && due(h->n_fine)) {
         const int64_t e = (int64_t)after.size();
@@ -1361,7 +1367,8 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
     else if (st == ROM_OK)
       st = record(L, after_last);
   }
-  if (st == ROM_OK) st = save(nseg);
+  // the end state (one segment: the backward pass leaves the handle there)
+  if (st == ROM_OK && nseg > 1) st = save(nseg);
   // seed at the end state
   if (st == ROM_OK) st = launch_online_seed(h, qbar, abar, phibar, s);
   if (st == ROM_OK) st = fill_zero(sigbar, br, s);
@@ -1382,11 +1389,12 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
         if (after[e] >= k) { e_next = e; break; }
       if (e_next >= 0 && after[e_next] == k) {
         const int64_t e = e_next;
-        st = flush();   // the event reads Phibar
-        if (st == ROM_OK)
-          st = launch_event_vjp(h, ev_phi(e), ev_y(e), ev_sold(e), ev_aold(e), ev_u(e),
-                                ev_pr(e), ev_snew(e), abar, phibar, sigbar, ycbar, scr0, scr1,
-                                evscr, s);
+        // the event reads Phibar with the pending step terms added (its first
+        // pass adds them)
+        st = launch_event_vjp(h, ev_phi(e), ev_y(e), ev_sold(e), ev_aold(e), ev_u(e), ev_pr(e),
+                              ev_snew(e), abar, phibar, sigbar, ycbar, scr0, scr1, evscr, s,
+                              nullptr, nullptr, npend, pend_uv, pend_lam, pend_a1);
+        npend = 0;
         // coarse step y_new = BE(y_prev) over z dt: ybar <- J_r(y_new)^-T ybar
         if (st == ROM_OK) st = convert_words(ycbar, true, rhs, f64, h->total_dof, s);
         if (st == ROM_OK) st = launch_assemble_adjoint(h, ev_y(e), z * c.dt, rhs, s);
@@ -1396,18 +1404,26 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
       if (st != ROM_OK) break;
       void* phi_k = e_next >= 0 ? (void*)ev_phi(e_next) : h->Phi;
       double* a_k = (double*)(rec_a + (size_t)k * br);
-      void* phi_live = h->Phi;
-      double* a_live = h->a;
-      h->Phi = phi_k;
-      h->a = a_k;
-      st = prepare_galerkin_pass(h, s);
-      if (st == ROM_OK) st = launch_galerkin_pass(h, s);
-      h->Phi = phi_live;
-      h->a = a_live;
+      // J_g at a_k: step k + 1's first pass (same basis) if it was recorded,
+      // else a pass here
+      const bool ev_after = e_next >= 0 && after[e_next] == k;
+      const void* mp = nullptr;
+      if (k + 1 < L && !ev_after) {
+        mp = taps + (size_t)(k + 1) * tap_b;
+      } else {
+        void* phi_live = h->Phi;
+        double* a_live = h->a;
+        h->Phi = phi_k;
+        h->a = a_k;
+        st = prepare_galerkin_pass(h, s);
+        if (st == ROM_OK) st = launch_galerkin_pass(h, s);
+        h->Phi = phi_live;
+        h->a = a_live;
+      }
       if (st == ROM_OK && npend == KP) st = flush();
       if (st == ROM_OK) {
         st = launch_step_vjp_deferred(h, phi_k, a_k, abar, pend_uv + (size_t)npend * h->total_dof,
-                                      s);
+                                      s, mp);
         if (st == ROM_OK) st = copy_words(abar, pend_lam + (size_t)npend * B * r, br, s);
         if (st == ROM_OK) st = copy_words(a_k, pend_a1 + (size_t)npend * B * r, br, s);
         ++npend;
@@ -1415,7 +1431,7 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
     }
   }
   if (st == ROM_OK) st = flush();
-  if (st == ROM_OK) st = restore(nseg);
+  if (st == ROM_OK && nseg > 1) st = restore(nseg);
   hipError_t e = hipStreamSynchronize(s);
   (void)hipFree(ws);
   ROM_TRY(st);

@@ -40,7 +40,7 @@ constexpr int kTile = 256;          // cells per tile of the stencil kernels
 constexpr int kPassRows = 2048;     // basis rows per block of the tall-skinny passes
 constexpr int kMaxR = 64;           // largest reduced dimension supported
 constexpr int kMaxNs = 2 * kMaxR;   // largest number of DEIM rows
-constexpr int kPhibarPending = 8;   // step terms the online adjoint defers (Phibar flushes)
+constexpr int kPhibarPending = 4;   // step terms the online adjoint defers (Phibar flushes)
 
 // Position of element (i, j) of one tile's r x r block of Phi^T J_f Phi in the
 // partials the FP32 MFMA pass writes for r = 32.  The single-wave solve keeps
@@ -166,6 +166,7 @@ struct rom_batch {
   uint64_t* norms = nullptr; // Newton norms: 3 blocks of (newton_max+1) x n_inst (residual, iterate, update)
   double* rstate = nullptr;  // reduced Newton workspace [n_inst * (r*r + 4r)]
   double* qtmp = nullptr;    // first Gram-Schmidt residual [total_dof] (FP64)
+  void* mpart_tap = nullptr; // when set: receives a copy of mpart after a Galerkin step's first pass
   void* mpart = nullptr;     // Galerkin block partials of Phi^T J Phi [n_ptiles * kMaxR^2] (T;
                              // mpart_pos32 order when the FP32 MFMA pass wrote them for r = 32)
   double* epart = nullptr;   // projection partials of the event chain [n_ptiles * kMaxR^2]
@@ -261,7 +262,8 @@ rom_status launch_online_seed(rom_batch* h, const void* qbar, double* abar, doub
 // lambda = abar and a1 beside it) for launch_phibar_flush, which applies K of
 // them in one pass
 rom_status launch_step_vjp_deferred(rom_batch* h, const void* Phi, const double* a1,
-                                    double* abar, double2* uv, hipStream_t s);
+                                    double* abar, double2* uv, hipStream_t s,
+                                    const void* mpart = nullptr);
 rom_status launch_phibar_flush(rom_batch* h, int K, const double2* uv, const double* lam,
                                const double* a1, double* phibar, hipStream_t s);
 rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new,
@@ -269,7 +271,8 @@ rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new
                             const double* pr, const double* sig_new, double* abar,
                             double* phibar, double* sigbar, double* ybar, double* qs, double* js,
                             double* evscr, hipStream_t s, double* qrbar = nullptr,
-                            double* dvbar = nullptr);
+                            double* dvbar = nullptr, int K = 0, const double2* puv = nullptr,
+                            const double* plam = nullptr, const double* pa1 = nullptr);
 // doubles of the event adjoint's scratch (per-tile partials, per-instance vectors)
 size_t event_vjp_scratch_doubles(const rom_batch* h);
 rom_status convert_words(const void* src, bool src_f64, void* dst, bool dst_f64, int64_t n,

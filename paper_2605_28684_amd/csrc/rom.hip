@@ -1246,6 +1246,15 @@ __global__ void k_rom_step_setup(int n_inst, int r, const double* __restrict__ a
 // k_galerkin_tail, one block per instance that has not converged.
 constexpr int kGridNewton = 2;
 
+// the first pass of a step evaluates at the previous step's converged state:
+// its partials are what that step's adjoint needs (taken only on request)
+rom_status tap_mpart(rom_batch* h, hipStream_t s) {
+  ROM_HIP_CHECK(hipMemcpyAsync(h->mpart_tap, h->mpart,
+                               h->esz * (size_t)std::max(h->n_ptiles, 1) * kMaxR * kMaxR,
+                               hipMemcpyDeviceToDevice, s));
+  return ROM_OK;
+}
+
 template <typename T>
 rom_status galerkin_step_t(rom_batch* h, hipStream_t s) {
   const int r = h->cfg.r, B = h->cfg.n_inst;
@@ -1259,6 +1268,7 @@ rom_status galerkin_step_t(rom_batch* h, hipStream_t s) {
       const int first = it == 0 ? 1 : 0;
       rom_status st = launch_galerkin_mfma(h, s, first);
       if (st != ROM_OK) return st;
+      if (first && h->mpart_tap) ROM_TRY(tap_mpart(h, s));
       if (r == 32)  // register-resident single-wave solve (r = 64 rows do not fit)
         hipLaunchKernelGGL(k_galerkin_solve_w<32>, dim3(B), dim3(64), 0, s, h->d_ptile_first,
                            gpart, (const float*)h->mpart, h->cfg.dt, h->d_var, h->a, h->a_prev,
@@ -1278,6 +1288,7 @@ rom_status galerkin_step_t(rom_batch* h, hipStream_t s) {
     hipLaunchKernelGGL((k_galerkin_pass<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                        h->d_dof_off, h->d_cell_off, h->d_phys, h->cfg.n_phys, (const T*)h->Phi,
                        r, (const T*)h->q_ref, h->d_var, h->a, h->active, gpart, (T*)h->mpart);
+    if (it == 0 && h->mpart_tap) ROM_TRY(tap_mpart(h, s));
     hipLaunchKernelGGL((k_galerkin_solve<T>), dim3(B), dim3(256), 0, s, h->d_ptile_first, gpart,
                        (const T*)h->mpart, r, h->cfg.dt, h->d_var, h->a, h->a_prev, h->active,
                        h->iters, h->cfg.rom_tol, h->flags, 0);
