@@ -314,6 +314,31 @@ __global__ __launch_bounds__(kRT) void k_phibar_flush(
   }
   __syncthreads();
   const int64_t g0 = dof_off[b] + t.cell0;
+  if (r % 8 == 0) {
+    // four threads per row, r / 4 contiguous columns each (double2 accesses);
+    // a row's K uv pairs are loaded once per thread
+    const int q = tid & 3, w4 = r / 4;
+    for (int64_t i = tid >> 2; i < t.ncell; i += kRT / 4) {
+      double2 wk[KM];
+#pragma unroll
+      for (int k = 0; k < KM; ++k)
+        wk[k] = k < K ? uv[(size_t)k * total + g0 + i] : make_double2(0.0, 0.0);
+      double2* pb = reinterpret_cast<double2*>(phibar + (g0 + i) * r + q * w4);
+      for (int m = 0; m < w4 / 2; ++m) {
+        double2 p = pb[m];
+        const int c = q * w4 + 2 * m;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          if (k < K) {
+            p.x += wk[k].x * sl[k][c] + wk[k].y * sa[k][c];
+            p.y += wk[k].x * sl[k][c + 1] + wk[k].y * sa[k][c + 1];
+          }
+        }
+        pb[m] = p;
+      }
+    }
+    return;
+  }
   const int64_t ne = t.ncell * r;
   for (int64_t e = tid; e < ne; e += kRT) {
     const int64_t i = e / r;
@@ -601,16 +626,29 @@ __global__ __launch_bounds__(kEV) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int b = t.inst;
   const double* pr = prs + (size_t)b * (2 * r + 2);
   const double irho = pr[2 * r];
-  if (irho == 0.0) return;   // rho = 0: the instance is flagged and skipped
-  for (int e = tid; e < n * n; e += kEV) U[e] = ubar[(size_t)b * n * n + e];
-  for (int c = tid; c < r; c += kEV) sp[c] = pr[c] + pr[r + c];
   for (int e = tid; e < K * r; e += kEV) {
     const int k = e / r, c = e - k * r;
     pl[k][c] = plam[((size_t)k * n_inst + b) * r + c];
     pa[k][c] = pa1[((size_t)k * n_inst + b) * r + c];
   }
-  __syncthreads();
   const int64_t base = dof_off[b] + t.cell0;
+  if (irho == 0.0) {   // rho = 0: flagged and skipped; the pending terms still land
+    __syncthreads();
+    for (int64_t e = tid; e < t.ncell * r; e += kEV) {
+      const int64_t k = e / r;
+      const int c = (int)(e - k * r);
+      double p = phibar[base * r + e];
+      for (int kk = 0; kk < K; ++kk) {
+        const double2 w = puv[(size_t)kk * total + base + k];
+        p += w.x * pl[kk][c] + w.y * pa[kk][c];
+      }
+      phibar[base * r + e] = p;
+    }
+    return;
+  }
+  for (int e = tid; e < n * n; e += kEV) U[e] = ubar[(size_t)b * n * n + e];
+  for (int c = tid; c < r; c += kEV) sp[c] = pr[c] + pr[r + c];
+  __syncthreads();
   const double* dvb = dvar + (size_t)b * nv;
   double* cB = wB[wave];
   double* cP = wP[wave];
@@ -903,15 +941,32 @@ __global__ __launch_bounds__(kEV) void k_ev_b(const Tile* __restrict__ tiles,
   ev_colsum_out(acc, r, scr, part + (size_t)blockIdx.x * evp_ld(r));
 }
 
+// A kept Phibar term that adds nothing: zero rows of the tile and, by the
+// instance's first tile, zero coefficients.
+DEV void ev_pending_zero(const Tile& t, const int64_t* __restrict__ dof_off, int r,
+                         double2* __restrict__ uv, double* __restrict__ ulam,
+                         double* __restrict__ ua1) {
+  const int64_t g0 = dof_off[t.inst] + t.cell0;
+  for (int64_t k = threadIdx.x; k < t.ncell; k += blockDim.x) uv[g0 + k] = make_double2(0.0, 0.0);
+  if (t.cell0 == 0)
+    for (int c = threadIdx.x; c < r; c += blockDim.x) {
+      ulam[(size_t)t.inst * r + c] = 0.0;
+      ua1[(size_t)t.inst * r + c] = 0.0;
+    }
+}
+
 // Pass C: q1 = yhat - Phi p1; q1bar = qbar + Phi p2bar (into js);
-// Phibar_old += -qbar p2^T + q1 p2bar^T; partials of Phi^T q1bar.
+// Phibar_old += -qbar p2^T + q1 p2bar^T; partials of Phi^T q1bar.  With uv,
+// the Phibar term is kept instead (uv = (-qbar, q1) per row, coefficients p2
+// and p2bar) for a later pass over Phibar, and Phibar is not read.
 template <typename T>
 __global__ __launch_bounds__(kEV) void k_ev_c(
     const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off, int r, int nv,
     const double* __restrict__ dvar, const T* __restrict__ Phi, const T* __restrict__ ynew,
     const T* __restrict__ qref, const double* __restrict__ prs, const double* __restrict__ evs,
     const double* __restrict__ qs, double* __restrict__ js, double* __restrict__ phibar,
-    double* __restrict__ part) {
+    double* __restrict__ part, double2* __restrict__ uv, double* __restrict__ ulam,
+    double* __restrict__ ua1) {
   extern __shared__ double sm[];
   __shared__ double p1[kMaxR], p2[kMaxR], p2b[kMaxR];
   const int LDR = r + 1, tid = threadIdx.x;
@@ -919,13 +974,20 @@ __global__ __launch_bounds__(kEV) void k_ev_c(
   const int b = t.inst;
   const double* pr = prs + (size_t)b * (2 * r + 2);
   const double irho = pr[2 * r];
-  if (irho == 0.0) return;
+  if (irho == 0.0) {   // rho = 0: flagged and skipped; a kept term adds nothing
+    if (uv) ev_pending_zero(t, dof_off, r, uv, ulam, ua1);
+    return;
+  }
   const double* e_in = evs + (size_t)b * evs_ld(r);
   const double rhob = e_in[r];
   for (int c = tid; c < r; c += kEV) {
     p1[c] = pr[c];
     p2[c] = pr[r + c];
     p2b[c] = e_in[r + 1 + c];
+    if (uv && t.cell0 == 0) {   // the term's coefficients, by the instance's first tile
+      ulam[(size_t)b * r + c] = pr[r + c];
+      ua1[(size_t)b * r + c] = e_in[r + 1 + c];
+    }
   }
   const int CH = ev_chunk(r);
   double* cP = sm;
@@ -941,7 +1003,7 @@ __global__ __launch_bounds__(kEV) void k_ev_c(
     const int nr = (int)(t.ncell - r0 < CH ? t.ncell - r0 : CH);
     const int64_t g0 = base + t.cell0 + r0;
     __syncthreads();
-    ev_stage(Phi, phibar, g0, nr, r, cP, cB);
+    ev_stage(Phi, phibar, g0, nr, r, cP, uv ? nullptr : cB);
     __syncthreads();
     for (int k = tid; k < nr; k += kEV) {
       const int64_t g = g0 + k;
@@ -956,12 +1018,14 @@ __global__ __launch_bounds__(kEV) void k_ev_c(
       c1[k] = q1;
       c2[k] = qb + tt;   // q1bar
       js[g] = qb + tt;
+      if (uv) uv[g] = make_double2(-qb, q1);   // the Phibar term, kept
     }
     __syncthreads();
-    for (int e = tid; e < nr * r; e += kEV) {
-      const int k = e / r, c = e % r;
-      phibar[g0 * r + e] = cB[k * LDR + c] - c0[k] * p2[c] + c1[k] * p2b[c];
-    }
+    if (!uv)
+      for (int e = tid; e < nr * r; e += kEV) {
+        const int k = e / r, c = e % r;
+        phibar[g0 * r + e] = cB[k * LDR + c] - c0[k] * p2[c] + c1[k] * p2b[c];
+      }
     ev_colsum(cP, c2, nr, r, acc);
   }
   ev_colsum_out(acc, r, scr, part + (size_t)blockIdx.x * evp_ld(r));
@@ -969,14 +1033,16 @@ __global__ __launch_bounds__(kEV) void k_ev_c(
 
 // Pass D: Phibar_old += -q1bar p1^T + yhat p1bar^T; yhatbar = q1bar + Phi p1bar;
 // ybar += D yhatbar; with qrbar: qrbar -= D yhatbar and partials of
-// sum yhatbar (y - q_ref) per variable.
+// sum yhatbar (y - q_ref) per variable.  With uv, the Phibar term is kept
+// (uv = (-q1bar, yhat), coefficients p1 and p1bar).
 template <typename T>
 __global__ __launch_bounds__(kEV) void k_ev_d(
     const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off, int r, int nv,
     const double* __restrict__ dvar, const T* __restrict__ Phi, const T* __restrict__ ynew,
     const T* __restrict__ qref, const double* __restrict__ prs, const double* __restrict__ evs,
     const double* __restrict__ js, double* __restrict__ phibar, double* __restrict__ ybar,
-    double* __restrict__ qrbar, double* __restrict__ part) {
+    double* __restrict__ qrbar, double* __restrict__ part, double2* __restrict__ uv,
+    double* __restrict__ ulam, double* __restrict__ ua1) {
   extern __shared__ double sm[];
   __shared__ double p1[kMaxR], p1b[kMaxR];
   __shared__ double red[kEV / 64];
@@ -984,11 +1050,18 @@ __global__ __launch_bounds__(kEV) void k_ev_d(
   const Tile t = tiles[blockIdx.x];
   const int b = t.inst;
   const double* pr = prs + (size_t)b * (2 * r + 2);
-  if (pr[2 * r] == 0.0) return;
+  if (pr[2 * r] == 0.0) {
+    if (uv) ev_pending_zero(t, dof_off, r, uv, ulam, ua1);
+    return;
+  }
   const double* e_in = evs + (size_t)b * evs_ld(r);
   for (int c = tid; c < r; c += kEV) {
     p1[c] = pr[c];
     p1b[c] = e_in[2 * r + 1 + c];
+    if (uv && t.cell0 == 0) {
+      ulam[(size_t)b * r + c] = pr[c];
+      ua1[(size_t)b * r + c] = e_in[2 * r + 1 + c];
+    }
   }
   const int CH = ev_chunk(r);
   double* cP = sm;
@@ -1003,7 +1076,7 @@ __global__ __launch_bounds__(kEV) void k_ev_d(
     const int nr = (int)(t.ncell - r0 < CH ? t.ncell - r0 : CH);
     const int64_t g0 = base + t.cell0 + r0;
     __syncthreads();
-    ev_stage(Phi, phibar, g0, nr, r, cP, cB);
+    ev_stage(Phi, phibar, g0, nr, r, cP, uv ? nullptr : cB);
     __syncthreads();
     for (int k = tid; k < nr; k += kEV) {
       const int64_t g = g0 + k;
@@ -1015,6 +1088,7 @@ __global__ __launch_bounds__(kEV) void k_ev_d(
       for (int c = 0; c < r; ++c) tt += cP[k * LDR + c] * p1b[c];
       c0[k] = q1b;
       c1[k] = d * dy;
+      if (uv) uv[g] = make_double2(-q1b, d * dy);   // the Phibar term, kept
       ybar[g] += d * (q1b + tt);
       if (qrbar) {
         qrbar[g] -= d * (q1b + tt);
@@ -1023,16 +1097,156 @@ __global__ __launch_bounds__(kEV) void k_ev_d(
       }
     }
     __syncthreads();
-    for (int e = tid; e < nr * r; e += kEV) {
-      const int k = e / r, c = e % r;
-      phibar[g0 * r + e] = cB[k * LDR + c] - c0[k] * p1[c] + c1[k] * p1b[c];
-    }
+    if (!uv)
+      for (int e = tid; e < nr * r; e += kEV) {
+        const int k = e / r, c = e % r;
+        phibar[g0 * r + e] = cB[k * LDR + c] - c0[k] * p1[c] + c1[k] * p1b[c];
+      }
   }
   if (qrbar) {
     double* out = part + (size_t)blockIdx.x * evp_ld(r);
     for (int v = 0; v < nv; ++v) {
       const double s = block_sum(dva[v], red);
       if (tid == 0) out[v] = s;
+    }
+  }
+}
+
+// Passes C and D for r = 32 with their Phibar terms kept (the online adjoint's
+// layout): four lanes per row, eight columns each loaded straight from the
+// basis, row dot products by a quad butterfly; no LDS staging.  Pass C also
+// sums Phi^T q1bar per column: each lane keeps its eight columns' sums, and
+// the 64 row groups' sums are added in group order at the end of the tile.
+template <typename T>
+DEV void ev_load8(const T* __restrict__ p, double (&v)[8]) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 a = reinterpret_cast<const float4*>(p)[0], b = reinterpret_cast<const float4*>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double2 a = reinterpret_cast<const double2*>(p)[u];
+      v[2 * u] = a.x;
+      v[2 * u + 1] = a.y;
+    }
+  }
+}
+
+DEV double quad_sum(double x) {
+  x += __shfl_xor(x, 1);
+  return x + __shfl_xor(x, 2);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kEV) void k_ev_c32(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off, int nv,
+    const double* __restrict__ dvar, const T* __restrict__ Phi, const T* __restrict__ ynew,
+    const T* __restrict__ qref, const double* __restrict__ prs, const double* __restrict__ evs,
+    const double* __restrict__ qs, double* __restrict__ js, double* __restrict__ part,
+    double2* __restrict__ uv, double* __restrict__ ulam, double* __restrict__ ua1) {
+  constexpr int r = 32;
+  __shared__ double p1[r], p2b[r];
+  __shared__ double red[kEV / 4][r + 1];
+  const int tid = threadIdx.x, q = tid & 3;
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  const double* pr = prs + (size_t)b * (2 * r + 2);
+  const double irho = pr[2 * r];
+  if (irho == 0.0) {
+    ev_pending_zero(t, dof_off, r, uv, ulam, ua1);
+    return;
+  }
+  const double* e_in = evs + (size_t)b * evs_ld(r);
+  const double rhob = e_in[r];
+  for (int c = tid; c < r; c += kEV) {
+    p1[c] = pr[c];
+    p2b[c] = e_in[r + 1 + c];
+    if (t.cell0 == 0) {
+      ulam[(size_t)b * r + c] = pr[r + c];
+      ua1[(size_t)b * r + c] = e_in[r + 1 + c];
+    }
+  }
+  __syncthreads();
+  const int64_t g0 = dof_off[b] + t.cell0;
+  const double* dvb = dvar + (size_t)b * nv;
+  double acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+  for (int64_t k = tid >> 2; k < t.ncell; k += kEV / 4) {
+    const int64_t g = g0 + k;
+    double v[8];
+    ev_load8(Phi + g * r + 8 * q, v);
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      s1 += v[u] * p1[8 * q + u];
+      s2 += v[u] * p2b[8 * q + u];
+    }
+    s1 = quad_sum(s1);
+    s2 = quad_sum(s2);
+    const double q1 = dvb[(t.cell0 + k) % nv] * ((double)ynew[g] - (double)qref[g]) - s1;
+    const double qb = (js[g] + rhob * qs[g]) * irho;
+    const double q1b = qb + s2;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += v[u] * q1b;
+    if (q == 0) {
+      js[g] = q1b;
+      uv[g] = make_double2(-qb, q1);
+    }
+  }
+  // column sums: thread (row group rg, quarter q) holds columns 8 q .. 8 q + 7
+#pragma unroll
+  for (int u = 0; u < 8; ++u) red[tid >> 2][8 * q + u] = acc[u];
+  __syncthreads();
+  if (tid < r) {
+    double sum = 0.0;
+    for (int gq = 0; gq < kEV / 4; ++gq) sum += red[gq][tid];
+    part[(size_t)blockIdx.x * evp_ld(r) + tid] = sum;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kEV) void k_ev_d32(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off, int nv,
+    const double* __restrict__ dvar, const T* __restrict__ Phi, const T* __restrict__ ynew,
+    const T* __restrict__ qref, const double* __restrict__ prs, const double* __restrict__ evs,
+    const double* __restrict__ js, double* __restrict__ ybar, double2* __restrict__ uv,
+    double* __restrict__ ulam, double* __restrict__ ua1) {
+  constexpr int r = 32;
+  __shared__ double p1b[r];
+  const int tid = threadIdx.x, q = tid & 3;
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  const double* pr = prs + (size_t)b * (2 * r + 2);
+  if (pr[2 * r] == 0.0) {
+    ev_pending_zero(t, dof_off, r, uv, ulam, ua1);
+    return;
+  }
+  const double* e_in = evs + (size_t)b * evs_ld(r);
+  for (int c = tid; c < r; c += kEV) {
+    p1b[c] = e_in[2 * r + 1 + c];
+    if (t.cell0 == 0) {
+      ulam[(size_t)b * r + c] = pr[c];
+      ua1[(size_t)b * r + c] = e_in[2 * r + 1 + c];
+    }
+  }
+  __syncthreads();
+  const int64_t g0 = dof_off[b] + t.cell0;
+  const double* dvb = dvar + (size_t)b * nv;
+  for (int64_t k = tid >> 2; k < t.ncell; k += kEV / 4) {
+    const int64_t g = g0 + k;
+    double v[8];
+    ev_load8(Phi + g * r + 8 * q, v);
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u] * p1b[8 * q + u];
+    s = quad_sum(s);
+    if (q == 0) {
+      const double d = dvb[(t.cell0 + k) % nv];
+      const double dy = (double)ynew[g] - (double)qref[g];
+      const double q1b = js[g];
+      ybar[g] += d * (q1b + s);
+      uv[g] = make_double2(-q1b, d * dy);
     }
   }
 }
@@ -1110,9 +1324,33 @@ rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new
                             const double* pr, const double* sig_new, double* abar,
                             double* phibar, double* sigbar, double* ybar, double* qs, double* js,
                             double* evscr, hipStream_t s, double* qrbar, double* dvbar,
-                            int K, const double2* puv, const double* plam, const double* pa1) {
+                            int* npend, int kp, double2* puv, double* plam, double* pa1) {
   const int B = h->cfg.n_inst, r = h->cfg.r, n = r + 1, nv = h->nv;
-  if (r != kEA) ROM_TRY(launch_phibar_flush(h, K, puv, plam, pa1, phibar, s));
+  // pending Phibar terms: pass A adds them (r = 32; else a flush first); passes
+  // C and D keep theirs as two more while there is room
+  int K = npend ? *npend : 0;
+  if (r != kEA) {
+    ROM_TRY(launch_phibar_flush(h, K, puv, plam, pa1, phibar, s));
+    K = 0;
+  }
+  const int kA = K;
+  K = 0;
+  auto slot = [&](double2*& u, double*& l, double*& a1) {
+    if (npend && K < kp) {
+      u = puv + (size_t)K * h->total_dof;
+      l = plam + (size_t)K * B * r;
+      a1 = pa1 + (size_t)K * B * r;
+      ++K;
+    } else {
+      u = nullptr;
+      l = a1 = nullptr;
+    }
+  };
+  double2 *uC, *uD;
+  double *lC, *aC, *lD, *aD;
+  slot(uC, lC, aC);
+  slot(uD, lD, aD);
+  if (npend) *npend = K;
   double* part = evscr;
   double* evs = evscr + (size_t)std::max(h->n_ptiles, 1) * evp_ld(r);
   const size_t ntl = (size_t)ev_ntl(r);
@@ -1129,7 +1367,7 @@ rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new
     if (r == kEA)
       hipLaunchKernelGGL((k_ev_a_mfma<T>), dim3(nt), dim3(kEV), 0, s, h->d_ptiles, h->d_dof_off,
                          nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref,
-                         ubar, pr, phibar, qs, js, part, K, h->total_dof, puv, plam, pa1, B);
+                         ubar, pr, phibar, qs, js, part, kA, h->total_dof, puv, plam, pa1, B);
     else
       hipLaunchKernelGGL((k_ev_a<T>), dim3(nt), dim3(kEV), shm_a, s, h->d_ptiles, h->d_dof_off,
                          r, nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref,
@@ -1141,14 +1379,24 @@ rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new
                        (const T*)Phi_old, pr, evs, qs, js, part);
     hipLaunchKernelGGL(k_ev_vec, dim3(B), dim3(64), 0, s, r, h->d_ptile_first, pr, part, evs,
                        r + 1, nv, (double*)nullptr);
-    hipLaunchKernelGGL((k_ev_c<T>), dim3(nt), dim3(kEV), shm_c, s, h->d_ptiles, h->d_dof_off, r,
-                       nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref, pr,
-                       evs, qs, js, phibar, part);
+    if (r == 32 && uC)
+      hipLaunchKernelGGL((k_ev_c32<T>), dim3(nt), dim3(kEV), 0, s, h->d_ptiles, h->d_dof_off, nv,
+                         h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref, pr,
+                         evs, qs, js, part, uC, lC, aC);
+    else
+      hipLaunchKernelGGL((k_ev_c<T>), dim3(nt), dim3(kEV), shm_c, s, h->d_ptiles, h->d_dof_off,
+                         r, nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref,
+                         pr, evs, qs, js, phibar, part, uC, lC, aC);
     hipLaunchKernelGGL(k_ev_vec, dim3(B), dim3(64), 0, s, r, h->d_ptile_first, pr, part, evs,
                        2 * r + 1, nv, (double*)nullptr);
-    hipLaunchKernelGGL((k_ev_d<T>), dim3(nt), dim3(kEV), shm_d, s, h->d_ptiles, h->d_dof_off, r,
-                       nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref, pr,
-                       evs, js, phibar, ybar, qrbar, part);
+    if (r == 32 && uD && !qrbar)
+      hipLaunchKernelGGL((k_ev_d32<T>), dim3(nt), dim3(kEV), 0, s, h->d_ptiles, h->d_dof_off, nv,
+                         h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref, pr,
+                         evs, js, ybar, uD, lD, aD);
+    else
+      hipLaunchKernelGGL((k_ev_d<T>), dim3(nt), dim3(kEV), shm_d, s, h->d_ptiles, h->d_dof_off, r,
+                         nv, h->d_var, (const T*)Phi_old, (const T*)y_new, (const T*)h->q_ref, pr,
+                         evs, js, phibar, ybar, qrbar, part, uD, lD, aD);
     if (qrbar)
       hipLaunchKernelGGL(k_ev_vec, dim3(B), dim3(64), 0, s, r, h->d_ptile_first, pr, part, evs,
                          0, nv, dvbar);

@@ -1248,9 +1248,10 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
   const size_t ev_b = phi_b + y_b + 3 * br + 8 * (size_t)B * n * n + 8 * (size_t)B * (2 * r + 2);
   const size_t td8 = 8 * (size_t)h->total_dof;
   const size_t evscr_b = 8 * event_vjp_scratch_doubles(h);
-  // the fine steps' Phibar terms wait for one pass per window: up to
-  // KP = min(z, kPhibarPending) steps of (uv, lambda, a1)
-  const int KP = std::min(z, kPhibarPending);
+  // Phibar terms (a window's fine steps, and two per event) wait for one pass
+  // over Phibar per window: up to KP = min(z + 2, kPhibarPending) of
+  // (uv, lambda, a1)
+  const int KP = std::min(z + 2, kPhibarPending);
   const size_t pend_b = (size_t)KP * (16 * (size_t)h->total_dof + 2 * br);
   // per recorded step: the partials of its first Galerkin pass, which is taken
   // at the previous step's converged state (that step's adjoint reuses them)
@@ -1393,8 +1394,7 @@ rom_status rom_online_vjp(rom_handle h, int32_t n_fine, int32_t n_ckpt, const vo
         // pass adds them)
         st = launch_event_vjp(h, ev_phi(e), ev_y(e), ev_sold(e), ev_aold(e), ev_u(e), ev_pr(e),
                               ev_snew(e), abar, phibar, sigbar, ycbar, scr0, scr1, evscr, s,
-                              nullptr, nullptr, npend, pend_uv, pend_lam, pend_a1);
-        npend = 0;
+                              nullptr, nullptr, &npend, KP, pend_uv, pend_lam, pend_a1);
         // coarse step y_new = BE(y_prev) over z dt: ybar <- J_r(y_new)^-T ybar
         if (st == ROM_OK) st = convert_words(ycbar, true, rhs, f64, h->total_dof, s);
         if (st == ROM_OK) st = launch_assemble_adjoint(h, ev_y(e), z * c.dt, rhs, s);

@@ -40,7 +40,7 @@ constexpr int kTile = 256;          // cells per tile of the stencil kernels
 constexpr int kPassRows = 2048;     // basis rows per block of the tall-skinny passes
 constexpr int kMaxR = 64;           // largest reduced dimension supported
 constexpr int kMaxNs = 2 * kMaxR;   // largest number of DEIM rows
-constexpr int kPhibarPending = 4;   // step terms the online adjoint defers (Phibar flushes)
+constexpr int kPhibarPending = 6;   // Phibar terms the online adjoint keeps for one pass
 
 // Position of element (i, j) of one tile's r x r block of Phi^T J_f Phi in the
 // partials the FP32 MFMA pass writes for r = 32.  The single-wave solve keeps
@@ -271,8 +271,9 @@ rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new
                             const double* pr, const double* sig_new, double* abar,
                             double* phibar, double* sigbar, double* ybar, double* qs, double* js,
                             double* evscr, hipStream_t s, double* qrbar = nullptr,
-                            double* dvbar = nullptr, int K = 0, const double2* puv = nullptr,
-                            const double* plam = nullptr, const double* pa1 = nullptr);
+                            double* dvbar = nullptr, int* npend = nullptr, int kp = 0,
+                            double2* puv = nullptr, double* plam = nullptr,
+                            double* pa1 = nullptr);
 // doubles of the event adjoint's scratch (per-tile partials, per-instance vectors)
 size_t event_vjp_scratch_doubles(const rom_batch* h);
 rom_status convert_words(const void* src, bool src_f64, void* dst, bool dst_f64, int64_t n,
