@@ -1205,6 +1205,43 @@ __global__ __launch_bounds__(kEV) void k_ev_c32(
   }
 }
 
+// Pass B for r = 32 in the same layout: qbar per row, column sums of
+// Phi^T qbar per lane, the row groups added in order.
+template <typename T>
+__global__ __launch_bounds__(kEV) void k_ev_b32(
+    const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off,
+    const T* __restrict__ Phi, const double* __restrict__ prs, const double* __restrict__ evs,
+    const double* __restrict__ qs, const double* __restrict__ js, double* __restrict__ part) {
+  constexpr int r = 32;
+  __shared__ double red[kEV / 4][r + 1];
+  const int tid = threadIdx.x, q = tid & 3;
+  const Tile t = tiles[blockIdx.x];
+  const int b = t.inst;
+  const double irho = prs[(size_t)b * (2 * r + 2) + 2 * r];
+  if (irho == 0.0) return;
+  const double rhob = evs[(size_t)b * evs_ld(r) + r];
+  const int64_t g0 = dof_off[b] + t.cell0;
+  double acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+  for (int64_t k = tid >> 2; k < t.ncell; k += kEV / 4) {
+    const int64_t g = g0 + k;
+    double v[8];
+    ev_load8(Phi + g * r + 8 * q, v);
+    const double qb = (js[g] + rhob * qs[g]) * irho;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += v[u] * qb;
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) red[tid >> 2][8 * q + u] = acc[u];
+  __syncthreads();
+  if (tid < r) {
+    double sum = 0.0;
+    for (int gq = 0; gq < kEV / 4; ++gq) sum += red[gq][tid];
+    part[(size_t)blockIdx.x * evp_ld(r) + tid] = sum;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kEV) void k_ev_d32(
     const Tile* __restrict__ tiles, const int64_t* __restrict__ dof_off, int nv,
@@ -1375,8 +1412,12 @@ rom_status launch_event_vjp(rom_batch* h, const void* Phi_old, const void* y_new
     hipLaunchKernelGGL(k_ev_core, dim3(B), dim3(kEV), shm_core, s, r, h->cfg.lambda,
                        h->d_ptile_first, part, sig_old, a_old, ubar, pr, sig_new, abar, sigbar,
                        evs, h->flags);
-    hipLaunchKernelGGL((k_ev_b<T>), dim3(nt), dim3(kEV), shm_b, s, h->d_ptiles, h->d_dof_off, r,
-                       (const T*)Phi_old, pr, evs, qs, js, part);
+    if (r == 32)
+      hipLaunchKernelGGL((k_ev_b32<T>), dim3(nt), dim3(kEV), 0, s, h->d_ptiles, h->d_dof_off,
+                         (const T*)Phi_old, pr, evs, qs, js, part);
+    else
+      hipLaunchKernelGGL((k_ev_b<T>), dim3(nt), dim3(kEV), shm_b, s, h->d_ptiles, h->d_dof_off,
+                         r, (const T*)Phi_old, pr, evs, qs, js, part);
     hipLaunchKernelGGL(k_ev_vec, dim3(B), dim3(64), 0, s, r, h->d_ptile_first, pr, part, evs,
                        r + 1, nv, (double*)nullptr);
     if (r == 32 && uC)
