@@ -41,7 +41,7 @@ MFMA_F32_TFLOPS = 157.3
 # summaries of those runs are kept in the profiles directory.
 COPY_SCALE = {"fetch": 524288.0 / 262157.4, "write": 1.0}
 MEASURED_KIB = {
-    "k_galerkin_mfma<32>": {"fetch": 133474.3, "write": 4245.8},
+    "k_galerkin_mfma<32>": {"fetch": 133445.3, "write": 4245.8},
     # streaming Euler residual on the 64 x 262,144-cell shape, every launch shape
     # of the autotuner (bench.py --only residual walks them in order)
     "k_residual_euler/0": {"fetch": 101935.9, "write": 196608.0},
@@ -585,7 +585,8 @@ def main():
         "roofline_mfma": roofline_mfma,
         "other_configs": configs,
         "online_adjoint": {"ms_per_window": round(adj_ms, 3), "windows": 2,
-                           "what": "rom_online_vjp: forward, sqrt(T) checkpointed recompute, "
+                           "what": "rom_online_vjp: forward recording the horizon (sqrt(T) "
+                                   "checkpoints and recomputation when memory is short), "
                                    "reverse (transposed reduced solves, iSVD backward, "
                                    "transposed banded solves)"},
     }
