@@ -143,6 +143,38 @@ __global__ __launch_bounds__(kEV) void k_seed_tile(
   __syncthreads();
   const int64_t g0 = dof_off[b] + t.cell0;
   const double* dvb = dvar + (size_t)b * nv;
+  if (r % 2 == 0 && kEV % (r / 2) == 0) {
+    // column pairs: thread (g, c) always on columns 2c, 2c + 1 of every row of
+    // group g; the pair sums are added over the groups in order as above
+    const int hr = r / 2, G2 = kEV / hr, c2 = tid % hr;
+    const int64_t ne2 = t.ncell * hr;
+    double ax = 0.0, ay = 0.0;
+    double2* pb = reinterpret_cast<double2*>(phibar + g0 * r);
+#pragma unroll 4
+    for (int64_t e = tid; e < ne2; e += kEV) {
+      const int64_t k = e / hr;
+      const double cq = (double)qbar[g0 + k] / dvb[(t.cell0 + k) % nv];
+      const T* pp = Phi + g0 * r + 2 * e;
+      ax += (double)pp[0] * cq;
+      ay += (double)pp[1] * cq;
+      pb[e] = make_double2(cq * sa[2 * c2], cq * sa[2 * c2 + 1]);
+    }
+    red[tid] = ax;
+    __syncthreads();
+    double sx = 0.0;
+    if (tid < hr)
+      for (int g = 0; g < G2; ++g) sx += red[g * hr + tid];
+    __syncthreads();
+    red[tid] = ay;
+    __syncthreads();
+    if (tid < hr) {
+      double sy = 0.0;
+      for (int g = 0; g < G2; ++g) sy += red[g * hr + tid];
+      part[(size_t)blockIdx.x * r + 2 * tid] = sx;
+      part[(size_t)blockIdx.x * r + 2 * tid + 1] = sy;
+    }
+    return;
+  }
   const int64_t ne = t.ncell * r, step = (int64_t)G * r;
   double acc = 0.0;
   if (on) {
