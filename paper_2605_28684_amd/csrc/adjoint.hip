@@ -699,14 +699,22 @@ __global__ __launch_bounds__(kEV) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int64_t r0 = (int64_t)kb * 16;
     const int nr = (int)(t.ncell - r0 < 16 ? t.ncell - r0 : 16);
     const int64_t g0 = base + r0;
-    // stage 16 rows: eight elements of each array per lane, loads first
+    // stage 16 rows: eight elements of each array per lane, loads first (all
+    // sixteen issued together: rows past the tile read its last row, then are
+    // zeroed; a load under a condition would be waited for on its own)
     {
       double vb[8], vp[8];
+      const int emax = nr * r - 1;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int e = lane + 64 * u, k = e >> 5;
-        vb[u] = k < nr ? phibar[g0 * r + e] : 0.0;
-        vp[u] = k < nr ? (double)Phi[g0 * r + e] : 0.0;
+        const int e = lane + 64 * u, ec = e < emax ? e : emax;
+        vb[u] = phibar[g0 * r + ec];
+        vp[u] = (double)Phi[g0 * r + ec];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = lane + 64 * u;
+        if ((e >> 5) >= nr) vb[u] = vp[u] = 0.0;
       }
       // the fine steps' pending Phibar terms, in the order k_phibar_flush adds
       // them; their uv values of the block's rows go through LDS first

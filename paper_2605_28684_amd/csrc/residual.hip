@@ -197,19 +197,22 @@ __global__ __launch_bounds__(kEulerThreads) void k_residual_euler(
   // registers: this thread's cells of the current / next tile (+ halo cells for two threads)
   Cell3<T> cur[kCellsPerThread], nxt[kCellsPerThread];
   Cell3<T> hcur, hnxt;  // halo cell: thread 0 -> left, thread 1 -> right
+  // Every load is issued unconditionally (cells past the tile read its last
+  // cell, threads other than 0 and 1 read the tile's first cell as their
+  // "halo"; those values are never used), so that all of them are in flight
+  // together: a load under a condition is waited for before the branch joins.
   auto fetch = [&](int ti, Cell3<T>* dst, Cell3<T>& hd) {
     const Tile t = tiles[ti];
     const int64_t n = t.n;
+    const int last = (int)t.ncell - 1;
 #pragma unroll
     for (int j = 0; j < kCellsPerThread; ++j) {
       const int lc = tid + kEulerThreads * j;
-      if (lc < t.ncell) dst[j] = load3<NT>(q + t.base + (t.cell0 + lc) * 3);
+      dst[j] = load3<NT>(q + t.base + (t.cell0 + (lc < last ? lc : last)) * 3);
     }
-    if (tid < 2) {
-      int64_t c = tid == 0 ? t.cell0 - 1 : t.cell0 + t.ncell;
-      c = c < 0 ? 0 : (c >= n ? n - 1 : c);   // zero-gradient ghosts
-      hd = *reinterpret_cast<const Cell3<T>*>(q + t.base + c * 3);
-    }
+    int64_t c = tid == 0 ? t.cell0 - 1 : (tid == 1 ? t.cell0 + t.ncell : t.cell0);
+    c = c < 0 ? 0 : (c >= n ? n - 1 : c);   // zero-gradient ghosts
+    hd = *reinterpret_cast<const Cell3<T>*>(q + t.base + c * 3);
   };
   int ti = blockIdx.x;
   if (ti < n_tiles) fetch(ti, cur, hcur);
@@ -296,26 +299,33 @@ __global__ __launch_bounds__(kEulerThreads) void k_residual_euler(
     if (!skip) {
       const T nn = T(n);
       uint64_t nb = 0;
+      // with q_prev, its loads are waited for here, and with them the next
+      // tile's (issued earlier); without it no load stands before the stores
+      auto emit = [&](auto with_prev) {
+        constexpr bool WP = decltype(with_prev)::value;
 #pragma unroll
-      for (int j = 0; j < kCellsPerThread; ++j) {
-        const int lc = tid + kEulerThreads * j;
-        if (lc < nt) {
-          const int64_t g = t.base + (t.cell0 + lc) * 3;
-          Cell3<T> o;
-          Cell3<T> pv;
-          if (qprev) pv = load3<NT>(qprev + g);
+        for (int j = 0; j < kCellsPerThread; ++j) {
+          const int lc = tid + kEulerThreads * j;
+          if (lc < nt) {
+            const int64_t g = t.base + (t.cell0 + lc) * 3;
+            Cell3<T> o;
+            Cell3<T> pv;
+            if constexpr (WP) pv = load3<NT>(qprev + g);
 #pragma unroll
-          for (int v = 0; v < 3; ++v) {
-            T val = -(sH[v * LH + lc + 1] - sH[v * LH + lc]) * nn;
-            if (qprev) val = cur[j].v[v] - pv.v[v] - dt * val;
-            if (!isfinite(val)) fl |= ROM_FLAG_NONFINITE;
-            o.v[v] = val;
-            const uint64_t bits = isfinite(val) ? norm_bits(val) : ~0ull;
-            nb = bits > nb ? bits : nb;
+            for (int v = 0; v < 3; ++v) {
+              T val = -(sH[v * LH + lc + 1] - sH[v * LH + lc]) * nn;
+              if constexpr (WP) val = cur[j].v[v] - pv.v[v] - dt * val;
+              if (!isfinite(val)) fl |= ROM_FLAG_NONFINITE;
+              o.v[v] = val;
+              const uint64_t bits = isfinite(val) ? norm_bits(val) : ~0ull;
+              nb = bits > nb ? bits : nb;
+            }
+            store3<NT>(out + g, o);
           }
-          store3<NT>(out + g, o);
         }
-      }
+      };
+      if (qprev) emit(std::true_type{});
+      else emit(std::false_type{});
       if (norms) wave_atomic_max(&norms[b], nb);
       flag_or<T>(flags, b, fl);
       fl = 0;
