@@ -133,12 +133,21 @@ __global__ __launch_bounds__(256) void k_bt_factor(int n_inst, const int64_t* __
   for (int e = 0; e < NN; ++e) { Pm[e] = (e % (NV + 1)) == 0 ? T(1) : T(0); Va[e] = T(0); }
 #pragma unroll
   for (int v = 0; v < NV; ++v) ga[v] = T(0);
+  // the next cell's row blocks are loaded while the current cell is
+  // eliminated (the loads do not depend on the recursion)
+  T A[NN], B[NN], C[NN], d[NV], nx[3 * NN + NV];
+  auto load_cell = [&](int64_t jj) {
+    const T* S = sys + (base + jj) * L::SYS;
+#pragma unroll
+    for (int e = 0; e < 3 * NN + NV; ++e) nx[e] = S[e];
+  };
+  load_cell(first);
   for (int64_t j = first; j < s; ++j) {
-    const T* S = sys + (base + j) * L::SYS;
-    const T* A = S;
-    const T* B = S + NN;
-    const T* C = S + 2 * NN;
-    const T* d = S + 3 * NN;
+#pragma unroll
+    for (int e = 0; e < NN; ++e) { A[e] = nx[e]; B[e] = nx[NN + e]; C[e] = nx[2 * NN + e]; }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) d[v] = nx[3 * NN + v];
+    if (j + 1 < s) load_cell(j + 1);
     if (j == first) {
 #pragma unroll
       for (int e = 0; e < NN; ++e) Bt[e] = B[e];
@@ -520,13 +529,52 @@ __global__ __launch_bounds__(256) void k_bt_back(int n_inst, const int64_t* __re
 #pragma unroll
     for (int v = 0; v < NV; ++v) xn[v] = F[2 * NN + v] - tv[v] - tw[v];
     emit(s - 1, xn);
-    for (int64_t j = s - 2; j >= first; --j) {
-      const T* G = fwd + (base + j) * L::FWD;
-      mv<T, NV>(G + NN, xl, tv);
-      mv<T, NV>(G, xn, tw);
+    if constexpr (NV <= 3) {
+      // the next cell's forward factors (and, in update mode, its old values)
+      // are loaded while the current cell is solved: they do not depend on it
+      T g[L::FWD], ng[L::FWD], uo[NV], nu[NV];
+      auto load_cell = [&](int64_t jj) {
+        const T* G = fwd + (base + jj) * L::FWD;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) xn[v] = G[2 * NN + v] - tv[v] - tw[v];
-      emit(j, xn);
+        for (int e = 0; e < L::FWD; ++e) ng[e] = G[e];
+        if (mode != 0) {
+          const T* u = upd + dof_off[b] + jj * NV;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) nu[v] = u[v];
+        }
+      };
+      if (s - 2 >= first) load_cell(s - 2);
+      for (int64_t j = s - 2; j >= first; --j) {
+#pragma unroll
+        for (int e = 0; e < L::FWD; ++e) g[e] = ng[e];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) uo[v] = nu[v];
+        if (j - 1 >= first) load_cell(j - 1);
+        mv<T, NV>(g + NN, xl, tv);
+        mv<T, NV>(g, xn, tw);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) xn[v] = g[2 * NN + v] - tv[v] - tw[v];
+        if (mode == 0) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) x[(base + j) * NV + v] = xn[v];
+        } else {
+          T* u = upd + dof_off[b] + j * NV;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            u[v] = uo[v] + xn[v];
+            dmax = fmax(dmax, fabs((double)xn[v]));
+          }
+        }
+      }
+    } else {
+      for (int64_t j = s - 2; j >= first; --j) {
+        const T* G = fwd + (base + j) * L::FWD;
+        mv<T, NV>(G + NN, xl, tv);
+        mv<T, NV>(G, xn, tw);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) xn[v] = G[2 * NN + v] - tv[v] - tw[v];
+        emit(j, xn);
+      }
     }
   }
   }

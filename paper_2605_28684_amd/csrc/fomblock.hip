@@ -164,8 +164,16 @@ __global__ __launch_bounds__(kFB) void k_fom_newton_block(
   const T inv = T(n), inv2 = T(n) * T(n);
 
   T q[MM];
+  // the part's state and previous state in registers, loaded unconditionally
+  // (indices clamped to the part; a guarded load is waited for on its own)
+  T qo_[MM];
+  {
+    const int lm = len > 0 ? len - 1 : 0;
 #pragma unroll
-  for (int j = 0; j < MM; ++j) q[j] = j < len ? qp[j] : T(0);
+    for (int j = 0; j < MM; ++j) qo_[j] = qp[j < lm ? j : lm];
+  }
+#pragma unroll
+  for (int j = 0; j < MM; ++j) q[j] = j < len ? qo_[j] : T(0);
   unsigned fl = 0;
   int it = 0;
   bool conv = false, sing = false;
@@ -197,7 +205,7 @@ __global__ __launch_bounds__(kFB) void k_fom_newton_block(
     for (int j = 0; j < MM; ++j) {
       if (j < len) {
         T A, B, C, d;
-        newton_row(mdl, QM(j), q[j], QN(j), qp[j], dt, inv, inv2, A, B, C, d, fl);
+        newton_row(mdl, QM(j), q[j], QN(j), qo_[j], dt, inv, inv2, A, B, C, d, fl);
         if (!isfinite(d)) { fl |= ROM_FLAG_NONFINITE; rfin = false; }
         else rmax = fmax(rmax, fabs(d));
         ymax = fmax(ymax, fabs(q[j]));
@@ -248,7 +256,7 @@ __global__ __launch_bounds__(kFB) void k_fom_newton_block(
         Cf[j] = gf[j] = T(0);
         if (j < len - 1) {
           T A, B, C, d;
-          newton_row(mdl, QM(j), q[j], QN(j), qp[j], dt, inv, inv2, A, B, C, d, fl);
+          newton_row(mdl, QM(j), q[j], QN(j), qo_[j], dt, inv, inv2, A, B, C, d, fl);
           const T Bt = j > 0 ? B - A * Cf[j > 0 ? j - 1 : 0] : B;
           const T Bi = Bt != T(0) ? T(1) / Bt : T(0);
           const T dd = j > 0 ? d - A * gf[j > 0 ? j - 1 : 0] : d - A * xl;
