@@ -89,6 +89,36 @@ DEV bool inv_block(const T* A, T* X) {
   return ok;
 }
 
+// v from another lane by one DPP control (whole rows, every bank), for 32- and
+// 64-bit types.
+template <int CTRL, typename T>
+DEV T dpp_mov(T v) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF,
+                                                          0xF, false));
+  } else {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(T, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+  }
+}
+
+// The largest v over each 16-lane row of the wavefront, in every lane of the
+// row (v never NaN): the quad, then the other quad of the half row (mirrored
+// within 8 lanes), then the other half (mirrored within 16).
+template <typename T>
+DEV T row16_max(T v) {
+  T o = dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  v = o > v ? o : v;
+  o = dpp_mov<0x4E>(v);     // quad_perm [2,3,0,1]
+  v = o > v ? o : v;
+  o = dpp_mov<0x141>(v);    // row_half_mirror
+  v = o > v ? o : v;
+  o = dpp_mov<0x140>(v);    // row_mirror
+  return o > v ? o : v;
+}
+
 DEV int find_inst(const int64_t* off, int n_inst, int64_t g) {
   int lo = 0, hi = n_inst;  // off[lo] <= g < off[hi]
   while (hi - lo > 1) {
@@ -292,15 +322,12 @@ __global__ __launch_bounds__(64) void k_bt_factor_rows(int n_inst, const int64_t
 #pragma unroll
     for (int kk = 0; kk < NV; ++kk) {
       const T a = aug[kk];
-      T key = done ? T(-1) : (isnan(a) ? T(INFINITY) : fabs(a));
-      int kl = i;
-#pragma unroll
-      for (int o = 8; o > 0; o >>= 1) {
-        const T ko = __shfl_xor(key, o, 16);
-        const int lo = __shfl_xor(kl, o, 16);
-        if (ko > key || (ko == key && lo < kl)) { key = ko; kl = lo; }
-      }
-      if (act && !(key != T(0))) ok = false;
+      // the pivot: the group's lowest lane holding its largest key (a group
+      // is one 16-lane DPP row; an unchosen row always has key >= 0)
+      const T key = done ? T(-1) : (isnan(a) ? T(INFINITY) : fabs(a));
+      const T kmax = row16_max(key);
+      const int kl = __builtin_ctz((unsigned)(__ballot(key == kmax) >> (16 * grp)) & 0xFFFFu);
+      if (act && !(kmax != T(0))) ok = false;
       if (i == kl) {
         const T ip = a != T(0) ? T(1) / a : T(0);
 #pragma unroll

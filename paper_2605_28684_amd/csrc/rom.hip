@@ -428,15 +428,11 @@ DEV void wave_lu_solve(const double* A, int ld, double* bvec, int n, int* ok) {
   for (int k = 0; k < NM; ++k) {
     if (k < n) {
       const double a = row[k];
-      double key = used ? -1.0 : (isnan(a) ? (double)INFINITY : fabs(a));
-      int kl = lane;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ko = __shfl_xor(key, off);
-        const int lo = __shfl_xor(kl, off);
-        if (ko > key || (ko == key && lo < kl)) { key = ko; kl = lo; }
-      }
-      const int p = __builtin_amdgcn_readfirstlane(kl);
+      // the pivot: the lowest lane holding the largest key (keys are never NaN;
+      // an unused row with lane < n exists, so the maximum is at least 0)
+      const double key = used ? -1.0 : (isnan(a) ? (double)INFINITY : fabs(a));
+      const double kmax = wave_fmax_d(key);
+      const int p = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(key == kmax)));
       const double pk = readlane_d(a, p);
       const double rp = pk != 0.0 ? 1.0 / pk : 0.0;
       if (!(pk != 0.0)) good = false;
@@ -693,7 +689,19 @@ __global__ __launch_bounds__(128) void k_hr_reduce_solve(
   const int i0 = g * kHrRedRows;
   const int ni = r - i0 < kHrRedRows ? r - i0 : kHrRedRows;
   const double* Mg = Mp + (size_t)b * r * ns + (size_t)i0 * ns;
-  for (int e = k; e < ni * ns; e += blockDim.x) sMr[e] = Mg[e];
+  // loads are issued unconditionally (indices clamped into range) so that
+  // a batch is in flight together; the guards apply to the stores and sums
+  {
+    const int ne = ni * ns;
+    for (int e0 = k; e0 < ne; e0 += 128 * 8) {
+      double v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = Mg[e0 + 128 * j < ne ? e0 + 128 * j : ne - 1];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (e0 + 128 * j < ne) sMr[e0 + 128 * j] = v[j];
+    }
+  }
   __syncthreads();
   double* out = hr_ar + (size_t)b * r * ld;
   if (k <= r) {
@@ -704,7 +712,7 @@ __global__ __launch_bounds__(128) void k_hr_reduce_solve(
     for (int s0 = 0; s0 < ns; s0 += 8) {
       double av[8];   // eight samples' loads in flight
 #pragma unroll
-      for (int j = 0; j < 8; ++j) av[j] = s0 + j < ns ? As[(size_t)(s0 + j) * ld] : 0.0;
+      for (int j = 0; j < 8; ++j) av[j] = As[(size_t)(s0 + j < ns ? s0 + j : ns - 1) * ld];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         if (s0 + j < ns) {
@@ -725,12 +733,12 @@ __global__ __launch_bounds__(128) void k_hr_reduce_solve(
   __syncthreads();
   if (!last) return;
   __threadfence();   // the other blocks' rows, not stale copies
-  for (int e0 = k; e0 < r * ld; e0 += 128 * 4) {
-    double v[4];   // four loads in flight per thread
+  for (int e0 = k; e0 < r * ld; e0 += 128 * 8) {
+    double v[8];   // eight loads in flight per thread
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = e0 + 128 * j < r * ld ? out[e0 + 128 * j] : 0.0;
+    for (int j = 0; j < 8; ++j) v[j] = out[e0 + 128 * j < r * ld ? e0 + 128 * j : r * ld - 1];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 8; ++j) {
       const int e = e0 + 128 * j;
       if (e < r * ld) {
         const int i = e / ld, c = e - i * ld;
