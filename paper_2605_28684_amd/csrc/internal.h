@@ -89,6 +89,70 @@ struct BtLevel {
   void* x = nullptr;      // solution per cell (nv)
 };
 
+// Cross-lane exchanges without LDS, for wave-wide reductions that must add or
+// compare exactly the pairs a shuffle-xor butterfly would.  The 64-bit value
+// of lane l ^ 32 and of lane l ^ 16 come from the VALU permutes of gfx950
+// (v_permlane32_swap: with both operands x, the first result holds the low
+// half's copy and the second the high half's; v_permlane16_swap: the first
+// result holds rows 0, 0, 2, 2 and the second rows 1, 1, 3, 3).  The other
+// offsets are DPP moves within 16-lane rows.
+__device__ __forceinline__ double bfly_join(unsigned lo, unsigned hi) {
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double bfly_xor32(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false,
+                                                   false);
+  return (__lane_id() & 32) ? bfly_join(lo[0], hi[0]) : bfly_join(lo[1], hi[1]);
+}
+__device__ __forceinline__ double bfly_xor16(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false,
+                                                   false);
+  return (__lane_id() & 16) ? bfly_join(lo[0], hi[0]) : bfly_join(lo[1], hi[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ double bfly_dpp(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  return bfly_join((unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xF, 0xF, false),
+                   (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF,
+                                                      false));
+}
+
+// The wave sum of v in every lane, with the additions of a shuffle-xor
+// butterfly over offsets 32, 16, 8, 4, 2, 1, in that order, so bit for bit its
+// result.  row_ror:8 is lane ^ 8; after the first three stages a lane's value
+// depends only on its index mod 8, where row_ror:4 equals lane ^ 4; the quad
+// permutes are lane ^ 2 and lane ^ 1.  Every lane of the wavefront must be
+// active.
+__device__ __forceinline__ double wave_sum_bfly(double v) {
+  v += bfly_xor32(v);
+  v += bfly_xor16(v);
+  v += bfly_dpp<0x128>(v);   // row_ror:8
+  v += bfly_dpp<0x124>(v);   // row_ror:4
+  v += bfly_dpp<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += bfly_dpp<0xB1>(v);    // quad_perm [1,0,3,2]
+  return v;
+}
+
+// The wave maximum of v in every lane (v never NaN; every lane active).
+__device__ __forceinline__ double wave_max_bfly(double v) {
+  double o = bfly_xor32(v);
+  v = o > v ? o : v;
+  o = bfly_xor16(v);
+  v = o > v ? o : v;
+  o = bfly_dpp<0x128>(v);
+  v = o > v ? o : v;
+  o = bfly_dpp<0x124>(v);
+  v = o > v ? o : v;
+  o = bfly_dpp<0x4E>(v);
+  v = o > v ? o : v;
+  o = bfly_dpp<0xB1>(v);
+  return o > v ? o : v;
+}
+
 // Max of v over the 64 lanes of a wavefront, then one atomicMax into *dst from
 // lane 0.  Every lane of the wavefront must call it with the same dst.
 __device__ __forceinline__ void wave_atomic_max(uint64_t* dst, uint64_t v) {

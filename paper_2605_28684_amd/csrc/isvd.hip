@@ -758,11 +758,9 @@ __global__ __launch_bounds__(256) void k_project_small(const Tile* __restrict__ 
       T v[kNarrow];   // all loads of the chunk in flight before the LDS writes
 #pragma unroll
       for (int u = 0; u < kNarrow; ++u) {
-        const int e = u * 256 + tid;
-        if (e < nr * k) {
-          const int rr = e / k;
-          v[u] = Phi[(g0 + rr) * ld + (e - rr * k)];
-        }
+        const int e = u * 256 + tid < nr * k ? u * 256 + tid : 0;   // unconditional load
+        const int rr = e / k;
+        v[u] = Phi[(g0 + rr) * ld + (e - rr * k)];
       }
 #pragma unroll
       for (int u = 0; u < kNarrow; ++u)
@@ -792,9 +790,7 @@ __global__ __launch_bounds__(256) void k_project_small(const Tile* __restrict__ 
   const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll
   for (int c = 0; c <= kNarrow; ++c) {
-    double v = acc[c];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const double v = wave_sum_bfly(acc[c]);
     if (lane == 0) red[wv][c] = v;
   }
   __syncthreads();

@@ -30,14 +30,12 @@ __device__ inline int block_lu_solve(double* A, int ld, double* b, int n) {
   if (tid == 0) okf = 1;
   for (int k = 0; k < n; ++k) {
     if (tid < 64) {
-      double v = (tid >= k && tid < n) ? fabs(A[tid * ld + k]) : -1.0;
-      int idx = tid;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(v, off);
-        const int oi = __shfl_xor(idx, off);
-        if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-      }
+      const double a = (tid >= k && tid < n) ? fabs(A[tid * ld + k]) : -1.0;
+      // the lowest lane holding the largest |a| (NaN entries are never chosen
+      // over numbers; an all-NaN column takes the lowest candidate row)
+      const double key = isnan(a) ? -0.5 : a;
+      const double v = wave_max_bfly(key);
+      const int idx = (int)__builtin_ctzll(__ballot(key == v));
       if (tid == 0) {
         piv = idx;
         if (v == 0.0) okf = 0;

@@ -974,8 +974,7 @@ DEV void qr_lstsq(double* A, int m, int nc, double* rhs, double* x) {
     if (wave == 0) {   // |A[k:, k]| by the first wavefront
       double s = 0.0;
       for (int i = k + lane; i < m; i += 64) s += A[i * ld + k] * A[i * ld + k];
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+      s = wave_sum_bfly(s);
       const double nrm = sqrt(s);
       const double akk = A[k * ld + k];
       const double alpha = akk >= 0.0 ? -nrm : nrm;
@@ -1014,9 +1013,7 @@ DEV void qr_lstsq(double* A, int m, int nc, double* rhs, double* x) {
           if (on[g]) sdot[g] += vi * col[g][i * cs[g]];
       }
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int g = 0; g < kQG; ++g) sdot[g] += __shfl_xor(sdot[g], off);
+      for (int g = 0; g < kQG; ++g) sdot[g] = wave_sum_bfly(sdot[g]);
 #pragma unroll
       for (int g = 0; g < kQG; ++g) sdot[g] *= beta;
       for (int i = k + lane; i < m; i += 64) {
@@ -1477,9 +1474,7 @@ __global__ __launch_bounds__(256) void k_hr_step_vjp(
     }
   }
   for (int w = 0; w < NV; ++w) {
-    double v = dva[w];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const double v = wave_sum_bfly(dva[w]);
     __syncthreads();
     if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
