@@ -171,7 +171,7 @@ void free_all(rom_batch* h) {
                 h->Phi, h->sigma, h->a, h->a_prev, h->q_ref, h->d_var, h->y_corr, h->flags, h->P,
                 h->M, h->mesh_phi, h->mesh_qref, h->chosen, h->part, h->red, h->ubar, h->lmat,
                 h->active, h->iters, h->norms, h->rstate, h->qtmp, h->mpart, h->fq, h->fq_prev, h->vjp_tmp,
-                h->d_epoch, h->rvjp, h->epart, h->ev_iters, h->phi_cm, h->Phi_alt, h->hr_as, h->hr_cnt};
+                h->d_epoch, h->rvjp, h->epart, h->ev_iters, h->phi_cm, h->Phi_alt, h->hr_as};
   for (void* p : ps) (void)hipFree(p);
   void* pw[] = {h->win, h->lift, h->zmat, h->zpinv, h->phit, h->sig_scratch, h->qdeim_q,
                 h->fgs_g, h->d_tile_first, h->mesh5_phi, h->mesh5_qref};
@@ -288,10 +288,6 @@ rom_status setup(rom_batch* h) {
   if (c.scheme == ROM_SCHEME_SSPRK43) {
     ROM_TRY(alloc(&h->mesh5_phi, (size_t)B * ns * 5 * h->nv * r));
     ROM_TRY(alloc(&h->mesh5_qref, (size_t)B * ns * 5 * h->nv));
-  }
-  if (c.hyper != ROM_HR_NONE) {
-    ROM_TRY(alloc(&h->hr_cnt, (size_t)B));
-    ROM_HIP_CHECK(hipMemset(h->hr_cnt, 0, sizeof(int32_t) * B));
   }
   ROM_TRY(alloc(&h->part, (size_t)std::max(h->n_ptiles, 1) * kMaxR * kMaxR));
   ROM_TRY(alloc(&h->red, (size_t)B * (2 * 128 + 8)));

@@ -215,7 +215,6 @@ struct rom_batch {
   uint32_t* chosen = nullptr;  // [total_dof] epoch marks for DEIM
   void* phi_cm = nullptr;      // T[total_dof * r]: Phi by columns per instance (DEIM only)
   double* hr_as = nullptr;     // [n_inst * (n_s + r) * (r + 1)]: rows of [A_s | b], then [M A_s | -M b] (DEIM only)
-  int32_t* hr_cnt = nullptr;   // [n_inst]: arrival counters of the HR reduction blocks (zero between launches)
   uint32_t deim_epoch = 0;
   double* qdeim_q = nullptr;   // [n_inst * kMaxR * kMaxR] QDEIM's orthonormal directions (QDEIM only)
   double* fgs_g = nullptr;     // [total_cells] squared feature gradient (feature-guided sampling)

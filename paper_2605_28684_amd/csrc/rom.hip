@@ -534,11 +534,11 @@ DEV void hr_row(const Mdl& m, const double* q3, int64_t c, int v, int64_t n, dou
   }
 }
 
-// One Gauss-Newton iteration is two launches: k_hr_eval spreads the sampled
+// One Gauss-Newton iteration is three launches: k_hr_eval spreads the sampled
 // rows of every instance over blocks of kHrRows rows (stencil states, the
-// sampled Jacobian rows, the rows of A_s and b); k_hr_reduce_solve forms M A_s
-// and M b over blocks of rows of M, and the last block of each instance solves
-// its r x r system on one wavefront and updates a.  Instances that have
+// sampled Jacobian rows, the rows of A_s and b); k_hr_reduce forms M A_s and
+// M b over blocks of rows of M, and k_hr_solve solves each instance's r x r
+// system on one wavefront and updates a.  Instances that have
 // converged skip both.
 constexpr int kHrRows = 8;            // sampled rows per evaluation block
 constexpr int kHrEvalThreads = 128;
@@ -668,85 +668,101 @@ __global__ __launch_bounds__(kHrEvalThreads) void k_hr_eval(
   if (tid == 0 && flacc) atomicOr(&flags[b], flacc);
 }
 
-// A_red = M A_s and rho = -M b, then the r x r solve and the update of a.  One
-// block per instance and group of kHrRedRows rows of M, one thread per column
-// of [A_s | b], summed over the samples in order, into hr_ar[b] (r rows of
-// r + 1: A_red | rho).  The last of an instance's blocks to finish (counted in
-// cnt[b], which it resets) solves the system on its first wavefront.
+// A_red = M A_s and rho = -M b: one block per instance and group of kHrRedRows
+// rows of M, into hr_ar[b] (r rows of r + 1: A_red | rho).  The block copies
+// its rows of M (sample-major) and the instance's [A_s | b] into LDS with
+// every thread's loads in flight together, then thread (column c, half h)
+// sums rows 4h .. 4h+3 of column c over the samples in order (FP64).
+// k_hr_solve then solves the system; the launch boundary between them
+// publishes the rows.
 constexpr int kHrRedRows = 8;
-template <int NM>
-__global__ __launch_bounds__(128) void k_hr_reduce_solve(
+constexpr int kHrRedThreads = 256;
+__global__ __launch_bounds__(kHrRedThreads) void k_hr_reduce(
     int r, int ns, int gpr, const double* __restrict__ Mp, const double* __restrict__ hr_as,
-    int32_t* __restrict__ active, double* __restrict__ hr_ar, int32_t* __restrict__ cnt,
-    double* __restrict__ a, int32_t* __restrict__ iters, double tol, uint32_t* flags) {
-  __shared__ double sMr[kHrRedRows * kMaxNs];   // the block's rows of M
-  __shared__ double Ar[kMaxR * (kMaxR + 1)];
-  __shared__ double rh[kMaxR];
-  __shared__ int ok, last;
-  const int b = blockIdx.x / gpr, g = blockIdx.x - b * gpr, k = threadIdx.x;
+    const int32_t* __restrict__ active, double* __restrict__ hr_ar) {
+  extern __shared__ double shr[];
+  const int b = blockIdx.x / gpr, g = blockIdx.x - b * gpr, tid = threadIdx.x;
   if (!active[b]) return;
   const int ld = r + 1;
   const int i0 = g * kHrRedRows;
   const int ni = r - i0 < kHrRedRows ? r - i0 : kHrRedRows;
-  const double* Mg = Mp + (size_t)b * r * ns + (size_t)i0 * ns;
-  // loads are issued unconditionally (indices clamped into range) so that
-  // a batch is in flight together; the guards apply to the stores and sums
+  double* sMt = shr;                      // [ns][kHrRedRows]: M[i0 + u][s] at s*8 + u
+  double* sA = shr + kHrRedRows * ns;     // [ns][ld]
   {
-    const int ne = ni * ns;
-    for (int e0 = k; e0 < ne; e0 += 128 * 8) {
+    // loads are issued unconditionally (indices clamped into range) so that a
+    // batch of eight is in flight together; the guards apply to the stores
+    const double* Mg = Mp + (size_t)b * r * ns + (size_t)i0 * ns;
+    const double* Ag = hr_as + (size_t)b * ns * ld;
+    const int nm = ni * ns, na = ns * ld;
+    for (int e0 = tid; e0 < nm + na; e0 += kHrRedThreads * 8) {
       double v[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = Mg[e0 + 128 * j < ne ? e0 + 128 * j : ne - 1];
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (e0 + 128 * j < ne) sMr[e0 + 128 * j] = v[j];
-    }
-  }
-  __syncthreads();
-  double* out = hr_ar + (size_t)b * r * ld;
-  if (k <= r) {
-    const double* As = hr_as + (size_t)b * ns * ld + k;
-    double acc[kHrRedRows];
-#pragma unroll
-    for (int u = 0; u < kHrRedRows; ++u) acc[u] = 0.0;
-    for (int s0 = 0; s0 < ns; s0 += 8) {
-      double av[8];   // eight samples' loads in flight
-#pragma unroll
-      for (int j = 0; j < 8; ++j) av[j] = As[(size_t)(s0 + j < ns ? s0 + j : ns - 1) * ld];
+      for (int j = 0; j < 8; ++j) {
+        const int e = e0 + kHrRedThreads * j;
+        const double* src = e < nm ? Mg + e : Ag + (e < nm + na ? e - nm : na - 1);
+        v[j] = *src;
+      }
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        if (s0 + j < ns) {
-#pragma unroll
-          for (int u = 0; u < kHrRedRows; ++u)
-            if (u < ni) acc[u] += sMr[u * ns + s0 + j] * av[j];
+        const int e = e0 + kHrRedThreads * j;
+        if (e < nm) {
+          const int u = e / ns;
+          sMt[(e - u * ns) * kHrRedRows + u] = v[j];
+        } else if (e < nm + na) {
+          sA[e - nm] = v[j];
         }
       }
     }
-#pragma unroll
-    for (int u = 0; u < kHrRedRows; ++u)
-      if (u < ni) out[(size_t)(i0 + u) * ld + k] = k < r ? acc[u] : -acc[u];
   }
-  // publish the rows, then count the block in
-  __threadfence();
   __syncthreads();
-  if (k == 0) last = atomicAdd(&cnt[b], 1) == gpr - 1 ? 1 : 0;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();   // the other blocks' rows, not stale copies
-  for (int e0 = k; e0 < r * ld; e0 += 128 * 8) {
+  const int c = tid % ld, h = tid / ld;
+  if (h < 2) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int s0 = 0; s0 < ns; ++s0) {
+      const double av = sA[s0 * ld + c];
+      const double* m = sMt + s0 * kHrRedRows + 4 * h;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += m[u] * av;
+    }
+    double* out = hr_ar + (size_t)b * r * ld;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (4 * h + u < ni) out[(size_t)(i0 + 4 * h + u) * ld + c] = c < r ? acc[u] : -acc[u];
+  }
+}
+
+size_t hr_reduce_shm(int r, int ns) {
+  return sizeof(double) * ((size_t)kHrRedRows * ns + (size_t)ns * (r + 1));
+}
+
+// The r x r solve of one instance (rows of hr_ar loaded by the block, solved by
+// its first wavefront) and the update of a.
+template <int NM>
+__global__ __launch_bounds__(256) void k_hr_solve(int r, const double* __restrict__ hr_ar,
+                                                  int32_t* __restrict__ active,
+                                                  double* __restrict__ a,
+                                                  int32_t* __restrict__ iters, double tol,
+                                                  uint32_t* flags) {
+  __shared__ double Ar[kMaxR * (kMaxR + 1)];
+  __shared__ double rh[kMaxR];
+  __shared__ int ok;
+  const int b = blockIdx.x, k = threadIdx.x;
+  if (!active[b]) return;
+  const int ld = r + 1;
+  const double* out = hr_ar + (size_t)b * r * ld;
+  for (int e0 = k; e0 < r * ld; e0 += 256 * 8) {
     double v[8];   // eight loads in flight per thread
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = out[e0 + 128 * j < r * ld ? e0 + 128 * j : r * ld - 1];
+    for (int j = 0; j < 8; ++j) v[j] = out[e0 + 256 * j < r * ld ? e0 + 256 * j : r * ld - 1];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int e = e0 + 128 * j;
+      const int e = e0 + 256 * j;
       if (e < r * ld) {
         const int i = e / ld, c = e - i * ld;
         if (c < r) Ar[e] = v[j]; else rh[i] = v[j];
       }
     }
   }
-  if (k == 0) cnt[b] = 0;   // ready for the next iteration
   __syncthreads();
   if (k >= 64) return;
   wave_lu_solve<NM>(Ar, ld, rh, r, &ok);
@@ -1097,11 +1113,34 @@ __global__ __launch_bounds__(256) void k_deim_select(const int* __restrict__ tfi
   const int m = tn;                     // rows available
   if (jn == 0) return;                  // no fit for the first column of a round
   const T* Pb = Phi + dof_off[b] * r;
-  for (int e = tid; e < m * jn; e += blockDim.x) {
-    const int i = e / jn, c = e % jn;
-    A[i * (kMaxR + 1) + c] = (double)Pb[(int64_t)P[(size_t)b * ns + i] * r + c];
+  __shared__ int64_t srow[kMaxNs];   // offsets of the chosen rows
+  for (int i = tid; i < m; i += blockDim.x) srow[i] = (int64_t)P[(size_t)b * ns + i] * r;
+  __syncthreads();
+  {
+    // the gather of A (m x jn) and rhs (column jn): eight loads per thread in
+    // flight together (indices clamped into range), then the LDS stores
+    const int ne = m * jn, nt = ne + m;
+    for (int e0 = tid; e0 < nt; e0 += 256 * 8) {
+      T v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = e0 + 256 * j < nt ? e0 + 256 * j : nt - 1;
+        const int i = e < ne ? e / jn : e - ne;
+        const int c = e < ne ? e - i * jn : jn;
+        v[j] = Pb[srow[i] + c];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = e0 + 256 * j;
+        if (e < ne) {
+          const int i = e / jn;
+          A[i * (kMaxR + 1) + (e - i * jn)] = (double)v[j];
+        } else if (e < nt) {
+          rhs[e - ne] = (double)v[j];
+        }
+      }
+    }
   }
-  for (int i = tid; i < m; i += blockDim.x) rhs[i] = (double)Pb[(int64_t)P[(size_t)b * ns + i] * r + jn];
   __syncthreads();
   qr_lstsq(A, m, jn, rhs, x);
   for (int c = tid; c < jn; c += blockDim.x) coef[(size_t)b * ldc + c] = x[c];
@@ -1508,10 +1547,12 @@ rom_status hr_step(rom_batch* h, hipStream_t s) {
                          h->mesh_qref, h->d_var, h->a, h->a_prev, h->cfg.dt, h->active,
                          h->hr_as, h->flags);
       // register rows of the solve sized to r rounded up to 16
-      auto rsolve = r <= 16 ? k_hr_reduce_solve<16> : r <= 32 ? k_hr_reduce_solve<32>
-                  : r <= 48 ? k_hr_reduce_solve<48> : k_hr_reduce_solve<64>;
-      hipLaunchKernelGGL(rsolve, dim3(B * gpr), dim3(128), 0, s, r, ns, gpr, h->M, h->hr_as,
-                         h->active, hr_ar, h->hr_cnt, h->a, h->iters, h->cfg.rom_tol, h->flags);
+      hipLaunchKernelGGL(k_hr_reduce, dim3(B * gpr), dim3(kHrRedThreads), hr_reduce_shm(r, ns), s,
+                         r, ns, gpr, h->M, h->hr_as, h->active, hr_ar);
+      auto rsolve = r <= 16 ? k_hr_solve<16> : r <= 32 ? k_hr_solve<32>
+                  : r <= 48 ? k_hr_solve<48> : k_hr_solve<64>;
+      hipLaunchKernelGGL(rsolve, dim3(B), dim3(256), 0, s, r, hr_ar, h->active, h->a, h->iters,
+                         h->cfg.rom_tol, h->flags);
     }
     hipLaunchKernelGGL(k_rom_finalize, dim3((B + 255) / 256), dim3(256), 0, s, B, h->active,
                        h->flags);
@@ -1597,6 +1638,8 @@ rom_status rom_kernels_prepare() {
   ROM_HIP_CHECK(vjp_attr((const void*)k_hr_step_vjp<ReactModel<double>, float>));
   ROM_HIP_CHECK(vjp_attr((const void*)k_hr_step_vjp<ReactModel<double>, double>));
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_rebuild<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_reduce, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)hr_reduce_shm(kMaxR, kMaxNs)));
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_rebuild<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   return ROM_OK;
 }
