@@ -44,18 +44,18 @@ MEASURED_KIB = {
     "k_galerkin_mfma<32>": {"fetch": 133445.3, "write": 4245.8},
     # streaming Euler residual on the 64 x 262,144-cell shape, every launch shape
     # of the autotuner (bench.py --only residual walks them in order)
-    "k_residual_euler/0": {"fetch": 101935.9, "write": 196608.0},
-    "k_residual_euler/1": {"fetch": 101933.5, "write": 196608.0},
-    "k_residual_euler/2": {"fetch": 105501.6, "write": 196608.0},
-    "k_residual_euler/3": {"fetch": 105501.6, "write": 196608.0},
-    "k_residual_euler/4": {"fetch": 105501.5, "write": 196608.0},
-    "k_residual_euler/5": {"fetch": 112663.1, "write": 196608.0},
-    "k_residual_euler/6": {"fetch": 112668.1, "write": 196608.0},
-    "k_residual_euler/7": {"fetch": 101936.4, "write": 196608.0},
-    "k_residual_euler/8": {"fetch": 105509.0, "write": 196608.1},
-    "k_residual_euler/9": {"fetch": 105508.9, "write": 196608.0},
-    "k_residual_euler/10": {"fetch": 112663.9, "write": 196608.0},
-    "k_residual_euler/11": {"fetch": 112664.5, "write": 196608.0},
+    "k_residual_euler/0": {"fetch": 101937.4, "write": 196608.3},
+    "k_residual_euler/1": {"fetch": 101935.0, "write": 196608.0},
+    "k_residual_euler/2": {"fetch": 105509.1, "write": 196609.4},
+    "k_residual_euler/3": {"fetch": 105509.1, "write": 196608.4},
+    "k_residual_euler/4": {"fetch": 105509.0, "write": 196608.0},
+    "k_residual_euler/5": {"fetch": 112667.6, "write": 196608.9},
+    "k_residual_euler/6": {"fetch": 112674.0, "write": 196608.5},
+    "k_residual_euler/7": {"fetch": 101944.8, "write": 204654.5},
+    "k_residual_euler/8": {"fetch": 105521.6, "write": 205916.6},
+    "k_residual_euler/9": {"fetch": 105512.3, "write": 203707.4},
+    "k_residual_euler/10": {"fetch": 112684.5, "write": 230598.9},
+    "k_residual_euler/11": {"fetch": 112682.3, "write": 232216.8},
 }
 
 
