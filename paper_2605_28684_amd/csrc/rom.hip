@@ -289,7 +289,13 @@ void k_galerkin_solve_w(
   // summed over the tiles in order in FP64.  No LDS anywhere in the kernel:
   // the solve shares its compute unit with LDS-heavy kernels of the event
   // chain and must not queue behind them.
+  // The loads are issued unconditionally (tile indices clamped to the last
+  // tile) so that a group's loads are in flight together; the state, a_prev
+  // and d of the instance are loaded first, beside them.
   constexpr int kTG = 2;
+  const double ai = a[(size_t)b * RT + i];
+  const double api = first ? ai : a_prev[(size_t)b * RT + i];
+  const double dvb = dvar[b];
   double A[NL];
 #pragma unroll
   for (int jj = 0; jj < NL; ++jj) A[jj] = 0.0;
@@ -299,12 +305,11 @@ void k_galerkin_solve_w(
     double gv[kTG];
 #pragma unroll
     for (int g = 0; g < kTG; ++g) {
-      if (tt + g < t1) {
-        const float4* src = reinterpret_cast<const float4*>(mpart + (size_t)(tt + g) * kMaxR * kMaxR);
+      const int tg = tt + g < t1 ? tt + g : t1 - 1;
+      const float4* src = reinterpret_cast<const float4*>(mpart + (size_t)tg * kMaxR * kMaxR);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[g][u] = src[lane + 64 * u];
-        gv[g] = gpart[(size_t)(tt + g) * kMaxR + i];
-      }
+      for (int u = 0; u < 4; ++u) v[g][u] = src[lane + 64 * u];
+      gv[g] = gpart[(size_t)tg * kMaxR + i];
     }
 #pragma unroll
     for (int g = 0; g < kTG; ++g) {
@@ -323,10 +328,9 @@ void k_galerkin_solve_w(
   // register jj of lane (i, h) holds column 2 jj + h of row i
 #pragma unroll
   for (int jj = 0; jj < NL; ++jj) A[jj] = (2 * jj + h == i ? 1.0 : 0.0) - dt * A[jj];
-  const double ai = a[(size_t)b * RT + i];
   // the first iteration of a step starts from a_prev = a (and records it)
   if (first && h == 0) a_prev[(size_t)b * RT + i] = ai;
-  double bi = -(ai - (first ? ai : a_prev[(size_t)b * RT + i]) - dt * dvar[b] * gs);
+  double bi = -(ai - api - dt * dvb * gs);
   bool used = false;
   int ord = -1;
   int pivl = 0;       // lane k: the pivot row of column k
