@@ -277,7 +277,7 @@ rom_status setup(rom_batch* h) {
   ROM_TRY(alloc(&h->flags, B));
   ROM_TRY(alloc(&h->P, (size_t)B * ns));
   ROM_TRY(alloc(&h->M, (size_t)B * r * ns));
-  ROM_TRY(alloc(&h->mesh_phi, (size_t)B * ns * 3 * h->nv * r));
+  ROM_TRY(alloc((char**)&h->mesh_phi, es * B * ns * 3 * h->nv * r));
   ROM_TRY(alloc(&h->mesh_qref, (size_t)B * ns * 3 * h->nv));
   ROM_TRY(alloc(&h->chosen, (size_t)td));
   if (c.hyper == ROM_HR_DEIM) ROM_TRY(alloc((char**)&h->phi_cm, es * td * r));

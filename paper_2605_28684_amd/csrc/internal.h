@@ -208,7 +208,7 @@ struct rom_batch {
   uint32_t* flags = nullptr; // [n_inst]
   int32_t* P = nullptr;      // [n_inst * n_s]
   double* M = nullptr;       // [n_inst * r * n_s]
-  double* mesh_phi = nullptr;  // [n_inst * n_s * 3 * nv * r]
+  void* mesh_phi = nullptr;    // T[n_inst * n_s * 3 * nv * r]: the bulk precision (values of Phi)
   double* mesh_qref = nullptr; // [n_inst * n_s * 3 * nv]
   double* mesh5_phi = nullptr;  // [n_inst * n_s * 5 * nv * r]: five-cell mesh (explicit scheme)
   double* mesh5_qref = nullptr; // [n_inst * n_s * 5 * nv]

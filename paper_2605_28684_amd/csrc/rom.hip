@@ -546,12 +546,13 @@ DEV void hr_row(const Mdl& m, const double* q3, int64_t c, int v, int64_t n, dou
 // converged skip both.
 constexpr int kHrRows = 8;            // sampled rows per evaluation block
 constexpr int kHrEvalThreads = 128;
-// mesh_phi[b][s][o][w][k], o in {0,1,2} = cells c-1, c, c+1 of the sampled row's cell.
+// mesh_phi[b][s][o][w][k] (bulk precision), o in {0,1,2} = cells c-1, c, c+1 of the
+// sampled row's cell.
 // hr_as[b][s][0..r) = row s of A_s, hr_as[b][s][r] = b_s.
-template <class Mdl>
+template <class Mdl, typename TM>
 __global__ __launch_bounds__(kHrEvalThreads) void k_hr_eval(
     int r, int ns, int gpi, const int64_t* __restrict__ cell_off, const double* __restrict__ phys,
-    int nphys, const int32_t* __restrict__ P, const double* __restrict__ mphi,
+    int nphys, const int32_t* __restrict__ P, const TM* __restrict__ mphi,
     const double* __restrict__ mqref, const double* __restrict__ dvar, const double* __restrict__ a,
     const double* __restrict__ a_prev, double dt, const int32_t* __restrict__ active,
     double* __restrict__ hr_as, uint32_t* flags) {
@@ -572,7 +573,7 @@ __global__ __launch_bounds__(kHrEvalThreads) void k_hr_eval(
   const int64_t n = cell_off[b + 1] - cell_off[b];
   Mdl m(phys + (size_t)b * nphys);
   const double* dv = dvar + (size_t)b * NV;
-  const double* mph = mphi + ((size_t)b * ns + s0) * E3 * r;   // the block's stencil rows
+  const TM* mph = mphi + ((size_t)b * ns + s0) * E3 * r;   // the block's stencil rows
   double* out = hr_as + ((size_t)b * ns + s0) * (r + 1);
   for (int c = tid; c < r; c += blockDim.x) {
     sa[c] = a[(size_t)b * r + c];
@@ -591,9 +592,9 @@ __global__ __launch_bounds__(kHrEvalThreads) void k_hr_eval(
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int idx = idx0 + h * step < nq ? idx0 + h * step : idx0;
-        const double* Ph = mph + (size_t)idx * r;
+        const TM* Ph = mph + (size_t)idx * r;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[h][u] = l8 + 8 * u < r ? Ph[l8 + 8 * u] : 0.0;
+        for (int u = 0; u < 8; ++u) v[h][u] = (double)Ph[l8 + 8 * u < r ? l8 + 8 * u : 0];
       }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -615,7 +616,7 @@ __global__ __launch_bounds__(kHrEvalThreads) void k_hr_eval(
   __syncthreads();
   // sampled rows of P^T D r and of the Jacobian P^T D J_r D^-1 (one row per thread)
   for (int s = tid; s < nr; s += blockDim.x) {
-    const double* Ph = mph + (size_t)s * E3 * r;
+    const TM* Ph = mph + (size_t)s * E3 * r;
     const int p = P[(size_t)b * ns + s0 + s];
     const int64_t c = p / NV;
     const int v = p % NV;
@@ -626,7 +627,7 @@ __global__ __launch_bounds__(kHrEvalThreads) void k_hr_eval(
     if (fl) atomicOr(&flacc, fl);
     const double dp = dv[v];
     double bsum = 0.0;
-    for (int k = 0; k < r; ++k) bsum += Ph[(NV + v) * r + k] * (sa[k] - sap[k]);
+    for (int k = 0; k < r; ++k) bsum += (double)Ph[(NV + v) * r + k] * (sa[k] - sap[k]);
     out[(size_t)s * (r + 1) + r] = bsum - dt * dp * fv;
     for (int w = 0; w < NV; ++w) {
       const double id = 1.0 / dv[w];
@@ -642,7 +643,7 @@ __global__ __launch_bounds__(kHrEvalThreads) void k_hr_eval(
   // (consecutive threads take consecutive basis columns), two per thread
   for (int idx0 = tid; idx0 < nr * r; idx0 += 2 * blockDim.x) {
     double acc[2] = {0.0, 0.0};
-    const double* Ph[2];
+    const TM* Ph[2];
     int sx[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -656,16 +657,16 @@ __global__ __launch_bounds__(kHrEvalThreads) void k_hr_eval(
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const double* jr = sjr + sx[h] * E3;
-        acc[h] += jr[w] * Ph[h][w * r];
-        acc[h] += jr[NV + w] * Ph[h][(NV + w) * r];
-        acc[h] += jr[2 * NV + w] * Ph[h][(2 * NV + w) * r];
+        acc[h] += jr[w] * (double)Ph[h][w * r];
+        acc[h] += jr[NV + w] * (double)Ph[h][(NV + w) * r];
+        acc[h] += jr[2 * NV + w] * (double)Ph[h][(2 * NV + w) * r];
       }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int idx = idx0 + h * blockDim.x;
       if (idx < nr * r) {
         const int s = sx[h], k = idx - s * r;
-        out[(size_t)s * (r + 1) + k] = Ph[h][(NV + sv[s]) * r] - sdd[s] * acc[h];
+        out[(size_t)s * (r + 1) + k] = (double)Ph[h][(NV + sv[s]) * r] - sdd[s] * acc[h];
       }
     }
   }
@@ -1157,7 +1158,7 @@ __global__ __launch_bounds__(256) void k_rebuild(int r, int ns, int nv, int peri
                                                  const int64_t* __restrict__ cell_off,
                                                  const T* __restrict__ Phi, const T* __restrict__ qref,
                                                  const int32_t* __restrict__ P, double* __restrict__ Mout,
-                                                 double* __restrict__ mphi, double* __restrict__ mqref,
+                                                 T* __restrict__ mphi, double* __restrict__ mqref,
                                                  uint32_t* flags) {
   extern __shared__ double sm[];
   constexpr int ld = kMaxR + 1;
@@ -1180,7 +1181,7 @@ __global__ __launch_bounds__(256) void k_rebuild(int r, int ns, int nv, int peri
     const int64_t row = cc * nv + w;
     mqref[((size_t)b * ns + s) * 3 * nv + rem] = (double)qref[base + row];
     for (int k = 0; k < r; ++k)
-      mphi[(((size_t)b * ns + s) * 3 * nv + rem) * r + k] = (double)Pb[row * r + k];
+      mphi[(((size_t)b * ns + s) * 3 * nv + rem) * r + k] = Pb[row * r + k];
   }
   for (int e = tid; e < ns * r; e += blockDim.x) {
     const int i = e / r, c = e % r;
@@ -1546,10 +1547,17 @@ rom_status hr_step(rom_batch* h, hipStream_t s) {
   auto go = [&](auto tag) -> rom_status {
     using M = typename decltype(tag)::type;
     for (int it = 0; it < h->cfg.rom_max; ++it) {
-      hipLaunchKernelGGL((k_hr_eval<M>), dim3(B * gpi), dim3(kHrEvalThreads), 0, s, r, ns, gpi,
-                         h->d_cell_off, h->d_phys, h->cfg.n_phys, h->P, h->mesh_phi,
-                         h->mesh_qref, h->d_var, h->a, h->a_prev, h->cfg.dt, h->active,
-                         h->hr_as, h->flags);
+      // the sampled-mesh basis is stored in the bulk precision
+      if (h->cfg.precision == ROM_F32)
+        hipLaunchKernelGGL((k_hr_eval<M, float>), dim3(B * gpi), dim3(kHrEvalThreads), 0, s, r,
+                           ns, gpi, h->d_cell_off, h->d_phys, h->cfg.n_phys, h->P,
+                           (const float*)h->mesh_phi, h->mesh_qref, h->d_var, h->a, h->a_prev,
+                           h->cfg.dt, h->active, h->hr_as, h->flags);
+      else
+        hipLaunchKernelGGL((k_hr_eval<M, double>), dim3(B * gpi), dim3(kHrEvalThreads), 0, s, r,
+                           ns, gpi, h->d_cell_off, h->d_phys, h->cfg.n_phys, h->P,
+                           (const double*)h->mesh_phi, h->mesh_qref, h->d_var, h->a, h->a_prev,
+                           h->cfg.dt, h->active, h->hr_as, h->flags);
       // register rows of the solve sized to r rounded up to 16
       hipLaunchKernelGGL(k_hr_reduce, dim3(B * gpr), dim3(kHrRedThreads), hr_reduce_shm(r, ns), s,
                          r, ns, gpr, h->M, h->hr_as, h->active, hr_ar);
@@ -1582,7 +1590,7 @@ rom_status rebuild_t(rom_batch* h, hipStream_t s) {
     hipLaunchKernelGGL((k_rebuild<T>), dim3(B), dim3(256), rebuild_shm(), s, r, ns, h->nv,
                        (h->cfg.problem == ROM_BURGERS || h->cfg.problem == ROM_REACT) ? 1 : 0,
                        h->d_dof_off, h->d_cell_off, (const T*)h->Phi, (const T*)h->q_ref, h->P,
-                       h->M, h->mesh_phi, h->mesh_qref, h->flags);
+                       h->M, (T*)h->mesh_phi, h->mesh_qref, h->flags);
     ROM_HIP_CHECK(hipGetLastError());
     return ROM_OK;
   }
@@ -1612,7 +1620,7 @@ rom_status rebuild_t(rom_batch* h, hipStream_t s) {
   hipLaunchKernelGGL((k_rebuild<T>), dim3(B), dim3(256), rebuild_shm(), s, r, ns, h->nv,
                      (h->cfg.problem == ROM_BURGERS || h->cfg.problem == ROM_REACT) ? 1 : 0,
                      h->d_dof_off, h->d_cell_off, (const T*)h->Phi, (const T*)h->q_ref, h->P, h->M,
-                     h->mesh_phi, h->mesh_qref, h->flags);
+                     (T*)h->mesh_phi, h->mesh_qref, h->flags);
   ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
 }
