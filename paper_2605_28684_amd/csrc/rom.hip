@@ -985,69 +985,81 @@ __global__ __launch_bounds__(128) void k_deim_argmax_v4(const Tile* __restrict__
 }
 
 // Householder QR least squares on an m x nc FP64 matrix in LDS (row-major,
-// ld = kMaxR + 1): overwrites x[0..nc) with argmin ||A x - rhs||.  Single
-// thread per column reflector application loop; sizes here are tiny.
+// ld = kMaxR + 1, m <= 128): overwrites x[0..nc) with argmin ||A x - rhs||.
+// Four wavefronts (blockDim.x == 256) keep the columns in registers: wavefront
+// w holds columns w, w + 4, ... (the rhs is column nc), lane l rows l and
+// l + 64.  At step k the owner of column k forms the reflector (squared norm
+// by a wave sum, the head from row k) and publishes v and beta through LDS
+// (double-buffered, one barrier per column); every wavefront then applies it
+// to its own later columns with one wave sum per column.  R and the rotated
+// rhs go back to LDS for the back-substitution.
 DEV void qr_lstsq(double* A, int m, int nc, double* rhs, double* x) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int ld = kMaxR + 1;
-  __shared__ double beta, alpha_s;
+  constexpr int NQ = (kMaxR + 1 + 3) / 4;   // columns per wavefront, the rhs included
+  static_assert(kMaxNs <= 128, "two rows per lane");
+  __shared__ double sv[2][128];
+  __shared__ double sbeta[2];
+  const int r0 = lane, r1 = lane + 64;
+  double c0[NQ], c1[NQ];   // rows r0 and r1 of columns wave + 4 q
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int c = wave + 4 * q;
+    const double* src = c < nc ? A + c : rhs;
+    const int cs = c < nc ? ld : 1;
+    c0[q] = (c <= nc && r0 < m) ? src[r0 * cs] : 0.0;
+    c1[q] = (c <= nc && r1 < m) ? src[r1 * cs] : 0.0;
+  }
   for (int k = 0; k < nc; ++k) {
-    if (wave == 0) {   // |A[k:, k]| by the first wavefront
-      double s = 0.0;
-      for (int i = k + lane; i < m; i += 64) s += A[i * ld + k] * A[i * ld + k];
-      s = wave_sum_bfly(s);
+    const int qk = k >> 2, buf = k & 1;
+    if (wave == (k & 3)) {
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (q == qk) { a0 = c0[q]; a1 = c1[q]; }
+      const double t0 = r0 >= k ? a0 : 0.0, t1 = r1 >= k ? a1 : 0.0;   // rows >= m hold 0
+      const double s = wave_sum_bfly(t0 * t0 + t1 * t1);
+      const double akk = readlane_d(k < 64 ? a0 : a1, k & 63);
       const double nrm = sqrt(s);
-      const double akk = A[k * ld + k];
       const double alpha = akk >= 0.0 ? -nrm : nrm;
       // v = x - alpha e1 in column k (rows k..m-1); v^T v = s - akk^2 + (akk - alpha)^2
       const double vk = akk - alpha;
       const double vv = (s - akk * akk) + vk * vk;
-      if (lane == 0) {
-        A[k * ld + k] = vk;
-        alpha_s = alpha;
-        beta = vv > 0.0 ? 2.0 / vv : 0.0;
-      }
+      sv[buf][r0] = r0 == k ? vk : t0;
+      sv[buf][r1] = r1 == k ? vk : t1;
+      if (lane == 0) sbeta[buf] = vv > 0.0 ? 2.0 / vv : 0.0;
+      // column k of R: alpha on the diagonal, zero below
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (q == qk) {
+          c0[q] = r0 == k ? alpha : (r0 > k ? 0.0 : a0);
+          c1[q] = r1 == k ? alpha : (r1 > k ? 0.0 : a1);
+        }
     }
     __syncthreads();
-    // apply H = I - beta v v^T to columns k+1..nc-1 and the rhs: each wavefront
-    // takes kQG consecutive columns at a time, whose dot products and updates
-    // are interleaved (independent chains in flight); every column's sum runs
-    // in the same order as with one column at a time
-    constexpr int kQG = 4;
-    for (int c0 = k + 1 + wave * kQG; c0 <= nc; c0 += nw * kQG) {
-      double* col[kQG];
-      int cs[kQG];
-      bool on[kQG];
-      double sdot[kQG];
+    const double v0 = sv[buf][r0], v1 = sv[buf][r1], beta = sbeta[buf];
 #pragma unroll
-      for (int g = 0; g < kQG; ++g) {
-        const int c = c0 + g;
-        on[g] = c <= nc;
-        col[g] = c < nc ? A + c : rhs;
-        cs[g] = c < nc ? ld : 1;
-        sdot[g] = 0.0;
-      }
-      for (int i = k + lane; i < m; i += 64) {
-        const double vi = A[i * ld + k];
-#pragma unroll
-        for (int g = 0; g < kQG; ++g)
-          if (on[g]) sdot[g] += vi * col[g][i * cs[g]];
-      }
-#pragma unroll
-      for (int g = 0; g < kQG; ++g) sdot[g] = wave_sum_bfly(sdot[g]);
-#pragma unroll
-      for (int g = 0; g < kQG; ++g) sdot[g] *= beta;
-      for (int i = k + lane; i < m; i += 64) {
-        const double vi = A[i * ld + k];
-#pragma unroll
-        for (int g = 0; g < kQG; ++g)
-          if (on[g]) col[g][i * cs[g]] -= sdot[g] * vi;
+    for (int q = 0; q < NQ; ++q) {
+      const int c = wave + 4 * q;
+      if (c > k && c <= nc) {   // uniform over the wavefront
+        const double d = beta * wave_sum_bfly(v0 * c0[q] + v1 * c1[q]);
+        c0[q] -= d * v0;
+        c1[q] -= d * v1;
       }
     }
-    __syncthreads();
-    if (tid == 0) A[k * ld + k] = alpha_s;  // R diagonal
-    __syncthreads();
   }
+  // R and the rotated rhs back to LDS
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int c = wave + 4 * q;
+    if (c <= nc) {
+      double* dst = c < nc ? A + c : rhs;
+      const int cs = c < nc ? ld : 1;
+      if (r0 < m) dst[r0 * cs] = c0[q];
+      if (r1 < m) dst[r1 * cs] = c1[q];
+    }
+  }
+  __syncthreads();
   // back substitution R x = rhs[0..nc), column-oriented by the first wavefront
   if (wave == 0) {
     for (int i = nc - 1; i >= 0; --i) {
