@@ -1000,6 +1000,8 @@ DEV void qr_lstsq(double* A, int m, int nc, double* rhs, double* x) {
   static_assert(kMaxNs <= 128, "two rows per lane");
   __shared__ double sv[2][128];
   __shared__ double sbeta[2];
+  __shared__ double scol[2][128];     // column k, as its owner last updated it
+  __shared__ double salpha[kMaxR];    // R's diagonal
   const int r0 = lane, r1 = lane + 64;
   double c0[NQ], c1[NQ];   // rows r0 and r1 of columns wave + 4 q
 #pragma unroll
@@ -1010,13 +1012,15 @@ DEV void qr_lstsq(double* A, int m, int nc, double* rhs, double* x) {
     c0[q] = (c <= nc && r0 < m) ? src[r0 * cs] : 0.0;
     c1[q] = (c <= nc && r1 < m) ? src[r1 * cs] : 0.0;
   }
+  if (wave == 0) {
+    scol[0][r0] = c0[0];
+    scol[0][r1] = c1[0];
+  }
+  __syncthreads();
   for (int k = 0; k < nc; ++k) {
-    const int qk = k >> 2, buf = k & 1;
+    const int buf = k & 1;
     if (wave == (k & 3)) {
-      double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        if (q == qk) { a0 = c0[q]; a1 = c1[q]; }
+      const double a0 = scol[buf][r0], a1 = scol[buf][r1];
       const double t0 = r0 >= k ? a0 : 0.0, t1 = r1 >= k ? a1 : 0.0;   // rows >= m hold 0
       const double s = wave_sum_bfly(t0 * t0 + t1 * t1);
       const double akk = readlane_d(k < 64 ? a0 : a1, k & 63);
@@ -1027,14 +1031,10 @@ DEV void qr_lstsq(double* A, int m, int nc, double* rhs, double* x) {
       const double vv = (s - akk * akk) + vk * vk;
       sv[buf][r0] = r0 == k ? vk : t0;
       sv[buf][r1] = r1 == k ? vk : t1;
-      if (lane == 0) sbeta[buf] = vv > 0.0 ? 2.0 / vv : 0.0;
-      // column k of R: alpha on the diagonal, zero below
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        if (q == qk) {
-          c0[q] = r0 == k ? alpha : (r0 > k ? 0.0 : a0);
-          c1[q] = r1 == k ? alpha : (r1 > k ? 0.0 : a1);
-        }
+      if (lane == 0) {
+        sbeta[buf] = vv > 0.0 ? 2.0 / vv : 0.0;
+        salpha[k] = alpha;   // column k of R: alpha on the diagonal (its rows below are zero)
+      }
     }
     __syncthreads();
     const double v0 = sv[buf][r0], v1 = sv[buf][r1], beta = sbeta[buf];
@@ -1045,6 +1045,10 @@ DEV void qr_lstsq(double* A, int m, int nc, double* rhs, double* x) {
         const double d = beta * wave_sum_bfly(v0 * c0[q] + v1 * c1[q]);
         c0[q] -= d * v0;
         c1[q] -= d * v1;
+        if (c == k + 1 && c < nc) {   // the next step's column, for its owner
+          scol[buf ^ 1][r0] = c0[q];
+          scol[buf ^ 1][r1] = c1[q];
+        }
       }
     }
   }
@@ -1055,8 +1059,12 @@ DEV void qr_lstsq(double* A, int m, int nc, double* rhs, double* x) {
     if (c <= nc) {
       double* dst = c < nc ? A + c : rhs;
       const int cs = c < nc ? ld : 1;
-      if (r0 < m) dst[r0 * cs] = c0[q];
-      if (r1 < m) dst[r1 * cs] = c1[q];
+      // R's column c: the rows above c as updated, alpha on the diagonal
+      // (the register copy of column c stopped at step c)
+      const double d0 = c < nc && r0 == c ? salpha[c] : c0[q];
+      const double d1 = c < nc && r1 == c ? salpha[c] : c1[q];
+      if (r0 < m) dst[r0 * cs] = d0;
+      if (r1 < m) dst[r1 * cs] = d1;
     }
   }
   __syncthreads();
