@@ -678,12 +678,22 @@ __global__ __launch_bounds__(256) void k_rotate(const Tile* __restrict__ tiles,
                                                 int ldu, size_t ustride, int mode,
                                                 const double* __restrict__ q1,
                                                 const double* __restrict__ pr, int ldpr,
-                                                const int32_t* __restrict__ enable) {
+                                                const int32_t* __restrict__ enable, int split) {
   __shared__ T sP[kChunk][kMaxK + 1];
   __shared__ double sS[kChunk];
   __shared__ double sU[(kMaxK + 1) * 64];
   __shared__ double sp[2 * kMaxR + 1];
-  const Tile t = tiles[blockIdx.x];
+  // block blockIdx.x takes part blockIdx.x % split of tile blockIdx.x / split
+  // (few tiles, as for one large instance, still fill the chip)
+  Tile t = tiles[blockIdx.x / split];
+  {
+    const int part = blockIdx.x % split;
+    const int64_t len = (t.ncell + split - 1) / split;
+    const int64_t lo = part * len;
+    if (lo >= t.ncell) return;
+    t.cell0 += lo;
+    t.ncell = t.ncell - lo < len ? t.ncell - lo : len;
+  }
   const int b = t.inst;
   if (enable && !enable[b]) return;
   const int tid = threadIdx.x;
@@ -701,9 +711,27 @@ __global__ __launch_bounds__(256) void k_rotate(const Tile* __restrict__ tiles,
     const int nr = (int)(t.ncell - r0 < kChunk ? t.ncell - r0 : kChunk);
     const int64_t row0 = t.cell0 + r0;
     __syncthreads();
-    for (int e = tid; e < nr * kin; e += blockDim.x) {
-      const int rr = e / kin, c = e - rr * kin;
-      sP[rr][c] = Phi_in[(base + row0 + rr) * ld_in + c];
+    {
+      // eight loads per thread in flight (indices clamped into the chunk),
+      // then the LDS stores
+      const int ne = nr * kin;
+      for (int e0 = tid; e0 < ne; e0 += 256 * 8) {
+        T v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = e0 + 256 * j < ne ? e0 + 256 * j : ne - 1;
+          const int rr = e / kin, c = e - rr * kin;
+          v[j] = Phi_in[(base + row0 + rr) * ld_in + c];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = e0 + 256 * j;
+          if (e < ne) {
+            const int rr = e / kin, c = e - rr * kin;
+            sP[rr][c] = v[j];
+          }
+        }
+      }
     }
     __syncthreads();
     if (mode == 1 && tid < nr) {
@@ -713,10 +741,26 @@ __global__ __launch_bounds__(256) void k_rotate(const Tile* __restrict__ tiles,
     }
     __syncthreads();
     if (lane < kout) {
-      for (int rr = grp; rr < nr; rr += 4) {
-        double acc = mode == 1 ? sS[rr] * sU[kin * 64 + lane] : 0.0;
-        for (int c = 0; c < kin; ++c) acc += (double)sP[rr][c] * sU[c * 64 + lane];
-        Phi_out[(base + row0 + rr) * ld_out + lane] = (T)acc;
+      // four rows per wave at a time (rows grp + 4 j), four independent sums,
+      // each over the columns in order
+      for (int rb = grp; rb < nr; rb += 16) {
+        double acc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int rr = rb + 4 * j < nr ? rb + 4 * j : rb;
+          acc[j] = mode == 1 ? sS[rr] * sU[kin * 64 + lane] : 0.0;
+        }
+        for (int c = 0; c < kin; ++c) {
+          const double u = sU[c * 64 + lane];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int rr = rb + 4 * j < nr ? rb + 4 * j : rb;
+            acc[j] += (double)sP[rr][c] * u;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (rb + 4 * j < nr) Phi_out[(base + row0 + rb + 4 * j) * ld_out + lane] = (T)acc[j];
       }
     }
   }
@@ -1225,10 +1269,12 @@ void rotate_t(rom_batch* h, const T* Phi_in, int ld_in, int kin, T* Phi_out, int
     hipLaunchKernelGGL((k_rotate_small<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                        h->d_dof_off, Phi_in, kin, Phi_out, kout, U, ldu, ustride, mode, q1, pr,
                        ldpr, enable);
-  else
-    hipLaunchKernelGGL((k_rotate<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+  else {
+    const int split = std::max(1, std::min(8, 2 * h->n_cu / std::max(h->n_ptiles, 1)));
+    hipLaunchKernelGGL((k_rotate<T>), dim3(h->n_ptiles * split), dim3(256), 0, s, h->d_ptiles,
                        h->d_dof_off, Phi_in, ld_in, kin, Phi_out, ld_out, kout, U, ldu, ustride,
-                       mode, q1, pr, ldpr, enable);
+                       mode, q1, pr, ldpr, enable, split);
+  }
 }
 
 template <typename T>
