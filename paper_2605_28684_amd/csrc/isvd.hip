@@ -45,12 +45,21 @@ __global__ __launch_bounds__(256) void k_project(const Tile* __restrict__ tiles,
                                                  const double* __restrict__ dvar, int nv,
                                                  const double* __restrict__ p1, int ldp, int mode,
                                                  double* __restrict__ part,
-                                                 double* __restrict__ q1out) {
+                                                 double* __restrict__ q1out, int split) {
   __shared__ T sP[kChunk][kMaxK + 1];
   __shared__ double sY[kChunk];
   __shared__ double sp[kMaxK];
   __shared__ double red[4][kMaxK + 1];
-  const Tile t = tiles[blockIdx.x];
+  // block blockIdx.x takes part blockIdx.x % split of tile blockIdx.x / split
+  // and writes its own partial (an empty part writes zeros)
+  Tile t = tiles[blockIdx.x / split];
+  {
+    const int pt = blockIdx.x % split;
+    const int64_t len = (t.ncell + split - 1) / split;
+    const int64_t lo = pt * len < t.ncell ? pt * len : t.ncell;
+    t.cell0 += lo;
+    t.ncell = t.ncell - lo < len ? t.ncell - lo : len;
+  }
   const int b = t.inst;
   const int tid = threadIdx.x;
   const int64_t base = dof_off[b];
@@ -63,9 +72,27 @@ __global__ __launch_bounds__(256) void k_project(const Tile* __restrict__ tiles,
     const int nr = (int)(t.ncell - r0 < kChunk ? t.ncell - r0 : kChunk);
     const int64_t row0 = t.cell0 + r0;  // instance-local row of the chunk
     __syncthreads();
-    for (int e = tid; e < nr * k; e += blockDim.x) {
-      const int rr = e / k, c = e - rr * k;
-      sP[rr][c] = Phi[(base + row0 + rr) * ld + c];
+    {
+      // eight loads per thread in flight (indices clamped into the chunk),
+      // then the LDS stores
+      const int ne = nr * k;
+      for (int e0 = tid; e0 < ne; e0 += 256 * 8) {
+        T v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = e0 + 256 * j < ne ? e0 + 256 * j : ne - 1;
+          const int rr = e / k, c = e - rr * k;
+          v[j] = Phi[(base + row0 + rr) * ld + c];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = e0 + 256 * j;
+          if (e < ne) {
+            const int rr = e / k, c = e - rr * k;
+            sP[rr][c] = v[j];
+          }
+        }
+      }
     }
     if (tid < nr) {
       const int64_t g = base + row0 + tid;
@@ -100,12 +127,13 @@ __global__ __launch_bounds__(256) void k_project(const Tile* __restrict__ tiles,
 }
 
 // Sum the tile partials of each instance in tile order: dst[b*ldd + c], c <= k.
+// With split > 1 each tile has split consecutive partials.
 __global__ void k_reduce_tiles(const int* __restrict__ tfirst, const double* __restrict__ part, int k,
-                               double* __restrict__ dst, int ldd) {
+                               double* __restrict__ dst, int ldd, int split) {
   const int b = blockIdx.x;
   for (int c = threadIdx.x; c <= k; c += blockDim.x) {
     double s = 0.0;
-    for (int tt = tfirst[b]; tt < tfirst[b + 1]; ++tt) s += part[(size_t)tt * kPst + c];
+    for (int tt = tfirst[b] * split; tt < tfirst[b + 1] * split; ++tt) s += part[(size_t)tt * kPst + c];
     dst[(size_t)b * ldd + c] = s;
   }
 }
@@ -1285,12 +1313,15 @@ rom_status project_t(rom_batch* h, const void* Phi, int ld, int k, const void* y
     hipLaunchKernelGGL((k_project_small<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                        h->d_dof_off, (const T*)Phi, ld, k, (const T*)y, (const T*)qref, h->d_var,
                        h->nv, p1, ldp, mode, h->part, q1out);
-  else
-    hipLaunchKernelGGL((k_project<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
+  int split = 1;
+  if (k > kNarrow) {
+    split = std::max(1, std::min(8, 2 * h->n_cu / std::max(h->n_ptiles, 1)));
+    hipLaunchKernelGGL((k_project<T>), dim3(h->n_ptiles * split), dim3(256), 0, s, h->d_ptiles,
                        h->d_dof_off, (const T*)Phi, ld, k, (const T*)y, (const T*)qref, h->d_var,
-                       h->nv, p1, ldp, mode, h->part, q1out);
+                       h->nv, p1, ldp, mode, h->part, q1out, split);
+  }
   hipLaunchKernelGGL(k_reduce_tiles, dim3(h->cfg.n_inst), dim3(128), 0, s, h->d_ptile_first,
-                     h->part, k, dst, ldd);
+                     h->part, k, dst, ldd, split);
   return ROM_OK;
 }
 
@@ -1307,7 +1338,7 @@ rom_status projection_pass(rom_batch* h, const void* y, const double* p1, int ld
     rom_status st = launch_project_fast(h, y, p1, ldp, mode, pp, kPst, q1out, s);
     if (st != ROM_OK) return st;
     hipLaunchKernelGGL(k_reduce_tiles, dim3(h->cfg.n_inst), dim3(128), 0, s, h->d_ptile_first,
-                       pp, r, dst, ldd);
+                       pp, r, dst, ldd, 1);
     return ROM_OK;
   }
   return project_t<T>(h, h->Phi, r, r, y, h->q_ref, p1, ldp, mode, dst, ldd, s, q1out);
@@ -1443,7 +1474,7 @@ rom_status pod_core_t(rom_batch* h, const void* cols, int w, bool pre, bool svd,
                        h->d_dof_off, Q, w, k, yk, qref, h->d_var, h->nv, prp,
                        2 * kMaxK + 2, h->qtmp, h->part);
     hipLaunchKernelGGL(k_reduce_tiles, dim3(B), dim3(128), 0, s, h->d_ptile_first, h->part, 0,
-                       redp, ldr);
+                       redp, ldr, 1);
     hipLaunchKernelGGL(k_pod_rho, dim3(B), dim3(64), 0, s, k, w, redp, ldr, R, prp, 2 * kMaxK + 2);
     hipLaunchKernelGGL((k_pod_scale<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                        h->d_dof_off, Q, w, k, prp, 2 * kMaxK + 2);
@@ -1635,7 +1666,7 @@ rom_status windowed_t(rom_batch* h, const void* y, hipStream_t s) {
   hipLaunchKernelGGL((k_project_vec<T>), dim3(h->n_ptiles), dim3(256), 0, s, h->d_ptiles,
                      h->d_dof_off, (const T*)h->Phi, r, h->lift, h->part);
   hipLaunchKernelGGL(k_reduce_tiles, dim3(B), dim3(128), 0, s, h->d_ptile_first, h->part, r - 1,
-                     h->a, r);
+                     h->a, r, 1);
   ROM_HIP_CHECK(hipGetLastError());
   return ROM_OK;
 }
