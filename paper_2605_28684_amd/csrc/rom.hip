@@ -988,11 +988,12 @@ __global__ __launch_bounds__(128) void k_deim_argmax_v4(const Tile* __restrict__
 // ld = kMaxR + 1, m <= 128): overwrites x[0..nc) with argmin ||A x - rhs||.
 // Four wavefronts (blockDim.x == 256) keep the columns in registers: wavefront
 // w holds columns w, w + 4, ... (the rhs is column nc), lane l rows l and
-// l + 64.  At step k the owner of column k forms the reflector (squared norm
-// by a wave sum, the head from row k) and publishes v and beta through LDS
-// (double-buffered, one barrier per column); every wavefront then applies it
-// to its own later columns with one wave sum per column.  R and the rotated
-// rhs go back to LDS for the back-substitution.
+// l + 64.  The owner of column k forms its reflector (squared norm by a wave
+// sum, the head from row k) as soon as step k - 1 has updated that column,
+// and publishes v and beta through LDS (double-buffered, one barrier per
+// column); every wavefront then applies it to its own later columns with one
+// wave sum per column.  R and the rotated rhs go back to LDS for the
+// back-substitution.
 DEV void qr_lstsq(double* A, int m, int nc, double* rhs, double* x) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int ld = kMaxR + 1;
@@ -1000,7 +1001,6 @@ DEV void qr_lstsq(double* A, int m, int nc, double* rhs, double* x) {
   static_assert(kMaxNs <= 128, "two rows per lane");
   __shared__ double sv[2][128];
   __shared__ double sbeta[2];
-  __shared__ double scol[2][128];     // column k, as its owner last updated it
   __shared__ double salpha[kMaxR];    // R's diagonal
   const int r0 = lane, r1 = lane + 64;
   double c0[NQ], c1[NQ];   // rows r0 and r1 of columns wave + 4 q
@@ -1012,32 +1012,33 @@ DEV void qr_lstsq(double* A, int m, int nc, double* rhs, double* x) {
     c0[q] = (c <= nc && r0 < m) ? src[r0 * cs] : 0.0;
     c1[q] = (c <= nc && r1 < m) ? src[r1 * cs] : 0.0;
   }
-  if (wave == 0) {
-    scol[0][r0] = c0[0];
-    scol[0][r1] = c1[0];
-  }
-  __syncthreads();
-  for (int k = 0; k < nc; ++k) {
-    const int buf = k & 1;
-    if (wave == (k & 3)) {
-      const double a0 = scol[buf][r0], a1 = scol[buf][r1];
-      const double t0 = r0 >= k ? a0 : 0.0, t1 = r1 >= k ? a1 : 0.0;   // rows >= m hold 0
-      const double s = wave_sum_bfly(t0 * t0 + t1 * t1);
-      const double akk = readlane_d(k < 64 ? a0 : a1, k & 63);
-      const double nrm = sqrt(s);
-      const double alpha = akk >= 0.0 ? -nrm : nrm;
-      // v = x - alpha e1 in column k (rows k..m-1); v^T v = s - akk^2 + (akk - alpha)^2
-      const double vk = akk - alpha;
-      const double vv = (s - akk * akk) + vk * vk;
-      sv[buf][r0] = r0 == k ? vk : t0;
-      sv[buf][r1] = r1 == k ? vk : t1;
-      if (lane == 0) {
-        sbeta[buf] = vv > 0.0 ? 2.0 / vv : 0.0;
-        salpha[k] = alpha;   // column k of R: alpha on the diagonal (its rows below are zero)
-      }
+  // The reflector of column k from that column's rows (a0, a1) as all earlier
+  // reflectors left them, by its owner: v and beta to LDS buffer k & 1, R's
+  // diagonal entry alpha to salpha[k].
+  auto reflector = [&](int k, double a0, double a1) {
+    const double t0 = r0 >= k ? a0 : 0.0, t1 = r1 >= k ? a1 : 0.0;   // rows >= m hold 0
+    const double s = wave_sum_bfly(t0 * t0 + t1 * t1);
+    const double akk = readlane_d(k < 64 ? a0 : a1, k & 63);
+    const double nrm = sqrt(s);
+    const double alpha = akk >= 0.0 ? -nrm : nrm;
+    // v = x - alpha e1 in column k (rows k..m-1); v^T v = s - akk^2 + (akk - alpha)^2
+    const double vk = akk - alpha;
+    const double vv = (s - akk * akk) + vk * vk;
+    sv[k & 1][r0] = r0 == k ? vk : t0;
+    sv[k & 1][r1] = r1 == k ? vk : t1;
+    if (lane == 0) {
+      sbeta[k & 1] = vv > 0.0 ? 2.0 / vv : 0.0;
+      salpha[k] = alpha;
     }
+  };
+  if (wave == 0) reflector(0, c0[0], c1[0]);
+  for (int k = 0; k < nc; ++k) {
     __syncthreads();
+    const int buf = k & 1;
     const double v0 = sv[buf][r0], v1 = sv[buf][r1], beta = sbeta[buf];
+    // each wavefront applies reflector k to its later columns; the owner of
+    // column k + 1 updates it first and forms the next reflector at once, so
+    // that its chain overlaps the remaining updates of every wavefront
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int c = wave + 4 * q;
@@ -1045,10 +1046,7 @@ DEV void qr_lstsq(double* A, int m, int nc, double* rhs, double* x) {
         const double d = beta * wave_sum_bfly(v0 * c0[q] + v1 * c1[q]);
         c0[q] -= d * v0;
         c1[q] -= d * v1;
-        if (c == k + 1 && c < nc) {   // the next step's column, for its owner
-          scol[buf ^ 1][r0] = c0[q];
-          scol[buf ^ 1][r1] = c1[q];
-        }
+        if (c == k + 1 && c < nc) reflector(k + 1, c0[q], c1[q]);
       }
     }
   }
