@@ -1181,10 +1181,10 @@ __global__ __launch_bounds__(256) void k_rebuild(int r, int ns, int nv, int peri
   extern __shared__ double sm[];
   constexpr int ld = kMaxR + 1;
   double* A = sm;                    // ns x ld : R above the diagonal, reflectors below
-  double* Q = A + kMaxNs * ld;       // ns x r  : first r columns of Q
-  double* vd = Q + kMaxNs * kMaxR;   // reflector heads
+  double* Q = A + kMaxNs * ld;       // ns x r  : first r columns of Q (row stride ld)
+  double* vd = Q + kMaxNs * ld;      // reflector heads
   double* bt = vd + kMaxR;           // reflector scales
-  __shared__ double nrm;
+  __shared__ double alpha_s;   // alpha of the current column
   const int b = blockIdx.x, tid = threadIdx.x;
   const int64_t base = dof_off[b];
   const int64_t n = cell_off[b + 1] - cell_off[b];
@@ -1207,23 +1207,27 @@ __global__ __launch_bounds__(256) void k_rebuild(int r, int ns, int nv, int peri
   }
   __syncthreads();
   // Householder QR: column k reflector v = x - alpha e_k, H = I - beta v v^T
+  // (the squared norms are summed by the first wavefront, lanes over rows)
+  const int lane = tid & 63;
   for (int k = 0; k < r; ++k) {
-    if (tid == 0) {
+    if (tid < 64) {
       double s2 = 0.0;
-      for (int i = k; i < ns; ++i) s2 += A[i * ld + k] * A[i * ld + k];
-      nrm = sqrt(s2);
+      for (int i = k + lane; i < ns; i += 64) s2 += A[i * ld + k] * A[i * ld + k];
+      s2 = wave_sum_bfly(s2);
+      const double akk = A[k * ld + k];
+      const double alpha = akk >= 0.0 ? -sqrt(s2) : sqrt(s2);
+      // v = x - alpha e_k; v^T v = s2 - akk^2 + (akk - alpha)^2
+      const double vk = akk - alpha;
+      const double vv = (s2 - akk * akk) + vk * vk;
+      if (lane == 0) {
+        alpha_s = alpha;
+        A[k * ld + k] = vk;
+        bt[k] = vv > 0.0 ? 2.0 / vv : 0.0;
+        vd[k] = vk;
+      }
     }
     __syncthreads();
-    const double alpha = A[k * ld + k] >= 0.0 ? -nrm : nrm;
-    __syncthreads();
-    if (tid == 0) {
-      A[k * ld + k] -= alpha;
-      double vv = 0.0;
-      for (int i = k; i < ns; ++i) vv += A[i * ld + k] * A[i * ld + k];
-      bt[k] = vv > 0.0 ? 2.0 / vv : 0.0;
-      vd[k] = A[k * ld + k];
-    }
-    __syncthreads();
+    const double alpha = alpha_s;
     for (int c = k + 1 + tid; c < r; c += blockDim.x) {
       double s2 = 0.0;
       for (int i = k; i < ns; ++i) s2 += A[i * ld + k] * A[i * ld + c];
@@ -1235,25 +1239,38 @@ __global__ __launch_bounds__(256) void k_rebuild(int r, int ns, int nv, int peri
     __syncthreads();
   }
   // Q[:, :r] = H_0 H_1 ... H_{r-1} [I; 0]
-  for (int e = tid; e < ns * r; e += blockDim.x) Q[e] = (e / r) == (e % r) ? 1.0 : 0.0;
+  for (int e = tid; e < ns * r; e += blockDim.x) {
+    const int i = e / r, c = e - i * r;
+    Q[i * ld + c] = i == c ? 1.0 : 0.0;
+  }
   __syncthreads();
   for (int k = r - 1; k >= 0; --k) {
     for (int c = tid; c < r; c += blockDim.x) {
-      double s2 = vd[k] * Q[k * r + c];
-      for (int i = k + 1; i < ns; ++i) s2 += A[i * ld + k] * Q[i * r + c];
+      double s2 = vd[k] * Q[k * ld + c];
+      for (int i = k + 1; i < ns; ++i) s2 += A[i * ld + k] * Q[i * ld + c];
       s2 *= bt[k];
-      Q[k * r + c] -= s2 * vd[k];
-      for (int i = k + 1; i < ns; ++i) Q[i * r + c] -= s2 * A[i * ld + k];
+      Q[k * ld + c] -= s2 * vd[k];
+      for (int i = k + 1; i < ns; ++i) Q[i * ld + c] -= s2 * A[i * ld + k];
     }
     __syncthreads();
   }
-  // M[:, s] = R^-1 Q[s, :]^T, one column per thread
+  // M[:, s] = R^-1 Q[s, :]^T, one column per thread, computed in place over
+  // row s of Q in LDS (the odd row stride keeps the threads' rows on distinct
+  // banks), then stored coalesced
   for (int s = tid; s < ns; s += blockDim.x) {
-    double* Mb = Mout + (size_t)b * r * ns;
+    double* qs = Q + s * ld;
     for (int i = r - 1; i >= 0; --i) {
-      double acc = Q[s * r + i];
-      for (int c = i + 1; c < r; ++c) acc -= A[i * ld + c] * Mb[c * ns + s];
-      Mb[i * ns + s] = A[i * ld + i] != 0.0 ? acc / A[i * ld + i] : 0.0;
+      double acc = qs[i];
+      for (int c = i + 1; c < r; ++c) acc -= A[i * ld + c] * qs[c];
+      qs[i] = A[i * ld + i] != 0.0 ? acc / A[i * ld + i] : 0.0;
+    }
+  }
+  __syncthreads();
+  {
+    double* Mb = Mout + (size_t)b * r * ns;
+    for (int e = tid; e < r * ns; e += blockDim.x) {
+      const int i = e / ns, s2 = e - i * ns;
+      Mb[e] = Q[s2 * ld + i];
     }
   }
   if (tid == 0) {
@@ -1267,7 +1284,7 @@ __global__ __launch_bounds__(256) void k_rebuild(int r, int ns, int nv, int peri
 }
 
 size_t rebuild_shm() {
-  return sizeof(double) * (kMaxNs * (kMaxR + 1) + kMaxNs * kMaxR + 2 * kMaxR);
+  return sizeof(double) * (2 * kMaxNs * (kMaxR + 1) + 2 * kMaxR);
 }
 
 template <typename T>
