@@ -1684,10 +1684,10 @@ rom_status rom_kernels_prepare() {
   ROM_HIP_CHECK(vjp_attr((const void*)k_hr_step_vjp<EulerModel<double, true>, double>));
   ROM_HIP_CHECK(vjp_attr((const void*)k_hr_step_vjp<ReactModel<double>, float>));
   ROM_HIP_CHECK(vjp_attr((const void*)k_hr_step_vjp<ReactModel<double>, double>));
-  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_rebuild<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_rebuild<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rebuild_shm()));
   ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_hr_reduce, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)hr_reduce_shm(kMaxR, kMaxNs)));
-  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_rebuild<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  ROM_HIP_CHECK(hipFuncSetAttribute((const void*)k_rebuild<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rebuild_shm()));
   return ROM_OK;
 }
 
