@@ -416,7 +416,8 @@ __global__ void k_rom_finalize(int n_inst, const int32_t* active, uint32_t* flag
 // multipliers are those of row-pivoted LU, and back-substitution reads each
 // column's pivot row by its lane.  x overwrites b; *ok is 0 if a pivot vanishes.
 // The caller synchronises the block afterwards.
-// NM >= n bounds the columns kept per lane (a multiple of 16 up to kMaxR).
+// NM >= n bounds the columns kept per lane (up to kMaxR; columns n .. NM - 1 cost
+// work, so the instances are sized to the configurations' r).
 template <int NM>
 DEV void wave_lu_solve(const double* A, int ld, double* bvec, int n, int* ok) {
   static_assert(NM <= kMaxR && NM <= 64, "one row per lane");
@@ -1593,11 +1594,11 @@ rom_status hr_step(rom_batch* h, hipStream_t s) {
                            ns, gpi, h->d_cell_off, h->d_phys, h->cfg.n_phys, h->P,
                            (const double*)h->mesh_phi, h->mesh_qref, h->d_var, h->a, h->a_prev,
                            h->cfg.dt, h->active, h->hr_as, h->flags);
-      // register rows of the solve sized to r rounded up to 16
+      // register rows of the solve sized to r rounded up to 16 (40 for r = 33..40)
       hipLaunchKernelGGL(k_hr_reduce, dim3(B * gpr), dim3(kHrRedThreads), hr_reduce_shm(r, ns), s,
                          r, ns, gpr, h->M, h->hr_as, h->active, hr_ar);
       auto rsolve = r <= 16 ? k_hr_solve<16> : r <= 32 ? k_hr_solve<32>
-                  : r <= 48 ? k_hr_solve<48> : k_hr_solve<64>;
+                  : r <= 40 ? k_hr_solve<40> : r <= 48 ? k_hr_solve<48> : k_hr_solve<64>;
       hipLaunchKernelGGL(rsolve, dim3(B), dim3(256), 0, s, r, hr_ar, h->active, h->a, h->iters,
                          h->cfg.rom_tol, h->flags);
     }

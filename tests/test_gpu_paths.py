@@ -212,8 +212,11 @@ def test_isvd_rho_zero_branch(precision, zeros):
 
 # ---------------------------------------------------------------- FP32 HR-LSPG windows
 def _hr_case(kind):
-    if kind == "sod_hllc_r40":          # the Sod configuration's r and n_s (<48> solve)
+    if kind == "sod_hllc_r40":          # the Sod configuration's r and n_s (<40> solve)
         w = W.sod_hllc_f32(n=1500, r=40, n_s=80, z=3, precision=W.F32, flux=W.EULER_HLLC)
+        n_win = 3
+    elif kind == "sod_hllc_r44":        # 40 < r <= 48 (<48> solve)
+        w = W.sod_hllc_f32(n=1500, r=44, n_s=88, z=3, precision=W.F32, flux=W.EULER_HLLC)
         n_win = 3
     elif kind == "sod_rusanov_r24":     # 16 < r <= 32 (<32> solve)
         w = W.sod_hllc_f32(n=900, r=24, n_s=40, z=3, precision=W.F32, flux=W.EULER_RUSANOV)
@@ -238,7 +241,7 @@ def _device_state(h, w):
                 qt=G.host(h.get(R.GET_QTILDE)))
 
 
-@pytest.mark.parametrize("kind", ["sod_hllc_r40", "sod_rusanov_r24", "react_r64"])
+@pytest.mark.parametrize("kind", ["sod_hllc_r40", "sod_hllc_r44", "sod_rusanov_r24", "react_r64"])
 def test_hr_lspg_windows_fp32_eager_graph_and_oracle(kind):
     """FP32 storage (basis, states, coarse step, DEIM passes) with FP64 sampled
     evaluation and solves.  Both handles start from the oracle's offline state
